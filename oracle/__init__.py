@@ -1,0 +1,24 @@
+"""Plain FP64 CPU oracle of the augmented subspace eigensolver.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library and its
+Python binding) imports, calls or links anything here; only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` do.
+It shares no code with the GPU path: the only common module is ``synth``,
+which draws the seeded inputs and holds none of the method's arithmetic.
+
+Written from the paper (Xie et al., "A parallel augmented subspace
+eigensolver", arXiv 2502.04589) with NumPy/SciPy in float64:
+
+* ``fem``        -- the model problem and its Q1 discretisation (Sec. 2.1).
+* ``multigrid``  -- nested spaces, interpolation I_H^h, Galerkin coarse
+                    operators (Alg. 3 inputs, Sec. 5.1) and the geometric
+                    multigrid V-cycle used to precondition the fine solves.
+* ``pase``       -- the outer loop: fine linear solves by CG (Alg. 3 step 3),
+                    composite matrices (eq. Definition_Hh), the augmented
+                    eigenproblem (Alg. 3 steps 5-6) and the stopping rule
+                    (Sec. 5, opening paragraph).
+
+Readings of points the paper leaves open are listed in the docstrings where
+they are taken.
+"""
+from . import fem, multigrid, pase  # noqa: F401
