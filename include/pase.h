@@ -1,0 +1,179 @@
+/*
+ * pase.h -- C ABI of the MI355X augmented subspace eigensolver (gfx950).
+ *
+ * Computes the nev smallest eigenpairs (lambda_i, u_i) of the Q1 finite
+ * element pencil A u = lambda M u of -div(kappa grad u) = lambda u on the unit
+ * square / cube with u = 0 on the boundary, kappa constant per element
+ * (Xie et al., arXiv 2502.04589, Sec. 2.1).  The method is the algebraic
+ * augmented subspace iteration (Alg. 3 with Alg. 1 as the correction step):
+ *   (a) per eigenvector, s steps of V-cycle preconditioned CG on
+ *       A w = lambda M u from w = u (Alg. 3 step 3),
+ *   (b) projection onto V_H + span{W}: A W, M W, restriction P^T A W and the
+ *       Gram products W^T A W, W^T M W (eq. Definition_Hh),
+ *   (c) the k smallest eigenpairs of the (N_H + k) augmented pencil and the
+ *       prolongation U = P y_H + W y_W (Alg. 3 steps 5-6).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * - Grids: level l has n[l] elements per side and m_l = n[l]-1 interior
+ *   nodes per side, N_l = m_l^dim nodes, numbered x fastest.  Level 0 is the
+ *   fine mesh, level nlevels-1 is the coarse space V_H.  n[l] = 2 n[l+1].
+ * - Multi-vectors are node-major: an N x k array of doubles with entry
+ *   (node i, column j) at i*k + j (row-major, leading dimension k).  All
+ *   multi-vector and coefficient pointers are DEVICE pointers unless the
+ *   argument name ends in _host.
+ * - Ownership: the caller owns every buffer it passes, including the
+ *   device workspace given to pase_setup.  Pointers are borrowed for the
+ *   duration of the call only (the workspace for the life of the handle).
+ *   The library never frees caller memory and never allocates device
+ *   memory after pase_setup.
+ * - Streams: all device work is enqueued on the stream given to pase_setup
+ *   (a hipStream_t passed as void*, NULL = the null stream).  Entry points
+ *   that return host results synchronise that stream before returning.
+ * - Errors: every call returns a pase_status; it never aborts or throws.
+ *   pase_last_error(h) gives a message for the last failure on h (or, with
+ *   h = NULL, for the last failure of a call that had no handle, per
+ *   thread).  A handle is not thread-safe; distinct handles on distinct
+ *   streams are.
+ * - Determinism: reductions use fixed-order trees (no floating-point
+ *   atomics); the same inputs on the same GPU give bitwise equal results.
+ */
+#ifndef PASE_H
+#define PASE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PASE_MAX_LEVELS 8
+#define PASE_MAX_NEV 256
+
+typedef enum pase_status {
+  PASE_OK = 0,
+  PASE_E_ARG = 1,          /* invalid argument (null, size, shape) */
+  PASE_E_HIP = 2,          /* a HIP runtime call failed */
+  PASE_E_NOMEM = 3,        /* workspace smaller than pase_workspace_bytes */
+  PASE_E_NOTCONV = 4,      /* max_outer reached; outputs hold the last iterate */
+  PASE_E_BREAKDOWN = 5,    /* non-SPD Gram / Cholesky failure / NaN */
+  PASE_E_UNSUPPORTED = 6   /* option or size not implemented */
+} pase_status;
+
+typedef enum pase_precision {
+  PASE_PREC_FP64 = 0,      /* every step in float64 */
+  PASE_PREC_MIXED = 1,     /* float32 CG / V-cycle, compensated Grams, float64 RR */
+  PASE_PREC_LEARNED = 2    /* learned preconditioner with GMG fallback */
+} pase_precision;
+
+/* The discrete problem (Alg. 3 "Require"): the fine Q1 pencil (A_h, B_h = M)
+ * of the element coefficient kappa and the nested grid hierarchy whose
+ * coarsest level is V_H.  I_H^h is trilinear (bilinear) interpolation,
+ * I_h^H its transpose, A_H / B_H the Galerkin products. */
+typedef struct pase_problem {
+  int dim;                       /* 2 or 3 */
+  int nlevels;                   /* 2 .. PASE_MAX_LEVELS */
+  int n[PASE_MAX_LEVELS];        /* elements per side; n[l] = 2*n[l+1], n[last] >= 2 */
+  const double* kappa;           /* device, n[0]^dim element values (x fastest), or NULL for kappa = 1 */
+} pase_problem;
+
+typedef struct pase_options {
+  int precision;                 /* pase_precision */
+  int nev_max;                   /* largest nev a later pase_solve may ask for (sizes the workspace) */
+  int cg_steps;                  /* s: CG steps per outer iteration (default 2) */
+  int max_outer;                 /* outer iteration limit (default 500) */
+  int nu;                        /* damped-Jacobi sweeps before and after the coarse correction (default 2) */
+  double omega;                  /* Jacobi damping (default 2/3) */
+} pase_options;
+
+/* Filled by pase_solve.  Array members are optional HOST buffers (NULL = not wanted). */
+typedef struct pase_report {
+  int outer_iters;               /* corrections performed */
+  int n_converged;               /* pairs with res_i <= tol at exit */
+  double* res_host;              /* nev: res_i = ||A u - lambda M u||_2 / (|lambda| ||M u||_2) */
+  double* res_literal_host;      /* nev: ||A u - lambda M u||_2 / |lambda| with u^T M u = 1 */
+  double* ritz_history_host;     /* (max_outer+1) x nev: Lambda before each correction and at exit */
+  int ritz_history_rows;         /* rows written to ritz_history_host */
+  double t_solve_ms;             /* device time of the solve (HIP events on the handle's stream) */
+} pase_report;
+
+typedef struct pase_handle pase_handle;
+
+/* ---------------------------------------------------------------- core API */
+
+/* Default options: FP64, nev_max 16, s = 2, max_outer 500, nu = 2, omega = 2/3. */
+void pase_options_default(pase_options* opt);
+
+/* Device workspace needed by pase_setup for this problem and options. */
+pase_status pase_workspace_bytes(const pase_problem* prob, const pase_options* opt, size_t* bytes);
+
+/* Builds the hierarchy (Galerkin coarse stencils, coarse factorisations) inside
+ * the caller's device workspace (>= pase_workspace_bytes, 256-byte aligned).
+ * prob->kappa is copied; it may be freed after the call.  *out receives a
+ * host-side handle released by pase_destroy. */
+pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* workspace,
+                       size_t workspace_bytes, void* stream, pase_handle** out);
+
+/* Alg. 3 ensure: the nev smallest eigenpairs of (A_h, M).
+ * U0: device N_0 x nev start block (any full-rank block; it is M-orthonormalised).
+ * lambda_host: nev eigenvalues, ascending.  U: device N_0 x nev, U^T M U = I.
+ * U0 and U may be the same buffer.  Stops when every res_i <= tol (see
+ * pase_report) or after opt.max_outer corrections (PASE_E_NOTCONV). */
+pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, double* lambda_host,
+                       double* U, pase_report* rep);
+
+pase_status pase_destroy(pase_handle* h);
+
+const char* pase_status_string(pase_status s);
+const char* pase_last_error(const pase_handle* h);
+
+/* N_l of level l (0 = fine). */
+pase_status pase_level_size(const pase_handle* h, int level, long long* N);
+
+/* ---------------------------------------------------------------- component entry points
+ * Single steps of the path, for parity tests and benchmarks.  k <= nev_max. */
+
+/* AX = A_l X, MX = M_l X on level l (either output may be NULL). */
+pase_status pase_apply(pase_handle* h, int level, int k, const double* X, double* AX, double* MX);
+
+/* Z = V(B): one V-cycle on level 0 from a zero initial guess (the CG preconditioner). */
+pase_status pase_vcycle(pase_handle* h, int k, const double* B, double* Z);
+
+/* Alg. 3 step 3: s preconditioned CG steps per column on A w = lambda_j M u_j from w = u_j.
+ * lambda_host: k values. */
+pase_status pase_pcg(pase_handle* h, int k, const double* lambda_host, const double* U, double* W);
+
+/* Xc = P^T Xf (fine level 0 -> coarsest), and Xf = P Xc (coarsest -> fine), P = I_H^h. */
+pase_status pase_restrict(pase_handle* h, int k, const double* Xf, double* Xc);
+pase_status pase_prolong(pase_handle* h, int k, const double* Xc, double* Xf);
+
+/* G = X^T Y for N x k node-major X, Y (G: k x k row-major, device).  N <= N_0. */
+pase_status pase_gram(pase_handle* h, long long N, int k, const double* X, const double* Y, double* G);
+
+/* The k smallest eigenpairs of a dense symmetric n x n matrix T (row-major, device):
+ * w_host (k, ascending) and V (device, n x k row-major, orthonormal columns).
+ * n <= pase_small_eig_max_n(h); T is not modified. */
+pase_status pase_small_eig(pase_handle* h, int n, int k, const double* T, double* w_host, double* V);
+int pase_small_eig_max_n(const pase_handle* h);
+
+/* One full correction (Alg. 1 / Alg. 3 steps 3-6) from (lambda, U) with U^T M U = I:
+ * U is overwritten with the new block and lambda_host with the new Ritz values. */
+pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* U);
+
+/* Benchmark support: average device time in ms of one launch of the kernel
+ * selected by `which`, over `reps` back-to-back launches bracketed by two HIP
+ * events on the handle's stream, at k columns, reading the handle's internal
+ * fine-level buffers (call after a pase_solve with the same k so they hold
+ * finite data).  Launch configuration is the one pase_solve uses.
+ *   which = 0: fine-level damped-Jacobi sweep x' = x + omega D^{-1}(b - A x)
+ *   which = 1: fine-level fused A X, M X
+ *   which = 2: Gram W^T (A W) on FP64 MFMA (including its fixed-order reduction)
+ *   which = 3: one V-cycle (all levels)
+ *   which = 4: one full correction (Alg. 3 steps 3-6) */
+pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PASE_H */

@@ -1,0 +1,73 @@
+"""ctypes declarations of the C ABI in include/pase.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpase.so")
+
+MAX_LEVELS = 8
+MAX_NEV = 256
+
+STATUS = {0: "PASE_OK", 1: "PASE_E_ARG", 2: "PASE_E_HIP", 3: "PASE_E_NOMEM", 4: "PASE_E_NOTCONV",
+          5: "PASE_E_BREAKDOWN", 6: "PASE_E_UNSUPPORTED"}
+PREC = {"fp64": 0, "mixed": 1, "learned": 2}
+
+
+class Problem(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nlevels", C.c_int), ("n", C.c_int * MAX_LEVELS), ("kappa", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("nev_max", C.c_int), ("cg_steps", C.c_int), ("max_outer", C.c_int),
+                ("nu", C.c_int), ("omega", C.c_double)]
+
+
+class Report(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("n_converged", C.c_int), ("res_host", C.c_void_p),
+                ("res_literal_host", C.c_void_p), ("ritz_history_host", C.c_void_p),
+                ("ritz_history_rows", C.c_int), ("t_solve_ms", C.c_double)]
+
+
+# (name, restype, argtypes) for every entry point of include/pase.h
+SIGNATURES = [
+    ("pase_options_default", None, [C.POINTER(Options)]),
+    ("pase_workspace_bytes", C.c_int, [C.POINTER(Problem), C.POINTER(Options), C.POINTER(C.c_size_t)]),
+    ("pase_setup", C.c_int, [C.POINTER(Problem), C.POINTER(Options), C.c_void_p, C.c_size_t, C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
+    ("pase_solve", C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.POINTER(Report)]),
+    ("pase_destroy", C.c_int, [C.c_void_p]),
+    ("pase_status_string", C.c_char_p, [C.c_int]),
+    ("pase_last_error", C.c_char_p, [C.c_void_p]),
+    ("pase_level_size", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_longlong)]),
+    ("pase_apply", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pase_vcycle", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    ("pase_pcg", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pase_restrict", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    ("pase_prolong", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    ("pase_gram", C.c_int, [C.c_void_p, C.c_longlong, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pase_small_eig", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pase_small_eig_max_n", C.c_int, [C.c_void_p]),
+    ("pase_correction", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    ("pase_time_kernel", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]),
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpase.so and declare its signatures.  Raises if the library was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libpase.so not found at {path}: run paper_2502_04589_amd.build.build() first")
+    lib = C.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

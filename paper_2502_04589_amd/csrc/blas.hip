@@ -1,0 +1,297 @@
+// Multi-vector BLAS kernels: per-column dot products (CG scalars), fused CG
+// updates, the tall-skinny Gram products W^T (A W), W^T (M W) on FP64 MFMA,
+// and a tiled FP64 GEMM for the small dense products.  Every reduction is a
+// fixed-order tree over fixed row tiles, so results are bitwise reproducible.
+#include "internal.hpp"
+
+namespace pase {
+
+namespace {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int per = nblocks >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+constexpr int kColdotPasses = 16;
+
+// partial[tile][j] = sum over the tile's rows of X[i,j] * Y[i,j]
+__global__ __launch_bounds__(kBlock) void coldot_kernel(long long N, int k, const double* __restrict__ X,
+                                                        const double* __restrict__ Y, double* __restrict__ partial,
+                                                        int tiles, int rows) {
+  __shared__ double red[kBlock];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= tiles) return;
+  const int slots = kBlock / k;
+  const int col = threadIdx.x % k;
+  const int slot = threadIdx.x / k;
+  const long long r0 = (long long)tile * rows;
+  const long long r1 = (r0 + rows < N) ? (r0 + rows) : N;
+  double acc = 0.0;
+  if (slot < slots)
+    for (long long r = r0 + slot; r < r1; r += slots) acc = fma(X[r * k + col], Y[r * k + col], acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < k) {
+    double s = 0.0;
+    for (int q = 0; q < slots; ++q) s += red[q * k + threadIdx.x];
+    partial[(size_t)tile * k + threadIdx.x] = s;
+  }
+}
+
+// out[j] = sum_t partial[t][j], one block per output, fixed order
+__global__ __launch_bounds__(kBlock) void reduce_partials_kernel(int tiles, int width,
+                                                                 const double* __restrict__ partial,
+                                                                 double* __restrict__ out) {
+  __shared__ double red[kBlock];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int t = threadIdx.x; t < tiles; t += kBlock) s += partial[(size_t)t * width + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+__global__ void pcg_alpha_kernel(int k, const double* rho, const double* pq, double* alpha) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  const double d = pq[j];
+  alpha[j] = (d > 0.0) ? rho[j] / d : 0.0;
+}
+
+__global__ void pcg_beta_kernel(int k, const double* rn, const double* ro, double* beta) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  const double d = ro[j];
+  beta[j] = (d != 0.0) ? rn[j] / d : 0.0;
+}
+
+__global__ void axpy2_kernel(long long N, int k, const double* __restrict__ alpha, const double* __restrict__ P,
+                             const double* __restrict__ Q, double* __restrict__ X, double* __restrict__ R) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  const double a = alpha[i % k];
+  X[i] = fma(a, P[i], X[i]);
+  R[i] = fma(-a, Q[i], R[i]);
+}
+
+__global__ void xpby_kernel(long long N, int k, const double* __restrict__ Z, const double* __restrict__ beta,
+                            double* __restrict__ P) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  P[i] = fma(beta[i % k], P[i], Z[i]);
+}
+
+__global__ void copy_kernel(size_t n, const double* __restrict__ s, double* __restrict__ d) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+// ---- Gram G = X^T Y on v_mfma_f64_16x16x4f64.
+// Operand layout of the 16x16x4 f64 MFMA (wave64): lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; accumulator register q of lane l holds
+// D[l/16 + 4q][l%16] (checked on gfx950 by the Gram parity test).  Here A = X^T restricted to 16 columns of X and 4 rows,
+// B = Y restricted to 4 rows and 16 columns.
+constexpr int kGramMaxTilesPerWave = 16;
+
+__global__ __launch_bounds__(kBlock) void gram_kernel(long long N, int k, const double* __restrict__ X,
+                                                      const double* __restrict__ Y, double* __restrict__ partial,
+                                                      int tiles, long long rows) {
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= tiles) return;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int T = (k + 15) >> 4;
+  const int TT = T * T;
+  const long long r0 = (long long)tile * rows;
+  const long long r1 = (r0 + rows < N) ? (r0 + rows) : N;
+  double4_t acc[kGramMaxTilesPerWave];
+#pragma unroll
+  for (int t = 0; t < kGramMaxTilesPerWave; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  const int li = lane & 15;   // column within a 16-wide tile
+  const int lk = lane >> 4;   // row within the 4-row step
+  for (long long r = r0; r < r1; r += 4) {
+    const long long row = r + lk;
+    const bool rok = row < r1;
+#pragma unroll
+    for (int t = 0; t < kGramMaxTilesPerWave; ++t) {
+      const int tt = wave + 4 * t;
+      if (tt < TT) {
+        const int ti = tt / T, tj = tt % T;
+        const int ca = ti * 16 + li, cb = tj * 16 + li;
+        const double av = (rok && ca < k) ? X[row * k + ca] : 0.0;
+        const double bv = (rok && cb < k) ? Y[row * k + cb] : 0.0;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  double* p = partial + (size_t)tile * k * k;
+#pragma unroll
+  for (int t = 0; t < kGramMaxTilesPerWave; ++t) {
+    const int tt = wave + 4 * t;
+    if (tt < TT) {
+      const int ti = tt / T, tj = tt % T;
+      const int j = tj * 16 + li;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = ti * 16 + lk + 4 * q;
+        if (i < k && j < k) p[(size_t)i * k + j] = acc[t][q];
+      }
+    }
+  }
+}
+
+// ---- generic tiled FP64 GEMM: C = alpha op(A) op(B) + beta C (row-major)
+constexpr int GT = 64, GK = 16;
+
+__global__ __launch_bounds__(kBlock) void gemm_kernel(int ta, int tb, int M, int N, int K, double alpha,
+                                                      const double* __restrict__ A, int lda,
+                                                      const double* __restrict__ B, int ldb, double beta,
+                                                      double* __restrict__ C, int ldc) {
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  const int bm = blockIdx.y * GT, bn = blockIdx.x * GT;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int e = threadIdx.x; e < GK * GT; e += kBlock) {
+      // A tile: op(A)[bm + i][k0 + kk]
+      const int kk = e / GT, i = e % GT;
+      const int gi = bm + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < M && gk < K) v = ta ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
+      As[kk][i] = v;
+      // B tile: op(B)[k0 + kk][bn + j]
+      const int j = i;
+      const int gj = bn + j;
+      double w = 0.0;
+      if (gj < N && gk < K) w = tb ? B[(size_t)gj * ldb + gk] : B[(size_t)gk * ldb + gj];
+      Bs[kk][j] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[kk][ty + 16 * q];
+        b[q] = Bs[kk][tx + 16 * q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = bm + ty + 16 * p, j = bn + tx + 16 * q;
+      if (i < M && j < N) {
+        double* c = C + (size_t)i * ldc + j;
+        *c = (beta == 0.0) ? alpha * acc[p][q] : fma(alpha, acc[p][q], beta * *c);
+      }
+    }
+}
+
+__global__ void set_blocks_kernel(int n, int nh, int k, const double* __restrict__ C0, const double* __restrict__ G,
+                                  const double* __restrict__ H, double* __restrict__ T) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  double v;
+  if (i < nh && j < nh) v = C0[(size_t)i * nh + j];
+  else if (i < nh) v = G[(size_t)i * k + (j - nh)];
+  else if (j < nh) v = G[(size_t)j * k + (i - nh)];
+  else v = H[(size_t)(i - nh) * k + (j - nh)];
+  T[e] = v;
+}
+
+inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+int coldot_tiles(long long N, int k) {
+  const int slots = kBlock / k;
+  const long long rows = (long long)slots * kColdotPasses;
+  long long t = (N + rows - 1) / rows;
+  return (int)(((t + 7) / 8) * 8);
+}
+
+void launch_coldot(long long N, int k, const double* X, const double* Y, double* partial, int ptiles, double* out,
+                   hipStream_t s) {
+  const int slots = kBlock / k;
+  const int rows = slots * kColdotPasses;
+  const int tiles = (int)((N + rows - 1) / rows);
+  const int blocks = ((tiles + 7) / 8) * 8;
+  (void)ptiles;
+  coldot_kernel<<<blocks, kBlock, 0, s>>>(N, k, X, Y, partial, tiles, rows);
+  reduce_partials_kernel<<<k, kBlock, 0, s>>>(tiles, k, partial, out);
+}
+
+void launch_reduce_partials(int tiles, int width, const double* partial, double* out, hipStream_t s) {
+  reduce_partials_kernel<<<width, kBlock, 0, s>>>(tiles, width, partial, out);
+}
+
+void launch_pcg_alpha(int k, const double* rho, const double* pq, double* alpha, hipStream_t s) {
+  pcg_alpha_kernel<<<1, kBlock, 0, s>>>(k, rho, pq, alpha);
+}
+
+void launch_pcg_beta(int k, const double* rn, const double* ro, double* beta, hipStream_t s) {
+  pcg_beta_kernel<<<1, kBlock, 0, s>>>(k, rn, ro, beta);
+}
+
+void launch_axpy2(long long N, int k, const double* alpha, const double* P, const double* Q, double* X, double* R,
+                  hipStream_t s) {
+  axpy2_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, R);
+}
+
+void launch_xpby(long long N, int k, const double* Z, const double* beta, double* P, hipStream_t s) {
+  xpby_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, Z, beta, P);
+}
+
+void launch_copy(size_t n, const double* src, double* dst, hipStream_t s) {
+  copy_kernel<<<nblk((long long)n), kBlock, 0, s>>>(n, src, dst);
+}
+
+int gram_tiles(long long N, int k) {
+  (void)k;
+  long long t = (N + 255) / 256;
+  if (t > 512) t = 512;
+  if (t < 1) t = 1;
+  return (int)t;
+}
+
+void launch_gram(long long N, int k, const double* X, const double* Y, double* partial, int tiles, double* G,
+                 hipStream_t s) {
+  long long rows = (N + tiles - 1) / tiles;
+  rows = ((rows + 3) / 4) * 4;
+  const int blocks = ((tiles + 7) / 8) * 8;
+  gram_kernel<<<blocks, kBlock, 0, s>>>(N, k, X, Y, partial, tiles, rows);
+  reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial, G);
+}
+
+void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
+                 int ldb, double beta, double* C, int ldc, hipStream_t s) {
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+  gemm_kernel<<<grid, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, hipStream_t s) {
+  launch_gemm(false, false, (int)N, k, k, 1.0, X, k, C, k, accumulate ? 1.0 : 0.0, Y, k, s);
+}
+
+void launch_set_diag_block(int n, int nh, int k, const double* C0, const double* G, const double* H, double* T,
+                           hipStream_t s) {
+  set_blocks_kernel<<<nblk((long long)n * n), kBlock, 0, s>>>(n, nh, k, C0, G, H, T);
+}
+
+}  // namespace pase

@@ -1,0 +1,458 @@
+// Grid kernels: Q1 stencil operators over node-major multi-vectors, damped
+// Jacobi, residuals, restriction / prolongation between nested levels, and the
+// setup kernels that build the Galerkin coarse stencils.
+//
+// Operators (paper Sec. 2.1, kappa constant per element):
+//   A[i, i+o] = Kpat(o) * (sum of kappa over the elements shared by nodes i and i+o)
+//   M[i, i+o] = (h/6)^d * prod_a (o_a == 0 ? 4 : 1)
+// with Kpat(o) = sum_a k1(o_a) prod_{b != a} m1(o_b), k1(0) = 1/h, k1(+-1) = -1/h,
+// m1(0) = 2h/6, m1(+-1) = h/6: the unit-coefficient Q1 element stiffness entry
+// between two vertices of one cell depends only on which coordinates differ.
+// Coarse levels carry the Galerkin product P^T A P as 3^d coefficients per node.
+#include "internal.hpp"
+
+namespace pase {
+
+namespace {
+
+template <int DIM>
+struct NSt { static constexpr int v = (DIM == 3) ? 27 : 9; };
+
+constexpr int kMaxNb = 64;
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous run of tiles so neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int per = nblocks >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+template <int DIM>
+__device__ __forceinline__ void offs(int o, int& ox, int& oy, int& oz) {
+  ox = o % 3 - 1;
+  oy = (o / 3) % 3 - 1;
+  oz = (DIM == 3) ? (o / 9 - 1) : 0;
+}
+
+template <int DIM>
+__device__ __forceinline__ double kpat(int o, double h) {
+  int ox, oy, oz;
+  offs<DIM>(o, ox, oy, oz);
+  const int od[3] = {ox, oy, oz};
+  const double k0 = 1.0 / h, k1 = -1.0 / h, m0 = 2.0 * h / 6.0, m1 = h / 6.0;
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    double t = (od[a] == 0) ? k0 : k1;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b)
+      if (b != a) t *= (od[b] == 0) ? m0 : m1;
+    s += t;
+  }
+  return s;
+}
+
+template <int DIM>
+__device__ __forceinline__ double mpat(int o, double h) {
+  int ox, oy, oz;
+  offs<DIM>(o, ox, oy, oz);
+  const double c = h / 6.0;
+  double s = ((ox == 0) ? 4.0 : 1.0) * c * ((oy == 0) ? 4.0 : 1.0) * c;
+  if (DIM == 3) s *= ((oz == 0) ? 4.0 : 1.0) * c;
+  return s;
+}
+
+template <int DIM>
+__device__ __forceinline__ void node_xyz(long long i, int m, int& x, int& y, int& z) {
+  x = (int)(i % m);
+  const long long q = i / m;
+  if (DIM == 3) {
+    y = (int)(q % m);
+    z = (int)(q / m);
+  } else {
+    y = (int)q;
+    z = 0;
+  }
+}
+
+// The 3^d A-coefficients of node (x,y,z) on the fine level, from kappa.
+template <int DIM>
+__device__ void kappa_coefs(const double* __restrict__ kappa, int m, double h, int x, int y, int z, double* c) {
+  const int n = m + 1;
+  // kappa of the 2^d cells around the node: cell (x + cx, y + cy, z + cz)
+  double kc[8];
+#pragma unroll
+  for (int q = 0; q < (1 << DIM); ++q) {
+    const int cx = q & 1, cy = (q >> 1) & 1, cz = (q >> 2) & 1;
+    long long e = (long long)(x + cx) + (long long)n * (y + cy);
+    if (DIM == 3) e += (long long)n * n * (z + cz);
+    kc[q] = kappa ? kappa[e] : 1.0;
+  }
+#pragma unroll
+  for (int o = 0; o < NSt<DIM>::v; ++o) {
+    int ox, oy, oz;
+    offs<DIM>(o, ox, oy, oz);
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q) {
+      const int cx = q & 1, cy = (q >> 1) & 1, cz = (q >> 2) & 1;
+      // cell holds both nodes iff for every axis with o != 0 the cell lies on that side
+      bool ok = (ox == 0 || cx == (ox > 0)) && (oy == 0 || cy == (oy > 0));
+      if (DIM == 3) ok = ok && (oz == 0 || cz == (oz > 0));
+      if (ok) s += kc[q];
+    }
+    c[o] = kpat<DIM>(o, h) * s;
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ long long flat_off(int o, int m) {
+  int ox, oy, oz;
+  offs<DIM>(o, ox, oy, oz);
+  long long f = ox + (long long)oy * m;
+  if (DIM == 3) f += (long long)oz * m * m;
+  return f;
+}
+
+template <int DIM, int SRC, int EPI>
+__global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs a, int slots, int nb, int tiles) {
+  constexpr int NS = NSt<DIM>::v;
+  __shared__ double sc[kMaxNb][NS];
+  __shared__ unsigned smask[kMaxNb];
+  __shared__ double sm[NS];
+  __shared__ double red[3][kBlock];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= tiles) return;
+  const long long n0 = (long long)tile * nb;
+  const int nloc = (int)((a.N - n0 < nb) ? (a.N - n0) : nb);
+  const int m = a.m;
+  for (int t = threadIdx.x; t < nloc; t += kBlock) {
+    int x, y, z;
+    node_xyz<DIM>(n0 + t, m, x, y, z);
+    unsigned mask = 0;
+#pragma unroll
+    for (int o = 0; o < NS; ++o) {
+      int ox, oy, oz;
+      offs<DIM>(o, ox, oy, oz);
+      bool ok = (x + ox >= 0) && (x + ox < m) && (y + oy >= 0) && (y + oy < m);
+      if (DIM == 3) ok = ok && (z + oz >= 0) && (z + oz < m);
+      mask |= ok ? (1u << o) : 0u;
+    }
+    smask[t] = mask;
+    if (EPI != EPI_AM || a.out1) {
+      if (SRC == (int)ASource::Kappa) {
+        double c[NS];
+        kappa_coefs<DIM>(a.kappa, m, a.h, x, y, z, c);
+#pragma unroll
+        for (int o = 0; o < NS; ++o) sc[t][o] = c[o];
+      } else {
+        const double* cp = a.coef + (n0 + t) * NS;
+#pragma unroll
+        for (int o = 0; o < NS; ++o) sc[t][o] = cp[o];
+      }
+    }
+  }
+  if (threadIdx.x < NS) sm[threadIdx.x] = mpat<DIM>(threadIdx.x, a.h);
+  __syncthreads();
+
+  const int k = a.k;
+  const int col = threadIdx.x % k;
+  const int slot = threadIdx.x / k;
+  const bool active = slot < slots;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  if (active) {
+    const double lamc = (EPI == EPI_EIGRES) ? a.lam[col] : 0.0;
+    for (int j = slot; j < nloc; j += slots) {
+      const long long node = n0 + j;
+      const long long idx = node * k + col;
+      const unsigned mask = smask[j];
+      double ax = 0.0, mx = 0.0;
+      const bool needA = (EPI != EPI_AM) || (a.out1 != nullptr);
+      const bool needM = (EPI == EPI_EIGRES) || (EPI == EPI_AM && a.out2 != nullptr);
+#pragma unroll
+      for (int o = 0; o < NS; ++o) {
+        if (mask & (1u << o)) {
+          const double v = a.x[idx + flat_off<DIM>(o, m) * k];
+          if (needA) ax = fma(sc[j][o], v, ax);
+          if (needM) mx = fma(sm[o], v, mx);
+        }
+      }
+      if (EPI == EPI_AM) {
+        if (a.out1) a.out1[idx] = ax;
+        if (a.out2) a.out2[idx] = mx;
+      } else if (EPI == EPI_RESID) {
+        a.out1[idx] = a.b[idx] - ax;
+      } else if (EPI == EPI_SWEEP) {
+        a.out1[idx] = a.x[idx] + a.omega * a.dinv[node] * (a.b[idx] - ax);
+      } else {  // EPI_EIGRES
+        const double r = lamc * mx - ax;
+        a.out1[idx] = r;
+        acc0 = fma(r, r, acc0);
+        acc1 = fma(mx, mx, acc1);
+        acc2 = fma(a.x[idx], mx, acc2);
+      }
+    }
+  }
+  if (EPI == EPI_EIGRES) {
+    red[0][threadIdx.x] = acc0;
+    red[1][threadIdx.x] = acc1;
+    red[2][threadIdx.x] = acc2;
+    __syncthreads();
+    if (threadIdx.x < k) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int s = 0; s < slots; ++s) {
+        s0 += red[0][s * k + threadIdx.x];
+        s1 += red[1][s * k + threadIdx.x];
+        s2 += red[2][s * k + threadIdx.x];
+      }
+      double* p = a.partial + (size_t)tile * 3 * k;
+      p[threadIdx.x] = s0;
+      p[k + threadIdx.x] = s1;
+      p[2 * k + threadIdx.x] = s2;
+    }
+  }
+}
+
+template <int DIM>
+__global__ void first_sweep_kernel(long long N, int k, const double* __restrict__ dinv, double omega,
+                                   const double* __restrict__ b, double* __restrict__ x) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  x[i] = omega * dinv[i / k] * b[i];
+}
+
+template <int DIM>
+__global__ void restrict_kernel(int mf, int mc, int k, const double* __restrict__ xf, double* __restrict__ xc) {
+  long long Nc = (long long)mc * mc;
+  if (DIM == 3) Nc *= mc;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Nc * k) return;
+  const long long node = i / k;
+  const int col = (int)(i % k);
+  int X, Y, Z;
+  node_xyz<DIM>(node, mc, X, Y, Z);
+  const int fx = 2 * X + 1, fy = 2 * Y + 1, fz = 2 * Z + 1;
+  double s = 0.0;
+  for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
+    const double wz = (oz == 0) ? 1.0 : 0.5;
+    for (int oy = -1; oy <= 1; ++oy) {
+      const double wy = (oy == 0) ? 1.0 : 0.5;
+      for (int ox = -1; ox <= 1; ++ox) {
+        const double wx = (ox == 0) ? 1.0 : 0.5;
+        long long f = (fx + ox) + (long long)mf * (fy + oy);
+        if (DIM == 3) f += (long long)mf * mf * (fz + oz);
+        s = fma(wx * wy * wz, xf[f * k + col], s);
+      }
+    }
+  }
+  xc[i] = s;
+}
+
+// Coarse indices and weights that interpolate fine coordinate f (ratio 2).
+__device__ __forceinline__ int p1d(int f, int mc, int* I, double* w) {
+  if (f & 1) {
+    I[0] = (f - 1) >> 1;
+    w[0] = 1.0;
+    return 1;
+  }
+  int c = 0;
+  const int a = (f >> 1) - 1, b = f >> 1;
+  if (a >= 0) { I[c] = a; w[c] = 0.5; ++c; }
+  if (b < mc) { I[c] = b; w[c] = 0.5; ++c; }
+  return c;
+}
+
+template <int DIM>
+__global__ void prolong_kernel(int mf, int mc, int k, const double* __restrict__ xc, double* __restrict__ xf,
+                               int mode) {
+  long long Nf = (long long)mf * mf;
+  if (DIM == 3) Nf *= mf;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Nf * k) return;
+  const long long node = i / k;
+  const int col = (int)(i % k);
+  int x, y, z;
+  node_xyz<DIM>(node, mf, x, y, z);
+  int Ix[2], Iy[2], Iz[2] = {0, 0};
+  double wx[2], wy[2], wz[2] = {1.0, 1.0};
+  const int nx = p1d(x, mc, Ix, wx), ny = p1d(y, mc, Iy, wy);
+  const int nz = (DIM == 3) ? p1d(z, mc, Iz, wz) : 1;
+  double s = 0.0;
+  for (int c = 0; c < nz; ++c)
+    for (int b = 0; b < ny; ++b)
+      for (int a = 0; a < nx; ++a) {
+        long long J = Ix[a] + (long long)mc * Iy[b];
+        if (DIM == 3) J += (long long)mc * mc * Iz[c];
+        s = fma(wx[a] * wy[b] * wz[c], xc[J * k + col], s);
+      }
+  if (mode == 0) xf[i] = s;
+  else if (mode == 1) xf[i] += s;
+  else xf[i] -= s;
+}
+
+template <int DIM>
+__global__ void kappa_dinv_kernel(int n, const double* __restrict__ kappa, double* __restrict__ dinv) {
+  const int m = n - 1;
+  long long N = (long long)m * m;
+  if (DIM == 3) N *= m;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int x, y, z;
+  node_xyz<DIM>(i, m, x, y, z);
+  double c[NSt<DIM>::v];
+  kappa_coefs<DIM>(kappa, m, 1.0 / n, x, y, z, c);
+  dinv[i] = 1.0 / c[NSt<DIM>::v / 2];
+}
+
+template <int DIM>
+__device__ __forceinline__ int color_of(int x, int y, int z) {
+  return (x % 3) + 3 * (y % 3) + ((DIM == 3) ? 9 * (z % 3) : 0);
+}
+
+template <int DIM>
+__global__ void color_probe_kernel(int m, double* __restrict__ E) {
+  constexpr int NS = NSt<DIM>::v;
+  long long N = (long long)m * m;
+  if (DIM == 3) N *= m;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * NS) return;
+  const long long node = i / NS;
+  const int c = (int)(i % NS);
+  int x, y, z;
+  node_xyz<DIM>(node, m, x, y, z);
+  E[i] = (color_of<DIM>(x, y, z) == c) ? 1.0 : 0.0;
+}
+
+// Y = (P^T A P) E for the colour probes E: Y[I, colour(J)] = A_c[I, J] for the
+// unique J of that colour within distance 1 of I.
+template <int DIM>
+__global__ void extract_galerkin_kernel(int m, const double* __restrict__ Y, double* __restrict__ coef,
+                                        double* __restrict__ dinv) {
+  constexpr int NS = NSt<DIM>::v;
+  long long N = (long long)m * m;
+  if (DIM == 3) N *= m;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int x, y, z;
+  node_xyz<DIM>(i, m, x, y, z);
+  for (int o = 0; o < NS; ++o) {
+    int ox, oy, oz;
+    offs<DIM>(o, ox, oy, oz);
+    bool ok = (x + ox >= 0) && (x + ox < m) && (y + oy >= 0) && (y + oy < m);
+    if (DIM == 3) ok = ok && (z + oz >= 0) && (z + oz < m);
+    coef[i * NS + o] = ok ? Y[i * NS + color_of<DIM>(x + ox, y + oy, z + oz)] : 0.0;
+  }
+  dinv[i] = 1.0 / coef[i * NS + NS / 2];
+}
+
+template <int DIM>
+__global__ void stencil_to_dense_kernel(int m, const double* __restrict__ coef, double hmass, int use_mass,
+                                        double* __restrict__ D) {
+  constexpr int NS = NSt<DIM>::v;
+  long long N = (long long)m * m;
+  if (DIM == 3) N *= m;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int x, y, z;
+  node_xyz<DIM>(i, m, x, y, z);
+  for (long long j = 0; j < N; ++j) D[i * N + j] = 0.0;
+  for (int o = 0; o < NS; ++o) {
+    int ox, oy, oz;
+    offs<DIM>(o, ox, oy, oz);
+    bool ok = (x + ox >= 0) && (x + ox < m) && (y + oy >= 0) && (y + oy < m);
+    if (DIM == 3) ok = ok && (z + oz >= 0) && (z + oz < m);
+    if (!ok) continue;
+    const long long j = i + flat_off<DIM>(o, m);
+    D[i * N + j] = use_mass ? mpat<DIM>(o, hmass) : coef[i * NS + o];
+  }
+}
+
+inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+GridLaunch grid_launch(long long N, int k) {
+  GridLaunch g;
+  g.slots = kBlock / k;
+  if (g.slots > kMaxNb) g.slots = kMaxNb;
+  if (g.slots < 1) g.slots = 1;
+  const int npass = (kMaxNb / g.slots) > 0 ? (kMaxNb / g.slots) : 1;
+  g.nb = g.slots * npass;
+  g.tiles = (int)((N + g.nb - 1) / g.nb);
+  g.blocks = ((g.tiles + 7) / 8) * 8;
+  return g;
+}
+
+template <int DIM, int SRC>
+static void stencil_dispatch_epi(const StencilArgs& a, Epi epi, const GridLaunch& g, hipStream_t s) {
+  switch (epi) {
+    case EPI_AM:
+      stencil_kernel<DIM, SRC, EPI_AM><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
+      break;
+    case EPI_RESID:
+      stencil_kernel<DIM, SRC, EPI_RESID><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
+      break;
+    case EPI_SWEEP:
+      stencil_kernel<DIM, SRC, EPI_SWEEP><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
+      break;
+    case EPI_EIGRES:
+      stencil_kernel<DIM, SRC, EPI_EIGRES><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
+      break;
+  }
+}
+
+void launch_stencil(const StencilArgs& a, Epi epi, hipStream_t s) {
+  const GridLaunch g = grid_launch(a.N, a.k);
+  if (a.dim == 3) {
+    if (a.src == ASource::Kappa) stencil_dispatch_epi<3, 0>(a, epi, g, s);
+    else stencil_dispatch_epi<3, 1>(a, epi, g, s);
+  } else {
+    if (a.src == ASource::Kappa) stencil_dispatch_epi<2, 0>(a, epi, g, s);
+    else stencil_dispatch_epi<2, 1>(a, epi, g, s);
+  }
+}
+
+void launch_first_sweep(int dim, long long N, int k, const double* dinv, double omega, const double* b, double* x,
+                        hipStream_t s) {
+  if (dim == 3) first_sweep_kernel<3><<<nblk(N * k), kBlock, 0, s>>>(N, k, dinv, omega, b, x);
+  else first_sweep_kernel<2><<<nblk(N * k), kBlock, 0, s>>>(N, k, dinv, omega, b, x);
+}
+
+void launch_restrict(int dim, int mf, int mc, int k, const double* xf, double* xc, hipStream_t s) {
+  long long Nc = (long long)mc * mc * (dim == 3 ? mc : 1);
+  if (dim == 3) restrict_kernel<3><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, k, xf, xc);
+  else restrict_kernel<2><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, k, xf, xc);
+}
+
+void launch_prolong(int dim, int mf, int mc, int k, const double* xc, double* xf, int mode, hipStream_t s) {
+  long long Nf = (long long)mf * mf * (dim == 3 ? mf : 1);
+  if (dim == 3) prolong_kernel<3><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
+  else prolong_kernel<2><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
+}
+
+void launch_kappa_dinv(int dim, int n, const double* kappa, double* dinv, hipStream_t s) {
+  const long long N = (long long)(n - 1) * (n - 1) * (dim == 3 ? (n - 1) : 1);
+  if (dim == 3) kappa_dinv_kernel<3><<<nblk(N), kBlock, 0, s>>>(n, kappa, dinv);
+  else kappa_dinv_kernel<2><<<nblk(N), kBlock, 0, s>>>(n, kappa, dinv);
+}
+
+void launch_color_probe(int dim, int m, double* E, hipStream_t s) {
+  const long long N = (long long)m * m * (dim == 3 ? m : 1);
+  if (dim == 3) color_probe_kernel<3><<<nblk(N * 27), kBlock, 0, s>>>(m, E);
+  else color_probe_kernel<2><<<nblk(N * 9), kBlock, 0, s>>>(m, E);
+}
+
+void launch_extract_galerkin(int dim, int m, const double* Y, double* coef, double* dinv, hipStream_t s) {
+  const long long N = (long long)m * m * (dim == 3 ? m : 1);
+  if (dim == 3) extract_galerkin_kernel<3><<<nblk(N), kBlock, 0, s>>>(m, Y, coef, dinv);
+  else extract_galerkin_kernel<2><<<nblk(N), kBlock, 0, s>>>(m, Y, coef, dinv);
+}
+
+void launch_stencil_to_dense(int dim, int m, const double* coef, double hmass, int use_mass, double* D,
+                             hipStream_t s) {
+  const long long N = (long long)m * m * (dim == 3 ? m : 1);
+  if (dim == 3) stencil_to_dense_kernel<3><<<nblk(N), kBlock, 0, s>>>(m, coef, hmass, use_mass, D);
+  else stencil_to_dense_kernel<2><<<nblk(N), kBlock, 0, s>>>(m, coef, hmass, use_mass, D);
+}
+
+}  // namespace pase

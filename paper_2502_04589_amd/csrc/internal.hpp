@@ -1,0 +1,115 @@
+// Internal declarations shared by the HIP translation units of libpase.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/pase.h"
+
+namespace pase {
+
+constexpr int kBlock = 256;          // threads per block of the grid kernels
+constexpr int kMaxStencil = 27;      // 3^dim neighbours
+
+// One grid level of the hierarchy.
+struct Level {
+  int n = 0;                 // elements per side
+  int m = 0;                 // interior nodes per side (n - 1)
+  long long N = 0;           // m^dim
+  double h = 0.0;            // mesh width 1/n
+  const double* kappa = nullptr;   // level 0: element coefficients (n^dim)
+  double* coef = nullptr;          // levels >= 1: assembled A stencil, N x 3^dim
+  double* dinv = nullptr;          // 1 / diag(A), N
+};
+
+// Stencil source of the operator A on a level.
+enum class ASource : int { Kappa = 0, Assembled = 1 };
+
+// Epilogue of the stencil kernel.
+enum Epi : int {
+  EPI_AM = 0,       // out1 = A x (opt), out2 = M x (opt)
+  EPI_RESID = 1,    // out1 = b - A x
+  EPI_SWEEP = 2,    // out1 = x + omega D^{-1} (b - A x)
+  EPI_EIGRES = 3,   // out1 = lambda_j M x - A x; partials of |out1|^2, |M x|^2, x.(M x) per column
+};
+
+struct StencilArgs {
+  int dim;
+  int m;                 // interior nodes per side
+  long long N;
+  int k;                 // columns (<= 256)
+  double h;
+  ASource src;
+  const double* kappa;   // Kappa source
+  const double* coef;    // Assembled source (N x 3^dim)
+  const double* dinv;
+  const double* x;
+  const double* b;       // rhs for RESID / SWEEP
+  const double* lam;     // EIGRES: k values (device)
+  double* out1;
+  double* out2;
+  double* partial;       // EIGRES: [tiles][3][k]
+  double omega;
+};
+
+// ---- grid kernels (grid.hip)
+struct GridLaunch {
+  int slots;        // nodes processed side by side per pass (256 / k)
+  int nb;           // nodes per block
+  int tiles;        // logical tiles
+  int blocks;       // launched blocks (tiles rounded up to a multiple of 8)
+};
+GridLaunch grid_launch(long long N, int k);
+void launch_stencil(const StencilArgs& a, Epi epi, hipStream_t s);
+void launch_first_sweep(int dim, long long N, int k, const double* dinv, double omega,
+                        const double* b, double* x, hipStream_t s);
+// restriction xc = P^T xf (ratio 2), prolongation xf (op)= P xc; mode 0: xf = P xc, 1: xf += P xc, 2: xf -= P xc
+void launch_restrict(int dim, int mf, int mc, int k, const double* xf, double* xc, hipStream_t s);
+void launch_prolong(int dim, int mf, int mc, int k, const double* xc, double* xf, int mode, hipStream_t s);
+// setup helpers
+void launch_kappa_dinv(int dim, int n, const double* kappa, double* dinv, hipStream_t s);
+void launch_color_probe(int dim, int m, double* E, hipStream_t s);                 // N x 3^dim
+void launch_extract_galerkin(int dim, int m, const double* Y, double* coef, double* dinv, hipStream_t s);
+void launch_stencil_to_dense(int dim, int m, const double* coef, double hmass, int use_mass, double* D,
+                             hipStream_t s);
+
+// ---- BLAS-like kernels (blas.hip)
+// per-column dot products of N x k blocks: out[j] = sum_i X[i,j] Y[i,j] (fixed-order two-pass)
+void launch_coldot(long long N, int k, const double* X, const double* Y, double* partial, int ptiles,
+                   double* out, hipStream_t s);
+int coldot_tiles(long long N, int k);
+void launch_reduce_partials(int tiles, int width, const double* partial, double* out, hipStream_t s);
+// PCG scalars / updates
+void launch_pcg_alpha(int k, const double* rho, const double* pq, double* alpha, hipStream_t s);
+void launch_pcg_beta(int k, const double* rho_new, const double* rho_old, double* beta, hipStream_t s);
+void launch_axpy2(long long N, int k, const double* alpha, const double* P, const double* Q, double* X,
+                  double* R, hipStream_t s);                    // X += a P ; R -= a Q
+void launch_xpby(long long N, int k, const double* Z, const double* beta, double* P, hipStream_t s);  // P = Z + b P
+void launch_copy(size_t n, const double* src, double* dst, hipStream_t s);
+// Gram G = X^T Y (k x k) by FP64 MFMA over row chunks, fixed-order reduction
+int gram_tiles(long long N, int k);
+void launch_gram(long long N, int k, const double* X, const double* Y, double* partial, int tiles, double* G,
+                 hipStream_t s);
+// C = alpha op(A) op(B) + beta C, row-major, FP64
+void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
+                 int ldb, double beta, double* C, int ldc, hipStream_t s);
+// tall-skinny: Y = X C (+ Y): X N x k, C k x k, Y N x k  (MFMA)
+void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, hipStream_t s);
+// small helpers
+void launch_set_diag_block(int n, int nh, int k, const double* C0, const double* G, const double* H, double* T,
+                           hipStream_t s);
+
+// ---- dense single-workgroup kernels (dense.hip)
+// In-place lower Cholesky of an n x n SPD matrix (row-major); info[0] = 0 ok, j+1 if pivot j failed.
+void launch_cholesky(int n, double* A, int lda, int* info, hipStream_t s);
+// Li = L^{-1} (lower) from a lower factor L; Li must not alias L.
+void launch_trinv(int n, const double* L, int ldl, double* Li, int ldi, hipStream_t s);
+// lowest k eigenpairs of dense symmetric T (n x n); T is overwritten; w, V device; work >= syev_work_doubles(n,k)
+size_t syev_work_doubles(int n, int k);
+void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s);
+int syev_max_n();
+void launch_symmetrize(int n, double* A, hipStream_t s);
+
+}  // namespace pase

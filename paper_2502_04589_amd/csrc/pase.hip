@@ -1,0 +1,751 @@
+// Host runtime and C ABI of libpase: hierarchy setup, the V-cycle, the CG
+// solves, the projection onto V_H + span{W}, the small eigenproblem and the
+// outer loop (paper Alg. 3, one correction step = Alg. 1).
+//
+// Basis of the augmented space used for step (c): the columns of
+// [P L_B^{-T}, W_perp L^{-T}], where B_H = L_B L_B^T, W_perp is W made
+// M-orthogonal to V_H (the vector form of the PRECOND-B factorisation of
+// Sec. 4) and W_perp^T M W_perp = L L^T.  The basis is M-orthonormal, so the
+// augmented pencil (A_Hh, B_Hh) becomes the standard symmetric matrix
+//   T = [[L_B^{-1} A_H L_B^{-T},  L_B^{-1} P^T A W_perp L^{-T}],
+//        [        (sym)        ,  L^{-1} W_perp^T A W_perp L^{-T}]]
+// whose k smallest eigenpairs are the Ritz pairs of V_H + span{W}.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace pase;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Bump {
+  char* base;
+  size_t off = 0;
+  explicit Bump(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct pase_handle {
+  pase_problem prob{};
+  pase_options opt{};
+  hipStream_t stream = nullptr;
+  int dim = 0, L = 0, NS = 0, K = 0;    // L = index of the coarsest level
+  Level lev[PASE_MAX_LEVELS];
+  // fine multi-vectors (N0 x K)
+  double *U = nullptr, *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *Q = nullptr;
+  double *W2 = nullptr, *W3 = nullptr;
+  // V-cycle buffers per level (level 0 uses xa and r only)
+  double *vb[PASE_MAX_LEVELS] = {}, *vx[PASE_MAX_LEVELS] = {}, *vxa[PASE_MAX_LEVELS] = {}, *vr[PASE_MAX_LEVELS] = {};
+  double* kappa = nullptr;
+  // coarse dense (NH x NH)
+  double *AinvL = nullptr, *LBinv = nullptr, *BHinv = nullptr, *C0 = nullptr, *dtmp = nullptr;
+  // small problem
+  int nT = 0;
+  double *Tm = nullptr, *Vs = nullptr, *syw = nullptr;
+  double *ca = nullptr, *cb = nullptr, *cc = nullptr;     // NH x K
+  double *kk1 = nullptr, *kk2 = nullptr, *kk3 = nullptr, *kk4 = nullptr, *kk5 = nullptr;   // K x K
+  // column scalars
+  double *lam = nullptr, *rho = nullptr, *rho2 = nullptr, *pq = nullptr, *alpha = nullptr, *beta = nullptr;
+  double* sums = nullptr;       // 3K
+  double* partial = nullptr;
+  size_t partial_doubles = 0;
+  int* info = nullptr;          // device status words
+  double* setup_scratch = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+};
+
+namespace {
+
+pase_status fail(pase_handle* h, pase_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  g_last_error = msg;
+  return s;
+}
+
+#define HIPC(call)                                                                        \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(h, PASE_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+long long level_nodes(int dim, int n) {
+  long long m = n - 1;
+  return dim == 3 ? m * m * m : m * m;
+}
+
+pase_status check_problem(const pase_problem* p, const pase_options* o) {
+  if (!p || !o) return PASE_E_ARG;
+  if (p->dim != 2 && p->dim != 3) return PASE_E_ARG;
+  if (p->nlevels < 2 || p->nlevels > PASE_MAX_LEVELS) return PASE_E_ARG;
+  for (int l = 0; l < p->nlevels; ++l) {
+    if (p->n[l] < 2) return PASE_E_ARG;
+    if (l > 0 && p->n[l - 1] != 2 * p->n[l]) return PASE_E_ARG;
+  }
+  if (o->nev_max < 1 || o->nev_max > PASE_MAX_NEV) return PASE_E_ARG;
+  if (o->cg_steps < 1 || o->max_outer < 0 || o->nu < 1) return PASE_E_ARG;
+  if (!(o->omega > 0.0)) return PASE_E_ARG;
+  if (o->precision != PASE_PREC_FP64) return PASE_E_UNSUPPORTED;
+  return PASE_OK;
+}
+
+// Lays out the workspace; with base == nullptr only counts bytes.
+size_t layout(pase_handle* h, void* base) {
+  Bump b(base);
+  const int dim = h->dim;
+  const long long N0 = h->lev[0].N;
+  const size_t K = h->K;
+  const size_t NS = h->NS;
+  const size_t mv = (size_t)N0 * K;
+  // fine multi-vectors; setup reuses this block as scratch
+  const size_t fine_doubles = std::max<size_t>(10 * mv, 3 * (size_t)N0 * NS + 64);
+  double* fine = b.take<double>(fine_doubles);
+  h->setup_scratch = fine;
+  double* f = fine;
+  auto nxt = [&](size_t n) { double* r = f; if (f) f += n; return r; };
+  h->U = nxt(mv); h->X = nxt(mv); h->R = nxt(mv); h->Z = nxt(mv); h->P = nxt(mv); h->Q = nxt(mv);
+  h->W2 = nxt(mv); h->W3 = nxt(mv);
+  h->vxa[0] = nxt(mv); h->vr[0] = nxt(mv);
+  const long long ne = (long long)h->lev[0].n * h->lev[0].n * (dim == 3 ? h->lev[0].n : 1);
+  h->kappa = b.take<double>((size_t)ne);
+  h->lev[0].dinv = b.take<double>((size_t)N0);
+  for (int l = 1; l <= h->L; ++l) {
+    const size_t Nl = (size_t)h->lev[l].N;
+    h->lev[l].coef = b.take<double>(Nl * NS);
+    h->lev[l].dinv = b.take<double>(Nl);
+    h->vb[l] = b.take<double>(Nl * K);
+    h->vx[l] = b.take<double>(Nl * K);
+    h->vxa[l] = b.take<double>(Nl * K);
+    h->vr[l] = b.take<double>(Nl * K);
+  }
+  const size_t NH = (size_t)h->lev[h->L].N;
+  h->AinvL = b.take<double>(NH * NH);
+  h->LBinv = b.take<double>(NH * NH);
+  h->BHinv = b.take<double>(NH * NH);
+  h->C0 = b.take<double>(NH * NH);
+  h->dtmp = b.take<double>(NH * NH);
+  h->nT = (int)(NH + K);
+  const size_t nT = (size_t)h->nT;
+  if (h->nT <= syev_max_n()) {
+    h->Tm = b.take<double>(nT * nT);
+    h->Vs = b.take<double>(nT * K);
+    h->syw = b.take<double>(syev_work_doubles(h->nT, (int)K));
+  }
+  h->ca = b.take<double>(NH * K);
+  h->cb = b.take<double>(NH * K);
+  h->cc = b.take<double>(NH * K);
+  h->kk1 = b.take<double>(K * K); h->kk2 = b.take<double>(K * K); h->kk3 = b.take<double>(K * K);
+  h->kk4 = b.take<double>(K * K); h->kk5 = b.take<double>(K * K);
+  h->lam = b.take<double>(K); h->rho = b.take<double>(K); h->rho2 = b.take<double>(K);
+  h->pq = b.take<double>(K); h->alpha = b.take<double>(K); h->beta = b.take<double>(K);
+  h->sums = b.take<double>(3 * K);
+  // partials: max over coldot, gram and eig-residual reductions for every k <= K
+  size_t pd = 0;
+  for (int k = 1; k <= (int)K; ++k) {
+    pd = std::max(pd, (size_t)coldot_tiles(N0, k) * k);
+    pd = std::max(pd, (size_t)gram_tiles(N0, k) * k * k);
+    pd = std::max(pd, (size_t)grid_launch(N0, k).blocks * 3 * k);
+  }
+  h->partial_doubles = pd;
+  h->partial = b.take<double>(pd);
+  h->info = b.take<int>(16);
+  return b.off + 256;
+}
+
+// ----------------------------------------------------------------- operators
+StencilArgs stencil_args(pase_handle* h, int l, int k) {
+  StencilArgs a{};
+  const Level& lv = h->lev[l];
+  a.dim = h->dim;
+  a.m = lv.m;
+  a.N = lv.N;
+  a.k = k;
+  a.h = lv.h;
+  a.src = (l == 0) ? ASource::Kappa : ASource::Assembled;
+  a.kappa = h->kappa;
+  a.coef = lv.coef;
+  a.dinv = lv.dinv;
+  a.omega = h->opt.omega;
+  return a;
+}
+
+void apply_AM(pase_handle* h, int l, int k, const double* x, double* ax, double* mx) {
+  StencilArgs a = stencil_args(h, l, k);
+  a.x = x;
+  a.out1 = ax;
+  a.out2 = mx;
+  launch_stencil(a, EPI_AM, h->stream);
+}
+
+// x = V(b) on level l (x must not alias b)
+void vcycle(pase_handle* h, int l, int k, const double* b, double* x) {
+  hipStream_t s = h->stream;
+  if (l == h->L) {
+    const int NH = (int)h->lev[l].N;
+    launch_gemm(false, false, NH, k, NH, 1.0, h->AinvL, NH, b, k, 0.0, x, k, s);
+    return;
+  }
+  const Level& lv = h->lev[l];
+  double* t0 = h->vxa[l];
+  double* t1 = x;
+  // sweeps alternate t0, t1, t0, ...; the last of the 2 nu sweeps lands in t1 = x
+  launch_first_sweep(h->dim, lv.N, k, lv.dinv, h->opt.omega, b, t0, s);
+  double* cur = t0;
+  double* oth = t1;
+  StencilArgs a = stencil_args(h, l, k);
+  a.b = b;
+  for (int i = 1; i < h->opt.nu; ++i) {
+    a.x = cur; a.out1 = oth;
+    launch_stencil(a, EPI_SWEEP, s);
+    std::swap(cur, oth);
+  }
+  a.x = cur; a.out1 = h->vr[l];
+  launch_stencil(a, EPI_RESID, s);
+  launch_restrict(h->dim, lv.m, h->lev[l + 1].m, k, h->vr[l], h->vb[l + 1], s);
+  vcycle(h, l + 1, k, h->vb[l + 1], h->vx[l + 1]);
+  launch_prolong(h->dim, lv.m, h->lev[l + 1].m, k, h->vx[l + 1], cur, 1, s);
+  for (int i = 0; i < h->opt.nu; ++i) {
+    a.x = cur; a.out1 = oth;
+    launch_stencil(a, EPI_SWEEP, s);
+    std::swap(cur, oth);
+  }
+}
+
+// composite restriction: xc (N_L x k) = P^T xf
+void restrict_all(pase_handle* h, int k, const double* xf, double* xc) {
+  const double* src = xf;
+  for (int l = 0; l < h->L; ++l) {
+    double* dst = (l + 1 == h->L) ? xc : h->vr[l + 1];
+    launch_restrict(h->dim, h->lev[l].m, h->lev[l + 1].m, k, src, dst, h->stream);
+    src = dst;
+  }
+}
+
+// composite prolongation into the fine level: xf (=, +=, -=) P xc
+void prolong_all(pase_handle* h, int k, const double* xc, double* xf, int mode) {
+  const double* src = xc;
+  for (int l = h->L; l >= 1; --l) {
+    double* dst = (l == 1) ? xf : h->vxa[l - 1];
+    launch_prolong(h->dim, h->lev[l - 1].m, h->lev[l].m, k, src, dst, (l == 1) ? mode : 0, h->stream);
+    src = dst;
+  }
+}
+
+void coldot(pase_handle* h, long long N, int k, const double* x, const double* y, double* out) {
+  launch_coldot(N, k, x, y, h->partial, 0, out, h->stream);
+}
+
+// s PCG steps per column on A x = b from x (in X), with residual R = b - A x given.
+void pcg(pase_handle* h, int k, double* X, double* R) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  vcycle(h, 0, k, R, h->Z);
+  launch_copy((size_t)N * k, h->Z, h->P, s);
+  coldot(h, N, k, R, h->Z, h->rho);
+  for (int j = 0; j < h->opt.cg_steps; ++j) {
+    apply_AM(h, 0, k, h->P, h->Q, nullptr);
+    coldot(h, N, k, h->P, h->Q, h->pq);
+    launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
+    launch_axpy2(N, k, h->alpha, h->P, h->Q, X, R, s);
+    if (j + 1 < h->opt.cg_steps) {
+      vcycle(h, 0, k, R, h->Z);
+      coldot(h, N, k, R, h->Z, h->rho2);
+      launch_pcg_beta(k, h->rho2, h->rho, h->beta, s);
+      launch_xpby(N, k, h->Z, h->beta, h->P, s);
+      std::swap(h->rho, h->rho2);
+    }
+  }
+}
+
+// R = lam M U - A U with fused column sums (|R|^2, |MU|^2, U.MU) into h->sums
+void eig_residual(pase_handle* h, int k, const double* U, double* R) {
+  StencilArgs a = stencil_args(h, 0, k);
+  a.x = U;
+  a.lam = h->lam;
+  a.out1 = R;
+  a.partial = h->partial;
+  launch_stencil(a, EPI_EIGRES, h->stream);
+  const GridLaunch g = grid_launch(h->lev[0].N, k);
+  launch_reduce_partials(g.tiles, 3 * k, h->partial, h->sums, h->stream);
+}
+
+// Cholesky-QR in the M inner product: U <- U L^{-T}, U^T M U = L L^T.  info slot 'slot'.
+void cholqr_m(pase_handle* h, int k, double*& U, double*& spare, int slot) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  apply_AM(h, 0, k, U, nullptr, h->W3);
+  launch_gram(N, k, U, h->W3, h->partial, gram_tiles(N, k), h->kk1, s);
+  launch_symmetrize(k, h->kk1, s);
+  launch_cholesky(k, h->kk1, k, h->info + slot, s);
+  launch_trinv(k, h->kk1, k, h->kk2, k, s);
+  launch_gemm(false, true, (int)N, k, k, 1.0, U, k, h->kk2, k, 0.0, spare, k, s);
+  std::swap(U, spare);
+}
+
+// One correction from (lam, U), U^T M U = I, with R = lam M U - A U already in h->R.
+// Returns new U in h->U (pointer members may be swapped).
+pase_status correction(pase_handle* h, int k) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  const int NH = (int)h->lev[h->L].N;
+  // (a) fine solves A w = lam M u from w = u: s CG steps per column
+  launch_copy((size_t)N * k, h->U, h->X, s);
+  pcg(h, k, h->X, h->R);
+  double* W = h->X;
+  // complement: W <- W - P B_H^{-1} P^T M W
+  apply_AM(h, 0, k, W, nullptr, h->W3);
+  restrict_all(h, k, h->W3, h->ca);
+  launch_gemm(false, false, NH, k, NH, 1.0, h->BHinv, NH, h->ca, k, 0.0, h->cb, k, s);
+  prolong_all(h, k, h->cb, W, 2);
+  // (b) projection: A W, M W, a = P^T A W, alpha = W^T A W, beta = W^T M W
+  apply_AM(h, 0, k, W, h->W2, h->W3);
+  restrict_all(h, k, h->W2, h->ca);
+  launch_gram(N, k, W, h->W2, h->partial, gram_tiles(N, k), h->kk1, s);   // alpha
+  launch_gram(N, k, W, h->W3, h->partial, gram_tiles(N, k), h->kk2, s);   // beta
+  launch_symmetrize(k, h->kk1, s);
+  launch_symmetrize(k, h->kk2, s);
+  launch_cholesky(k, h->kk2, k, h->info + 1, s);           // beta = L L^T
+  launch_trinv(k, h->kk2, k, h->kk3, k, s);                // Li = L^{-1}
+  // H = Li alpha Li^T
+  launch_gemm(false, false, k, k, k, 1.0, h->kk3, k, h->kk1, k, 0.0, h->kk4, k, s);
+  launch_gemm(false, true, k, k, k, 1.0, h->kk4, k, h->kk3, k, 0.0, h->kk5, k, s);
+  launch_symmetrize(k, h->kk5, s);
+  // G = LB^{-1} a Li^T
+  launch_gemm(false, false, NH, k, NH, 1.0, h->LBinv, NH, h->ca, k, 0.0, h->cb, k, s);
+  launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->cc, k, s);
+  // (c) small problem
+  const int nT = NH + k;
+  launch_set_diag_block(nT, NH, k, h->C0, h->cc, h->kk5, h->Tm, s);
+  launch_syev_lowest(nT, k, h->Tm, h->lam, h->Vs, h->syw, h->info + 2, s);
+  // coordinates: y_H = LB^{-T} V_H, y_W = Li^T V_W
+  launch_gemm(true, false, NH, k, NH, 1.0, h->LBinv, NH, h->Vs, k, 0.0, h->ca, k, s);
+  launch_gemm(true, false, k, k, k, 1.0, h->kk3, k, h->Vs + (size_t)NH * k, k, 0.0, h->kk4, k, s);
+  // prolongation: U = P y_H + W y_W
+  prolong_all(h, k, h->ca, h->U, 0);
+  launch_gemm(false, false, (int)N, k, k, 1.0, W, k, h->kk4, k, 1.0, h->U, k, s);
+  return PASE_OK;
+}
+
+pase_status read_info(pase_handle* h, int* out, int n) {
+  HIPC(hipMemcpyAsync(out, h->info, sizeof(int) * n, hipMemcpyDeviceToHost, h->stream));
+  HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
+pase_status check_k(pase_handle* h, int k) {
+  if (!h) return fail(nullptr, PASE_E_ARG, "null handle");
+  if (k < 1 || k > h->K) return fail(h, PASE_E_ARG, "k must be in [1, nev_max]");
+  return PASE_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+void pase_options_default(pase_options* opt) {
+  if (!opt) return;
+  opt->precision = PASE_PREC_FP64;
+  opt->nev_max = 16;
+  opt->cg_steps = 2;
+  opt->max_outer = 500;
+  opt->nu = 2;
+  opt->omega = 2.0 / 3.0;
+}
+
+const char* pase_status_string(pase_status s) {
+  switch (s) {
+    case PASE_OK: return "ok";
+    case PASE_E_ARG: return "invalid argument";
+    case PASE_E_HIP: return "HIP runtime error";
+    case PASE_E_NOMEM: return "workspace too small";
+    case PASE_E_NOTCONV: return "not converged";
+    case PASE_E_BREAKDOWN: return "breakdown (non-SPD Gram or non-finite values)";
+    case PASE_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* pase_last_error(const pase_handle* h) { return h ? h->err.c_str() : g_last_error.c_str(); }
+
+pase_status pase_workspace_bytes(const pase_problem* prob, const pase_options* opt, size_t* bytes) {
+  pase_handle* h = nullptr;
+  if (!bytes) return fail(h, PASE_E_ARG, "bytes is null");
+  const pase_status st = check_problem(prob, opt);
+  if (st != PASE_OK) return fail(h, st, "invalid or unsupported problem/options");
+  pase_handle tmp;
+  tmp.dim = prob->dim;
+  tmp.L = prob->nlevels - 1;
+  tmp.NS = prob->dim == 3 ? 27 : 9;
+  tmp.K = opt->nev_max;
+  for (int l = 0; l < prob->nlevels; ++l) {
+    tmp.lev[l].n = prob->n[l];
+    tmp.lev[l].m = prob->n[l] - 1;
+    tmp.lev[l].N = level_nodes(prob->dim, prob->n[l]);
+  }
+  *bytes = layout(&tmp, nullptr);
+  return PASE_OK;
+}
+
+pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* workspace, size_t workspace_bytes,
+                       void* stream, pase_handle** out) {
+  pase_handle* h = nullptr;
+  if (!out) return fail(h, PASE_E_ARG, "out is null");
+  *out = nullptr;
+  const pase_status st = check_problem(prob, opt);
+  if (st != PASE_OK) return fail(h, st, "invalid or unsupported problem/options");
+  if (!workspace) return fail(h, PASE_E_ARG, "workspace is null");
+  if (((uintptr_t)workspace) & 255) return fail(h, PASE_E_ARG, "workspace must be 256-byte aligned");
+  h = new pase_handle();
+  h->prob = *prob;
+  h->opt = *opt;
+  h->stream = (hipStream_t)stream;
+  h->dim = prob->dim;
+  h->L = prob->nlevels - 1;
+  h->NS = prob->dim == 3 ? 27 : 9;
+  h->K = opt->nev_max;
+  for (int l = 0; l < prob->nlevels; ++l) {
+    h->lev[l].n = prob->n[l];
+    h->lev[l].m = prob->n[l] - 1;
+    h->lev[l].N = level_nodes(prob->dim, prob->n[l]);
+    h->lev[l].h = 1.0 / prob->n[l];
+  }
+  const size_t need = layout(h, nullptr);
+  if (workspace_bytes < need) {
+    const pase_status r = fail(h, PASE_E_NOMEM, "workspace smaller than pase_workspace_bytes");
+    delete h;
+    return r;
+  }
+  layout(h, workspace);
+  h->lev[0].kappa = h->kappa;
+  hipStream_t s = h->stream;
+  auto bail = [&](pase_status r) {
+    g_last_error = h->err;
+    delete h;
+    return r;
+  };
+#define HIPS(call)                                                                            \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      fail(h, PASE_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));                 \
+      return bail(PASE_E_HIP);                                                                \
+    }                                                                                         \
+  } while (0)
+  const Level& f = h->lev[0];
+  const size_t ne = (size_t)f.n * f.n * (h->dim == 3 ? f.n : 1);
+  if (prob->kappa) {
+    HIPS(hipMemcpyAsync(h->kappa, prob->kappa, ne * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    std::vector<double> ones(ne, 1.0);
+    HIPS(hipMemcpyAsync(h->kappa, ones.data(), ne * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPS(hipStreamSynchronize(s));
+  }
+  launch_kappa_dinv(h->dim, f.n, h->kappa, h->lev[0].dinv, s);
+  // Galerkin stencils A_l = P_l^T A_{l-1} P_l from 3^d colour probes
+  const int NS = h->NS;
+  for (int l = 1; l <= h->L; ++l) {
+    const Level& c = h->lev[l];
+    const Level& p = h->lev[l - 1];
+    double* E = h->setup_scratch;
+    double* PE = E + (size_t)c.N * NS;
+    double* APE = PE + (size_t)p.N * NS;
+    launch_color_probe(h->dim, c.m, E, s);
+    launch_prolong(h->dim, p.m, c.m, NS, E, PE, 0, s);
+    apply_AM(h, l - 1, NS, PE, APE, nullptr);
+    launch_restrict(h->dim, p.m, c.m, NS, APE, E, s);
+    launch_extract_galerkin(h->dim, c.m, E, h->lev[l].coef, h->lev[l].dinv, s);
+  }
+  // coarse dense factorisations
+  const Level& cl = h->lev[h->L];
+  const int NH = (int)cl.N;
+  double* AL = h->dtmp;
+  launch_stencil_to_dense(h->dim, cl.m, cl.coef, cl.h, 0, AL, s);
+  launch_cholesky(NH, AL, NH, h->info + 8, s);                       // AL <- L_A
+  launch_trinv(NH, AL, NH, h->C0, NH, s);                            // C0 <- L_A^{-1} (temp)
+  launch_gemm(true, false, NH, NH, NH, 1.0, h->C0, NH, h->C0, NH, 0.0, h->AinvL, NH, s);
+  launch_symmetrize(NH, h->AinvL, s);
+  double* BL = h->dtmp;
+  launch_stencil_to_dense(h->dim, cl.m, nullptr, cl.h, 1, BL, s);
+  launch_cholesky(NH, BL, NH, h->info + 9, s);                       // BL <- L_B
+  launch_trinv(NH, BL, NH, h->LBinv, NH, s);
+  launch_gemm(true, false, NH, NH, NH, 1.0, h->LBinv, NH, h->LBinv, NH, 0.0, h->BHinv, NH, s);
+  launch_symmetrize(NH, h->BHinv, s);
+  // C0 = LB^{-1} A_H LB^{-T}
+  launch_stencil_to_dense(h->dim, cl.m, cl.coef, cl.h, 0, AL, s);
+  double* tmp = h->setup_scratch;
+  launch_gemm(false, false, NH, NH, NH, 1.0, h->LBinv, NH, AL, NH, 0.0, tmp, NH, s);
+  launch_gemm(false, true, NH, NH, NH, 1.0, tmp, NH, h->LBinv, NH, 0.0, h->C0, NH, s);
+  launch_symmetrize(NH, h->C0, s);
+  HIPS(hipGetLastError());
+  int inf[16];
+  HIPS(hipMemcpyAsync(inf, h->info, sizeof(inf), hipMemcpyDeviceToHost, s));
+  HIPS(hipStreamSynchronize(s));
+  if (inf[8] || inf[9]) {
+    fail(h, PASE_E_BREAKDOWN, "coarse Cholesky failed");
+    return bail(PASE_E_BREAKDOWN);
+  }
+  HIPS(hipEventCreate(&h->ev0));
+  HIPS(hipEventCreate(&h->ev1));
+#undef HIPS
+  *out = h;
+  return PASE_OK;
+}
+
+pase_status pase_destroy(pase_handle* h) {
+  if (!h) return PASE_OK;
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  delete h;
+  return PASE_OK;
+}
+
+pase_status pase_level_size(const pase_handle* h, int level, long long* N) {
+  if (!h || !N || level < 0 || level > h->L) return PASE_E_ARG;
+  *N = h->lev[level].N;
+  return PASE_OK;
+}
+
+pase_status pase_apply(pase_handle* h, int level, int k, const double* X, double* AX, double* MX) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (level < 0 || level > h->L || !X) return fail(h, PASE_E_ARG, "bad level or X");
+  apply_AM(h, level, k, X, AX, MX);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
+pase_status pase_vcycle(pase_handle* h, int k, const double* B, double* Z) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (!B || !Z || B == Z) return fail(h, PASE_E_ARG, "B, Z must be distinct non-null buffers");
+  vcycle(h, 0, k, B, Z);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
+pase_status pase_pcg(pase_handle* h, int k, const double* lambda_host, const double* U, double* W) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (!lambda_host || !U || !W) return fail(h, PASE_E_ARG, "null argument");
+  const long long N = h->lev[0].N;
+  HIPC(hipMemcpyAsync(h->lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, h->stream));
+  eig_residual(h, k, U, h->R);
+  launch_copy((size_t)N * k, U, h->X, h->stream);
+  pcg(h, k, h->X, h->R);
+  launch_copy((size_t)N * k, h->X, W, h->stream);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
+pase_status pase_restrict(pase_handle* h, int k, const double* Xf, double* Xc) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (!Xf || !Xc) return fail(h, PASE_E_ARG, "null argument");
+  restrict_all(h, k, Xf, Xc);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
+pase_status pase_prolong(pase_handle* h, int k, const double* Xc, double* Xf) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (!Xf || !Xc) return fail(h, PASE_E_ARG, "null argument");
+  prolong_all(h, k, Xc, Xf, 0);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
+pase_status pase_gram(pase_handle* h, long long N, int k, const double* X, const double* Y, double* G) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (!X || !Y || !G || N < 1 || N > h->lev[0].N) return fail(h, PASE_E_ARG, "bad Gram arguments");
+  launch_gram(N, k, X, Y, h->partial, gram_tiles(N, k), G, h->stream);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
+int pase_small_eig_max_n(const pase_handle* h) { return h ? std::min(h->nT, syev_max_n()) : 0; }
+
+pase_status pase_small_eig(pase_handle* h, int n, int k, const double* T, double* w_host, double* V) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (!h->Tm) return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
+  if (!T || !w_host || !V || n < 2 || n > pase_small_eig_max_n(h) || k > n)
+    return fail(h, PASE_E_ARG, "bad small_eig arguments");
+  HIPC(hipMemcpyAsync(h->Tm, T, sizeof(double) * n * n, hipMemcpyDeviceToDevice, h->stream));
+  launch_syev_lowest(n, k, h->Tm, h->lam, V, h->syw, h->info + 2, h->stream);
+  HIPC(hipGetLastError());
+  HIPC(hipMemcpyAsync(w_host, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, h->stream));
+  int inf[16];
+  st = read_info(h, inf, 16);
+  if (st) return st;
+  if (inf[2]) return fail(h, PASE_E_BREAKDOWN, "small eigensolver breakdown");
+  return PASE_OK;
+}
+
+pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* U) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (!h->Tm) return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
+  if (!lambda_host || !U) return fail(h, PASE_E_ARG, "null argument");
+  const long long N = h->lev[0].N;
+  hipStream_t s = h->stream;
+  HIPC(hipMemcpyAsync(h->lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
+  launch_copy((size_t)N * k, U, h->U, s);
+  eig_residual(h, k, h->U, h->R);
+  st = correction(h, k);
+  if (st) return st;
+  launch_copy((size_t)N * k, h->U, U, s);
+  HIPC(hipGetLastError());
+  HIPC(hipMemcpyAsync(lambda_host, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  int inf[16];
+  st = read_info(h, inf, 16);
+  if (st) return st;
+  if (inf[1] || inf[2]) return fail(h, PASE_E_BREAKDOWN, "Gram Cholesky or small eigensolver breakdown");
+  return PASE_OK;
+}
+
+pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, double* lambda_host, double* U,
+                       pase_report* rep) {
+  pase_status st = check_k(h, nev);
+  if (st) return st;
+  if (!h->Tm) return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
+  if (!U0 || !lambda_host || !U) return fail(h, PASE_E_ARG, "null argument");
+  if (!(tol > 0.0)) return fail(h, PASE_E_ARG, "tol must be positive");
+  const int k = nev;
+  const long long N = h->lev[0].N;
+  hipStream_t s = h->stream;
+  HIPC(hipEventRecord(h->ev0, s));
+  HIPC(hipMemsetAsync(h->info, 0, 16 * sizeof(int), s));
+  launch_copy((size_t)N * k, U0, h->U, s);
+  // start: two passes of Cholesky-QR in M, Lambda0 = diag(U^T A U)
+  for (int pass = 0; pass < 2; ++pass) cholqr_m(h, k, h->U, h->X, 3 + pass);
+  apply_AM(h, 0, k, h->U, h->W2, nullptr);
+  coldot(h, N, k, h->U, h->W2, h->lam);
+  std::vector<double> hs(3 * k), hl(k);
+  int it = 0;
+  bool conv = false;
+  int nconv = 0;
+  std::vector<double> res(k), lit(k);
+  int rows = 0;
+  pase_status result = PASE_OK;
+  while (true) {
+    eig_residual(h, k, h->U, h->R);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(hs.data(), h->sums, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(hl.data(), h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    int inf[16];
+    st = read_info(h, inf, 16);
+    if (st) return st;
+    if (inf[1] || inf[2] || inf[3] || inf[4])
+      return fail(h, PASE_E_BREAKDOWN, "Cholesky of a Gram matrix or the small eigensolver failed");
+    nconv = 0;
+    bool finite = true;
+    for (int j = 0; j < k; ++j) {
+      const double rn = std::sqrt(hs[j]);
+      res[j] = rn / (std::fabs(hl[j]) * std::sqrt(hs[k + j]));
+      lit[j] = rn / (std::fabs(hl[j]) * std::sqrt(hs[2 * k + j]));
+      if (!std::isfinite(res[j]) || !std::isfinite(hl[j])) finite = false;
+      if (res[j] <= tol) ++nconv;
+    }
+    if (rep && rep->ritz_history_host && rows <= h->opt.max_outer) {
+      std::memcpy(rep->ritz_history_host + (size_t)rows * k, hl.data(), sizeof(double) * k);
+      ++rows;
+    }
+    if (!finite) {
+      result = fail(h, PASE_E_BREAKDOWN, "non-finite residual or Ritz value");
+      break;
+    }
+    if (nconv == k) { conv = true; break; }
+    if (it >= h->opt.max_outer) break;
+    st = correction(h, k);
+    if (st) return st;
+    ++it;
+  }
+  launch_copy((size_t)N * k, h->U, U, s);
+  HIPC(hipEventRecord(h->ev1, s));
+  HIPC(hipMemcpyAsync(lambda_host, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPC(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  if (rep) {
+    rep->outer_iters = it;
+    rep->n_converged = nconv;
+    rep->ritz_history_rows = rows;
+    rep->t_solve_ms = ms;
+    if (rep->res_host) std::memcpy(rep->res_host, res.data(), sizeof(double) * k);
+    if (rep->res_literal_host) std::memcpy(rep->res_literal_host, lit.data(), sizeof(double) * k);
+  }
+  if (result != PASE_OK) return result;
+  if (!conv) return fail(h, PASE_E_NOTCONV, "max_outer reached before every pair met tol");
+  return PASE_OK;
+}
+
+pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double* ms) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (!ms || reps < 1 || which < 0 || which > 4) return fail(h, PASE_E_ARG, "bad timing arguments");
+  if (which == 4 && !h->Tm) return fail(h, PASE_E_UNSUPPORTED, "no dense small-problem workspace");
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  auto once = [&]() {
+    switch (which) {
+      case 0: {
+        StencilArgs a = stencil_args(h, 0, k);
+        a.x = h->U; a.b = h->R; a.out1 = h->Z;
+        launch_stencil(a, EPI_SWEEP, s);
+        break;
+      }
+      case 1: apply_AM(h, 0, k, h->U, h->W2, h->W3); break;
+      case 2: launch_gram(N, k, h->U, h->W2, h->partial, gram_tiles(N, k), h->kk1, s); break;
+      case 3: vcycle(h, 0, k, h->R, h->Z); break;
+      case 4: {
+        // a correction consumes R and overwrites U; run it on copies so repeated calls see the same input
+        launch_copy((size_t)N * k, h->U, h->W2, s);
+        eig_residual(h, k, h->U, h->R);
+        correction(h, k);
+        launch_copy((size_t)N * k, h->W2, h->U, s);
+        break;
+      }
+    }
+  };
+  once();   // warm
+  HIPC(hipEventRecord(h->ev0, s));
+  for (int r = 0; r < reps; ++r) once();
+  HIPC(hipEventRecord(h->ev1, s));
+  HIPC(hipGetLastError());
+  HIPC(hipEventSynchronize(h->ev1));
+  float t = 0.f;
+  HIPC(hipEventElapsedTime(&t, h->ev0, h->ev1));
+  *ms = (double)t / reps;
+  return PASE_OK;
+}
+
+}  // extern "C"

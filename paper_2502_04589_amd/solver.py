@@ -1,0 +1,208 @@
+"""Solver: a handle on libpase with torch-owned device memory.
+
+Argument marshalling only: shapes are checked, torch tensors are passed by
+device pointer, and every computation happens in libpase's HIP kernels on
+the stream that was current when the Solver was created.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _native as nat
+
+
+class PaseError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.status_name = nat.STATUS.get(status, str(status))
+        super().__init__(f"{self.status_name}: {message}")
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Solver:
+    """Augmented subspace eigensolver for the Q1 pencil of -div(kappa grad u) = lambda u.
+
+    dim:     2 or 3.
+    levels:  elements per side of each grid, fine first, halving each time;
+             the last one is the coarse space V_H.
+    kappa:   None (kappa = 1) or n^dim element values, x fastest (array or tensor).
+    nev_max: largest nev a solve may ask for.
+    """
+
+    def __init__(self, dim, levels, kappa=None, nev_max=16, precision="fp64", cg_steps=2, max_outer=500,
+                 nu=2, omega=2.0 / 3.0, device="cuda:0"):
+        self.lib = nat.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        self.dim = int(dim)
+        self.levels = [int(n) for n in levels]
+        prob = nat.Problem()
+        prob.dim = self.dim
+        prob.nlevels = len(self.levels)
+        if not 2 <= prob.nlevels <= nat.MAX_LEVELS:
+            raise ValueError("need 2..8 levels")
+        for i, n in enumerate(self.levels):
+            prob.n[i] = n
+        self._kappa = None
+        if kappa is not None:
+            ne = self.levels[0] ** self.dim
+            kt = torch.as_tensor(kappa, dtype=torch.float64).reshape(-1)
+            if kt.numel() != ne:
+                raise ValueError(f"kappa must have {ne} entries")
+            self._kappa = kt.to(self.device).contiguous()
+        prob.kappa = _ptr(self._kappa)
+        opt = nat.Options()
+        self.lib.pase_options_default(C.byref(opt))
+        opt.precision = nat.PREC[precision]
+        opt.nev_max = int(nev_max)
+        opt.cg_steps = int(cg_steps)
+        opt.max_outer = int(max_outer)
+        opt.nu = int(nu)
+        opt.omega = float(omega)
+        self.opt = opt
+        nbytes = C.c_size_t(0)
+        self._check(self.lib.pase_workspace_bytes(C.byref(prob), C.byref(opt), C.byref(nbytes)), None)
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = self.lib.pase_setup(C.byref(prob), C.byref(opt), _ptr(self.workspace), nbytes,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._check(st, None)
+        self.h = h
+        self._kappa = None
+        self.N = [self.level_size(l) for l in range(len(self.levels))]
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, st, h):
+        if st != 0:
+            msg = self.lib.pase_last_error(h if h is not None else None)
+            raise PaseError(st, msg.decode() if msg else "")
+
+    def _mv(self, t, rows, k, name):
+        if not (isinstance(t, torch.Tensor) and t.device == self.device and t.dtype == torch.float64):
+            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+        if t.shape != (rows, k) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {rows} x {k} tensor")
+        return t
+
+    def _new(self, rows, k):
+        return torch.empty((rows, k), dtype=torch.float64, device=self.device)
+
+    def level_size(self, level):
+        n = C.c_longlong(0)
+        self._check(self.lib.pase_level_size(self.h, int(level), C.byref(n)), self.h)
+        return int(n.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pase_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ solve
+    def solve(self, nev, tol, U0, history=False, raise_notconv=True):
+        """nev smallest eigenpairs.  Returns (lam [np], U [torch N x nev], report dict)."""
+        N = self.N[0]
+        U0 = self._mv(U0, N, nev, "U0")
+        U = self._new(N, nev)
+        lam = np.zeros(nev)
+        res = np.zeros(nev)
+        lit = np.zeros(nev)
+        hist = np.zeros((self.opt.max_outer + 1, nev)) if history else None
+        rep = nat.Report()
+        rep.res_host = res.ctypes.data
+        rep.res_literal_host = lit.ctypes.data
+        rep.ritz_history_host = hist.ctypes.data if history else None
+        st = self.lib.pase_solve(self.h, int(nev), float(tol), _ptr(U0), lam.ctypes.data, _ptr(U), C.byref(rep))
+        report = {"outer_iters": rep.outer_iters, "n_converged": rep.n_converged, "res": res,
+                  "res_literal": lit, "t_solve_ms": rep.t_solve_ms, "status": nat.STATUS.get(st, st)}
+        if history:
+            report["ritz_history"] = hist[:rep.ritz_history_rows].copy()
+        if st != 0 and not (st == 4 and not raise_notconv):
+            self._check(st, self.h)
+        return lam, U, report
+
+    # ------------------------------------------------------------------ components
+    def apply(self, level, X):
+        k = X.shape[1]
+        X = self._mv(X, self.N[level], k, "X")
+        AX, MX = self._new(self.N[level], k), self._new(self.N[level], k)
+        self._check(self.lib.pase_apply(self.h, int(level), k, _ptr(X), _ptr(AX), _ptr(MX)), self.h)
+        return AX, MX
+
+    def vcycle(self, B):
+        k = B.shape[1]
+        B = self._mv(B, self.N[0], k, "B")
+        Z = self._new(self.N[0], k)
+        self._check(self.lib.pase_vcycle(self.h, k, _ptr(B), _ptr(Z)), self.h)
+        return Z
+
+    def pcg(self, lam, U):
+        k = U.shape[1]
+        U = self._mv(U, self.N[0], k, "U")
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        W = self._new(self.N[0], k)
+        self._check(self.lib.pase_pcg(self.h, k, lam.ctypes.data, _ptr(U), _ptr(W)), self.h)
+        return W
+
+    def restrict(self, Xf):
+        k = Xf.shape[1]
+        Xf = self._mv(Xf, self.N[0], k, "Xf")
+        Xc = self._new(self.N[-1], k)
+        self._check(self.lib.pase_restrict(self.h, k, _ptr(Xf), _ptr(Xc)), self.h)
+        return Xc
+
+    def prolong(self, Xc):
+        k = Xc.shape[1]
+        Xc = self._mv(Xc, self.N[-1], k, "Xc")
+        Xf = self._new(self.N[0], k)
+        self._check(self.lib.pase_prolong(self.h, k, _ptr(Xc), _ptr(Xf)), self.h)
+        return Xf
+
+    def gram(self, X, Y):
+        N, k = X.shape
+        X = self._mv(X, N, k, "X")
+        Y = self._mv(Y, N, k, "Y")
+        G = self._new(k, k)
+        self._check(self.lib.pase_gram(self.h, int(N), k, _ptr(X), _ptr(Y), _ptr(G)), self.h)
+        return G
+
+    def small_eig(self, T, k):
+        n = T.shape[0]
+        T = self._mv(T, n, n, "T")
+        w = np.zeros(k)
+        V = self._new(n, k)
+        self._check(self.lib.pase_small_eig(self.h, n, int(k), _ptr(T), w.ctypes.data, _ptr(V)), self.h)
+        return w, V
+
+    def small_eig_max_n(self):
+        return int(self.lib.pase_small_eig_max_n(self.h))
+
+    KERNELS = {"sweep": 0, "apply": 1, "gram": 2, "vcycle": 3, "correction": 4}
+
+    def time_kernel(self, name, k, reps=20):
+        """Average device ms per launch of a hot-path kernel (HIP events on the solver's stream)."""
+        ms = C.c_double(0.0)
+        self._check(self.lib.pase_time_kernel(self.h, self.KERNELS[name], int(k), int(reps), C.byref(ms)), self.h)
+        return float(ms.value)
+
+    def correction(self, lam, U):
+        k = U.shape[1]
+        U = self._mv(U, self.N[0], k, "U").clone()
+        lam = np.array(lam, dtype=np.float64)
+        self._check(self.lib.pase_correction(self.h, k, lam.ctypes.data, _ptr(U)), self.h)
+        return lam, U

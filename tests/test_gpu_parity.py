@@ -1,0 +1,228 @@
+"""GPU parity: every step of the HIP path against the CPU oracle (FP64).
+
+All calls go through the C ABI (ctypes binding).  Sizes span several tiles
+and ragged tails; tolerances are stated per test.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import multigrid, pase as opase
+from tests.closed_form import q1_laplace_eigs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    _require_gpu()
+
+
+def Solver(*a, **kw):
+    from paper_2502_04589_amd import Solver as S
+    return S(*a, **kw)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+CASES = [
+    (2, [32, 16, 8, 4], None),
+    (2, [64, 32, 16], 3),
+    (3, [16, 8, 4, 2], None),
+    (3, [16, 8, 4], 5),
+]
+
+
+@pytest.mark.parametrize("dim,levels,kseed", CASES)
+@pytest.mark.parametrize("k", [1, 7, 27])
+def test_apply_every_level(dim, levels, kseed, k):
+    kap = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
+    H = multigrid.Hierarchy(dim, levels, kap)
+    s = Solver(dim, levels, kap, nev_max=32)
+    rng = np.random.default_rng(k)
+    for l in range(len(levels)):
+        X = rng.standard_normal((H.A[l].shape[0], k))
+        AX, MX = s.apply(l, dev(X))
+        assert relerr(host(AX), H.A[l] @ X) < 1e-13, l
+        assert relerr(host(MX), H.M[l] @ X) < 1e-14, l
+
+
+@pytest.mark.parametrize("dim,levels,kseed", CASES)
+def test_transfer_and_vcycle(dim, levels, kseed):
+    kap = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
+    H = multigrid.Hierarchy(dim, levels, kap)
+    s = Solver(dim, levels, kap, nev_max=16)
+    rng = np.random.default_rng(0)
+    for k in (3, 16):
+        Xf = rng.standard_normal((H.A[0].shape[0], k))
+        Xc = rng.standard_normal((H.A[-1].shape[0], k))
+        assert relerr(host(s.restrict(dev(Xf))), H.Pc.T @ Xf) < 1e-14
+        assert relerr(host(s.prolong(dev(Xc))), H.Pc @ Xc) < 1e-14
+        assert relerr(host(s.vcycle(dev(Xf))), H.vcycle(Xf)) < 1e-12
+
+
+@pytest.mark.parametrize("N,k", [(1, 1), (37, 5), (1000, 16), (4099, 17), (20000, 50), (9000, 100)])
+def test_gram_mfma(N, k):
+    s = Solver(3, [32, 16, 8], nev_max=max(k, 16))
+    rng = np.random.default_rng(N + k)
+    X = rng.standard_normal((N, k))
+    Y = rng.standard_normal((N, k))
+    G = host(s.gram(dev(X), dev(Y)))
+    ref = X.T @ Y
+    assert np.abs(G - ref).max() <= 1e-13 * np.sqrt(N) * np.abs(X).max() * np.abs(Y).max() + 1e-14
+
+
+def test_gram_is_bitwise_deterministic():
+    s = Solver(3, [32, 16, 8], nev_max=50)
+    rng = np.random.default_rng(1)
+    X = dev(rng.standard_normal((29791, 50)))
+    assert torch.equal(s.gram(X, X), s.gram(X, X))
+
+
+@pytest.mark.parametrize("dim,levels,kseed", CASES[1:3])
+def test_pcg_s_steps(dim, levels, kseed):
+    kap = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
+    H = multigrid.Hierarchy(dim, levels, kap)
+    s = Solver(dim, levels, kap, nev_max=8, cg_steps=2)
+    k = 6
+    U = opase.cholqr_m(synth.initial_vectors(H.A[0].shape[0], k, 3), H.M[0])
+    lam = np.einsum("ij,ij->j", U, H.A[0] @ U)
+    W = host(s.pcg(lam, dev(U)))
+    ref = opase.pcg(H, (H.M[0] @ U) * lam, U, 2)
+    assert relerr(W, ref) < 1e-12
+
+
+def _symmetric_with_clusters(n, rng):
+    w = np.sort(rng.uniform(1.0, 100.0, n))
+    w[3:6] = w[3]              # triple
+    w[10:12] = w[10] * (1 + 1e-13)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return (Q * w) @ Q.T, w
+
+
+@pytest.mark.parametrize("n,k", [(2, 1), (3, 3), (40, 12), (235, 10), (393, 50), (300, 64)])
+def test_small_dense_eigensolver(n, k):
+    s = Solver(3, [16, 8, 4], nev_max=64)
+    if n > s.small_eig_max_n():
+        s = Solver(3, [64, 32, 16, 8], nev_max=64)
+    rng = np.random.default_rng(n)
+    T, _ = _symmetric_with_clusters(n, rng) if n > 12 else (None, None)
+    if T is None:
+        A = rng.standard_normal((n, n))
+        T = A + A.T
+    w, V = s.small_eig(dev(T), k)
+    V = host(V)
+    ref = np.linalg.eigvalsh(T)[:k]
+    scale = np.abs(np.linalg.eigvalsh(T)).max()
+    assert np.abs(w - ref).max() <= 1e-13 * scale
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-13
+    assert np.abs(T @ V - V * w).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("dim,levels,kseed,k", [(2, [32, 16, 8, 4], None, 6), (3, [16, 8, 4], 5, 8),
+                                                 (3, [16, 8, 4, 2], 2, 5)])
+def test_one_correction_matches_literal_composite(dim, levels, kseed, k):
+    """Alg. 3 steps 3-6 once: Ritz values of the literal composite pencil (oracle)."""
+    kap = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
+    H = multigrid.Hierarchy(dim, levels, kap)
+    s = Solver(dim, levels, kap, nev_max=k)
+    U = opase.cholqr_m(synth.initial_vectors(H.A[0].shape[0], k, 1), H.M[0])
+    lam = np.einsum("ij,ij->j", U, H.A[0] @ U)
+    W = opase.pcg(H, (H.M[0] @ U) * lam, U, 2)
+    ref_lam, Y = opase.small_solve(*opase.composite(H, W), k)
+    NH = H.A[-1].shape[0]
+    ref_U = H.Pc @ Y[:NH] + W @ Y[NH:]
+    lam2, U2 = s.correction(lam, dev(U))
+    U2 = host(U2)
+    np.testing.assert_allclose(lam2, ref_lam, rtol=1e-11)
+    assert np.abs(U2.T @ (H.M[0] @ U2) - np.eye(k)).max() < 1e-12
+    # same block of Ritz vectors (signs and rotations inside clusters are free)
+    cos = np.linalg.svd(ref_U.T @ (H.M[0] @ U2), compute_uv=False)
+    assert cos.min() > 1 - 1e-9
+
+
+def test_config1_closed_form_and_oracle():
+    """2D 128x128, V_H = 16x16, nev 10, 2 CG steps, tol 1e-10."""
+    levels, k = [128, 64, 32, 16], 10
+    s = Solver(2, levels, nev_max=k)
+    U0 = synth.initial_vectors(127 ** 2, k, 0)
+    lam, U, rep = s.solve(k, 1e-10, dev(U0), history=True)
+    ref = opase.solve(multigrid.Hierarchy(2, levels), k, 1e-10, U0)
+    np.testing.assert_allclose(lam, ref.lam, rtol=1e-10)
+    np.testing.assert_allclose(lam, q1_laplace_eigs(2, 128, k), rtol=1e-10)
+    assert rep["n_converged"] == k and np.all(rep["res"] <= 1e-10)
+    assert abs(rep["outer_iters"] - ref.iters) <= 2
+    H = multigrid.Hierarchy(2, levels)
+    Uh = host(U)
+    assert np.abs(Uh.T @ (H.M[0] @ Uh) - np.eye(k)).max() < 1e-12
+    hist = rep["ritz_history"]
+    assert np.all(hist[1:] <= hist[:-1] * (1 + 1e-12))
+
+
+def test_variable_kappa_3d_matches_oracle():
+    levels, k = [16, 8, 4], 8
+    kap = synth.kappa_field(3, 16, 11)
+    s = Solver(3, levels, kap, nev_max=k)
+    H = multigrid.Hierarchy(3, levels, kap)
+    U0 = synth.initial_vectors(H.A[0].shape[0], k, 2)
+    lam, U, rep = s.solve(k, 1e-10, dev(U0))
+    ref = opase.solve(H, k, 1e-10, U0)
+    np.testing.assert_allclose(lam, ref.lam, rtol=1e-10)
+    w = sla.eigh(H.A[0].toarray(), H.M[0].toarray(), subset_by_index=[0, k - 1], eigvals_only=True)
+    np.testing.assert_allclose(lam, w, rtol=1e-10)
+
+
+@pytest.mark.slow
+def test_config2_closed_form_full_size():
+    """3D 64^3 (250,047 DOFs), V_H = 8^3, nev 50, tol 1e-8: closed-form Q1 eigenvalues."""
+    levels, k = [64, 32, 16, 8], 50
+    s = Solver(3, levels, nev_max=k)
+    U0 = synth.initial_vectors(63 ** 3, k, 0)
+    lam, U, rep = s.solve(k, 1e-8, dev(U0))
+    np.testing.assert_allclose(lam, q1_laplace_eigs(3, 64, k), rtol=1e-10)
+    assert rep["n_converged"] == k
+    _, MU = s.apply(0, U)
+    G = host(U.T.contiguous() @ MU)
+    assert np.abs(G - np.eye(k)).max() < 1e-12
+
+
+def test_edge_cases():
+    levels = [16, 8, 4]
+    s = Solver(2, levels, nev_max=4, max_outer=0)
+    N = s.N[0]
+    U0 = synth.initial_vectors(N, 1, 0)
+    # max_outer = 0: not converged, residuals reported
+    lam, U, rep = s.solve(1, 1e-10, dev(U0), raise_notconv=False)
+    assert rep["status"] == "PASE_E_NOTCONV" and rep["res"][0] > 0
+    s2 = Solver(2, levels, nev_max=4)
+    lam, U, rep = s2.solve(1, 1e-11, dev(U0))
+    np.testing.assert_allclose(lam, q1_laplace_eigs(2, 16, 1), rtol=1e-11)
+    # duplicate columns: the M-Gram is singular
+    bad = np.repeat(U0, 2, axis=1)
+    from paper_2502_04589_amd import PaseError
+    with pytest.raises(PaseError) as e:
+        s2.solve(2, 1e-8, dev(bad))
+    assert e.value.status_name == "PASE_E_BREAKDOWN"
+    nan = U0.copy()
+    nan[3, 0] = np.nan
+    with pytest.raises(PaseError):
+        s2.solve(1, 1e-8, dev(nan))
+    with pytest.raises(PaseError):
+        s2.solve(5, 1e-8, dev(synth.initial_vectors(N, 5, 0)))   # nev > nev_max
