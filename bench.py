@@ -25,6 +25,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of one fine-level sweep launch (laplace3d-64, k = 50), from two rocprofv3 --pmc
+# runs of this script (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads
+# for the plain device copy this script makes before timing (profiles/laplace3d-64_sweep_traffic.md).
+# Valid only for the stencil source it was measured on: bench.py reports null if the hash differs.
+SWEEP_TRAFFIC = {"bytes": 397.5e6, "stencil_sha256_prefix": None}
+
 WORKLOADS = {
     # name: (dim, levels, nev, tol, kappa_seed)
     "laplace3d-64": (3, [64, 32, 16, 8], 50, 1e-8, None),
@@ -32,14 +38,27 @@ WORKLOADS = {
 }
 
 
-def sweep_bytes(dim, n, k):
+def sweep_bytes(dim, n, k, variable_kappa):
     """Algorithmic HBM bytes of one fine-level damped-Jacobi sweep launch.
 
-    Reads x and b (N x k doubles each) and writes x' (N x k); reads kappa
-    (n^dim doubles) and D^{-1} (N doubles).  Halo re-reads are not counted.
+    Reads x and b (N x k doubles each) and writes x' (N x k); with a variable
+    coefficient also reads kappa (n^dim doubles).  The diagonal is formed in
+    the kernel.  Halo re-reads are not counted.
     """
     N = (n - 1) ** dim
-    return N * (3 * k * 8 + 8) + n ** dim * 8
+    return N * 3 * k * 8 + (n ** dim * 8 if variable_kappa else 0)
+
+
+def stencil_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2502_04589_amd", "csrc", "stencil3d.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def sweep_traffic(workload):
+    if workload != "laplace3d-64" or SWEEP_TRAFFIC["stencil_sha256_prefix"] != stencil_hash():
+        return None
+    return SWEEP_TRAFFIC["bytes"]
 
 
 def cpu_baseline(dim, levels, nev, tol, U0, gpu_iters, n_iter=2):
@@ -87,6 +106,13 @@ def main():
     import synth
     from paper_2502_04589_amd import Solver
 
+    # plain copy of a known size (calibrates the FETCH_SIZE / WRITE_SIZE counters of --pmc runs)
+    cal_src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
+    del cal_src, cal_dst
+
     dim, levels, nev, tol, kseed = WORKLOADS[args.workload]
     kappa = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
     t0 = time.perf_counter()
@@ -113,7 +139,7 @@ def main():
 
     # dominant kernel vs HBM roofline, timed live with HIP events on the solver's stream
     ms = s.time_kernel("sweep", nev, reps=50)
-    nbytes = sweep_bytes(dim, levels[0], nev)
+    nbytes = sweep_bytes(dim, levels[0], nev, kseed is not None)
     achieved = nbytes / (ms * 1e-3) / 1e9
     out = {
         "metric": "converged eigenpairs/s @ tol (plain FP64)",
@@ -137,13 +163,13 @@ def main():
             "max_rel_err_vs_closed_form": None,
         },
         "roofline": {
-            "kernel": "fine-level damped-Jacobi sweep (stencil_kernel<3,Kappa,SWEEP>)",
+            "kernel": "fine-level damped-Jacobi sweep (fine3v_kernel<double, SWEEP>, LDS-staged 3D Q1 stencil)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": sweep_traffic(args.workload),
             "launch_ms": ms,
             "algorithmic_bytes_per_launch": nbytes,
         },

@@ -20,6 +20,12 @@ constexpr int kDenseThreads = 1024;
 constexpr int kDenseWaves = kDenseThreads / 64;
 constexpr int kSyevMaxN = 1024;
 
+__global__ void zero_info_kernel(int* info) { *info = 0; }
+
+__global__ void copy_lam_kernel(int k, const double* __restrict__ a, double* __restrict__ b) {
+  for (int i = threadIdx.x; i < k; i += blockDim.x) b[i] = a[i];
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -40,6 +46,20 @@ __device__ double block_sum(double v, double* red) {
 
 // A pivot at or below n * eps * max_i A[i][i] counts as a breakdown (numerically
 // rank-deficient Gram matrices are reported, not factored).
+// Fixed-order block sum with one barrier: alternate between two scratch rows
+// (the barrier of the call in between orders reuse of a row).
+__device__ double block_sum1(double v, double (*red)[kDenseWaves], int& parity) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* r = red[parity];
+  parity ^= 1;
+  if (lane == 0) r[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kDenseWaves; ++w) s += r[w];
+  return s;
+}
+
 __global__ __launch_bounds__(kDenseThreads) void cholesky_kernel(int n, double* A, int lda, int* info) {
   __shared__ int fail;
   __shared__ double ptol;
@@ -96,19 +116,11 @@ __global__ __launch_bounds__(kBlock) void trinv_kernel(int n, const double* __re
   }
 }
 
-// ---- eigensolver helpers
-__device__ int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
-  int c = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  c += (q < 0.0);
-  for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    c += (q < 0.0);
-  }
-  return c;
-}
+// ---- eigensolver
+// Layout of the eigensolver work area (doubles):
+//   tri[0:n) = d, tri[n:2n) = e, tri[2n:3n) = tau, tri[3n:3n+8) = scalars
+//   lam[k], Vt[n*k] (tridiagonal eigenvectors), wy[kWyB * k * 2]
+constexpr int kWyB = 32;          // reflectors per block of the back-transformation
 
 __device__ __forceinline__ double hash_unit(unsigned a, unsigned b) {
   unsigned h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
@@ -120,265 +132,481 @@ __device__ __forceinline__ double hash_unit(unsigned a, unsigned b) {
   return (double)(h & 0xFFFFFF) / (double)0x800000 - 1.0;   // [-1, 1)
 }
 
-// Inverse iteration for eigenvalue lam of the tridiagonal (d, e): x <- (T - lam)^{-1} x,
-// with Gaussian elimination and row interchanges.  Scratch: u0,u1,u2,mul (n each), piv (n).
-__device__ void tri_lu(int n, const double* d, const double* e, double lam, double tiny, double* u0, double* u1,
-                       double* u2, double* mul, unsigned char* piv) {
-  double r0 = d[0] - lam, r1 = (n > 1) ? e[0] : 0.0, r2 = 0.0;
-  for (int i = 0; i < n - 1; ++i) {
-    const double s0 = e[i], s1 = d[i + 1] - lam, s2 = (i + 2 < n) ? e[i + 1] : 0.0;
-    double m, n0, n1;
-    if (fabs(r0) >= fabs(s0)) {
-      if (r0 == 0.0) r0 = tiny;
-      m = s0 / r0;
-      piv[i] = 0;
-      u0[i] = r0; u1[i] = r1; u2[i] = r2;
-      n0 = s1 - m * r1;
-      n1 = s2 - m * r2;
-    } else {
-      m = r0 / s0;
-      piv[i] = 1;
-      u0[i] = s0; u1[i] = s1; u2[i] = s2;
-      n0 = r1 - m * s1;
-      n1 = r2 - m * s2;
-    }
-    mul[i] = m;
-    r0 = n0; r1 = n1; r2 = 0.0;
-  }
-  if (r0 == 0.0) r0 = tiny;
-  u0[n - 1] = r0;
-  u1[n - 1] = 0.0;
-  u2[n - 1] = 0.0;
+// 1. Householder reduction of the symmetric n x n matrix T (row-major, full
+// storage) to tridiagonal form.  Reflector j is stored in row j of T
+// (entries j+2 .. n-1; its entry j+1 is an implicit 1), tau[j] in tri.
+// Step j applies A22 <- A22 - v w^T - w v^T (w = p - K v, p = tau A22 v) and,
+// in the same pass over the trailing block, forms the product of the next
+// reflector with the updated block (look-ahead): row j+1 is updated first, the
+// next reflector built from it, then one read-modify-write sweep of the rest.
+// Threads own columns (coalesced across threads); symmetry gives
+// (A v)_r = sum_c A[c][r] v_c.
+__device__ __forceinline__ void colsum_map(int cols, int& G, int t, int& r, int& g) {
+  G = 1024 / cols;
+  if (G > 16) G = 16;
+  if (G < 1) G = 1;
+  r = t % cols;
+  g = t / cols;
 }
 
-__device__ void tri_solve(int n, const double* u0, const double* u1, const double* u2, const double* mul,
-                          const unsigned char* piv, double* x) {
-  for (int i = 0; i < n - 1; ++i) {
-    if (piv[i]) { const double t = x[i]; x[i] = x[i + 1]; x[i + 1] = t; }
-    x[i + 1] -= mul[i] * x[i];
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double s = x[i];
-    if (i + 1 < n) s -= u1[i] * x[i + 1];
-    if (i + 2 < n) s -= u2[i] * x[i + 2];
-    x[i] = s / u0[i];
-  }
-}
-
-// work layout (doubles): [T-sized scratch not needed] per-thread LU scratch 5n x k, V-tri n x k, gram k x k
-__global__ __launch_bounds__(kDenseThreads) void syev_lowest_kernel(int n, int k, double* __restrict__ T,
-                                                                   double* __restrict__ wout,
-                                                                   double* __restrict__ V,
-                                                                   double* __restrict__ work, int* info) {
-  __shared__ double d[kSyevMaxN], e[kSyevMaxN], e2[kSyevMaxN], tau[kSyevMaxN];
-  __shared__ double v[kSyevMaxN], p[kSyevMaxN];
-  __shared__ double lam[PASE_MAX_NEV];
-  __shared__ int cstart[PASE_MAX_NEV + 1];
-  __shared__ double red[kDenseWaves];
-  __shared__ double sh_scalar[4];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (tid == 0) *info = 0;
-
-  // ---- 1. Householder tridiagonalisation (T row-major, symmetric, full storage)
-  for (int j = 0; j + 2 < n; ++j) {
-    const int m = n - j - 1;
-    const double* row = T + (size_t)j * n + j + 1;     // x = T[j][j+1 .. n-1]
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += kDenseThreads) part += row[i] * row[i];
-    const double xnorm2 = block_sum(part, red);
+__global__ __launch_bounds__(kDenseThreads) void tridiag_kernel(int n, double* __restrict__ T,
+                                                               double* __restrict__ tri) {
+  __shared__ double va[kSyevMaxN], pa[kSyevMaxN], vb[kSyevMaxN], pb[kSyevMaxN];
+  __shared__ double part[kDenseThreads];
+  __shared__ double red[2][kDenseWaves];
+  int parity = 0;
+  const int tid = threadIdx.x;
+  double* d = tri;
+  double* e = tri + n;
+  double* tau = tri + 2 * n;
+  double* v = va; double* p = pa; double* v2 = vb; double* p2 = pb;
+  double tcur = 0.0, K = 0.0;
+  if (n >= 3) {
+    // reflector 0 from row 0 and p0 = tau0 A22 v0
+    const int m = n - 1;
+    double* row = T + 1;
+    double part0 = 0.0;
+    for (int i = 1 + tid; i < m; i += kDenseThreads) part0 = fma(row[i], row[i], part0);
+    const double xn2 = block_sum1(part0, red, parity);
     const double alpha = row[0];
-    if (xnorm2 == 0.0) {
-      if (tid == 0) { tau[j] = 0.0; e[j] = alpha; d[j] = T[(size_t)j * n + j]; }
-      __syncthreads();
-      continue;
+    if (tid == 0) d[0] = T[0];
+    if (xn2 == 0.0) {
+      tcur = 0.0;
+      for (int i = tid; i < m; i += kDenseThreads) v[i] = (i == 0) ? 1.0 : 0.0;
+      if (tid == 0) { tau[0] = 0.0; e[0] = alpha; }
+    } else {
+      const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tcur = (beta - alpha) / beta;
+      const double sc = 1.0 / (alpha - beta);
+      for (int i = tid; i < m; i += kDenseThreads) {
+        const double vi = (i == 0) ? 1.0 : row[i] * sc;
+        v[i] = vi;
+        if (i > 0) row[i] = vi;
+      }
+      if (tid == 0) { tau[0] = tcur; e[0] = beta; }
     }
-    const double beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-    const double tj = (beta - alpha) / beta;
-    const double scale = 1.0 / (alpha - beta);
-    for (int i = tid; i < m; i += kDenseThreads) v[i] = (i == 0) ? 1.0 : row[i] * scale;
     __syncthreads();
-    // store v (i >= 1) in row j for the back-transformation
-    for (int i = 1 + tid; i < m; i += kDenseThreads) T[(size_t)j * n + j + 1 + i] = v[i];
-    if (tid == 0) { tau[j] = tj; e[j] = beta; d[j] = T[(size_t)j * n + j]; }
-    // p = tau A22 v
-    double* A22 = T + (size_t)(j + 1) * n + (j + 1);
-    for (int r = wave; r < m; r += kDenseWaves) {
-      const double* ar = A22 + (size_t)r * n;
-      double s = 0.0;
-      for (int c = lane; c < m; c += 64) s = fma(ar[c], v[c], s);
-      s = wave_sum(s);
-      if (lane == 0) p[r] = tj * s;
-    }
+    const double* A22 = T + (size_t)n + 1;
+    int G, r, g;
+    colsum_map(m, G, tid, r, g);
+    double acc = 0.0;
+    if (tid < G * m)
+      for (int c = g; c < m; c += G) acc = fma(A22[(size_t)c * n + r], v[c], acc);
+    part[tid] = acc;
     __syncthreads();
     double pv = 0.0;
-    for (int i = tid; i < m; i += kDenseThreads) pv += p[i] * v[i];
-    const double K = 0.5 * tj * block_sum(pv, red);
-    // w = p - K v (in p)
-    for (int i = tid; i < m; i += kDenseThreads) p[i] -= K * v[i];
-    __syncthreads();
-    for (long long q = tid; q < (long long)m * m; q += kDenseThreads) {
-      const int r = (int)(q / m), c = (int)(q % m);
-      A22[(size_t)r * n + c] -= v[r] * p[c] + p[r] * v[c];
+    if (tid < m) {
+      double sum = 0.0;
+      for (int q = 0; q < G; ++q) sum += part[q * m + tid];
+      p[tid] = tcur * sum;
+      pv = p[tid] * v[tid];
+    }
+    K = 0.5 * tcur * block_sum1(pv, red, parity);
+  }
+  for (int j = 0; j + 2 < n; ++j) {
+    const int m = n - j - 1;
+    double* A22 = T + (size_t)(j + 1) * n + (j + 1);
+    const bool has_next = (j + 3 < n);
+    // (a) row 0 of A22: update and the norm of its tail (next reflector's x)
+    double nrm = 0.0;
+    const double w0 = p[0] - K * v[0];
+    for (int c = tid; c < m; c += kDenseThreads) {
+      const double a = A22[c] - (v[0] * (p[c] - K * v[c]) + w0 * v[c]);
+      A22[c] = a;
+      if (c >= 2) nrm = fma(a, a, nrm);
+    }
+    const double xn2 = block_sum1(nrm, red, parity);
+    double tnext = 0.0;
+    if (has_next) {
+      const double alpha = A22[1];
+      if (xn2 == 0.0) {
+        for (int i = tid; i < m - 1; i += kDenseThreads) v2[i] = (i == 0) ? 1.0 : 0.0;
+        if (tid == 0) { tau[j + 1] = 0.0; e[j + 1] = alpha; }
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tnext = (beta - alpha) / beta;
+        const double sc = 1.0 / (alpha - beta);
+        for (int i = tid; i < m - 1; i += kDenseThreads) {
+          const double vi = (i == 0) ? 1.0 : A22[1 + i] * sc;
+          v2[i] = vi;
+          if (i > 0) A22[1 + i] = vi;
+        }
+        if (tid == 0) { tau[j + 1] = tnext; e[j + 1] = beta; }
+      }
+      if (tid == 0) d[j + 1] = A22[0];
     }
     __syncthreads();
+    // (b) fused sweep over A33 = A22[1:, 1:]: update, and partial products with v2
+    const int cols = m - 1;
+    int G, r, g;
+    colsum_map(cols, G, tid, r, g);
+    double acc = 0.0;
+    if (tid < G * cols) {
+      const int rr = r + 1;
+      const double vr = v[rr], wr = p[rr] - K * v[rr];
+      constexpr int kBatch = 10;
+      for (int c0 = 1 + g; c0 < m; c0 += kBatch * G) {
+        double a[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {          // issue the batch's loads together
+          const int c = c0 + u * G;
+          a[u] = (c < m) ? A22[(size_t)c * n + rr] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const int c = c0 + u * G;
+          if (c < m) {
+            const double nv = a[u] - (v[c] * wr + (p[c] - K * v[c]) * vr);
+            A22[(size_t)c * n + rr] = nv;
+            if (has_next) acc = fma(nv, v2[c - 1], acc);
+          }
+        }
+      }
+    }
+    part[tid] = acc;
+    __syncthreads();
+    double pv = 0.0;
+    if (has_next && tid < cols) {
+      double sum = 0.0;
+      for (int q = 0; q < G; ++q) sum += part[q * cols + tid];
+      p2[tid] = tnext * sum;
+      pv = p2[tid] * v2[tid];
+    }
+    const double Kn = 0.5 * tnext * block_sum1(pv, red, parity);
+    double* t1 = v; v = v2; v2 = t1;
+    double* t2 = p; p = p2; p2 = t2;
+    tcur = tnext;
+    K = Kn;
   }
+  __syncthreads();
   if (tid == 0) {
+    if (n < 3) d[0] = T[0];
     if (n >= 2) {
       d[n - 2] = T[(size_t)(n - 2) * n + (n - 2)];
       e[n - 2] = T[(size_t)(n - 2) * n + (n - 1)];
+      tau[n - 2] = 0.0;
     }
     d[n - 1] = T[(size_t)(n - 1) * n + (n - 1)];
     e[n - 1] = 0.0;
-    if (n >= 2) tau[n - 2] = 0.0;
     tau[n - 1] = 0.0;
-  }
-  __syncthreads();
-  for (int i = tid; i < n; i += kDenseThreads) e2[i] = e[i] * e[i];
-  // Gershgorin interval and pivmin
-  if (tid == 0) {
     double lo = DBL_MAX, hi = -DBL_MAX, emax = 0.0;
     for (int i = 0; i < n; ++i) {
-      const double r = ((i > 0) ? fabs(e[i - 1]) : 0.0) + ((i + 1 < n) ? fabs(e[i]) : 0.0);
-      lo = fmin(lo, d[i] - r);
-      hi = fmax(hi, d[i] + r);
-      if (i + 1 < n) emax = fmax(emax, e2[i]);
+      const double rr = ((i > 0) ? fabs(e[i - 1]) : 0.0) + ((i + 1 < n) ? fabs(e[i]) : 0.0);
+      lo = fmin(lo, d[i] - rr);
+      hi = fmax(hi, d[i] + rr);
+      if (i + 1 < n) emax = fmax(emax, e[i] * e[i]);
     }
     const double tnorm = fmax(fabs(lo), fabs(hi));
-    lo -= 2.0 * DBL_EPSILON * tnorm * n + DBL_MIN;
-    hi += 2.0 * DBL_EPSILON * tnorm * n + DBL_MIN;
-    sh_scalar[0] = lo;
-    sh_scalar[1] = hi;
-    sh_scalar[2] = DBL_MIN * fmax(1.0, emax);
-    sh_scalar[3] = tnorm;
+    double* sc = tri + 3 * n;
+    sc[0] = lo - (2.0 * DBL_EPSILON * tnorm * n + DBL_MIN);
+    sc[1] = hi + (2.0 * DBL_EPSILON * tnorm * n + DBL_MIN);
+    sc[2] = DBL_MIN * fmax(1.0, emax);
+    sc[3] = tnorm;
   }
-  __syncthreads();
-  const double glo = sh_scalar[0], ghi = sh_scalar[1], pivmin = sh_scalar[2], tnorm = sh_scalar[3];
+}
 
-  // ---- 2. bisection: thread t finds the (t+1)-th smallest eigenvalue
-  for (int t = tid; t < k; t += kDenseThreads) {
-    double lo = glo, hi = ghi;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin || mid == lo || mid == hi) break;
-      if (sturm_count(n, d, e2, mid, pivmin) <= t) lo = mid;
-      else hi = mid;
-    }
-    lam[t] = 0.5 * (lo + hi);
+__device__ int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  c += (q < 0.0);
+  for (int i = 1; i < n; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += (q < 0.0);
   }
-  __syncthreads();
+  return c;
+}
 
-  // ---- 3. inverse iteration; tight clusters (gap < 1e-7 |T|) are re-orthogonalised in place
-  const double clus = 1e-7 * tnorm;
-  if (tid == 0) {
-    int nc = 0;
-    for (int t = 0; t < k; ++t)
-      if (t == 0 || lam[t] - lam[t - 1] > clus) cstart[nc++] = t;
-    cstart[nc] = k;
-    sh_scalar[0] = (double)nc;
+// 2. The (t+1)-th smallest eigenvalue of the tridiagonal, t = blockIdx.x, by
+// multisection: each of the 64 lanes counts eigenvalues below one of 64
+// interior points of the current interval (Sturm sequence), the interval
+// shrinks 65-fold per round.
+__global__ __launch_bounds__(64) void bisect_kernel(int n, const double* __restrict__ tri,
+                                                   double* __restrict__ lam) {
+  __shared__ double d[kSyevMaxN], e2[kSyevMaxN];
+  const int t = blockIdx.x, lane = threadIdx.x;
+  for (int i = lane; i < n; i += 64) {
+    d[i] = tri[i];
+    const double ei = tri[n + i];
+    e2[i] = ei * ei;
   }
   __syncthreads();
-  const int ncl = (int)sh_scalar[0];
-  double* Vt = work;                                   // n x k tridiagonal eigenvectors
-  double* G = work + (size_t)n * k;                    // k x k Gram
-  double* scr = G + (size_t)k * k;                     // per-cluster scratch, 5n each
-  unsigned char* pivs = (unsigned char*)(scr + (size_t)5 * n * k);
+  const double* sc = tri + 3 * n;
+  double lo = sc[0], hi = sc[1];
+  const double pivmin = sc[2];
+  for (int round = 0; round < 40; ++round) {
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    const int cnt = sturm_count(n, d, e2, x, pivmin);
+    const unsigned long long below = __ballot(cnt <= t);
+    const int c = __popcll(below);                   // lanes 0..c-1 have count <= t
+    const double nlo = (c > 0) ? __shfl(x, c - 1, 64) : lo;
+    const double nhi = (c < 64) ? __shfl(x, c < 64 ? c : 63, 64) : hi;
+    if (nlo == lo && nhi == hi) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) lam[t] = 0.5 * (lo + hi);
+}
+
+// 3. Eigenvectors of the tridiagonal by inverse iteration, one block per
+// eigenvalue, stored vector-major (vector j at Vt[j*n .. j*n+n)).  Lane 0 runs
+// the sequential LU (Gaussian elimination with row interchanges) and the
+// solves in LDS.  Members of a cluster of (nearly) equal eigenvalues start
+// from different pseudo-random vectors, so they span the cluster's invariant
+// subspace; the Cholesky-QR passes that follow make them orthonormal (mixing
+// eigenvectors whose eigenvalues differ by g changes residuals by at most g
+// times the remaining contamination, which three iterations bring to the
+// rounding level).
+__global__ __launch_bounds__(64) void invit_kernel(int n, int k, const double* __restrict__ tri,
+                                                  const double* __restrict__ lam, double* __restrict__ Vt) {
+  __shared__ double d[kSyevMaxN], e[kSyevMaxN];
+  __shared__ double u0[kSyevMaxN], u1[kSyevMaxN], u2[kSyevMaxN], x[kSyevMaxN];
+  __shared__ unsigned char piv[kSyevMaxN];
+  __shared__ double mulv[kSyevMaxN];
+  const int j = blockIdx.x, lane = threadIdx.x;
+  const double tnorm = tri[3 * n + 3];
+  for (int i = lane; i < n; i += 64) {
+    d[i] = tri[i];
+    e[i] = tri[n + i];
+    x[i] = hash_unit(j + 1, i + 1);
+  }
+  __syncthreads();
   const double tiny = DBL_EPSILON * tnorm;
-  for (int c = tid; c < ncl; c += kDenseThreads) {
-    double* u0 = scr + (size_t)5 * n * c;
-    double* u1 = u0 + n;
-    double* u2 = u1 + n;
-    double* mul = u2 + n;
-    double* x = mul + n;
-    unsigned char* piv = pivs + (size_t)n * c;
-    for (int t = cstart[c]; t < cstart[c + 1]; ++t) {
-      double lt = lam[t];
-      if (t > cstart[c]) lt = fmax(lt, lam[t - 1] + 10.0 * tiny);   // keep shifts distinct in a cluster
-      tri_lu(n, d, e, lt, tiny, u0, u1, u2, mul, piv);
-      for (int i = 0; i < n; ++i) x[i] = hash_unit(t + 1, i + 1);
-      for (int it = 0; it < 3; ++it) {
-        double xm = 0.0;
-        for (int i = 0; i < n; ++i) xm = fmax(xm, fabs(x[i]));
-        if (xm > 0.0)
-          for (int i = 0; i < n; ++i) x[i] /= xm;
-        tri_solve(n, u0, u1, u2, mul, piv, x);
-        for (int q = cstart[c]; q < t; ++q) {
-          double s = 0.0;
-          for (int i = 0; i < n; ++i) s += Vt[(size_t)i * k + q] * x[i];
-          for (int i = 0; i < n; ++i) x[i] -= s * Vt[(size_t)i * k + q];
-        }
-        double nn = 0.0;
-        for (int i = 0; i < n; ++i) nn += x[i] * x[i];
-        nn = sqrt(nn);
-        for (int i = 0; i < n; ++i) x[i] /= nn;
+  const double lj = lam[j];
+  if (lane == 0) {
+    double r0 = d[0] - lj, r1 = (n > 1) ? e[0] : 0.0, r2 = 0.0;
+    for (int i = 0; i < n - 1; ++i) {
+      const double s0 = e[i], s1 = d[i + 1] - lj, s2 = (i + 2 < n) ? e[i + 1] : 0.0;
+      double mlt, n0, n1;
+      if (fabs(r0) >= fabs(s0)) {
+        if (r0 == 0.0) r0 = tiny;
+        mlt = s0 / r0;
+        piv[i] = 0;
+        u0[i] = r0; u1[i] = r1; u2[i] = r2;
+        n0 = s1 - mlt * r1;
+        n1 = s2 - mlt * r2;
+      } else {
+        mlt = r0 / s0;
+        piv[i] = 1;
+        u0[i] = s0; u1[i] = s1; u2[i] = s2;
+        n0 = r1 - mlt * s1;
+        n1 = r2 - mlt * s2;
       }
-      for (int i = 0; i < n; ++i) Vt[(size_t)i * k + t] = x[i];
+      mulv[i] = mlt;
+      r0 = n0; r1 = n1; r2 = 0.0;
+    }
+    if (r0 == 0.0) r0 = tiny;
+    u0[n - 1] = 1.0 / r0; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
+    for (int i = 0; i < n - 1; ++i) u0[i] = 1.0 / u0[i];   // solves multiply by the pivot inverses
+  }
+  __syncthreads();
+  for (int it = 0; it < 3; ++it) {
+    double xm = 0.0;
+    for (int i = lane; i < n; i += 64) xm = fmax(xm, fabs(x[i]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) xm = fmax(xm, __shfl_xor(xm, o, 64));
+    const double inv = (xm > 0.0) ? 1.0 / xm : 1.0;
+    for (int i = lane; i < n; i += 64) x[i] *= inv;
+    __syncthreads();
+    if (lane == 0) {
+      double xi = x[0];
+      for (int i = 0; i < n - 1; ++i) {
+        double xn = x[i + 1];
+        if (piv[i]) { const double tt = xi; xi = xn; xn = tt; }
+        xn -= mulv[i] * xi;
+        x[i] = xi;
+        xi = xn;
+      }
+      x[n - 1] = xi;
+      double xp1 = 0.0, xp2 = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        const double v = (x[i] - u1[i] * xp1 - u2[i] * xp2) * u0[i];
+        x[i] = v;
+        xp2 = xp1;
+        xp1 = v;
+      }
+    }
+    __syncthreads();
+  }
+  double nn = 0.0;
+  for (int i = lane; i < n; i += 64) nn = fma(x[i], x[i], nn);
+  nn = wave_sum(nn);
+  const double rn = 1.0 / sqrt(nn);
+  for (int i = lane; i < n; i += 64) Vt[(size_t)j * n + i] = x[i] * rn;
+}
+
+// 4a. Gram of the k vectors: G[a][b] = v_a . v_b for a >= b (one thread per pair).
+__global__ __launch_bounds__(kBlock) void vgram_kernel(int n, int k, const double* __restrict__ Vt,
+                                                      double* __restrict__ G) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= k * k) return;
+  const int a = q / k, b = q % k;
+  if (b > a) return;
+  const double* va = Vt + (size_t)a * n;
+  const double* vb = Vt + (size_t)b * n;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 3 < n; i += 4) {
+    s0 = fma(va[i], vb[i], s0);
+    s1 = fma(va[i + 1], vb[i + 1], s1);
+    s2 = fma(va[i + 2], vb[i + 2], s2);
+    s3 = fma(va[i + 3], vb[i + 3], s3);
+  }
+  for (; i < n; ++i) s0 = fma(va[i], vb[i], s0);
+  G[(size_t)a * k + b] = (s0 + s1) + (s2 + s3);
+}
+
+// 4b. L = chol(G), G <- L^{-1} (lower), in LDS, one block.  k <= kOrthoMaxK.
+constexpr int kOrthoMaxK = 128;
+__global__ __launch_bounds__(kDenseThreads) void cholinv_kernel(int k, double* __restrict__ G, int* info) {
+  __shared__ double L[kOrthoMaxK][kOrthoMaxK + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int q = tid; q < k * k; q += kDenseThreads) {
+    const int a = q / k, b = q % k;
+    L[a][b] = (b <= a) ? G[(size_t)a * k + b] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      const double dj = L[j][j];
+      if (!(dj > 0.0)) bad = 1;
+      L[j][j] = sqrt(dj > 0.0 ? dj : 1.0);
+    }
+    __syncthreads();
+    const double djj = L[j][j];
+    for (int i = j + 1 + tid; i < k; i += kDenseThreads) L[i][j] /= djj;
+    __syncthreads();
+    const int w = k - j - 1;
+    for (int q = tid; q < w * w; q += kDenseThreads) {
+      const int i = j + 1 + q / w, l = j + 1 + q % w;
+      if (l <= i) L[i][l] -= L[i][j] * L[l][j];
+    }
+    __syncthreads();
+  }
+  // inverse: column c by thread c (forward substitution), written to G
+  for (int c = tid; c < k; c += kDenseThreads) {
+    for (int i = 0; i < k; ++i) {
+      double sacc = (i == c) ? 1.0 : 0.0;
+      if (i >= c) {
+        for (int l = c; l < i; ++l) sacc -= L[i][l] * G[(size_t)l * k + c];
+        G[(size_t)i * k + c] = sacc / L[i][i];
+      } else {
+        G[(size_t)i * k + c] = 0.0;
+      }
+    }
+  }
+  if (tid == 0 && bad) *info = 1;
+}
+
+// 4c. Vo = L^{-1} Vi in the vector index: vo_j = sum_{l <= j} Li[j][l] vi_l.
+__global__ __launch_bounds__(kBlock) void vorth_apply_kernel(int n, int k, const double* __restrict__ Li,
+                                                            const double* __restrict__ Vi,
+                                                            double* __restrict__ Vo) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (long long)n * k) return;
+  const int j = (int)(q / n), i = (int)(q % n);
+  double s = 0.0;
+  for (int l = 0; l <= j; ++l) s = fma(Li[(size_t)j * k + l], Vi[(size_t)l * n + i], s);
+  Vo[q] = s;
+}
+
+// 4d. S matrices of the blocked back-transformation, one block of kWyB
+// reflectors per workgroup: S[r][r] = tau_r, S[0:r, r] = -tau_r S[0:r,0:r] (Y^T Y)[0:r, r].
+__global__ __launch_bounds__(kBlock) void wy_prep_kernel(int n, const double* __restrict__ T,
+                                                        const double* __restrict__ tri,
+                                                        double* __restrict__ Sall) {
+  __shared__ double YY[kWyB][kWyB + 1];
+  __shared__ double S[kWyB][kWyB + 1];
+  const int blk = blockIdx.x;
+  const int j0 = blk * kWyB;
+  const int nref = n - 2;
+  const int b = (nref - j0 < kWyB) ? nref - j0 : kWyB;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const double* tau = tri + 2 * n;
+  for (int pr = wave; pr < b * b; pr += kBlock / 64) {
+    const int l = pr / b, r = pr % b;
+    if (l > r) continue;
+    const int jl = j0 + l, jr = j0 + r;
+    double s2 = 0.0;
+    for (int i = jr + 1 + lane; i < n; i += 64) {
+      const double yl = (i == jl + 1) ? 1.0 : T[(size_t)jl * n + i];
+      const double yr = (i == jr + 1) ? 1.0 : T[(size_t)jr * n + i];
+      s2 = fma(yl, yr, s2);
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) { YY[l][r] = s2; YY[r][l] = s2; }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    for (int r = 0; r < b; ++r) {
+      double s2 = 0.0;
+      if (lane < r)
+        for (int q = lane; q < r; ++q) s2 = fma(S[lane][q], YY[q][r], s2);
+      if (lane < r) S[lane][r] = -tau[j0 + r] * s2;     // lane l owns row l of S
+      if (lane == r) S[r][r] = tau[j0 + r];
+      if (lane > r && lane < b) S[lane][r] = 0.0;
     }
   }
   __syncthreads();
-
-  // ---- 3b. two passes of Cholesky-QR over the n x k block (global orthogonality)
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int q = tid; q < k * k; q += kDenseThreads) {
-      const int a = q / k, b = q % k;
-      if (b > a) continue;
-      double s = 0.0;
-      for (int i = 0; i < n; ++i) s += Vt[(size_t)i * k + a] * Vt[(size_t)i * k + b];
-      G[(size_t)a * k + b] = s;
-    }
-    __syncthreads();
-    if (tid == 0) {   // k x k Cholesky, lower, in G
-      for (int j = 0; j < k; ++j) {
-        double s = G[(size_t)j * k + j];
-        for (int l = 0; l < j; ++l) s -= G[(size_t)j * k + l] * G[(size_t)j * k + l];
-        if (!(s > 0.0)) { *info = 1; s = 1.0; }
-        const double djj = sqrt(s);
-        G[(size_t)j * k + j] = djj;
-        for (int i = j + 1; i < k; ++i) {
-          double t = G[(size_t)i * k + j];
-          for (int l = 0; l < j; ++l) t -= G[(size_t)i * k + l] * G[(size_t)j * k + l];
-          G[(size_t)i * k + j] = t / djj;
-        }
-      }
-    }
-    __syncthreads();
-    // rows of Vt: x^T <- x^T L^{-T}, i.e. solve L y = x per row
-    for (int i = tid; i < n; i += kDenseThreads) {
-      double* xr = Vt + (size_t)i * k;
-      for (int j = 0; j < k; ++j) {
-        double s = xr[j];
-        for (int l = 0; l < j; ++l) s -= G[(size_t)j * k + l] * xr[l];
-        xr[j] = s / G[(size_t)j * k + j];
-      }
-    }
-    __syncthreads();
+  double* So = Sall + (size_t)blk * kWyB * kWyB;
+  for (int q = tid; q < kWyB * kWyB; q += kBlock) {
+    const int r = q / kWyB, c = q % kWyB;
+    So[q] = (r < b && c < b) ? S[r][c] : 0.0;
   }
+}
 
-  // ---- 4. back-transformation V = H_0 ... H_{n-3} Vt
-  for (int i = tid; i < n * k; i += kDenseThreads) V[i] = Vt[i];
+// 4e. Back-transformation of one eigenvector per workgroup, x <- Q x with
+// Q = prod_blocks (I - Y S Y^T), last block first; result stored into column c
+// of V (n x k, row-major).
+__global__ __launch_bounds__(kBlock) void wy_apply_kernel(int n, int k, const double* __restrict__ T,
+                                                         const double* __restrict__ Sall,
+                                                         const double* __restrict__ Vt, double* __restrict__ V) {
+  __shared__ double x[kSyevMaxN];
+  __shared__ double w1[kWyB], w2[kWyB];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < n; i += kBlock) x[i] = Vt[(size_t)c * n + i];
   __syncthreads();
-  for (int j = n - 3; j >= 0; --j) {
-    const double tj = tau[j];
-    if (tj == 0.0) continue;
-    const int m = n - j - 1;
-    // p[c] = tau * sum_i v_i V[j+1+i][c]
-    for (int c = wave; c < k; c += kDenseWaves) {
-      double s = 0.0;
-      for (int i = lane; i < m; i += 64) {
-        const double vi = (i == 0) ? 1.0 : T[(size_t)j * n + j + 1 + i];
-        s = fma(vi, V[(size_t)(j + 1 + i) * k + c], s);
+  const int nref = n - 2;
+  const int nblk = (nref + kWyB - 1) / kWyB;
+  for (int blk = nblk - 1; blk >= 0; --blk) {
+    const int j0 = blk * kWyB;
+    const int b = (nref - j0 < kWyB) ? nref - j0 : kWyB;
+    for (int r = wave; r < b; r += kBlock / 64) {
+      const int jr = j0 + r;
+      double s2 = 0.0;
+      for (int i = jr + 1 + lane; i < n; i += 64) {
+        const double yr = (i == jr + 1) ? 1.0 : T[(size_t)jr * n + i];
+        s2 = fma(yr, x[i], s2);
       }
-      s = wave_sum(s);
-      if (lane == 0) p[c] = tj * s;
+      s2 = wave_sum(s2);
+      if (lane == 0) w1[r] = s2;
     }
     __syncthreads();
-    for (int q = tid; q < m * k; q += kDenseThreads) {
-      const int i = q / k, c = q % k;
-      const double vi = (i == 0) ? 1.0 : T[(size_t)j * n + j + 1 + i];
-      V[(size_t)(j + 1 + i) * k + c] -= vi * p[c];
+    const double* S = Sall + (size_t)blk * kWyB * kWyB;
+    if (tid < b) {
+      double s2 = 0.0;
+      for (int l = tid; l < b; ++l) s2 = fma(S[tid * kWyB + l], w1[l], s2);
+      w2[tid] = s2;
+    }
+    __syncthreads();
+    for (int i = j0 + 1 + tid; i < n; i += kBlock) {
+      double s2 = 0.0;
+      const int rmax = (i - j0 - 1 < b - 1) ? (i - j0 - 1) : (b - 1);
+      for (int r = 0; r <= rmax; ++r) {
+        const int jr = j0 + r;
+        const double yr = (i == jr + 1) ? 1.0 : T[(size_t)jr * n + i];
+        s2 = fma(yr, w2[r], s2);
+      }
+      x[i] -= s2;
     }
     __syncthreads();
   }
-  for (int t = tid; t < k; t += kDenseThreads) wout[t] = lam[t];
+  for (int i = tid; i < n; i += kBlock) V[(size_t)i * k + c] = x[i];
 }
 
 }  // namespace
@@ -392,12 +620,35 @@ void launch_trinv(int n, const double* L, int ldl, double* Li, int ldi, hipStrea
 }
 
 size_t syev_work_doubles(int n, int k) {
-  // Vt (n k) + G (k k) + scratch (5 n k) + pivots (n k bytes, in doubles)
-  return (size_t)n * k + (size_t)k * k + (size_t)5 * n * k + ((size_t)n * k + 7) / 8 + 8;
+  // tri (3n + 8) + lam (k) + Vt, Vt2 (n k each) + G (k k) + S blocks
+  const size_t nblk = (size_t)(n + kWyB - 1) / kWyB + 1;
+  return (size_t)3 * n + 8 + (size_t)k + (size_t)2 * n * k + (size_t)k * k + nblk * kWyB * kWyB + 64;
 }
 
+int syev_max_k() { return kOrthoMaxK; }
+
 void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s) {
-  syev_lowest_kernel<<<1, kDenseThreads, 0, s>>>(n, k, T, w, V, work, info);
+  double* tri = work;
+  double* lam = tri + 3 * n + 8;
+  double* Vt = lam + k;
+  double* Vt2 = Vt + (size_t)n * k;
+  double* G = Vt2 + (size_t)n * k;
+  double* Sall = G + (size_t)k * k;
+  const unsigned gb = (unsigned)((k * k + kBlock - 1) / kBlock);
+  const unsigned ab = (unsigned)(((long long)n * k + kBlock - 1) / kBlock);
+  tridiag_kernel<<<1, kDenseThreads, 0, s>>>(n, T, tri);
+  bisect_kernel<<<k, 64, 0, s>>>(n, tri, lam);
+  invit_kernel<<<k, 64, 0, s>>>(n, k, tri, lam, Vt);
+  zero_info_kernel<<<1, 1, 0, s>>>(info);
+  for (int pass = 0; pass < 2; ++pass) {
+    vgram_kernel<<<gb, kBlock, 0, s>>>(n, k, Vt, G);
+    cholinv_kernel<<<1, kDenseThreads, 0, s>>>(k, G, info);
+    vorth_apply_kernel<<<ab, kBlock, 0, s>>>(n, k, G, Vt, Vt2);
+    double* t = Vt; Vt = Vt2; Vt2 = t;
+  }
+  if (n > 2) wy_prep_kernel<<<(n - 2 + kWyB - 1) / kWyB, kBlock, 0, s>>>(n, T, tri, Sall);
+  wy_apply_kernel<<<k, kBlock, 0, s>>>(n, k, T, Sall, Vt, V);
+  copy_lam_kernel<<<1, 256, 0, s>>>(k, lam, w);
 }
 
 int syev_max_n() { return kSyevMaxN; }

@@ -75,6 +75,30 @@ void launch_extract_galerkin(int dim, int m, const double* Y, double* coef, doub
 void launch_stencil_to_dense(int dim, int m, const double* coef, double hmass, int use_mass, double* D,
                              hipStream_t s);
 
+// ---- fine-level 3D LDS-staged stencil (stencil3d.hip)
+struct Fine3Args {
+  int m;                 // interior nodes per side
+  int k;                 // columns
+  double h;
+  const double* kappa;   // n^3 element coefficients or nullptr (kappa = 1)
+  const void* x;         // N x k (double or float)
+  const void* b;
+  const double* lam;
+  void* out1;
+  void* out2;
+  double* partial;       // EIGRES: [spatial blocks][3][k]
+  double omega;
+  int nzc;               // z-runs per column chunk
+  int fp32;              // 1: multi-vectors are float
+  const void* zero;      // >= 16 zero bytes (read by out-of-domain halo lanes)
+};
+void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s);
+int fine3_spatial_blocks(int m, int nzc);
+int fine3_default_nzc(int m);
+void fine3_set_zrun(int zl);
+void fine3_set_tile(int t);
+int fine3_max_spatial_blocks(int m);
+
 // ---- BLAS-like kernels (blas.hip)
 // per-column dot products of N x k blocks: out[j] = sum_i X[i,j] Y[i,j] (fixed-order two-pass)
 void launch_coldot(long long N, int k, const double* X, const double* Y, double* partial, int ptiles,
@@ -110,6 +134,7 @@ void launch_trinv(int n, const double* L, int ldl, double* Li, int ldi, hipStrea
 size_t syev_work_doubles(int n, int k);
 void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s);
 int syev_max_n();
+int syev_max_k();
 void launch_symmetrize(int n, double* A, hipStream_t s);
 
 }  // namespace pase

@@ -56,6 +56,7 @@ struct pase_handle {
   // V-cycle buffers per level (level 0 uses xa and r only)
   double *vb[PASE_MAX_LEVELS] = {}, *vx[PASE_MAX_LEVELS] = {}, *vxa[PASE_MAX_LEVELS] = {}, *vr[PASE_MAX_LEVELS] = {};
   double* kappa = nullptr;
+  bool kappa_is_one = false;    // problem given with kappa = NULL (constant coefficient)
   // coarse dense (NH x NH)
   double *AinvL = nullptr, *LBinv = nullptr, *BHinv = nullptr, *C0 = nullptr, *dtmp = nullptr;
   // small problem
@@ -69,6 +70,7 @@ struct pase_handle {
   double* partial = nullptr;
   size_t partial_doubles = 0;
   int* info = nullptr;          // device status words
+  double* zero16 = nullptr;     // 64 zero bytes
   double* setup_scratch = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
@@ -146,7 +148,7 @@ size_t layout(pase_handle* h, void* base) {
   h->dtmp = b.take<double>(NH * NH);
   h->nT = (int)(NH + K);
   const size_t nT = (size_t)h->nT;
-  if (h->nT <= syev_max_n()) {
+  if (h->nT <= syev_max_n() && (int)K <= syev_max_k()) {
     h->Tm = b.take<double>(nT * nT);
     h->Vs = b.take<double>(nT * K);
     h->syw = b.take<double>(syev_work_doubles(h->nT, (int)K));
@@ -165,10 +167,12 @@ size_t layout(pase_handle* h, void* base) {
     pd = std::max(pd, (size_t)coldot_tiles(N0, k) * k);
     pd = std::max(pd, (size_t)gram_tiles(N0, k) * k * k);
     pd = std::max(pd, (size_t)grid_launch(N0, k).blocks * 3 * k);
+    if (dim == 3) pd = std::max(pd, (size_t)fine3_max_spatial_blocks(h->lev[0].m) * 3 * k);
   }
   h->partial_doubles = pd;
   h->partial = b.take<double>(pd);
   h->info = b.take<int>(16);
+  h->zero16 = b.take<double>(8);
   return b.off + 256;
 }
 
@@ -189,12 +193,46 @@ StencilArgs stencil_args(pase_handle* h, int l, int k) {
   return a;
 }
 
-void apply_AM(pase_handle* h, int l, int k, const double* x, double* ax, double* mx) {
+// Every stencil application goes through here: the 3D fine level uses the
+// LDS-staged kernel, 2D problems and coarse levels the generic one.
+void stencil_op(pase_handle* h, int l, int k, Epi epi, const double* x, const double* b, double* out1,
+                double* out2) {
+  if (l == 0 && h->dim == 3) {
+    Fine3Args f{};
+    f.m = h->lev[0].m;
+    f.k = k;
+    f.h = h->lev[0].h;
+    f.kappa = h->kappa_is_one ? nullptr : h->kappa;
+    f.x = x;
+    f.b = b;
+    f.lam = h->lam;
+    f.out1 = out1;
+    f.out2 = out2;
+    f.partial = h->partial;
+    f.omega = h->opt.omega;
+    f.nzc = fine3_default_nzc(f.m);
+    f.fp32 = 0;
+    f.zero = h->zero16;
+    launch_fine3(f, epi, h->stream);
+    return;
+  }
   StencilArgs a = stencil_args(h, l, k);
   a.x = x;
-  a.out1 = ax;
-  a.out2 = mx;
-  launch_stencil(a, EPI_AM, h->stream);
+  a.b = b;
+  a.lam = h->lam;
+  a.out1 = out1;
+  a.out2 = out2;
+  a.partial = h->partial;
+  launch_stencil(a, epi, h->stream);
+}
+
+int eigres_tiles(pase_handle* h, int k) {
+  if (h->dim == 3) return fine3_spatial_blocks(h->lev[0].m, fine3_default_nzc(h->lev[0].m));
+  return grid_launch(h->lev[0].N, k).tiles;
+}
+
+void apply_AM(pase_handle* h, int l, int k, const double* x, double* ax, double* mx) {
+  stencil_op(h, l, k, EPI_AM, x, nullptr, ax, mx);
 }
 
 // x = V(b) on level l (x must not alias b)
@@ -212,21 +250,16 @@ void vcycle(pase_handle* h, int l, int k, const double* b, double* x) {
   launch_first_sweep(h->dim, lv.N, k, lv.dinv, h->opt.omega, b, t0, s);
   double* cur = t0;
   double* oth = t1;
-  StencilArgs a = stencil_args(h, l, k);
-  a.b = b;
   for (int i = 1; i < h->opt.nu; ++i) {
-    a.x = cur; a.out1 = oth;
-    launch_stencil(a, EPI_SWEEP, s);
+    stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr);
     std::swap(cur, oth);
   }
-  a.x = cur; a.out1 = h->vr[l];
-  launch_stencil(a, EPI_RESID, s);
+  stencil_op(h, l, k, EPI_RESID, cur, b, h->vr[l], nullptr);
   launch_restrict(h->dim, lv.m, h->lev[l + 1].m, k, h->vr[l], h->vb[l + 1], s);
   vcycle(h, l + 1, k, h->vb[l + 1], h->vx[l + 1]);
   launch_prolong(h->dim, lv.m, h->lev[l + 1].m, k, h->vx[l + 1], cur, 1, s);
   for (int i = 0; i < h->opt.nu; ++i) {
-    a.x = cur; a.out1 = oth;
-    launch_stencil(a, EPI_SWEEP, s);
+    stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr);
     std::swap(cur, oth);
   }
 }
@@ -279,14 +312,8 @@ void pcg(pase_handle* h, int k, double* X, double* R) {
 
 // R = lam M U - A U with fused column sums (|R|^2, |MU|^2, U.MU) into h->sums
 void eig_residual(pase_handle* h, int k, const double* U, double* R) {
-  StencilArgs a = stencil_args(h, 0, k);
-  a.x = U;
-  a.lam = h->lam;
-  a.out1 = R;
-  a.partial = h->partial;
-  launch_stencil(a, EPI_EIGRES, h->stream);
-  const GridLaunch g = grid_launch(h->lev[0].N, k);
-  launch_reduce_partials(g.tiles, 3 * k, h->partial, h->sums, h->stream);
+  stencil_op(h, 0, k, EPI_EIGRES, U, nullptr, R, nullptr);
+  launch_reduce_partials(eigres_tiles(h, k), 3 * k, h->partial, h->sums, h->stream);
 }
 
 // Cholesky-QR in the M inner product: U <- U L^{-T}, U^T M U = L L^T.  info slot 'slot'.
@@ -438,6 +465,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   }
   layout(h, workspace);
   h->lev[0].kappa = h->kappa;
+  h->kappa_is_one = (prob->kappa == nullptr);
   hipStream_t s = h->stream;
   auto bail = [&](pase_status r) {
     g_last_error = h->err;
@@ -461,6 +489,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
     HIPS(hipMemcpyAsync(h->kappa, ones.data(), ne * sizeof(double), hipMemcpyHostToDevice, s));
     HIPS(hipStreamSynchronize(s));
   }
+  HIPS(hipMemsetAsync(h->zero16, 0, 8 * sizeof(double), s));
   launch_kappa_dinv(h->dim, f.n, h->kappa, h->lev[0].dinv, s);
   // Galerkin stencils A_l = P_l^T A_{l-1} P_l from 3^d colour probes
   const int NS = h->NS;
@@ -597,7 +626,7 @@ pase_status pase_small_eig(pase_handle* h, int n, int k, const double* T, double
   pase_status st = check_k(h, k);
   if (st) return st;
   if (!h->Tm) return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
-  if (!T || !w_host || !V || n < 2 || n > pase_small_eig_max_n(h) || k > n)
+  if (!T || !w_host || !V || n < 2 || n > pase_small_eig_max_n(h) || k > n || k > syev_max_k())
     return fail(h, PASE_E_ARG, "bad small_eig arguments");
   HIPC(hipMemcpyAsync(h->Tm, T, sizeof(double) * n * n, hipMemcpyDeviceToDevice, h->stream));
   launch_syev_lowest(n, k, h->Tm, h->lam, V, h->syw, h->info + 2, h->stream);
@@ -708,6 +737,10 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   return PASE_OK;
 }
 
+// Tuning knob: z-run length of the fine-level 3D stencil blocks (0 = default).
+void pase_tune_fine3_zrun(int zl) { fine3_set_zrun(zl); }
+void pase_tune_fine3_tile(int t) { fine3_set_tile(t); }
+
 pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double* ms) {
   pase_status st = check_k(h, k);
   if (st) return st;
@@ -717,12 +750,7 @@ pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double*
   const long long N = h->lev[0].N;
   auto once = [&]() {
     switch (which) {
-      case 0: {
-        StencilArgs a = stencil_args(h, 0, k);
-        a.x = h->U; a.b = h->R; a.out1 = h->Z;
-        launch_stencil(a, EPI_SWEEP, s);
-        break;
-      }
+      case 0: stencil_op(h, 0, k, EPI_SWEEP, h->U, h->R, h->Z, nullptr); break;
       case 1: apply_AM(h, 0, k, h->U, h->W2, h->W3); break;
       case 2: launch_gram(N, k, h->U, h->W2, h->partial, gram_tiles(N, k), h->kk1, s); break;
       case 3: vcycle(h, 0, k, h->R, h->Z); break;
