@@ -21,6 +21,9 @@ constexpr int kDenseWaves = kDenseThreads / 64;
 constexpr int kSyevMaxN = 1024;
 
 __global__ void zero_info_kernel(int* info) { *info = 0; }
+__global__ void fold_err_kernel(int* info, const int* err) {
+  if (*err) *info = 2;
+}
 
 __global__ void copy_lam_kernel(int k, const double* __restrict__ a, double* __restrict__ b) {
   for (int i = threadIdx.x; i < k; i += blockDim.x) b[i] = a[i];
@@ -305,6 +308,238 @@ __global__ __launch_bounds__(kDenseThreads) void tridiag_kernel(int n, double* _
   }
 }
 
+// 1b. Cooperative Householder tridiagonalisation for n <= kCoopMaxN.
+//
+// NW workgroups each hold a cyclic slab of rows of T in LDS (block b owns rows
+// i with i % NW == b), so the matrix never streams from L2.  Step j needs the
+// product p_j = tau_j A22 v_j over all rows and row j+1 after update j; both are
+// exchanged through global memory with one software grid barrier per step:
+//   - after the barrier every block reads p_j (m values) and row j+1 as it was
+//     before update j, forms w_j = p_j - K_j v_j, updates its copy of row j+1
+//     and builds reflector j+1 from it (every block the same way, so v_{j+1} is
+//     identical everywhere without a second barrier);
+//   - one pass over its own rows applies update j and accumulates
+//     p_{j+1} = tau_{j+1} A v_{j+1}; the owner of row j+2 publishes that row.
+// The grid is launched 8x larger than NW and only blocks with index % 8 == 0
+// work, so the working blocks share one XCD (blocks are dealt round-robin over
+// the 8 XCDs) and its L2.  Exchanged data is read with agent-scope atomic loads
+// and published before a release on the barrier counter.  The spin on the
+// counter is bounded: on timeout a block raises *err and returns, so every wave
+// exits.
+constexpr int kCoopMaxN = 512;
+constexpr int kCoopThreads = 512;
+constexpr int kCoopWaves = kCoopThreads / 64;
+
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ bool grid_barrier(unsigned* counter, unsigned target, int* err) {
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    ok = 1;
+    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 26) ||
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+__device__ double block_sum_c(double v, double (*red)[kCoopWaves], int& parity) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* r = red[parity];
+  parity ^= 1;
+  if (lane == 0) r[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kCoopWaves; ++w) s += r[w];
+  return s;
+}
+
+// reflector from x = row[0 .. mm-1]: v[0] = 1, v[i] = x[i] / (alpha - beta); returns tau
+__device__ double make_reflector(const double* row, int mm, double* v, double& beta_out,
+                                 double (*red)[kCoopWaves], int& parity) {
+  double part = 0.0;
+  for (int i = 1 + threadIdx.x; i < mm; i += kCoopThreads) part = fma(row[i], row[i], part);
+  const double xn2 = block_sum_c(part, red, parity);
+  const double alpha = row[0];
+  if (xn2 == 0.0) {
+    for (int i = threadIdx.x; i < mm; i += kCoopThreads) v[i] = (i == 0) ? 1.0 : 0.0;
+    beta_out = alpha;
+    __syncthreads();
+    return 0.0;
+  }
+  const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+  const double sc = 1.0 / (alpha - beta);
+  for (int i = threadIdx.x; i < mm; i += kCoopThreads) v[i] = (i == 0) ? 1.0 : row[i] * sc;
+  beta_out = beta;
+  __syncthreads();
+  return (beta - alpha) / beta;
+}
+
+__global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int n, int NW, double* __restrict__ T,
+                                                                   double* __restrict__ tri,
+                                                                   double* __restrict__ xchg,
+                                                                   unsigned* counter, int* err) {
+  if (blockIdx.x % 8 != 0) return;
+  const int b = blockIdx.x / 8;
+  if (b >= NW) return;
+  extern __shared__ double dyn[];
+  const int R = (n + NW - 1) / NW;               // owned rows (cyclic)
+  double* slab = dyn;                            // R x n
+  double* v = slab + (size_t)R * n;              // reflector j     (indexed by global column - (j+1))
+  double* w = v + kCoopMaxN;                     // w_j / scratch
+  double* v2 = w + kCoopMaxN;                    // reflector j+1
+  double* prow = v2 + kCoopMaxN;                 // row j+1 copy (global column index)
+  double* pp = prow + kCoopMaxN;                 // p_j (indexed like v)
+  __shared__ double red[2][kCoopWaves];
+  int parity = 0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double* pbuf = xchg;                           // 2 x kCoopMaxN, alternating per step
+  double* rbuf = xchg + 2 * kCoopMaxN;           // 2 x kCoopMaxN
+  double* d = tri;
+  double* e = tri + n;
+  double* tau = tri + 2 * n;
+  unsigned target = 0;
+  // load owned rows
+  for (int q = 0; q < R; ++q) {
+    const int r = q * NW + b;
+    for (int c = tid; c < n; c += kCoopThreads) slab[(size_t)q * n + c] = (r < n) ? T[(size_t)r * n + c] : 0.0;
+  }
+  // reflector 0 from row 0 (every block)
+  for (int c = tid; c < n; c += kCoopThreads) prow[c] = T[c];
+  __syncthreads();
+  double beta0;
+  double tcur = make_reflector(prow + 1, n - 1, v, beta0, red, parity);
+  if (b == 0 && tid == 0) { d[0] = prow[0]; e[0] = beta0; tau[0] = tcur; }
+  if (b == 0) for (int i = 1 + tid; i < n - 1; i += kCoopThreads) T[i + 1] = v[i];
+  // p_0 over owned rows r >= 1: p[r-1] = tau0 sum_{c>=1} A[r][c] v[c-1]
+  for (int q = wave; q < R; q += kCoopWaves) {
+    const int r = q * NW + b;
+    if (r < 1 || r >= n) continue;
+    const double* ar = slab + (size_t)q * n;
+    double acc = 0.0;
+    for (int c = 1 + lane; c < n; c += 64) acc = fma(ar[c], v[c - 1], acc);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) __hip_atomic_store(&pbuf[r - 1], tcur * acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (1 % NW == b)
+    for (int c = tid; c < n; c += kCoopThreads)
+      __hip_atomic_store(&rbuf[c], slab[(size_t)(1 / NW) * n + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  target += NW;
+  if (!grid_barrier(counter, target, err)) return;
+  for (int j = 0; j + 2 < n; ++j) {
+    const int m = n - j - 1;                     // trailing size of step j (global cols j+1 .. n-1)
+    const int par = j & 1;
+    const double* pin = pbuf + par * kCoopMaxN;
+    const double* rin = rbuf + par * kCoopMaxN;
+    double* pout = pbuf + (par ^ 1) * kCoopMaxN;
+    double* rout = rbuf + (par ^ 1) * kCoopMaxN;
+    for (int i = tid; i < m; i += kCoopThreads) pp[i] = ld_agent(pin + i);
+    for (int c = tid; c < n; c += kCoopThreads) prow[c] = (c >= j + 1) ? ld_agent(rin + c) : 0.0;
+    __syncthreads();
+    double pv = 0.0;
+    for (int i = tid; i < m; i += kCoopThreads) pv = fma(pp[i], v[i], pv);
+    const double K = 0.5 * tcur * block_sum_c(pv, red, parity);
+    for (int i = tid; i < m; i += kCoopThreads) w[i] = pp[i] - K * v[i];
+    __syncthreads();
+    // row j+1 after update j: prow[c] -= v[0] w[c'] + w[0] v[c']  (c' = c - (j+1))
+    const double v0 = v[0], w0 = w[0];
+    for (int c = j + 1 + tid; c < n; c += kCoopThreads) {
+      const int cc = c - (j + 1);
+      prow[c] -= v0 * w[cc] + w0 * v[cc];
+    }
+    __syncthreads();
+    const bool has_next = (j + 3 < n);
+    double tnext = 0.0, bnext = 0.0;
+    if (has_next) {
+      tnext = make_reflector(prow + (j + 2), m - 1, v2, bnext, red, parity);
+      if (b == 0 && tid == 0) { d[j + 1] = prow[j + 1]; e[j + 1] = bnext; tau[j + 1] = tnext; }
+      if ((j + 1) % NW == b)
+        for (int i = 1 + tid; i < m - 1; i += kCoopThreads) T[(size_t)(j + 1) * n + (j + 2) + i] = v2[i];
+    } else if (b == 0 && tid == 0) {
+      d[j + 1] = prow[j + 1];
+      e[j + 1] = prow[j + 2];
+      tau[j + 1] = 0.0;
+    }
+    // update j on owned rows r >= j+2 (columns >= j+2) and p_{j+1} = tnext A v2
+    for (int q = wave; q < R; q += kCoopWaves) {
+      const int r = q * NW + b;
+      if (r < j + 2 || r >= n) continue;
+      double* ar = slab + (size_t)q * n;
+      const int rr = r - (j + 1);
+      const double vr = v[rr], wr = w[rr];
+      double acc = 0.0;
+      for (int c = j + 2 + lane; c < n; c += 64) {
+        const int cc = c - (j + 1);
+        const double a = ar[c] - (vr * w[cc] + wr * v[cc]);
+        ar[c] = a;
+        acc = fma(a, v2[c - (j + 2)], acc);
+      }
+      if (has_next) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0)
+          __hip_atomic_store(&pout[r - (j + 2)], tnext * acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __syncthreads();
+    if (has_next && (j + 2) % NW == b) {
+      const double* ar = slab + (size_t)((j + 2) / NW) * n;
+      for (int c = j + 2 + tid; c < n; c += kCoopThreads)
+        __hip_atomic_store(&rout[c], ar[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!has_next) {
+      // last step: row n-1 after update j is in the slab of its owner
+      if ((n - 1) % NW == b && tid == 0) d[n - 1] = slab[(size_t)((n - 1) / NW) * n + (n - 1)];
+      break;
+    }
+    double* t1 = v; v = v2; v2 = t1;
+    tcur = tnext;
+    target += NW;
+    if (!grid_barrier(counter, target, err)) return;
+  }
+}
+
+__global__ void tri_finish_kernel(int n, double* __restrict__ tri) {
+  // Gershgorin interval, pivmin and |T| of the tridiagonal (one thread)
+  double* d = tri;
+  double* e = tri + n;
+  e[n - 1] = 0.0;
+  double lo = DBL_MAX, hi = -DBL_MAX, emax = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double rr = ((i > 0) ? fabs(e[i - 1]) : 0.0) + ((i + 1 < n) ? fabs(e[i]) : 0.0);
+    lo = fmin(lo, d[i] - rr);
+    hi = fmax(hi, d[i] + rr);
+    if (i + 1 < n) emax = fmax(emax, e[i] * e[i]);
+  }
+  const double tnorm = fmax(fabs(lo), fabs(hi));
+  double* sc = tri + 3 * n;
+  sc[0] = lo - (2.0 * DBL_EPSILON * tnorm * n + DBL_MIN);
+  sc[1] = hi + (2.0 * DBL_EPSILON * tnorm * n + DBL_MIN);
+  sc[2] = DBL_MIN * fmax(1.0, emax);
+  sc[3] = tnorm;
+}
+
+__global__ void coop_reset_kernel(unsigned* counter, int* err) {
+  *counter = 0u;
+  *err = 0;
+}
+
 __device__ int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
   int c = 0;
   double q = d[0] - x;
@@ -463,6 +698,7 @@ constexpr int kOrthoMaxK = 128;
 __global__ __launch_bounds__(kDenseThreads) void cholinv_kernel(int k, double* __restrict__ G, int* info) {
   __shared__ double L[kOrthoMaxK][kOrthoMaxK + 1];
   __shared__ int bad;
+  __shared__ double ptol;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
   for (int q = tid; q < k * k; q += kDenseThreads) {
@@ -470,10 +706,16 @@ __global__ __launch_bounds__(kDenseThreads) void cholinv_kernel(int k, double* _
     L[a][b] = (b <= a) ? G[(size_t)a * k + b] : 0.0;
   }
   __syncthreads();
+  if (tid == 0) {      // pivots at or below k eps max_i G_ii count as rank deficiency
+    double dmax = 0.0;
+    for (int i = 0; i < k; ++i) dmax = fmax(dmax, L[i][i]);
+    ptol = k * DBL_EPSILON * dmax;
+  }
+  __syncthreads();
   for (int j = 0; j < k; ++j) {
     if (tid == 0) {
       const double dj = L[j][j];
-      if (!(dj > 0.0)) bad = 1;
+      if (!(dj > ptol)) bad = 1;
       L[j][j] = sqrt(dj > 0.0 ? dj : 1.0);
     }
     __syncthreads();
@@ -622,10 +864,15 @@ void launch_trinv(int n, const double* L, int ldl, double* Li, int ldi, hipStrea
 size_t syev_work_doubles(int n, int k) {
   // tri (3n + 8) + lam (k) + Vt, Vt2 (n k each) + G (k k) + S blocks
   const size_t nblk = (size_t)(n + kWyB - 1) / kWyB + 1;
-  return (size_t)3 * n + 8 + (size_t)k + (size_t)2 * n * k + (size_t)k * k + nblk * kWyB * kWyB + 64;
+  return (size_t)3 * n + 8 + (size_t)k + (size_t)2 * n * k + (size_t)k * k + nblk * kWyB * kWyB +
+         4 * kCoopMaxN + 72;
 }
 
 int syev_max_k() { return kOrthoMaxK; }
+
+void launch_cholinv(int k, double* G, int* info, hipStream_t s) {
+  cholinv_kernel<<<1, kDenseThreads, 0, s>>>(k, G, info);
+}
 
 void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s) {
   double* tri = work;
@@ -634,12 +881,31 @@ void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* w
   double* Vt2 = Vt + (size_t)n * k;
   double* G = Vt2 + (size_t)n * k;
   double* Sall = G + (size_t)k * k;
+  const size_t nblk = (size_t)(n + kWyB - 1) / kWyB + 1;
+  double* xchg = Sall + nblk * kWyB * kWyB;                  // 4 x kCoopMaxN
+  unsigned* coop_counter = (unsigned*)(xchg + 4 * kCoopMaxN);
+  int* coop_err = (int*)(coop_counter + 1);
+  zero_info_kernel<<<1, 1, 0, s>>>(info);
   const unsigned gb = (unsigned)((k * k + kBlock - 1) / kBlock);
   const unsigned ab = (unsigned)(((long long)n * k + kBlock - 1) / kBlock);
-  tridiag_kernel<<<1, kDenseThreads, 0, s>>>(n, T, tri);
+  // cooperative path: NW blocks whose row slabs fit in LDS
+  int NW = 0;
+  if (n >= 8 && n <= kCoopMaxN) {
+    for (int nw = 8; nw <= 32; nw *= 2) {
+      const size_t lds = ((size_t)((n + nw - 1) / nw) * n + 5 * kCoopMaxN) * sizeof(double);
+      if (lds <= 150 * 1024) { NW = nw; break; }
+    }
+  }
+  if (NW > 0) {
+    const size_t lds = ((size_t)((n + NW - 1) / NW) * n + 5 * kCoopMaxN) * sizeof(double);
+    coop_reset_kernel<<<1, 1, 0, s>>>(coop_counter, coop_err);
+    tridiag_coop_kernel<<<8 * NW, kCoopThreads, lds, s>>>(n, NW, T, tri, xchg, coop_counter, coop_err);
+    tri_finish_kernel<<<1, 1, 0, s>>>(n, tri);
+  } else {
+    tridiag_kernel<<<1, kDenseThreads, 0, s>>>(n, T, tri);
+  }
   bisect_kernel<<<k, 64, 0, s>>>(n, tri, lam);
   invit_kernel<<<k, 64, 0, s>>>(n, k, tri, lam, Vt);
-  zero_info_kernel<<<1, 1, 0, s>>>(info);
   for (int pass = 0; pass < 2; ++pass) {
     vgram_kernel<<<gb, kBlock, 0, s>>>(n, k, Vt, G);
     cholinv_kernel<<<1, kDenseThreads, 0, s>>>(k, G, info);
@@ -649,6 +915,7 @@ void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* w
   if (n > 2) wy_prep_kernel<<<(n - 2 + kWyB - 1) / kWyB, kBlock, 0, s>>>(n, T, tri, Sall);
   wy_apply_kernel<<<k, kBlock, 0, s>>>(n, k, T, Sall, Vt, V);
   copy_lam_kernel<<<1, 256, 0, s>>>(k, lam, w);
+  if (NW > 0) fold_err_kernel<<<1, 1, 0, s>>>(info, coop_err);
 }
 
 int syev_max_n() { return kSyevMaxN; }

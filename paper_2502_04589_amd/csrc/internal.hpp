@@ -135,6 +135,8 @@ size_t syev_work_doubles(int n, int k);
 void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s);
 int syev_max_n();
 int syev_max_k();
+// G (k x k, lower part read) <- L^{-1} with G = L L^T, in LDS; *info = 1 on a non-positive pivot. k <= syev_max_k()
+void launch_cholinv(int k, double* G, int* info, hipStream_t s);
 void launch_symmetrize(int n, double* A, hipStream_t s);
 
 }  // namespace pase

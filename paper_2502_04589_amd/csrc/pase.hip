@@ -321,10 +321,8 @@ void cholqr_m(pase_handle* h, int k, double*& U, double*& spare, int slot) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   apply_AM(h, 0, k, U, nullptr, h->W3);
-  launch_gram(N, k, U, h->W3, h->partial, gram_tiles(N, k), h->kk1, s);
-  launch_symmetrize(k, h->kk1, s);
-  launch_cholesky(k, h->kk1, k, h->info + slot, s);
-  launch_trinv(k, h->kk1, k, h->kk2, k, s);
+  launch_gram(N, k, U, h->W3, h->partial, gram_tiles(N, k), h->kk2, s);
+  launch_cholinv(k, h->kk2, h->info + slot, s);            // kk2 <- L^{-1}
   launch_gemm(false, true, (int)N, k, k, 1.0, U, k, h->kk2, k, 0.0, spare, k, s);
   std::swap(U, spare);
 }
@@ -351,8 +349,8 @@ pase_status correction(pase_handle* h, int k) {
   launch_gram(N, k, W, h->W3, h->partial, gram_tiles(N, k), h->kk2, s);   // beta
   launch_symmetrize(k, h->kk1, s);
   launch_symmetrize(k, h->kk2, s);
-  launch_cholesky(k, h->kk2, k, h->info + 1, s);           // beta = L L^T
-  launch_trinv(k, h->kk2, k, h->kk3, k, s);                // Li = L^{-1}
+  launch_cholinv(k, h->kk2, h->info + 1, s);               // beta = L L^T, kk2 <- L^{-1}
+  launch_copy((size_t)k * k, h->kk2, h->kk3, s);           // Li
   // H = Li alpha Li^T
   launch_gemm(false, false, k, k, k, 1.0, h->kk3, k, h->kk1, k, 0.0, h->kk4, k, s);
   launch_gemm(false, true, k, k, k, 1.0, h->kk4, k, h->kk3, k, 0.0, h->kk5, k, s);
@@ -646,6 +644,7 @@ pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* 
   if (!lambda_host || !U) return fail(h, PASE_E_ARG, "null argument");
   const long long N = h->lev[0].N;
   hipStream_t s = h->stream;
+  HIPC(hipMemsetAsync(h->info, 0, 16 * sizeof(int), s));
   HIPC(hipMemcpyAsync(h->lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
   launch_copy((size_t)N * k, U, h->U, s);
   eig_residual(h, k, h->U, h->R);
