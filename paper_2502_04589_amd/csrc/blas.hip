@@ -18,8 +18,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 constexpr int kColdotPasses = 16;
 
 // partial[tile][j] = sum over the tile's rows of X[i,j] * Y[i,j]
-__global__ __launch_bounds__(kBlock) void coldot_kernel(long long N, int k, const double* __restrict__ X,
-                                                        const double* __restrict__ Y, double* __restrict__ partial,
+template <typename T>
+__global__ __launch_bounds__(kBlock) void coldot_kernel(long long N, int k, const T* __restrict__ X,
+                                                        const T* __restrict__ Y, double* __restrict__ partial,
                                                         int tiles, int rows) {
   __shared__ double red[kBlock];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -31,7 +32,7 @@ __global__ __launch_bounds__(kBlock) void coldot_kernel(long long N, int k, cons
   const long long r1 = (r0 + rows < N) ? (r0 + rows) : N;
   double acc = 0.0;
   if (slot < slots)
-    for (long long r = r0 + slot; r < r1; r += slots) acc = fma(X[r * k + col], Y[r * k + col], acc);
+    for (long long r = r0 + slot; r < r1; r += slots) acc = fma((double)X[r * k + col], (double)Y[r * k + col], acc);
   red[threadIdx.x] = acc;
   __syncthreads();
   if (threadIdx.x < k) {
@@ -72,20 +73,48 @@ __global__ void pcg_beta_kernel(int k, const double* rn, const double* ro, doubl
   beta[j] = (d != 0.0) ? rn[j] / d : 0.0;
 }
 
-__global__ void axpy2_kernel(long long N, int k, const double* __restrict__ alpha, const double* __restrict__ P,
-                             const double* __restrict__ Q, double* __restrict__ X, double* __restrict__ R) {
+template <typename T>
+__global__ void axpy2_kernel(long long N, int k, const double* __restrict__ alpha, const T* __restrict__ P,
+                             const T* __restrict__ Q, T* __restrict__ X, T* __restrict__ R) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * k) return;
   const double a = alpha[i % k];
-  X[i] = fma(a, P[i], X[i]);
-  R[i] = fma(-a, Q[i], R[i]);
+  X[i] = (T)fma(a, (double)P[i], (double)X[i]);
+  R[i] = (T)fma(-a, (double)Q[i], (double)R[i]);
 }
 
-__global__ void xpby_kernel(long long N, int k, const double* __restrict__ Z, const double* __restrict__ beta,
-                            double* __restrict__ P) {
+template <typename T>
+__global__ void xpby_kernel(long long N, int k, const T* __restrict__ Z, const double* __restrict__ beta,
+                            T* __restrict__ P) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * k) return;
-  P[i] = fma(beta[i % k], P[i], Z[i]);
+  P[i] = (T)fma(beta[i % k], (double)P[i], (double)Z[i]);
+}
+
+__global__ void d2f_kernel(size_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// start of the correction-form CG: r = (float)R, e = 0
+__global__ void cg_start_f32_kernel(size_t n, const double* __restrict__ R, float* __restrict__ r,
+                                    float* __restrict__ e) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    r[i] = (float)R[i];
+    e[i] = 0.0f;
+  }
+}
+
+__global__ void copy_f32_kernel(size_t n, const float* __restrict__ s, float* __restrict__ d) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+__global__ void add_f2d_kernel(size_t n, const double* __restrict__ u, const float* __restrict__ e,
+                               double* __restrict__ w) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = u[i] + (double)e[i];
 }
 
 __global__ void copy_kernel(size_t n, const double* __restrict__ s, double* __restrict__ d) {
@@ -150,34 +179,35 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(long long N, int k, const 
 // ---- generic tiled FP64 GEMM: C = alpha op(A) op(B) + beta C (row-major)
 constexpr int GT = 64, GK = 16;
 
+template <typename T>
 __global__ __launch_bounds__(kBlock) void gemm_kernel(int ta, int tb, int M, int N, int K, double alpha,
-                                                      const double* __restrict__ A, int lda,
-                                                      const double* __restrict__ B, int ldb, double beta,
-                                                      double* __restrict__ C, int ldc) {
-  __shared__ double As[GK][GT + 1];
-  __shared__ double Bs[GK][GT + 1];
+                                                      const T* __restrict__ A, int lda,
+                                                      const T* __restrict__ B, int ldb, double beta,
+                                                      T* __restrict__ C, int ldc) {
+  __shared__ T As[GK][GT + 1];
+  __shared__ T Bs[GK][GT + 1];
   const int bm = blockIdx.y * GT, bn = blockIdx.x * GT;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4] = {};
+  T acc[4][4] = {};
   for (int k0 = 0; k0 < K; k0 += GK) {
     for (int e = threadIdx.x; e < GK * GT; e += kBlock) {
       // A tile: op(A)[bm + i][k0 + kk]
       const int kk = e / GT, i = e % GT;
       const int gi = bm + i, gk = k0 + kk;
-      double v = 0.0;
+      T v = (T)0;
       if (gi < M && gk < K) v = ta ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
       As[kk][i] = v;
       // B tile: op(B)[k0 + kk][bn + j]
       const int j = i;
       const int gj = bn + j;
-      double w = 0.0;
+      T w = (T)0;
       if (gj < N && gk < K) w = tb ? B[(size_t)gj * ldb + gk] : B[(size_t)gk * ldb + gj];
       Bs[kk][j] = w;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < GK; ++kk) {
-      double a[4], b[4];
+      T a[4], b[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         a[q] = As[kk][ty + 16 * q];
@@ -196,8 +226,8 @@ __global__ __launch_bounds__(kBlock) void gemm_kernel(int ta, int tb, int M, int
     for (int q = 0; q < 4; ++q) {
       const int i = bm + ty + 16 * p, j = bn + tx + 16 * q;
       if (i < M && j < N) {
-        double* c = C + (size_t)i * ldc + j;
-        *c = (beta == 0.0) ? alpha * acc[p][q] : fma(alpha, acc[p][q], beta * *c);
+        T* c = C + (size_t)i * ldc + j;
+        *c = (beta == 0.0) ? (T)(alpha * acc[p][q]) : (T)fma(alpha, (double)acc[p][q], beta * (double)*c);
       }
     }
 }
@@ -233,7 +263,17 @@ void launch_coldot(long long N, int k, const double* X, const double* Y, double*
   const int tiles = (int)((N + rows - 1) / rows);
   const int blocks = ((tiles + 7) / 8) * 8;
   (void)ptiles;
-  coldot_kernel<<<blocks, kBlock, 0, s>>>(N, k, X, Y, partial, tiles, rows);
+  coldot_kernel<double><<<blocks, kBlock, 0, s>>>(N, k, X, Y, partial, tiles, rows);
+  reduce_partials_kernel<<<k, kBlock, 0, s>>>(tiles, k, partial, out);
+}
+
+void launch_coldot_f32(long long N, int k, const float* X, const float* Y, double* partial, double* out,
+                       hipStream_t s) {
+  const int slots = kBlock / k;
+  const int rows = slots * kColdotPasses;
+  const int tiles = (int)((N + rows - 1) / rows);
+  const int blocks = ((tiles + 7) / 8) * 8;
+  coldot_kernel<float><<<blocks, kBlock, 0, s>>>(N, k, X, Y, partial, tiles, rows);
   reduce_partials_kernel<<<k, kBlock, 0, s>>>(tiles, k, partial, out);
 }
 
@@ -251,11 +291,36 @@ void launch_pcg_beta(int k, const double* rn, const double* ro, double* beta, hi
 
 void launch_axpy2(long long N, int k, const double* alpha, const double* P, const double* Q, double* X, double* R,
                   hipStream_t s) {
-  axpy2_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, R);
+  axpy2_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, R);
 }
 
 void launch_xpby(long long N, int k, const double* Z, const double* beta, double* P, hipStream_t s) {
-  xpby_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, Z, beta, P);
+  xpby_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, Z, beta, P);
+}
+
+void launch_axpy2_f32(long long N, int k, const double* alpha, const float* P, const float* Q, float* X, float* R,
+                      hipStream_t s) {
+  axpy2_kernel<float><<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, R);
+}
+
+void launch_xpby_f32(long long N, int k, const float* Z, const double* beta, float* P, hipStream_t s) {
+  xpby_kernel<float><<<nblk(N * k), kBlock, 0, s>>>(N, k, Z, beta, P);
+}
+
+void launch_d2f(size_t n, const double* a, float* b, hipStream_t s) {
+  d2f_kernel<<<nblk((long long)n), kBlock, 0, s>>>(n, a, b);
+}
+
+void launch_cg_start_f32(size_t n, const double* R, float* r, float* e, hipStream_t s) {
+  cg_start_f32_kernel<<<nblk((long long)n), kBlock, 0, s>>>(n, R, r, e);
+}
+
+void launch_copy_f32(size_t n, const float* src, float* dst, hipStream_t s) {
+  copy_f32_kernel<<<nblk((long long)n), kBlock, 0, s>>>(n, src, dst);
+}
+
+void launch_add_f2d(size_t n, const double* u, const float* e, double* w, hipStream_t s) {
+  add_f2d_kernel<<<nblk((long long)n), kBlock, 0, s>>>(n, u, e, w);
 }
 
 void launch_copy(size_t n, const double* src, double* dst, hipStream_t s) {
@@ -282,7 +347,13 @@ void launch_gram(long long N, int k, const double* X, const double* Y, double* p
 void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
                  int ldb, double beta, double* C, int ldc, hipStream_t s) {
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
-  gemm_kernel<<<grid, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  gemm_kernel<double><<<grid, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+void launch_gemm_f32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda, const float* B,
+                     int ldb, double beta, float* C, int ldc, hipStream_t s) {
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+  gemm_kernel<float><<<grid, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, hipStream_t s) {

@@ -114,8 +114,12 @@ __device__ __forceinline__ long long flat_off(int o, int m) {
   return f;
 }
 
-template <int DIM, int SRC, int EPI>
+template <int DIM, int SRC, int EPI, typename T>
 __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs a, int slots, int nb, int tiles) {
+  const T* __restrict__ X = (const T*)a.x;
+  const T* __restrict__ Bv = (const T*)a.b;
+  T* __restrict__ O1 = (T*)a.out1;
+  T* __restrict__ O2 = (T*)a.out2;
   constexpr int NS = NSt<DIM>::v;
   __shared__ double sc[kMaxNb][NS];
   __shared__ unsigned smask[kMaxNb];
@@ -172,24 +176,24 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs a, int slot
 #pragma unroll
       for (int o = 0; o < NS; ++o) {
         if (mask & (1u << o)) {
-          const double v = a.x[idx + flat_off<DIM>(o, m) * k];
+          const double v = (double)X[idx + flat_off<DIM>(o, m) * k];
           if (needA) ax = fma(sc[j][o], v, ax);
           if (needM) mx = fma(sm[o], v, mx);
         }
       }
       if (EPI == EPI_AM) {
-        if (a.out1) a.out1[idx] = ax;
-        if (a.out2) a.out2[idx] = mx;
+        if (O1) O1[idx] = (T)ax;
+        if (O2) O2[idx] = (T)mx;
       } else if (EPI == EPI_RESID) {
-        a.out1[idx] = a.b[idx] - ax;
+        O1[idx] = (T)((double)Bv[idx] - ax);
       } else if (EPI == EPI_SWEEP) {
-        a.out1[idx] = a.x[idx] + a.omega * a.dinv[node] * (a.b[idx] - ax);
+        O1[idx] = (T)((double)X[idx] + a.omega * a.dinv[node] * ((double)Bv[idx] - ax));
       } else {  // EPI_EIGRES
         const double r = lamc * mx - ax;
-        a.out1[idx] = r;
+        O1[idx] = (T)r;
         acc0 = fma(r, r, acc0);
         acc1 = fma(mx, mx, acc1);
-        acc2 = fma(a.x[idx], mx, acc2);
+        acc2 = fma((double)X[idx], mx, acc2);
       }
     }
   }
@@ -213,16 +217,16 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs a, int slot
   }
 }
 
-template <int DIM>
+template <typename T>
 __global__ void first_sweep_kernel(long long N, int k, const double* __restrict__ dinv, double omega,
-                                   const double* __restrict__ b, double* __restrict__ x) {
+                                   const T* __restrict__ b, T* __restrict__ x) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * k) return;
-  x[i] = omega * dinv[i / k] * b[i];
+  x[i] = (T)(omega * dinv[i / k] * (double)b[i]);
 }
 
-template <int DIM>
-__global__ void restrict_kernel(int mf, int mc, int k, const double* __restrict__ xf, double* __restrict__ xc) {
+template <int DIM, typename T>
+__global__ void restrict_kernel(int mf, int mc, int k, const T* __restrict__ xf, T* __restrict__ xc) {
   long long Nc = (long long)mc * mc;
   if (DIM == 3) Nc *= mc;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,11 +245,11 @@ __global__ void restrict_kernel(int mf, int mc, int k, const double* __restrict_
         const double wx = (ox == 0) ? 1.0 : 0.5;
         long long f = (fx + ox) + (long long)mf * (fy + oy);
         if (DIM == 3) f += (long long)mf * mf * (fz + oz);
-        s = fma(wx * wy * wz, xf[f * k + col], s);
+        s = fma(wx * wy * wz, (double)xf[f * k + col], s);
       }
     }
   }
-  xc[i] = s;
+  xc[i] = (T)s;
 }
 
 // Coarse indices and weights that interpolate fine coordinate f (ratio 2).
@@ -262,8 +266,8 @@ __device__ __forceinline__ int p1d(int f, int mc, int* I, double* w) {
   return c;
 }
 
-template <int DIM>
-__global__ void prolong_kernel(int mf, int mc, int k, const double* __restrict__ xc, double* __restrict__ xf,
+template <int DIM, typename T>
+__global__ void prolong_kernel(int mf, int mc, int k, const T* __restrict__ xc, T* __restrict__ xf,
                                int mode) {
   long long Nf = (long long)mf * mf;
   if (DIM == 3) Nf *= mf;
@@ -283,11 +287,11 @@ __global__ void prolong_kernel(int mf, int mc, int k, const double* __restrict__
       for (int a = 0; a < nx; ++a) {
         long long J = Ix[a] + (long long)mc * Iy[b];
         if (DIM == 3) J += (long long)mc * mc * Iz[c];
-        s = fma(wx[a] * wy[b] * wz[c], xc[J * k + col], s);
+        s = fma(wx[a] * wy[b] * wz[c], (double)xc[J * k + col], s);
       }
-  if (mode == 0) xf[i] = s;
-  else if (mode == 1) xf[i] += s;
-  else xf[i] -= s;
+  if (mode == 0) xf[i] = (T)s;
+  else if (mode == 1) xf[i] = (T)((double)xf[i] + s);
+  else xf[i] = (T)((double)xf[i] - s);
 }
 
 template <int DIM>
@@ -383,51 +387,70 @@ GridLaunch grid_launch(long long N, int k) {
   return g;
 }
 
-template <int DIM, int SRC>
+template <int DIM, int SRC, typename T>
 static void stencil_dispatch_epi(const StencilArgs& a, Epi epi, const GridLaunch& g, hipStream_t s) {
   switch (epi) {
     case EPI_AM:
-      stencil_kernel<DIM, SRC, EPI_AM><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
+      stencil_kernel<DIM, SRC, EPI_AM, T><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
       break;
     case EPI_RESID:
-      stencil_kernel<DIM, SRC, EPI_RESID><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
+      stencil_kernel<DIM, SRC, EPI_RESID, T><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
       break;
     case EPI_SWEEP:
-      stencil_kernel<DIM, SRC, EPI_SWEEP><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
+      stencil_kernel<DIM, SRC, EPI_SWEEP, T><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
       break;
     case EPI_EIGRES:
-      stencil_kernel<DIM, SRC, EPI_EIGRES><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
+      stencil_kernel<DIM, SRC, EPI_EIGRES, T><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
       break;
+  }
+}
+
+template <typename T>
+static void launch_stencil_t(const StencilArgs& a, Epi epi, hipStream_t s) {
+  const GridLaunch g = grid_launch(a.N, a.k);
+  if (a.dim == 3) {
+    if (a.src == ASource::Kappa) stencil_dispatch_epi<3, 0, T>(a, epi, g, s);
+    else stencil_dispatch_epi<3, 1, T>(a, epi, g, s);
+  } else {
+    if (a.src == ASource::Kappa) stencil_dispatch_epi<2, 0, T>(a, epi, g, s);
+    else stencil_dispatch_epi<2, 1, T>(a, epi, g, s);
   }
 }
 
 void launch_stencil(const StencilArgs& a, Epi epi, hipStream_t s) {
-  const GridLaunch g = grid_launch(a.N, a.k);
-  if (a.dim == 3) {
-    if (a.src == ASource::Kappa) stencil_dispatch_epi<3, 0>(a, epi, g, s);
-    else stencil_dispatch_epi<3, 1>(a, epi, g, s);
-  } else {
-    if (a.src == ASource::Kappa) stencil_dispatch_epi<2, 0>(a, epi, g, s);
-    else stencil_dispatch_epi<2, 1>(a, epi, g, s);
-  }
+  if (a.fp32) launch_stencil_t<float>(a, epi, s);
+  else launch_stencil_t<double>(a, epi, s);
 }
 
-void launch_first_sweep(int dim, long long N, int k, const double* dinv, double omega, const double* b, double* x,
-                        hipStream_t s) {
-  if (dim == 3) first_sweep_kernel<3><<<nblk(N * k), kBlock, 0, s>>>(N, k, dinv, omega, b, x);
-  else first_sweep_kernel<2><<<nblk(N * k), kBlock, 0, s>>>(N, k, dinv, omega, b, x);
+void launch_first_sweep(int dim, long long N, int k, const double* dinv, double omega, const void* b, void* x,
+                        int fp32, hipStream_t s) {
+  (void)dim;
+  if (fp32) first_sweep_kernel<float><<<nblk(N * k), kBlock, 0, s>>>(N, k, dinv, omega, (const float*)b, (float*)x);
+  else first_sweep_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, dinv, omega, (const double*)b, (double*)x);
 }
 
-void launch_restrict(int dim, int mf, int mc, int k, const double* xf, double* xc, hipStream_t s) {
+template <typename T>
+static void launch_restrict_t(int dim, int mf, int mc, int k, const T* xf, T* xc, hipStream_t s) {
   long long Nc = (long long)mc * mc * (dim == 3 ? mc : 1);
-  if (dim == 3) restrict_kernel<3><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, k, xf, xc);
-  else restrict_kernel<2><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, k, xf, xc);
+  if (dim == 3) restrict_kernel<3, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, k, xf, xc);
+  else restrict_kernel<2, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, k, xf, xc);
 }
 
-void launch_prolong(int dim, int mf, int mc, int k, const double* xc, double* xf, int mode, hipStream_t s) {
+void launch_restrict(int dim, int mf, int mc, int k, const void* xf, void* xc, int fp32, hipStream_t s) {
+  if (fp32) launch_restrict_t<float>(dim, mf, mc, k, (const float*)xf, (float*)xc, s);
+  else launch_restrict_t<double>(dim, mf, mc, k, (const double*)xf, (double*)xc, s);
+}
+
+template <typename T>
+static void launch_prolong_t(int dim, int mf, int mc, int k, const T* xc, T* xf, int mode, hipStream_t s) {
   long long Nf = (long long)mf * mf * (dim == 3 ? mf : 1);
-  if (dim == 3) prolong_kernel<3><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
-  else prolong_kernel<2><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
+  if (dim == 3) prolong_kernel<3, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
+  else prolong_kernel<2, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
+}
+
+void launch_prolong(int dim, int mf, int mc, int k, const void* xc, void* xf, int mode, int fp32, hipStream_t s) {
+  if (fp32) launch_prolong_t<float>(dim, mf, mc, k, (const float*)xc, (float*)xf, mode, s);
+  else launch_prolong_t<double>(dim, mf, mc, k, (const double*)xc, (double*)xf, mode, s);
 }
 
 void launch_kappa_dinv(int dim, int n, const double* kappa, double* dinv, hipStream_t s) {

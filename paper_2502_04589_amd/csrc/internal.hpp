@@ -45,13 +45,14 @@ struct StencilArgs {
   const double* kappa;   // Kappa source
   const double* coef;    // Assembled source (N x 3^dim)
   const double* dinv;
-  const double* x;
-  const double* b;       // rhs for RESID / SWEEP
+  const void* x;         // multi-vectors: double, or float when fp32
+  const void* b;         // rhs for RESID / SWEEP
   const double* lam;     // EIGRES: k values (device)
-  double* out1;
-  double* out2;
+  void* out1;
+  void* out2;
   double* partial;       // EIGRES: [tiles][3][k]
   double omega;
+  int fp32;
 };
 
 // ---- grid kernels (grid.hip)
@@ -64,10 +65,10 @@ struct GridLaunch {
 GridLaunch grid_launch(long long N, int k);
 void launch_stencil(const StencilArgs& a, Epi epi, hipStream_t s);
 void launch_first_sweep(int dim, long long N, int k, const double* dinv, double omega,
-                        const double* b, double* x, hipStream_t s);
+                        const void* b, void* x, int fp32, hipStream_t s);
 // restriction xc = P^T xf (ratio 2), prolongation xf (op)= P xc; mode 0: xf = P xc, 1: xf += P xc, 2: xf -= P xc
-void launch_restrict(int dim, int mf, int mc, int k, const double* xf, double* xc, hipStream_t s);
-void launch_prolong(int dim, int mf, int mc, int k, const double* xc, double* xf, int mode, hipStream_t s);
+void launch_restrict(int dim, int mf, int mc, int k, const void* xf, void* xc, int fp32, hipStream_t s);
+void launch_prolong(int dim, int mf, int mc, int k, const void* xc, void* xf, int mode, int fp32, hipStream_t s);
 // setup helpers
 void launch_kappa_dinv(int dim, int n, const double* kappa, double* dinv, hipStream_t s);
 void launch_color_probe(int dim, int m, double* E, hipStream_t s);                 // N x 3^dim
@@ -119,7 +120,19 @@ void launch_gram(long long N, int k, const double* X, const double* Y, double* p
 // C = alpha op(A) op(B) + beta C, row-major, FP64
 void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
                  int ldb, double beta, double* C, int ldc, hipStream_t s);
-// tall-skinny: Y = X C (+ Y): X N x k, C k x k, Y N x k  (MFMA)
+// FP32 multi-vector variants (scalars and reductions stay FP64)
+void launch_coldot_f32(long long N, int k, const float* X, const float* Y, double* partial, double* out,
+                       hipStream_t s);
+void launch_axpy2_f32(long long N, int k, const double* alpha, const float* P, const float* Q, float* X, float* R,
+                      hipStream_t s);
+void launch_xpby_f32(long long N, int k, const float* Z, const double* beta, float* P, hipStream_t s);
+void launch_gemm_f32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda, const float* B,
+                     int ldb, double beta, float* C, int ldc, hipStream_t s);
+void launch_d2f(size_t n, const double* a, float* b, hipStream_t s);
+void launch_add_f2d(size_t n, const double* u, const float* e, double* w, hipStream_t s);
+void launch_cg_start_f32(size_t n, const double* R, float* r, float* e, hipStream_t s);
+void launch_copy_f32(size_t n, const float* src, float* dst, hipStream_t s);
+// tall-skinny: Y = X C (+ Y): X N x k, C k x k, Y N x k
 void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, hipStream_t s);
 // small helpers
 void launch_set_diag_block(int n, int nh, int k, const double* C0, const double* G, const double* H, double* T,

@@ -72,6 +72,11 @@ struct pase_handle {
   int* info = nullptr;          // device status words
   double* zero16 = nullptr;     // 64 zero bytes
   double* setup_scratch = nullptr;
+  // mixed precision: FP32 multi-vectors for the correction-form CG and its V-cycle
+  float *R32 = nullptr, *Z32 = nullptr, *P32 = nullptr, *Q32 = nullptr, *E32 = nullptr;
+  float *vb32[PASE_MAX_LEVELS] = {}, *vx32[PASE_MAX_LEVELS] = {}, *vxa32[PASE_MAX_LEVELS] = {},
+        *vr32[PASE_MAX_LEVELS] = {};
+  float* AinvL32 = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 };
@@ -107,7 +112,7 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (o->nev_max < 1 || o->nev_max > PASE_MAX_NEV) return PASE_E_ARG;
   if (o->cg_steps < 1 || o->max_outer < 0 || o->nu < 1) return PASE_E_ARG;
   if (!(o->omega > 0.0)) return PASE_E_ARG;
-  if (o->precision != PASE_PREC_FP64) return PASE_E_UNSUPPORTED;
+  if (o->precision != PASE_PREC_FP64 && o->precision != PASE_PREC_MIXED) return PASE_E_UNSUPPORTED;
   return PASE_OK;
 }
 
@@ -139,6 +144,18 @@ size_t layout(pase_handle* h, void* base) {
     h->vx[l] = b.take<double>(Nl * K);
     h->vxa[l] = b.take<double>(Nl * K);
     h->vr[l] = b.take<double>(Nl * K);
+  }
+  if (h->opt.precision == PASE_PREC_MIXED) {
+    h->R32 = b.take<float>(mv); h->Z32 = b.take<float>(mv); h->P32 = b.take<float>(mv);
+    h->Q32 = b.take<float>(mv); h->E32 = b.take<float>(mv);
+    h->vxa32[0] = b.take<float>(mv); h->vr32[0] = b.take<float>(mv);
+    for (int l = 1; l <= h->L; ++l) {
+      const size_t Nl = (size_t)h->lev[l].N;
+      h->vb32[l] = b.take<float>(Nl * K); h->vx32[l] = b.take<float>(Nl * K);
+      h->vxa32[l] = b.take<float>(Nl * K); h->vr32[l] = b.take<float>(Nl * K);
+    }
+    const size_t NHf = (size_t)h->lev[h->L].N;
+    h->AinvL32 = b.take<float>(NHf * NHf);
   }
   const size_t NH = (size_t)h->lev[h->L].N;
   h->AinvL = b.take<double>(NH * NH);
@@ -195,8 +212,8 @@ StencilArgs stencil_args(pase_handle* h, int l, int k) {
 
 // Every stencil application goes through here: the 3D fine level uses the
 // LDS-staged kernel, 2D problems and coarse levels the generic one.
-void stencil_op(pase_handle* h, int l, int k, Epi epi, const double* x, const double* b, double* out1,
-                double* out2) {
+void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void* b, void* out1, void* out2,
+                int fp32 = 0) {
   if (l == 0 && h->dim == 3) {
     Fine3Args f{};
     f.m = h->lev[0].m;
@@ -211,7 +228,7 @@ void stencil_op(pase_handle* h, int l, int k, Epi epi, const double* x, const do
     f.partial = h->partial;
     f.omega = h->opt.omega;
     f.nzc = fine3_default_nzc(f.m);
-    f.fp32 = 0;
+    f.fp32 = fp32;
     f.zero = h->zero16;
     launch_fine3(f, epi, h->stream);
     return;
@@ -223,6 +240,7 @@ void stencil_op(pase_handle* h, int l, int k, Epi epi, const double* x, const do
   a.out1 = out1;
   a.out2 = out2;
   a.partial = h->partial;
+  a.fp32 = fp32;
   launch_stencil(a, epi, h->stream);
 }
 
@@ -235,33 +253,61 @@ void apply_AM(pase_handle* h, int l, int k, const double* x, double* ax, double*
   stencil_op(h, l, k, EPI_AM, x, nullptr, ax, mx);
 }
 
-// x = V(b) on level l (x must not alias b)
-void vcycle(pase_handle* h, int l, int k, const double* b, double* x) {
+// Buffers of one V-cycle precision.
+struct VBufs {
+  void* b[PASE_MAX_LEVELS];
+  void* x[PASE_MAX_LEVELS];
+  void* xa[PASE_MAX_LEVELS];
+  void* r[PASE_MAX_LEVELS];
+  int fp32;
+};
+
+VBufs vbufs(pase_handle* h, int fp32) {
+  VBufs v{};
+  for (int l = 0; l <= h->L; ++l) {
+    v.b[l] = fp32 ? (void*)h->vb32[l] : (void*)h->vb[l];
+    v.x[l] = fp32 ? (void*)h->vx32[l] : (void*)h->vx[l];
+    v.xa[l] = fp32 ? (void*)h->vxa32[l] : (void*)h->vxa[l];
+    v.r[l] = fp32 ? (void*)h->vr32[l] : (void*)h->vr[l];
+  }
+  v.fp32 = fp32;
+  return v;
+}
+
+// x = V(b) on level l (x must not alias b), in the precision of B
+void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x) {
   hipStream_t s = h->stream;
   if (l == h->L) {
     const int NH = (int)h->lev[l].N;
-    launch_gemm(false, false, NH, k, NH, 1.0, h->AinvL, NH, b, k, 0.0, x, k, s);
+    if (B.fp32)
+      launch_gemm_f32(false, false, NH, k, NH, 1.0, h->AinvL32, NH, (const float*)b, k, 0.0, (float*)x, k, s);
+    else
+      launch_gemm(false, false, NH, k, NH, 1.0, h->AinvL, NH, (const double*)b, k, 0.0, (double*)x, k, s);
     return;
   }
   const Level& lv = h->lev[l];
-  double* t0 = h->vxa[l];
-  double* t1 = x;
+  void* t0 = B.xa[l];
+  void* t1 = x;
   // sweeps alternate t0, t1, t0, ...; the last of the 2 nu sweeps lands in t1 = x
-  launch_first_sweep(h->dim, lv.N, k, lv.dinv, h->opt.omega, b, t0, s);
-  double* cur = t0;
-  double* oth = t1;
+  launch_first_sweep(h->dim, lv.N, k, lv.dinv, h->opt.omega, b, t0, B.fp32, s);
+  void* cur = t0;
+  void* oth = t1;
   for (int i = 1; i < h->opt.nu; ++i) {
-    stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr);
+    stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr, B.fp32);
     std::swap(cur, oth);
   }
-  stencil_op(h, l, k, EPI_RESID, cur, b, h->vr[l], nullptr);
-  launch_restrict(h->dim, lv.m, h->lev[l + 1].m, k, h->vr[l], h->vb[l + 1], s);
-  vcycle(h, l + 1, k, h->vb[l + 1], h->vx[l + 1]);
-  launch_prolong(h->dim, lv.m, h->lev[l + 1].m, k, h->vx[l + 1], cur, 1, s);
+  stencil_op(h, l, k, EPI_RESID, cur, b, B.r[l], nullptr, B.fp32);
+  launch_restrict(h->dim, lv.m, h->lev[l + 1].m, k, B.r[l], B.b[l + 1], B.fp32, s);
+  vcycle(h, B, l + 1, k, B.b[l + 1], B.x[l + 1]);
+  launch_prolong(h->dim, lv.m, h->lev[l + 1].m, k, B.x[l + 1], cur, 1, B.fp32, s);
   for (int i = 0; i < h->opt.nu; ++i) {
-    stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr);
+    stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr, B.fp32);
     std::swap(cur, oth);
   }
+}
+
+void vcycle(pase_handle* h, int l, int k, const double* b, double* x) {
+  vcycle(h, vbufs(h, 0), l, k, b, x);
 }
 
 // composite restriction: xc (N_L x k) = P^T xf
@@ -269,7 +315,7 @@ void restrict_all(pase_handle* h, int k, const double* xf, double* xc) {
   const double* src = xf;
   for (int l = 0; l < h->L; ++l) {
     double* dst = (l + 1 == h->L) ? xc : h->vr[l + 1];
-    launch_restrict(h->dim, h->lev[l].m, h->lev[l + 1].m, k, src, dst, h->stream);
+    launch_restrict(h->dim, h->lev[l].m, h->lev[l + 1].m, k, src, dst, 0, h->stream);
     src = dst;
   }
 }
@@ -279,7 +325,7 @@ void prolong_all(pase_handle* h, int k, const double* xc, double* xf, int mode) 
   const double* src = xc;
   for (int l = h->L; l >= 1; --l) {
     double* dst = (l == 1) ? xf : h->vxa[l - 1];
-    launch_prolong(h->dim, h->lev[l - 1].m, h->lev[l].m, k, src, dst, (l == 1) ? mode : 0, h->stream);
+    launch_prolong(h->dim, h->lev[l - 1].m, h->lev[l].m, k, src, dst, (l == 1) ? mode : 0, 0, h->stream);
     src = dst;
   }
 }
@@ -310,6 +356,35 @@ void pcg(pase_handle* h, int k, double* X, double* R) {
   }
 }
 
+// Mixed precision: s FP32 PCG steps per column on the correction equation A E = R from E = 0
+// (R = lam M U - A U, the FP64 residual), then W = U + E in FP64.  In exact arithmetic W equals
+// the iterate of s PCG steps on A w = lam M u from w = u.
+void pcg_correction_f32(pase_handle* h, int k, const double* U, const double* R, double* W) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  const size_t nk = (size_t)N * k;
+  const VBufs B = vbufs(h, 1);
+  float* r = h->R32;
+  launch_cg_start_f32(nk, R, r, h->E32, s);
+  vcycle(h, B, 0, k, r, h->Z32);
+  launch_copy_f32(nk, h->Z32, h->P32, s);
+  launch_coldot_f32(N, k, r, h->Z32, h->partial, h->rho, s);
+  for (int j = 0; j < h->opt.cg_steps; ++j) {
+    stencil_op(h, 0, k, EPI_AM, h->P32, nullptr, h->Q32, nullptr, 1);
+    launch_coldot_f32(N, k, h->P32, h->Q32, h->partial, h->pq, s);
+    launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
+    launch_axpy2_f32(N, k, h->alpha, h->P32, h->Q32, h->E32, r, s);
+    if (j + 1 < h->opt.cg_steps) {
+      vcycle(h, B, 0, k, r, h->Z32);
+      launch_coldot_f32(N, k, r, h->Z32, h->partial, h->rho2, s);
+      launch_pcg_beta(k, h->rho2, h->rho, h->beta, s);
+      launch_xpby_f32(N, k, h->Z32, h->beta, h->P32, s);
+      std::swap(h->rho, h->rho2);
+    }
+  }
+  launch_add_f2d(nk, U, h->E32, W, s);
+}
+
 // R = lam M U - A U with fused column sums (|R|^2, |MU|^2, U.MU) into h->sums
 void eig_residual(pase_handle* h, int k, const double* U, double* R) {
   stencil_op(h, 0, k, EPI_EIGRES, U, nullptr, R, nullptr);
@@ -334,8 +409,12 @@ pase_status correction(pase_handle* h, int k) {
   const long long N = h->lev[0].N;
   const int NH = (int)h->lev[h->L].N;
   // (a) fine solves A w = lam M u from w = u: s CG steps per column
-  launch_copy((size_t)N * k, h->U, h->X, s);
-  pcg(h, k, h->X, h->R);
+  if (h->opt.precision == PASE_PREC_MIXED) {
+    pcg_correction_f32(h, k, h->U, h->R, h->X);
+  } else {
+    launch_copy((size_t)N * k, h->U, h->X, s);
+    pcg(h, k, h->X, h->R);
+  }
   double* W = h->X;
   // complement: W <- W - P B_H^{-1} P^T M W
   apply_AM(h, 0, k, W, nullptr, h->W3);
@@ -419,6 +498,7 @@ pase_status pase_workspace_bytes(const pase_problem* prob, const pase_options* o
   const pase_status st = check_problem(prob, opt);
   if (st != PASE_OK) return fail(h, st, "invalid or unsupported problem/options");
   pase_handle tmp;
+  tmp.opt = *opt;
   tmp.dim = prob->dim;
   tmp.L = prob->nlevels - 1;
   tmp.NS = prob->dim == 3 ? 27 : 9;
@@ -498,9 +578,9 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
     double* PE = E + (size_t)c.N * NS;
     double* APE = PE + (size_t)p.N * NS;
     launch_color_probe(h->dim, c.m, E, s);
-    launch_prolong(h->dim, p.m, c.m, NS, E, PE, 0, s);
+    launch_prolong(h->dim, p.m, c.m, NS, E, PE, 0, 0, s);
     apply_AM(h, l - 1, NS, PE, APE, nullptr);
-    launch_restrict(h->dim, p.m, c.m, NS, APE, E, s);
+    launch_restrict(h->dim, p.m, c.m, NS, APE, E, 0, s);
     launch_extract_galerkin(h->dim, c.m, E, h->lev[l].coef, h->lev[l].dinv, s);
   }
   // coarse dense factorisations
@@ -512,6 +592,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   launch_trinv(NH, AL, NH, h->C0, NH, s);                            // C0 <- L_A^{-1} (temp)
   launch_gemm(true, false, NH, NH, NH, 1.0, h->C0, NH, h->C0, NH, 0.0, h->AinvL, NH, s);
   launch_symmetrize(NH, h->AinvL, s);
+  if (h->AinvL32) launch_d2f((size_t)NH * NH, h->AinvL, h->AinvL32, s);
   double* BL = h->dtmp;
   launch_stencil_to_dense(h->dim, cl.m, nullptr, cl.h, 1, BL, s);
   launch_cholesky(NH, BL, NH, h->info + 9, s);                       // BL <- L_B

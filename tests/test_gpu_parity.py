@@ -226,3 +226,67 @@ def test_edge_cases():
         s2.solve(1, 1e-8, dev(nan))
     with pytest.raises(PaseError):
         s2.solve(5, 1e-8, dev(synth.initial_vectors(N, 5, 0)))   # nev > nev_max
+
+
+# ---- mixed precision: FP32 PCG on the correction equation, FP64 master vectors and projection
+
+def test_mixed_config1_matches_fp64_oracle():
+    """2D 128x128, nev 10: the mixed form reaches tol 1e-10 and the FP64 oracle's eigenvalues.
+
+    The bar for the mixed form is 1e-8 relative per eigenvalue; FP64 master
+    vectors with an FP32 inner solve land far inside it, so 1e-9 is asserted.
+    """
+    levels, k = [128, 64, 32, 16], 10
+    s = Solver(2, levels, nev_max=k, precision="mixed")
+    U0 = synth.initial_vectors(127 ** 2, k, 0)
+    lam, U, rep = s.solve(k, 1e-10, dev(U0))
+    H = multigrid.Hierarchy(2, levels)
+    ref = opase.solve(H, k, 1e-10, U0)
+    np.testing.assert_allclose(lam, ref.lam, rtol=1e-9)
+    np.testing.assert_allclose(lam, q1_laplace_eigs(2, 128, k), rtol=1e-9)
+    assert rep["n_converged"] == k and np.all(rep["res"] <= 1e-10)
+    assert abs(rep["outer_iters"] - ref.iters) <= 3
+    Uh = host(U)
+    assert np.abs(Uh.T @ (H.M[0] @ Uh) - np.eye(k)).max() < 1e-12
+    res = opase.residuals(H.A[0], H.M[0], Uh, lam)[0]
+    assert np.all(res <= 1e-10 * (1 + 1e-6))
+
+
+def test_mixed_variable_kappa_3d_matches_dense():
+    levels, k = [16, 8, 4], 8
+    kap = synth.kappa_field(3, 16, 11)
+    s = Solver(3, levels, kap, nev_max=k, precision="mixed")
+    H = multigrid.Hierarchy(3, levels, kap)
+    U0 = synth.initial_vectors(H.A[0].shape[0], k, 2)
+    lam, U, rep = s.solve(k, 1e-10, dev(U0))
+    w = sla.eigh(H.A[0].toarray(), H.M[0].toarray(), subset_by_index=[0, k - 1], eigvals_only=True)
+    np.testing.assert_allclose(lam, w, rtol=1e-9)
+    ref = opase.solve(H, k, 1e-10, U0)
+    assert abs(rep["outer_iters"] - ref.iters) <= 3
+
+
+def test_mixed_k_with_ragged_fp32_vectors():
+    """3D 32^3, k = 13 (not a multiple of the 4-float vector width): ragged column tails in FP32."""
+    levels, k = [32, 16, 8, 4], 13
+    s = Solver(3, levels, nev_max=k, precision="mixed")
+    U0 = synth.initial_vectors(31 ** 3, k, 4)
+    lam, U, rep = s.solve(k, 1e-9, dev(U0))
+    np.testing.assert_allclose(lam, q1_laplace_eigs(3, 32, k), rtol=1e-9)
+    s64 = Solver(3, levels, nev_max=k)
+    lam64, _, rep64 = s64.solve(k, 1e-9, dev(U0))
+    assert abs(rep["outer_iters"] - rep64["outer_iters"]) <= 3
+
+
+@pytest.mark.slow
+def test_mixed_config2_closed_form_full_size():
+    """3D 64^3, V_H = 8^3, nev 50, tol 1e-8, mixed form: closed-form eigenvalues to 1e-8 relative."""
+    levels, k = [64, 32, 16, 8], 50
+    s = Solver(3, levels, nev_max=k, precision="mixed")
+    U0 = synth.initial_vectors(63 ** 3, k, 0)
+    lam, U, rep = s.solve(k, 1e-8, dev(U0))
+    err = np.abs(lam / q1_laplace_eigs(3, 64, k) - 1)
+    assert err.max() < 1e-8, err.max()
+    assert rep["n_converged"] == k and np.all(rep["res"] <= 1e-8)
+    _, MU = s.apply(0, U)
+    G = host(U.T.contiguous() @ MU)
+    assert np.abs(G - np.eye(k)).max() < 1e-12

@@ -216,6 +216,30 @@ def test_complement_form_gives_same_ritz_values():
     np.testing.assert_allclose(v1, v2, rtol=1e-12)
 
 
+def test_correction_equation_gives_the_same_pcg_iterate():
+    """s PCG steps on A w = lam M u from w = u equal u + (s PCG steps on A e = lam M u - A u from e = 0).
+
+    The V-cycle is a fixed linear operator, so every Krylov quantity depends on
+    the initial residual alone: the mixed form solves for the correction and
+    adds it to the FP64 master vectors.
+    """
+    H = multigrid.Hierarchy(2, [16, 8, 4], synth.kappa_field(2, 16, seed=8))
+    k = 4
+    N = H.A[0].shape[0]
+    U = pase.cholqr_m(synth.initial_vectors(N, k, 5), H.M[0])
+    lam = np.einsum("ij,ij->j", U, H.A[0] @ U)
+    rhs = (H.M[0] @ U) * lam
+    for s in (1, 2, 3):
+        W = pase.pcg(H, rhs, U, s)
+        E = pase.pcg(H, rhs - H.A[0] @ U, np.zeros_like(U), s)
+        np.testing.assert_allclose(U + E, W, rtol=0, atol=1e-12 * np.abs(W).max())
+    # the V-cycle is linear: V(a r1 + r2) = a V(r1) + V(r2)
+    r1, r2 = synth.initial_vectors(N, 2, 6).T
+    lhs = H.vcycle((2.5 * r1 + r2)[:, None])[:, 0]
+    rhs2 = 2.5 * H.vcycle(r1[:, None])[:, 0] + H.vcycle(r2[:, None])[:, 0]
+    np.testing.assert_allclose(lhs, rhs2, rtol=0, atol=1e-13 * np.abs(lhs).max())
+
+
 @pytest.mark.slow
 def test_config1_closed_form():
     """2D 128x128, coarse 16x16, nev 10, 2 CG steps, tol 1e-10: closed-form eigenvalues."""
