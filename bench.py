@@ -128,11 +128,13 @@ def main():
     torch.cuda.synchronize()
     conv = 0
     iters = []
+    fast = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         lam, U, rep = s.solve(nev, tol, U0)
         conv += rep["n_converged"]
         iters.append(rep["outer_iters"])
+        fast.append(rep["small_fast_iters"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = conv / dt
@@ -159,6 +161,7 @@ def main():
                         f"({s.N[0]} DOFs), V_H {levels[-1]}^{dim} ({s.N[-1]} DOFs), GMG levels "
                         f"{'/'.join(map(str, levels))}, nev {nev}, tol {tol:g}, 2 CG steps, plain FP64",
             "dofs": s.N[0], "nev": nev, "tol": tol, "outer_iters": iters[-1],
+            "small_structured_iters": fast[-1],
             "setup_s": round(setup_s, 3),
             "max_rel_err_vs_closed_form": None,
         },

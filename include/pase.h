@@ -84,6 +84,8 @@ typedef struct pase_options {
   int max_outer;                 /* outer iteration limit (default 500) */
   int nu;                        /* damped-Jacobi sweeps before and after the coarse correction (default 2) */
   double omega;                  /* Jacobi damping (default 2/3) */
+  int small_solver;              /* augmented eigenproblem: 0 = structured shift-invert path with dense
+                                    fallback (default), 1 = dense eigensolver only */
 } pase_options;
 
 /* Filled by pase_solve.  Array members are optional HOST buffers (NULL = not wanted). */
@@ -95,6 +97,10 @@ typedef struct pase_report {
   double* ritz_history_host;     /* (max_outer+1) x nev: Lambda before each correction and at exit */
   int ritz_history_rows;         /* rows written to ritz_history_host */
   double t_solve_ms;             /* device time of the solve (HIP events on the handle's stream) */
+  int small_fast_iters;          /* corrections whose augmented eigenproblem the structured path solved */
+  int* small_path_host;          /* max_outer: per correction, 1 = structured path accepted, 0 = dense
+                                    only, -1 = rejected (residual or orthogonality), -2 = rejected by the
+                                    eigenvalue count */
 } pase_report;
 
 typedef struct pase_handle pase_handle;

@@ -21,13 +21,14 @@ class Problem(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("nev_max", C.c_int), ("cg_steps", C.c_int), ("max_outer", C.c_int),
-                ("nu", C.c_int), ("omega", C.c_double)]
+                ("nu", C.c_int), ("omega", C.c_double), ("small_solver", C.c_int)]
 
 
 class Report(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("n_converged", C.c_int), ("res_host", C.c_void_p),
                 ("res_literal_host", C.c_void_p), ("ritz_history_host", C.c_void_p),
-                ("ritz_history_rows", C.c_int), ("t_solve_ms", C.c_double)]
+                ("ritz_history_rows", C.c_int), ("t_solve_ms", C.c_double), ("small_fast_iters", C.c_int),
+                ("small_path_host", C.c_void_p)]
 
 
 # (name, restype, argtypes) for every entry point of include/pase.h

@@ -176,6 +176,114 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(long long N, int k, const 
   }
 }
 
+// ---- LDS-staged Gram: G_y = X^T Y_y for NY = 1 or 2 right-hand blocks (X read once).
+// Each block owns a contiguous run of rows and walks it in chunks of kGramRows
+// rows.  A chunk of X and Y_y is a contiguous run of kGramRows * k doubles: the
+// block loads it with coalesced loads into registers one chunk ahead, stores it
+// to LDS (zero-padded to 16-column tiles), and its four waves feed the MFMA
+// tiles from LDS.  Partial k x k sums per block are reduced in a fixed order.
+constexpr int kGramRows = 32;
+
+template <int NY, int KMAX>
+__global__ __launch_bounds__(kBlock) void gram_lds_kernel(long long N, int k, const double* __restrict__ X,
+                                                          const double* __restrict__ Y1,
+                                                          const double* __restrict__ Y2,
+                                                          double* __restrict__ partial, int tiles, long long rows) {
+  constexpr int TMAX = (KMAX / 16) * (KMAX / 16) / 4;   // tiles per wave
+  constexpr int U = kGramRows * KMAX / kBlock;          // staged doubles per thread per matrix
+  extern __shared__ double lds[];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= tiles) return;
+  const int T = (k + 15) >> 4, TT = T * T;
+  const int LD = T * 16 + 1;
+  double* xs = lds;
+  double* y1s = xs + kGramRows * LD;
+  double* y2s = y1s + kGramRows * LD;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < (1 + NY) * kGramRows * LD; e += kBlock) lds[e] = 0.0;
+  const long long r0 = (long long)tile * rows;
+  const long long r1 = (r0 + rows < N) ? (r0 + rows) : N;
+  const int ck = kGramRows * k;
+  // per-thread slots of a chunk: element e = tid + kBlock u -> (row e / k, col e % k)
+  int soff[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = tid + kBlock * u;
+    const int rr = e / k;
+    soff[u] = (e < ck) ? rr * LD + (e - rr * k) : -1;
+  }
+  double rx[U], ry1[U], ry2[U];
+  auto fetch = [&](long long rc) {
+    const long long lim = (r1 - rc) * k;      // valid elements of this chunk
+    const unsigned nval = (unsigned)((lim < ck) ? lim : ck);
+    const double* __restrict__ px = X + rc * k;
+    const double* __restrict__ py1 = Y1 + rc * k;
+    const double* __restrict__ py2 = (NY == 2) ? Y2 + rc * k : Y1 + rc * k;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned e = (unsigned)(tid + kBlock * u);
+      const bool ok = e < nval;
+      rx[u] = ok ? px[e] : 0.0;
+      ry1[u] = ok ? py1[e] : 0.0;
+      if (NY == 2) ry2[u] = ok ? py2[e] : 0.0;
+    }
+  };
+  double4_t acc1[TMAX], acc2[TMAX];
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) {
+    acc1[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    acc2[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  }
+  const int li = lane & 15, lk = lane >> 4;
+  if (r0 < r1) fetch(r0);
+  __syncthreads();
+  for (long long rc = r0; rc < r1; rc += kGramRows) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (soff[u] >= 0) {
+        xs[soff[u]] = rx[u];
+        y1s[soff[u]] = ry1[u];
+        if (NY == 2) y2s[soff[u]] = ry2[u];
+      }
+    }
+    __syncthreads();
+    if (rc + kGramRows < r1) fetch(rc + kGramRows);
+#pragma unroll 2
+    for (int st = 0; st < kGramRows / 4; ++st) {
+      const int row = (4 * st + lk) * LD;
+#pragma unroll
+      for (int t = 0; t < TMAX; ++t) {
+        const int tt = wave + 4 * t;
+        if (tt < TT) {
+          const int ti = tt / T, tj = tt - (tt / T) * T;
+          const double av = xs[row + ti * 16 + li];
+          acc1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, y1s[row + tj * 16 + li], acc1[t], 0, 0, 0);
+          if (NY == 2)
+            acc2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, y2s[row + tj * 16 + li], acc2[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int y = 0; y < NY; ++y) {
+    double* p = partial + ((size_t)y * tiles + tile) * k * k;
+#pragma unroll
+    for (int t = 0; t < TMAX; ++t) {
+      const int tt = wave + 4 * t;
+      if (tt < TT) {
+        const int ti = tt / T, tj = tt - (tt / T) * T;
+        const int j = tj * 16 + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = ti * 16 + lk + 4 * q;
+          if (i < k && j < k) p[(size_t)i * k + j] = (y == 0) ? acc1[t][q] : acc2[t][q];
+        }
+      }
+    }
+  }
+}
+
 // ---- generic tiled FP64 GEMM: C = alpha op(A) op(B) + beta C (row-major)
 constexpr int GT = 64, GK = 16;
 
@@ -230,6 +338,109 @@ __global__ __launch_bounds__(kBlock) void gemm_kernel(int ta, int tb, int M, int
         *c = (beta == 0.0) ? (T)(alpha * acc[p][q]) : (T)fma(alpha, (double)acc[p][q], beta * (double)*c);
       }
     }
+}
+
+// ---- small GEMM (M <= kSmallM, K <= kSmallK): one block per output row and
+// 64-column chunk; the four waves split K and their partial sums meet in LDS.
+// Latency-oriented: the coarse-space products (N_H x N_H times N_H x k, k x k
+// products) have too few 64 x 64 tiles to fill the chip.
+constexpr int kSmallM = 4096, kSmallK = 4096;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void gemm_small_kernel(int ta, int tb, int M, int N, int K, double alpha,
+                                                            const T* __restrict__ A, int lda,
+                                                            const T* __restrict__ B, int ldb, double beta,
+                                                            T* __restrict__ C, int ldc) {
+  __shared__ double arow[kSmallK];
+  __shared__ double part[4][64];
+  const int i = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  for (int kk = threadIdx.x; kk < K; kk += kBlock)
+    arow[kk] = (double)(ta ? A[(size_t)kk * lda + i] : A[(size_t)i * lda + kk]);
+  __syncthreads();
+  const int kq = (K + 3) / 4;
+  const int k0 = wave * kq, k1 = (k0 + kq < K) ? k0 + kq : K;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  if (j < N) {
+    int kk = k0;
+    if (!tb) {
+      const T* __restrict__ bp = B + j;
+      for (; kk + 4 <= k1; kk += 4) {
+        acc0 = fma(arow[kk], (double)bp[(size_t)kk * ldb], acc0);
+        acc1 = fma(arow[kk + 1], (double)bp[(size_t)(kk + 1) * ldb], acc1);
+        acc2 = fma(arow[kk + 2], (double)bp[(size_t)(kk + 2) * ldb], acc2);
+        acc3 = fma(arow[kk + 3], (double)bp[(size_t)(kk + 3) * ldb], acc3);
+      }
+      for (; kk < k1; ++kk) acc0 = fma(arow[kk], (double)bp[(size_t)kk * ldb], acc0);
+    } else {
+      const T* __restrict__ bp = B + (size_t)j * ldb;
+      for (; kk + 4 <= k1; kk += 4) {
+        acc0 = fma(arow[kk], (double)bp[kk], acc0);
+        acc1 = fma(arow[kk + 1], (double)bp[kk + 1], acc1);
+        acc2 = fma(arow[kk + 2], (double)bp[kk + 2], acc2);
+        acc3 = fma(arow[kk + 3], (double)bp[kk + 3], acc3);
+      }
+      for (; kk < k1; ++kk) acc0 = fma(arow[kk], (double)bp[kk], acc0);
+    }
+  }
+  part[wave][lane] = (acc0 + acc1) + (acc2 + acc3);
+  __syncthreads();
+  if (wave == 0 && j < N) {
+    const double acc = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    T* c = C + (size_t)i * ldc + j;
+    *c = (beta == 0.0) ? (T)(alpha * acc) : (T)fma(alpha, acc, beta * (double)*c);
+  }
+}
+
+// ---- tall-skinny Y = X op(C) (+ Y), X and Y N x k (row-major), C k x k, k <= 64.
+// Lane j of every wave keeps column j of op(C) in registers; a block stages 64
+// consecutive rows of X (one contiguous run) in LDS and each wave produces 16 of
+// the rows, reading X from LDS as a broadcast.
+constexpr int kTsRows = 64;
+
+template <int TB>
+__global__ __launch_bounds__(kBlock) void tsmm_kernel(long long N, int k, const double* __restrict__ X,
+                                                      const double* __restrict__ C, double* __restrict__ Y,
+                                                      int accumulate) {
+  __shared__ double xs[kTsRows * 64];   // row r at xs[64 r], columns k..63 zero
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long r0 = (long long)blockIdx.x * kTsRows;
+  const int nr = (N - r0 < kTsRows) ? (int)(N - r0) : kTsRows;
+  const double* __restrict__ xp = X + r0 * k;
+  for (int e = tid; e < kTsRows * 64; e += kBlock) xs[e] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < nr * k; e += kBlock) {
+    const int r = e / k;
+    xs[r * 64 + (e - r * k)] = xp[e];
+  }
+  double creg[64];
+#pragma unroll
+  for (int l = 0; l < 64; ++l)
+    creg[l] = (lane < k && l < k) ? (TB ? C[(size_t)lane * k + l] : C[(size_t)l * k + lane]) : 0.0;
+  __syncthreads();
+  constexpr int RW = kTsRows / 4;   // rows per wave: wave, wave + 4, ...
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    double yv[RW / 2];
+#pragma unroll
+    for (int q = 0; q < RW / 2; ++q) {
+      const int rr = wave + 4 * (half * (RW / 2) + q);
+      yv[q] = (accumulate && lane < k && rr < nr) ? Y[(r0 + rr) * k + lane] : 0.0;
+    }
+#pragma unroll 2
+    for (int q = 0; q < RW / 2; ++q) {
+      const int rr = wave + 4 * (half * (RW / 2) + q);
+      const double* xr = xs + rr * 64;
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int l = 0; l < 64; l += 2) {
+        a0 = fma(xr[l], creg[l], a0);
+        a1 = fma(xr[l + 1], creg[l + 1], a1);
+      }
+      if (lane < k && rr < nr) Y[(r0 + rr) * k + lane] = yv[q] + (a0 + a1);
+    }
+  }
 }
 
 __global__ void set_blocks_kernel(int n, int nh, int k, const double* __restrict__ C0, const double* __restrict__ G,
@@ -335,8 +546,34 @@ int gram_tiles(long long N, int k) {
   return (int)t;
 }
 
+void launch_gram2(long long N, int k, const double* X, const double* Y1, const double* Y2, double* partial,
+                  int tiles, double* G1, double* G2, hipStream_t s) {
+  long long rows = (N + tiles - 1) / tiles;
+  rows = ((rows + 3) / 4) * 4;
+  const int blocks = ((tiles + 7) / 8) * 8;
+  const int T = (k + 15) / 16;
+  const size_t lds = (size_t)(Y2 ? 3 : 2) * kGramRows * (T * 16 + 1) * sizeof(double);
+  if (k <= 64) {
+    if (Y2) gram_lds_kernel<2, 64><<<blocks, kBlock, lds, s>>>(N, k, X, Y1, Y2, partial, tiles, rows);
+    else gram_lds_kernel<1, 64><<<blocks, kBlock, lds, s>>>(N, k, X, Y1, nullptr, partial, tiles, rows);
+  } else {
+    // k > 64: one right-hand block per pass (keeps the accumulators in registers)
+    const size_t lds1 = (size_t)2 * kGramRows * (T * 16 + 1) * sizeof(double);
+    gram_lds_kernel<1, 128><<<blocks, kBlock, lds1, s>>>(N, k, X, Y1, nullptr, partial, tiles, rows);
+    if (Y2)
+      gram_lds_kernel<1, 128><<<blocks, kBlock, lds1, s>>>(N, k, X, Y2, nullptr, partial + (size_t)tiles * k * k,
+                                                           tiles, rows);
+  }
+  reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial, G1);
+  if (Y2) reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial + (size_t)tiles * k * k, G2);
+}
+
 void launch_gram(long long N, int k, const double* X, const double* Y, double* partial, int tiles, double* G,
                  hipStream_t s) {
+  if (k <= 128) {
+    launch_gram2(N, k, X, Y, nullptr, partial, tiles, G, nullptr, s);
+    return;
+  }
   long long rows = (N + tiles - 1) / tiles;
   rows = ((rows + 3) / 4) * 4;
   const int blocks = ((tiles + 7) / 8) * 8;
@@ -346,18 +583,37 @@ void launch_gram(long long N, int k, const double* X, const double* Y, double* p
 
 void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
                  int ldb, double beta, double* C, int ldc, hipStream_t s) {
+  if (M <= kSmallM && K <= kSmallK) {
+    dim3 g((N + 63) / 64, M);
+    gemm_small_kernel<double><<<g, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                   ldc);
+    return;
+  }
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
   gemm_kernel<double><<<grid, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 void launch_gemm_f32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda, const float* B,
                      int ldb, double beta, float* C, int ldc, hipStream_t s) {
+  if (M <= kSmallM && K <= kSmallK) {
+    dim3 g((N + 63) / 64, M);
+    gemm_small_kernel<float><<<g, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                  ldc);
+    return;
+  }
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
   gemm_kernel<float><<<grid, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
-void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, hipStream_t s) {
-  launch_gemm(false, false, (int)N, k, k, 1.0, X, k, C, k, accumulate ? 1.0 : 0.0, Y, k, s);
+void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, int tb,
+                 hipStream_t s) {
+  if (k <= 64) {
+    const unsigned blocks = (unsigned)((N + kTsRows - 1) / kTsRows);
+    if (tb) tsmm_kernel<1><<<blocks, kBlock, 0, s>>>(N, k, X, C, Y, accumulate);
+    else tsmm_kernel<0><<<blocks, kBlock, 0, s>>>(N, k, X, C, Y, accumulate);
+    return;
+  }
+  launch_gemm(false, tb != 0, (int)N, k, k, 1.0, X, k, C, k, accumulate ? 1.0 : 0.0, Y, k, s);
 }
 
 void launch_set_diag_block(int n, int nh, int k, const double* C0, const double* G, const double* H, double* T,

@@ -322,10 +322,8 @@ __global__ __launch_bounds__(kDenseThreads) void tridiag_kernel(int n, double* _
 //     p_{j+1} = tau_{j+1} A v_{j+1}; the owner of row j+2 publishes that row.
 // The grid is launched 8x larger than NW and only blocks with index % 8 == 0
 // work, so the working blocks share one XCD (blocks are dealt round-robin over
-// the 8 XCDs) and its L2.  Exchanged data is read with agent-scope atomic loads
-// and published before a release on the barrier counter.  The spin on the
-// counter is bounded: on timeout a block raises *err and returns, so every wave
-// exits.
+// the 8 XCDs) and its L2.  Exchanged data is written and read with device-scope
+// atomic accesses (L1 bypass); the barrier below orders them.
 constexpr int kCoopMaxN = 512;
 constexpr int kCoopThreads = 512;
 constexpr int kCoopWaves = kCoopThreads / 64;
@@ -334,18 +332,19 @@ __device__ __forceinline__ double ld_agent(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ bool grid_barrier(unsigned* counter, unsigned target, int* err) {
-  __syncthreads();
+// Software barriers of the NW working blocks (bounded spin: on timeout a block
+// raises *err and returns, so every wave exits).
+constexpr unsigned kCoopMaxSpins = 1u << 22;
+
+__device__ bool barrier_spin(unsigned* counter, unsigned target, int* err, bool acquire) {
   __shared__ int ok;
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
     ok = 1;
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while ((acquire ? __hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                    : __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1u << 26) ||
-          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      if (++spins > kCoopMaxSpins || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
@@ -354,6 +353,33 @@ __device__ bool grid_barrier(unsigned* counter, unsigned target, int* err) {
   }
   __syncthreads();
   return ok != 0;
+}
+
+// Agent-scope barrier: release fence and acquire spin (L2 write-back and
+// invalidate included), valid wherever the blocks run.
+__device__ bool grid_barrier_fenced(unsigned* counter, unsigned target, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return barrier_spin(counter, target, err, true);
+}
+
+// Barrier for blocks that share one XCD (checked at kernel start): every
+// exchanged value is written and read with device-scope accesses, which bypass
+// the per-CU L1 and meet in that XCD's L2, so it suffices that this block's
+// stores have completed before it arrives; no L2 write-back or invalidate.
+__device__ bool grid_barrier_xcd(unsigned* counter, unsigned target, int* err) {
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's stores are at the L2
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return barrier_spin(counter, target, err, false);
+}
+
+__device__ __forceinline__ unsigned xcc_id() {
+  // HW_REG_XCC_ID (hardware register 20), bits [3:0]: the XCD this wave runs on
+  return (unsigned)__builtin_amdgcn_s_getreg((3 << 11) | 20) & 0xFu;
 }
 
 __device__ double block_sum_c(double v, double (*red)[kCoopWaves], int& parity) {
@@ -393,10 +419,13 @@ __device__ double make_reflector(const double* row, int mm, double* v, double& b
 __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int n, int NW, double* __restrict__ T,
                                                                    double* __restrict__ tri,
                                                                    double* __restrict__ xchg,
-                                                                   unsigned* counter, int* err) {
+                                                                   unsigned* counter, int* err,
+                                                                   unsigned* xccs) {
   if (blockIdx.x % 8 != 0) return;
   const int b = blockIdx.x / 8;
   if (b >= NW) return;
+  const unsigned myxcc = xcc_id();
+  if (threadIdx.x == 0) __hip_atomic_store(&xccs[b], myxcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   extern __shared__ double dyn[];
   const int R = (n + NW - 1) / NW;               // owned rows (cyclic)
   double* slab = dyn;                            // R x n
@@ -441,7 +470,17 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int n, int N
     for (int c = tid; c < n; c += kCoopThreads)
       __hip_atomic_store(&rbuf[c], slab[(size_t)(1 / NW) * n + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   target += NW;
-  if (!grid_barrier(counter, target, err)) return;
+  if (!grid_barrier_fenced(counter, target, err)) return;
+  // the cheap barrier only if every working block shares this XCD
+  __shared__ int one_xcd;
+  if (threadIdx.x == 0) {
+    int same = 1;
+    for (int q = 0; q < NW; ++q)
+      same &= (__hip_atomic_load(&xccs[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == myxcc) ? 1 : 0;
+    one_xcd = same;
+  }
+  __syncthreads();
+  const bool fast_barrier = one_xcd != 0;
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;                     // trailing size of step j (global cols j+1 .. n-1)
     const int par = j & 1;
@@ -511,28 +550,47 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int n, int N
     double* t1 = v; v = v2; v2 = t1;
     tcur = tnext;
     target += NW;
-    if (!grid_barrier(counter, target, err)) return;
+    if (!(fast_barrier ? grid_barrier_xcd(counter, target, err) : grid_barrier_fenced(counter, target, err))) return;
   }
 }
 
-__global__ void tri_finish_kernel(int n, double* __restrict__ tri) {
-  // Gershgorin interval, pivmin and |T| of the tridiagonal (one thread)
+__global__ __launch_bounds__(256) void tri_finish_kernel(int n, double* __restrict__ tri) {
+  // Gershgorin interval, pivmin and |T| of the tridiagonal (one block)
+  __shared__ double r_lo[4], r_hi[4], r_e[4];
   double* d = tri;
   double* e = tri + n;
-  e[n - 1] = 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double lo = DBL_MAX, hi = -DBL_MAX, emax = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const double rr = ((i > 0) ? fabs(e[i - 1]) : 0.0) + ((i + 1 < n) ? fabs(e[i]) : 0.0);
+  for (int i = tid; i < n; i += 256) {
+    const double el = (i > 0) ? e[i - 1] : 0.0;
+    const double er = (i + 1 < n) ? e[i] : 0.0;
+    const double rr = fabs(el) + fabs(er);
     lo = fmin(lo, d[i] - rr);
     hi = fmax(hi, d[i] + rr);
-    if (i + 1 < n) emax = fmax(emax, e[i] * e[i]);
+    emax = fmax(emax, er * er);
   }
-  const double tnorm = fmax(fabs(lo), fabs(hi));
-  double* sc = tri + 3 * n;
-  sc[0] = lo - (2.0 * DBL_EPSILON * tnorm * n + DBL_MIN);
-  sc[1] = hi + (2.0 * DBL_EPSILON * tnorm * n + DBL_MIN);
-  sc[2] = DBL_MIN * fmax(1.0, emax);
-  sc[3] = tnorm;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+    emax = fmax(emax, __shfl_xor(emax, o, 64));
+  }
+  if (lane == 0) { r_lo[wave] = lo; r_hi[wave] = hi; r_e[wave] = emax; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w) {
+      lo = fmin(lo, r_lo[w]);
+      hi = fmax(hi, r_hi[w]);
+      emax = fmax(emax, r_e[w]);
+    }
+    e[n - 1] = 0.0;
+    const double tnorm = fmax(fabs(lo), fabs(hi));
+    double* sc = tri + 3 * n;
+    sc[0] = lo - (2.0 * DBL_EPSILON * tnorm * n + DBL_MIN);
+    sc[1] = hi + (2.0 * DBL_EPSILON * tnorm * n + DBL_MIN);
+    sc[2] = DBL_MIN * fmax(1.0, emax);
+    sc[3] = tnorm;
+  }
 }
 
 __global__ void coop_reset_kernel(unsigned* counter, int* err) {
@@ -694,54 +752,202 @@ __global__ __launch_bounds__(kBlock) void vgram_kernel(int n, int k, const doubl
 }
 
 // 4b. L = chol(G), G <- L^{-1} (lower), in LDS, one block.  k <= kOrthoMaxK.
+//
+// Right-looking Cholesky with one barrier per pivot: in step j every thread
+// reads the (final) pivot G_jj and applies the rank-1 update of the trailing
+// lower triangle with the unscaled column j divided by the pivot; the scaling of
+// column j by 1/sqrt(pivot) is deferred to step j+1, where nothing reads it.
+// The inverse is then formed column by column (forward substitution, one thread
+// per column), its strictly lower part stored transposed in the unused upper
+// triangle of the LDS array.
 constexpr int kOrthoMaxK = 128;
 __global__ __launch_bounds__(kDenseThreads) void cholinv_kernel(int k, double* __restrict__ G, int* info) {
   __shared__ double L[kOrthoMaxK][kOrthoMaxK + 1];
+  __shared__ double dinv[kOrthoMaxK];
+  __shared__ double wmax[kDenseThreads / 64];
   __shared__ int bad;
-  __shared__ double ptol;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) bad = 0;
+  double dm = 0.0;
   for (int q = tid; q < k * k; q += kDenseThreads) {
     const int a = q / k, b = q % k;
-    L[a][b] = (b <= a) ? G[(size_t)a * k + b] : 0.0;
+    const double g = G[(size_t)a * k + b];
+    L[a][b] = (b <= a) ? g : 0.0;
+    if (a == b) dm = fmax(dm, g);
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  if (lane == 0) wmax[wave] = dm;
   __syncthreads();
-  if (tid == 0) {      // pivots at or below k eps max_i G_ii count as rank deficiency
-    double dmax = 0.0;
-    for (int i = 0; i < k; ++i) dmax = fmax(dmax, L[i][i]);
-    ptol = k * DBL_EPSILON * dmax;
-  }
-  __syncthreads();
+  dm = 0.0;
+  for (int w = 0; w < kDenseThreads / 64; ++w) dm = fmax(dm, wmax[w]);
+  const double ptol = k * DBL_EPSILON * dm;   // pivots at or below this count as rank deficiency
+  // 2D thread layout for the trailing updates: 32 x 32
+  const int tx = tid & 31, ty = tid >> 5;
+  double prev_scale = 1.0;
   for (int j = 0; j < k; ++j) {
-    if (tid == 0) {
-      const double dj = L[j][j];
-      if (!(dj > ptol)) bad = 1;
-      L[j][j] = sqrt(dj > 0.0 ? dj : 1.0);
+    const double dj = L[j][j];
+    const double pe = (dj > 0.0) ? dj : 1.0;
+    if (tid == 0 && !(dj > ptol)) bad = 1;
+    if (j > 0) {   // finish column j-1 (nothing reads it in this step)
+      for (int i = j - 1 + tid; i < k; i += kDenseThreads)
+        L[i][j - 1] = (i == j - 1) ? 1.0 / prev_scale : L[i][j - 1] * prev_scale;
     }
-    __syncthreads();
-    const double djj = L[j][j];
-    for (int i = j + 1 + tid; i < k; i += kDenseThreads) L[i][j] /= djj;
-    __syncthreads();
-    const int w = k - j - 1;
-    for (int q = tid; q < w * w; q += kDenseThreads) {
-      const int i = j + 1 + q / w, l = j + 1 + q % w;
-      if (l <= i) L[i][l] -= L[i][j] * L[l][j];
+    const double rp = 1.0 / pe;
+    for (int i = j + 1 + ty; i < k; i += 32) {
+      const double lij = L[i][j] * rp;
+      for (int l = j + 1 + tx; l <= i; l += 32) L[i][l] = fma(-lij, L[l][j], L[i][l]);
     }
+    prev_scale = 1.0 / sqrt(pe);
     __syncthreads();
   }
-  // inverse: column c by thread c (forward substitution), written to G
+  if (tid == 0) L[k - 1][k - 1] = 1.0 / prev_scale;   // column k-1 has no entries below the diagonal
+  __syncthreads();
+  for (int c = tid; c < k; c += kDenseThreads) dinv[c] = 1.0 / L[c][c];
+  __syncthreads();
+  // inverse: thread c owns column c of L^{-1}; entry (i, c), i > c, lives at L[c][i]
   for (int c = tid; c < k; c += kDenseThreads) {
-    for (int i = 0; i < k; ++i) {
-      double sacc = (i == c) ? 1.0 : 0.0;
-      if (i >= c) {
-        for (int l = c; l < i; ++l) sacc -= L[i][l] * G[(size_t)l * k + c];
-        G[(size_t)i * k + c] = sacc / L[i][i];
-      } else {
-        G[(size_t)i * k + c] = 0.0;
-      }
+    const double dc = dinv[c];
+    for (int i = c + 1; i < k; ++i) {
+      double acc = L[i][c] * dc;
+      for (int l = c + 1; l < i; ++l) acc = fma(L[i][l], L[c][l], acc);
+      L[c][i] = -acc * dinv[i];
     }
+  }
+  __syncthreads();
+  for (int q = tid; q < k * k; q += kDenseThreads) {
+    const int i = q / k, c = q % k;
+    G[q] = (i > c) ? L[c][i] : ((i == c) ? dinv[c] : 0.0);
   }
   if (tid == 0 && bad) *info = 1;
+}
+
+// 4b''. The same for k <= 64 with 256 threads: right-looking Cholesky with one
+// barrier per pivot (16 x 16 thread tiles over the trailing triangle, column
+// scaling deferred by one step), then the inverse by columns (one thread per
+// column) into a separate LDS array, so the loads of a column's inner products
+// do not wait on its stores.
+__global__ __launch_bounds__(256) void cholinv256_kernel(int k, double* __restrict__ G, int* info) {
+  __shared__ double L[64][65];
+  __shared__ double X[64][65];   // X[c][i] = (L^{-1})[i][c]
+  __shared__ double dinv[64];
+  __shared__ double wmax[4];
+  __shared__ int bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tx = tid & 15, ty = tid >> 4;
+  if (tid == 0) bad = 0;
+  double dm = 0.0;
+  for (int q = tid; q < k * k; q += 256) {
+    const int a = q / k, b = q - (q / k) * k;
+    const double g = G[q];
+    L[a][b] = (b <= a) ? g : 0.0;
+    if (a == b) dm = fmax(dm, g);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  if (lane == 0) wmax[wave] = dm;
+  __syncthreads();
+  dm = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+  const double ptol = k * DBL_EPSILON * dm;   // pivots at or below this count as rank deficiency
+  double prev = 1.0;
+  for (int j = 0; j < k; ++j) {
+    const double dj = L[j][j];
+    const double pe = (dj > 0.0) ? dj : 1.0;
+    if (tid == 0 && !(dj > ptol)) bad = 1;
+    if (j > 0)
+      for (int i = j - 1 + tid; i < k; i += 256) L[i][j - 1] = (i == j - 1) ? 1.0 / prev : L[i][j - 1] * prev;
+    const double rp = 1.0 / pe;
+    for (int i = j + 1 + ty; i < k; i += 16) {
+      const double lij = L[i][j] * rp;
+      for (int l = j + 1 + tx; l <= i; l += 16) L[i][l] = fma(-lij, L[l][j], L[i][l]);
+    }
+    prev = 1.0 / sqrt(pe);
+    __syncthreads();
+  }
+  if (tid == 0) L[k - 1][k - 1] = 1.0 / prev;
+  __syncthreads();
+  for (int c = tid; c < k; c += 256) dinv[c] = 1.0 / L[c][c];
+  __syncthreads();
+  for (int c = tid; c < k; c += 256) {
+    const double dc = dinv[c];
+    X[c][c] = dc;
+    for (int i = c + 1; i < k; ++i) {
+      double a0 = L[i][c] * dc, a1 = 0.0;
+      int l = c + 1;
+      for (; l + 1 < i; l += 2) {
+        a0 = fma(L[i][l], X[c][l], a0);
+        a1 = fma(L[i][l + 1], X[c][l + 1], a1);
+      }
+      if (l < i) a0 = fma(L[i][l], X[c][l], a0);
+      X[c][i] = -(a0 + a1) * dinv[i];
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < k * k; q += 256) {
+    const int i = q / k, c = q - (q / k) * k;
+    G[q] = (i >= c) ? X[c][i] : 0.0;
+  }
+  if (tid == 0 && bad) *info = 1;
+}
+
+// 4b'. The same for k <= 64 with one wavefront.  Lane i keeps row i of the
+// factor in registers (row[l] = L[i][l]); pivot step j broadcasts column j
+// through LDS (every lane writes its own entry), so a step costs one LDS write,
+// a broadcast read of the column and one FMA per trailing entry.  The inverse
+// is formed column by column (lane c solves L x = e_c) with L read from LDS as
+// a broadcast.  Register arrays are only indexed by unrolled constants.
+__global__ __launch_bounds__(64) void cholinv64_kernel(int k, double* __restrict__ G, int* info) {
+  __shared__ double colj[64];
+  __shared__ double Ls[64][64];
+  const int lane = threadIdx.x;
+  double row[64];
+#pragma unroll
+  for (int l = 0; l < 64; ++l) row[l] = (lane < k && l < k && l <= lane) ? G[(size_t)lane * k + l] : 0.0;
+  double dm = (lane < k) ? G[(size_t)lane * k + lane] : 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  const double ptol = k * DBL_EPSILON * dm;   // pivots at or below this count as rank deficiency
+  int bad = 0;
+  for (int j = 0; j < k; ++j) {
+    double rj = 0.0;                           // row[j] (unrolled select)
+#pragma unroll
+    for (int t = 0; t < 64; ++t) rj = (t == j) ? row[t] : rj;
+    colj[lane] = rj;
+    __syncthreads();
+    const double dj = colj[j];
+    const double pe = (dj > 0.0) ? dj : 1.0;
+    bad |= !(dj > ptol);
+    const double sq = sqrt(pe), rs = 1.0 / sq;
+    const double lij = (lane > j) ? rj * rs : 0.0;    // final L[lane][j]
+    const double nj = (lane == j) ? sq : ((lane > j) ? lij : rj);
+#pragma unroll
+    for (int t = 0; t < 64; ++t) {
+      // trailing update L[lane][t] -= L[lane][j] L[t][j] for j < t <= lane
+      const double upd = fma(-lij, colj[t] * rs, row[t]);
+      row[t] = (t == j) ? nj : ((t > j && t <= lane) ? upd : row[t]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int l = 0; l < 64; ++l) Ls[lane][l] = row[l];
+  __syncthreads();
+  // lane c: x = L^{-1} e_c by forward substitution; x[i] = 0 for i < c
+  double x[64];
+  const int c = lane;
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int l = 0; l < i; ++l) acc = fma(-Ls[i][l], x[l], acc);
+    x[i] = (i < k && i >= c) ? acc / Ls[i][i] : 0.0;
+  }
+  for (int i = 0; i < k; ++i) {
+    double xi = 0.0;
+#pragma unroll
+    for (int t = 0; t < 64; ++t) xi = (t == i) ? x[t] : xi;
+    if (c < k) G[(size_t)i * k + c] = xi;
+  }
+  if (lane == 0 && bad) *info = 1;
 }
 
 // 4c. Vo = L^{-1} Vi in the vector index: vo_j = sum_{l <= j} Li[j][l] vi_l.
@@ -862,16 +1068,18 @@ void launch_trinv(int n, const double* L, int ldl, double* Li, int ldi, hipStrea
 }
 
 size_t syev_work_doubles(int n, int k) {
-  // tri (3n + 8) + lam (k) + Vt, Vt2 (n k each) + G (k k) + S blocks
+  // tri (3n + 8) + lam (k) + Vt, Vt2 (n k each) + G (k k) + S blocks (+ a second k x k
+  // for the triangular inverse when k exceeds the one-block Cholesky-inverse)
   const size_t nblk = (size_t)(n + kWyB - 1) / kWyB + 1;
   return (size_t)3 * n + 8 + (size_t)k + (size_t)2 * n * k + (size_t)k * k + nblk * kWyB * kWyB +
-         4 * kCoopMaxN + 72;
+         4 * kCoopMaxN + 72 + ((k > kOrthoMaxK) ? (size_t)k * k : 0);
 }
 
 int syev_max_k() { return kOrthoMaxK; }
 
 void launch_cholinv(int k, double* G, int* info, hipStream_t s) {
-  cholinv_kernel<<<1, kDenseThreads, 0, s>>>(k, G, info);
+  if (k <= 64) cholinv256_kernel<<<1, 256, 0, s>>>(k, G, info);
+  else cholinv_kernel<<<1, kDenseThreads, 0, s>>>(k, G, info);
 }
 
 void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s) {
@@ -899,17 +1107,25 @@ void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* w
   if (NW > 0) {
     const size_t lds = ((size_t)((n + NW - 1) / NW) * n + 5 * kCoopMaxN) * sizeof(double);
     coop_reset_kernel<<<1, 1, 0, s>>>(coop_counter, coop_err);
-    tridiag_coop_kernel<<<8 * NW, kCoopThreads, lds, s>>>(n, NW, T, tri, xchg, coop_counter, coop_err);
-    tri_finish_kernel<<<1, 1, 0, s>>>(n, tri);
+    tridiag_coop_kernel<<<8 * NW, kCoopThreads, lds, s>>>(n, NW, T, tri, xchg, coop_counter, coop_err,
+                                                        (unsigned*)(xchg + 4 * kCoopMaxN + 1));
+    tri_finish_kernel<<<1, 256, 0, s>>>(n, tri);
   } else {
     tridiag_kernel<<<1, kDenseThreads, 0, s>>>(n, T, tri);
   }
   bisect_kernel<<<k, 64, 0, s>>>(n, tri, lam);
   invit_kernel<<<k, 64, 0, s>>>(n, k, tri, lam, Vt);
+  double* G2 = xchg + 4 * kCoopMaxN + 8;                    // after the barrier counter and flag
   for (int pass = 0; pass < 2; ++pass) {
     vgram_kernel<<<gb, kBlock, 0, s>>>(n, k, Vt, G);
-    cholinv_kernel<<<1, kDenseThreads, 0, s>>>(k, G, info);
-    vorth_apply_kernel<<<ab, kBlock, 0, s>>>(n, k, G, Vt, Vt2);
+    if (k <= kOrthoMaxK) {
+      launch_cholinv(k, G, info, s);
+      vorth_apply_kernel<<<ab, kBlock, 0, s>>>(n, k, G, Vt, Vt2);
+    } else {
+      launch_cholesky(k, G, k, info, s);
+      launch_trinv(k, G, k, G2, k, s);
+      vorth_apply_kernel<<<ab, kBlock, 0, s>>>(n, k, G2, Vt, Vt2);
+    }
     double* t = Vt; Vt = Vt2; Vt2 = t;
   }
   if (n > 2) wy_prep_kernel<<<(n - 2 + kWyB - 1) / kWyB, kBlock, 0, s>>>(n, T, tri, Sall);
@@ -919,6 +1135,16 @@ void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* w
 }
 
 int syev_max_n() { return kSyevMaxN; }
+
+void launch_vorth2(int n, int k, double* Vt, double* Vt2, double* G, int* info, hipStream_t s) {
+  const unsigned gb = (unsigned)((k * k + kBlock - 1) / kBlock);
+  const unsigned ab = (unsigned)(((long long)n * k + kBlock - 1) / kBlock);
+  for (int pass = 0; pass < 2; ++pass) {
+    vgram_kernel<<<gb, kBlock, 0, s>>>(n, k, pass ? Vt2 : Vt, G);
+    launch_cholinv(k, G, info, s);
+    vorth_apply_kernel<<<ab, kBlock, 0, s>>>(n, k, G, pass ? Vt2 : Vt, pass ? Vt : Vt2);
+  }
+}
 
 namespace {
 __global__ void symmetrize_kernel(int n, double* A) {

@@ -217,6 +217,182 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs a, int slot
   }
 }
 
+// ---- flat (node, column) kernels: thread q handles node q / k, column q % k.
+// 32-bit index arithmetic (the launchers fall back to the 64-bit kernels when
+// N k >= 2^31); one thread per output keeps thousands of waves in flight, which
+// the small coarse levels need to hide L2 latency.
+
+__device__ __forceinline__ void flat_split(unsigned q, unsigned k, unsigned& node, unsigned& col) {
+  node = q / k;
+  col = q - node * k;
+}
+
+template <int DIM>
+__device__ __forceinline__ void node_xyz32(unsigned node, unsigned m, int& x, int& y, int& z) {
+  const unsigned q = node / m;
+  x = (int)(node - q * m);
+  if (DIM == 3) {
+    const unsigned r = q / m;
+    y = (int)(q - r * m);
+    z = (int)r;
+  } else {
+    y = (int)q;
+    z = 0;
+  }
+}
+
+// A x, M x, b - A x or a damped Jacobi sweep on a level whose operator is
+// given by 3^d coefficients per node (Galerkin coarse levels) or formed from
+// kappa (fine level of 2D problems).
+template <int DIM, int SRC, int EPI, typename T>
+__global__ __launch_bounds__(kBlock) void flat_stencil_kernel(StencilArgs a) {
+  constexpr int NS = NSt<DIM>::v;
+  const unsigned k = (unsigned)a.k, N = (unsigned)a.N;
+  const unsigned q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= N * k) return;
+  unsigned node, col;
+  flat_split(q, k, node, col);
+  const int m = a.m;
+  int x, y, z;
+  node_xyz32<DIM>(node, (unsigned)m, x, y, z);
+  const T* __restrict__ X = (const T*)a.x;
+  const bool needA = (EPI != EPI_AM) || (a.out1 != nullptr);
+  const bool needM = (EPI == EPI_AM) && (a.out2 != nullptr);
+  double c[NS];
+  if (needA) {
+    if (SRC == (int)ASource::Kappa) {
+      kappa_coefs<DIM>(a.kappa, m, a.h, x, y, z, c);
+    } else {
+      const double* __restrict__ cp = a.coef + (size_t)node * NS;
+#pragma unroll
+      for (int o = 0; o < NS; ++o) c[o] = cp[o];
+    }
+  }
+  const bool vx[3] = {x > 0, true, x + 1 < m};
+  const bool vy[3] = {y > 0, true, y + 1 < m};
+  const bool vz[3] = {DIM == 3 ? z > 0 : false, true, DIM == 3 ? z + 1 < m : false};
+  const int sy = m * (int)k, sz = m * m * (int)k;
+  const long long base = (long long)q;
+  double ax = 0.0, mx = 0.0, xc = 0.0;
+#pragma unroll
+  for (int o = 0; o < NS; ++o) {
+    const int ox = o % 3, oy = (o / 3) % 3, oz = (DIM == 3) ? o / 9 : 1;
+    if (vx[ox] && vy[oy] && vz[oz]) {
+      const long long off = (long long)(ox - 1) * (int)k + (long long)(oy - 1) * sy +
+                            ((DIM == 3) ? (long long)(oz - 1) * sz : 0);
+      const double v = (double)X[base + off];
+      if (o == NS / 2) xc = v;
+      if (needA) ax = fma(c[o], v, ax);
+      if (needM) mx = fma(mpat<DIM>(o, a.h), v, mx);
+    }
+  }
+  if (EPI == EPI_AM) {
+    if (a.out1) ((T*)a.out1)[q] = (T)ax;
+    if (a.out2) ((T*)a.out2)[q] = (T)mx;
+  } else if (EPI == EPI_RESID) {
+    ((T*)a.out1)[q] = (T)((double)((const T*)a.b)[q] - ax);
+  } else {  // EPI_SWEEP
+    ((T*)a.out1)[q] = (T)(xc + a.omega * a.dinv[node] * ((double)((const T*)a.b)[q] - ax));
+  }
+}
+
+template <typename T>
+__global__ void first_sweep_flat_kernel(unsigned n, unsigned k, const double* __restrict__ dinv, double omega,
+                                        const T* __restrict__ b, T* __restrict__ x) {
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] = (T)(omega * dinv[i / k] * (double)b[i]);
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void restrict_flat_kernel(int mf, int mc, unsigned k, const T* __restrict__ xf,
+                                                              T* __restrict__ xc) {
+  unsigned Nc = (unsigned)mc * mc;
+  if (DIM == 3) Nc *= mc;
+  const unsigned q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= Nc * k) return;
+  unsigned node, col;
+  flat_split(q, k, node, col);
+  int X, Y, Z;
+  node_xyz32<DIM>(node, (unsigned)mc, X, Y, Z);
+  // fine node (2X+1, 2Y+1, 2Z+1) and its neighbours, weights 1 (centre) and 1/2 per offset axis;
+  // all 3^d fine nodes are interior because the coarse node is
+  const unsigned ctr = (unsigned)(2 * X + 1) + (unsigned)mf * ((unsigned)(2 * Y + 1) +
+                       (DIM == 3 ? (unsigned)mf * (unsigned)(2 * Z + 1) : 0u));
+  const long long sy = (long long)mf * k, sz = (long long)mf * mf * k;
+  const T* __restrict__ p = xf + (long long)ctr * k + col;
+  double s = 0.0;
+#pragma unroll
+  for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
+    const double wz = (oz == 0) ? 1.0 : 0.5;
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy) {
+      const double wy = (oy == 0) ? 1.0 : 0.5;
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        const double wx = (ox == 0) ? 1.0 : 0.5;
+        s = fma(wx * wy * wz, (double)p[ox * (long long)k + oy * sy + oz * sz], s);
+      }
+    }
+  }
+  xc[q] = (T)s;
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void prolong_flat_kernel(int mf, int mc, unsigned k, const T* __restrict__ xc,
+                                                             T* __restrict__ xf, int mode) {
+  unsigned Nf = (unsigned)mf * mf;
+  if (DIM == 3) Nf *= mf;
+  const unsigned q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= Nf * k) return;
+  unsigned node, col;
+  flat_split(q, k, node, col);
+  int x, y, z;
+  node_xyz32<DIM>(node, (unsigned)mf, x, y, z);
+  // per axis: odd fine coordinate f = 2c+1 sits on coarse node c (weight 1); even f lies
+  // between coarse nodes f/2 - 1 and f/2 (weight 1/2 each, a missing one is the boundary)
+  int lo[3], hi[3];
+  double wl[3], wh[3];
+  const int f[3] = {x, y, z};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    if (f[d] & 1) {
+      lo[d] = hi[d] = (f[d] - 1) >> 1;
+      wl[d] = 1.0;
+      wh[d] = 0.0;
+    } else {
+      lo[d] = (f[d] >> 1) - 1;
+      hi[d] = f[d] >> 1;
+      wl[d] = (lo[d] >= 0) ? 0.5 : 0.0;
+      wh[d] = (hi[d] < mc) ? 0.5 : 0.0;
+      lo[d] = (lo[d] >= 0) ? lo[d] : hi[d];     // clamp (its weight is 0)
+      hi[d] = (hi[d] < mc) ? hi[d] : lo[d];
+    }
+  }
+  double s = 0.0;
+  const unsigned mcu = (unsigned)mc;
+#pragma unroll
+  for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c) {
+    const int iz = (DIM == 3) ? (c ? hi[2] : lo[2]) : 0;
+    const double wz = (DIM == 3) ? (c ? wh[2] : wl[2]) : 1.0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int iy = b ? hi[1] : lo[1];
+      const double wy = b ? wh[1] : wl[1];
+#pragma unroll
+      for (int a2 = 0; a2 < 2; ++a2) {
+        const int ix = a2 ? hi[0] : lo[0];
+        const double w = (a2 ? wh[0] : wl[0]) * wy * wz;
+        const unsigned J = (unsigned)ix + mcu * ((unsigned)iy + (DIM == 3 ? mcu * (unsigned)iz : 0u));
+        if (w != 0.0) s = fma(w, (double)xc[(long long)J * k + col], s);
+      }
+    }
+  }
+  if (mode == 0) xf[q] = (T)s;
+  else if (mode == 1) xf[q] = (T)((double)xf[q] + s);
+  else xf[q] = (T)((double)xf[q] - s);
+}
+
 template <typename T>
 __global__ void first_sweep_kernel(long long N, int k, const double* __restrict__ dinv, double omega,
                                    const T* __restrict__ b, T* __restrict__ x) {
@@ -405,8 +581,31 @@ static void stencil_dispatch_epi(const StencilArgs& a, Epi epi, const GridLaunch
   }
 }
 
+constexpr long long kFlatMax = 0x7fffffffLL;   // flat kernels index (node, column) pairs in 32 bits
+
+template <int DIM, int SRC, typename T>
+static void flat_dispatch_epi(const StencilArgs& a, Epi epi, hipStream_t s) {
+  const unsigned blocks = nblk(a.N * a.k);
+  switch (epi) {
+    case EPI_AM: flat_stencil_kernel<DIM, SRC, EPI_AM, T><<<blocks, kBlock, 0, s>>>(a); break;
+    case EPI_RESID: flat_stencil_kernel<DIM, SRC, EPI_RESID, T><<<blocks, kBlock, 0, s>>>(a); break;
+    case EPI_SWEEP: flat_stencil_kernel<DIM, SRC, EPI_SWEEP, T><<<blocks, kBlock, 0, s>>>(a); break;
+    default: break;
+  }
+}
+
 template <typename T>
 static void launch_stencil_t(const StencilArgs& a, Epi epi, hipStream_t s) {
+  if (epi != EPI_EIGRES && a.N * a.k <= kFlatMax) {
+    if (a.dim == 3) {
+      if (a.src == ASource::Kappa) flat_dispatch_epi<3, 0, T>(a, epi, s);
+      else flat_dispatch_epi<3, 1, T>(a, epi, s);
+    } else {
+      if (a.src == ASource::Kappa) flat_dispatch_epi<2, 0, T>(a, epi, s);
+      else flat_dispatch_epi<2, 1, T>(a, epi, s);
+    }
+    return;
+  }
   const GridLaunch g = grid_launch(a.N, a.k);
   if (a.dim == 3) {
     if (a.src == ASource::Kappa) stencil_dispatch_epi<3, 0, T>(a, epi, g, s);
@@ -425,6 +624,16 @@ void launch_stencil(const StencilArgs& a, Epi epi, hipStream_t s) {
 void launch_first_sweep(int dim, long long N, int k, const double* dinv, double omega, const void* b, void* x,
                         int fp32, hipStream_t s) {
   (void)dim;
+  if (N * k <= kFlatMax) {
+    const unsigned n = (unsigned)(N * k);
+    if (fp32)
+      first_sweep_flat_kernel<float><<<nblk(N * k), kBlock, 0, s>>>(n, (unsigned)k, dinv, omega, (const float*)b,
+                                                                    (float*)x);
+    else
+      first_sweep_flat_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(n, (unsigned)k, dinv, omega, (const double*)b,
+                                                                     (double*)x);
+    return;
+  }
   if (fp32) first_sweep_kernel<float><<<nblk(N * k), kBlock, 0, s>>>(N, k, dinv, omega, (const float*)b, (float*)x);
   else first_sweep_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, dinv, omega, (const double*)b, (double*)x);
 }
@@ -432,6 +641,12 @@ void launch_first_sweep(int dim, long long N, int k, const double* dinv, double 
 template <typename T>
 static void launch_restrict_t(int dim, int mf, int mc, int k, const T* xf, T* xc, hipStream_t s) {
   long long Nc = (long long)mc * mc * (dim == 3 ? mc : 1);
+  long long Nf = (long long)mf * mf * (dim == 3 ? mf : 1);
+  if (Nf * k <= kFlatMax) {
+    if (dim == 3) restrict_flat_kernel<3, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xf, xc);
+    else restrict_flat_kernel<2, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xf, xc);
+    return;
+  }
   if (dim == 3) restrict_kernel<3, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, k, xf, xc);
   else restrict_kernel<2, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, k, xf, xc);
 }
@@ -444,6 +659,11 @@ void launch_restrict(int dim, int mf, int mc, int k, const void* xf, void* xc, i
 template <typename T>
 static void launch_prolong_t(int dim, int mf, int mc, int k, const T* xc, T* xf, int mode, hipStream_t s) {
   long long Nf = (long long)mf * mf * (dim == 3 ? mf : 1);
+  if (Nf * k <= kFlatMax) {
+    if (dim == 3) prolong_flat_kernel<3, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode);
+    else prolong_flat_kernel<2, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode);
+    return;
+  }
   if (dim == 3) prolong_kernel<3, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
   else prolong_kernel<2, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
 }

@@ -115,6 +115,9 @@ void launch_xpby(long long N, int k, const double* Z, const double* beta, double
 void launch_copy(size_t n, const double* src, double* dst, hipStream_t s);
 // Gram G = X^T Y (k x k) by FP64 MFMA over row chunks, fixed-order reduction
 int gram_tiles(long long N, int k);
+// G1 = X^T Y1 and, if Y2, G2 = X^T Y2 in one pass over X (partial: 2 x tiles x k x k)
+void launch_gram2(long long N, int k, const double* X, const double* Y1, const double* Y2, double* partial,
+                  int tiles, double* G1, double* G2, hipStream_t s);
 void launch_gram(long long N, int k, const double* X, const double* Y, double* partial, int tiles, double* G,
                  hipStream_t s);
 // C = alpha op(A) op(B) + beta C, row-major, FP64
@@ -132,8 +135,9 @@ void launch_d2f(size_t n, const double* a, float* b, hipStream_t s);
 void launch_add_f2d(size_t n, const double* u, const float* e, double* w, hipStream_t s);
 void launch_cg_start_f32(size_t n, const double* R, float* r, float* e, hipStream_t s);
 void launch_copy_f32(size_t n, const float* src, float* dst, hipStream_t s);
-// tall-skinny: Y = X C (+ Y): X N x k, C k x k, Y N x k
-void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, hipStream_t s);
+// tall-skinny: Y = X op(C) (+ Y): X N x k, C k x k (transposed if tb), Y N x k; Y must not alias X
+void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, int tb,
+                 hipStream_t s);
 // small helpers
 void launch_set_diag_block(int n, int nh, int k, const double* C0, const double* G, const double* H, double* T,
                            hipStream_t s);
@@ -150,6 +154,25 @@ int syev_max_n();
 int syev_max_k();
 // G (k x k, lower part read) <- L^{-1} with G = L L^T, in LDS; *info = 1 on a non-positive pivot. k <= syev_max_k()
 void launch_cholinv(int k, double* G, int* info, hipStream_t s);
+// two Cholesky-QR passes over a vector-major n x k block (result back in Vt; Vt2 scratch)
+void launch_vorth2(int n, int k, double* Vt, double* Vt2, double* G, int* info, hipStream_t s);
+
+// ---- structured augmented eigenproblem (small.hip): Tt = [[diag(theta), Gt], [Gt^T, H]]
+int small_fast_max_k();
+int small_fast_max_nh();   // N_H limit
+// shift-invert / Rayleigh-quotient iteration per pair from the shifts sigma; Vt vector-major (N_H + k) x k
+void launch_small_rqi(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* sigma,
+                      double scale, double* Vt, double* rq, hipStream_t s);
+// Rayleigh quotients and residual norms of the columns of an orthonormal Vt
+void launch_small_rr(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
+                     double* rq, double* res, hipStream_t s);
+// acceptance: residuals <= tol_abs and the inertia count below max(rq) + gap equals k;
+// writes lam ascending, perm, status[0] (1 accepted) and status[1] (the count)
+void launch_small_accept(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* rq,
+                         const double* res, double tol_abs, double gap, double* lam, int* perm, int* status,
+                         hipStream_t s);
+// V (n x k row-major) = columns perm of Vt
+void launch_small_emit(int n, int k, const double* Vt, const int* perm, double* V, hipStream_t s);
 void launch_symmetrize(int n, double* A, hipStream_t s);
 
 }  // namespace pase

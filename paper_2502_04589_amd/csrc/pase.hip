@@ -77,6 +77,14 @@ struct pase_handle {
   float *vb32[PASE_MAX_LEVELS] = {}, *vx32[PASE_MAX_LEVELS] = {}, *vxa32[PASE_MAX_LEVELS] = {},
         *vr32[PASE_MAX_LEVELS] = {};
   float* AinvL32 = nullptr;
+  // structured augmented eigenproblem: C0 = Phi diag(theta) Phi^T, Psi = L_B^{-T} Phi
+  bool fast = false;
+  double *theta = nullptr, *Psi = nullptr, *Gtl = nullptr, *Vtf = nullptr, *Vtf2 = nullptr, *Gf = nullptr;
+  double *rqf = nullptr, *resf = nullptr;
+  int *permf = nullptr, *statf = nullptr;
+  double small_scale = 1.0;
+  int fast_hits = 0;            // corrections solved by the structured path (this solve)
+  int last_path = 0;            // 1 accepted, 0 dense only, -1 residual/orthogonality, -2 count
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 };
@@ -112,6 +120,7 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (o->nev_max < 1 || o->nev_max > PASE_MAX_NEV) return PASE_E_ARG;
   if (o->cg_steps < 1 || o->max_outer < 0 || o->nu < 1) return PASE_E_ARG;
   if (!(o->omega > 0.0)) return PASE_E_ARG;
+  if (o->small_solver != 0 && o->small_solver != 1) return PASE_E_ARG;
   if (o->precision != PASE_PREC_FP64 && o->precision != PASE_PREC_MIXED) return PASE_E_UNSUPPORTED;
   return PASE_OK;
 }
@@ -166,9 +175,24 @@ size_t layout(pase_handle* h, void* base) {
   h->nT = (int)(NH + K);
   const size_t nT = (size_t)h->nT;
   if (h->nT <= syev_max_n() && (int)K <= syev_max_k()) {
+    h->fast = (h->opt.small_solver == 0) && (int)K <= small_fast_max_k() && (int)NH <= small_fast_max_nh();
     h->Tm = b.take<double>(nT * nT);
     h->Vs = b.take<double>(nT * K);
-    h->syw = b.take<double>(syev_work_doubles(h->nT, (int)K));
+    size_t sw = syev_work_doubles(h->nT, (int)K);
+    if (h->fast) sw = std::max(sw, syev_work_doubles((int)NH, (int)NH));   // setup: all of C0
+    h->syw = b.take<double>(sw);
+  }
+  if (h->fast) {
+    h->theta = b.take<double>(NH);
+    h->Psi = b.take<double>(NH * NH);
+    h->Gtl = b.take<double>(NH * K);
+    h->Vtf = b.take<double>(nT * K);
+    h->Vtf2 = b.take<double>(nT * K);
+    h->Gf = b.take<double>(K * K);
+    h->rqf = b.take<double>(K);
+    h->resf = b.take<double>(K);
+    h->permf = b.take<int>(K);
+    h->statf = b.take<int>(4);
   }
   h->ca = b.take<double>(NH * K);
   h->cb = b.take<double>(NH * K);
@@ -182,7 +206,7 @@ size_t layout(pase_handle* h, void* base) {
   size_t pd = 0;
   for (int k = 1; k <= (int)K; ++k) {
     pd = std::max(pd, (size_t)coldot_tiles(N0, k) * k);
-    pd = std::max(pd, (size_t)gram_tiles(N0, k) * k * k);
+    pd = std::max(pd, (size_t)2 * gram_tiles(N0, k) * k * k);
     pd = std::max(pd, (size_t)grid_launch(N0, k).blocks * 3 * k);
     if (dim == 3) pd = std::max(pd, (size_t)fine3_max_spatial_blocks(h->lev[0].m) * 3 * k);
   }
@@ -398,7 +422,7 @@ void cholqr_m(pase_handle* h, int k, double*& U, double*& spare, int slot) {
   apply_AM(h, 0, k, U, nullptr, h->W3);
   launch_gram(N, k, U, h->W3, h->partial, gram_tiles(N, k), h->kk2, s);
   launch_cholinv(k, h->kk2, h->info + slot, s);            // kk2 <- L^{-1}
-  launch_gemm(false, true, (int)N, k, k, 1.0, U, k, h->kk2, k, 0.0, spare, k, s);
+  launch_tsmm(N, k, U, h->kk2, spare, 0, 1, s);
   std::swap(U, spare);
 }
 
@@ -424,8 +448,7 @@ pase_status correction(pase_handle* h, int k) {
   // (b) projection: A W, M W, a = P^T A W, alpha = W^T A W, beta = W^T M W
   apply_AM(h, 0, k, W, h->W2, h->W3);
   restrict_all(h, k, h->W2, h->ca);
-  launch_gram(N, k, W, h->W2, h->partial, gram_tiles(N, k), h->kk1, s);   // alpha
-  launch_gram(N, k, W, h->W3, h->partial, gram_tiles(N, k), h->kk2, s);   // beta
+  launch_gram2(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
   launch_symmetrize(k, h->kk1, s);
   launch_symmetrize(k, h->kk2, s);
   launch_cholinv(k, h->kk2, h->info + 1, s);               // beta = L L^T, kk2 <- L^{-1}
@@ -434,19 +457,47 @@ pase_status correction(pase_handle* h, int k) {
   launch_gemm(false, false, k, k, k, 1.0, h->kk3, k, h->kk1, k, 0.0, h->kk4, k, s);
   launch_gemm(false, true, k, k, k, 1.0, h->kk4, k, h->kk3, k, 0.0, h->kk5, k, s);
   launch_symmetrize(k, h->kk5, s);
-  // G = LB^{-1} a Li^T
-  launch_gemm(false, false, NH, k, NH, 1.0, h->LBinv, NH, h->ca, k, 0.0, h->cb, k, s);
-  launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->cc, k, s);
   // (c) small problem
   const int nT = NH + k;
-  launch_set_diag_block(nT, NH, k, h->C0, h->cc, h->kk5, h->Tm, s);
-  launch_syev_lowest(nT, k, h->Tm, h->lam, h->Vs, h->syw, h->info + 2, s);
-  // coordinates: y_H = LB^{-T} V_H, y_W = Li^T V_W
-  launch_gemm(true, false, NH, k, NH, 1.0, h->LBinv, NH, h->Vs, k, 0.0, h->ca, k, s);
+  bool solved = false;
+  h->last_path = 0;
+  if (h->fast) {
+    // structured path in the eigenbasis of C0: Gt = Psi^T a Li^T, shifts = the current Ritz values
+    HIPC(hipMemsetAsync(h->statf, 0, 4 * sizeof(int), s));
+    launch_gemm(true, false, NH, k, NH, 1.0, h->Psi, NH, h->ca, k, 0.0, h->cb, k, s);
+    launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->Gtl, k, s);
+    const double sc = h->small_scale;
+    launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, sc, h->Vtf, h->rqf, s);
+    launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
+    launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
+    launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, 1e-11 * sc, 1e-9 * sc, h->lam, h->permf,
+                        h->statf, s);
+    int st[4];
+    HIPC(hipMemcpyAsync(st, h->statf, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    h->last_path = (st[2] != 0 || st[1] == 0) ? -1 : -2;
+    if (st[0] == 1 && st[2] == 0) {
+      h->last_path = 1;
+      launch_small_emit(nT, k, h->Vtf, h->permf, h->Vs, s);
+      // y_H = L_B^{-T} Phi V_Theta
+      launch_gemm(false, false, NH, k, NH, 1.0, h->Psi, NH, h->Vs, k, 0.0, h->ca, k, s);
+      solved = true;
+      ++h->fast_hits;
+    }
+  }
+  if (!solved) {
+    // dense path: G = LB^{-1} a Li^T, T = [[C0, G], [G^T, H]]
+    launch_gemm(false, false, NH, k, NH, 1.0, h->LBinv, NH, h->ca, k, 0.0, h->cb, k, s);
+    launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->cc, k, s);
+    launch_set_diag_block(nT, NH, k, h->C0, h->cc, h->kk5, h->Tm, s);
+    launch_syev_lowest(nT, k, h->Tm, h->lam, h->Vs, h->syw, h->info + 2, s);
+    launch_gemm(true, false, NH, k, NH, 1.0, h->LBinv, NH, h->Vs, k, 0.0, h->ca, k, s);
+  }
+  // coordinates of the W block: y_W = Li^T V_W
   launch_gemm(true, false, k, k, k, 1.0, h->kk3, k, h->Vs + (size_t)NH * k, k, 0.0, h->kk4, k, s);
   // prolongation: U = P y_H + W y_W
   prolong_all(h, k, h->ca, h->U, 0);
-  launch_gemm(false, false, (int)N, k, k, 1.0, W, k, h->kk4, k, 1.0, h->U, k, s);
+  launch_tsmm(N, k, W, h->kk4, h->U, 1, 0, s);
   return PASE_OK;
 }
 
@@ -475,6 +526,7 @@ void pase_options_default(pase_options* opt) {
   opt->max_outer = 500;
   opt->nu = 2;
   opt->omega = 2.0 / 3.0;
+  opt->small_solver = 0;
 }
 
 const char* pase_status_string(pase_status s) {
@@ -605,6 +657,13 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   launch_gemm(false, false, NH, NH, NH, 1.0, h->LBinv, NH, AL, NH, 0.0, tmp, NH, s);
   launch_gemm(false, true, NH, NH, NH, 1.0, tmp, NH, h->LBinv, NH, 0.0, h->C0, NH, s);
   launch_symmetrize(NH, h->C0, s);
+  if (h->fast) {
+    // C0 = Phi diag(theta) Phi^T (all N_H pairs, dense solver), Psi = L_B^{-T} Phi
+    HIPS(hipMemcpyAsync(h->Tm, h->C0, sizeof(double) * NH * NH, hipMemcpyDeviceToDevice, s));
+    double* Phi = h->dtmp;
+    launch_syev_lowest(NH, NH, h->Tm, h->theta, Phi, h->syw, h->info + 10, s);
+    launch_gemm(true, false, NH, NH, NH, 1.0, h->LBinv, NH, Phi, NH, 0.0, h->Psi, NH, s);
+  }
   HIPS(hipGetLastError());
   int inf[16];
   HIPS(hipMemcpyAsync(inf, h->info, sizeof(inf), hipMemcpyDeviceToHost, s));
@@ -612,6 +671,18 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   if (inf[8] || inf[9]) {
     fail(h, PASE_E_BREAKDOWN, "coarse Cholesky failed");
     return bail(PASE_E_BREAKDOWN);
+  }
+  if (h->fast) {
+    if (inf[10]) {
+      h->fast = false;   // the dense path stays available
+    } else {
+      std::vector<double> th(NH);
+      HIPS(hipMemcpyAsync(th.data(), h->theta, sizeof(double) * NH, hipMemcpyDeviceToHost, s));
+      HIPS(hipStreamSynchronize(s));
+      double mx = 1.0;
+      for (double t : th) mx = std::max(mx, std::fabs(t));
+      h->small_scale = mx;
+    }
   }
   HIPS(hipEventCreate(&h->ev0));
   HIPS(hipEventCreate(&h->ev1));
@@ -753,6 +824,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   hipStream_t s = h->stream;
   HIPC(hipEventRecord(h->ev0, s));
   HIPC(hipMemsetAsync(h->info, 0, 16 * sizeof(int), s));
+  h->fast_hits = 0;
   launch_copy((size_t)N * k, U0, h->U, s);
   // start: two passes of Cholesky-QR in M, Lambda0 = diag(U^T A U)
   for (int pass = 0; pass < 2; ++pass) cholqr_m(h, k, h->U, h->X, 3 + pass);
@@ -796,6 +868,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     if (it >= h->opt.max_outer) break;
     st = correction(h, k);
     if (st) return st;
+    if (rep && rep->small_path_host && it < h->opt.max_outer) rep->small_path_host[it] = h->last_path;
     ++it;
   }
   launch_copy((size_t)N * k, h->U, U, s);
@@ -809,6 +882,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     rep->n_converged = nconv;
     rep->ritz_history_rows = rows;
     rep->t_solve_ms = ms;
+    rep->small_fast_iters = h->fast_hits;
     if (rep->res_host) std::memcpy(rep->res_host, res.data(), sizeof(double) * k);
     if (rep->res_literal_host) std::memcpy(rep->res_literal_host, lit.data(), sizeof(double) * k);
   }

@@ -36,7 +36,7 @@ class Solver:
     """
 
     def __init__(self, dim, levels, kappa=None, nev_max=16, precision="fp64", cg_steps=2, max_outer=500,
-                 nu=2, omega=2.0 / 3.0, device="cuda:0"):
+                 nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0"):
         self.lib = nat.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
@@ -66,6 +66,7 @@ class Solver:
         opt.max_outer = int(max_outer)
         opt.nu = int(nu)
         opt.omega = float(omega)
+        opt.small_solver = {"auto": 0, "dense": 1}[small_solver]
         self.opt = opt
         nbytes = C.c_size_t(0)
         self._check(self.lib.pase_workspace_bytes(C.byref(prob), C.byref(opt), C.byref(nbytes)), None)
@@ -123,13 +124,17 @@ class Solver:
         res = np.zeros(nev)
         lit = np.zeros(nev)
         hist = np.zeros((self.opt.max_outer + 1, nev)) if history else None
+        paths = np.zeros(max(self.opt.max_outer, 1), dtype=np.int32)
         rep = nat.Report()
         rep.res_host = res.ctypes.data
         rep.res_literal_host = lit.ctypes.data
         rep.ritz_history_host = hist.ctypes.data if history else None
+        rep.small_path_host = paths.ctypes.data
         st = self.lib.pase_solve(self.h, int(nev), float(tol), _ptr(U0), lam.ctypes.data, _ptr(U), C.byref(rep))
         report = {"outer_iters": rep.outer_iters, "n_converged": rep.n_converged, "res": res,
-                  "res_literal": lit, "t_solve_ms": rep.t_solve_ms, "status": nat.STATUS.get(st, st)}
+                  "res_literal": lit, "t_solve_ms": rep.t_solve_ms, "small_fast_iters": rep.small_fast_iters,
+                  "small_path": paths[:rep.outer_iters].copy(),
+                  "status": nat.STATUS.get(st, st)}
         if history:
             report["ritz_history"] = hist[:rep.ritz_history_rows].copy()
         if st != 0 and not (st == 4 and not raise_notconv):

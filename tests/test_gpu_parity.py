@@ -290,3 +290,27 @@ def test_mixed_config2_closed_form_full_size():
     _, MU = s.apply(0, U)
     G = host(U.T.contiguous() @ MU)
     assert np.abs(G - np.eye(k)).max() < 1e-12
+
+
+# ---- structured augmented eigenproblem (shift-invert in the eigenbasis of C0) vs the dense solver
+
+@pytest.mark.parametrize("dim,levels,kseed,k,tol", [
+    (2, [128, 64, 32, 16], None, 10, 1e-10),
+    (3, [16, 8, 4], 5, 8, 1e-10),
+    (3, [32, 16, 8, 4], None, 20, 1e-9),
+])
+def test_structured_small_solver_matches_dense(dim, levels, kseed, k, tol):
+    kap = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
+    fast = Solver(dim, levels, kap, nev_max=k)
+    dense = Solver(dim, levels, kap, nev_max=k, small_solver="dense")
+    U0 = dev(synth.initial_vectors(fast.N[0], k, 1))
+    lam_f, U_f, rep_f = fast.solve(k, tol, U0)
+    lam_d, U_d, rep_d = dense.solve(k, tol, U0)
+    assert rep_d["small_fast_iters"] == 0
+    assert rep_f["small_fast_iters"] > rep_f["outer_iters"] // 2, rep_f
+    np.testing.assert_allclose(lam_f, lam_d, rtol=1e-11)
+    # rounding differences between the two small solvers shift slow convergence by a few steps
+    assert abs(rep_f["outer_iters"] - rep_d["outer_iters"]) <= max(2, rep_d["outer_iters"] // 50)
+    _, MU = fast.apply(0, U_f)
+    G = host(U_f.T.contiguous() @ MU)
+    assert np.abs(G - np.eye(k)).max() < 1e-12
