@@ -822,7 +822,7 @@ __global__ __launch_bounds__(kDenseThreads) void cholinv_kernel(int k, double* _
   if (tid == 0 && bad) *info = 1;
 }
 
-// 4b''. The same for k <= 64 with 256 threads: right-looking Cholesky with one
+// 4b'. The same for k <= 64 with 256 threads: right-looking Cholesky with one
 // barrier per pivot (16 x 16 thread tiles over the trailing triangle, column
 // scaling deferred by one step), then the inverse by columns (one thread per
 // column) into a separate LDS array, so the loads of a column's inner products
@@ -888,66 +888,6 @@ __global__ __launch_bounds__(256) void cholinv256_kernel(int k, double* __restri
     G[q] = (i >= c) ? X[c][i] : 0.0;
   }
   if (tid == 0 && bad) *info = 1;
-}
-
-// 4b'. The same for k <= 64 with one wavefront.  Lane i keeps row i of the
-// factor in registers (row[l] = L[i][l]); pivot step j broadcasts column j
-// through LDS (every lane writes its own entry), so a step costs one LDS write,
-// a broadcast read of the column and one FMA per trailing entry.  The inverse
-// is formed column by column (lane c solves L x = e_c) with L read from LDS as
-// a broadcast.  Register arrays are only indexed by unrolled constants.
-__global__ __launch_bounds__(64) void cholinv64_kernel(int k, double* __restrict__ G, int* info) {
-  __shared__ double colj[64];
-  __shared__ double Ls[64][64];
-  const int lane = threadIdx.x;
-  double row[64];
-#pragma unroll
-  for (int l = 0; l < 64; ++l) row[l] = (lane < k && l < k && l <= lane) ? G[(size_t)lane * k + l] : 0.0;
-  double dm = (lane < k) ? G[(size_t)lane * k + lane] : 0.0;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
-  const double ptol = k * DBL_EPSILON * dm;   // pivots at or below this count as rank deficiency
-  int bad = 0;
-  for (int j = 0; j < k; ++j) {
-    double rj = 0.0;                           // row[j] (unrolled select)
-#pragma unroll
-    for (int t = 0; t < 64; ++t) rj = (t == j) ? row[t] : rj;
-    colj[lane] = rj;
-    __syncthreads();
-    const double dj = colj[j];
-    const double pe = (dj > 0.0) ? dj : 1.0;
-    bad |= !(dj > ptol);
-    const double sq = sqrt(pe), rs = 1.0 / sq;
-    const double lij = (lane > j) ? rj * rs : 0.0;    // final L[lane][j]
-    const double nj = (lane == j) ? sq : ((lane > j) ? lij : rj);
-#pragma unroll
-    for (int t = 0; t < 64; ++t) {
-      // trailing update L[lane][t] -= L[lane][j] L[t][j] for j < t <= lane
-      const double upd = fma(-lij, colj[t] * rs, row[t]);
-      row[t] = (t == j) ? nj : ((t > j && t <= lane) ? upd : row[t]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int l = 0; l < 64; ++l) Ls[lane][l] = row[l];
-  __syncthreads();
-  // lane c: x = L^{-1} e_c by forward substitution; x[i] = 0 for i < c
-  double x[64];
-  const int c = lane;
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    double acc = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-    for (int l = 0; l < i; ++l) acc = fma(-Ls[i][l], x[l], acc);
-    x[i] = (i < k && i >= c) ? acc / Ls[i][i] : 0.0;
-  }
-  for (int i = 0; i < k; ++i) {
-    double xi = 0.0;
-#pragma unroll
-    for (int t = 0; t < 64; ++t) xi = (t == i) ? x[t] : xi;
-    if (c < k) G[(size_t)i * k + c] = xi;
-  }
-  if (lane == 0 && bad) *info = 1;
 }
 
 // 4c. Vo = L^{-1} Vi in the vector index: vo_j = sum_{l <= j} Li[j][l] vi_l.

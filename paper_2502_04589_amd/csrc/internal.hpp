@@ -160,9 +160,11 @@ void launch_vorth2(int n, int k, double* Vt, double* Vt2, double* G, int* info, 
 // ---- structured augmented eigenproblem (small.hip): Tt = [[diag(theta), Gt], [Gt^T, H]]
 int small_fast_max_k();
 int small_fast_max_nh();   // N_H limit
-// shift-invert / Rayleigh-quotient iteration per pair from the shifts sigma; Vt vector-major (N_H + k) x k
+// shift-invert / Rayleigh-quotient iteration per pair; start vectors: column i of X0 ((N_H + k) x k
+// row-major; first shift its Rayleigh quotient) or, if X0 is null, a fixed pseudo-random vector with
+// first shift sigma[i]; Vt vector-major (N_H + k) x k
 void launch_small_rqi(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* sigma,
-                      double scale, double* Vt, double* rq, hipStream_t s);
+                      const double* X0, double scale, double* Vt, double* rq, hipStream_t s);
 // Rayleigh quotients and residual norms of the columns of an orthonormal Vt
 void launch_small_rr(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
                      double* rq, double* res, hipStream_t s);

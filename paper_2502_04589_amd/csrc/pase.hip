@@ -81,6 +81,7 @@ struct pase_handle {
   bool fast = false;
   double *theta = nullptr, *Psi = nullptr, *Gtl = nullptr, *Vtf = nullptr, *Vtf2 = nullptr, *Gf = nullptr;
   double *rqf = nullptr, *resf = nullptr;
+  double *cmw = nullptr, *kkb = nullptr, *X0f = nullptr;   // P^T M W, beta, start block
   int *permf = nullptr, *statf = nullptr;
   double small_scale = 1.0;
   int fast_hits = 0;            // corrections solved by the structured path (this solve)
@@ -191,6 +192,9 @@ size_t layout(pase_handle* h, void* base) {
     h->Gf = b.take<double>(K * K);
     h->rqf = b.take<double>(K);
     h->resf = b.take<double>(K);
+    h->cmw = b.take<double>(NH * K);
+    h->kkb = b.take<double>(K * K);
+    h->X0f = b.take<double>(nT * K);
     h->permf = b.take<int>(K);
     h->statf = b.take<int>(4);
   }
@@ -445,12 +449,14 @@ pase_status correction(pase_handle* h, int k) {
   restrict_all(h, k, h->W3, h->ca);
   launch_gemm(false, false, NH, k, NH, 1.0, h->BHinv, NH, h->ca, k, 0.0, h->cb, k, s);
   prolong_all(h, k, h->cb, W, 2);
+  if (h->fast) launch_copy((size_t)NH * k, h->ca, h->cmw, s);   // P^T M W: W's coarse coordinates
   // (b) projection: A W, M W, a = P^T A W, alpha = W^T A W, beta = W^T M W
   apply_AM(h, 0, k, W, h->W2, h->W3);
   restrict_all(h, k, h->W2, h->ca);
   launch_gram2(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
   launch_symmetrize(k, h->kk1, s);
   launch_symmetrize(k, h->kk2, s);
+  if (h->fast) launch_copy((size_t)k * k, h->kk2, h->kkb, s);
   launch_cholinv(k, h->kk2, h->info + 1, s);               // beta = L L^T, kk2 <- L^{-1}
   launch_copy((size_t)k * k, h->kk2, h->kk3, s);           // Li
   // H = Li alpha Li^T
@@ -466,8 +472,11 @@ pase_status correction(pase_handle* h, int k) {
     HIPC(hipMemsetAsync(h->statf, 0, 4 * sizeof(int), s));
     launch_gemm(true, false, NH, k, NH, 1.0, h->Psi, NH, h->ca, k, 0.0, h->cb, k, s);
     launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->Gtl, k, s);
+    // start block: the coordinates of W in the new basis, [Psi^T P^T M W ; L^T] (L^T = L^{-1} beta)
+    launch_gemm(true, false, NH, k, NH, 1.0, h->Psi, NH, h->cmw, k, 0.0, h->X0f, k, s);
+    launch_gemm(false, false, k, k, k, 1.0, h->kk3, k, h->kkb, k, 0.0, h->X0f + (size_t)NH * k, k, s);
     const double sc = h->small_scale;
-    launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, sc, h->Vtf, h->rqf, s);
+    launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, h->Vtf, h->rqf, s);
     launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
     launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
     launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, 1e-11 * sc, 1e-9 * sc, h->lam, h->permf,

@@ -198,12 +198,12 @@ __device__ void colsum_r(int nH, int k, const double* g, double w, RLds& L, doub
 }
 
 // In-place LU with partial pivoting of L.S (k x k): U in L.S (upper), unit-lower
-// multipliers in L.M, ipiv[j] = row exchanged with j.  Two barriers per pivot.
+// multipliers in L.M, ipiv[j] = row exchanged with j.  Two barriers per pivot;
+// every wave finds the pivot itself (same data, same order, same result).
 __device__ void lu_factor_r(int k, RLds& L) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int tx = tid & 15, ty = tid >> 4;   // 16 x 32
   for (int j = 0; j < k; ++j) {
-    // every wave finds the pivot (same data, same order: same result)
     double c = (lane >= j && lane < k) ? fabs(L.S[lane][j]) : -1.0;
     int p = lane;
 #pragma unroll
@@ -268,8 +268,8 @@ __device__ double lu_solve_wave(int k, const RLds& L, double b) {
 // Output: unit vector Vt[i*n .. i*n+n) (n = N_H + k) and its Rayleigh quotient.
 __global__ __launch_bounds__(kRT) void srqi_kernel(int nH, int k, const double* __restrict__ theta,
                                                  const double* __restrict__ Gt, const double* __restrict__ Hm,
-                                                 const double* __restrict__ sigma, double scale,
-                                                 double* __restrict__ Vt, double* __restrict__ rq) {
+                                                 const double* __restrict__ sigma, const double* __restrict__ X0,
+                                                 double scale, double* __restrict__ Vt, double* __restrict__ rq) {
   __shared__ RLds L;
   const int i = blockIdx.x;
   const int n = nH + k;
@@ -279,20 +279,35 @@ __global__ __launch_bounds__(kRT) void srqi_kernel(int nH, int k, const double* 
   const double th = (tid < nH) ? theta[tid] : 0.0;
   double nx = 0.0;
   for (int r = tid; r < n; r += kRT) {
-    const double v = hash_pm1((unsigned)i + 1u, (unsigned)r);
+    const double v = X0 ? X0[(size_t)r * k + i] : hash_pm1((unsigned)i + 1u, (unsigned)r);
     L.xs[r] = v;
     nx = fma(v, v, nx);
   }
   nx = bsum(nx, L.red);
   const double inx = 1.0 / sqrt(nx);
   for (int r = tid; r < n; r += kRT) L.xs[r] *= inx;
-  double mu = sigma[i], rho = mu;
+  double mu = sigma[i];
+  if (X0) {
+    // first shift: Rayleigh quotient of the start vector, x^T Tt x
+    __syncthreads();
+    const double xj0 = (tid < nH) ? L.xs[tid] : 0.0;
+    double part = 0.0;
+    if (tid < nH) part = xj0 * fma(th, xj0, 2.0 * rowdot(g, L.xs + nH));
+    if (tid < k) {
+      double hx = 0.0;
+      for (int b = 0; b < k; ++b) hx = fma(Hm[(size_t)tid * k + b], L.xs[nH + b], hx);
+      part = fma(L.xs[nH + tid], hx, part);
+    }
+    mu = bsum(part, L.red);
+  }
+  double rho = mu;
   double dv = (tid < nH) ? 1.0 / (th - mu) : 0.0;
   form_schur_r(nH, k, g, dv, Hm, mu, L);
   lu_factor_r(k, L);
   int nfac = 1, since = 0;
+  const int hold = X0 ? 1 : 2;               // solves per factorisation before a new shift
   for (int it = 0; it < kMaxSolve; ++it) {
-    if (since >= 2 && nfac < kMaxFactor) {   // Rayleigh-quotient shift
+    if (since >= hold && nfac < kMaxFactor) {   // Rayleigh-quotient shift
       mu = rho;
       dv = (tid < nH) ? 1.0 / (th - mu) : 0.0;
       form_schur_r(nH, k, g, dv, Hm, mu, L);
@@ -488,8 +503,8 @@ int small_fast_max_k() { return kSK; }
 int small_fast_max_nh() { return kRMaxH; }
 
 void launch_small_rqi(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* sigma,
-                      double scale, double* Vt, double* rq, hipStream_t s) {
-  srqi_kernel<<<k, kRT, 0, s>>>(nH, k, theta, Gt, Hm, sigma, scale, Vt, rq);
+                      const double* X0, double scale, double* Vt, double* rq, hipStream_t s) {
+  srqi_kernel<<<k, kRT, 0, s>>>(nH, k, theta, Gt, Hm, sigma, X0, scale, Vt, rq);
 }
 
 void launch_small_rr(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
