@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="laplace3d-64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="time the plain FP64 form only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -115,29 +116,39 @@ def main():
 
     dim, levels, nev, tol, kseed = WORKLOADS[args.workload]
     kappa = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
-    t0 = time.perf_counter()
-    s = Solver(dim, levels, kappa, nev_max=nev)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    U0h = synth.initial_vectors(s.N[0], nev, 0)
-    U0 = torch.from_numpy(U0h).cuda()
-    torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
-        s.solve(nev, tol, U0)
-    torch.cuda.synchronize()
-    conv = 0
-    iters = []
-    fast = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        lam, U, rep = s.solve(nev, tol, U0)
-        conv += rep["n_converged"]
-        iters.append(rep["outer_iters"])
-        fast.append(rep["small_fast_iters"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = conv / dt
+    def run_form(precision):
+        t0 = time.perf_counter()
+        s = Solver(dim, levels, kappa, nev_max=nev, precision=precision)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        U0h = synth.initial_vectors(s.N[0], nev, 0)
+        U0 = torch.from_numpy(U0h).cuda()
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            s.solve(nev, tol, U0)
+        torch.cuda.synchronize()
+        conv, iters, fast = 0, [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lam, U, rep = s.solve(nev, tol, U0)
+            conv += rep["n_converged"]
+            iters.append(rep["outer_iters"])
+            fast.append(rep["small_fast_iters"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = None
+        if kseed is None:
+            from tests.closed_form import q1_laplace_eigs
+            err = float(np.max(np.abs(lam / q1_laplace_eigs(dim, levels[0], nev) - 1.0)))
+        return s, U0h, {"value": conv / dt, "ms_per_step": dt / args.steps * 1e3, "outer_iters": iters[-1],
+                        "small_structured_iters": fast[-1], "setup_s": round(setup_s, 3),
+                        "max_rel_err_vs_closed_form": err, "max_res": float(np.max(rep["res"]))}
+
+    s, U0h, plain = run_form("fp64")
+    mixed = None if args.no_mixed else run_form("mixed")[2]
+    value = plain["value"]
+    iters = [plain["outer_iters"]]
 
     # dominant kernel vs HBM roofline, timed live with HIP events on the solver's stream
     ms = s.time_kernel("sweep", nev, reps=50)
@@ -150,7 +161,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": plain["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -159,11 +170,15 @@ def main():
         "config": {
             "workload": f"{args.workload}: {dim}D Q1 Laplace, {levels[0]}^{dim} mesh "
                         f"({s.N[0]} DOFs), V_H {levels[-1]}^{dim} ({s.N[-1]} DOFs), GMG levels "
-                        f"{'/'.join(map(str, levels))}, nev {nev}, tol {tol:g}, 2 CG steps, plain FP64",
-            "dofs": s.N[0], "nev": nev, "tol": tol, "outer_iters": iters[-1],
-            "small_structured_iters": fast[-1],
-            "setup_s": round(setup_s, 3),
-            "max_rel_err_vs_closed_form": None,
+                        f"{'/'.join(map(str, levels))}, nev {nev}, tol {tol:g}, 2 CG steps; value = plain FP64 form",
+            "dofs": s.N[0], "nev": nev, "tol": tol,
+        },
+        "forms": {
+            "fp64": plain,
+            "mixed": mixed,
+            "mixed_over_fp64": None if mixed is None else mixed["value"] / plain["value"],
+            "mixed_note": "FP32 correction-equation CG and V-cycle over FP64 master vectors; FP64 projection, "
+                          "Cholesky-QR and small eigenproblem",
         },
         "roofline": {
             "kernel": "fine-level damped-Jacobi sweep (fine3v_kernel<double, SWEEP>, LDS-staged 3D Q1 stencil)",
@@ -177,13 +192,6 @@ def main():
             "algorithmic_bytes_per_launch": nbytes,
         },
     }
-    try:
-        from tests.closed_form import q1_laplace_eigs
-        if kseed is None:
-            out["config"]["max_rel_err_vs_closed_form"] = float(
-                np.max(np.abs(lam / q1_laplace_eigs(dim, levels[0], nev) - 1.0)))
-    except Exception:
-        pass
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dim, levels, nev, tol, U0h, iters[-1])
     print(json.dumps(out), flush=True)

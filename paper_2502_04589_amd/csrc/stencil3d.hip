@@ -49,41 +49,42 @@ __device__ __forceinline__ double kpat(double k0, double k1, double m0, double m
   return kx * my * mz + mx * ky * mz + mx * my * kz;
 }
 
-// 16-byte vector of a thread's VW consecutive columns
-template <typename T> struct Vec;
-template <> struct Vec<double> { typedef double2 type; static constexpr int n = 2; };
-template <> struct Vec<float> { typedef float4 type; static constexpr int n = 4; };
+// vector of a thread's VW consecutive columns: double2 (16 bytes), float2 (8 bytes, k even)
+// or float4 (16 bytes, k a multiple of 4)
+template <typename T, int W> struct Vec;
+template <> struct Vec<double, 2> { typedef double2 type; static constexpr int n = 2; };
+template <> struct Vec<float, 2> { typedef float2 type; static constexpr int n = 2; };
+template <> struct Vec<float, 4> { typedef float4 type; static constexpr int n = 4; };
 
-template <typename T>
-__device__ __forceinline__ double vget(const typename Vec<T>::type& v, int i) {
-  if constexpr (Vec<T>::n == 2) return i == 0 ? v.x : v.y;
+template <typename T, int W>
+__device__ __forceinline__ double vget(const typename Vec<T, W>::type& v, int i) {
+  if constexpr (W == 2) return i == 0 ? (double)v.x : (double)v.y;
   else return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
-template <typename T>
-__device__ __forceinline__ void vset(typename Vec<T>::type& v, int i, double x) {
-  if constexpr (Vec<T>::n == 2) { if (i == 0) v.x = x; else v.y = x; }
+template <typename T, int W>
+__device__ __forceinline__ void vset(typename Vec<T, W>::type& v, int i, double x) {
+  if constexpr (W == 2) { if (i == 0) v.x = (T)x; else v.y = (T)x; }
   else { if (i == 0) v.x = (float)x; else if (i == 1) v.y = (float)x; else if (i == 2) v.z = (float)x; else v.w = (float)x; }
 }
 
 constexpr int kSlots = 4;             // LDS ring: planes z-1, z, z+1 and the one being filled
 
-template <typename T, int BX, int BY>
+template <typename T, int W, int BX, int BY>
 struct Fine3SmemV {
-  typedef typename Vec<T>::type V;
+  typedef typename Vec<T, W>::type V;
   union {
     V xs[kSlots][BY + 2][BX + 2][4];
-    double red[3][BX * BY * 4 * Vec<T>::n];
+    double red[3][BX * BY * 4 * W];
   };
 };
 
-template <typename T, int EPI, bool CONSTK, bool VEC, int BX, int BY>
+template <typename T, int VW, int EPI, bool CONSTK, bool VEC, int BX, int BY>
 __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
   constexpr int TX = BX, TY = BY;
   constexpr int kThreadsV = BX * BY * 4;    // (node, column vector) pairs of a tile
-  typedef typename Vec<T>::type V;
-  constexpr int VW = Vec<T>::n;
+  typedef typename Vec<T, VW>::type V;
   constexpr int KC = 4 * VW;                 // columns per block
-  __shared__ Fine3SmemV<T, BX, BY> sm;
+  __shared__ Fine3SmemV<T, VW, BX, BY> sm;
   const int m = a.m, n = m + 1, k = a.k;
   const int ntx = (m + TX - 1) / TX;
   const int nty = (m + TY - 1) / TY;
@@ -110,7 +111,6 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
   const int gx = tx0 + lx, gy = ty0 + ly;
   const int colv = c0 + qv * VW;             // first column of this thread
   const bool nodeok = (gx < m) && (gy < m);
-  constexpr bool vecok = VEC;                // k % VW == 0: rows are 16-byte aligned
   const T* __restrict__ X = (const T*)a.x;
 
   // halo plane: (TX+2)(TY+2) nodes x 4 vectors = 400 vectors; thread owns entries tid and
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
         const int cq = ((tid + u * kThreadsV) & 3);
         const bool oki = ok && (c0 + cq * VW + i < k);
         const T* p = oki ? X + z * plane + hoff[u] + i : (const T*)zerov;
-        vset<T>(v, i, (double)*p);
+        vset<T, VW>(v, i, (double)*p);
       }
       return v;
     }
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
       for (int i = 0; i < VW; ++i) {
         const bool oki = ok && colv + i < k;
         const T* p = oki ? B + z * plane + cbase + i : (const T*)zerov;
-        vset<T>(v, i, (double)*p);
+        vset<T, VW>(v, i, (double)*p);
       }
       return v;
     }
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
     } else {
 #pragma unroll
       for (int i = 0; i < VW; ++i)
-        if (colv + i < k) base[off + i] = (T)vget<T>(v, i);
+        if (colv + i < k) base[off + i] = (T)vget<T, VW>(v, i);
     }
   };
   auto kap = [&](int ex, int ey, int ez) -> double {
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
     }                                                                                              \
     if (needM) mp = (double)(((OX) == 0 ? 4 : 1) * ((OY) == 0 ? 4 : 1) * ((OZ) == 0 ? 4 : 1)) * mc3; \
     _Pragma("unroll") for (int i = 0; i < VW; ++i) {                                               \
-      const double xv = vget<T>(v, i);                                                             \
+      const double xv = vget<T, VW>(v, i);                                                             \
       if ((OX) == 0 && (OY) == 0 && (OZ) == 0) center[i] = xv;                                     \
       if (needA) ax[i] = fma(coef, xv, ax[i]);                                                     \
       if (needM) mx[i] = fma(mp, xv, mx[i]);                                                       \
@@ -279,23 +279,23 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
     V o1, o2;
     if (EPI == EPI_AM) {
 #pragma unroll
-      for (int i = 0; i < VW; ++i) { vset<T>(o1, i, ax[i]); vset<T>(o2, i, mx[i]); }
+      for (int i = 0; i < VW; ++i) { vset<T, VW>(o1, i, ax[i]); vset<T, VW>(o2, i, mx[i]); }
       if (a.out1) stvec((T*)a.out1, off, o1);
       if (a.out2) stvec((T*)a.out2, off, o2);
     } else if (EPI == EPI_RESID) {
 #pragma unroll
-      for (int i = 0; i < VW; ++i) vset<T>(o1, i, vget<T>(bv, i) - ax[i]);
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, vget<T, VW>(bv, i) - ax[i]);
       stvec((T*)a.out1, off, o1);
     } else if (EPI == EPI_SWEEP) {
       const double wd = a.omega / dcoef;
 #pragma unroll
-      for (int i = 0; i < VW; ++i) vset<T>(o1, i, center[i] + wd * (vget<T>(bv, i) - ax[i]));
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, center[i] + wd * (vget<T, VW>(bv, i) - ax[i]));
       stvec((T*)a.out1, off, o1);
     } else {
 #pragma unroll
       for (int i = 0; i < VW; ++i) {
         const double r = lamc[i] * mx[i] - ax[i];
-        vset<T>(o1, i, r);
+        vset<T, VW>(o1, i, r);
         acc0[i] = fma(r, r, acc0[i]);
         acc1[i] = fma(mx[i], mx[i], acc1[i]);
         acc2[i] = fma(center[i], mx[i], acc2[i]);
@@ -338,30 +338,41 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
 
 static int g_tile = 1;   // 0: 16 x 8, 1: 8 x 8 (default), 2: 16 x 16
 
-template <typename T, int EPI, bool CONSTK, bool VEC>
+template <typename T, int VW, int EPI, bool CONSTK, bool VEC>
 void launchv_tile(const Fine3Args& a, hipStream_t s) {
-  constexpr int KC = 4 * Vec<T>::n;
+  constexpr int KC = 4 * VW;
   auto go = [&](auto bx, auto by) {
     constexpr int BX = decltype(bx)::value, BY = decltype(by)::value;
     const int ntx = (a.m + BX - 1) / BX, nty = (a.m + BY - 1) / BY, nch = (a.k + KC - 1) / KC;
     const int total = ntx * nty * a.nzc * nch;
     const int blocks = ((total + 7) / 8) * 8;
-    fine3v_kernel<T, EPI, CONSTK, VEC, BX, BY><<<blocks, BX * BY * 4, 0, s>>>(a);
+    fine3v_kernel<T, VW, EPI, CONSTK, VEC, BX, BY><<<blocks, BX * BY * 4, 0, s>>>(a);
   };
   if (g_tile == 1) go(std::integral_constant<int, 8>(), std::integral_constant<int, 8>());
   else if (g_tile == 2) go(std::integral_constant<int, 16>(), std::integral_constant<int, 16>());
   else go(std::integral_constant<int, 16>(), std::integral_constant<int, 8>());
 }
 
+template <typename T, int VW, int EPI>
+void launchv_w(const Fine3Args& a, hipStream_t s) {
+  const bool vec = (a.k % VW) == 0;
+  if (a.kappa) {
+    if (vec) launchv_tile<T, VW, EPI, false, true>(a, s);
+    else launchv_tile<T, VW, EPI, false, false>(a, s);
+  } else {
+    if (vec) launchv_tile<T, VW, EPI, true, true>(a, s);
+    else launchv_tile<T, VW, EPI, true, false>(a, s);
+  }
+}
+
+// double: double2 vectors; float: float4 when k is a multiple of 4, else float2
 template <typename T, int EPI>
 void launchv(const Fine3Args& a, hipStream_t s) {
-  const bool vec = (a.k % Vec<T>::n) == 0;
-  if (a.kappa) {
-    if (vec) launchv_tile<T, EPI, false, true>(a, s);
-    else launchv_tile<T, EPI, false, false>(a, s);
+  if constexpr (sizeof(T) == 8) {
+    launchv_w<T, 2, EPI>(a, s);
   } else {
-    if (vec) launchv_tile<T, EPI, true, true>(a, s);
-    else launchv_tile<T, EPI, true, false>(a, s);
+    if (a.k % 4 == 0) launchv_w<T, 4, EPI>(a, s);
+    else launchv_w<T, 2, EPI>(a, s);
   }
 }
 
