@@ -242,11 +242,14 @@ StencilArgs stencil_args(pase_handle* h, int l, int k) {
 // LDS-staged kernel, 2D problems and coarse levels the generic one.
 void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void* b, void* out1, void* out2,
                 int fp32 = 0) {
-  if (l == 0 && h->dim == 3) {
+  // 3D: the LDS-tiled stencil on the fine level, and on every level when kappa = 1 (nested Q1
+  // spaces with exact integration: the Galerkin operator P^T A P equals the Q1 stencil of the
+  // coarse mesh, so the constant stencil of width h_l applies it)
+  if (h->dim == 3 && (l == 0 || h->kappa_is_one)) {
     Fine3Args f{};
-    f.m = h->lev[0].m;
+    f.m = h->lev[l].m;
     f.k = k;
-    f.h = h->lev[0].h;
+    f.h = h->lev[l].h;
     f.kappa = h->kappa_is_one ? nullptr : h->kappa;
     f.x = x;
     f.b = b;

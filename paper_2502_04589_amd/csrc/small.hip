@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kRT) void srqi_kernel(int nH, int k, const double* 
   form_schur_r(nH, k, g, dv, Hm, mu, L);
   lu_factor_r(k, L);
   int nfac = 1, since = 0;
-  const int hold = X0 ? 1 : 2;               // solves per factorisation before a new shift
+  const int hold = X0 ? 3 : 2;               // solves per factorisation before a new shift
   for (int it = 0; it < kMaxSolve; ++it) {
     if (since >= hold && nfac < kMaxFactor) {   // Rayleigh-quotient shift
       mu = rho;

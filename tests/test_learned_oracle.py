@@ -1,0 +1,152 @@
+"""Pins of the learned-preconditioner oracle (oracle/unet.py), CPU only.
+
+Every check compares the oracle with something other than itself: explicit
+loops, central finite differences, adjoint identities, a closed-form Adam step,
+and the plain PCG of oracle/pase.py.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import multigrid, pase, unet
+
+
+def conv_loops(x, w, m):
+    """conv3d written as plain loops over nodes, offsets and channels."""
+    B, N, cin = x.shape
+    out = np.zeros((B, N, w.shape[2]))
+    for b in range(B):
+        for z in range(m):
+            for y in range(m):
+                for xx in range(m):
+                    n = xx + m * (y + m * z)
+                    for o in range(27):
+                        dx, dy, dz = o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1
+                        X, Y, Z = xx + dx, y + dy, z + dz
+                        if 0 <= X < m and 0 <= Y < m and 0 <= Z < m:
+                            out[b, n] += x[b, X + m * (Y + m * Z)] @ w[o]
+    return out
+
+
+def test_conv3d_matches_loops():
+    rng = np.random.default_rng(0)
+    m = 4
+    x = rng.standard_normal((2, m ** 3, 3))
+    w = rng.standard_normal((27, 3, 5))
+    np.testing.assert_allclose(unet.conv3d(x, w, m), conv_loops(x, w, m), rtol=1e-13, atol=1e-12)
+
+
+def test_conv3d_backward_adjoint_and_fd():
+    rng = np.random.default_rng(1)
+    m = 5
+    x = rng.standard_normal((2, m ** 3, 3))
+    w = rng.standard_normal((27, 3, 4))
+    d = rng.standard_normal((2, m ** 3, 4))
+    dx, dw = unet.conv3d_backward(x, w, d, m)
+    # adjoint: <conv(x, w), d> = <x, dX> = <w, dW> (the map is linear in x and in w)
+    lhs = np.sum(unet.conv3d(x, w, m) * d)
+    assert abs(lhs - np.sum(x * dx)) <= 1e-11 * abs(lhs)
+    assert abs(lhs - np.sum(w * dw)) <= 1e-11 * abs(lhs)
+    # central differences on a few entries
+    eps = 1e-6
+    for (o, ci, co) in [(0, 0, 0), (13, 2, 3), (26, 1, 2)]:
+        wp, wm = w.copy(), w.copy()
+        wp[o, ci, co] += eps
+        wm[o, ci, co] -= eps
+        fd = (np.sum(unet.conv3d(x, wp, m) * d) - np.sum(unet.conv3d(x, wm, m) * d)) / (2 * eps)
+        assert abs(fd - dw[o, ci, co]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_unet_gradient_matches_finite_differences():
+    """Loss gradient through every layer (tiny mesh n = 8, channels 2/4/8)."""
+    net = unet.UNet(8, channels=(2, 4, 8))
+    W = net.init(3)
+    N = net.m[0] ** 3
+    rng = np.random.default_rng(4)
+    R = rng.standard_normal((N, 2))
+    C = rng.standard_normal((N, 2))
+    logk = rng.standard_normal(N) * 0.3
+    L, G = unet.loss_and_grad(net, W, R, C, logk)
+    eps = 1e-6
+    for layer in range(11):
+        for _ in range(2):
+            idx = tuple(int(rng.integers(0, s)) for s in W[layer].shape)
+            Wp = [w.copy() for w in W]
+            Wm = [w.copy() for w in W]
+            Wp[layer][idx] += eps
+            Wm[layer][idx] -= eps
+            fd = (unet.loss_and_grad(net, Wp, R, C, logk)[0] - unet.loss_and_grad(net, Wm, R, C, logk)[0]) / (2 * eps)
+            assert abs(fd - G[layer][idx]) <= 1e-6 * max(1e-3, abs(fd)), (layer, idx, fd, G[layer][idx])
+
+
+def test_network_output_scales_with_the_residual():
+    net = unet.UNet(8, channels=(2, 4, 8))
+    W = net.init(5)
+    rng = np.random.default_rng(6)
+    R = rng.standard_normal((net.m[0] ** 3, 3))
+    logk = np.zeros(net.m[0] ** 3)
+    Z = net.apply(W, R, logk)
+    np.testing.assert_allclose(net.apply(W, 7.5 * R, logk), 7.5 * Z, rtol=1e-13, atol=1e-14)
+
+
+def test_node_log_kappa():
+    n = 4
+    assert np.allclose(unet.node_log_kappa(n, np.full(n ** 3, 2.0)), np.log(2.0))
+    kap = np.exp(synth.kappa_field(3, n, 2) * 0 + np.arange(n ** 3) % 5)     # log kappa = element index mod 5
+    lk = np.log(kap).reshape(n, n, n)
+    node = unet.node_log_kappa(n, kap).reshape(n - 1, n - 1, n - 1)
+    # node (x=1, y=0, z=2) sits between elements x in {1,2}, y in {0,1}, z in {2,3}
+    assert np.isclose(node[2, 0, 1], lk[2:4, 0:2, 1:3].mean())
+
+
+def test_adam_first_step_closed_form():
+    g = np.array([[0.5, -2.0, 1e-3]])
+    opt = unet.Adam([g.shape], lr=1e-2)
+    W = opt.step([np.zeros_like(g)], [g])
+    # t = 1: bias-corrected m = g, v = g^2, so the step is -lr g / (|g| + eps)
+    np.testing.assert_allclose(W[0], -1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-14)
+    # second step with the same gradient: m_hat = g, v_hat = g^2 again
+    W = opt.step(W, [g])
+    np.testing.assert_allclose(W[0], -2e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def _setup(n=8):
+    H = multigrid.Hierarchy(3, [n, n // 2, n // 4])
+    N = H.A[0].shape[0]
+    U = pase.cholqr_m(synth.initial_vectors(N, 3, 7), H.M[0])
+    lam = np.einsum("ij,ij->j", U, H.A[0] @ U)
+    return H, U, (H.M[0] @ U) * lam
+
+
+def test_flexible_pcg_with_the_vcycle_equals_pcg():
+    """With a fixed SPD preconditioner the flexible beta equals the standard one."""
+    H, U, rhs = _setup()
+    x, on = unet.flexible_pcg(H, rhs, U, 3, lambda R, cols: H.vcycle(R))
+    np.testing.assert_allclose(x, pase.pcg(H, rhs, U, 3), rtol=0, atol=1e-11 * np.abs(x).max())
+    assert on.all()
+
+
+def test_zero_network_falls_back_to_the_vcycle():
+    """A network that returns zero makes no progress, trips the 0.5 test at step 1, and
+    the remaining steps are V-cycle PCG from the unchanged iterate."""
+    H, U, rhs = _setup()
+    x, on = unet.flexible_pcg(H, rhs, U, 3, lambda R, cols: np.zeros_like(R))
+    assert not on.any()
+    np.testing.assert_allclose(x, pase.pcg(H, rhs, U, 2), rtol=0, atol=1e-11 * np.abs(x).max())
+
+
+def test_training_reduces_the_loss():
+    """Sixty Adam steps on (r, V(r)) pairs lower the relative loss (tiny network)."""
+    H = multigrid.Hierarchy(3, [8, 4, 2])
+    net = unet.UNet(8, channels=(2, 4, 8))
+    W = net.init(0)
+    N = net.m[0] ** 3
+    R = np.random.default_rng(8).standard_normal((N, 4))
+    C = H.vcycle(R)
+    logk = np.zeros(N)
+    opt = unet.Adam(net.shapes, lr=3e-3)
+    L0 = unet.loss_and_grad(net, W, R, C, logk)[0]
+    for _ in range(60):
+        L, G = unet.loss_and_grad(net, W, R, C, logk)
+        W = opt.step(W, G)
+    assert unet.loss_and_grad(net, W, R, C, logk)[0] < 0.6 * L0
