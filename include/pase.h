@@ -101,9 +101,11 @@ typedef struct pase_report {
   int* small_path_host;          /* max_outer: per correction, 1 = structured path accepted, 0 = dense
                                     only, -1 = rejected (residual or orthogonality), -2 = rejected by the
                                     eigenvalue count */
+  int learned_fallbacks;         /* learned form: column switches to the V-cycle, summed over the solve */
 } pase_report;
 
 typedef struct pase_handle pase_handle;
+typedef struct pase_unet pase_unet;
 
 /* ---------------------------------------------------------------- core API */
 
@@ -177,6 +179,59 @@ pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* 
  *   which = 3: one V-cycle (all levels)
  *   which = 4: one full correction (Alg. 3 steps 3-6) */
 pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double* ms);
+
+/* ---------------------------------------------------------------- learned preconditioner
+ * The learned form of the method (an extension the paper does not define) replaces the
+ * V-cycle inside the fine-grid PCG by a small 3D convolutional network N trained on the
+ * solver's own (residual, V-cycle correction) pairs, with the V-cycle as fallback.
+ * Network: 3-level U-Net on the interior nodes of the fine n^3 mesh (n divisible by 4),
+ * channels {16, 32, 64} (the only set the kernels are built for); per level two 3x3x3
+ * convolutions without bias, each followed by ReLU; full-weighting restriction down,
+ * trilinear prolongation up, skip connections by channel concatenation, final 3x3x3
+ * convolution to one channel.  Inputs: r / ||r||_2 and the node average of log kappa;
+ * N(r) = ||r||_2 net(r / ||r||, log kappa).  BF16 weights and activations on MFMA with
+ * FP32 accumulation; FP32 master weights and Adam moments.
+ *
+ * Parameters: 11 FP32 tensors W_i[27][Cin][Cout] (offset o = 0..26 enumerates (dx, dy, dz)
+ * in {-1,0,1}^3 with dx fastest) concatenated in layer order: 2->16, 16->16, 16->32,
+ * 32->32, 32->64, 64->64, (64+32)->32, 32->32, (32+16)->16, 16->16, 16->1; concatenated
+ * inputs list the up-sampled channels first.
+ * Multi-vectors R, C, Z are device FP64, N_0 x batch, node-major (row = node, x fastest);
+ * logk is device FP64 N_0 (or NULL for kappa = 1).  Errors: PASE_E_ARG for bad shapes,
+ * PASE_E_NOMEM for a small workspace, PASE_E_HIP for runtime failures. */
+pase_status pase_unet_param_count(const int* channels, size_t* count);
+pase_status pase_unet_workspace_bytes(int n, int batch_max, const int* channels, size_t* bytes);
+/* The network lives in the caller's device workspace (256-byte aligned); its work is
+ * enqueued on `stream`.  Weights are undefined until pase_unet_set_weights. */
+pase_status pase_unet_create(int n, int batch_max, const int* channels, void* workspace, size_t bytes,
+                             void* stream, pase_unet** out);
+pase_status pase_unet_destroy(pase_unet* u);
+const char* pase_unet_last_error(const pase_unet* u);
+/* W: device FP32 parameter vector (pase_unet_param_count entries); resets the Adam state. */
+pase_status pase_unet_set_weights(pase_unet* u, const float* W);
+pase_status pase_unet_get_weights(const pase_unet* u, float* W);
+/* Z = N(R), column by column. */
+pase_status pase_unet_apply(pase_unet* u, int batch, const double* R, const double* logk, double* Z);
+/* Loss L = mean_b ||N(r_b) - c_b||^2 / ||c_b||^2 (written to *loss_host if non-NULL, which
+ * synchronises the stream) and its gradient with respect to the parameters, kept for
+ * pase_unet_adam_step and copied to the device vector G if non-NULL. */
+pase_status pase_unet_loss_grad(pase_unet* u, int batch, const double* R, const double* C, const double* logk,
+                                double* loss_host, float* G);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the gradient of the last loss_grad. */
+pase_status pase_unet_adam_step(pase_unet* u, float lr);
+
+/* Learned form: attaches a network (created for this fine mesh, batch_max >= nev_max) to a
+ * 3D handle set up with precision PASE_PREC_LEARNED.  The network's work then runs on the
+ * handle's stream.  In every outer step the s CG steps become flexible PCG preconditioned
+ * by the network; a column whose residual norm does not drop below half its previous value
+ * switches to the V-cycle for the rest of that outer step (the step is kept). */
+pase_status pase_attach_unet(pase_handle* h, pase_unet* u);
+/* Training pairs for the network: R = Lambda M U - A U for the pairs (lambda_host, U) and
+ * V = one V-cycle applied to R (device N_0 x k each). */
+pase_status pase_harvest(pase_handle* h, int k, const double* lambda_host, const double* U, double* R, double* V);
+/* Node average of log kappa over the elements around each interior fine node (device N_0;
+ * zeros for kappa = 1): the network's second input channel. */
+pase_status pase_node_logk(pase_handle* h, double* logk);
 
 #ifdef __cplusplus
 }

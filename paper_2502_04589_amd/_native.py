@@ -53,6 +53,18 @@ SIGNATURES = [
     ("pase_small_eig_max_n", C.c_int, [C.c_void_p]),
     ("pase_correction", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     ("pase_time_kernel", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]),
+    ("pase_unet_param_count", C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
+    ("pase_unet_workspace_bytes", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
+    ("pase_unet_create", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_void_p, C.c_size_t, C.c_void_p,
+                                   C.POINTER(C.c_void_p)]),
+    ("pase_unet_destroy", C.c_int, [C.c_void_p]),
+    ("pase_unet_last_error", C.c_char_p, [C.c_void_p]),
+    ("pase_unet_set_weights", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pase_unet_get_weights", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pase_unet_apply", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pase_unet_loss_grad", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(C.c_double), C.c_void_p]),
+    ("pase_unet_adam_step", C.c_int, [C.c_void_p, C.c_float]),
 ]
 
 _lib = None

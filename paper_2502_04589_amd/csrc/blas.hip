@@ -73,6 +73,34 @@ __global__ void pcg_beta_kernel(int k, const double* rn, const double* ro, doubl
   beta[j] = (d != 0.0) ? rn[j] / d : 0.0;
 }
 
+// flexible PCG: beta = (r+^T z+ - r+^T z) / (r^T z)
+__global__ void flex_beta_kernel(int k, const double* a, const double* b, const double* c, double* beta) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  const double d = c[j];
+  beta[j] = (d != 0.0) ? (a[j] - b[j]) / d : 0.0;
+}
+
+// learned-PCG fallback: a column keeps the network while ||r+||^2 <= ratio^2 ||r||^2
+__global__ void fallback_kernel(int k, double ratio2, const double* rn, const double* ro, int* mask) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  if (mask[j] && !(rn[j] <= ratio2 * ro[j])) mask[j] = 0;
+}
+
+// Z[:, j] = mask[j] ? A[:, j] : Z[:, j]
+__global__ void select_cols_kernel(long long N, int k, const int* __restrict__ mask, const double* __restrict__ A,
+                                   double* __restrict__ Z) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  if (mask[i % k]) Z[i] = A[i];
+}
+
+__global__ void fill_int_kernel(int n, int v, int* p) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) p[j] = v;
+}
+
 template <typename T>
 __global__ void axpy2_kernel(long long N, int k, const double* __restrict__ alpha, const T* __restrict__ P,
                              const T* __restrict__ Q, T* __restrict__ X, T* __restrict__ R) {
@@ -504,6 +532,20 @@ void launch_axpy2(long long N, int k, const double* alpha, const double* P, cons
                   hipStream_t s) {
   axpy2_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, R);
 }
+
+void launch_flex_beta(int k, const double* a, const double* b, const double* c, double* beta, hipStream_t s) {
+  flex_beta_kernel<<<1, kBlock, 0, s>>>(k, a, b, c, beta);
+}
+
+void launch_fallback(int k, double ratio, const double* rn, const double* ro, int* mask, hipStream_t s) {
+  fallback_kernel<<<1, kBlock, 0, s>>>(k, ratio * ratio, rn, ro, mask);
+}
+
+void launch_select_cols(long long N, int k, const int* mask, const double* A, double* Z, hipStream_t s) {
+  select_cols_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, mask, A, Z);
+}
+
+void launch_fill_int(int n, int v, int* p, hipStream_t s) { fill_int_kernel<<<1, kBlock, 0, s>>>(n, v, p); }
 
 void launch_xpby(long long N, int k, const double* Z, const double* beta, double* P, hipStream_t s) {
   xpby_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, Z, beta, P);

@@ -470,6 +470,20 @@ __global__ void prolong_kernel(int mf, int mc, int k, const T* __restrict__ xc, 
   else xf[i] = (T)((double)xf[i] - s);
 }
 
+// node average of log kappa over the 2^3 elements around each interior node (3D)
+__global__ void node_logk_kernel(int n, const double* __restrict__ kappa, double* __restrict__ out) {
+  const int m = n - 1;
+  const long long N = (long long)m * m * m;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int x = (int)(i % m), y = (int)((i / m) % m), z = (int)(i / ((long long)m * m));
+  double s = 0.0;
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) s += log(kappa[((long long)(z + cz) * n + (y + cy)) * n + (x + cx)]);
+  out[i] = s / 8.0;
+}
+
 template <int DIM>
 __global__ void kappa_dinv_kernel(int n, const double* __restrict__ kappa, double* __restrict__ dinv) {
   const int m = n - 1;
@@ -677,6 +691,11 @@ void launch_kappa_dinv(int dim, int n, const double* kappa, double* dinv, hipStr
   const long long N = (long long)(n - 1) * (n - 1) * (dim == 3 ? (n - 1) : 1);
   if (dim == 3) kappa_dinv_kernel<3><<<nblk(N), kBlock, 0, s>>>(n, kappa, dinv);
   else kappa_dinv_kernel<2><<<nblk(N), kBlock, 0, s>>>(n, kappa, dinv);
+}
+
+void launch_node_logk(int n, const double* kappa, double* out, hipStream_t s) {
+  const long long N = (long long)(n - 1) * (n - 1) * (n - 1);
+  node_logk_kernel<<<nblk(N), kBlock, 0, s>>>(n, kappa, out);
 }
 
 void launch_color_probe(int dim, int m, double* E, hipStream_t s) {

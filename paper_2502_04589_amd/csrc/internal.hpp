@@ -134,6 +134,16 @@ void launch_gemm_f32(bool ta, bool tb, int M, int N, int K, double alpha, const 
 void launch_d2f(size_t n, const double* a, float* b, hipStream_t s);
 void launch_add_f2d(size_t n, const double* u, const float* e, double* w, hipStream_t s);
 void launch_cg_start_f32(size_t n, const double* R, float* r, float* e, hipStream_t s);
+// learned form: flexible-PCG beta, per-column fallback to the V-cycle, column selection
+void launch_flex_beta(int k, const double* a, const double* b, const double* c, double* beta, hipStream_t s);
+void launch_fallback(int k, double ratio, const double* rn, const double* ro, int* mask, hipStream_t s);
+void launch_select_cols(long long N, int k, const int* mask, const double* A, double* Z, hipStream_t s);
+void launch_fill_int(int n, int v, int* p, hipStream_t s);
+void launch_node_logk(int n, const double* kappa, double* out, hipStream_t s);
+// the network's kernels run on the given stream from now on
+void unet_set_stream(pase_unet* u, hipStream_t s);
+int unet_fine_n(const pase_unet* u);
+int unet_batch_max(const pase_unet* u);
 void launch_copy_f32(size_t n, const float* src, float* dst, hipStream_t s);
 // tall-skinny: Y = X op(C) (+ Y): X N x k, C k x k (transposed if tb), Y N x k; Y must not alias X
 void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, int tb,

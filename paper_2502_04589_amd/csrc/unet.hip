@@ -1,0 +1,803 @@
+// Learned preconditioner of the learned form: a 3-level 3D U-Net on the
+// interior nodes of the fine mesh, trained on the solver's own (residual,
+// V-cycle correction) pairs.  The paper does not define the network; the
+// architecture is: per level two 3x3x3 convolutions without bias, each
+// followed by ReLU; full-weighting restriction down, trilinear prolongation up
+// (the multigrid transfers), skips by channel concatenation, a final 3x3x3
+// convolution to one channel; inputs r / ||r|| and the node average of
+// log kappa; output scaled by ||r||.
+//
+// Activations are BF16, node-major per batch item ([b][node][channel]).
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation: a wave computes 16 nodes x Cout, K = 27 Cin runs over
+// (offset, channel) with channel fastest, in chunks of 32.  Operand layout of
+// the instruction (wave64): lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and
+// B[8(l/16) .. +7][l%16]; accumulator register q holds D[4(l/16) + q][l%16].
+// Weights: FP32 master tensors W[o][ci][co]; BF16 copies Wf[co][K]
+// (forward) and Wb[ci][K'] with K' = o' Cout + co and o' = 26 - o (data
+// gradient).  Offsets o enumerate (dx, dy, dz) in {-1,0,1}^3 with dx fastest.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace pase {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int off_dx(int o) { return o % 3 - 1; }
+__device__ __forceinline__ int off_dy(int o) { return (o / 3) % 3 - 1; }
+__device__ __forceinline__ int off_dz(int o) { return o / 9 - 1; }
+
+// ---------------------------------------------------------------- convolution (implicit GEMM)
+//
+// out[b][n][co] = act( sum_{o, ci} in[b][n + o][ci] Wf[co][o Cin + ci] ), in = [srcA | srcB] along
+// channels (cinA + cinB channels; cinA and cinB multiples of 8, or cinB = 0 and cinA any).
+// mask: if nonzero, out *= (maskt[b][n][co] > 0) (ReLU backward of the layer that produced maskt).
+// Block: 4 waves x 16 nodes; grid.y = batch.
+template <int COUT, bool RELU, bool VEC>
+__global__ __launch_bounds__(256) void conv_kernel(int m, int cinA, int cinB, const __bf16* __restrict__ srcA,
+                                                   const __bf16* __restrict__ srcB, const __bf16* __restrict__ Wf,
+                                                   __bf16* __restrict__ out, const __bf16* __restrict__ maskt,
+                                                   int splitc, __bf16* __restrict__ out2) {
+  const int N = m * m * m;
+  const int b = blockIdx.y;
+  const int cin = cinA + cinB;
+  const int K = 27 * cin;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n0 = (blockIdx.x * 4 + wave) * 16;
+  if (n0 >= N) return;
+  const int li = lane & 15, lg = lane >> 4;
+  const int node = n0 + li;                      // A row of this lane
+  const bool nodeok = node < N;
+  int x = 0, y = 0, z = 0;
+  if (nodeok) {
+    x = node % m;
+    y = (node / m) % m;
+    z = node / (m * m);
+  }
+  const __bf16* __restrict__ a0 = srcA + (size_t)b * N * cinA;
+  const __bf16* __restrict__ b0 = srcB ? srcB + (size_t)b * N * cinB : nullptr;
+  constexpr int NT = COUT / 16;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int kk = k0 + 8 * lg;                  // first K of this lane's 8
+    bf16x8 av;
+    if (VEC) {
+      // 8 consecutive channels of one offset
+      bool ok = nodeok && kk < K;
+      int o = 0, ci = 0;
+      if (ok) {
+        o = kk / cin;
+        ci = kk - o * cin;
+      }
+      const int X = x + off_dx(o), Y = y + off_dy(o), Z = z + off_dz(o);
+      ok = ok && X >= 0 && X < m && Y >= 0 && Y < m && Z >= 0 && Z < m;
+      const int nb = (Z * m + Y) * m + X;
+      if (ok) {
+        const __bf16* p = (ci < cinA) ? a0 + (size_t)nb * cinA + ci : b0 + (size_t)nb * cinB + (ci - cinA);
+        av = *(const bf16x8*)p;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) av[j] = (__bf16)0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int kj = kk + j;
+        __bf16 v = (__bf16)0.0f;
+        if (nodeok && kj < K) {
+          const int o = kj / cin, ci = kj - (kj / cin) * cin;
+          const int X = x + off_dx(o), Y = y + off_dy(o), Z = z + off_dz(o);
+          if (X >= 0 && X < m && Y >= 0 && Y < m && Z >= 0 && Z < m) {
+            const int nb = (Z * m + Y) * m + X;
+            v = (ci < cinA) ? a0[(size_t)nb * cinA + ci] : b0[(size_t)nb * cinB + (ci - cinA)];
+          }
+        }
+        av[j] = v;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = 16 * t + li;
+      bf16x8 bv;
+      if (VEC && kk < K) {                       // K = 27 cin is a multiple of 8: aligned rows
+        bv = *(const bf16x8*)(Wf + (size_t)co * K + kk);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bv[j] = (kk + j < K) ? Wf[(size_t)co * K + kk + j] : (__bf16)0.0f;
+      }
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+    }
+  }
+  // output channels [0, splitc) go to out (row stride splitc), the rest to out2 (stride COUT - splitc)
+  const int c1 = splitc, c2 = COUT - splitc;
+  __bf16* o1 = out + (size_t)b * N * c1;
+  __bf16* o2 = out2 ? out2 + (size_t)b * N * c2 : nullptr;
+  const __bf16* mk = maskt ? maskt + (size_t)b * N * COUT : nullptr;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int nd = n0 + 4 * lg + q;
+      const int co = 16 * t + li;
+      if (nd < N) {
+        float v = acc[t][q];
+        if (RELU) v = fmaxf(v, 0.f);
+        if (mk && !((float)mk[(size_t)nd * COUT + co] > 0.f)) v = 0.f;
+        if (co < c1) o1[(size_t)nd * c1 + co] = (__bf16)v;
+        else o2[(size_t)nd * c2 + (co - c1)] = (__bf16)v;
+      }
+    }
+  }
+}
+
+// Single output channel (final layer forward): y[b][n] = sum_{o, ci} in[b][n + o][ci] w[o cin + ci],
+// FP32 result.
+__global__ __launch_bounds__(256) void conv_out1_kernel(int m, int cin, const __bf16* __restrict__ src,
+                                                        const __bf16* __restrict__ w, float* __restrict__ y) {
+  const int N = m * m * m;
+  const int b = blockIdx.y;
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int x = node % m, yy = (node / m) % m, z = node / (m * m);
+  const __bf16* s = src + (size_t)b * N * cin;
+  float acc = 0.f;
+  for (int o = 0; o < 27; ++o) {
+    const int X = x + off_dx(o), Y = yy + off_dy(o), Z = z + off_dz(o);
+    if (X < 0 || X >= m || Y < 0 || Y >= m || Z < 0 || Z >= m) continue;
+    const __bf16* p = s + (size_t)((Z * m + Y) * m + X) * cin;
+    const __bf16* wo = w + o * cin;
+    for (int ci = 0; ci < cin; ++ci) acc = fmaf((float)p[ci], (float)wo[ci], acc);
+  }
+  y[(size_t)b * N + node] = acc;
+}
+
+// Data gradient of the final layer: d[b][n][c] = (sum_o g[b][n - o] w[o][c]) * (f[b][n][c] > 0),
+// g one channel, w[o][c] the final layer's FP32 master weights, f the layer's input.
+template <int C>
+__global__ __launch_bounds__(256) void conv_out1_bwd_kernel(int m, const float* __restrict__ g,
+                                                            const float* __restrict__ w,
+                                                            const __bf16* __restrict__ f, __bf16* __restrict__ d) {
+  const int N = m * m * m;
+  const int b = blockIdx.y;
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int x = node % m, yy = (node / m) % m, z = node / (m * m);
+  const float* gb = g + (size_t)b * N;
+  float acc[C];
+#pragma unroll
+  for (int ci = 0; ci < C; ++ci) acc[ci] = 0.f;
+  for (int o = 0; o < 27; ++o) {
+    const int X = x - off_dx(o), Y = yy - off_dy(o), Z = z - off_dz(o);
+    if (X < 0 || X >= m || Y < 0 || Y >= m || Z < 0 || Z >= m) continue;
+    const float gv = gb[(Z * m + Y) * m + X];
+#pragma unroll
+    for (int ci = 0; ci < C; ++ci) acc[ci] = fmaf(gv, w[o * C + ci], acc[ci]);
+  }
+  const __bf16* fb = f + ((size_t)b * N + node) * C;
+  __bf16* db = d + ((size_t)b * N + node) * C;
+#pragma unroll
+  for (int ci = 0; ci < C; ++ci) db[ci] = (__bf16)(((float)fb[ci] > 0.f) ? acc[ci] : 0.f);
+}
+
+// ---------------------------------------------------------------- transfers on channels (BF16)
+// restriction (full weighting, P^T) from level mf to mc = (mf - 1) / 2, c channels
+__global__ void down_kernel(int mf, int c, const __bf16* __restrict__ xf, __bf16* __restrict__ xc) {
+  const int mc = (mf - 1) / 2;
+  const long long Nc = (long long)mc * mc * mc, Nf = (long long)mf * mf * mf;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (q >= Nc * c) return;
+  const int node = (int)(q / c), ch = (int)(q % c);
+  const int X = node % mc, Y = (node / mc) % mc, Z = node / (mc * mc);
+  const __bf16* s = xf + (size_t)b * Nf * c;
+  float acc = 0.f;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const float w = (dx ? 0.5f : 1.f) * (dy ? 0.5f : 1.f) * (dz ? 0.5f : 1.f);
+        const int fx = 2 * X + 1 + dx, fy = 2 * Y + 1 + dy, fz = 2 * Z + 1 + dz;
+        acc = fmaf(w, (float)s[((size_t)(fz * mf + fy) * mf + fx) * c + ch], acc);
+      }
+  xc[(size_t)b * Nc * c + q] = (__bf16)acc;
+}
+
+// prolongation (trilinear, P) from mc to mf = 2 mc + 1, c channels; out row stride cs (>= c)
+__global__ void up_kernel(int mf, int c, int cs, const __bf16* __restrict__ xc, __bf16* __restrict__ xf) {
+  const int mc = (mf - 1) / 2;
+  const long long Nc = (long long)mc * mc * mc, Nf = (long long)mf * mf * mf;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (q >= Nf * c) return;
+  const int node = (int)(q / c), ch = (int)(q % c);
+  const int f[3] = {node % mf, (node / mf) % mf, node / (mf * mf)};
+  int lo[3], hi[3];
+  float wl[3], wh[3];
+  for (int d = 0; d < 3; ++d) {
+    if (f[d] & 1) {
+      lo[d] = hi[d] = (f[d] - 1) >> 1;
+      wl[d] = 1.f;
+      wh[d] = 0.f;
+    } else {
+      lo[d] = (f[d] >> 1) - 1;
+      hi[d] = f[d] >> 1;
+      wl[d] = (lo[d] >= 0) ? 0.5f : 0.f;
+      wh[d] = (hi[d] < mc) ? 0.5f : 0.f;
+    }
+  }
+  const __bf16* s = xc + (size_t)b * Nc * c;
+  float acc = 0.f;
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const float w = (cx ? wh[0] : wl[0]) * (cy ? wh[1] : wl[1]) * (cz ? wh[2] : wl[2]);
+        if (w == 0.f) continue;
+        const int I = cx ? hi[0] : lo[0], J = cy ? hi[1] : lo[1], L = cz ? hi[2] : lo[2];
+        acc = fmaf(w, (float)s[((size_t)(L * mc + J) * mc + I) * c + ch], acc);
+      }
+  xf[((size_t)b * Nf + node) * cs + ch] = (__bf16)acc;
+}
+
+// ---------------------------------------------------------------- input / output
+// x[b][n][0] = r[n][b] / ||r_b||, x[b][n][1] = logk[n]; nrm[b] = ||r_b|| from the column sums s[b]
+__global__ void input_kernel(long long N, int k, const double* __restrict__ R, const double* __restrict__ logk,
+                             const double* __restrict__ colsq, __bf16* __restrict__ x) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * k) return;
+  const long long n = q / k;
+  const int b = (int)(q % k);
+  const double s = sqrt(colsq[b]);
+  const double r = (s > 0.0) ? R[q] / s : 0.0;
+  __bf16* xb = x + ((size_t)b * N + n) * 2;
+  xb[0] = (__bf16)(float)r;
+  xb[1] = (__bf16)(float)(logk ? logk[n] : 0.0);
+}
+
+// Z[n][b] = ||r_b|| y[b][n]
+__global__ void output_kernel(long long N, int k, const float* __restrict__ y, const double* __restrict__ colsq,
+                              double* __restrict__ Z) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * k) return;
+  const long long n = q / k;
+  const int b = (int)(q % k);
+  Z[q] = sqrt(colsq[b]) * (double)y[(size_t)b * N + n];
+}
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------- weight gradient
+// partial[t][o cin + ci][co] = sum over nodes n of tile t (tile = kWgNodes nodes of one batch item)
+// of x[b][n + o][ci] g[b][n][co]; x = [srcA | srcB] along channels.  One thread per (K, co) entry
+// (co fastest); g rows staged in LDS per 64-node step.
+constexpr int kWgNodes = 4096;
+
+template <typename TG>
+__global__ __launch_bounds__(256) void wgrad_kernel(int m, int cinA, int cinB, int cout,
+                                                    const __bf16* __restrict__ srcA, const __bf16* __restrict__ srcB,
+                                                    const TG* __restrict__ g, float* __restrict__ partial,
+                                                    int tiles_per_item) {
+  __shared__ float gs[64][64 + 1];
+  const int N = m * m * m;
+  const int cin = cinA + cinB;
+  const int E = 27 * cin * cout;
+  const int tile = blockIdx.y;                          // (batch item, node range)
+  const int b = tile / tiles_per_item;
+  const int n_begin = (tile % tiles_per_item) * kWgNodes;
+  const int n_end = min(N, n_begin + kWgNodes);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const bool active = e < E;
+  const int co = active ? e % cout : 0;
+  const int K = active ? e / cout : 0;
+  const int o = K / cin, ci = K - (K / cin) * cin;
+  const int dx = off_dx(o), dy = off_dy(o), dz = off_dz(o);
+  const __bf16* a0 = srcA + (size_t)b * N * cinA;
+  const __bf16* b0 = srcB ? srcB + (size_t)b * N * cinB : nullptr;
+  const TG* gb = g + (size_t)b * N * cout;
+  float acc = 0.f;
+  for (int n0 = n_begin; n0 < n_end; n0 += 64) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * cout; q += 256) {
+      const int r = q / cout, c = q - (q / cout) * cout;
+      gs[r][c] = (n0 + r < n_end) ? (float)gb[(size_t)(n0 + r) * cout + c] : 0.f;
+    }
+    __syncthreads();
+    if (active) {
+      const int cnt = min(64, n_end - n0);
+      for (int r = 0; r < cnt; ++r) {
+        const int n = n0 + r;
+        const int x = n % m, y = (n / m) % m, z = n / (m * m);
+        const int X = x + dx, Y = y + dy, Z = z + dz;
+        if (X < 0 || X >= m || Y < 0 || Y >= m || Z < 0 || Z >= m) continue;
+        const int nb = (Z * m + Y) * m + X;
+        const float xv = (ci < cinA) ? (float)a0[(size_t)nb * cinA + ci] : (float)b0[(size_t)nb * cinB + ci - cinA];
+        acc = fmaf(xv, gs[r][co], acc);
+      }
+    }
+  }
+  if (active) partial[(size_t)tile * E + e] = acc;
+}
+
+// out[e] = sum_t partial[t][e] (fixed order)
+__global__ void wgrad_reduce_kernel(int tiles, int E, const float* __restrict__ partial, float* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  float s = 0.f;
+  for (int t = 0; t < tiles; ++t) s += partial[(size_t)t * E + e];
+  out[e] = s;
+}
+
+// ---------------------------------------------------------------- loss
+// z = ||r_b|| y, e = z - c; per column: num[b] = sum e^2, den[b] = sum c^2 (fixed-order partials
+// by the caller); here the elementwise part: err[b][n] = z - c
+__global__ void loss_err_kernel(long long N, int k, const float* __restrict__ y, const double* __restrict__ colsq,
+                                const double* __restrict__ C, double* __restrict__ err) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * k) return;
+  const long long n = q / k;
+  const int b = (int)(q % k);
+  err[q] = sqrt(colsq[b]) * (double)y[(size_t)b * N + n] - C[q];
+}
+
+// dL/dy[b][n] = 2 err[n][b] / den[b] / B * ||r_b||
+__global__ void loss_grad_kernel(long long N, int k, const double* __restrict__ err, const double* __restrict__ den,
+                                 const double* __restrict__ colsq, float* __restrict__ gy) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * k) return;
+  const long long n = q / k;
+  const int b = (int)(q % k);
+  gy[(size_t)b * N + n] = (float)(2.0 * err[q] / den[b] / k * sqrt(colsq[b]));
+}
+
+// ---------------------------------------------------------------- elementwise helpers
+// d = (a + (b ? b : 0)) masked by (f > 0); c channels, row strides sa, sb (channels of a and b rows)
+__global__ void add_mask_kernel(long long rows, int c, const __bf16* __restrict__ a, int sa, int oa,
+                                const __bf16* __restrict__ b2, int sb, int ob, const __bf16* __restrict__ f,
+                                __bf16* __restrict__ d) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= rows * c) return;
+  const long long r = q / c;
+  const int ch = (int)(q % c);
+  float v = (float)a[r * sa + oa + ch];
+  if (b2) v += (float)b2[r * sb + ob + ch];
+  if (!((float)f[q] > 0.f)) v = 0.f;
+  d[q] = (__bf16)v;
+}
+
+// ---------------------------------------------------------------- Adam and weight layouts
+__global__ void adam_kernel(int n, float lr, float b1, float b2, float eps, float c1, float c2,
+                            const float* __restrict__ g, float* __restrict__ w, float* __restrict__ mo,
+                            float* __restrict__ vo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float m = b1 * mo[i] + (1.f - b1) * gi;
+  const float v = b2 * vo[i] + (1.f - b2) * gi * gi;
+  mo[i] = m;
+  vo[i] = v;
+  w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// W[o][ci][co] (FP32) -> Wf[co][o cin + ci] and Wb[ci][(26 - o) cout + co] (BF16)
+__global__ void relayout_kernel(int cin, int cout, const float* __restrict__ W, __bf16* __restrict__ Wf,
+                                __bf16* __restrict__ Wb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 27 * cin * cout) return;
+  const int co = e % cout, ci = (e / cout) % cin, o = e / (cout * cin);
+  const __bf16 v = (__bf16)W[e];
+  Wf[(size_t)co * 27 * cin + o * cin + ci] = v;
+  Wb[(size_t)ci * 27 * cout + (26 - o) * cout + co] = v;
+}
+
+inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- network driver
+namespace unet {
+
+struct Layer {
+  int cinA = 0, cinB = 0, cout = 0, level = 0;
+  size_t woff = 0;                // offset of W (FP32 master) in the parameter vector
+  __bf16 *Wf = nullptr, *Wb = nullptr;
+  size_t E() const { return (size_t)27 * (cinA + cinB) * cout; }
+};
+
+}  // namespace unet
+}  // namespace pase
+
+using pase::unet::Layer;
+
+struct pase_unet {
+  int n = 0, m[3] = {0, 0, 0}, ch[3] = {0, 0, 0}, bmax = 0;
+  long long N[3] = {0, 0, 0};
+  hipStream_t stream = nullptr;
+  Layer L[11];
+  size_t P = 0;
+  float *W = nullptr, *G = nullptr, *Mo = nullptr, *Vo = nullptr;
+  int t = 0;
+  // activations (BF16, per batch item [node][channel])
+  __bf16 *x = nullptr, *h0 = nullptr, *e0 = nullptr, *d1 = nullptr, *h1 = nullptr, *e1 = nullptr, *d2 = nullptr,
+         *h2 = nullptr, *e2 = nullptr, *u1 = nullptr, *g1 = nullptr, *f1 = nullptr, *u0 = nullptr, *g0 = nullptr,
+         *f0 = nullptr;
+  float *y = nullptr, *gy = nullptr;
+  // gradients with respect to pre-activations (ga) and other intermediates
+  __bf16 *ga9 = nullptr, *ga8 = nullptr, *du0 = nullptr, *de0s = nullptr, *df1 = nullptr, *ga7 = nullptr,
+         *ga6 = nullptr, *du1 = nullptr, *de1s = nullptr, *de2 = nullptr, *ga5 = nullptr, *ga4 = nullptr,
+         *dd2 = nullptr, *ude1 = nullptr, *ga3 = nullptr, *ga2 = nullptr, *dd1 = nullptr, *ude0 = nullptr,
+         *ga1 = nullptr, *ga0 = nullptr;
+  double *colsq = nullptr, *cden = nullptr, *cnum = nullptr, *err = nullptr, *dpart = nullptr;
+  float* wpart = nullptr;
+  size_t wpart_floats = 0;
+  std::string errmsg;
+};
+
+namespace {
+
+using namespace pase;
+
+struct Bump {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+bool valid_shape(int n, int bmax, const int* ch) {
+  if (n < 8 || n % 4 || n > 1024 || bmax < 1 || bmax > 256 || !ch) return false;
+  return ch[0] == 16 && ch[1] == 32 && ch[2] == 64;   // the kernels are instantiated for 16/32/64
+}
+
+void define_layers(pase_unet* u) {
+  const int c0 = u->ch[0], c1 = u->ch[1], c2 = u->ch[2];
+  const int spec[11][4] = {{2, 0, c0, 0},  {c0, 0, c0, 0}, {c0, 0, c1, 1}, {c1, 0, c1, 1},
+                           {c1, 0, c2, 2}, {c2, 0, c2, 2}, {c2, c1, c1, 1}, {c1, 0, c1, 1},
+                           {c1, c0, c0, 0}, {c0, 0, c0, 0}, {c0, 0, 1, 0}};
+  size_t off = 0;
+  for (int i = 0; i < 11; ++i) {
+    u->L[i].cinA = spec[i][0];
+    u->L[i].cinB = spec[i][1];
+    u->L[i].cout = spec[i][2];
+    u->L[i].level = spec[i][3];
+    u->L[i].woff = off;
+    off += u->L[i].E();
+  }
+  u->P = off;
+}
+
+size_t layout(pase_unet* u, void* base) {
+  Bump b{(char*)base};
+  const size_t B = (size_t)u->bmax;
+  const size_t N0 = u->N[0], N1 = u->N[1], N2 = u->N[2];
+  const int c0 = u->ch[0], c1 = u->ch[1], c2 = u->ch[2];
+  u->W = b.take<float>(u->P); u->G = b.take<float>(u->P);
+  u->Mo = b.take<float>(u->P); u->Vo = b.take<float>(u->P);
+  for (int i = 0; i < 11; ++i) {
+    u->L[i].Wf = b.take<__bf16>(u->L[i].E());
+    u->L[i].Wb = b.take<__bf16>(u->L[i].E());
+  }
+  u->x = b.take<__bf16>(B * N0 * 2);
+  u->h0 = b.take<__bf16>(B * N0 * c0); u->e0 = b.take<__bf16>(B * N0 * c0);
+  u->d1 = b.take<__bf16>(B * N1 * c0);
+  u->h1 = b.take<__bf16>(B * N1 * c1); u->e1 = b.take<__bf16>(B * N1 * c1);
+  u->d2 = b.take<__bf16>(B * N2 * c1);
+  u->h2 = b.take<__bf16>(B * N2 * c2); u->e2 = b.take<__bf16>(B * N2 * c2);
+  u->u1 = b.take<__bf16>(B * N1 * c2);
+  u->g1 = b.take<__bf16>(B * N1 * c1); u->f1 = b.take<__bf16>(B * N1 * c1);
+  u->u0 = b.take<__bf16>(B * N0 * c1);
+  u->g0 = b.take<__bf16>(B * N0 * c0); u->f0 = b.take<__bf16>(B * N0 * c0);
+  u->y = b.take<float>(B * N0); u->gy = b.take<float>(B * N0);
+  u->ga9 = b.take<__bf16>(B * N0 * c0); u->ga8 = b.take<__bf16>(B * N0 * c0);
+  u->du0 = b.take<__bf16>(B * N0 * c1); u->de0s = b.take<__bf16>(B * N0 * c0);
+  u->df1 = b.take<__bf16>(B * N1 * c1); u->ga7 = b.take<__bf16>(B * N1 * c1);
+  u->ga6 = b.take<__bf16>(B * N1 * c1);
+  u->du1 = b.take<__bf16>(B * N1 * c2); u->de1s = b.take<__bf16>(B * N1 * c1);
+  u->de2 = b.take<__bf16>(B * N2 * c2); u->ga5 = b.take<__bf16>(B * N2 * c2);
+  u->ga4 = b.take<__bf16>(B * N2 * c2); u->dd2 = b.take<__bf16>(B * N2 * c1);
+  u->ude1 = b.take<__bf16>(B * N1 * c1); u->ga3 = b.take<__bf16>(B * N1 * c1);
+  u->ga2 = b.take<__bf16>(B * N1 * c1); u->dd1 = b.take<__bf16>(B * N1 * c0);
+  u->ude0 = b.take<__bf16>(B * N0 * c0); u->ga1 = b.take<__bf16>(B * N0 * c0);
+  u->ga0 = b.take<__bf16>(B * N0 * c0);
+  u->colsq = b.take<double>(B); u->cden = b.take<double>(B); u->cnum = b.take<double>(B);
+  u->err = b.take<double>(B * N0);
+  u->dpart = b.take<double>((size_t)coldot_tiles((long long)N0, (int)B) * B + 64);
+  size_t wp = 0;
+  for (int i = 0; i < 11; ++i) {
+    const long long Nl = u->N[u->L[i].level];
+    const size_t tiles = B * (size_t)((Nl + kWgNodes - 1) / kWgNodes);
+    wp = std::max(wp, tiles * u->L[i].E());
+  }
+  u->wpart_floats = wp;
+  u->wpart = b.take<float>(wp);
+  return b.off + 256;
+}
+
+template <int COUT, bool RELU>
+void conv_launch(const pase_unet* u, int lev, int batch, int cinA, int cinB, const __bf16* a, const __bf16* b2,
+                 const __bf16* W, __bf16* out, const __bf16* mask, int splitc, __bf16* out2) {
+  const int m = u->m[lev];
+  const long long N = u->N[lev];
+  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)batch);
+  const bool vec = ((cinA % 8) == 0) && ((cinB % 8) == 0);
+  if (vec)
+    conv_kernel<COUT, RELU, true><<<grid, 256, 0, u->stream>>>(m, cinA, cinB, a, b2, W, out, mask, splitc, out2);
+  else
+    conv_kernel<COUT, RELU, false><<<grid, 256, 0, u->stream>>>(m, cinA, cinB, a, b2, W, out, mask, splitc, out2);
+}
+
+// forward convolution of layer i: out = relu(conv(in))
+void fwd_layer(const pase_unet* u, int i, int batch, const __bf16* a, const __bf16* b2, __bf16* out) {
+  const Layer& l = u->L[i];
+  switch (l.cout) {
+    case 16: conv_launch<16, true>(u, l.level, batch, l.cinA, l.cinB, a, b2, l.Wf, out, nullptr, 16, nullptr); break;
+    case 32: conv_launch<32, true>(u, l.level, batch, l.cinA, l.cinB, a, b2, l.Wf, out, nullptr, 32, nullptr); break;
+    case 64: conv_launch<64, true>(u, l.level, batch, l.cinA, l.cinB, a, b2, l.Wf, out, nullptr, 64, nullptr); break;
+    default: break;
+  }
+}
+
+// data gradient of layer i: dIn = convT(ga) (masked by `mask` when given), split at splitc
+void bwd_data(const pase_unet* u, int i, int batch, const __bf16* ga, const __bf16* mask, __bf16* out, int splitc,
+              __bf16* out2) {
+  const Layer& l = u->L[i];
+  const int cin = l.cinA + l.cinB;
+  switch (cin) {
+    case 16: conv_launch<16, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
+    case 32: conv_launch<32, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
+    case 48: conv_launch<48, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
+    case 64: conv_launch<64, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
+    case 96: conv_launch<96, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
+    default: break;
+  }
+}
+
+template <typename TG>
+void wgrad(pase_unet* u, int i, int batch, const __bf16* a, const __bf16* b2, const TG* g) {
+  const Layer& l = u->L[i];
+  const long long N = u->N[l.level];
+  const int tpi = (int)((N + kWgNodes - 1) / kWgNodes);
+  const int E = (int)l.E();
+  const dim3 grid((unsigned)((E + 255) / 256), (unsigned)(tpi * batch));
+  wgrad_kernel<TG><<<grid, 256, 0, u->stream>>>(u->m[l.level], l.cinA, l.cinB, l.cout, a, b2, g, u->wpart, tpi);
+  wgrad_reduce_kernel<<<nb256(E), 256, 0, u->stream>>>(tpi * batch, E, u->wpart, u->G + l.woff);
+}
+
+void down(const pase_unet* u, int lf, int batch, int c, const __bf16* xf, __bf16* xc) {
+  const long long Nc = u->N[lf + 1];
+  down_kernel<<<dim3(nb256(Nc * c), (unsigned)batch), 256, 0, u->stream>>>(u->m[lf], c, xf, xc);
+}
+
+void up(const pase_unet* u, int lf, int batch, int c, const __bf16* xc, __bf16* xf) {
+  const long long Nf = u->N[lf];
+  up_kernel<<<dim3(nb256(Nf * c), (unsigned)batch), 256, 0, u->stream>>>(u->m[lf], c, c, xc, xf);
+}
+
+void add_mask(const pase_unet* u, int lev, int batch, int c, const __bf16* a, const __bf16* b2, const __bf16* f,
+              __bf16* d) {
+  const long long rows = u->N[lev] * batch;
+  add_mask_kernel<<<nb256(rows * c), 256, 0, u->stream>>>(rows, c, a, c, 0, b2, c, 0, f, d);
+}
+
+// forward pass of the whole network on the first `batch` items of u->x; result in u->y (FP32)
+void forward(pase_unet* u, int batch) {
+  fwd_layer(u, 0, batch, u->x, nullptr, u->h0);
+  fwd_layer(u, 1, batch, u->h0, nullptr, u->e0);
+  down(u, 0, batch, u->ch[0], u->e0, u->d1);
+  fwd_layer(u, 2, batch, u->d1, nullptr, u->h1);
+  fwd_layer(u, 3, batch, u->h1, nullptr, u->e1);
+  down(u, 1, batch, u->ch[1], u->e1, u->d2);
+  fwd_layer(u, 4, batch, u->d2, nullptr, u->h2);
+  fwd_layer(u, 5, batch, u->h2, nullptr, u->e2);
+  up(u, 1, batch, u->ch[2], u->e2, u->u1);
+  fwd_layer(u, 6, batch, u->u1, u->e1, u->g1);
+  fwd_layer(u, 7, batch, u->g1, nullptr, u->f1);
+  up(u, 0, batch, u->ch[1], u->f1, u->u0);
+  fwd_layer(u, 8, batch, u->u0, u->e0, u->g0);
+  fwd_layer(u, 9, batch, u->g0, nullptr, u->f0);
+  conv_out1_kernel<<<dim3(nb256(u->N[0]), (unsigned)batch), 256, 0, u->stream>>>(u->m[0], u->ch[0], u->f0,
+                                                                                   u->L[10].Wf, u->y);
+}
+
+// backward pass from u->gy (dL/dy) into u->G
+void backward(pase_unet* u, int batch) {
+  const int c0 = u->ch[0], c1 = u->ch[1], c2 = u->ch[2];
+  wgrad<float>(u, 10, batch, u->f0, nullptr, u->gy);
+  conv_out1_bwd_kernel<16><<<dim3(nb256(u->N[0]), (unsigned)batch), 256, 0, u->stream>>>(
+      u->m[0], u->gy, u->W + u->L[10].woff, u->f0, u->ga9);
+  wgrad<__bf16>(u, 9, batch, u->g0, nullptr, u->ga9);
+  bwd_data(u, 9, batch, u->ga9, u->g0, u->ga8, c0, nullptr);
+  wgrad<__bf16>(u, 8, batch, u->u0, u->e0, u->ga8);
+  bwd_data(u, 8, batch, u->ga8, nullptr, u->du0, c1, u->de0s);          // [d u0 (c1) | d e0 skip (c0)]
+  down(u, 0, batch, c1, u->du0, u->df1);
+  add_mask(u, 1, batch, c1, u->df1, nullptr, u->f1, u->ga7);
+  wgrad<__bf16>(u, 7, batch, u->g1, nullptr, u->ga7);
+  bwd_data(u, 7, batch, u->ga7, u->g1, u->ga6, c1, nullptr);
+  wgrad<__bf16>(u, 6, batch, u->u1, u->e1, u->ga6);
+  bwd_data(u, 6, batch, u->ga6, nullptr, u->du1, c2, u->de1s);          // [d u1 (c2) | d e1 skip (c1)]
+  down(u, 1, batch, c2, u->du1, u->de2);
+  add_mask(u, 2, batch, c2, u->de2, nullptr, u->e2, u->ga5);
+  wgrad<__bf16>(u, 5, batch, u->h2, nullptr, u->ga5);
+  bwd_data(u, 5, batch, u->ga5, u->h2, u->ga4, c2, nullptr);
+  wgrad<__bf16>(u, 4, batch, u->d2, nullptr, u->ga4);
+  bwd_data(u, 4, batch, u->ga4, nullptr, u->dd2, c1, nullptr);
+  up(u, 1, batch, c1, u->dd2, u->ude1);
+  add_mask(u, 1, batch, c1, u->de1s, u->ude1, u->e1, u->ga3);
+  wgrad<__bf16>(u, 3, batch, u->h1, nullptr, u->ga3);
+  bwd_data(u, 3, batch, u->ga3, u->h1, u->ga2, c1, nullptr);
+  wgrad<__bf16>(u, 2, batch, u->d1, nullptr, u->ga2);
+  bwd_data(u, 2, batch, u->ga2, nullptr, u->dd1, c0, nullptr);
+  up(u, 0, batch, c0, u->dd1, u->ude0);
+  add_mask(u, 0, batch, c0, u->de0s, u->ude0, u->e0, u->ga1);
+  wgrad<__bf16>(u, 1, batch, u->h0, nullptr, u->ga1);
+  bwd_data(u, 1, batch, u->ga1, u->h0, u->ga0, c0, nullptr);
+  wgrad<__bf16>(u, 0, batch, u->x, nullptr, u->ga0);
+}
+
+void relayout_all(pase_unet* u) {
+  for (int i = 0; i < 11; ++i) {
+    const Layer& l = u->L[i];
+    relayout_kernel<<<nb256((long long)l.E()), 256, 0, u->stream>>>(l.cinA + l.cinB, l.cout, u->W + l.woff, l.Wf,
+                                                                      l.Wb);
+  }
+}
+
+void prepare_input(pase_unet* u, int batch, const double* R, const double* logk) {
+  const long long N = u->N[0];
+  launch_coldot(N, batch, R, R, u->dpart, coldot_tiles(N, batch), u->colsq, u->stream);
+  input_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, R, logk, u->colsq, u->x);
+}
+
+pase_status ufail(pase_unet* u, pase_status s, const char* msg) {
+  if (u) u->errmsg = msg;
+  return s;
+}
+
+}  // namespace
+
+namespace pase {
+void unet_set_stream(pase_unet* u, hipStream_t s) { u->stream = s; }
+int unet_fine_n(const pase_unet* u) { return u->n; }
+int unet_batch_max(const pase_unet* u) { return u->bmax; }
+}  // namespace pase
+
+extern "C" {
+
+pase_status pase_unet_param_count(const int* channels, size_t* count) {
+  if (!channels || !count || !valid_shape(8, 1, channels)) return PASE_E_ARG;
+  pase_unet u;
+  for (int i = 0; i < 3; ++i) u.ch[i] = channels[i];
+  define_layers(&u);
+  *count = u.P;
+  return PASE_OK;
+}
+
+pase_status pase_unet_workspace_bytes(int n, int batch_max, const int* channels, size_t* bytes) {
+  if (!bytes || !valid_shape(n, batch_max, channels)) return PASE_E_ARG;
+  pase_unet u;
+  u.n = n;
+  u.bmax = batch_max;
+  for (int i = 0; i < 3; ++i) {
+    u.ch[i] = channels[i];
+    u.m[i] = (n >> i) - 1;
+    u.N[i] = (long long)u.m[i] * u.m[i] * u.m[i];
+  }
+  define_layers(&u);
+  *bytes = layout(&u, nullptr);
+  return PASE_OK;
+}
+
+pase_status pase_unet_create(int n, int batch_max, const int* channels, void* workspace, size_t bytes, void* stream,
+                             pase_unet** out) {
+  if (!out || !workspace || !valid_shape(n, batch_max, channels)) return PASE_E_ARG;
+  if (((uintptr_t)workspace & 255) != 0) return PASE_E_ARG;
+  pase_unet* u = new pase_unet;
+  u->n = n;
+  u->bmax = batch_max;
+  u->stream = (hipStream_t)stream;
+  for (int i = 0; i < 3; ++i) {
+    u->ch[i] = channels[i];
+    u->m[i] = (n >> i) - 1;
+    u->N[i] = (long long)u->m[i] * u->m[i] * u->m[i];
+  }
+  define_layers(u);
+  if (layout(u, nullptr) > bytes) {
+    delete u;
+    return PASE_E_NOMEM;
+  }
+  layout(u, workspace);
+  if (hipMemsetAsync(u->Mo, 0, u->P * sizeof(float), u->stream) != hipSuccess ||
+      hipMemsetAsync(u->Vo, 0, u->P * sizeof(float), u->stream) != hipSuccess) {
+    delete u;
+    return PASE_E_HIP;
+  }
+  *out = u;
+  return PASE_OK;
+}
+
+pase_status pase_unet_destroy(pase_unet* u) {
+  delete u;
+  return PASE_OK;
+}
+
+const char* pase_unet_last_error(const pase_unet* u) { return u ? u->errmsg.c_str() : ""; }
+
+pase_status pase_unet_set_weights(pase_unet* u, const float* W) {
+  if (!u || !W) return PASE_E_ARG;
+  if (hipMemcpyAsync(u->W, W, u->P * sizeof(float), hipMemcpyDeviceToDevice, u->stream) != hipSuccess)
+    return ufail(u, PASE_E_HIP, "copy of the weights failed");
+  if (hipMemsetAsync(u->Mo, 0, u->P * sizeof(float), u->stream) != hipSuccess ||
+      hipMemsetAsync(u->Vo, 0, u->P * sizeof(float), u->stream) != hipSuccess)
+    return ufail(u, PASE_E_HIP, "reset of the Adam moments failed");
+  u->t = 0;
+  relayout_all(u);
+  return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");
+}
+
+pase_status pase_unet_get_weights(const pase_unet* u, float* W) {
+  if (!u || !W) return PASE_E_ARG;
+  return (hipMemcpyAsync(W, u->W, u->P * sizeof(float), hipMemcpyDeviceToDevice, u->stream) == hipSuccess)
+             ? PASE_OK
+             : PASE_E_HIP;
+}
+
+pase_status pase_unet_apply(pase_unet* u, int batch, const double* R, const double* logk, double* Z) {
+  if (!u || !R || !Z || batch < 1 || batch > u->bmax) return PASE_E_ARG;
+  prepare_input(u, batch, R, logk);
+  forward(u, batch);
+  output_kernel<<<nb256(u->N[0] * batch), 256, 0, u->stream>>>(u->N[0], batch, u->y, u->colsq, Z);
+  return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");
+}
+
+pase_status pase_unet_loss_grad(pase_unet* u, int batch, const double* R, const double* C, const double* logk,
+                                double* loss_host, float* G) {
+  if (!u || !R || !C || batch < 1 || batch > u->bmax) return PASE_E_ARG;
+  const long long N = u->N[0];
+  prepare_input(u, batch, R, logk);
+  forward(u, batch);
+  loss_err_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, u->y, u->colsq, C, u->err);
+  launch_coldot(N, batch, u->err, u->err, u->dpart, coldot_tiles(N, batch), u->cnum, u->stream);
+  launch_coldot(N, batch, C, C, u->dpart, coldot_tiles(N, batch), u->cden, u->stream);
+  loss_grad_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, u->err, u->cden, u->colsq, u->gy);
+  backward(u, batch);
+  if (G && hipMemcpyAsync(G, u->G, u->P * sizeof(float), hipMemcpyDeviceToDevice, u->stream) != hipSuccess)
+    return ufail(u, PASE_E_HIP, "copy of the gradient failed");
+  if (loss_host) {
+    std::vector<double> num(batch), den(batch);
+    if (hipMemcpyAsync(num.data(), u->cnum, sizeof(double) * batch, hipMemcpyDeviceToHost, u->stream) != hipSuccess ||
+        hipMemcpyAsync(den.data(), u->cden, sizeof(double) * batch, hipMemcpyDeviceToHost, u->stream) != hipSuccess ||
+        hipStreamSynchronize(u->stream) != hipSuccess)
+      return ufail(u, PASE_E_HIP, "loss readback failed");
+    double l = 0.0;
+    for (int b = 0; b < batch; ++b) l += num[b] / den[b];
+    *loss_host = l / batch;
+  }
+  return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");
+}
+
+pase_status pase_unet_adam_step(pase_unet* u, float lr) {
+  if (!u || !(lr > 0.f)) return PASE_E_ARG;
+  u->t += 1;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.f - powf(b1, (float)u->t), c2 = 1.f - powf(b2, (float)u->t);
+  adam_kernel<<<nb256((long long)u->P), 256, 0, u->stream>>>((int)u->P, lr, b1, b2, eps, c1, c2, u->G, u->W, u->Mo,
+                                                             u->Vo);
+  relayout_all(u);
+  return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");
+}
+
+}  // extern "C"

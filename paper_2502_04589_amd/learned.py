@@ -1,0 +1,104 @@
+"""UNet: a handle on the learned preconditioner of libpase (torch-owned device memory).
+
+Argument marshalling only; every computation runs in libpase's HIP kernels on
+the stream that was current when the network was created.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _native as nat
+from .solver import PaseError, _ptr
+
+CHANNELS = (16, 32, 64)
+
+
+class UNet:
+    """3-level U-Net preconditioner on the interior nodes of an n^3 Q1 mesh (n divisible by 4)."""
+
+    def __init__(self, n, batch_max, device="cuda:0"):
+        self.lib = nat.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("UNet needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        self.n = int(n)
+        self.batch_max = int(batch_max)
+        self.N = (self.n - 1) ** 3
+        ch = (C.c_int * 3)(*CHANNELS)
+        cnt = C.c_size_t(0)
+        self._check(self.lib.pase_unet_param_count(ch, C.byref(cnt)))
+        self.num_params = int(cnt.value)
+        nbytes = C.c_size_t(0)
+        self._check(self.lib.pase_unet_workspace_bytes(self.n, self.batch_max, ch, C.byref(nbytes)))
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        self._check(self.lib.pase_unet_create(self.n, self.batch_max, ch, _ptr(self.workspace), nbytes,
+                                              C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.pase_unet_last_error(getattr(self, "h", None)) if getattr(self, "h", None) else b""
+            raise PaseError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pase_unet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _mv(self, t, k, name):
+        if not (isinstance(t, torch.Tensor) and t.device == self.device and t.dtype == torch.float64):
+            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+        if t.shape != (self.N, k) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.N} x {k} tensor")
+        return t
+
+    def _logk(self, logk):
+        if logk is None:
+            return None
+        if not (isinstance(logk, torch.Tensor) and logk.dtype == torch.float64 and logk.numel() == self.N):
+            raise TypeError("logk must be a float64 device tensor with one value per node")
+        return logk.contiguous()
+
+    def set_weights(self, W):
+        W = torch.as_tensor(W, dtype=torch.float32).reshape(-1).to(self.device).contiguous()
+        if W.numel() != self.num_params:
+            raise ValueError(f"expected {self.num_params} parameters")
+        self._w = W
+        self._check(self.lib.pase_unet_set_weights(self.h, _ptr(W)))
+
+    def get_weights(self):
+        W = torch.empty(self.num_params, dtype=torch.float32, device=self.device)
+        self._check(self.lib.pase_unet_get_weights(self.h, _ptr(W)))
+        return W
+
+    def apply(self, R, logk=None):
+        k = R.shape[1]
+        R = self._mv(R, k, "R")
+        lk = self._logk(logk)
+        Z = torch.empty_like(R)
+        self._check(self.lib.pase_unet_apply(self.h, k, _ptr(R), _ptr(lk), _ptr(Z)))
+        return Z
+
+    def loss_grad(self, R, Cm, logk=None):
+        k = R.shape[1]
+        R = self._mv(R, k, "R")
+        Cm = self._mv(Cm, k, "C")
+        lk = self._logk(logk)
+        G = torch.empty(self.num_params, dtype=torch.float32, device=self.device)
+        loss = C.c_double(0.0)
+        self._check(self.lib.pase_unet_loss_grad(self.h, k, _ptr(R), _ptr(Cm), _ptr(lk), C.byref(loss), _ptr(G)))
+        return float(loss.value), G
+
+    def adam_step(self, lr):
+        self._check(self.lib.pase_unet_adam_step(self.h, C.c_float(lr)))
