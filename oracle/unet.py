@@ -26,7 +26,10 @@ the readings taken here are:
 * Flexible PCG (Notay, 2000): beta_j = r_{j+1}^T (z_{j+1} - z_j) / (r_j^T z_j);
   a column whose residual norm does not drop below half its previous value
   while it uses the network switches to the V-cycle for the remaining steps
-  of that outer iteration (the step itself is kept).
+  of that outer iteration (the step itself is kept).  At the switch the CG
+  recurrence restarts (beta = 0), so the remaining steps are V-cycle PCG from
+  the kept iterate: a direction from a poor network, with r^T z near zero,
+  would otherwise dominate the next search direction through beta.
 
 Layout: fields are node-major (B, N, C) with x fastest, as the GPU kernels use.
 Convolution offsets o = 0..26 enumerate (dx, dy, dz) in {-1,0,1}^3 with dx
@@ -233,7 +236,8 @@ def flexible_pcg(hier, rhs, x0, s, precond, ratio=0.5):
     precond(R, cols) returns the network correction for the residual columns
     listed in cols.  A column falls back to the V-cycle for the remaining steps
     once its residual norm fails to drop below ratio times its previous value
-    while it used the network.  Returns (x, used_net_mask).
+    while it used the network, and its recurrence restarts there (beta = 0).
+    Returns (x, used_net_mask).
     """
     A = hier.A[0]
     x = x0.copy()
@@ -258,10 +262,12 @@ def flexible_pcg(hier, rhs, x0, s, precond, ratio=0.5):
         x += p * alpha
         rn = r - q * alpha
         worse = np.linalg.norm(rn, axis=0) > ratio * np.linalg.norm(r, axis=0)
+        switched = net_on & worse
         net_on &= ~worse
         if j + 1 < s:
             zn = apply(rn)
             beta = np.where(rz != 0, np.einsum("ij,ij->j", rn, zn - z) / np.where(rz != 0, rz, 1.0), 0.0)
+            beta[switched] = 0.0          # restart: plain V-cycle PCG from the kept iterate
             p = zn + p * beta
             z = zn
             rz = np.einsum("ij,ij->j", rn, zn)

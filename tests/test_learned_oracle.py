@@ -135,6 +135,23 @@ def test_zero_network_falls_back_to_the_vcycle():
     np.testing.assert_allclose(x, pase.pcg(H, rhs, U, 2), rtol=0, atol=1e-11 * np.abs(x).max())
 
 
+def test_bad_network_step_then_vcycle_pcg_from_the_kept_iterate():
+    """A network whose output ignores the residual (a constant field) fails the 0.5 test at
+    step 1 in every column; the first step is the exact line search along its output and the
+    remaining steps are plain V-cycle PCG from that iterate (restart at the switch)."""
+    H, U, rhs = _setup()
+    A = H.A[0]
+    bad = lambda R, cols: np.ones_like(R)    # noqa: E731
+    x, on = unet.flexible_pcg(H, rhs, U, 3, bad)
+    assert not on.any()
+    r0 = rhs - A @ U
+    z0 = bad(r0, None)
+    a0 = np.einsum("ij,ij->j", r0, z0) / np.einsum("ij,ij->j", z0, A @ z0)
+    x1 = U + z0 * a0
+    assert np.all(np.linalg.norm(rhs - A @ x1, axis=0) > 0.5 * np.linalg.norm(r0, axis=0))
+    np.testing.assert_allclose(x, pase.pcg(H, rhs, x1, 2), rtol=0, atol=1e-11 * np.abs(x).max())
+
+
 def test_training_reduces_the_loss():
     """Sixty Adam steps on (r, V(r)) pairs lower the relative loss (tiny network)."""
     H = multigrid.Hierarchy(3, [8, 4, 2])
