@@ -95,7 +95,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="laplace3d-64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="time the plain FP64 form only")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned form")
+    ap.add_argument("--train-steps", type=int, default=200, help="Adam steps of the learned preconditioner")
+    ap.add_argument("--harvest-iters", type=int, default=8, help="outer iterations harvested for training")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -117,24 +120,61 @@ def main():
     dim, levels, nev, tol, kseed = WORKLOADS[args.workload]
     kappa = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
 
-    def run_form(precision):
+    def train_network():
+        """Harvest (r, V(r)) pairs along the first outer iterations of a plain solve started from
+        another seed, then train the network on them (timed separately from the solves)."""
+        from paper_2502_04589_amd import UNet
+        t0 = time.perf_counter()
+        s = Solver(dim, levels, kappa, nev_max=nev, precision="learned")
+        # one correction of the plain form gives an M-orthonormal block and its Ritz values
+        src = Solver(dim, levels, kappa, nev_max=nev, precision="fp64", max_outer=1)
+        lam, U, _ = src.solve(nev, tol, torch.from_numpy(synth.initial_vectors(s.N[0], nev, 1)).cuda(),
+                              raise_notconv=False)
+        Rs, Vs = [], []
+        for _ in range(args.harvest_iters):
+            R, V = s.harvest(lam, U)
+            Rs.append(R)
+            Vs.append(V)
+            lam, U = src.correction(lam, U)
+        R = torch.cat(Rs, 1).contiguous()
+        V = torch.cat(Vs, 1).contiguous()
+        del Rs, Vs
+        torch.cuda.synchronize()
+        harvest_s = time.perf_counter() - t0
+        net = UNet(levels[0], batch_max=nev)
+        net.init_weights(0)
+        logk = s.node_logk()
+        t0 = time.perf_counter()
+        losses = net.train(R, V, logk, steps=args.train_steps, lr=1e-3, seed=0)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        del R, V, s, src
+        return net, {"harvest_s": round(harvest_s, 3), "train_s": round(train_s, 3),
+                     "train_steps": args.train_steps, "pairs": args.harvest_iters * nev,
+                     "loss_first": losses[0], "loss_last": float(np.mean(losses[-10:]))}
+
+    def run_form(precision, net=None):
         t0 = time.perf_counter()
         s = Solver(dim, levels, kappa, nev_max=nev, precision=precision)
+        if net is not None:
+            s.attach(net)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         U0h = synth.initial_vectors(s.N[0], nev, 0)
         U0 = torch.from_numpy(U0h).cuda()
         torch.cuda.synchronize()
+        strict = precision != "learned"     # the learned form reports what converged
         for _ in range(args.warmup):
-            s.solve(nev, tol, U0)
+            s.solve(nev, tol, U0, raise_notconv=strict)
         torch.cuda.synchronize()
-        conv, iters, fast = 0, [], []
+        conv, iters, fast, fb = 0, [], [], []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            lam, U, rep = s.solve(nev, tol, U0)
+            lam, U, rep = s.solve(nev, tol, U0, raise_notconv=strict)
             conv += rep["n_converged"]
             iters.append(rep["outer_iters"])
             fast.append(rep["small_fast_iters"])
+            fb.append(rep["learned_fallbacks"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         err = None
@@ -143,10 +183,16 @@ def main():
             err = float(np.max(np.abs(lam / q1_laplace_eigs(dim, levels[0], nev) - 1.0)))
         return s, U0h, {"value": conv / dt, "ms_per_step": dt / args.steps * 1e3, "outer_iters": iters[-1],
                         "small_structured_iters": fast[-1], "setup_s": round(setup_s, 3),
-                        "max_rel_err_vs_closed_form": err, "max_res": float(np.max(rep["res"]))}
+                        "max_rel_err_vs_closed_form": err, "max_res": float(np.max(rep["res"])),
+                        "learned_fallbacks": fb[-1] if precision == "learned" else None}
 
     s, U0h, plain = run_form("fp64")
     mixed = None if args.no_mixed else run_form("mixed")[2]
+    learned = None
+    if not args.no_learned:
+        net, training = train_network()
+        learned = run_form("learned", net)[2]
+        learned["training"] = training
     value = plain["value"]
     iters = [plain["outer_iters"]]
 
@@ -179,6 +225,11 @@ def main():
             "mixed_over_fp64": None if mixed is None else mixed["value"] / plain["value"],
             "mixed_note": "FP32 correction-equation CG and V-cycle over FP64 master vectors; FP64 projection, "
                           "Cholesky-QR and small eigenproblem",
+            "learned": learned,
+            "learned_over_fp64": None if learned is None else learned["value"] / plain["value"],
+            "learned_note": "flexible PCG preconditioned by a 16/32/64-channel 3D U-Net (BF16 MFMA, FP32 "
+                            "accumulation) with per-column V-cycle fallback; trained on (r, V(r)) pairs harvested "
+                            "from a plain solve of another start block; training time not in value",
         },
         "roofline": {
             "kernel": "fine-level damped-Jacobi sweep (fine3v_kernel<double, SWEEP>, LDS-staged 3D Q1 stencil)",

@@ -148,7 +148,8 @@ pase_status pase_apply(pase_handle* h, int level, int k, const double* X, double
 pase_status pase_vcycle(pase_handle* h, int k, const double* B, double* Z);
 
 /* Alg. 3 step 3: s preconditioned CG steps per column on A w = lambda_j M u_j from w = u_j.
- * lambda_host: k values. */
+ * lambda_host: k values.  A learned-form handle runs the flexible PCG with its attached network
+ * and the per-column V-cycle fallback (PASE_E_ARG without a network). */
 pase_status pase_pcg(pase_handle* h, int k, const double* lambda_host, const double* U, double* W);
 
 /* Xc = P^T Xf (fine level 0 -> coarsest), and Xf = P Xc (coarsest -> fine), P = I_H^h. */

@@ -28,7 +28,7 @@ class Report(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("n_converged", C.c_int), ("res_host", C.c_void_p),
                 ("res_literal_host", C.c_void_p), ("ritz_history_host", C.c_void_p),
                 ("ritz_history_rows", C.c_int), ("t_solve_ms", C.c_double), ("small_fast_iters", C.c_int),
-                ("small_path_host", C.c_void_p)]
+                ("small_path_host", C.c_void_p), ("learned_fallbacks", C.c_int)]
 
 
 # (name, restype, argtypes) for every entry point of include/pase.h
@@ -65,6 +65,9 @@ SIGNATURES = [
     ("pase_unet_loss_grad", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_double), C.c_void_p]),
     ("pase_unet_adam_step", C.c_int, [C.c_void_p, C.c_float]),
+    ("pase_attach_unet", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pase_harvest", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pase_node_logk", C.c_int, [C.c_void_p, C.c_void_p]),
 ]
 
 _lib = None

@@ -73,27 +73,37 @@ __global__ void pcg_beta_kernel(int k, const double* rn, const double* ro, doubl
   beta[j] = (d != 0.0) ? rn[j] / d : 0.0;
 }
 
-// flexible PCG: beta = (r+^T z+ - r+^T z) / (r^T z)
-__global__ void flex_beta_kernel(int k, const double* a, const double* b, const double* c, double* beta) {
+// Learned-PCG column state: 1 = on the network, 2 = switched to the V-cycle in this step,
+// 0 = on the V-cycle.
+//
+// flexible PCG: beta = (r+^T z+ - r+^T z) / (r^T z); 0 for a column that switched in this step
+// (the recurrence restarts there), whose state then becomes 0
+__global__ void flex_beta_kernel(int k, const double* a, const double* b, const double* c, int* mask,
+                                 double* beta) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= k) return;
   const double d = c[j];
-  beta[j] = (d != 0.0) ? (a[j] - b[j]) / d : 0.0;
+  double v = (d != 0.0) ? (a[j] - b[j]) / d : 0.0;
+  if (mask[j] == 2) {
+    v = 0.0;
+    mask[j] = 0;
+  }
+  beta[j] = v;
 }
 
 // learned-PCG fallback: a column keeps the network while ||r+||^2 <= ratio^2 ||r||^2
 __global__ void fallback_kernel(int k, double ratio2, const double* rn, const double* ro, int* mask) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= k) return;
-  if (mask[j] && !(rn[j] <= ratio2 * ro[j])) mask[j] = 0;
+  if (mask[j] == 1 && !(rn[j] <= ratio2 * ro[j])) mask[j] = 2;
 }
 
-// Z[:, j] = mask[j] ? A[:, j] : Z[:, j]
+// Z[:, j] = (mask[j] == 1) ? A[:, j] : Z[:, j]
 __global__ void select_cols_kernel(long long N, int k, const int* __restrict__ mask, const double* __restrict__ A,
                                    double* __restrict__ Z) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * k) return;
-  if (mask[i % k]) Z[i] = A[i];
+  if (mask[i % k] == 1) Z[i] = A[i];
 }
 
 __global__ void fill_int_kernel(int n, int v, int* p) {
@@ -533,8 +543,9 @@ void launch_axpy2(long long N, int k, const double* alpha, const double* P, cons
   axpy2_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, R);
 }
 
-void launch_flex_beta(int k, const double* a, const double* b, const double* c, double* beta, hipStream_t s) {
-  flex_beta_kernel<<<1, kBlock, 0, s>>>(k, a, b, c, beta);
+void launch_flex_beta(int k, const double* a, const double* b, const double* c, int* mask, double* beta,
+                      hipStream_t s) {
+  flex_beta_kernel<<<1, kBlock, 0, s>>>(k, a, b, c, mask, beta);
 }
 
 void launch_fallback(int k, double ratio, const double* rn, const double* ro, int* mask, hipStream_t s) {

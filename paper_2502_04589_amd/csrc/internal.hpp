@@ -135,7 +135,8 @@ void launch_d2f(size_t n, const double* a, float* b, hipStream_t s);
 void launch_add_f2d(size_t n, const double* u, const float* e, double* w, hipStream_t s);
 void launch_cg_start_f32(size_t n, const double* R, float* r, float* e, hipStream_t s);
 // learned form: flexible-PCG beta, per-column fallback to the V-cycle, column selection
-void launch_flex_beta(int k, const double* a, const double* b, const double* c, double* beta, hipStream_t s);
+void launch_flex_beta(int k, const double* a, const double* b, const double* c, int* mask, double* beta,
+                      hipStream_t s);
 void launch_fallback(int k, double ratio, const double* rn, const double* ro, int* mask, hipStream_t s);
 void launch_select_cols(long long N, int k, const int* mask, const double* A, double* Z, hipStream_t s);
 void launch_fill_int(int n, int v, int* p, hipStream_t s);

@@ -84,6 +84,11 @@ struct pase_handle {
   double *cmw = nullptr, *kkb = nullptr, *X0f = nullptr;   // P^T M W, beta, start block
   int *permf = nullptr, *statf = nullptr;
   double small_scale = 1.0;
+  // learned form: attached network, node log kappa, flexible-PCG column state
+  pase_unet* net = nullptr;
+  double *logk = nullptr, *rr0 = nullptr, *rr1 = nullptr, *rzo = nullptr;
+  int* netmask = nullptr;
+  int fallbacks = 0;            // column switches to the V-cycle (this solve)
   int fast_hits = 0;            // corrections solved by the structured path (this solve)
   int last_path = 0;            // 1 accepted, 0 dense only, -1 residual/orthogonality, -2 count
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -122,7 +127,9 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (o->cg_steps < 1 || o->max_outer < 0 || o->nu < 1) return PASE_E_ARG;
   if (!(o->omega > 0.0)) return PASE_E_ARG;
   if (o->small_solver != 0 && o->small_solver != 1) return PASE_E_ARG;
-  if (o->precision != PASE_PREC_FP64 && o->precision != PASE_PREC_MIXED) return PASE_E_UNSUPPORTED;
+  if (o->precision != PASE_PREC_FP64 && o->precision != PASE_PREC_MIXED && o->precision != PASE_PREC_LEARNED)
+    return PASE_E_UNSUPPORTED;
+  if (o->precision == PASE_PREC_LEARNED && p->dim != 3) return PASE_E_UNSUPPORTED;   // the network is 3D
   return PASE_OK;
 }
 
@@ -166,6 +173,11 @@ size_t layout(pase_handle* h, void* base) {
     }
     const size_t NHf = (size_t)h->lev[h->L].N;
     h->AinvL32 = b.take<float>(NHf * NHf);
+  }
+  if (h->opt.precision == PASE_PREC_LEARNED) {
+    h->logk = b.take<double>((size_t)N0);
+    h->rr0 = b.take<double>(K); h->rr1 = b.take<double>(K); h->rzo = b.take<double>(K);
+    h->netmask = b.take<int>(K);
   }
   const size_t NH = (size_t)h->lev[h->L].N;
   h->AinvL = b.take<double>(NH * NH);
@@ -416,6 +428,73 @@ void pcg_correction_f32(pase_handle* h, int k, const double* U, const double* R,
   launch_add_f2d(nk, U, h->E32, W, s);
 }
 
+// Learned form: z = N(r) for the columns still on the network, z = V(r) for the others.
+// non = number of columns on the network (the host copy of the mask count).
+pase_status learned_precond(pase_handle* h, int k, const double* R, double* Z, int non) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  if (non < k) vcycle(h, 0, k, R, Z);
+  if (non == 0) return PASE_OK;
+  const pase_status st = pase_unet_apply(h->net, k, R, h->logk, (non == k) ? Z : h->W2);
+  if (st) return fail(h, st, std::string("network: ") + pase_unet_last_error(h->net));
+  if (non < k) launch_select_cols(N, k, h->netmask, h->W2, Z, s);
+  return PASE_OK;
+}
+
+// s steps of flexible PCG per column on A x = b from x (in X), R = b - A x given, preconditioned
+// by the network; beta_j = r_{j+1}^T (z_{j+1} - z_j) / (r_j^T z_j) (Notay's flexible CG).  A
+// column whose residual norm does not fall below half its previous value switches to the
+// V-cycle for the remaining steps; the step is kept and the recurrence restarts (beta = 0), so
+// the remaining steps are V-cycle PCG from that iterate.  Returns the number of switches.
+pase_status learned_pcg(pase_handle* h, int k, double* X, double* R, int* switches) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  *switches = 0;
+  launch_fill_int(k, 1, h->netmask, s);
+  int non = k;
+  std::vector<int> mk(k);
+  pase_status st = learned_precond(h, k, R, h->Z, non);
+  if (st) return st;
+  launch_copy((size_t)N * k, h->Z, h->P, s);
+  coldot(h, N, k, R, h->Z, h->rho);
+  for (int j = 0; j < h->opt.cg_steps; ++j) {
+    apply_AM(h, 0, k, h->P, h->Q, nullptr);
+    coldot(h, N, k, h->P, h->Q, h->pq);
+    launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
+    if (non > 0) coldot(h, N, k, R, R, h->rr0);
+    launch_axpy2(N, k, h->alpha, h->P, h->Q, X, R, s);
+    if (non > 0) {
+      coldot(h, N, k, R, R, h->rr1);
+      launch_fallback(k, 0.5, h->rr1, h->rr0, h->netmask, s);
+    }
+    if (j + 1 < h->opt.cg_steps) {
+      if (non > 0) {
+        HIPC(hipMemcpyAsync(mk.data(), h->netmask, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        int c = 0;
+        for (int v : mk) c += (v == 1);
+        *switches += non - c;
+        non = c;
+      }
+      coldot(h, N, k, R, h->Z, h->rzo);                       // r_{j+1}^T z_j
+      st = learned_precond(h, k, R, h->Z, non);
+      if (st) return st;
+      coldot(h, N, k, R, h->Z, h->rho2);                      // r_{j+1}^T z_{j+1}
+      launch_flex_beta(k, h->rho2, h->rzo, h->rho, h->netmask, h->beta, s);
+      launch_xpby(N, k, h->Z, h->beta, h->P, s);
+      std::swap(h->rho, h->rho2);
+    }
+  }
+  if (non > 0) {
+    HIPC(hipMemcpyAsync(mk.data(), h->netmask, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    int c = 0;
+    for (int v : mk) c += (v == 1);
+    *switches += non - c;
+  }
+  return PASE_OK;
+}
+
 // R = lam M U - A U with fused column sums (|R|^2, |MU|^2, U.MU) into h->sums
 void eig_residual(pase_handle* h, int k, const double* U, double* R) {
   stencil_op(h, 0, k, EPI_EIGRES, U, nullptr, R, nullptr);
@@ -442,6 +521,13 @@ pase_status correction(pase_handle* h, int k) {
   // (a) fine solves A w = lam M u from w = u: s CG steps per column
   if (h->opt.precision == PASE_PREC_MIXED) {
     pcg_correction_f32(h, k, h->U, h->R, h->X);
+  } else if (h->opt.precision == PASE_PREC_LEARNED) {
+    if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
+    launch_copy((size_t)N * k, h->U, h->X, s);
+    int sw = 0;
+    const pase_status st = learned_pcg(h, k, h->X, h->R, &sw);
+    if (st) return st;
+    h->fallbacks += sw;
   } else {
     launch_copy((size_t)N * k, h->U, h->X, s);
     pcg(h, k, h->X, h->R);
@@ -633,6 +719,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   }
   HIPS(hipMemsetAsync(h->zero16, 0, 8 * sizeof(double), s));
   launch_kappa_dinv(h->dim, f.n, h->kappa, h->lev[0].dinv, s);
+  if (h->logk) launch_node_logk(f.n, h->kappa, h->logk, s);
   // Galerkin stencils A_l = P_l^T A_{l-1} P_l from 3^d colour probes
   const int NS = h->NS;
   for (int l = 1; l <= h->L; ++l) {
@@ -745,7 +832,15 @@ pase_status pase_pcg(pase_handle* h, int k, const double* lambda_host, const dou
   HIPC(hipMemcpyAsync(h->lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, h->stream));
   eig_residual(h, k, U, h->R);
   launch_copy((size_t)N * k, U, h->X, h->stream);
-  pcg(h, k, h->X, h->R);
+  if (h->opt.precision == PASE_PREC_LEARNED) {
+    if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
+    int sw = 0;
+    st = learned_pcg(h, k, h->X, h->R, &sw);
+    if (st) return st;
+    h->fallbacks = sw;
+  } else {
+    pcg(h, k, h->X, h->R);
+  }
   launch_copy((size_t)N * k, h->X, W, h->stream);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(h->stream));
@@ -837,6 +932,9 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   HIPC(hipEventRecord(h->ev0, s));
   HIPC(hipMemsetAsync(h->info, 0, 16 * sizeof(int), s));
   h->fast_hits = 0;
+  h->fallbacks = 0;
+  if (h->opt.precision == PASE_PREC_LEARNED && !h->net)
+    return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
   launch_copy((size_t)N * k, U0, h->U, s);
   // start: two passes of Cholesky-QR in M, Lambda0 = diag(U^T A U)
   for (int pass = 0; pass < 2; ++pass) cholqr_m(h, k, h->U, h->X, 3 + pass);
@@ -895,11 +993,45 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     rep->ritz_history_rows = rows;
     rep->t_solve_ms = ms;
     rep->small_fast_iters = h->fast_hits;
+    rep->learned_fallbacks = h->fallbacks;
     if (rep->res_host) std::memcpy(rep->res_host, res.data(), sizeof(double) * k);
     if (rep->res_literal_host) std::memcpy(rep->res_literal_host, lit.data(), sizeof(double) * k);
   }
   if (result != PASE_OK) return result;
   if (!conv) return fail(h, PASE_E_NOTCONV, "max_outer reached before every pair met tol");
+  return PASE_OK;
+}
+
+pase_status pase_attach_unet(pase_handle* h, pase_unet* u) {
+  if (!h || !u) return fail(h, PASE_E_ARG, "null argument");
+  if (h->opt.precision != PASE_PREC_LEARNED) return fail(h, PASE_E_ARG, "the handle is not set up for the learned form");
+  if (unet_fine_n(u) != h->lev[0].n) return fail(h, PASE_E_ARG, "the network was created for another fine mesh");
+  if (unet_batch_max(u) < h->K) return fail(h, PASE_E_ARG, "the network's batch_max is below nev_max");
+  unet_set_stream(u, h->stream);
+  h->net = u;
+  return PASE_OK;
+}
+
+pase_status pase_harvest(pase_handle* h, int k, const double* lambda_host, const double* U, double* R, double* V) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (!lambda_host || !U || !R || !V || R == V || U == R || U == V)
+    return fail(h, PASE_E_ARG, "U, R, V must be distinct non-null buffers");
+  hipStream_t s = h->stream;
+  HIPC(hipMemcpyAsync(h->lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
+  eig_residual(h, k, U, R);
+  vcycle(h, 0, k, R, V);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(s));
+  return PASE_OK;
+}
+
+pase_status pase_node_logk(pase_handle* h, double* logk) {
+  if (!h || !logk) return fail(h, PASE_E_ARG, "null argument");
+  if (h->dim != 3) return fail(h, PASE_E_UNSUPPORTED, "3D only");
+  launch_node_logk(h->lev[0].n, h->kappa, logk, h->stream);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(h->stream));
   return PASE_OK;
 }
 

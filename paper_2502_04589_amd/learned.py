@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes as C
 
+import numpy as np
 import torch
 
 from . import _native as nat
@@ -90,15 +91,50 @@ class UNet:
         self._check(self.lib.pase_unet_apply(self.h, k, _ptr(R), _ptr(lk), _ptr(Z)))
         return Z
 
-    def loss_grad(self, R, Cm, logk=None):
+    def loss_grad(self, R, Cm, logk=None, want_grad=True):
         k = R.shape[1]
         R = self._mv(R, k, "R")
         Cm = self._mv(Cm, k, "C")
         lk = self._logk(logk)
-        G = torch.empty(self.num_params, dtype=torch.float32, device=self.device)
+        G = torch.empty(self.num_params, dtype=torch.float32, device=self.device) if want_grad else None
         loss = C.c_double(0.0)
         self._check(self.lib.pase_unet_loss_grad(self.h, k, _ptr(R), _ptr(Cm), _ptr(lk), C.byref(loss), _ptr(G)))
         return float(loss.value), G
 
     def adam_step(self, lr):
         self._check(self.lib.pase_unet_adam_step(self.h, C.c_float(lr)))
+
+    # ------------------------------------------------------------------ training
+    @staticmethod
+    def layer_shapes(channels=CHANNELS):
+        """(27, Cin, Cout) of the 11 convolutions in parameter order (the order libpase uses)."""
+        c0, c1, c2 = channels
+        io = [(2, c0), (c0, c0), (c0, c1), (c1, c1), (c1, c2), (c2, c2), (c2 + c1, c1), (c1, c1),
+              (c1 + c0, c0), (c0, c0), (c0, 1)]
+        return [(27, a, b) for a, b in io]
+
+    def init_weights(self, seed=0):
+        """He-normal initialisation (std sqrt(2 / (27 Cin))) from a seeded CPU generator."""
+        g = torch.Generator().manual_seed(int(seed))
+        parts = [torch.randn(sh, generator=g, dtype=torch.float32) * (2.0 / (sh[0] * sh[1])) ** 0.5
+                 for sh in self.layer_shapes()]
+        self.set_weights(torch.cat([p.reshape(-1) for p in parts]))
+
+    def train(self, R, V, logk=None, steps=100, lr=1e-3, seed=0):
+        """Adam on the pairs (R[:, j], V[:, j]) (device N x P each): every step draws batch_max
+        distinct columns (seeded), runs the loss, its gradient and one Adam step.  Returns the
+        loss of every step."""
+        P = R.shape[1]
+        R = self._mv(R, P, "R")
+        V = self._mv(V, P, "V")
+        rng = np.random.default_rng(seed)
+        b = min(self.batch_max, P)
+        losses = []
+        for _ in range(int(steps)):
+            cols = torch.from_numpy(rng.choice(P, size=b, replace=False)).to(self.device)
+            Rb = R.index_select(1, cols).contiguous()
+            Vb = V.index_select(1, cols).contiguous()
+            loss, _ = self.loss_grad(Rb, Vb, logk, want_grad=False)
+            self.adam_step(lr)
+            losses.append(loss)
+        return losses

@@ -133,7 +133,7 @@ class Solver:
         st = self.lib.pase_solve(self.h, int(nev), float(tol), _ptr(U0), lam.ctypes.data, _ptr(U), C.byref(rep))
         report = {"outer_iters": rep.outer_iters, "n_converged": rep.n_converged, "res": res,
                   "res_literal": lit, "t_solve_ms": rep.t_solve_ms, "small_fast_iters": rep.small_fast_iters,
-                  "small_path": paths[:rep.outer_iters].copy(),
+                  "small_path": paths[:rep.outer_iters].copy(), "learned_fallbacks": rep.learned_fallbacks,
                   "status": nat.STATUS.get(st, st)}
         if history:
             report["ritz_history"] = hist[:rep.ritz_history_rows].copy()
@@ -204,6 +204,27 @@ class Solver:
         ms = C.c_double(0.0)
         self._check(self.lib.pase_time_kernel(self.h, self.KERNELS[name], int(k), int(reps), C.byref(ms)), self.h)
         return float(ms.value)
+
+    # ------------------------------------------------------------------ learned form
+    def attach(self, net):
+        """Use the UNet `net` as the PCG preconditioner (precision="learned" only)."""
+        self._check(self.lib.pase_attach_unet(self.h, net.h), self.h)
+        self._net = net          # keeps the network's memory alive while attached
+
+    def harvest(self, lam, U):
+        """Training pair for the network: R = Lambda M U - A U and V = V-cycle(R)."""
+        k = U.shape[1]
+        U = self._mv(U, self.N[0], k, "U")
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        R, V = self._new(self.N[0], k), self._new(self.N[0], k)
+        self._check(self.lib.pase_harvest(self.h, k, lam.ctypes.data, _ptr(U), _ptr(R), _ptr(V)), self.h)
+        return R, V
+
+    def node_logk(self):
+        """Node average of log kappa on the fine mesh (the network's second input)."""
+        out = torch.empty(self.N[0], dtype=torch.float64, device=self.device)
+        self._check(self.lib.pase_node_logk(self.h, _ptr(out)), self.h)
+        return out
 
     def correction(self, lam, U):
         k = U.shape[1]

@@ -6,8 +6,10 @@ below), and the Adam step matches its formula in FP32.
 """
 import numpy as np
 import pytest
+import scipy.linalg as sla
 
-from oracle import multigrid, unet as ounet
+import synth
+from oracle import multigrid, pase as opase, unet as ounet
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -102,3 +104,114 @@ def test_training_steps_reduce_the_loss():
         g.adam_step(3e-3)
     L1, _ = g.loss_grad(Rd, Cm, lk)
     assert L1 < 0.7 * L0, (L0, L1)
+
+
+# ---------------------------------------------------------------- the learned form inside the solver
+LEVELS = [16, 8, 4]
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def learned_solver(kap, k, weights):
+    from paper_2502_04589_amd import Solver, UNet
+    s = Solver(3, LEVELS, kap, nev_max=k, precision="learned")
+    g = UNet(LEVELS[0], batch_max=k)
+    g.set_weights(np.asarray(weights, dtype=np.float32))
+    s.attach(g)
+    return s, g
+
+
+def start(H, k, seed):
+    U = opase.cholqr_m(synth.initial_vectors(H.A[0].shape[0], k, seed), H.M[0])
+    lam = np.einsum("ij,ij->j", U, H.A[0] @ U)
+    return U, lam
+
+
+def param_count():
+    from paper_2502_04589_amd import UNet
+    return sum(int(np.prod(sh)) for sh in UNet.layer_shapes())
+
+
+@pytest.mark.parametrize("kseed", [None, 6])
+def test_node_log_kappa_matches_oracle(kseed):
+    from paper_2502_04589_amd import Solver
+    kap = None if kseed is None else synth.kappa_field(3, 16, kseed)
+    s = Solver(3, LEVELS, kap, nev_max=2, precision="learned")
+    ref = ounet.node_log_kappa(16, kap)
+    np.testing.assert_allclose(host(s.node_logk()), ref, rtol=1e-14, atol=1e-15)
+
+
+def test_harvest_matches_oracle():
+    from paper_2502_04589_amd import Solver
+    kap = synth.kappa_field(3, 16, 8)
+    H = multigrid.Hierarchy(3, LEVELS, kap)
+    s = Solver(3, LEVELS, kap, nev_max=5, precision="learned")
+    U, lam = start(H, 5, 1)
+    R, V = s.harvest(lam, dev(U))
+    Rref = (H.M[0] @ U) * lam - H.A[0] @ U
+    assert relerr(host(R), Rref) < 1e-12
+    assert relerr(host(V), H.vcycle(Rref)) < 1e-12
+
+
+def test_zero_network_is_vcycle_pcg_with_one_step_less():
+    """N(r) = 0 makes no progress in the first step and trips the fallback in every column;
+    the second step is V-cycle PCG from the unchanged iterate (exact in any precision)."""
+    kap = synth.kappa_field(3, 16, 9)
+    H = multigrid.Hierarchy(3, LEVELS, kap)
+    s, g = learned_solver(kap, 5, np.zeros(param_count()))
+    U, lam = start(H, 5, 2)
+    W = host(s.pcg(lam, dev(U)))
+    ref = opase.pcg(H, (H.M[0] @ U) * lam, U, 1)
+    assert relerr(W, ref) < 1e-12
+
+
+def test_learned_pcg_matches_oracle_network():
+    """Random network (every column falls back after its first step): the flexible PCG iterate
+    agrees with the oracle's to the BF16 accuracy of the network output."""
+    kap = synth.kappa_field(3, 16, 10)
+    H = multigrid.Hierarchy(3, LEVELS, kap)
+    net = ounet.UNet(16)
+    W0 = net.init(7)
+    Wr = [w.astype(np.float32).astype(np.float64) for w in W0]
+    s, g = learned_solver(kap, 4, np.concatenate([w.ravel() for w in W0]))
+    U, lam = start(H, 4, 3)
+    logk = ounet.node_log_kappa(16, kap)
+    X = host(s.pcg(lam, dev(U)))
+    ref, on = ounet.flexible_pcg(H, (H.M[0] @ U) * lam, U, 2, lambda R, cols: net.apply(Wr, R, logk))
+    for j in range(4):
+        assert relerr(X[:, j] - U[:, j], ref[:, j] - U[:, j]) < 5e-2, j
+
+
+def test_learned_solve_with_zero_network_matches_one_step_oracle():
+    k = 5
+    kap = synth.kappa_field(3, 16, 12)
+    H = multigrid.Hierarchy(3, LEVELS, kap)
+    s, g = learned_solver(kap, k, np.zeros(param_count()))
+    U0 = synth.initial_vectors(H.A[0].shape[0], k, 4)
+    lam, U, rep = s.solve(k, 1e-9, dev(U0))
+    ref = opase.solve(H, k, 1e-9, U0, s=1)
+    np.testing.assert_allclose(lam, ref.lam, rtol=1e-10)
+    assert abs(rep["outer_iters"] - ref.iters) <= 2
+    assert rep["learned_fallbacks"] == k * rep["outer_iters"]
+
+
+def test_learned_solve_converges_with_a_random_network():
+    k = 6
+    kap = synth.kappa_field(3, 16, 13)
+    H = multigrid.Hierarchy(3, LEVELS, kap)
+    net = ounet.UNet(16)
+    s, g = learned_solver(kap, k, np.concatenate([w.ravel() for w in net.init(2)]))
+    U0 = synth.initial_vectors(H.A[0].shape[0], k, 5)
+    lam, U, rep = s.solve(k, 1e-9, dev(U0))
+    w = sla.eigh(H.A[0].toarray(), H.M[0].toarray(), subset_by_index=[0, k - 1], eigvals_only=True)
+    np.testing.assert_allclose(lam, w, rtol=1e-9)
+    assert rep["n_converged"] == k
+
+
+def test_learned_form_needs_a_network():
+    from paper_2502_04589_amd import PaseError, Solver
+    s = Solver(3, LEVELS, None, nev_max=2, precision="learned")
+    with pytest.raises(PaseError):
+        s.solve(2, 1e-8, dev(synth.initial_vectors(15 ** 3, 2, 0)))
