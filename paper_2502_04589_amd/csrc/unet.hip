@@ -140,25 +140,141 @@ __global__ __launch_bounds__(256) void conv_kernel(int m, int cinA, int cinB, co
   }
 }
 
-// Single output channel (final layer forward): y[b][n] = sum_{o, ci} in[b][n + o][ci] w[o cin + ci],
-// FP32 result.
-__global__ __launch_bounds__(256) void conv_out1_kernel(int m, int cin, const __bf16* __restrict__ src,
-                                                        const __bf16* __restrict__ w, float* __restrict__ y) {
+// LDS-tiled implicit GEMM (Cin in {16, 32, 48, 64, 96}).  A block stages a TX x TY x TZ tile of
+// nodes of one batch item plus a one-node halo, all Cin channels, in LDS (rows of RS BF16, zero
+// outside the mesh), then its 4 waves each take MT = TX TY TZ / 64 M-tiles of 16 nodes.  The K loop
+// (K = 27 Cin in chunks of 32) is outermost: each chunk's weights are loaded once per wave (NT
+// 16-column tiles) and reused for all of the wave's M-tiles; the A operand (8 channels of one
+// neighbour) is one 16-byte LDS read per lane.
+// MODE 0: out = ReLU(conv), MODE 1: out = conv masked by (maskt > 0), MODE 2: y = conv, one
+// output channel (FP32; the weights are one row, the other 15 B columns are zero), MODE 3:
+// out = conv.
+template <int CIN>
+struct TileCfg;
+template <>
+struct TileCfg<16> { static constexpr int TX = 8, TY = 8, TZ = 8, RS = 24; };
+template <>
+struct TileCfg<32> { static constexpr int TX = 8, TY = 8, TZ = 4, RS = 40; };
+template <>
+struct TileCfg<48> { static constexpr int TX = 8, TY = 8, TZ = 4, RS = 48; };
+template <>
+struct TileCfg<64> { static constexpr int TX = 8, TY = 4, TZ = 4, RS = 72; };
+template <>
+struct TileCfg<96> { static constexpr int TX = 4, TY = 4, TZ = 4, RS = 104; };
+
+template <int CINA, int CINB, int COUT, int MODE>
+__global__ __launch_bounds__(256) void conv_tile_kernel(int m, const __bf16* __restrict__ srcA,
+                                                        const __bf16* __restrict__ srcB,
+                                                        const __bf16* __restrict__ Wf, __bf16* __restrict__ out,
+                                                        const __bf16* __restrict__ maskt, int splitc,
+                                                        __bf16* __restrict__ out2, float* __restrict__ y) {
+  constexpr int CIN = CINA + CINB;
+  using C = TileCfg<CIN>;
+  constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, RS = C::RS;
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HN = HX * HY * HZ;
+  constexpr int K = 27 * CIN;
+  constexpr int KC = (K + 31) / 32;
+  constexpr int NT = (MODE == 2) ? 1 : COUT / 16;
+  constexpr int MT = TX * TY * TZ / 64;                 // M-tiles per wave
+  constexpr int CH8 = CIN / 8;
+  static_assert(CIN % 8 == 0 && RS % 8 == 0 && (TX * TY * TZ) % 64 == 0, "tile shape");
+  __shared__ __align__(16) __bf16 tile[HN * RS];
+
   const int N = m * m * m;
   const int b = blockIdx.y;
-  const int node = blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
-  const int x = node % m, yy = (node / m) % m, z = node / (m * m);
-  const __bf16* s = src + (size_t)b * N * cin;
-  float acc = 0.f;
-  for (int o = 0; o < 27; ++o) {
-    const int X = x + off_dx(o), Y = yy + off_dy(o), Z = z + off_dz(o);
-    if (X < 0 || X >= m || Y < 0 || Y >= m || Z < 0 || Z >= m) continue;
-    const __bf16* p = s + (size_t)((Z * m + Y) * m + X) * cin;
-    const __bf16* wo = w + o * cin;
-    for (int ci = 0; ci < cin; ++ci) acc = fmaf((float)p[ci], (float)wo[ci], acc);
+  const int ntx = (m + TX - 1) / TX, nty = (m + TY - 1) / TY;
+  const int tx = blockIdx.x % ntx, ty = (blockIdx.x / ntx) % nty, tz = blockIdx.x / (ntx * nty);
+  const int x0 = tx * TX - 1, y0 = ty * TY - 1, z0 = tz * TZ - 1;
+  const __bf16* __restrict__ a0 = srcA + (size_t)b * N * CINA;
+  const __bf16* __restrict__ b0 = (CINB > 0) ? srcB + (size_t)b * N * CINB : nullptr;
+
+  // stage the halo tile: 16-byte chunks, node-major, x fastest
+  for (int q = threadIdx.x; q < HN * CH8; q += 256) {
+    const int hn = q / CH8, c8 = q - (q / CH8) * CH8;
+    const int hx = hn % HX, hy = (hn / HX) % HY, hz = hn / (HX * HY);
+    const int X = x0 + hx, Y = y0 + hy, Z = z0 + hz;
+    bf16x8 v;
+    if (X >= 0 && X < m && Y >= 0 && Y < m && Z >= 0 && Z < m) {
+      const size_t nb = (size_t)(Z * m + Y) * m + X;
+      const int c = c8 * 8;
+      v = (c < CINA) ? *(const bf16x8*)(a0 + nb * CINA + c) : *(const bf16x8*)(b0 + nb * CINB + (c - CINA));
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
+    }
+    *(bf16x8*)(tile + hn * RS + c8 * 8) = v;
   }
-  y[(size_t)b * N + node] = acc;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  int base[MT];                                         // halo index of this lane's node, per M-tile
+#pragma unroll
+  for (int j = 0; j < MT; ++j) {
+    const int q = (wave + 4 * j) * 16 + li;
+    const int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
+    base[j] = ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1);
+  }
+  f32x4 acc[MT][NT];
+#pragma unroll
+  for (int j = 0; j < MT; ++j)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[j][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll 2
+  for (int kc = 0; kc < KC; ++kc) {
+    const int kk = kc * 32 + 8 * lg;
+    const bool kin = kk < K;
+    const int o = kin ? kk / CIN : 13;
+    const int ci = kin ? kk - o * CIN : 0;
+    const int delta = (o / 9 - 1) * (HY * HX) + ((o / 3) % 3 - 1) * HX + (o % 3 - 1);
+    bf16x8 bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = 16 * t + li;
+      if (kin && (MODE != 2 || co == 0)) {
+        bv[t] = *(const bf16x8*)(Wf + (size_t)co * K + kk);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bv[t][j] = (__bf16)0.0f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < MT; ++j) {
+      bf16x8 av = *(const bf16x8*)(tile + (base[j] + delta) * RS + ci);
+      if (!kin) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = (__bf16)0.0f;
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[t], acc[j][t], 0, 0, 0);
+    }
+  }
+
+  const int c1 = splitc, c2 = COUT - splitc;
+#pragma unroll
+  for (int j = 0; j < MT; ++j) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ql = (wave + 4 * j) * 16 + 4 * lg + q;
+      const int X = x0 + 1 + ql % TX, Y = y0 + 1 + (ql / TX) % TY, Z = z0 + 1 + ql / (TX * TY);
+      if (X >= m || Y >= m || Z >= m) continue;
+      const size_t nd = (size_t)b * N + (size_t)(Z * m + Y) * m + X;
+      if (MODE == 2) {
+        if (li == 0) y[nd] = acc[j][0][q];
+        continue;
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int co = 16 * t + li;
+        float v = acc[j][t][q];
+        if (MODE == 0) v = fmaxf(v, 0.f);
+        if (MODE == 1 && !((float)maskt[nd * COUT + co] > 0.f)) v = 0.f;
+        if (co < c1) out[nd * c1 + co] = (__bf16)v;
+        else out2[nd * c2 + (co - c1)] = (__bf16)v;
+      }
+    }
+  }
 }
 
 // Data gradient of the final layer: d[b][n][c] = (sum_o g[b][n - o] w[o][c]) * (f[b][n][c] > 0),
@@ -190,38 +306,51 @@ __global__ __launch_bounds__(256) void conv_out1_bwd_kernel(int m, const float* 
 }
 
 // ---------------------------------------------------------------- transfers on channels (BF16)
-// restriction (full weighting, P^T) from level mf to mc = (mf - 1) / 2, c channels
+// restriction (full weighting, P^T) from level mf to mc = (mf - 1) / 2, c channels (a multiple of
+// 8); one thread per (coarse node, 8 channels), 16-byte loads and stores
 __global__ void down_kernel(int mf, int c, const __bf16* __restrict__ xf, __bf16* __restrict__ xc) {
   const int mc = (mf - 1) / 2;
+  const int c8 = c / 8;
   const long long Nc = (long long)mc * mc * mc, Nf = (long long)mf * mf * mf;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
-  if (q >= Nc * c) return;
-  const int node = (int)(q / c), ch = (int)(q % c);
+  if (q >= Nc * c8) return;
+  const int node = (int)(q / c8), ch = (int)(q % c8) * 8;
   const int X = node % mc, Y = (node / mc) % mc, Z = node / (mc * mc);
-  const __bf16* s = xf + (size_t)b * Nf * c;
-  float acc = 0.f;
+  const __bf16* s = xf + (size_t)b * Nf * c + ch;
+  float acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = 0.f;
   for (int dz = -1; dz <= 1; ++dz)
     for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const float w = (dx ? 0.5f : 1.f) * (dy ? 0.5f : 1.f) * (dz ? 0.5f : 1.f);
         const int fx = 2 * X + 1 + dx, fy = 2 * Y + 1 + dy, fz = 2 * Z + 1 + dz;
-        acc = fmaf(w, (float)s[((size_t)(fz * mf + fy) * mf + fx) * c + ch], acc);
+        const bf16x8 v = *(const bf16x8*)(s + ((size_t)(fz * mf + fy) * mf + fx) * c);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = fmaf(w, (float)v[j], acc[j]);
       }
-  xc[(size_t)b * Nc * c + q] = (__bf16)acc;
+  bf16x8 o;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = (__bf16)acc[j];
+  *(bf16x8*)(xc + ((size_t)b * Nc + node) * c + ch) = o;
 }
 
-// prolongation (trilinear, P) from mc to mf = 2 mc + 1, c channels; out row stride cs (>= c)
-__global__ void up_kernel(int mf, int c, int cs, const __bf16* __restrict__ xc, __bf16* __restrict__ xf) {
+// prolongation (trilinear, P) from mc to mf = 2 mc + 1, c channels (a multiple of 8); one thread
+// per (fine node, 8 channels)
+__global__ void up_kernel(int mf, int c, const __bf16* __restrict__ xc, __bf16* __restrict__ xf) {
   const int mc = (mf - 1) / 2;
+  const int c8 = c / 8;
   const long long Nc = (long long)mc * mc * mc, Nf = (long long)mf * mf * mf;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
-  if (q >= Nf * c) return;
-  const int node = (int)(q / c), ch = (int)(q % c);
+  if (q >= Nf * c8) return;
+  const int node = (int)(q / c8), ch = (int)(q % c8) * 8;
   const int f[3] = {node % mf, (node / mf) % mf, node / (mf * mf)};
   int lo[3], hi[3];
   float wl[3], wh[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (f[d] & 1) {
       lo[d] = hi[d] = (f[d] - 1) >> 1;
@@ -234,17 +363,24 @@ __global__ void up_kernel(int mf, int c, int cs, const __bf16* __restrict__ xc, 
       wh[d] = (hi[d] < mc) ? 0.5f : 0.f;
     }
   }
-  const __bf16* s = xc + (size_t)b * Nc * c;
-  float acc = 0.f;
+  const __bf16* s = xc + (size_t)b * Nc * c + ch;
+  float acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = 0.f;
   for (int cz = 0; cz < 2; ++cz)
     for (int cy = 0; cy < 2; ++cy)
       for (int cx = 0; cx < 2; ++cx) {
         const float w = (cx ? wh[0] : wl[0]) * (cy ? wh[1] : wl[1]) * (cz ? wh[2] : wl[2]);
         if (w == 0.f) continue;
         const int I = cx ? hi[0] : lo[0], J = cy ? hi[1] : lo[1], L = cz ? hi[2] : lo[2];
-        acc = fmaf(w, (float)s[((size_t)(L * mc + J) * mc + I) * c + ch], acc);
+        const bf16x8 v = *(const bf16x8*)(s + ((size_t)(L * mc + J) * mc + I) * c);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = fmaf(w, (float)v[j], acc[j]);
       }
-  xf[((size_t)b * Nf + node) * cs + ch] = (__bf16)acc;
+  bf16x8 o;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = (__bf16)acc[j];
+  *(bf16x8*)(xf + ((size_t)b * Nf + node) * c + ch) = o;
 }
 
 // ---------------------------------------------------------------- input / output
@@ -277,55 +413,143 @@ __global__ void output_kernel(long long N, int k, const float* __restrict__ y, c
 namespace {
 
 // ---------------------------------------------------------------- weight gradient
-// partial[t][o cin + ci][co] = sum over nodes n of tile t (tile = kWgNodes nodes of one batch item)
-// of x[b][n + o][ci] g[b][n][co]; x = [srcA | srcB] along channels.  One thread per (K, co) entry
-// (co fastest); g rows staged in LDS per 64-node step.
-constexpr int kWgNodes = 4096;
+// Weight gradient, LDS-tiled: dW[o][ci][co] = sum over (b, n) of x[b][n + o][ci] g[b][n][co].
+// grid.x: groups of 256 tasks, a task = (offset o, 8 input channels, 4 output channels) with its
+// 32 sums in registers; grid.y: node chunks, each looping over (batch item, spatial tile) pairs
+// t = blockIdx.y, blockIdx.y + gridDim.y, ...  Per tile the block stages the x halo tile (BF16,
+// node-major, rows of RS) and the g tile (FP32, rows of 4 CO4) in LDS; every thread then walks the
+// tile's nodes with one 16-byte read of each.  partial[blockIdx.y][e] receives the chunk's sums.
+template <int CIN>
+struct WgCfg;
+template <>
+struct WgCfg<2> { static constexpr int TX = 8, TY = 4, TZ = 4, RS = 8; };
+template <>
+struct WgCfg<16> { static constexpr int TX = 8, TY = 4, TZ = 4, RS = 24; };
+template <>
+struct WgCfg<32> { static constexpr int TX = 8, TY = 4, TZ = 4, RS = 40; };
+template <>
+struct WgCfg<48> { static constexpr int TX = 8, TY = 4, TZ = 4, RS = 48; };
+template <>
+struct WgCfg<64> { static constexpr int TX = 8, TY = 4, TZ = 2, RS = 72; };
+template <>
+struct WgCfg<96> { static constexpr int TX = 8, TY = 4, TZ = 2, RS = 104; };
 
-template <typename TG>
-__global__ __launch_bounds__(256) void wgrad_kernel(int m, int cinA, int cinB, int cout,
-                                                    const __bf16* __restrict__ srcA, const __bf16* __restrict__ srcB,
-                                                    const TG* __restrict__ g, float* __restrict__ partial,
-                                                    int tiles_per_item) {
-  __shared__ float gs[64][64 + 1];
+template <int CIN, int COUT>
+struct WgShape {
+  using C = WgCfg<CIN>;
+  static constexpr int CI8 = (CIN + 7) / 8, CO4 = (COUT + 3) / 4;
+  static constexpr int NTASK = 27 * CI8 * CO4;
+  static constexpr int TASK_BLOCKS = (NTASK + 255) / 256;
+  __host__ __device__ static int tiles(int m) { return ((m + C::TX - 1) / C::TX) * ((m + C::TY - 1) / C::TY) * ((m + C::TZ - 1) / C::TZ); }
+  // node chunks: about 4096 blocks in all, never more than the (item, tile) pairs
+  static int chunks(int m, int batch) { return std::max(1, std::min(tiles(m) * batch, 4096 / TASK_BLOCKS)); }
+};
+
+template <int CINA, int CINB, int COUT, typename TG>
+__global__ __launch_bounds__(256) void wgrad_tile_kernel(int m, int batch, const __bf16* __restrict__ srcA,
+                                                         const __bf16* __restrict__ srcB, const TG* __restrict__ g,
+                                                         float* __restrict__ partial) {
+  constexpr int CIN = CINA + CINB;
+  using S = WgShape<CIN, COUT>;
+  using C = WgCfg<CIN>;
+  constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, RS = C::RS;
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HN = HX * HY * HZ, TN = TX * TY * TZ;
+  constexpr int CI8 = S::CI8, CO4 = S::CO4, GS = 4 * CO4;
+  constexpr int E = 27 * CIN * COUT;
+  __shared__ __align__(16) __bf16 xs[HN * RS];
+  __shared__ __align__(16) float gs[TN * GS];
+
   const int N = m * m * m;
-  const int cin = cinA + cinB;
-  const int E = 27 * cin * cout;
-  const int tile = blockIdx.y;                          // (batch item, node range)
-  const int b = tile / tiles_per_item;
-  const int n_begin = (tile % tiles_per_item) * kWgNodes;
-  const int n_end = min(N, n_begin + kWgNodes);
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  const bool active = e < E;
-  const int co = active ? e % cout : 0;
-  const int K = active ? e / cout : 0;
-  const int o = K / cin, ci = K - (K / cin) * cin;
-  const int dx = off_dx(o), dy = off_dy(o), dz = off_dz(o);
-  const __bf16* a0 = srcA + (size_t)b * N * cinA;
-  const __bf16* b0 = srcB ? srcB + (size_t)b * N * cinB : nullptr;
-  const TG* gb = g + (size_t)b * N * cout;
-  float acc = 0.f;
-  for (int n0 = n_begin; n0 < n_end; n0 += 64) {
+  const int task = blockIdx.x * 256 + threadIdx.x;
+  const bool active = task < S::NTASK;
+  const int co4 = task % CO4, ci8 = (task / CO4) % CI8, o = active ? task / (CO4 * CI8) : 13;
+  const int delta = (o / 9 - 1) * (HY * HX) + ((o / 3) % 3 - 1) * HX + (o % 3 - 1);
+  float acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+
+  const int ntx = (m + TX - 1) / TX, nty = (m + TY - 1) / TY;
+  const int nsp = S::tiles(m);
+  for (int t = blockIdx.y; t < nsp * batch; t += gridDim.y) {
+    const int b = t / nsp, sp = t - (t / nsp) * nsp;
+    const int tx = sp % ntx, ty = (sp / ntx) % nty, tz = sp / (ntx * nty);
+    const int x0 = tx * TX - 1, y0 = ty * TY - 1, z0 = tz * TZ - 1;
     __syncthreads();
-    for (int q = threadIdx.x; q < 64 * cout; q += 256) {
-      const int r = q / cout, c = q - (q / cout) * cout;
-      gs[r][c] = (n0 + r < n_end) ? (float)gb[(size_t)(n0 + r) * cout + c] : 0.f;
+    if (CIN >= 8) {
+      for (int q = threadIdx.x; q < HN * CI8; q += 256) {
+        const int hn = q / CI8, c8 = q - (q / CI8) * CI8;
+        const int hx = hn % HX, hy = (hn / HX) % HY, hz = hn / (HX * HY);
+        const int X = x0 + hx, Y = y0 + hy, Z = z0 + hz;
+        bf16x8 v;
+        if (X >= 0 && X < m && Y >= 0 && Y < m && Z >= 0 && Z < m) {
+          const size_t nb = (size_t)b * N + (size_t)(Z * m + Y) * m + X;
+          const int c = c8 * 8;
+          v = (c < CINA) ? *(const bf16x8*)(srcA + nb * CINA + c) : *(const bf16x8*)(srcB + nb * CINB + (c - CINA));
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
+        }
+        *(bf16x8*)(xs + hn * RS + c8 * 8) = v;
+      }
+    } else {                                            // fewer than 8 input channels (first layer)
+      for (int hn = threadIdx.x; hn < HN; hn += 256) {
+        const int hx = hn % HX, hy = (hn / HX) % HY, hz = hn / (HX * HY);
+        const int X = x0 + hx, Y = y0 + hy, Z = z0 + hz;
+        const bool in = X >= 0 && X < m && Y >= 0 && Y < m && Z >= 0 && Z < m;
+        const size_t nb = in ? (size_t)b * N + (size_t)(Z * m + Y) * m + X : 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) xs[hn * RS + c] = (in && c < CIN) ? srcA[nb * CIN + c] : (__bf16)0.0f;
+      }
+    }
+    for (int q = threadIdx.x; q < TN * CO4; q += 256) {
+      const int n = q / CO4, c4 = q - (q / CO4) * CO4;
+      const int X = x0 + 1 + n % TX, Y = y0 + 1 + (n / TX) % TY, Z = z0 + 1 + n / (TX * TY);
+      const bool in = X < m && Y < m && Z < m;
+      const size_t nd = (size_t)b * N + (size_t)(Z * m + Y) * m + X;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = 4 * c4 + j;
+        gs[n * GS + c] = (in && c < COUT) ? (float)g[nd * COUT + c] : 0.f;
+      }
     }
     __syncthreads();
     if (active) {
-      const int cnt = min(64, n_end - n0);
-      for (int r = 0; r < cnt; ++r) {
-        const int n = n0 + r;
-        const int x = n % m, y = (n / m) % m, z = n / (m * m);
-        const int X = x + dx, Y = y + dy, Z = z + dz;
-        if (X < 0 || X >= m || Y < 0 || Y >= m || Z < 0 || Z >= m) continue;
-        const int nb = (Z * m + Y) * m + X;
-        const float xv = (ci < cinA) ? (float)a0[(size_t)nb * cinA + ci] : (float)b0[(size_t)nb * cinB + ci - cinA];
-        acc = fmaf(xv, gs[r][co], acc);
-      }
+#pragma unroll 1
+      for (int lz = 0; lz < TZ; ++lz)
+#pragma unroll 1
+        for (int ly = 0; ly < TY; ++ly) {
+          const int hrow = ((lz + 1) * HY + (ly + 1)) * HX + 1 + delta;
+          const int nrow = (lz * TY + ly) * TX;
+#pragma unroll
+          for (int lx = 0; lx < TX; ++lx) {
+            const bf16x8 xv = *(const bf16x8*)(xs + (hrow + lx) * RS + ci8 * 8);
+            const float4 gv = *(const float4*)(gs + (nrow + lx) * GS + co4 * 4);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const float xf = (float)xv[i];
+              acc[i][0] = fmaf(xf, gv.x, acc[i][0]);
+              acc[i][1] = fmaf(xf, gv.y, acc[i][1]);
+              acc[i][2] = fmaf(xf, gv.z, acc[i][2]);
+              acc[i][3] = fmaf(xf, gv.w, acc[i][3]);
+            }
+          }
+        }
     }
   }
-  if (active) partial[(size_t)tile * E + e] = acc;
+  if (!active) return;
+  float* dst = partial + (size_t)blockIdx.y * E;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int ci = ci8 * 8 + i;
+    if (ci >= CIN) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int co = co4 * 4 + j;
+      if (co < COUT) dst[(size_t)(o * CIN + ci) * COUT + co] = acc[i][j];
+    }
+  }
 }
 
 // out[e] = sum_t partial[t][e] (fixed order)
@@ -480,6 +704,26 @@ void define_layers(pase_unet* u) {
   u->P = off;
 }
 
+// partial sums the weight-gradient kernels of layer i need (floats), for `batch` items
+size_t wgrad_partial_floats(const pase_unet* u, int i, int batch) {
+  const Layer& l = u->L[i];
+  const int m = u->m[l.level];
+  int chunks = 1;
+  switch ((l.cinA << 16) | (l.cinB << 8) | l.cout) {
+    case (2 << 16) | (0 << 8) | 16: chunks = WgShape<2, 16>::chunks(m, batch); break;
+    case (16 << 16) | (0 << 8) | 16: chunks = WgShape<16, 16>::chunks(m, batch); break;
+    case (16 << 16) | (0 << 8) | 32: chunks = WgShape<16, 32>::chunks(m, batch); break;
+    case (32 << 16) | (0 << 8) | 32: chunks = WgShape<32, 32>::chunks(m, batch); break;
+    case (32 << 16) | (0 << 8) | 64: chunks = WgShape<32, 64>::chunks(m, batch); break;
+    case (64 << 16) | (0 << 8) | 64: chunks = WgShape<64, 64>::chunks(m, batch); break;
+    case (64 << 16) | (32 << 8) | 32: chunks = WgShape<96, 32>::chunks(m, batch); break;
+    case (32 << 16) | (16 << 8) | 16: chunks = WgShape<48, 16>::chunks(m, batch); break;
+    case (16 << 16) | (0 << 8) | 1: chunks = WgShape<16, 1>::chunks(m, batch); break;
+    default: break;
+  }
+  return (size_t)chunks * l.E();
+}
+
 size_t layout(pase_unet* u, void* base) {
   Bump b{(char*)base};
   const size_t B = (size_t)u->bmax;
@@ -517,74 +761,116 @@ size_t layout(pase_unet* u, void* base) {
   u->err = b.take<double>(B * N0);
   u->dpart = b.take<double>((size_t)coldot_tiles((long long)N0, (int)B) * B + 64);
   size_t wp = 0;
-  for (int i = 0; i < 11; ++i) {
-    const long long Nl = u->N[u->L[i].level];
-    const size_t tiles = B * (size_t)((Nl + kWgNodes - 1) / kWgNodes);
-    wp = std::max(wp, tiles * u->L[i].E());
-  }
+  for (int i = 0; i < 11; ++i)
+    for (int bt = 1; bt <= (int)B; ++bt) wp = std::max(wp, wgrad_partial_floats(u, i, bt));
   u->wpart_floats = wp;
   u->wpart = b.take<float>(wp);
   return b.off + 256;
 }
 
-template <int COUT, bool RELU>
-void conv_launch(const pase_unet* u, int lev, int batch, int cinA, int cinB, const __bf16* a, const __bf16* b2,
-                 const __bf16* W, __bf16* out, const __bf16* mask, int splitc, __bf16* out2) {
+template <int CINA, int CINB, int COUT, int MODE>
+void tile_launch(const pase_unet* u, int lev, int batch, const __bf16* a, const __bf16* b2, const __bf16* W,
+                 __bf16* out, const __bf16* mask, int splitc, __bf16* out2, float* y) {
+  using C = TileCfg<CINA + CINB>;
   const int m = u->m[lev];
-  const long long N = u->N[lev];
-  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)batch);
-  const bool vec = ((cinA % 8) == 0) && ((cinB % 8) == 0);
-  if (vec)
-    conv_kernel<COUT, RELU, true><<<grid, 256, 0, u->stream>>>(m, cinA, cinB, a, b2, W, out, mask, splitc, out2);
-  else
-    conv_kernel<COUT, RELU, false><<<grid, 256, 0, u->stream>>>(m, cinA, cinB, a, b2, W, out, mask, splitc, out2);
+  const unsigned tiles = (unsigned)(((m + C::TX - 1) / C::TX) * ((m + C::TY - 1) / C::TY) * ((m + C::TZ - 1) / C::TZ));
+  conv_tile_kernel<CINA, CINB, COUT, MODE><<<dim3(tiles, (unsigned)batch), 256, 0, u->stream>>>(
+      m, a, b2, W, out, mask, splitc, out2, y);
 }
 
 // forward convolution of layer i: out = relu(conv(in))
 void fwd_layer(const pase_unet* u, int i, int batch, const __bf16* a, const __bf16* b2, __bf16* out) {
   const Layer& l = u->L[i];
-  switch (l.cout) {
-    case 16: conv_launch<16, true>(u, l.level, batch, l.cinA, l.cinB, a, b2, l.Wf, out, nullptr, 16, nullptr); break;
-    case 32: conv_launch<32, true>(u, l.level, batch, l.cinA, l.cinB, a, b2, l.Wf, out, nullptr, 32, nullptr); break;
-    case 64: conv_launch<64, true>(u, l.level, batch, l.cinA, l.cinB, a, b2, l.Wf, out, nullptr, 64, nullptr); break;
+  const int lev = l.level;
+  const __bf16* W = l.Wf;
+  if (i == 0) {                                   // 2 input channels: the gather kernel
+    const dim3 grid((unsigned)((u->N[lev] + 63) / 64), (unsigned)batch);
+    conv_kernel<16, true, false><<<grid, 256, 0, u->stream>>>(u->m[lev], l.cinA, 0, a, nullptr, W, out, nullptr, 16,
+                                                              nullptr);
+    return;
+  }
+  const int key = (l.cinA << 16) | (l.cinB << 8) | l.cout;
+  switch (key) {
+    case (16 << 16) | (0 << 8) | 16: tile_launch<16, 0, 16, 0>(u, lev, batch, a, b2, W, out, nullptr, 16, nullptr, nullptr); break;
+    case (16 << 16) | (0 << 8) | 32: tile_launch<16, 0, 32, 0>(u, lev, batch, a, b2, W, out, nullptr, 32, nullptr, nullptr); break;
+    case (32 << 16) | (0 << 8) | 32: tile_launch<32, 0, 32, 0>(u, lev, batch, a, b2, W, out, nullptr, 32, nullptr, nullptr); break;
+    case (32 << 16) | (0 << 8) | 64: tile_launch<32, 0, 64, 0>(u, lev, batch, a, b2, W, out, nullptr, 64, nullptr, nullptr); break;
+    case (64 << 16) | (0 << 8) | 64: tile_launch<64, 0, 64, 0>(u, lev, batch, a, b2, W, out, nullptr, 64, nullptr, nullptr); break;
+    case (64 << 16) | (32 << 8) | 32: tile_launch<64, 32, 32, 0>(u, lev, batch, a, b2, W, out, nullptr, 32, nullptr, nullptr); break;
+    case (32 << 16) | (16 << 8) | 16: tile_launch<32, 16, 16, 0>(u, lev, batch, a, b2, W, out, nullptr, 16, nullptr, nullptr); break;
     default: break;
   }
+}
+
+// final layer: y = conv(in), one FP32 channel
+void out_layer(const pase_unet* u, int batch, const __bf16* f, float* y) {
+  tile_launch<16, 0, 16, 2>(u, 0, batch, f, nullptr, u->L[10].Wf, nullptr, nullptr, 16, nullptr, y);
 }
 
 // data gradient of layer i: dIn = convT(ga) (masked by `mask` when given), split at splitc
 void bwd_data(const pase_unet* u, int i, int batch, const __bf16* ga, const __bf16* mask, __bf16* out, int splitc,
               __bf16* out2) {
   const Layer& l = u->L[i];
-  const int cin = l.cinA + l.cinB;
-  switch (cin) {
-    case 16: conv_launch<16, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
-    case 32: conv_launch<32, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
-    case 48: conv_launch<48, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
-    case 64: conv_launch<64, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
-    case 96: conv_launch<96, false>(u, l.level, batch, l.cout, 0, ga, nullptr, l.Wb, out, mask, splitc, out2); break;
+  const int lev = l.level;
+  const __bf16* W = l.Wb;
+  const int key = (l.cout << 8) | (l.cinA + l.cinB);
+  if (mask) {
+    switch (key) {
+      case (16 << 8) | 16: tile_launch<16, 0, 16, 1>(u, lev, batch, ga, nullptr, W, out, mask, splitc, out2, nullptr); break;
+      case (32 << 8) | 32: tile_launch<32, 0, 32, 1>(u, lev, batch, ga, nullptr, W, out, mask, splitc, out2, nullptr); break;
+      case (64 << 8) | 64: tile_launch<64, 0, 64, 1>(u, lev, batch, ga, nullptr, W, out, mask, splitc, out2, nullptr); break;
+      default: break;
+    }
+  } else {
+    switch (key) {
+      case (16 << 8) | 48: tile_launch<16, 0, 48, 3>(u, lev, batch, ga, nullptr, W, out, nullptr, splitc, out2, nullptr); break;
+      case (32 << 8) | 96: tile_launch<32, 0, 96, 3>(u, lev, batch, ga, nullptr, W, out, nullptr, splitc, out2, nullptr); break;
+      case (64 << 8) | 32: tile_launch<64, 0, 32, 3>(u, lev, batch, ga, nullptr, W, out, nullptr, splitc, out2, nullptr); break;
+      case (32 << 8) | 16: tile_launch<32, 0, 16, 3>(u, lev, batch, ga, nullptr, W, out, nullptr, splitc, out2, nullptr); break;
+      default: break;
+    }
+  }
+}
+
+template <int CINA, int CINB, int COUT, typename TG>
+void wgrad_launch(pase_unet* u, int i, int batch, const __bf16* a, const __bf16* b2, const TG* g) {
+  using S = WgShape<CINA + CINB, COUT>;
+  const Layer& l = u->L[i];
+  const int m = u->m[l.level];
+  const int chunks = S::chunks(m, batch);
+  const int E = (int)l.E();
+  wgrad_tile_kernel<CINA, CINB, COUT, TG><<<dim3((unsigned)S::TASK_BLOCKS, (unsigned)chunks), 256, 0, u->stream>>>(
+      m, batch, a, b2, g, u->wpart);
+  wgrad_reduce_kernel<<<nb256(E), 256, 0, u->stream>>>(chunks, E, u->wpart, u->G + l.woff);
+}
+
+// weight gradient of layer i from its input [a | b2] and the gradient g of its pre-activation
+template <typename TG>
+void wgrad(pase_unet* u, int i, int batch, const __bf16* a, const __bf16* b2, const TG* g) {
+  const Layer& l = u->L[i];
+  const int key = (l.cinA << 16) | (l.cinB << 8) | l.cout;
+  switch (key) {
+    case (2 << 16) | (0 << 8) | 16: wgrad_launch<2, 0, 16>(u, i, batch, a, b2, g); break;
+    case (16 << 16) | (0 << 8) | 16: wgrad_launch<16, 0, 16>(u, i, batch, a, b2, g); break;
+    case (16 << 16) | (0 << 8) | 32: wgrad_launch<16, 0, 32>(u, i, batch, a, b2, g); break;
+    case (32 << 16) | (0 << 8) | 32: wgrad_launch<32, 0, 32>(u, i, batch, a, b2, g); break;
+    case (32 << 16) | (0 << 8) | 64: wgrad_launch<32, 0, 64>(u, i, batch, a, b2, g); break;
+    case (64 << 16) | (0 << 8) | 64: wgrad_launch<64, 0, 64>(u, i, batch, a, b2, g); break;
+    case (64 << 16) | (32 << 8) | 32: wgrad_launch<64, 32, 32>(u, i, batch, a, b2, g); break;
+    case (32 << 16) | (16 << 8) | 16: wgrad_launch<32, 16, 16>(u, i, batch, a, b2, g); break;
+    case (16 << 16) | (0 << 8) | 1: wgrad_launch<16, 0, 1>(u, i, batch, a, b2, g); break;
     default: break;
   }
 }
 
-template <typename TG>
-void wgrad(pase_unet* u, int i, int batch, const __bf16* a, const __bf16* b2, const TG* g) {
-  const Layer& l = u->L[i];
-  const long long N = u->N[l.level];
-  const int tpi = (int)((N + kWgNodes - 1) / kWgNodes);
-  const int E = (int)l.E();
-  const dim3 grid((unsigned)((E + 255) / 256), (unsigned)(tpi * batch));
-  wgrad_kernel<TG><<<grid, 256, 0, u->stream>>>(u->m[l.level], l.cinA, l.cinB, l.cout, a, b2, g, u->wpart, tpi);
-  wgrad_reduce_kernel<<<nb256(E), 256, 0, u->stream>>>(tpi * batch, E, u->wpart, u->G + l.woff);
-}
-
 void down(const pase_unet* u, int lf, int batch, int c, const __bf16* xf, __bf16* xc) {
   const long long Nc = u->N[lf + 1];
-  down_kernel<<<dim3(nb256(Nc * c), (unsigned)batch), 256, 0, u->stream>>>(u->m[lf], c, xf, xc);
+  down_kernel<<<dim3(nb256(Nc * (c / 8)), (unsigned)batch), 256, 0, u->stream>>>(u->m[lf], c, xf, xc);
 }
 
 void up(const pase_unet* u, int lf, int batch, int c, const __bf16* xc, __bf16* xf) {
   const long long Nf = u->N[lf];
-  up_kernel<<<dim3(nb256(Nf * c), (unsigned)batch), 256, 0, u->stream>>>(u->m[lf], c, c, xc, xf);
+  up_kernel<<<dim3(nb256(Nf * (c / 8)), (unsigned)batch), 256, 0, u->stream>>>(u->m[lf], c, xc, xf);
 }
 
 void add_mask(const pase_unet* u, int lev, int batch, int c, const __bf16* a, const __bf16* b2, const __bf16* f,
@@ -609,8 +895,7 @@ void forward(pase_unet* u, int batch) {
   up(u, 0, batch, u->ch[1], u->f1, u->u0);
   fwd_layer(u, 8, batch, u->u0, u->e0, u->g0);
   fwd_layer(u, 9, batch, u->g0, nullptr, u->f0);
-  conv_out1_kernel<<<dim3(nb256(u->N[0]), (unsigned)batch), 256, 0, u->stream>>>(u->m[0], u->ch[0], u->f0,
-                                                                                   u->L[10].Wf, u->y);
+  out_layer(u, batch, u->f0, u->y);
 }
 
 // backward pass from u->gy (dL/dy) into u->G
