@@ -9,8 +9,8 @@
 //
 // Activations are BF16, node-major per batch item ([b][node][channel]).
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 with FP32
-// accumulation: a wave computes 16 nodes x Cout, K = 27 Cin runs over
-// (offset, channel) with channel fastest, in chunks of 32.  Operand layout of
+// accumulation over a node tile staged in LDS: an M-tile is 16 nodes x Cout,
+// K = 27 Cin runs over (offset, channel) with channel fastest, in chunks of 32.  Operand layout of
 // the instruction (wave64): lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and
 // B[8(l/16) .. +7][l%16]; accumulator register q holds D[4(l/16) + q][l%16].
 // Weights: FP32 master tensors W[o][ci][co]; BF16 copies Wf[co][K]
@@ -36,111 +36,8 @@ __device__ __forceinline__ int off_dy(int o) { return (o / 3) % 3 - 1; }
 __device__ __forceinline__ int off_dz(int o) { return o / 9 - 1; }
 
 // ---------------------------------------------------------------- convolution (implicit GEMM)
-//
-// out[b][n][co] = act( sum_{o, ci} in[b][n + o][ci] Wf[co][o Cin + ci] ), in = [srcA | srcB] along
-// channels (cinA + cinB channels; cinA and cinB multiples of 8, or cinB = 0 and cinA any).
-// mask: if nonzero, out *= (maskt[b][n][co] > 0) (ReLU backward of the layer that produced maskt).
-// Block: 4 waves x 16 nodes; grid.y = batch.
-template <int COUT, bool RELU, bool VEC>
-__global__ __launch_bounds__(256) void conv_kernel(int m, int cinA, int cinB, const __bf16* __restrict__ srcA,
-                                                   const __bf16* __restrict__ srcB, const __bf16* __restrict__ Wf,
-                                                   __bf16* __restrict__ out, const __bf16* __restrict__ maskt,
-                                                   int splitc, __bf16* __restrict__ out2) {
-  const int N = m * m * m;
-  const int b = blockIdx.y;
-  const int cin = cinA + cinB;
-  const int K = 27 * cin;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int n0 = (blockIdx.x * 4 + wave) * 16;
-  if (n0 >= N) return;
-  const int li = lane & 15, lg = lane >> 4;
-  const int node = n0 + li;                      // A row of this lane
-  const bool nodeok = node < N;
-  int x = 0, y = 0, z = 0;
-  if (nodeok) {
-    x = node % m;
-    y = (node / m) % m;
-    z = node / (m * m);
-  }
-  const __bf16* __restrict__ a0 = srcA + (size_t)b * N * cinA;
-  const __bf16* __restrict__ b0 = srcB ? srcB + (size_t)b * N * cinB : nullptr;
-  constexpr int NT = COUT / 16;
-  f32x4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    const int kk = k0 + 8 * lg;                  // first K of this lane's 8
-    bf16x8 av;
-    if (VEC) {
-      // 8 consecutive channels of one offset
-      bool ok = nodeok && kk < K;
-      int o = 0, ci = 0;
-      if (ok) {
-        o = kk / cin;
-        ci = kk - o * cin;
-      }
-      const int X = x + off_dx(o), Y = y + off_dy(o), Z = z + off_dz(o);
-      ok = ok && X >= 0 && X < m && Y >= 0 && Y < m && Z >= 0 && Z < m;
-      const int nb = (Z * m + Y) * m + X;
-      if (ok) {
-        const __bf16* p = (ci < cinA) ? a0 + (size_t)nb * cinA + ci : b0 + (size_t)nb * cinB + (ci - cinA);
-        av = *(const bf16x8*)p;
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) av[j] = (__bf16)0.0f;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int kj = kk + j;
-        __bf16 v = (__bf16)0.0f;
-        if (nodeok && kj < K) {
-          const int o = kj / cin, ci = kj - (kj / cin) * cin;
-          const int X = x + off_dx(o), Y = y + off_dy(o), Z = z + off_dz(o);
-          if (X >= 0 && X < m && Y >= 0 && Y < m && Z >= 0 && Z < m) {
-            const int nb = (Z * m + Y) * m + X;
-            v = (ci < cinA) ? a0[(size_t)nb * cinA + ci] : b0[(size_t)nb * cinB + (ci - cinA)];
-          }
-        }
-        av[j] = v;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int co = 16 * t + li;
-      bf16x8 bv;
-      if (VEC && kk < K) {                       // K = 27 cin is a multiple of 8: aligned rows
-        bv = *(const bf16x8*)(Wf + (size_t)co * K + kk);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bv[j] = (kk + j < K) ? Wf[(size_t)co * K + kk + j] : (__bf16)0.0f;
-      }
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
-    }
-  }
-  // output channels [0, splitc) go to out (row stride splitc), the rest to out2 (stride COUT - splitc)
-  const int c1 = splitc, c2 = COUT - splitc;
-  __bf16* o1 = out + (size_t)b * N * c1;
-  __bf16* o2 = out2 ? out2 + (size_t)b * N * c2 : nullptr;
-  const __bf16* mk = maskt ? maskt + (size_t)b * N * COUT : nullptr;
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int nd = n0 + 4 * lg + q;
-      const int co = 16 * t + li;
-      if (nd < N) {
-        float v = acc[t][q];
-        if (RELU) v = fmaxf(v, 0.f);
-        if (mk && !((float)mk[(size_t)nd * COUT + co] > 0.f)) v = 0.f;
-        if (co < c1) o1[(size_t)nd * c1 + co] = (__bf16)v;
-        else o2[(size_t)nd * c2 + (co - c1)] = (__bf16)v;
-      }
-    }
-  }
-}
-
-// LDS-tiled implicit GEMM (Cin in {16, 32, 48, 64, 96}).  A block stages a TX x TY x TZ tile of
+// LDS-tiled implicit GEMM (Cin in {2, 16, 32, 48, 64, 96}; 2 channels are padded to 8 with zeros,
+// and the weights of such a layer are laid out with K = 27 x 8).  A block stages a TX x TY x TZ tile of
 // nodes of one batch item plus a one-node halo, all Cin channels, in LDS (rows of RS BF16, zero
 // outside the mesh), then its 4 waves each take MT = TX TY TZ / 64 M-tiles of 16 nodes.  The K loop
 // (K = 27 Cin in chunks of 32) is outermost: each chunk's weights are loaded once per wave (NT
@@ -151,6 +48,8 @@ __global__ __launch_bounds__(256) void conv_kernel(int m, int cinA, int cinB, co
 // out = conv.
 template <int CIN>
 struct TileCfg;
+template <>
+struct TileCfg<8> { static constexpr int TX = 8, TY = 8, TZ = 8, RS = 8; };
 template <>
 struct TileCfg<16> { static constexpr int TX = 8, TY = 8, TZ = 8, RS = 24; };
 template <>
@@ -168,7 +67,8 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(int m, const __bf16* __r
                                                         const __bf16* __restrict__ Wf, __bf16* __restrict__ out,
                                                         const __bf16* __restrict__ maskt, int splitc,
                                                         __bf16* __restrict__ out2, float* __restrict__ y) {
-  constexpr int CIN = CINA + CINB;
+  constexpr int CINR = CINA + CINB;                   // channels in memory
+  constexpr int CIN = CINR < 8 ? 8 : CINR;            // channels in LDS and in K
   using C = TileCfg<CIN>;
   constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, RS = C::RS;
   constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HN = HX * HY * HZ;
@@ -194,13 +94,17 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(int m, const __bf16* __r
     const int hx = hn % HX, hy = (hn / HX) % HY, hz = hn / (HX * HY);
     const int X = x0 + hx, Y = y0 + hy, Z = z0 + hz;
     bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
     if (X >= 0 && X < m && Y >= 0 && Y < m && Z >= 0 && Z < m) {
       const size_t nb = (size_t)(Z * m + Y) * m + X;
       const int c = c8 * 8;
-      v = (c < CINA) ? *(const bf16x8*)(a0 + nb * CINA + c) : *(const bf16x8*)(b0 + nb * CINB + (c - CINA));
-    } else {
+      if (CINR < 8) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
+        for (int j = 0; j < CINR; ++j) v[j] = a0[nb * CINR + j];
+      } else {
+        v = (c < CINA) ? *(const bf16x8*)(a0 + nb * CINA + c) : *(const bf16x8*)(b0 + nb * CINB + (c - CINA));
+      }
     }
     *(bf16x8*)(tile + hn * RS + c8 * 8) = v;
   }
@@ -612,14 +516,15 @@ __global__ void adam_kernel(int n, float lr, float b1, float b2, float eps, floa
   w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
-// W[o][ci][co] (FP32) -> Wf[co][o cin + ci] and Wb[ci][(26 - o) cout + co] (BF16)
-__global__ void relayout_kernel(int cin, int cout, const float* __restrict__ W, __bf16* __restrict__ Wf,
+// W[o][ci][co] (FP32) -> Wf[co][o cinp + ci] and Wb[ci][(26 - o) cout + co] (BF16); cinp >= cin is
+// the padded channel count of the forward layout (the padding entries stay zero)
+__global__ void relayout_kernel(int cin, int cinp, int cout, const float* __restrict__ W, __bf16* __restrict__ Wf,
                                 __bf16* __restrict__ Wb) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 27 * cin * cout) return;
   const int co = e % cout, ci = (e / cout) % cin, o = e / (cout * cin);
   const __bf16 v = (__bf16)W[e];
-  Wf[(size_t)co * 27 * cin + o * cin + ci] = v;
+  Wf[(size_t)co * 27 * cinp + o * cinp + ci] = v;
   Wb[(size_t)ci * 27 * cout + (26 - o) * cout + co] = v;
 }
 
@@ -732,8 +637,9 @@ size_t layout(pase_unet* u, void* base) {
   u->W = b.take<float>(u->P); u->G = b.take<float>(u->P);
   u->Mo = b.take<float>(u->P); u->Vo = b.take<float>(u->P);
   for (int i = 0; i < 11; ++i) {
-    u->L[i].Wf = b.take<__bf16>(u->L[i].E());
-    u->L[i].Wb = b.take<__bf16>(u->L[i].E());
+    const Layer& l = u->L[i];
+    u->L[i].Wf = b.take<__bf16>((size_t)27 * std::max(l.cinA + l.cinB, 8) * l.cout);   // forward layout, K padded
+    u->L[i].Wb = b.take<__bf16>(l.E());
   }
   u->x = b.take<__bf16>(B * N0 * 2);
   u->h0 = b.take<__bf16>(B * N0 * c0); u->e0 = b.take<__bf16>(B * N0 * c0);
@@ -771,7 +677,7 @@ size_t layout(pase_unet* u, void* base) {
 template <int CINA, int CINB, int COUT, int MODE>
 void tile_launch(const pase_unet* u, int lev, int batch, const __bf16* a, const __bf16* b2, const __bf16* W,
                  __bf16* out, const __bf16* mask, int splitc, __bf16* out2, float* y) {
-  using C = TileCfg<CINA + CINB>;
+  using C = TileCfg<(CINA + CINB < 8) ? 8 : CINA + CINB>;
   const int m = u->m[lev];
   const unsigned tiles = (unsigned)(((m + C::TX - 1) / C::TX) * ((m + C::TY - 1) / C::TY) * ((m + C::TZ - 1) / C::TZ));
   conv_tile_kernel<CINA, CINB, COUT, MODE><<<dim3(tiles, (unsigned)batch), 256, 0, u->stream>>>(
@@ -783,14 +689,9 @@ void fwd_layer(const pase_unet* u, int i, int batch, const __bf16* a, const __bf
   const Layer& l = u->L[i];
   const int lev = l.level;
   const __bf16* W = l.Wf;
-  if (i == 0) {                                   // 2 input channels: the gather kernel
-    const dim3 grid((unsigned)((u->N[lev] + 63) / 64), (unsigned)batch);
-    conv_kernel<16, true, false><<<grid, 256, 0, u->stream>>>(u->m[lev], l.cinA, 0, a, nullptr, W, out, nullptr, 16,
-                                                              nullptr);
-    return;
-  }
   const int key = (l.cinA << 16) | (l.cinB << 8) | l.cout;
   switch (key) {
+    case (2 << 16) | (0 << 8) | 16: tile_launch<2, 0, 16, 0>(u, lev, batch, a, b2, W, out, nullptr, 16, nullptr, nullptr); break;
     case (16 << 16) | (0 << 8) | 16: tile_launch<16, 0, 16, 0>(u, lev, batch, a, b2, W, out, nullptr, 16, nullptr, nullptr); break;
     case (16 << 16) | (0 << 8) | 32: tile_launch<16, 0, 32, 0>(u, lev, batch, a, b2, W, out, nullptr, 32, nullptr, nullptr); break;
     case (32 << 16) | (0 << 8) | 32: tile_launch<32, 0, 32, 0>(u, lev, batch, a, b2, W, out, nullptr, 32, nullptr, nullptr); break;
@@ -936,8 +837,9 @@ void backward(pase_unet* u, int batch) {
 void relayout_all(pase_unet* u) {
   for (int i = 0; i < 11; ++i) {
     const Layer& l = u->L[i];
-    relayout_kernel<<<nb256((long long)l.E()), 256, 0, u->stream>>>(l.cinA + l.cinB, l.cout, u->W + l.woff, l.Wf,
-                                                                      l.Wb);
+    const int cin = l.cinA + l.cinB;
+    relayout_kernel<<<nb256((long long)l.E()), 256, 0, u->stream>>>(cin, std::max(cin, 8), l.cout, u->W + l.woff,
+                                                                      l.Wf, l.Wb);
   }
 }
 
@@ -1005,7 +907,8 @@ pase_status pase_unet_create(int n, int batch_max, const int* channels, void* wo
     return PASE_E_NOMEM;
   }
   layout(u, workspace);
-  if (hipMemsetAsync(u->Mo, 0, u->P * sizeof(float), u->stream) != hipSuccess ||
+  if (hipMemsetAsync(u->L[0].Wf, 0, sizeof(__bf16) * 27 * 8 * u->L[0].cout, u->stream) != hipSuccess ||
+      hipMemsetAsync(u->Mo, 0, u->P * sizeof(float), u->stream) != hipSuccess ||
       hipMemsetAsync(u->Vo, 0, u->P * sizeof(float), u->stream) != hipSuccess) {
     delete u;
     return PASE_E_HIP;
