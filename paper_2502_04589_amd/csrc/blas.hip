@@ -452,10 +452,17 @@ __global__ __launch_bounds__(kBlock) void tsmm_kernel(long long N, int k, const 
     const int r = e / k;
     xs[r * 64 + (e - r * k)] = xp[e];
   }
+  // coefficient column of this lane: unconditional loads from clamped addresses (all in flight
+  // together), then zero outside k
   double creg[64];
+  const int lc = (lane < k) ? lane : k - 1;
 #pragma unroll
-  for (int l = 0; l < 64; ++l)
-    creg[l] = (lane < k && l < k) ? (TB ? C[(size_t)lane * k + l] : C[(size_t)l * k + lane]) : 0.0;
+  for (int l = 0; l < 64; ++l) {
+    const int l2 = (l < k) ? l : k - 1;
+    creg[l] = TB ? C[(size_t)lc * k + l2] : C[(size_t)l2 * k + lc];
+  }
+#pragma unroll
+  for (int l = 0; l < 64; ++l) creg[l] = (lane < k && l < k) ? creg[l] : 0.0;
   __syncthreads();
   constexpr int RW = kTsRows / 4;   // rows per wave: wave, wave + 4, ...
 #pragma unroll 1
@@ -464,7 +471,9 @@ __global__ __launch_bounds__(kBlock) void tsmm_kernel(long long N, int k, const 
 #pragma unroll
     for (int q = 0; q < RW / 2; ++q) {
       const int rr = wave + 4 * (half * (RW / 2) + q);
-      yv[q] = (accumulate && lane < k && rr < nr) ? Y[(r0 + rr) * k + lane] : 0.0;
+      const int rc = (rr < nr) ? rr : nr - 1;
+      const double y = Y[(r0 + rc) * k + lc];
+      yv[q] = (accumulate && lane < k && rr < nr) ? y : 0.0;
     }
 #pragma unroll 2
     for (int q = 0; q < RW / 2; ++q) {

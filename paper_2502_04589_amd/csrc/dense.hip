@@ -733,22 +733,25 @@ __global__ __launch_bounds__(64) void invit_kernel(int n, int k, const double* _
 // 4a. Gram of the k vectors: G[a][b] = v_a . v_b for a >= b (one thread per pair).
 __global__ __launch_bounds__(kBlock) void vgram_kernel(int n, int k, const double* __restrict__ Vt,
                                                       double* __restrict__ G) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  // one wave per entry (a, b), b <= a: lanes stride the vector index, then a shuffle tree
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = blockIdx.x * (kBlock / 64) + wave;
   if (q >= k * k) return;
   const int a = q / k, b = q % k;
   if (b > a) return;
   const double* va = Vt + (size_t)a * n;
   const double* vb = Vt + (size_t)b * n;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int i = 0;
-  for (; i + 3 < n; i += 4) {
+  double s0 = 0.0, s1 = 0.0;
+  int i = lane;
+  for (; i + 64 < n; i += 128) {
     s0 = fma(va[i], vb[i], s0);
-    s1 = fma(va[i + 1], vb[i + 1], s1);
-    s2 = fma(va[i + 2], vb[i + 2], s2);
-    s3 = fma(va[i + 3], vb[i + 3], s3);
+    s1 = fma(va[i + 64], vb[i + 64], s1);
   }
-  for (; i < n; ++i) s0 = fma(va[i], vb[i], s0);
-  G[(size_t)a * k + b] = (s0 + s1) + (s2 + s3);
+  if (i < n) s0 = fma(va[i], vb[i], s0);
+  double sum = s0 + s1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (lane == 0) G[(size_t)a * k + b] = sum;
 }
 
 // 4b. L = chol(G), G <- L^{-1} (lower), in LDS, one block.  k <= kOrthoMaxK.
@@ -890,6 +893,71 @@ __global__ __launch_bounds__(256) void cholinv256_kernel(int k, double* __restri
   if (tid == 0 && bad) *info = 1;
 }
 
+// 4b''. The same for k <= 64 in one wave.  Cholesky by rows: lane i keeps row i of the
+// trailing matrix in registers (static indices: every loop is unrolled to 64 and guarded by
+// k); at pivot j the scaled column j is broadcast through LDS and each lane updates its row.
+// Inverse by columns: L goes to LDS by rows, lane c forms column c of L^{-1} by forward
+// substitution, reading the rows of L as LDS broadcasts (x[l] = 0 for l < c, so the sums need
+// no lane-dependent bounds).
+__global__ __launch_bounds__(64) void cholinv_wave_kernel(int k, double* __restrict__ G, int* info) {
+  __shared__ double col[64];
+  __shared__ double Ls[64][65];
+  const int i = threadIdx.x;
+  double r[64];
+  // unconditional loads from clamped addresses, all in flight at once, then the selects
+  const int ic = (i < k) ? i : k - 1;
+#pragma unroll
+  for (int l = 0; l < 64; ++l) r[l] = G[ic * k + ((l < k) ? l : k - 1)];
+#pragma unroll
+  for (int l = 0; l < 64; ++l) r[l] = (i < k && l < k && l <= i) ? r[l] : (l == i ? 1.0 : 0.0);
+  double dm = (i < k) ? r[0] : 0.0;
+#pragma unroll
+  for (int l = 1; l < 64; ++l)
+    if (l == i && i < k) dm = r[l];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  const double ptol = k * DBL_EPSILON * dm;   // pivots at or below this count as rank deficiency
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    // pivots j >= k meet the identity padding (d = 1, zero column): no effect
+    const double d = __shfl(r[j], j, 64);
+    bad = bad || (j < k && !(d > ptol));
+    const double pe = (d > 0.0) ? d : 1.0;
+    const double sq = sqrt(pe);
+    const double rs = 1.0 / sq;
+    r[j] = (i > j) ? r[j] * rs : ((i == j) ? sq : r[j]);
+    col[i] = r[j];
+    __syncthreads();
+#pragma unroll
+    for (int l = j + 1; l < 64; ++l) {
+      const double c = col[l];
+      r[l] = (l <= i) ? fma(-r[j], c, r[l]) : r[l];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int l = 0; l < 64; ++l) Ls[i][l] = r[l];
+  __syncthreads();
+  // column c = i of X = L^{-1}
+  const int c = i;
+  double x[64];
+#pragma unroll
+  for (int a = 0; a < 64; ++a) {
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < a; ++l) acc = fma(Ls[a][l], x[l], acc);
+    const double rhs = (a == c) ? 1.0 : -acc;
+    x[a] = (a < c) ? 0.0 : rhs / Ls[a][a];
+  }
+  if (c < k) {
+#pragma unroll
+    for (int a = 0; a < 64; ++a)
+      if (a < k) G[a * k + c] = x[a];
+  }
+  if (i == 0 && bad) *info = 1;
+}
+
 // 4c. Vo = L^{-1} Vi in the vector index: vo_j = sum_{l <= j} Li[j][l] vi_l.
 __global__ __launch_bounds__(kBlock) void vorth_apply_kernel(int n, int k, const double* __restrict__ Li,
                                                             const double* __restrict__ Vi,
@@ -1018,7 +1086,7 @@ size_t syev_work_doubles(int n, int k) {
 int syev_max_k() { return kOrthoMaxK; }
 
 void launch_cholinv(int k, double* G, int* info, hipStream_t s) {
-  if (k <= 64) cholinv256_kernel<<<1, 256, 0, s>>>(k, G, info);
+  if (k <= 64) cholinv_wave_kernel<<<1, 64, 0, s>>>(k, G, info);
   else cholinv_kernel<<<1, kDenseThreads, 0, s>>>(k, G, info);
 }
 
@@ -1034,7 +1102,7 @@ void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* w
   unsigned* coop_counter = (unsigned*)(xchg + 4 * kCoopMaxN);
   int* coop_err = (int*)(coop_counter + 1);
   zero_info_kernel<<<1, 1, 0, s>>>(info);
-  const unsigned gb = (unsigned)((k * k + kBlock - 1) / kBlock);
+  const unsigned gb = (unsigned)((k * k + kBlock / 64 - 1) / (kBlock / 64));   // vgram: one wave per entry
   const unsigned ab = (unsigned)(((long long)n * k + kBlock - 1) / kBlock);
   // cooperative path: NW blocks whose row slabs fit in LDS
   int NW = 0;
@@ -1077,7 +1145,7 @@ void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* w
 int syev_max_n() { return kSyevMaxN; }
 
 void launch_vorth2(int n, int k, double* Vt, double* Vt2, double* G, int* info, hipStream_t s) {
-  const unsigned gb = (unsigned)((k * k + kBlock - 1) / kBlock);
+  const unsigned gb = (unsigned)((k * k + kBlock / 64 - 1) / (kBlock / 64));   // vgram: one wave per entry
   const unsigned ab = (unsigned)(((long long)n * k + kBlock - 1) / kBlock);
   for (int pass = 0; pass < 2; ++pass) {
     vgram_kernel<<<gb, kBlock, 0, s>>>(n, k, pass ? Vt2 : Vt, G);

@@ -338,6 +338,76 @@ __global__ __launch_bounds__(kBlock) void restrict_flat_kernel(int mf, int mc, u
   xc[q] = (T)s;
 }
 
+// Prolongation by coarse cells: thread (group g, column) with g = (gx, gy, gz), each in
+// [-1, mc - 1], owns the fine nodes 2g+1 (on coarse node g, weight 1) and 2g+2 (between coarse
+// nodes g and g+1, weights 1/2) per axis: 2^d fine nodes from the 2^d coarse corners, so every
+// coarse value is read about once per cell instead of once per fine node.  Corners outside
+// [0, mc) are the Dirichlet boundary (zero); fine nodes 2g+1 with g = -1 do not exist.
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void prolong_cell_kernel(int mf, int mc, unsigned k, const T* __restrict__ xc,
+                                                             T* __restrict__ xf, int mode) {
+  const unsigned ng = (unsigned)mc + 1;
+  unsigned G = ng * ng;
+  if (DIM == 3) G *= ng;
+  const unsigned q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= G * k) return;
+  unsigned grp, col;
+  flat_split(q, k, grp, col);
+  int gx, gy, gz;
+  node_xyz32<DIM>(grp, ng, gx, gy, gz);
+  gx -= 1;
+  gy -= 1;
+  gz -= (DIM == 3) ? 1 : 0;
+  // corners (unconditional loads from clamped addresses, zeroed outside the mesh)
+  constexpr int NZ = (DIM == 3) ? 2 : 1;
+  double v[NZ][2][2];
+#pragma unroll
+  for (int cz = 0; cz < NZ; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+        const int X = gx + cx, Y = gy + cy, Z = (DIM == 3) ? gz + cz : 0;
+        const bool in = X >= 0 && X < mc && Y >= 0 && Y < mc && (DIM == 2 || (Z >= 0 && Z < mc));
+        const int Xc = min(max(X, 0), mc - 1), Yc = min(max(Y, 0), mc - 1), Zc = (DIM == 3) ? min(max(Z, 0), mc - 1) : 0;
+        const unsigned cn = (unsigned)Xc + (unsigned)mc * ((unsigned)Yc + (DIM == 3 ? (unsigned)mc * (unsigned)Zc : 0u));
+        const double val = (double)xc[(size_t)cn * k + col];
+        v[cz][cy][cx] = in ? val : 0.0;
+      }
+  // separable interpolation: per axis, a = corner 0 (weight 1), b = (corner 0 + corner 1) / 2
+  double wx[NZ][2][2];                          // [cz][cy][a/b]
+#pragma unroll
+  for (int cz = 0; cz < NZ; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy) {
+      wx[cz][cy][0] = v[cz][cy][0];
+      wx[cz][cy][1] = 0.5 * (v[cz][cy][0] + v[cz][cy][1]);
+    }
+  double wy[NZ][2][2];                          // [cz][ya/yb][xa/xb]
+#pragma unroll
+  for (int cz = 0; cz < NZ; ++cz)
+#pragma unroll
+    for (int sx = 0; sx < 2; ++sx) {
+      wy[cz][0][sx] = wx[cz][0][sx];
+      wy[cz][1][sx] = 0.5 * (wx[cz][0][sx] + wx[cz][1][sx]);
+    }
+#pragma unroll
+  for (int sz = 0; sz < NZ; ++sz)
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx) {
+        const double val = (DIM == 3) ? (sz ? 0.5 * (wy[0][sy][sx] + wy[1][sy][sx]) : wy[0][sy][sx]) : wy[0][sy][sx];
+        const int fx = 2 * gx + 1 + sx, fy = 2 * gy + 1 + sy, fz = (DIM == 3) ? 2 * gz + 1 + sz : 0;
+        if (fx < 0 || fy < 0 || fz < 0) continue;                 // fine node 2g+1 with g = -1
+        const unsigned fn = (unsigned)fx + (unsigned)mf * ((unsigned)fy + (DIM == 3 ? (unsigned)mf * (unsigned)fz : 0u));
+        T* dst = xf + (size_t)fn * k + col;
+        if (mode == 0) *dst = (T)val;
+        else if (mode == 1) *dst = (T)((double)*dst + val);
+        else *dst = (T)((double)*dst - val);
+      }
+}
+
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void prolong_flat_kernel(int mf, int mc, unsigned k, const T* __restrict__ xc,
                                                              T* __restrict__ xf, int mode) {
@@ -673,9 +743,10 @@ void launch_restrict(int dim, int mf, int mc, int k, const void* xf, void* xc, i
 template <typename T>
 static void launch_prolong_t(int dim, int mf, int mc, int k, const T* xc, T* xf, int mode, hipStream_t s) {
   long long Nf = (long long)mf * mf * (dim == 3 ? mf : 1);
-  if (Nf * k <= kFlatMax) {
-    if (dim == 3) prolong_flat_kernel<3, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode);
-    else prolong_flat_kernel<2, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode);
+  const long long G = (long long)(mc + 1) * (mc + 1) * (dim == 3 ? (mc + 1) : 1);
+  if (Nf * k <= kFlatMax && G * k <= kFlatMax) {
+    if (dim == 3) prolong_cell_kernel<3, T><<<nblk(G * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode);
+    else prolong_cell_kernel<2, T><<<nblk(G * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode);
     return;
   }
   if (dim == 3) prolong_kernel<3, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);

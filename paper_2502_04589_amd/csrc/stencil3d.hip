@@ -397,8 +397,9 @@ int fine3_max_spatial_blocks(int m) {
 
 int fine3_default_nzc(int m) {
   // Every block marches its z-run sequentially, so short runs give the grid more
-  // parallelism; each run re-reads two halo planes.
-  const int zl = g_zrun > 0 ? g_zrun : 16;
+  // parallelism; each run re-reads two halo planes.  Coarse levels (m < 48) take runs of 4:
+  // their grids are small and their vectors stay in L2.
+  const int zl = g_zrun > 0 ? g_zrun : (m >= 48 ? 16 : 4);
   return (m + zl - 1) / zl;
 }
 
