@@ -218,6 +218,13 @@ pase_status pase_unet_apply(pase_unet* u, int batch, const double* R, const doub
  * pase_unet_adam_step and copied to the device vector G if non-NULL. */
 pase_status pase_unet_loss_grad(pase_unet* u, int batch, const double* R, const double* C, const double* logk,
                                 double* loss_host, float* G);
+/* Output scale fit (done once before training): multiplies the last layer's weights by
+ * s = <N(R), C> / <N(R), N(R)> over the batch, the least-squares scale of the output against the
+ * targets C (device N_0 x batch each).  The network is positively homogeneous in its last layer, so
+ * the fitted output is s N(R) (s < 0 flips the sign).  s goes to *scale_host (may be NULL).
+ * PASE_E_BREAKDOWN if s is zero or not finite (weights unchanged). */
+pase_status pase_unet_fit_scale(pase_unet* u, int batch, const double* R, const double* C, const double* logk,
+                                double* scale_host);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the gradient of the last loss_grad. */
 pase_status pase_unet_adam_step(pase_unet* u, float lr);
 

@@ -65,6 +65,8 @@ SIGNATURES = [
     ("pase_unet_loss_grad", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_double), C.c_void_p]),
     ("pase_unet_adam_step", C.c_int, [C.c_void_p, C.c_float]),
+    ("pase_unet_fit_scale", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(C.c_double)]),
     ("pase_attach_unet", C.c_int, [C.c_void_p, C.c_void_p]),
     ("pase_harvest", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pase_node_logk", C.c_int, [C.c_void_p, C.c_void_p]),

@@ -516,6 +516,11 @@ __global__ void adam_kernel(int n, float lr, float b1, float b2, float eps, floa
   w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
+__global__ void scale_f32_kernel(int n, float a, float* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] *= a;
+}
+
 // W[o][ci][co] (FP32) -> Wf[co][o cinp + ci] and Wb[ci][(26 - o) cout + co] (BF16); cinp >= cin is
 // the padded channel count of the forward layout (the padding entries stay zero)
 __global__ void relayout_kernel(int cin, int cinp, int cout, const float* __restrict__ W, __bf16* __restrict__ Wf,
@@ -974,6 +979,35 @@ pase_status pase_unet_loss_grad(pase_unet* u, int batch, const double* R, const 
     for (int b = 0; b < batch; ++b) l += num[b] / den[b];
     *loss_host = l / batch;
   }
+  return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");
+}
+
+pase_status pase_unet_fit_scale(pase_unet* u, int batch, const double* R, const double* C, const double* logk,
+                                double* scale_host) {
+  if (!u || !R || !C || batch < 1 || batch > u->bmax) return PASE_E_ARG;
+  const long long N = u->N[0];
+  prepare_input(u, batch, R, logk);
+  forward(u, batch);
+  output_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, u->y, u->colsq, u->err);
+  launch_coldot(N, batch, u->err, C, u->dpart, coldot_tiles(N, batch), u->cnum, u->stream);
+  launch_coldot(N, batch, u->err, u->err, u->dpart, coldot_tiles(N, batch), u->cden, u->stream);
+  std::vector<double> num(batch), den(batch);
+  if (hipMemcpyAsync(num.data(), u->cnum, sizeof(double) * batch, hipMemcpyDeviceToHost, u->stream) != hipSuccess ||
+      hipMemcpyAsync(den.data(), u->cden, sizeof(double) * batch, hipMemcpyDeviceToHost, u->stream) != hipSuccess ||
+      hipStreamSynchronize(u->stream) != hipSuccess)
+    return ufail(u, PASE_E_HIP, "scale readback failed");
+  double a = 0.0, b = 0.0;
+  for (int j = 0; j < batch; ++j) {
+    a += num[j];
+    b += den[j];
+  }
+  if (!(b > 0.0) || !std::isfinite(a / b) || a == 0.0)
+    return ufail(u, PASE_E_BREAKDOWN, "the network output is zero or orthogonal to the targets");
+  const double sc = a / b;
+  const Layer& l = u->L[10];
+  scale_f32_kernel<<<nb256((long long)l.E()), 256, 0, u->stream>>>((int)l.E(), (float)sc, u->W + l.woff);
+  relayout_all(u);
+  if (scale_host) *scale_host = sc;
   return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");
 }
 

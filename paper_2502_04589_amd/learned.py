@@ -101,6 +101,16 @@ class UNet:
         self._check(self.lib.pase_unet_loss_grad(self.h, k, _ptr(R), _ptr(Cm), _ptr(lk), C.byref(loss), _ptr(G)))
         return float(loss.value), G
 
+    def fit_scale(self, R, Cm, logk=None):
+        """Rescale the last layer so the output best matches Cm in least squares; returns the factor."""
+        k = R.shape[1]
+        R = self._mv(R, k, "R")
+        Cm = self._mv(Cm, k, "C")
+        lk = self._logk(logk)
+        sc = C.c_double(0.0)
+        self._check(self.lib.pase_unet_fit_scale(self.h, k, _ptr(R), _ptr(Cm), _ptr(lk), C.byref(sc)))
+        return float(sc.value)
+
     def adam_step(self, lr):
         self._check(self.lib.pase_unet_adam_step(self.h, C.c_float(lr)))
 
@@ -120,16 +130,19 @@ class UNet:
                  for sh in self.layer_shapes()]
         self.set_weights(torch.cat([p.reshape(-1) for p in parts]))
 
-    def train(self, R, V, logk=None, steps=100, lr=1e-3, seed=0):
+    def train(self, R, V, logk=None, steps=100, lr=1e-3, seed=0, fit_scale=True):
         """Adam on the pairs (R[:, j], V[:, j]) (device N x P each): every step draws batch_max
-        distinct columns (seeded), runs the loss, its gradient and one Adam step.  Returns the
-        loss of every step."""
+        distinct columns (seeded), runs the loss, its gradient and one Adam step.  With fit_scale
+        the output scale is first fitted on one such batch.  Returns the loss of every step."""
         P = R.shape[1]
         R = self._mv(R, P, "R")
         V = self._mv(V, P, "V")
         rng = np.random.default_rng(seed)
         b = min(self.batch_max, P)
         losses = []
+        if fit_scale:
+            cols = torch.from_numpy(rng.choice(P, size=b, replace=False)).to(self.device)
+            self.fit_scale(R.index_select(1, cols).contiguous(), V.index_select(1, cols).contiguous(), logk)
         for _ in range(int(steps)):
             cols = torch.from_numpy(rng.choice(P, size=b, replace=False)).to(self.device)
             Rb = R.index_select(1, cols).contiguous()

@@ -92,6 +92,22 @@ def test_adam_step_matches_formula():
     np.testing.assert_allclose(W1, expect, rtol=1e-5, atol=1e-7)
 
 
+def test_output_scale_fit_matches_oracle():
+    """The fitted scale is the least-squares factor <N(r), c> / <N(r), N(r)> of the oracle network
+    at the same weights, and the output is multiplied by it."""
+    net, W, g, R, logk = setup(seed=6, batch=4)
+    H = multigrid.Hierarchy(3, [16, 8, 4])
+    Cm = H.vcycle(R)
+    Wr = [w.astype(np.float32).astype(np.float64) for w in W]
+    Zr = net.apply(Wr, R, logk)
+    s_ref = float(np.sum(Zr * Cm) / np.sum(Zr * Zr))
+    Z0 = g.apply(dev(R), dev(logk)).cpu().numpy()
+    sc = g.fit_scale(dev(R), dev(Cm), dev(logk))
+    assert abs(sc - s_ref) <= 2e-2 * abs(s_ref), (sc, s_ref)
+    Z1 = g.apply(dev(R), dev(logk)).cpu().numpy()
+    assert relerr(Z1, sc * Z0) < 1e-2
+
+
 def test_training_steps_reduce_the_loss():
     """A handful of GPU Adam steps on fixed (r, V(r)) pairs lower the relative loss."""
     net, W, g, R, logk = setup(seed=4, batch=4)
@@ -215,3 +231,50 @@ def test_learned_form_needs_a_network():
     s = Solver(3, LEVELS, None, nev_max=2, precision="learned")
     with pytest.raises(PaseError):
         s.solve(2, 1e-8, dev(synth.initial_vectors(15 ** 3, 2, 0)))
+
+
+def test_trained_network_gain_over_untrained_and_vcycle():
+    """What training gains: on a held-out block, one CG step preconditioned by the trained network
+    reduces the residual more than one with the untrained network (the same initial weights), and
+    its output is closer to the V-cycle it imitates.  The ratio against the plain V-cycle step is
+    reported (a measurement, not pinned: the network imitates one V-cycle)."""
+    from paper_2502_04589_amd import Solver, UNet
+    k = 8
+    kap = None            # constant coefficient, as the benchmark's workload
+    src = Solver(3, LEVELS, kap, nev_max=k, max_outer=1)
+    lam, U, _ = src.solve(k, 1e-8, dev(synth.initial_vectors(15 ** 3, k, 3)), raise_notconv=False)
+    s = Solver(3, LEVELS, kap, nev_max=k, precision="learned")
+    Rs, Vs = [], []
+    for _ in range(8):
+        R, V = s.harvest(lam, U)
+        Rs.append(R)
+        Vs.append(V)
+        lam, U = src.correction(lam, U)
+    R = torch.cat(Rs, 1).contiguous()
+    V = torch.cat(Vs, 1).contiguous()
+    logk = s.node_logk()
+    net = UNet(16, batch_max=k)
+    net.init_weights(5)
+    untrained = UNet(16, batch_max=k)
+    untrained.init_weights(5)
+    losses = net.train(R, V, logk, steps=200, lr=1e-3, seed=0)
+    assert np.mean(losses[-10:]) < 0.5 * losses[0], losses[::15]
+    # held-out block: another start seed after 2 plain corrections
+    held = Solver(3, LEVELS, kap, nev_max=k, max_outer=2)
+    lam, U, _ = held.solve(k, 1e-8, dev(synth.initial_vectors(15 ** 3, k, 4)), raise_notconv=False)
+    AU, MU = held.apply(0, U)
+    rhs = MU * torch.from_numpy(lam).cuda()
+    r0 = torch.linalg.norm(rhs - AU, dim=0)
+    ratio = {}
+    for name, prec, nn in (("vcycle", "fp64", None), ("trained", "learned", net), ("untrained", "learned", untrained)):
+        one = Solver(3, LEVELS, kap, nev_max=k, precision=prec, cg_steps=1)
+        if nn is not None:
+            one.attach(nn)
+        W = one.pcg(lam, U)
+        ratio[name] = float(torch.median(torch.linalg.norm(rhs - one.apply(0, W)[0], dim=0) / r0))
+    Rh, Vh = s.harvest(lam, U)
+    err = {name: float(torch.linalg.norm(nn.apply(Rh, logk) - Vh) / torch.linalg.norm(Vh))
+           for name, nn in (("trained", net), ("untrained", untrained))}
+    print("one-step ||r1||/||r0|| (median):", ratio, "relative error against V(r):", err)
+    assert err["trained"] < 0.5 * err["untrained"], err
+    assert ratio["trained"] < ratio["untrained"], ratio
