@@ -113,11 +113,12 @@ __global__ void fill_int_kernel(int n, int v, int* p) {
 
 template <typename T>
 __global__ void axpy2_kernel(long long N, int k, const double* __restrict__ alpha, const T* __restrict__ P,
-                             const T* __restrict__ Q, T* __restrict__ X, T* __restrict__ R) {
+                             const T* __restrict__ Q, const T* Xin, T* X, T* __restrict__ R) {
+  // X = Xin + alpha P (Xin may be X), R -= alpha Q
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * k) return;
   const double a = alpha[i % k];
-  X[i] = (T)fma(a, (double)P[i], (double)X[i]);
+  X[i] = (T)fma(a, (double)P[i], (double)Xin[i]);
   R[i] = (T)fma(-a, (double)Q[i], (double)R[i]);
 }
 
@@ -446,11 +447,22 @@ __global__ __launch_bounds__(kBlock) void tsmm_kernel(long long N, int k, const 
   const long long r0 = (long long)blockIdx.x * kTsRows;
   const int nr = (N - r0 < kTsRows) ? (int)(N - r0) : kTsRows;
   const double* __restrict__ xp = X + r0 * k;
-  for (int e = tid; e < kTsRows * 64; e += kBlock) xs[e] = 0.0;
-  __syncthreads();
-  for (int e = tid; e < nr * k; e += kBlock) {
-    const int r = e / k;
-    xs[r * 64 + (e - r * k)] = xp[e];
+  // stage the chunk: slot s = (row s / 64, column s % 64), zero outside (nr, k); the loads are
+  // unconditional from clamped addresses so all of a thread's are in flight together
+  constexpr int SE = kTsRows * 64 / kBlock;
+  double sv[SE];
+#pragma unroll
+  for (int u = 0; u < SE; ++u) {
+    const int sl = tid + kBlock * u;
+    const int r = sl >> 6, c = sl & 63;
+    const int rc = (r < nr) ? r : nr - 1, cc = (c < k) ? c : k - 1;
+    sv[u] = xp[rc * k + cc];
+  }
+#pragma unroll
+  for (int u = 0; u < SE; ++u) {
+    const int sl = tid + kBlock * u;
+    const int r = sl >> 6, c = sl & 63;
+    xs[sl] = (r < nr && c < k) ? sv[u] : 0.0;
   }
   // coefficient column of this lane: unconditional loads from clamped addresses (all in flight
   // together), then zero outside k
@@ -549,7 +561,12 @@ void launch_pcg_beta(int k, const double* rn, const double* ro, double* beta, hi
 
 void launch_axpy2(long long N, int k, const double* alpha, const double* P, const double* Q, double* X, double* R,
                   hipStream_t s) {
-  axpy2_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, R);
+  axpy2_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, X, R);
+}
+
+void launch_axpy2_from(long long N, int k, const double* alpha, const double* P, const double* Q, const double* Xin,
+                       double* X, double* R, hipStream_t s) {
+  axpy2_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, Xin, X, R);
 }
 
 void launch_flex_beta(int k, const double* a, const double* b, const double* c, int* mask, double* beta,
@@ -573,7 +590,7 @@ void launch_xpby(long long N, int k, const double* Z, const double* beta, double
 
 void launch_axpy2_f32(long long N, int k, const double* alpha, const float* P, const float* Q, float* X, float* R,
                       hipStream_t s) {
-  axpy2_kernel<float><<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, R);
+  axpy2_kernel<float><<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, P, Q, X, X, R);
 }
 
 void launch_xpby_f32(long long N, int k, const float* Z, const double* beta, float* P, hipStream_t s) {

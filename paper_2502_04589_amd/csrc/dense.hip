@@ -920,21 +920,25 @@ __global__ __launch_bounds__(64) void cholinv_wave_kernel(int k, double* __restr
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < 64; ++j) {
-    // pivots j >= k meet the identity padding (d = 1, zero column): no effect
-    const double d = __shfl(r[j], j, 64);
-    bad = bad || (j < k && !(d > ptol));
-    const double pe = (d > 0.0) ? d : 1.0;
-    const double sq = sqrt(pe);
-    const double rs = 1.0 / sq;
-    r[j] = (i > j) ? r[j] * rs : ((i == j) ? sq : r[j]);
-    col[i] = r[j];
-    __syncthreads();
+    if (j < k) {                              // uniform; the unrolled body keeps static indices
+      // one LDS exchange per pivot: the unscaled column j (its entry j is the pivot d); row i
+      // becomes L[i][j] = a_ij / sqrt(d) and the trailing update is a_il -= a_ij a_lj / d
+      col[i] = r[j];
+      __syncthreads();
+      const double d = col[j];
+      bad = bad || !(d > ptol);
+      const double pe = (d > 0.0) ? d : 1.0;
+      const double rd = 1.0 / pe;
+      const double sq = sqrt(pe);
+      const double lij = r[j] * rd;
 #pragma unroll
-    for (int l = j + 1; l < 64; ++l) {
-      const double c = col[l];
-      r[l] = (l <= i) ? fma(-r[j], c, r[l]) : r[l];
+      for (int l = j + 1; l < 64; ++l) {
+        const double c = col[l];
+        r[l] = (l <= i) ? fma(-lij, c, r[l]) : r[l];
+      }
+      r[j] = (i > j) ? r[j] / sq : ((i == j) ? sq : r[j]);
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int l = 0; l < 64; ++l) Ls[i][l] = r[l];
@@ -944,10 +948,11 @@ __global__ __launch_bounds__(64) void cholinv_wave_kernel(int k, double* __restr
   double x[64];
 #pragma unroll
   for (int a = 0; a < 64; ++a) {
-    double acc = 0.0;
+    if (a >= k) continue;                     // uniform
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};     // four short chains instead of one long one
 #pragma unroll
-    for (int l = 0; l < a; ++l) acc = fma(Ls[a][l], x[l], acc);
-    const double rhs = (a == c) ? 1.0 : -acc;
+    for (int l = 0; l < a; ++l) acc[l & 3] = fma(Ls[a][l], x[l], acc[l & 3]);
+    const double rhs = (a == c) ? 1.0 : -((acc[0] + acc[1]) + (acc[2] + acc[3]));
     x[a] = (a < c) ? 0.0 : rhs / Ls[a][a];
   }
   if (c < k) {

@@ -110,7 +110,10 @@ void launch_reduce_partials(int tiles, int width, const double* partial, double*
 void launch_pcg_alpha(int k, const double* rho, const double* pq, double* alpha, hipStream_t s);
 void launch_pcg_beta(int k, const double* rho_new, const double* rho_old, double* beta, hipStream_t s);
 void launch_axpy2(long long N, int k, const double* alpha, const double* P, const double* Q, double* X,
-                  double* R, hipStream_t s);                    // X += a P ; R -= a Q
+                  double* R, hipStream_t s);
+// X = Xin + alpha P, R -= alpha Q (column-wise alpha); X and Xin distinct buffers
+void launch_axpy2_from(long long N, int k, const double* alpha, const double* P, const double* Q, const double* Xin,
+                       double* X, double* R, hipStream_t s);                    // X += a P ; R -= a Q
 void launch_xpby(long long N, int k, const double* Z, const double* beta, double* P, hipStream_t s);  // P = Z + b P
 void launch_copy(size_t n, const double* src, double* dst, hipStream_t s);
 // Gram G = X^T Y (k x k) by FP64 MFMA over row chunks, fixed-order reduction

@@ -377,18 +377,21 @@ void coldot(pase_handle* h, long long N, int k, const double* x, const double* y
   launch_coldot(N, k, x, y, h->partial, 0, out, h->stream);
 }
 
-// s PCG steps per column on A x = b from x (in X), with residual R = b - A x given.
-void pcg(pase_handle* h, int k, double* X, double* R) {
+// s PCG steps per column on A x = b from x0 (X0, not modified) into X, with residual
+// R = b - A x0 given.  p_0 = z_0 by exchanging the Z and P buffers, and the first update reads
+// x0 from X0, so neither start needs a copy.
+void pcg(pase_handle* h, int k, const double* X0, double* X, double* R) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   vcycle(h, 0, k, R, h->Z);
-  launch_copy((size_t)N * k, h->Z, h->P, s);
-  coldot(h, N, k, R, h->Z, h->rho);
+  std::swap(h->Z, h->P);
+  coldot(h, N, k, R, h->P, h->rho);
   for (int j = 0; j < h->opt.cg_steps; ++j) {
     apply_AM(h, 0, k, h->P, h->Q, nullptr);
     coldot(h, N, k, h->P, h->Q, h->pq);
     launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
-    launch_axpy2(N, k, h->alpha, h->P, h->Q, X, R, s);
+    if (j == 0 && X0 != X) launch_axpy2_from(N, k, h->alpha, h->P, h->Q, X0, X, R, s);
+    else launch_axpy2(N, k, h->alpha, h->P, h->Q, X, R, s);
     if (j + 1 < h->opt.cg_steps) {
       vcycle(h, 0, k, R, h->Z);
       coldot(h, N, k, R, h->Z, h->rho2);
@@ -410,8 +413,8 @@ void pcg_correction_f32(pase_handle* h, int k, const double* U, const double* R,
   float* r = h->R32;
   launch_cg_start_f32(nk, R, r, h->E32, s);
   vcycle(h, B, 0, k, r, h->Z32);
-  launch_copy_f32(nk, h->Z32, h->P32, s);
-  launch_coldot_f32(N, k, r, h->Z32, h->partial, h->rho, s);
+  std::swap(h->Z32, h->P32);                                  // p_0 = z_0
+  launch_coldot_f32(N, k, r, h->P32, h->partial, h->rho, s);
   for (int j = 0; j < h->opt.cg_steps; ++j) {
     stencil_op(h, 0, k, EPI_AM, h->P32, nullptr, h->Q32, nullptr, 1);
     launch_coldot_f32(N, k, h->P32, h->Q32, h->partial, h->pq, s);
@@ -446,7 +449,7 @@ pase_status learned_precond(pase_handle* h, int k, const double* R, double* Z, i
 // column whose residual norm does not fall below half its previous value switches to the
 // V-cycle for the remaining steps; the step is kept and the recurrence restarts (beta = 0), so
 // the remaining steps are V-cycle PCG from that iterate.  Returns the number of switches.
-pase_status learned_pcg(pase_handle* h, int k, double* X, double* R, int* switches) {
+pase_status learned_pcg(pase_handle* h, int k, const double* X0, double* X, double* R, int* switches) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   *switches = 0;
@@ -455,14 +458,15 @@ pase_status learned_pcg(pase_handle* h, int k, double* X, double* R, int* switch
   std::vector<int> mk(k);
   pase_status st = learned_precond(h, k, R, h->Z, non);
   if (st) return st;
-  launch_copy((size_t)N * k, h->Z, h->P, s);
-  coldot(h, N, k, R, h->Z, h->rho);
+  std::swap(h->Z, h->P);                                      // p_0 = z_0
+  coldot(h, N, k, R, h->P, h->rho);
   for (int j = 0; j < h->opt.cg_steps; ++j) {
     apply_AM(h, 0, k, h->P, h->Q, nullptr);
     coldot(h, N, k, h->P, h->Q, h->pq);
     launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
     if (non > 0) coldot(h, N, k, R, R, h->rr0);
-    launch_axpy2(N, k, h->alpha, h->P, h->Q, X, R, s);
+    if (j == 0 && X0 != X) launch_axpy2_from(N, k, h->alpha, h->P, h->Q, X0, X, R, s);
+    else launch_axpy2(N, k, h->alpha, h->P, h->Q, X, R, s);
     if (non > 0) {
       coldot(h, N, k, R, R, h->rr1);
       launch_fallback(k, 0.5, h->rr1, h->rr0, h->netmask, s);
@@ -476,7 +480,7 @@ pase_status learned_pcg(pase_handle* h, int k, double* X, double* R, int* switch
         *switches += non - c;
         non = c;
       }
-      coldot(h, N, k, R, h->Z, h->rzo);                       // r_{j+1}^T z_j
+      coldot(h, N, k, R, (j == 0) ? h->P : h->Z, h->rzo);     // r_{j+1}^T z_j (p_0 = z_0)
       st = learned_precond(h, k, R, h->Z, non);
       if (st) return st;
       coldot(h, N, k, R, h->Z, h->rho2);                      // r_{j+1}^T z_{j+1}
@@ -523,14 +527,12 @@ pase_status correction(pase_handle* h, int k) {
     pcg_correction_f32(h, k, h->U, h->R, h->X);
   } else if (h->opt.precision == PASE_PREC_LEARNED) {
     if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
-    launch_copy((size_t)N * k, h->U, h->X, s);
     int sw = 0;
-    const pase_status st = learned_pcg(h, k, h->X, h->R, &sw);
+    const pase_status st = learned_pcg(h, k, h->U, h->X, h->R, &sw);
     if (st) return st;
     h->fallbacks += sw;
   } else {
-    launch_copy((size_t)N * k, h->U, h->X, s);
-    pcg(h, k, h->X, h->R);
+    pcg(h, k, h->U, h->X, h->R);
   }
   double* W = h->X;
   // complement: W <- W - P B_H^{-1} P^T M W
@@ -831,15 +833,14 @@ pase_status pase_pcg(pase_handle* h, int k, const double* lambda_host, const dou
   const long long N = h->lev[0].N;
   HIPC(hipMemcpyAsync(h->lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, h->stream));
   eig_residual(h, k, U, h->R);
-  launch_copy((size_t)N * k, U, h->X, h->stream);
   if (h->opt.precision == PASE_PREC_LEARNED) {
     if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
     int sw = 0;
-    st = learned_pcg(h, k, h->X, h->R, &sw);
+    st = learned_pcg(h, k, U, h->X, h->R, &sw);
     if (st) return st;
     h->fallbacks = sw;
   } else {
-    pcg(h, k, h->X, h->R);
+    pcg(h, k, U, h->X, h->R);
   }
   launch_copy((size_t)N * k, h->X, W, h->stream);
   HIPC(hipGetLastError());

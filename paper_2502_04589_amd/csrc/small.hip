@@ -204,17 +204,18 @@ __device__ void lu_factor_r(int k, RLds& L) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int tx = tid & 15, ty = tid >> 4;   // 16 x 32
   for (int j = 0; j < k; ++j) {
-    double c = (lane >= j && lane < k) ? fabs(L.S[lane][j]) : -1.0;
-    int p = lane;
+    // pivot search on one 64-bit key per lane: the bits of |S[lane][j]| (ordered like the
+    // values, being non-negative) with the low 6 bits replaced by 63 - lane, so the maximum
+    // key is the largest magnitude and, among magnitudes equal to 2^-46 relative, the lowest row
+    unsigned long long key = 0ull;
+    if (lane >= j && lane < k)
+      key = ((unsigned long long)__double_as_longlong(fabs(L.S[lane][j])) & ~63ull) | (unsigned long long)(63 - lane);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-      const double c2 = __shfl_xor(c, o, 64);
-      const int p2 = __shfl_xor(p, o, 64);
-      if (c2 > c || (c2 == c && p2 < p)) {
-        c = c2;
-        p = p2;
-      }
+      const unsigned long long k2 = (unsigned long long)__shfl_xor((long long)key, o, 64);
+      key = (k2 > key) ? k2 : key;
     }
+    const int p = 63 - (int)(key & 63ull);
     if (tid == 0) L.ipiv[j] = p;
     if (p != j) {
       for (int t = tid; t < k; t += kRT) {

@@ -242,11 +242,80 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
     st1((sb + 3) & 3, 1, PS1);                                                                          \
     __syncthreads();                                                                                    \
   }
+  // Constant coefficient (residual, sweep and eigen-residual epilogues): reuse along z.  A plane
+  // is read once (9 taps) when it becomes the
+  // newest, and each tap goes into the running sums of the three outputs it touches (its
+  // coefficient depends only on whether the z offset is zero): ra/rm[0] = output z (completed by
+  // plane z+1), [1] = output z+1, [2] = output z+2.  cen[0] is x at output z, cen[1] at z+1.
+  double ra[3][VW], rm[3][VW], cen[2][VW];
+#pragma unroll
+  for (int i = 0; i < VW; ++i) {
+    ra[0][i] = ra[1][i] = ra[2][i] = 0.0;
+    rm[0][i] = rm[1][i] = rm[2][i] = 0.0;
+    cen[0][i] = cen[1][i] = 0.0;
+  }
+  // MODE 0: plane z0-1 (only output z0, offset -1); 1: plane z0 (outputs z0 and z0+1, centre of
+  // z0); 2: plane z+1 in step z (outputs z, z+1, z+2, centre of z+1)
+  auto plane9 = [&](int slot, int mode) {
+#define PASE_TAP9(OX, OY)                                                                            \
+  {                                                                                                  \
+    const V v = sm.xs[slot][ly + 1 + (OY)][lx + 1 + (OX)][qv];                                       \
+    constexpr double sxy = (double)(((OX) == 0 ? 2 : 1) * ((OY) == 0 ? 2 : 1));                      \
+    const double cz = needA ? kpat<OX, OY, 0>(k0, k1, m0, m1) * (2.0 * sxy) : 0.0;                   \
+    const double cn = needA ? kpat<OX, OY, 1>(k0, k1, m0, m1) * sxy : 0.0;                           \
+    constexpr double mxy = (double)(((OX) == 0 ? 4 : 1) * ((OY) == 0 ? 4 : 1));                      \
+    const double mz = mxy * 4.0 * mc3, mn = mxy * mc3;                                               \
+    _Pragma("unroll") for (int i = 0; i < VW; ++i) {                                                 \
+      const double xv = vget<T, VW>(v, i);                                                           \
+      if (mode == 0) {                                                                               \
+        if (needA) ra[0][i] = fma(cn, xv, ra[0][i]);                                                 \
+        if (needM) rm[0][i] = fma(mn, xv, rm[0][i]);                                                 \
+      } else if (mode == 1) {                                                                        \
+        if ((OX) == 0 && (OY) == 0) cen[0][i] = xv;                                                  \
+        if (needA) { ra[0][i] = fma(cz, xv, ra[0][i]); ra[1][i] = fma(cn, xv, ra[1][i]); }           \
+        if (needM) { rm[0][i] = fma(mz, xv, rm[0][i]); rm[1][i] = fma(mn, xv, rm[1][i]); }           \
+      } else {                                                                                       \
+        if ((OX) == 0 && (OY) == 0) cen[1][i] = xv;                                                  \
+        if (needA) {                                                                                 \
+          ra[0][i] = fma(cn, xv, ra[0][i]);                                                          \
+          ra[1][i] = fma(cz, xv, ra[1][i]);                                                          \
+          ra[2][i] = fma(cn, xv, ra[2][i]);                                                          \
+        }                                                                                            \
+        if (needM) {                                                                                 \
+          rm[0][i] = fma(mn, xv, rm[0][i]);                                                          \
+          rm[1][i] = fma(mz, xv, rm[1][i]);                                                          \
+          rm[2][i] = fma(mn, xv, rm[2][i]);                                                          \
+        }                                                                                            \
+      }                                                                                              \
+    }                                                                                                \
+  }
+    PASE_TAP9(-1, -1) PASE_TAP9(0, -1) PASE_TAP9(1, -1)
+    PASE_TAP9(-1, 0)  PASE_TAP9(0, 0)  PASE_TAP9(1, 0)
+    PASE_TAP9(-1, 1)  PASE_TAP9(0, 1)  PASE_TAP9(1, 1)
+#undef PASE_TAP9
+  };
   auto compute_plane = [&](int z, int sb, const V& bv) {
     double ax[VW], mx[VW], center[VW];
 #pragma unroll
     for (int i = 0; i < VW; ++i) ax[i] = mx[i] = center[i] = 0.0;
     double dcoef = 1.0;
+    if constexpr (CONSTK && EPI != EPI_AM) {
+      plane9((sb + 2) & 3, 2);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        ax[i] = ra[0][i];
+        mx[i] = rm[0][i];
+        center[i] = cen[0][i];
+        ra[0][i] = ra[1][i];
+        ra[1][i] = ra[2][i];
+        ra[2][i] = 0.0;
+        rm[0][i] = rm[1][i];
+        rm[1][i] = rm[2][i];
+        rm[2][i] = 0.0;
+        cen[0][i] = cen[1][i];
+      }
+      dcoef = kpat<0, 0, 0>(k0, k1, m0, m1) * 8.0;
+    } else {
 #define PASE_TAP(OX, OY, OZ)                                                                       \
   {                                                                                                \
     const V v = sm.xs[(sb + 1 + (OZ)) & 3][ly + 1 + (OY)][lx + 1 + (OX)][qv];                      \
@@ -275,6 +344,7 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
     PASE_TAP(-1, 0, 1)   PASE_TAP(0, 0, 1)   PASE_TAP(1, 0, 1)
     PASE_TAP(-1, 1, 1)   PASE_TAP(0, 1, 1)   PASE_TAP(1, 1, 1)
 #undef PASE_TAP
+    }
     const long long off = (long long)z * plane + cbase;
     V o1, o2;
     if (EPI == EPI_AM) {
@@ -303,6 +373,10 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
       stvec((T*)a.out1, off, o1);
     }
   };
+  if (CONSTK && EPI != EPI_AM && nodeok && colv < k) {
+    plane9(0, 0);       // plane z0 - 1
+    plane9(1, 1);       // plane z0
+  }
   for (int z = z0; z < z1; z += 2) {
     PASE_STEP(z, pB0, pB1, pA0, pA1, bA, bB)
     if (z + 1 < z1) PASE_STEP(z + 1, pA0, pA1, pB0, pB1, bB, bA)
