@@ -460,9 +460,15 @@ __global__ __launch_bounds__(256) void wgrad_tile_kernel(int m, int batch, const
 __global__ void wgrad_reduce_kernel(int tiles, int E, const float* __restrict__ partial, float* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
-  float s = 0.f;
-  for (int t = 0; t < tiles; ++t) s += partial[(size_t)t * E + e];
-  out[e] = s;
+  // eight independent sums (t mod 8) so eight loads are in flight at a time; fixed order
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int t = 0;
+  for (; t + 8 <= tiles; t += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += partial[(size_t)(t + u) * E + e];
+  }
+  for (int u = 0; t < tiles; ++t, ++u) s[u] += partial[(size_t)t * E + e];
+  out[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // ---------------------------------------------------------------- loss
