@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kBlock) void coldot_kernel(long long N, int k, cons
     for (long long r = r0 + slot; r < r1; r += slots) acc = fma((double)X[r * k + col], (double)Y[r * k + col], acc);
   red[threadIdx.x] = acc;
   __syncthreads();
-  if (threadIdx.x < k) {
+  if ((int)threadIdx.x < k) {
     double s = 0.0;
     for (int q = 0; q < slots; ++q) s += red[q * k + threadIdx.x];
     partial[(size_t)tile * k + threadIdx.x] = s;

@@ -35,20 +35,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Fixed-order block sum; every thread gets the result.  Uses red[kDenseWaves].
-__device__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < kDenseWaves; ++w) s += red[w];
-  return s;
-}
-
-// A pivot at or below n * eps * max_i A[i][i] counts as a breakdown (numerically
-// rank-deficient Gram matrices are reported, not factored).
 // Fixed-order block sum with one barrier: alternate between two scratch rows
 // (the barrier of the call in between orders reuse of a row).
 __device__ double block_sum1(double v, double (*red)[kDenseWaves], int& parity) {
@@ -63,6 +49,9 @@ __device__ double block_sum1(double v, double (*red)[kDenseWaves], int& parity) 
   return s;
 }
 
+// Cholesky of an n x n SPD matrix in place (lower), one block.  A pivot at or below
+// n * eps * max_i A[i][i] counts as a breakdown (numerically rank-deficient Gram matrices are
+// reported, not factored).
 __global__ __launch_bounds__(kDenseThreads) void cholesky_kernel(int n, double* A, int lda, int* info) {
   __shared__ int fail;
   __shared__ double ptol;
@@ -825,75 +814,7 @@ __global__ __launch_bounds__(kDenseThreads) void cholinv_kernel(int k, double* _
   if (tid == 0 && bad) *info = 1;
 }
 
-// 4b'. The same for k <= 64 with 256 threads: right-looking Cholesky with one
-// barrier per pivot (16 x 16 thread tiles over the trailing triangle, column
-// scaling deferred by one step), then the inverse by columns (one thread per
-// column) into a separate LDS array, so the loads of a column's inner products
-// do not wait on its stores.
-__global__ __launch_bounds__(256) void cholinv256_kernel(int k, double* __restrict__ G, int* info) {
-  __shared__ double L[64][65];
-  __shared__ double X[64][65];   // X[c][i] = (L^{-1})[i][c]
-  __shared__ double dinv[64];
-  __shared__ double wmax[4];
-  __shared__ int bad;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = tid & 15, ty = tid >> 4;
-  if (tid == 0) bad = 0;
-  double dm = 0.0;
-  for (int q = tid; q < k * k; q += 256) {
-    const int a = q / k, b = q - (q / k) * k;
-    const double g = G[q];
-    L[a][b] = (b <= a) ? g : 0.0;
-    if (a == b) dm = fmax(dm, g);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
-  if (lane == 0) wmax[wave] = dm;
-  __syncthreads();
-  dm = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
-  const double ptol = k * DBL_EPSILON * dm;   // pivots at or below this count as rank deficiency
-  double prev = 1.0;
-  for (int j = 0; j < k; ++j) {
-    const double dj = L[j][j];
-    const double pe = (dj > 0.0) ? dj : 1.0;
-    if (tid == 0 && !(dj > ptol)) bad = 1;
-    if (j > 0)
-      for (int i = j - 1 + tid; i < k; i += 256) L[i][j - 1] = (i == j - 1) ? 1.0 / prev : L[i][j - 1] * prev;
-    const double rp = 1.0 / pe;
-    for (int i = j + 1 + ty; i < k; i += 16) {
-      const double lij = L[i][j] * rp;
-      for (int l = j + 1 + tx; l <= i; l += 16) L[i][l] = fma(-lij, L[l][j], L[i][l]);
-    }
-    prev = 1.0 / sqrt(pe);
-    __syncthreads();
-  }
-  if (tid == 0) L[k - 1][k - 1] = 1.0 / prev;
-  __syncthreads();
-  for (int c = tid; c < k; c += 256) dinv[c] = 1.0 / L[c][c];
-  __syncthreads();
-  for (int c = tid; c < k; c += 256) {
-    const double dc = dinv[c];
-    X[c][c] = dc;
-    for (int i = c + 1; i < k; ++i) {
-      double a0 = L[i][c] * dc, a1 = 0.0;
-      int l = c + 1;
-      for (; l + 1 < i; l += 2) {
-        a0 = fma(L[i][l], X[c][l], a0);
-        a1 = fma(L[i][l + 1], X[c][l + 1], a1);
-      }
-      if (l < i) a0 = fma(L[i][l], X[c][l], a0);
-      X[c][i] = -(a0 + a1) * dinv[i];
-    }
-  }
-  __syncthreads();
-  for (int q = tid; q < k * k; q += 256) {
-    const int i = q / k, c = q - (q / k) * k;
-    G[q] = (i >= c) ? X[c][i] : 0.0;
-  }
-  if (tid == 0 && bad) *info = 1;
-}
-
-// 4b''. The same for k <= 64 in one wave.  Cholesky by rows: lane i keeps row i of the
+// 4b'. The same for k <= 64 in one wave.  Cholesky by rows: lane i keeps row i of the
 // trailing matrix in registers (static indices: every loop is unrolled to 64 and guarded by
 // k); at pivot j the scaled column j is broadcast through LDS and each lane updates its row.
 // Inverse by columns: L goes to LDS by rows, lane c forms column c of L^{-1} by forward

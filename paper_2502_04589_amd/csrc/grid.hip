@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs a, int slot
     red[1][threadIdx.x] = acc1;
     red[2][threadIdx.x] = acc2;
     __syncthreads();
-    if (threadIdx.x < k) {
+    if ((int)threadIdx.x < k) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
       for (int s = 0; s < slots; ++s) {
         s0 += red[0][s * k + threadIdx.x];
@@ -406,61 +406,6 @@ __global__ __launch_bounds__(kBlock) void prolong_cell_kernel(int mf, int mc, un
         else if (mode == 1) *dst = (T)((double)*dst + val);
         else *dst = (T)((double)*dst - val);
       }
-}
-
-template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void prolong_flat_kernel(int mf, int mc, unsigned k, const T* __restrict__ xc,
-                                                             T* __restrict__ xf, int mode) {
-  unsigned Nf = (unsigned)mf * mf;
-  if (DIM == 3) Nf *= mf;
-  const unsigned q = blockIdx.x * kBlock + threadIdx.x;
-  if (q >= Nf * k) return;
-  unsigned node, col;
-  flat_split(q, k, node, col);
-  int x, y, z;
-  node_xyz32<DIM>(node, (unsigned)mf, x, y, z);
-  // per axis: odd fine coordinate f = 2c+1 sits on coarse node c (weight 1); even f lies
-  // between coarse nodes f/2 - 1 and f/2 (weight 1/2 each, a missing one is the boundary)
-  int lo[3], hi[3];
-  double wl[3], wh[3];
-  const int f[3] = {x, y, z};
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    if (f[d] & 1) {
-      lo[d] = hi[d] = (f[d] - 1) >> 1;
-      wl[d] = 1.0;
-      wh[d] = 0.0;
-    } else {
-      lo[d] = (f[d] >> 1) - 1;
-      hi[d] = f[d] >> 1;
-      wl[d] = (lo[d] >= 0) ? 0.5 : 0.0;
-      wh[d] = (hi[d] < mc) ? 0.5 : 0.0;
-      lo[d] = (lo[d] >= 0) ? lo[d] : hi[d];     // clamp (its weight is 0)
-      hi[d] = (hi[d] < mc) ? hi[d] : lo[d];
-    }
-  }
-  double s = 0.0;
-  const unsigned mcu = (unsigned)mc;
-#pragma unroll
-  for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c) {
-    const int iz = (DIM == 3) ? (c ? hi[2] : lo[2]) : 0;
-    const double wz = (DIM == 3) ? (c ? wh[2] : wl[2]) : 1.0;
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int iy = b ? hi[1] : lo[1];
-      const double wy = b ? wh[1] : wl[1];
-#pragma unroll
-      for (int a2 = 0; a2 < 2; ++a2) {
-        const int ix = a2 ? hi[0] : lo[0];
-        const double w = (a2 ? wh[0] : wl[0]) * wy * wz;
-        const unsigned J = (unsigned)ix + mcu * ((unsigned)iy + (DIM == 3 ? mcu * (unsigned)iz : 0u));
-        if (w != 0.0) s = fma(w, (double)xc[(long long)J * k + col], s);
-      }
-    }
-  }
-  if (mode == 0) xf[q] = (T)s;
-  else if (mode == 1) xf[q] = (T)((double)xf[q] + s);
-  else xf[q] = (T)((double)xf[q] - s);
 }
 
 template <typename T>

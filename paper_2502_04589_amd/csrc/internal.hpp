@@ -33,6 +33,8 @@ enum Epi : int {
   EPI_RESID = 1,    // out1 = b - A x
   EPI_SWEEP = 2,    // out1 = x + omega D^{-1} (b - A x)
   EPI_EIGRES = 3,   // out1 = lambda_j M x - A x; partials of |out1|^2, |M x|^2, x.(M x) per column
+  EPI_AMDOT = 4,    // out1 = A x; partials of x.(A x) per column (3D LDS-staged stencil only)
+  EPI_SWEEPDOT = 5, // out1 = the sweep of EPI_SWEEP; partials of b.out1 per column (3D LDS-staged only)
 };
 
 struct StencilArgs {

@@ -317,8 +317,9 @@ VBufs vbufs(pase_handle* h, int fp32) {
   return v;
 }
 
-// x = V(b) on level l (x must not alias b), in the precision of B
-void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x) {
+// x = V(b) on level l (x must not alias b), in the precision of B.  With dot (level 0 only),
+// dot[j] = b_j^T x_j as well: fused into the last sweep on the 3D path.
+void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x, double* dot = nullptr) {
   hipStream_t s = h->stream;
   if (l == h->L) {
     const int NH = (int)h->lev[l].N;
@@ -343,14 +344,35 @@ void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x
   launch_restrict(h->dim, lv.m, h->lev[l + 1].m, k, B.r[l], B.b[l + 1], B.fp32, s);
   vcycle(h, B, l + 1, k, B.b[l + 1], B.x[l + 1]);
   launch_prolong(h->dim, lv.m, h->lev[l + 1].m, k, B.x[l + 1], cur, 1, B.fp32, s);
+  const bool fuse = dot && l == 0 && h->dim == 3;
   for (int i = 0; i < h->opt.nu; ++i) {
-    stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr, B.fp32);
+    const bool last = i + 1 == h->opt.nu;
+    stencil_op(h, l, k, (fuse && last) ? EPI_SWEEPDOT : EPI_SWEEP, cur, b, oth, nullptr, B.fp32);
     std::swap(cur, oth);
+  }
+  if (fuse) {
+    launch_reduce_partials(eigres_tiles(h, k), k, h->partial, dot, s);
+  } else if (dot) {
+    if (B.fp32) launch_coldot_f32(lv.N, k, (const float*)b, (const float*)x, h->partial, dot, s);
+    else launch_coldot(lv.N, k, (const double*)b, (const double*)x, h->partial, 0, dot, s);
   }
 }
 
-void vcycle(pase_handle* h, int l, int k, const double* b, double* x) {
-  vcycle(h, vbufs(h, 0), l, k, b, x);
+void vcycle(pase_handle* h, int l, int k, const double* b, double* x, double* dot = nullptr) {
+  vcycle(h, vbufs(h, 0), l, k, b, x, dot);
+}
+
+// Q = A P and pq[j] = p_j^T A p_j on level 0 (fused into the stencil on the 3D path)
+void apply_dot(pase_handle* h, int k, const void* P, void* Q, double* pq, int fp32) {
+  const long long N = h->lev[0].N;
+  if (h->dim == 3) {
+    stencil_op(h, 0, k, EPI_AMDOT, P, nullptr, Q, nullptr, fp32);
+    launch_reduce_partials(eigres_tiles(h, k), k, h->partial, pq, h->stream);
+    return;
+  }
+  stencil_op(h, 0, k, EPI_AM, P, nullptr, Q, nullptr, fp32);
+  if (fp32) launch_coldot_f32(N, k, (const float*)P, (const float*)Q, h->partial, pq, h->stream);
+  else launch_coldot(N, k, (const double*)P, (const double*)Q, h->partial, 0, pq, h->stream);
 }
 
 // composite restriction: xc (N_L x k) = P^T xf
@@ -383,18 +405,15 @@ void coldot(pase_handle* h, long long N, int k, const double* x, const double* y
 void pcg(pase_handle* h, int k, const double* X0, double* X, double* R) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
-  vcycle(h, 0, k, R, h->Z);
+  vcycle(h, 0, k, R, h->Z, h->rho);
   std::swap(h->Z, h->P);
-  coldot(h, N, k, R, h->P, h->rho);
   for (int j = 0; j < h->opt.cg_steps; ++j) {
-    apply_AM(h, 0, k, h->P, h->Q, nullptr);
-    coldot(h, N, k, h->P, h->Q, h->pq);
+    apply_dot(h, k, h->P, h->Q, h->pq, 0);
     launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
     if (j == 0 && X0 != X) launch_axpy2_from(N, k, h->alpha, h->P, h->Q, X0, X, R, s);
     else launch_axpy2(N, k, h->alpha, h->P, h->Q, X, R, s);
     if (j + 1 < h->opt.cg_steps) {
-      vcycle(h, 0, k, R, h->Z);
-      coldot(h, N, k, R, h->Z, h->rho2);
+      vcycle(h, 0, k, R, h->Z, h->rho2);
       launch_pcg_beta(k, h->rho2, h->rho, h->beta, s);
       launch_xpby(N, k, h->Z, h->beta, h->P, s);
       std::swap(h->rho, h->rho2);
@@ -412,17 +431,14 @@ void pcg_correction_f32(pase_handle* h, int k, const double* U, const double* R,
   const VBufs B = vbufs(h, 1);
   float* r = h->R32;
   launch_cg_start_f32(nk, R, r, h->E32, s);
-  vcycle(h, B, 0, k, r, h->Z32);
+  vcycle(h, B, 0, k, r, h->Z32, h->rho);
   std::swap(h->Z32, h->P32);                                  // p_0 = z_0
-  launch_coldot_f32(N, k, r, h->P32, h->partial, h->rho, s);
   for (int j = 0; j < h->opt.cg_steps; ++j) {
-    stencil_op(h, 0, k, EPI_AM, h->P32, nullptr, h->Q32, nullptr, 1);
-    launch_coldot_f32(N, k, h->P32, h->Q32, h->partial, h->pq, s);
+    apply_dot(h, k, h->P32, h->Q32, h->pq, 1);
     launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
     launch_axpy2_f32(N, k, h->alpha, h->P32, h->Q32, h->E32, r, s);
     if (j + 1 < h->opt.cg_steps) {
-      vcycle(h, B, 0, k, r, h->Z32);
-      launch_coldot_f32(N, k, r, h->Z32, h->partial, h->rho2, s);
+      vcycle(h, B, 0, k, r, h->Z32, h->rho2);
       launch_pcg_beta(k, h->rho2, h->rho, h->beta, s);
       launch_xpby_f32(N, k, h->Z32, h->beta, h->P32, s);
       std::swap(h->rho, h->rho2);

@@ -52,9 +52,9 @@ __device__ __forceinline__ double kpat(double k0, double k1, double m0, double m
 // vector of a thread's VW consecutive columns: double2 (16 bytes), float2 (8 bytes, k even)
 // or float4 (16 bytes, k a multiple of 4)
 template <typename T, int W> struct Vec;
-template <> struct Vec<double, 2> { typedef double2 type; static constexpr int n = 2; };
-template <> struct Vec<float, 2> { typedef float2 type; static constexpr int n = 2; };
-template <> struct Vec<float, 4> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec<double, 2> { typedef double2 type; };
+template <> struct Vec<float, 2> { typedef float2 type; };
+template <> struct Vec<float, 4> { typedef float4 type; };
 
 template <typename T, int W>
 __device__ __forceinline__ double vget(const typename Vec<T, W>::type& v, int i) {
@@ -159,7 +159,9 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
     if (hslot[u] >= 0) xsflat[slot][hslot[u]] = v;
   };
   const long long cbase = ((long long)gy * m + gx) * k + colv;
-  const bool bneed = (EPI == EPI_RESID || EPI == EPI_SWEEP) && nodeok && colv < k;
+  constexpr bool kSweep = (EPI == EPI_SWEEP || EPI == EPI_SWEEPDOT);
+  constexpr bool kSums1 = (EPI == EPI_AMDOT || EPI == EPI_SWEEPDOT);   // one column sum
+  const bool bneed = (EPI == EPI_RESID || kSweep) && nodeok && colv < k;
   auto bload = [&](int z) -> V {
     const bool ok = bneed && z < z1;
     const T* B = (const T*)a.b;
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
 #define PASE_STEP(z, PL0, PL1, PS0, PS1, BV, BN)                                                       \
   {                                                                                                     \
     const int sb = ((z) - z0) & 3;                                                                      \
-    if (EPI == EPI_RESID || EPI == EPI_SWEEP) BN = bload((z) + 1);                                      \
+    if (EPI == EPI_RESID || kSweep) BN = bload((z) + 1);                                                \
     PL0 = ld1((z) + 3, 0);                                                                              \
     PL1 = ld1((z) + 3, 1);                                                                              \
     if (!CONSTK) {                                                                                      \
@@ -356,11 +358,21 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, vget<T, VW>(bv, i) - ax[i]);
       stvec((T*)a.out1, off, o1);
-    } else if (EPI == EPI_SWEEP) {
+    } else if (kSweep) {
       const double wd = a.omega / dcoef;
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, center[i] + wd * (vget<T, VW>(bv, i) - ax[i]));
       stvec((T*)a.out1, off, o1);
+      if (EPI == EPI_SWEEPDOT) {
+#pragma unroll
+        for (int i = 0; i < VW; ++i) acc0[i] = fma(vget<T, VW>(bv, i), vget<T, VW>(o1, i), acc0[i]);
+      }
+    } else if (EPI == EPI_AMDOT) {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, ax[i]);
+      stvec((T*)a.out1, off, o1);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) acc0[i] = fma(center[i], vget<T, VW>(o1, i), acc0[i]);
     } else {
 #pragma unroll
       for (int i = 0; i < VW; ++i) {
@@ -382,6 +394,20 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
     if (z + 1 < z1) PASE_STEP(z + 1, pA0, pA1, pB0, pB1, bB, bA)
   }
 #undef PASE_STEP
+  if (kSums1) {
+    // one column sum per column: partial[spatial block][column]
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < VW; ++i) sm.red[0][tid * VW + i] = acc0[i];
+    __syncthreads();
+    if (tid < KC && c0 + tid < k) {
+      const int tq = tid / VW, ti = tid % VW;
+      double s0 = 0.0;
+      for (int nd = 0; nd < TX * TY; ++nd) s0 += sm.red[0][(nd * 4 + tq) * VW + ti];
+      const int sbk = (zc * nty + tyi) * ntx + txi;
+      a.partial[(size_t)sbk * k + c0 + tid] = s0;
+    }
+  }
   if (EPI == EPI_EIGRES) {
     __syncthreads();
 #pragma unroll
@@ -484,6 +510,8 @@ void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s) {
       case EPI_RESID: launchv<float, EPI_RESID>(a, s); break;
       case EPI_SWEEP: launchv<float, EPI_SWEEP>(a, s); break;
       case EPI_EIGRES: launchv<float, EPI_EIGRES>(a, s); break;
+      case EPI_AMDOT: launchv<float, EPI_AMDOT>(a, s); break;
+      case EPI_SWEEPDOT: launchv<float, EPI_SWEEPDOT>(a, s); break;
     }
   } else {
     switch (epi) {
@@ -491,6 +519,8 @@ void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s) {
       case EPI_RESID: launchv<double, EPI_RESID>(a, s); break;
       case EPI_SWEEP: launchv<double, EPI_SWEEP>(a, s); break;
       case EPI_EIGRES: launchv<double, EPI_EIGRES>(a, s); break;
+      case EPI_AMDOT: launchv<double, EPI_AMDOT>(a, s); break;
+      case EPI_SWEEPDOT: launchv<double, EPI_SWEEPDOT>(a, s); break;
     }
   }
 }
