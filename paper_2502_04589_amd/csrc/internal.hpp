@@ -35,6 +35,8 @@ enum Epi : int {
   EPI_EIGRES = 3,   // out1 = lambda_j M x - A x; partials of |out1|^2, |M x|^2, x.(M x) per column
   EPI_AMDOT = 4,    // out1 = A x; partials of x.(A x) per column (3D LDS-staged stencil only)
   EPI_SWEEPDOT = 5, // out1 = the sweep of EPI_SWEEP; partials of b.out1 per column (3D LDS-staged only)
+  EPI_SWEEP2 = 6,   // out1 = two damped-Jacobi sweeps from x = 0 with x passed as b (constant
+                    // coefficient, 3D LDS-staged only): x1 = c b, out = x1 + c (b - A x1), c = omega / a_ii
 };
 
 struct StencilArgs {

@@ -333,10 +333,19 @@ void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x
   void* t0 = B.xa[l];
   void* t1 = x;
   // sweeps alternate t0, t1, t0, ...; the last of the 2 nu sweeps lands in t1 = x
-  launch_first_sweep(h->dim, lv.N, k, lv.dinv, h->opt.omega, b, t0, B.fp32, s);
   void* cur = t0;
   void* oth = t1;
-  for (int i = 1; i < h->opt.nu; ++i) {
+  int i0 = 1;
+  if (h->dim == 3 && h->kappa_is_one && h->opt.nu >= 2) {
+    // constant coefficient: the first two sweeps from x = 0 in one pass over b
+    stencil_op(h, l, k, EPI_SWEEP2, b, nullptr, t1, nullptr, B.fp32);
+    cur = t1;
+    oth = t0;
+    i0 = 2;
+  } else {
+    launch_first_sweep(h->dim, lv.N, k, lv.dinv, h->opt.omega, b, t0, B.fp32, s);
+  }
+  for (int i = i0; i < h->opt.nu; ++i) {
     stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr, B.fp32);
     std::swap(cur, oth);
   }

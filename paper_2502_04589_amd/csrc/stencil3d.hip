@@ -358,6 +358,12 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, vget<T, VW>(bv, i) - ax[i]);
       stvec((T*)a.out1, off, o1);
+    } else if (EPI == EPI_SWEEP2) {
+      // the staged planes hold b: x1 = c b, A x1 = c (A b), out = x1 + c (b - A x1)
+      const double c = a.omega / dcoef;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, c * center[i] + c * (center[i] - c * ax[i]));
+      stvec((T*)a.out1, off, o1);
     } else if (kSweep) {
       const double wd = a.omega / dcoef;
 #pragma unroll
@@ -512,6 +518,7 @@ void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s) {
       case EPI_EIGRES: launchv<float, EPI_EIGRES>(a, s); break;
       case EPI_AMDOT: launchv<float, EPI_AMDOT>(a, s); break;
       case EPI_SWEEPDOT: launchv<float, EPI_SWEEPDOT>(a, s); break;
+      case EPI_SWEEP2: launchv<float, EPI_SWEEP2>(a, s); break;
     }
   } else {
     switch (epi) {
@@ -521,6 +528,7 @@ void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s) {
       case EPI_EIGRES: launchv<double, EPI_EIGRES>(a, s); break;
       case EPI_AMDOT: launchv<double, EPI_AMDOT>(a, s); break;
       case EPI_SWEEPDOT: launchv<double, EPI_SWEEPDOT>(a, s); break;
+      case EPI_SWEEP2: launchv<double, EPI_SWEEP2>(a, s); break;
     }
   }
 }
