@@ -379,56 +379,84 @@ __global__ __launch_bounds__(kBlock) void gemm_kernel(int ta, int tb, int M, int
     }
 }
 
-// ---- small GEMM (M <= kSmallM, K <= kSmallK): one block per output row and
-// 64-column chunk; the four waves split K and their partial sums meet in LDS.
-// Latency-oriented: the coarse-space products (N_H x N_H times N_H x k, k x k
-// products) have too few 64 x 64 tiles to fill the chip.
+// ---- small GEMM (M <= kSmallM, K <= kSmallK), latency-oriented: the coarse-space
+// products (N_H x N_H times N_H x k, k x k products) have too few 64 x 64 tiles to
+// fill the chip, so a block takes a few rows and one 64-column chunk and its waves
+// split K.
 constexpr int kSmallM = 4096, kSmallK = 4096;
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void gemm_small_kernel(int ta, int tb, int M, int N, int K, double alpha,
-                                                            const T* __restrict__ A, int lda,
-                                                            const T* __restrict__ B, int ldb, double beta,
-                                                            T* __restrict__ C, int ldc) {
-  __shared__ double arow[kSmallK];
-  __shared__ double part[4][64];
-  const int i = blockIdx.y;
+// Rows i0 .. i0+R-1 of C per block (1024 threads = 16 waves): the R rows of op(A) are staged in LDS,
+// lane j of every wave owns column j of a 64-column slice, the 16 waves split K, and one load of
+// op(B)[kk][j] serves all R rows.  Partial sums meet in LDS in a fixed order.
+constexpr int kSmallWaves = 16;
+
+template <typename T, int R>
+__global__ __launch_bounds__(kSmallWaves * 64) void gemm_small_kernel(int ta, int tb, int M, int N, int K, double alpha,
+                                                                     const T* __restrict__ A, int lda,
+                                                                     const T* __restrict__ B, int ldb, double beta,
+                                                                     T* __restrict__ C, int ldc) {
+  extern __shared__ double gsm[];
+  double* arow = gsm;                                 // [R][K]
+  double* part = gsm + (size_t)R * K;                 // [kSmallWaves][R][64]
+  const int i0 = blockIdx.y * R;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
-  for (int kk = threadIdx.x; kk < K; kk += kBlock)
-    arow[kk] = (double)(ta ? A[(size_t)kk * lda + i] : A[(size_t)i * lda + kk]);
+  for (int e = threadIdx.x; e < R * K; e += kSmallWaves * 64) {
+    const int r = e / K, kk = e - (e / K) * K;
+    const int i = i0 + r;
+    arow[e] = (i < M) ? (double)(ta ? A[(size_t)kk * lda + i] : A[(size_t)i * lda + kk]) : 0.0;
+  }
   __syncthreads();
-  const int kq = (K + 3) / 4;
+  const int kq = (K + kSmallWaves - 1) / kSmallWaves;
   const int k0 = wave * kq, k1 = (k0 + kq < K) ? k0 + kq : K;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
   if (j < N) {
+    const size_t bs = tb ? 1 : (size_t)ldb;           // stride of op(B) along kk
+    const T* __restrict__ bp = tb ? B + (size_t)j * ldb : B + j;
     int kk = k0;
-    if (!tb) {
-      const T* __restrict__ bp = B + j;
-      for (; kk + 4 <= k1; kk += 4) {
-        acc0 = fma(arow[kk], (double)bp[(size_t)kk * ldb], acc0);
-        acc1 = fma(arow[kk + 1], (double)bp[(size_t)(kk + 1) * ldb], acc1);
-        acc2 = fma(arow[kk + 2], (double)bp[(size_t)(kk + 2) * ldb], acc2);
-        acc3 = fma(arow[kk + 3], (double)bp[(size_t)(kk + 3) * ldb], acc3);
+    for (; kk + 4 <= k1; kk += 4) {
+      const double b0 = (double)bp[kk * bs], b1 = (double)bp[(kk + 1) * bs];
+      const double b2 = (double)bp[(kk + 2) * bs], b3 = (double)bp[(kk + 3) * bs];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double* ar = arow + (size_t)r * K + kk;
+        acc[r] = fma(ar[0], b0, fma(ar[1], b1, fma(ar[2], b2, fma(ar[3], b3, acc[r]))));
       }
-      for (; kk < k1; ++kk) acc0 = fma(arow[kk], (double)bp[(size_t)kk * ldb], acc0);
-    } else {
-      const T* __restrict__ bp = B + (size_t)j * ldb;
-      for (; kk + 4 <= k1; kk += 4) {
-        acc0 = fma(arow[kk], (double)bp[kk], acc0);
-        acc1 = fma(arow[kk + 1], (double)bp[kk + 1], acc1);
-        acc2 = fma(arow[kk + 2], (double)bp[kk + 2], acc2);
-        acc3 = fma(arow[kk + 3], (double)bp[kk + 3], acc3);
-      }
-      for (; kk < k1; ++kk) acc0 = fma(arow[kk], (double)bp[kk], acc0);
+    }
+    for (; kk < k1; ++kk) {
+      const double bv = (double)bp[kk * bs];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = fma(arow[(size_t)r * K + kk], bv, acc[r]);
     }
   }
-  part[wave][lane] = (acc0 + acc1) + (acc2 + acc3);
+#pragma unroll
+  for (int r = 0; r < R; ++r) part[(wave * R + r) * 64 + lane] = acc[r];
   __syncthreads();
-  if (wave == 0 && j < N) {
-    const double acc = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-    T* c = C + (size_t)i * ldc + j;
-    *c = (beta == 0.0) ? (T)(alpha * acc) : (T)fma(alpha, acc, beta * (double)*c);
+  if (wave < R) {
+    const int r = wave, i = i0 + r;
+    if (i < M && j < N) {
+      double t = 0.0;
+      for (int w = 0; w < kSmallWaves; ++w) t += part[(w * R + r) * 64 + lane];
+      T* c = C + (size_t)i * ldc + j;
+      *c = (beta == 0.0) ? (T)(alpha * t) : (T)fma(alpha, t, beta * (double)*c);
+    }
+  }
+}
+
+template <typename T>
+void launch_gemm_small(int ta, int tb, int M, int N, int K, double alpha, const T* A, int lda, const T* B, int ldb,
+                       double beta, T* C, int ldc, hipStream_t s) {
+  if (K <= 1024) {
+    constexpr int R = 4;
+    const size_t lds = ((size_t)R * K + (size_t)kSmallWaves * R * 64) * sizeof(double);
+    gemm_small_kernel<T, R><<<dim3((N + 63) / 64, (M + R - 1) / R), kSmallWaves * 64, lds, s>>>(
+        ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  } else {
+    const size_t lds = ((size_t)K + (size_t)kSmallWaves * 64) * sizeof(double);
+    gemm_small_kernel<T, 1><<<dim3((N + 63) / 64, M), kSmallWaves * 64, lds, s>>>(ta, tb, M, N, K, alpha, A, lda, B,
+                                                                                  ldb, beta, C, ldc);
   }
 }
 
@@ -663,9 +691,7 @@ void launch_gram(long long N, int k, const double* X, const double* Y, double* p
 void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
                  int ldb, double beta, double* C, int ldc, hipStream_t s) {
   if (M <= kSmallM && K <= kSmallK) {
-    dim3 g((N + 63) / 64, M);
-    gemm_small_kernel<double><<<g, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                   ldc);
+    launch_gemm_small<double>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
     return;
   }
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
@@ -675,9 +701,7 @@ void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const doub
 void launch_gemm_f32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda, const float* B,
                      int ldb, double beta, float* C, int ldc, hipStream_t s) {
   if (M <= kSmallM && K <= kSmallK) {
-    dim3 g((N + 63) / 64, M);
-    gemm_small_kernel<float><<<g, kBlock, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                  ldc);
+    launch_gemm_small<float>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
     return;
   }
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
