@@ -1,7 +1,10 @@
 """UNet: a handle on the learned preconditioner of libpase (torch-owned device memory).
 
-Argument marshalling only; every computation runs in libpase's HIP kernels on
-the stream that was current when the network was created.
+Argument marshalling only: the network's forward and backward passes, the loss,
+the output-scale fit and Adam run in libpase's HIP kernels on the stream that was
+current when the network was created.  Host-side training plumbing uses torch: the
+He-normal initial weights come from a seeded CPU generator, and each step's batch
+of pair columns is gathered with torch indexing (data movement only).
 """
 from __future__ import annotations
 
