@@ -17,8 +17,11 @@ the readings taken here are:
 * Inputs: the residual scaled to unit 2-norm and the node average of log kappa
   (mean over the 2^3 elements around a node; zero when kappa = 1).  With no
   biases the network is positively homogeneous in its first channel only
-  through the scaling, so the output is rescaled by ||r||_2:
-  N(r) = ||r|| net(r / ||r||, log kappa).
+  through the scaling, so the output is rescaled by ||r||_2 and, node-wise, by
+  the inverse diagonal of A (D^-1 r is the Jacobi part of V(r) and carries its
+  1/kappa scaling, which the log kappa channel alone learns slowly):
+  N(r) = ||r|| D^-1 net(r / ||r||, log kappa).  The scale is an argument
+  (None = 1), so the network is also usable without it.
 * Loss: mean over the batch of ||N(r) - c||^2 / ||c||^2 with c = V(r) (one
   V-cycle from zero).
 * Optimiser: Adam (Kingma and Ba, 2015) with beta1 = 0.9, beta2 = 0.999,
@@ -186,24 +189,27 @@ class UNet:
         x[:, :, 1] = logk[None, :]
         return x, nr
 
-    def apply(self, W, R, logk):
-        """N(R) column by column: ||r|| net(r / ||r||, log kappa); R is (N0, B)."""
+    def apply(self, W, R, logk, oscale=None):
+        """N(R) column by column: ||r|| s * net(r / ||r||, log kappa); R is (N0, B), s the
+        node-wise output scale (oscale, e.g. the inverse diagonal of A; None = 1)."""
         x, nr = self.inputs(R, logk)
         y, _ = self.forward(W, x)
-        return y[:, :, 0].T * nr[None, :]
+        Z = y[:, :, 0].T * nr[None, :]
+        return Z if oscale is None else Z * np.asarray(oscale)[:, None]
 
 
-def loss_and_grad(net, W, R, C, logk):
+def loss_and_grad(net, W, R, C, logk, oscale=None):
     """L = mean_b ||N(r_b) - c_b||^2 / ||c_b||^2 and its gradient (R, C: (N0, B))."""
     x, nr = net.inputs(R, logk)
     y, cache = net.forward(W, x)
-    Z = y[:, :, 0].T * nr[None, :]
+    sc = np.ones(R.shape[0]) if oscale is None else np.asarray(oscale, dtype=np.float64)
+    Z = y[:, :, 0].T * nr[None, :] * sc[:, None]
     E = Z - C
     cn = np.einsum("ij,ij->j", C, C)
     B = R.shape[1]
     L = float(np.mean(np.einsum("ij,ij->j", E, E) / cn))
     dZ = 2.0 * E / cn[None, :] / B
-    dy = (dZ * nr[None, :]).T[:, :, None]
+    dy = (dZ * nr[None, :] * sc[:, None]).T[:, :, None]
     return L, net.backward(W, cache, dy)
 
 

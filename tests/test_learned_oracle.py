@@ -89,6 +89,29 @@ def test_network_output_scales_with_the_residual():
     np.testing.assert_allclose(net.apply(W, 7.5 * R, logk), 7.5 * Z, rtol=1e-13, atol=1e-14)
 
 
+def test_output_scale_is_node_wise_and_in_the_gradient():
+    """N with a node-wise output scale s equals s * N without it, and the gradient of the loss
+    with the scale matches central differences."""
+    net = unet.UNet(8, channels=(2, 4, 8))
+    W = net.init(9)
+    N = net.m[0] ** 3
+    rng = np.random.default_rng(10)
+    R = rng.standard_normal((N, 2))
+    C = rng.standard_normal((N, 2))
+    logk = rng.standard_normal(N) * 0.2
+    sc = np.exp(rng.standard_normal(N))
+    np.testing.assert_allclose(net.apply(W, R, logk, sc), sc[:, None] * net.apply(W, R, logk), rtol=1e-13)
+    L, G = unet.loss_and_grad(net, W, R, C, logk, sc)
+    eps = 1e-6
+    for layer, idx in [(0, (4, 1, 1)), (5, (13, 3, 7)), (10, (20, 1, 0))]:
+        Wp = [w.copy() for w in W]
+        Wm = [w.copy() for w in W]
+        Wp[layer][idx] += eps
+        Wm[layer][idx] -= eps
+        fd = (unet.loss_and_grad(net, Wp, R, C, logk, sc)[0] - unet.loss_and_grad(net, Wm, R, C, logk, sc)[0]) / (2 * eps)
+        assert abs(fd - G[layer][idx]) <= 1e-6 * max(1e-3, abs(fd)), (layer, fd, G[layer][idx])
+
+
 def test_node_log_kappa():
     n = 4
     assert np.allclose(unet.node_log_kappa(n, np.full(n ** 3, 2.0)), np.log(2.0))
