@@ -218,11 +218,15 @@ pase_status pase_unet_apply(pase_unet* u, int batch, const double* R, const doub
  * pase_unet_adam_step and copied to the device vector G if non-NULL. */
 pase_status pase_unet_loss_grad(pase_unet* u, int batch, const double* R, const double* C, const double* logk,
                                 double* loss_host, float* G);
-/* Output scale fit (done once before training): multiplies the last layer's weights by
- * s = <N(R), C> / <N(R), N(R)> over the batch, the least-squares scale of the output against the
- * targets C (device N_0 x batch each).  The network is positively homogeneous in its last layer, so
- * the fitted output is s N(R) (s < 0 flips the sign).  s goes to *scale_host (may be NULL).
- * PASE_E_BREAKDOWN if s is zero or not finite (weights unchanged). */
+/* Node-wise output scale s (device, N_0 values, caller-owned and kept alive while the network
+ * uses it; NULL = 1): from now on N(R) = ||r|| s * net(r / ||r||, log kappa) in apply, loss_grad
+ * and fit_scale.  The learned form uses s = the inverse diagonal of A (pase_fine_diag_inverse). */
+pase_status pase_unet_set_output_scale(pase_unet* u, const double* scale);
+/* Output scale fit (done once before training): multiplies the weights of the three layers after
+ * the last concatenation by s^(1/3), s = ||C||_F / ||N(R)||_F over the batch (targets C and
+ * residuals R: device N_0 x batch each), so the output's size matches the targets' (each of those
+ * layers is positively homogeneous, so the output becomes s N(R)).  s goes to *scale_host (may be
+ * NULL).  PASE_E_BREAKDOWN if the output or the targets are zero (weights unchanged). */
 pase_status pase_unet_fit_scale(pase_unet* u, int batch, const double* R, const double* C, const double* logk,
                                 double* scale_host);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the gradient of the last loss_grad. */
@@ -237,6 +241,8 @@ pase_status pase_attach_unet(pase_handle* h, pase_unet* u);
 /* Training pairs for the network: R = Lambda M U - A U for the pairs (lambda_host, U) and
  * V = one V-cycle applied to R (device N_0 x k each). */
 pase_status pase_harvest(pase_handle* h, int k, const double* lambda_host, const double* U, double* R, double* V);
+/* 1 / A_ii at the fine nodes (device N_0): the network's output scale in the learned form. */
+pase_status pase_fine_diag_inverse(pase_handle* h, double* dinv);
 /* Node average of log kappa over the elements around each interior fine node (device N_0;
  * zeros for kappa = 1): the network's second input channel. */
 pase_status pase_node_logk(pase_handle* h, double* logk);

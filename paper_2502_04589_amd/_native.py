@@ -70,6 +70,8 @@ SIGNATURES = [
     ("pase_attach_unet", C.c_int, [C.c_void_p, C.c_void_p]),
     ("pase_harvest", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pase_node_logk", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pase_fine_diag_inverse", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pase_unet_set_output_scale", C.c_int, [C.c_void_p, C.c_void_p]),
 ]
 
 _lib = None

@@ -1052,6 +1052,13 @@ pase_status pase_harvest(pase_handle* h, int k, const double* lambda_host, const
   return PASE_OK;
 }
 
+pase_status pase_fine_diag_inverse(pase_handle* h, double* dinv) {
+  if (!h || !dinv) return fail(h, PASE_E_ARG, "null argument");
+  HIPC(hipMemcpyAsync(dinv, h->lev[0].dinv, sizeof(double) * h->lev[0].N, hipMemcpyDeviceToDevice, h->stream));
+  HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
 pase_status pase_node_logk(pase_handle* h, double* logk) {
   if (!h || !logk) return fail(h, PASE_E_ARG, "null argument");
   if (h->dim != 3) return fail(h, PASE_E_UNSUPPORTED, "3D only");

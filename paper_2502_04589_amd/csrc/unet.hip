@@ -302,14 +302,14 @@ __global__ void input_kernel(long long N, int k, const double* __restrict__ R, c
   xb[1] = (__bf16)(float)(logk ? logk[n] : 0.0);
 }
 
-// Z[n][b] = ||r_b|| y[b][n]
+// Z[n][b] = ||r_b|| s[n] y[b][n] (s = node-wise output scale, NULL = 1)
 __global__ void output_kernel(long long N, int k, const float* __restrict__ y, const double* __restrict__ colsq,
-                              double* __restrict__ Z) {
+                              const double* __restrict__ os, double* __restrict__ Z) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= N * k) return;
   const long long n = q / k;
   const int b = (int)(q % k);
-  Z[q] = sqrt(colsq[b]) * (double)y[(size_t)b * N + n];
+  Z[q] = sqrt(colsq[b]) * (os ? os[n] : 1.0) * (double)y[(size_t)b * N + n];
 }
 
 }  // namespace
@@ -475,22 +475,24 @@ __global__ void wgrad_reduce_kernel(int tiles, int E, const float* __restrict__ 
 // z = ||r_b|| y, e = z - c; per column: num[b] = sum e^2, den[b] = sum c^2 (fixed-order partials
 // by the caller); here the elementwise part: err[b][n] = z - c
 __global__ void loss_err_kernel(long long N, int k, const float* __restrict__ y, const double* __restrict__ colsq,
-                                const double* __restrict__ C, double* __restrict__ err) {
+                                const double* __restrict__ os, const double* __restrict__ C,
+                                double* __restrict__ err) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= N * k) return;
   const long long n = q / k;
   const int b = (int)(q % k);
-  err[q] = sqrt(colsq[b]) * (double)y[(size_t)b * N + n] - C[q];
+  err[q] = sqrt(colsq[b]) * (os ? os[n] : 1.0) * (double)y[(size_t)b * N + n] - C[q];
 }
 
-// dL/dy[b][n] = 2 err[n][b] / den[b] / B * ||r_b||
+// dL/dy[b][n] = 2 err[n][b] / den[b] / B * ||r_b|| s[n]
 __global__ void loss_grad_kernel(long long N, int k, const double* __restrict__ err, const double* __restrict__ den,
-                                 const double* __restrict__ colsq, float* __restrict__ gy) {
+                                 const double* __restrict__ colsq, const double* __restrict__ os,
+                                 float* __restrict__ gy) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= N * k) return;
   const long long n = q / k;
   const int b = (int)(q % k);
-  gy[(size_t)b * N + n] = (float)(2.0 * err[q] / den[b] / k * sqrt(colsq[b]));
+  gy[(size_t)b * N + n] = (float)(2.0 * err[q] / den[b] / k * sqrt(colsq[b]) * (os ? os[n] : 1.0));
 }
 
 // ---------------------------------------------------------------- elementwise helpers
@@ -579,6 +581,7 @@ struct pase_unet {
   double *colsq = nullptr, *cden = nullptr, *cnum = nullptr, *err = nullptr, *dpart = nullptr;
   float* wpart = nullptr;
   size_t wpart_floats = 0;
+  const double* oscale = nullptr;   // node-wise output scale (caller-owned device N_0 values), NULL = 1
   std::string errmsg;
 };
 
@@ -958,7 +961,7 @@ pase_status pase_unet_apply(pase_unet* u, int batch, const double* R, const doub
   if (!u || !R || !Z || batch < 1 || batch > u->bmax) return PASE_E_ARG;
   prepare_input(u, batch, R, logk);
   forward(u, batch);
-  output_kernel<<<nb256(u->N[0] * batch), 256, 0, u->stream>>>(u->N[0], batch, u->y, u->colsq, Z);
+  output_kernel<<<nb256(u->N[0] * batch), 256, 0, u->stream>>>(u->N[0], batch, u->y, u->colsq, u->oscale, Z);
   return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");
 }
 
@@ -968,10 +971,10 @@ pase_status pase_unet_loss_grad(pase_unet* u, int batch, const double* R, const 
   const long long N = u->N[0];
   prepare_input(u, batch, R, logk);
   forward(u, batch);
-  loss_err_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, u->y, u->colsq, C, u->err);
+  loss_err_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, u->y, u->colsq, u->oscale, C, u->err);
   launch_coldot(N, batch, u->err, u->err, u->dpart, coldot_tiles(N, batch), u->cnum, u->stream);
   launch_coldot(N, batch, C, C, u->dpart, coldot_tiles(N, batch), u->cden, u->stream);
-  loss_grad_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, u->err, u->cden, u->colsq, u->gy);
+  loss_grad_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, u->err, u->cden, u->colsq, u->oscale, u->gy);
   backward(u, batch);
   if (G && hipMemcpyAsync(G, u->G, u->P * sizeof(float), hipMemcpyDeviceToDevice, u->stream) != hipSuccess)
     return ufail(u, PASE_E_HIP, "copy of the gradient failed");
@@ -988,30 +991,41 @@ pase_status pase_unet_loss_grad(pase_unet* u, int batch, const double* R, const 
   return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");
 }
 
+pase_status pase_unet_set_output_scale(pase_unet* u, const double* scale) {
+  if (!u) return PASE_E_ARG;
+  u->oscale = scale;
+  return PASE_OK;
+}
+
 pase_status pase_unet_fit_scale(pase_unet* u, int batch, const double* R, const double* C, const double* logk,
                                 double* scale_host) {
   if (!u || !R || !C || batch < 1 || batch > u->bmax) return PASE_E_ARG;
   const long long N = u->N[0];
   prepare_input(u, batch, R, logk);
   forward(u, batch);
-  output_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, u->y, u->colsq, u->err);
-  launch_coldot(N, batch, u->err, C, u->dpart, coldot_tiles(N, batch), u->cnum, u->stream);
+  output_kernel<<<nb256(N * batch), 256, 0, u->stream>>>(N, batch, u->y, u->colsq, u->oscale, u->err);
+  // norm match: s = ||C|| / ||N(R)|| over the batch
   launch_coldot(N, batch, u->err, u->err, u->dpart, coldot_tiles(N, batch), u->cden, u->stream);
-  std::vector<double> num(batch), den(batch);
-  if (hipMemcpyAsync(num.data(), u->cnum, sizeof(double) * batch, hipMemcpyDeviceToHost, u->stream) != hipSuccess ||
-      hipMemcpyAsync(den.data(), u->cden, sizeof(double) * batch, hipMemcpyDeviceToHost, u->stream) != hipSuccess ||
+  launch_coldot(N, batch, C, C, u->dpart, coldot_tiles(N, batch), u->cnum, u->stream);
+  std::vector<double> cc(batch), zz(batch);
+  if (hipMemcpyAsync(cc.data(), u->cnum, sizeof(double) * batch, hipMemcpyDeviceToHost, u->stream) != hipSuccess ||
+      hipMemcpyAsync(zz.data(), u->cden, sizeof(double) * batch, hipMemcpyDeviceToHost, u->stream) != hipSuccess ||
       hipStreamSynchronize(u->stream) != hipSuccess)
     return ufail(u, PASE_E_HIP, "scale readback failed");
-  double a = 0.0, b = 0.0;
+  double sc2 = 0.0, sz2 = 0.0;
   for (int j = 0; j < batch; ++j) {
-    a += num[j];
-    b += den[j];
+    sc2 += cc[j];
+    sz2 += zz[j];
   }
-  if (!(b > 0.0) || !std::isfinite(a / b) || a == 0.0)
-    return ufail(u, PASE_E_BREAKDOWN, "the network output is zero or orthogonal to the targets");
-  const double sc = a / b;
-  const Layer& l = u->L[10];
-  scale_f32_kernel<<<nb256((long long)l.E()), 256, 0, u->stream>>>((int)l.E(), (float)sc, u->W + l.woff);
+  const double sc = sqrt(sc2 / sz2);
+  if (!(sz2 > 0.0) || !std::isfinite(sc) || !(sc > 0.0))
+    return ufail(u, PASE_E_BREAKDOWN, "the network output or the targets are zero");
+  // spread over the three layers after the last concatenation (each positively homogeneous)
+  const float c3 = (float)cbrt(sc);
+  for (int i = 8; i < 11; ++i) {
+    const Layer& l = u->L[i];
+    scale_f32_kernel<<<nb256((long long)l.E()), 256, 0, u->stream>>>((int)l.E(), c3, u->W + l.woff);
+  }
   relayout_all(u);
   if (scale_host) *scale_host = sc;
   return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");

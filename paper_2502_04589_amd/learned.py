@@ -104,8 +104,20 @@ class UNet:
         self._check(self.lib.pase_unet_loss_grad(self.h, k, _ptr(R), _ptr(Cm), _ptr(lk), C.byref(loss), _ptr(G)))
         return float(loss.value), G
 
+    def set_output_scale(self, scale):
+        """Node-wise output scale (float64 device tensor with one value per node, or None = 1);
+        the learned form uses the inverse diagonal of A (Solver.fine_diag_inverse())."""
+        if scale is not None:
+            if not (isinstance(scale, torch.Tensor) and scale.dtype == torch.float64 and scale.numel() == self.N
+                    and scale.device == self.device):
+                raise TypeError("scale must be a float64 device tensor with one value per node")
+            scale = scale.contiguous()
+        self._oscale = scale              # the library keeps the pointer: hold the memory
+        self._check(self.lib.pase_unet_set_output_scale(self.h, _ptr(scale)))
+
     def fit_scale(self, R, Cm, logk=None):
-        """Rescale the last layer so the output best matches Cm in least squares; returns the factor."""
+        """Rescale the output to the targets' norm (s = ||Cm|| / ||N(R)||, spread over the last three
+        layers); returns s."""
         k = R.shape[1]
         R = self._mv(R, k, "R")
         Cm = self._mv(Cm, k, "C")

@@ -220,6 +220,12 @@ class Solver:
         self._check(self.lib.pase_harvest(self.h, k, lam.ctypes.data, _ptr(U), _ptr(R), _ptr(V)), self.h)
         return R, V
 
+    def fine_diag_inverse(self):
+        """1 / A_ii at the fine nodes (the learned form's network output scale)."""
+        out = torch.empty(self.N[0], dtype=torch.float64, device=self.device)
+        self._check(self.lib.pase_fine_diag_inverse(self.h, _ptr(out)), self.h)
+        return out
+
     def node_logk(self):
         """Node average of log kappa on the fine mesh (the network's second input)."""
         out = torch.empty(self.N[0], dtype=torch.float64, device=self.device)

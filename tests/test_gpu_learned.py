@@ -78,6 +78,31 @@ def test_loss_and_gradients_match_oracle():
         assert cos > 0.999 and relerr(gg, gi) < 5e-2, (i, cos, relerr(gg, gi))
 
 
+def test_output_scale_in_forward_and_gradient_matches_oracle():
+    """Node-wise output scale (a seeded positive field): output, loss and gradients against the
+    oracle network with the same scale."""
+    net, W, g, R, logk = setup(seed=7)
+    H = multigrid.Hierarchy(3, [16, 8, 4])
+    Cm = H.vcycle(R)
+    sc = np.exp(0.5 * np.random.default_rng(3).standard_normal(net.m[0] ** 3)) * 0.01
+    Wr = [w.astype(np.float32).astype(np.float64) for w in W]
+    scd = dev(sc)
+    g.set_output_scale(scd)
+    Z = g.apply(dev(R), dev(logk)).cpu().numpy()
+    assert relerr(Z, net.apply(Wr, R, logk, sc)) < 2e-2
+    L, G = ounet.loss_and_grad(net, Wr, R, Cm, logk, sc)
+    Lg, Gg = g.loss_grad(dev(R), dev(Cm), dev(logk))
+    assert abs(Lg - L) <= 2e-2 * L, (Lg, L)
+    Gg = Gg.cpu().numpy().astype(np.float64)
+    off = 0
+    for i, gi in enumerate(G):
+        gg = Gg[off:off + gi.size].reshape(gi.shape)
+        off += gi.size
+        cos = float(np.sum(gg * gi) / (np.linalg.norm(gg) * np.linalg.norm(gi)))
+        # the node scale widens the range of the BF16 activations' gradients: a little looser
+        assert cos > 0.998 and relerr(gg, gi) < 8e-2, (i, cos, relerr(gg, gi))
+
+
 def test_adam_step_matches_formula():
     net, W, g, R, logk = setup(seed=3)
     H = multigrid.Hierarchy(3, [16, 8, 4])
@@ -93,14 +118,14 @@ def test_adam_step_matches_formula():
 
 
 def test_output_scale_fit_matches_oracle():
-    """The fitted scale is the least-squares factor <N(r), c> / <N(r), N(r)> of the oracle network
-    at the same weights, and the output is multiplied by it."""
+    """The fitted scale is the norm ratio ||c|| / ||N(r)|| of the oracle network at the same
+    weights, and the output is multiplied by it."""
     net, W, g, R, logk = setup(seed=6, batch=4)
     H = multigrid.Hierarchy(3, [16, 8, 4])
     Cm = H.vcycle(R)
     Wr = [w.astype(np.float32).astype(np.float64) for w in W]
     Zr = net.apply(Wr, R, logk)
-    s_ref = float(np.sum(Zr * Cm) / np.sum(Zr * Zr))
+    s_ref = float(np.sqrt(np.sum(Cm * Cm) / np.sum(Zr * Zr)))
     Z0 = g.apply(dev(R), dev(logk)).cpu().numpy()
     sc = g.fit_scale(dev(R), dev(Cm), dev(logk))
     assert abs(sc - s_ref) <= 2e-2 * abs(s_ref), (sc, s_ref)
@@ -253,10 +278,13 @@ def test_trained_network_gain_over_untrained_and_vcycle():
     R = torch.cat(Rs, 1).contiguous()
     V = torch.cat(Vs, 1).contiguous()
     logk = s.node_logk()
+    dinv = s.fine_diag_inverse()
     net = UNet(16, batch_max=k)
     net.init_weights(5)
+    net.set_output_scale(dinv)
     untrained = UNet(16, batch_max=k)
     untrained.init_weights(5)
+    untrained.set_output_scale(dinv)
     losses = net.train(R, V, logk, steps=200, lr=1e-3, seed=0)
     assert np.mean(losses[-10:]) < 0.5 * losses[0], losses[::15]
     # held-out block: another start seed after 2 plain corrections
@@ -278,3 +306,65 @@ def test_trained_network_gain_over_untrained_and_vcycle():
     print("one-step ||r1||/||r0|| (median):", ratio, "relative error against V(r):", err)
     assert err["trained"] < 0.5 * err["untrained"], err
     assert ratio["trained"] < ratio["untrained"], ratio
+
+
+# ---------------------------------------------------------------- full size (64^3 Q1, kappa field, nev 32)
+FULL = [64, 32, 16, 8]
+
+
+@pytest.fixture(scope="module")
+def full_case():
+    kap = synth.kappa_field(3, 64, 3)
+    H = multigrid.Hierarchy(3, FULL, kap)
+    U, lam = start(H, 32, 1)
+    return kap, H, U, lam
+
+
+@pytest.mark.slow
+def test_full_size_harvest_and_zero_network_pcg_match_oracle(full_case):
+    """At the training configuration's size: harvested pairs and the learned PCG with a zero
+    network (= V-cycle PCG with one step less) against the oracle, every output."""
+    from paper_2502_04589_amd import Solver, UNet
+    kap, H, U, lam = full_case
+    s = Solver(3, FULL, kap, nev_max=32, precision="learned")
+    g = UNet(64, batch_max=32)
+    g.set_weights(np.zeros(param_count(), dtype=np.float32))
+    s.attach(g)
+    R, V = s.harvest(lam, dev(U))
+    Rref = (H.M[0] @ U) * lam - H.A[0] @ U
+    assert relerr(host(R), Rref) < 1e-12
+    assert relerr(host(V), H.vcycle(Rref)) < 1e-12
+    W = host(s.pcg(lam, dev(U)))
+    assert relerr(W, opase.pcg(H, (H.M[0] @ U) * lam, U, 1)) < 1e-12
+
+
+@pytest.mark.slow
+def test_full_size_trained_learned_solve(full_case):
+    """Harvest, a short training and a learned solve at full size: every pair meets 1e-8, the
+    block is M-orthonormal and the eigenvalues agree with the plain FP64 solve to 1e-8."""
+    from paper_2502_04589_amd import Solver, UNet
+    kap, H, U, lam = full_case
+    k = 32
+    s = Solver(3, FULL, kap, nev_max=k, precision="learned")
+    src = Solver(3, FULL, kap, nev_max=k)
+    Ud = dev(U)
+    Rs, Vs = [], []
+    for _ in range(3):
+        R, V = s.harvest(lam, Ud)
+        Rs.append(R)
+        Vs.append(V)
+        lam, Ud = src.correction(lam, Ud)
+    net = UNet(64, batch_max=k)
+    net.init_weights(0)
+    net.set_output_scale(s.fine_diag_inverse())
+    losses = net.train(torch.cat(Rs, 1).contiguous(), torch.cat(Vs, 1).contiguous(), s.node_logk(), steps=40)
+    assert np.mean(losses[-5:]) < 0.8 * losses[0], losses[::5]
+    s.attach(net)
+    U0 = dev(synth.initial_vectors(63 ** 3, k, 2))
+    lam_l, U_l, rep = s.solve(k, 1e-8, U0)
+    lam_p, _, _ = src.solve(k, 1e-8, U0)
+    assert rep["n_converged"] == k and np.max(rep["res"]) <= 1e-8
+    np.testing.assert_allclose(lam_l, lam_p, rtol=1e-8)
+    _, MU = s.apply(0, U_l)
+    G = host(U_l.T.contiguous() @ MU)
+    assert np.max(np.abs(G - np.eye(k))) < 1e-10
