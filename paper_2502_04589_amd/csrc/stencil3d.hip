@@ -69,22 +69,24 @@ __device__ __forceinline__ void vset(typename Vec<T, W>::type& v, int i, double 
 
 constexpr int kSlots = 4;             // LDS ring: planes z-1, z, z+1 and the one being filled
 
-template <typename T, int W, int BX, int BY>
+template <typename T, int W, int BX, int BY, int NQ>
 struct Fine3SmemV {
   typedef typename Vec<T, W>::type V;
   union {
-    V xs[kSlots][BY + 2][BX + 2][4];
-    double red[3][BX * BY * 4 * W];
+    V xs[kSlots][BY + 2][BX + 2][NQ];
+    double red[3][BX * BY * NQ * W];
   };
 };
 
-template <typename T, int VW, int EPI, bool CONSTK, bool VEC, int BX, int BY>
-__global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
+// NQ threads per node, each with a VW-column vector: a block covers KC = NQ VW columns of its
+// tile (NQ = 5 when it splits k into whole chunks and 4 does not, e.g. k = 50 with VW = 2)
+template <typename T, int VW, int EPI, bool CONSTK, bool VEC, int BX, int BY, int NQ>
+__global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   constexpr int TX = BX, TY = BY;
-  constexpr int kThreadsV = BX * BY * 4;    // (node, column vector) pairs of a tile
+  constexpr int kThreadsV = BX * BY * NQ;   // (node, column vector) pairs of a tile
   typedef typename Vec<T, VW>::type V;
-  constexpr int KC = 4 * VW;                 // columns per block
-  __shared__ Fine3SmemV<T, VW, BX, BY> sm;
+  constexpr int KC = NQ * VW;                // columns per block
+  __shared__ Fine3SmemV<T, VW, BX, BY, NQ> sm;
   const int m = a.m, n = m + 1, k = a.k;
   const int ntx = (m + TX - 1) / TX;
   const int nty = (m + TY - 1) / TY;
@@ -105,18 +107,18 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
   const int z0 = zc * zlen;
   const int z1 = (z0 + zlen < m) ? z0 + zlen : m;
   const int tid = threadIdx.x;
-  const int qv = tid & 3;                    // column vector within the chunk
-  const int node = tid >> 2;
+  const int qv = tid % NQ;                   // column vector within the chunk
+  const int node = tid / NQ;
   const int lx = node % TX, ly = node / TX;
   const int gx = tx0 + lx, gy = ty0 + ly;
   const int colv = c0 + qv * VW;             // first column of this thread
   const bool nodeok = (gx < m) && (gy < m);
   const T* __restrict__ X = (const T*)a.x;
 
-  // halo plane: (TX+2)(TY+2) nodes x 4 vectors = 400 vectors; thread owns entries tid and
-  // tid + 256.  Loads are branch-free: entries outside the domain (or the column range)
-  // read a zero vector, so loaded registers stay in flight until they are stashed.
-  constexpr int HV = (TX + 2) * (TY + 2) * 4;
+  // halo plane: (TX+2)(TY+2) nodes x NQ vectors; thread owns entries tid and tid + kThreadsV.
+  // Loads are branch-free: entries outside the domain (or the column range) read a zero
+  // vector, so loaded registers stay in flight until they are stashed.
+  constexpr int HV = (TX + 2) * (TY + 2) * NQ;
   static_assert(HV <= 2 * kThreadsV, "two halo entries per thread");
   const V* __restrict__ zerov = (const V*)a.zero;
   // per-thread halo entry geometry (independent of z)
@@ -126,8 +128,8 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int e = tid + u * kThreadsV;
-    const int cq = e & 3;
-    const int hn = e >> 2;
+    const int cq = e % NQ;
+    const int hn = e / NQ;
     const int hx = hn % (TX + 2), hy = hn / (TX + 2);
     const int x = tx0 + hx - 1, y = ty0 + hy - 1;
     hin[u] = e < HV && x >= 0 && x < m && y >= 0 && y < m && c0 + cq * VW < k;
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
       V v;
 #pragma unroll
       for (int i = 0; i < VW; ++i) {
-        const int cq = ((tid + u * kThreadsV) & 3);
+        const int cq = ((tid + u * kThreadsV) % NQ);
         const bool oki = ok && (c0 + cq * VW + i < k);
         const T* p = oki ? X + z * plane + hoff[u] + i : (const T*)zerov;
         vset<T, VW>(v, i, (double)*p);
@@ -409,7 +411,7 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
     if (tid < KC && c0 + tid < k) {
       const int tq = tid / VW, ti = tid % VW;
       double s0 = 0.0;
-      for (int nd = 0; nd < TX * TY; ++nd) s0 += sm.red[0][(nd * 4 + tq) * VW + ti];
+      for (int nd = 0; nd < TX * TY; ++nd) s0 += sm.red[0][(nd * NQ + tq) * VW + ti];
       const int sbk = (zc * nty + tyi) * ntx + txi;
       a.partial[(size_t)sbk * k + c0 + tid] = s0;
     }
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(BX * BY * 4) void fine3v_kernel(Fine3Args a) {
       const int tq = tid / VW, ti = tid % VW;
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
       for (int nd = 0; nd < TX * TY; ++nd) {
-        const int src = (nd * 4 + tq) * VW + ti;
+        const int src = (nd * NQ + tq) * VW + ti;
         s0 += sm.red[0][src];
         s1 += sm.red[1][src];
         s2 += sm.red[2][src];
@@ -446,17 +448,29 @@ static int g_tile = 1;   // 0: 16 x 8, 1: 8 x 8 (default), 2: 16 x 16
 
 template <typename T, int VW, int EPI, bool CONSTK, bool VEC>
 void launchv_tile(const Fine3Args& a, hipStream_t s) {
-  constexpr int KC = 4 * VW;
-  auto go = [&](auto bx, auto by) {
-    constexpr int BX = decltype(bx)::value, BY = decltype(by)::value;
+  auto go = [&](auto bx, auto by, auto nq) {
+    constexpr int BX = decltype(bx)::value, BY = decltype(by)::value, NQ = decltype(nq)::value;
+    constexpr int KC = NQ * VW;
     const int ntx = (a.m + BX - 1) / BX, nty = (a.m + BY - 1) / BY, nch = (a.k + KC - 1) / KC;
     const int total = ntx * nty * a.nzc * nch;
     const int blocks = ((total + 7) / 8) * 8;
-    fine3v_kernel<T, VW, EPI, CONSTK, VEC, BX, BY><<<blocks, BX * BY * 4, 0, s>>>(a);
+    fine3v_kernel<T, VW, EPI, CONSTK, VEC, BX, BY, NQ><<<blocks, BX * BY * NQ, 0, s>>>(a);
   };
-  if (g_tile == 1) go(std::integral_constant<int, 8>(), std::integral_constant<int, 8>());
-  else if (g_tile == 2) go(std::integral_constant<int, 16>(), std::integral_constant<int, 16>());
-  else go(std::integral_constant<int, 16>(), std::integral_constant<int, 8>());
+  using I8 = std::integral_constant<int, 8>;
+  using I16 = std::integral_constant<int, 16>;
+  if (g_tile == 1) {
+    // column chunks of 5 vectors when that wastes fewer padded columns than chunks of 4 (not for
+    // the A+M and eigen-residual epilogues, whose register use makes the larger block slower)
+    const int w4 = ((a.k + 4 * VW - 1) / (4 * VW)) * 4 * VW - a.k;
+    const int w5 = ((a.k + 5 * VW - 1) / (5 * VW)) * 5 * VW - a.k;
+    constexpr bool five_ok = EPI != EPI_AM && EPI != EPI_EIGRES;
+    if (five_ok && w5 < w4) go(I8(), I8(), std::integral_constant<int, 5>());
+    else go(I8(), I8(), std::integral_constant<int, 4>());
+  } else if (g_tile == 2) {
+    go(I16(), I16(), std::integral_constant<int, 4>());
+  } else {
+    go(I16(), I8(), std::integral_constant<int, 4>());
+  }
 }
 
 template <typename T, int VW, int EPI>
