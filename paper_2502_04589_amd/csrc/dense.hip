@@ -852,17 +852,16 @@ __global__ __launch_bounds__(64) void cholinv_wave_kernel(int k, double* __restr
       const double rd = 1.0 / pe;
       const double sq = sqrt(pe);
       const double lij = r[j] * rd;
+      // unconditional update: in a lane i < l it only writes the strict upper triangle of row i,
+      // which no later pivot reads (col[l] is read only for l > j >= i) and is cleared below
 #pragma unroll
-      for (int l = j + 1; l < 64; ++l) {
-        const double c = col[l];
-        r[l] = (l <= i) ? fma(-lij, c, r[l]) : r[l];
-      }
+      for (int l = j + 1; l < 64; ++l) r[l] = fma(-lij, col[l], r[l]);
       r[j] = (i > j) ? r[j] / sq : ((i == j) ? sq : r[j]);
       __syncthreads();
     }
   }
 #pragma unroll
-  for (int l = 0; l < 64; ++l) Ls[i][l] = r[l];
+  for (int l = 0; l < 64; ++l) Ls[i][l] = (l <= i) ? r[l] : 0.0;
   __syncthreads();
   // column c = i of X = L^{-1}
   const int c = i;

@@ -458,18 +458,20 @@ void launchv_tile(const Fine3Args& a, hipStream_t s) {
   };
   using I8 = std::integral_constant<int, 8>;
   using I16 = std::integral_constant<int, 16>;
+  // column chunks of 5 vectors when that wastes fewer padded columns than chunks of 4 (not for
+  // the A+M and eigen-residual epilogues, whose register use makes the larger block slower)
+  const int w4 = ((a.k + 4 * VW - 1) / (4 * VW)) * 4 * VW - a.k;
+  const int w5 = ((a.k + 5 * VW - 1) / (5 * VW)) * 5 * VW - a.k;
+  constexpr bool five_ok = EPI != EPI_AM && EPI != EPI_EIGRES;
+  const bool five = five_ok && w5 < w4;
   if (g_tile == 1) {
-    // column chunks of 5 vectors when that wastes fewer padded columns than chunks of 4 (not for
-    // the A+M and eigen-residual epilogues, whose register use makes the larger block slower)
-    const int w4 = ((a.k + 4 * VW - 1) / (4 * VW)) * 4 * VW - a.k;
-    const int w5 = ((a.k + 5 * VW - 1) / (5 * VW)) * 5 * VW - a.k;
-    constexpr bool five_ok = EPI != EPI_AM && EPI != EPI_EIGRES;
-    if (five_ok && w5 < w4) go(I8(), I8(), std::integral_constant<int, 5>());
+    if (five) go(I8(), I8(), std::integral_constant<int, 5>());
     else go(I8(), I8(), std::integral_constant<int, 4>());
   } else if (g_tile == 2) {
     go(I16(), I16(), std::integral_constant<int, 4>());
   } else {
-    go(I16(), I8(), std::integral_constant<int, 4>());
+    if (five) go(I16(), I8(), std::integral_constant<int, 5>());
+    else go(I16(), I8(), std::integral_constant<int, 4>());
   }
 }
 
