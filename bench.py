@@ -280,6 +280,23 @@ def main():
             "algorithmic_bytes_per_launch": nbytes,
         },
     }
+    # achieved rates of the kernel families, timed live on the solver's stream (HIP events):
+    # SpMM = fused A X, M X; CG = fused update; V-cycle = fine sweep; Gram = FP64 MFMA W^T Y
+    N = s.N[0]
+    mv = N * nev * 8
+    rates = {}
+    for name, key, nbytes in (("spmm_AX_MX", "apply", 3 * mv), ("cg_update", "cg_update", 6 * mv),
+                              ("vcycle_sweep", "sweep", sweep_bytes(dim, levels[0], nev, kseed is not None))):
+        t = s.time_kernel(key, nev, reps=50)
+        gbs = nbytes / (t * 1e-3) / 1e9
+        rates[name] = {"us": t * 1e3, "bytes": nbytes, "GB/s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS}
+    t = s.time_kernel("gram", nev, reps=50)
+    tf = 2.0 * N * nev * nev / (t * 1e-3) / 1e12
+    rates["gram_mfma_f64"] = {"us": t * 1e3, "flops": 2 * N * nev * nev, "TFLOP/s": tf,
+                              "frac_fp64_mfma_peak": tf / 78.6,
+                              "note": "one Gram X^T Y (N x k by N x k) incl. its fixed-order reduction; "
+                                      "HBM-bound (k/8 flops per byte)"}
+    out["kernel_rates"] = rates
     # the paper's own numbers are CPU-cluster wall times of larger problems: context, not a target
     out["paper_context"] = {
         "note": "the paper reports CPU-cluster wall times only (no GPU numbers); closest row, for context",

@@ -1075,7 +1075,7 @@ void pase_tune_fine3_tile(int t) { fine3_set_tile(t); }
 pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double* ms) {
   pase_status st = check_k(h, k);
   if (st) return st;
-  if (!ms || reps < 1 || which < 0 || which > 4) return fail(h, PASE_E_ARG, "bad timing arguments");
+  if (!ms || reps < 1 || which < 0 || which > 5) return fail(h, PASE_E_ARG, "bad timing arguments");
   if (which == 4 && !h->Tm) return fail(h, PASE_E_UNSUPPORTED, "no dense small-problem workspace");
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
@@ -1085,6 +1085,7 @@ pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double*
       case 1: apply_AM(h, 0, k, h->U, h->W2, h->W3); break;
       case 2: launch_gram(N, k, h->U, h->W2, h->partial, gram_tiles(N, k), h->kk1, s); break;
       case 3: vcycle(h, 0, k, h->R, h->Z); break;
+      case 5: launch_axpy2(N, k, h->alpha, h->P, h->Q, h->W2, h->W3, s); break;   // on scratch
       case 4: {
         // a correction consumes R and overwrites U; run it on copies so repeated calls see the same input
         launch_copy((size_t)N * k, h->U, h->W2, s);
