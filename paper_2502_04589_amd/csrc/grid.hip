@@ -304,6 +304,46 @@ __global__ void first_sweep_flat_kernel(unsigned n, unsigned k, const double* __
   x[i] = (T)(omega * dinv[i / k] * (double)b[i]);
 }
 
+// 3D restriction marching along x: thread (column, coarse Y, coarse Z, run of kRestrictRun coarse
+// x) forms, for each fine x-plane it meets, the weighted 3 x 3 (y, z) sum around (2Y+1, 2Z+1), and
+// combines three consecutive ones with weights 1/2, 1, 1/2; the plane at 2X+2 is shared with the
+// next coarse node, so a coarse value costs 18 fine loads instead of 27.
+constexpr int kRestrictRun = 8;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void restrict_march_kernel(int mf, int mc, unsigned k, const T* __restrict__ xf,
+                                                               T* __restrict__ xc) {
+  const unsigned nseg = (unsigned)(mc + kRestrictRun - 1) / kRestrictRun;
+  const unsigned q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= (unsigned)mc * (unsigned)mc * nseg * k) return;
+  unsigned col, t;
+  flat_split(q, k, t, col);
+  const int Y = (int)(t % (unsigned)mc);
+  t /= (unsigned)mc;
+  const int Z = (int)(t % (unsigned)mc);
+  const int seg = (int)(t / (unsigned)mc);
+  const int X0 = seg * kRestrictRun, X1 = min(mc, X0 + kRestrictRun);
+  const long long sy = (long long)mf * k, sz = (long long)mf * mf * k;
+  const T* __restrict__ base = xf + (long long)(2 * Z + 1) * sz + (long long)(2 * Y + 1) * sy + col;
+  auto plane = [&](int fx) -> double {
+    const T* p = base + (long long)fx * k;
+    double s = 0.0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+        s = fma((dz ? 0.5 : 1.0) * (dy ? 0.5 : 1.0), (double)p[dz * sz + dy * sy], s);
+    return s;
+  };
+  double prev = plane(2 * X0);
+  T* __restrict__ out = xc + ((long long)(Z * mc + Y) * mc) * k + col;
+  for (int X = X0; X < X1; ++X) {
+    const double mid = plane(2 * X + 1), nxt = plane(2 * X + 2);
+    out[(long long)X * k] = (T)(0.5 * prev + mid + 0.5 * nxt);
+    prev = nxt;
+  }
+}
+
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void restrict_flat_kernel(int mf, int mc, unsigned k, const T* __restrict__ xf,
                                                               T* __restrict__ xc) {
@@ -672,8 +712,14 @@ static void launch_restrict_t(int dim, int mf, int mc, int k, const T* xf, T* xc
   long long Nc = (long long)mc * mc * (dim == 3 ? mc : 1);
   long long Nf = (long long)mf * mf * (dim == 3 ? mf : 1);
   if (Nf * k <= kFlatMax) {
-    if (dim == 3) restrict_flat_kernel<3, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xf, xc);
-    else restrict_flat_kernel<2, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xf, xc);
+    if (dim == 3 && mc >= 24) {                 // small levels: the gather has more parallelism
+      const long long nseg = (mc + kRestrictRun - 1) / kRestrictRun;
+      restrict_march_kernel<T><<<nblk((long long)mc * mc * nseg * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xf, xc);
+    } else if (dim == 3) {
+      restrict_flat_kernel<3, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xf, xc);
+    } else {
+      restrict_flat_kernel<2, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xf, xc);
+    }
     return;
   }
   if (dim == 3) restrict_kernel<3, T><<<nblk(Nc * k), kBlock, 0, s>>>(mf, mc, k, xf, xc);
