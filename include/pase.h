@@ -99,8 +99,8 @@ typedef struct pase_report {
   double t_solve_ms;             /* device time of the solve (HIP events on the handle's stream) */
   int small_fast_iters;          /* corrections whose augmented eigenproblem the structured path solved */
   int* small_path_host;          /* max_outer: per correction, 1 = structured path accepted, 0 = dense
-                                    only, -1 = rejected (residual or orthogonality), -2 = rejected by the
-                                    eigenvalue count */
+                                    only, -1 = rejected by a residual, -2 = rejected by the eigenvalue
+                                    count, -3 = its Cholesky-QR orthonormalisation broke down */
   int learned_fallbacks;         /* learned form: column switches to the V-cycle, summed over the solve */
 } pase_report;
 

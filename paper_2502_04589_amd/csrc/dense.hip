@@ -837,6 +837,21 @@ __global__ __launch_bounds__(64) void cholinv_wave_kernel(int k, double* __restr
     if (l == i && i < k) dm = r[l];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  // G = I + E with max |E| <= 1e-9 (the second pass of a Cholesky-QR): L = I + tril(E) - diag(E) / 2
+  // and L^{-1} = I - tril(E) + diag(E) / 2 up to O(k |E|^2) <= 1e-16, so no factorisation is needed
+  double em = 0.0;
+#pragma unroll
+  for (int l = 0; l < 64; ++l) em = fmax(em, fabs(r[l] - ((l == i) ? 1.0 : 0.0)));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) em = fmax(em, __shfl_xor(em, o, 64));
+  if (em <= 1e-9) {
+    if (i < k) {
+#pragma unroll
+      for (int l = 0; l < 64; ++l)
+        if (l < k) G[i * k + l] = (l < i) ? -r[l] : ((l == i) ? 1.0 - 0.5 * (r[l] - 1.0) : 0.0);
+    }
+    return;
+  }
   const double ptol = k * DBL_EPSILON * dm;   // pivots at or below this count as rank deficiency
   bool bad = false;
 #pragma unroll

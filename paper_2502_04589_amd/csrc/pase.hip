@@ -90,7 +90,7 @@ struct pase_handle {
   int* netmask = nullptr;
   int fallbacks = 0;            // column switches to the V-cycle (this solve)
   int fast_hits = 0;            // corrections solved by the structured path (this solve)
-  int last_path = 0;            // 1 accepted, 0 dense only, -1 residual/orthogonality, -2 count
+  int last_path = 0;            // 1 accepted, 0 dense only, -1 residual, -2 count, -3 orthonormalisation
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 };
@@ -600,7 +600,7 @@ pase_status correction(pase_handle* h, int k) {
     int st[4];
     HIPC(hipMemcpyAsync(st, h->statf, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    h->last_path = (st[2] != 0 || st[1] == 0) ? -1 : -2;
+    h->last_path = (st[2] != 0) ? -3 : (st[1] == 0 ? -1 : -2);
     if (st[0] == 1 && st[2] == 0) {
       h->last_path = 1;
       launch_small_emit(nT, k, h->Vtf, h->permf, h->Vs, s);
