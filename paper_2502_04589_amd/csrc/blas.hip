@@ -530,6 +530,97 @@ __global__ __launch_bounds__(kBlock) void tsmm_kernel(long long N, int k, const 
   }
 }
 
+// ---- the same product on MFMA (v_mfma_f64_16x16x4f64), k <= 64.  A block walks chunks of 64
+// consecutive rows; a chunk of X (and of Y) is one contiguous run of 64 k doubles, read and written
+// with coalesced accesses.  Wave w owns output columns 16w .. 16w+15 and keeps that strip of op(C)
+// as B fragments in registers; the X chunk is staged in LDS (row stride kTsmLd) and read as A
+// fragments; the 64 x k result goes back through the same LDS array for the contiguous store.
+// MFMA operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register q
+// holds D[l/16 + 4q][l%16].
+constexpr int kTsmRows = 64;
+constexpr int kTsmLd = 66;   // 16 rows x 4 columns of an A fragment fall in distinct LDS banks
+constexpr int kTsmSE = kTsmRows * 64 / kBlock;   // staged doubles per thread (k <= 64)
+
+template <int TB>
+__global__ __launch_bounds__(kBlock) void tsmm_mfma_kernel(long long N, int k, const double* __restrict__ X,
+                                                           const double* __restrict__ C, double* __restrict__ Y,
+                                                           int accumulate, long long nchunks) {
+  __shared__ double xs[kTsmRows * kTsmLd];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int KS = (k + 3) >> 2;
+  for (int e = tid; e < kTsmRows * kTsmLd; e += kBlock) xs[e] = 0.0;   // columns >= k stay zero
+  // B fragments of this wave's column strip: b[s] = op(C)[4s + lk][16w + li], zero outside k
+  double b[16];
+  {
+    const int j = 16 * w + li, jc = (j < k) ? j : k - 1;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int kk = 4 * s + lk, kc = (kk < k) ? kk : k - 1;
+      const double v = TB ? C[(size_t)jc * k + kc] : C[(size_t)kc * k + jc];
+      b[s] = (kk < k && j < k) ? v : 0.0;
+    }
+  }
+  const int ck = kTsmRows * k;
+  // LDS slot of each staged element (row e / k, column e % k); independent of the chunk
+  int soff[kTsmSE];
+#pragma unroll
+  for (int u = 0; u < kTsmSE; ++u) {
+    const int e = tid + kBlock * u;
+    const int r = e / k;
+    soff[u] = (e < ck) ? r * kTsmLd + (e - r * k) : -1;
+  }
+  for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const long long lim = (N - c * kTsmRows) * k;
+    const int nval = (int)((lim < ck) ? lim : ck);   // valid doubles of this chunk
+    const double* __restrict__ xp = X + c * kTsmRows * k;
+    double* __restrict__ yp = Y + c * kTsmRows * k;
+    double sv[kTsmSE], yv[kTsmSE];
+#pragma unroll
+    for (int u = 0; u < kTsmSE; ++u) {
+      const int e = tid + kBlock * u;
+      const int ec = (e < nval) ? e : nval - 1;   // clamped, unconditional: all loads in flight together
+      sv[u] = xp[ec];
+      yv[u] = accumulate ? yp[ec] : 0.0;
+    }
+    __syncthreads();   // the previous chunk's result has been read out of xs
+#pragma unroll
+    for (int u = 0; u < kTsmSE; ++u) {
+      const int e = tid + kBlock * u;
+      if (soff[u] >= 0) xs[soff[u]] = (e < nval) ? sv[u] : 0.0;   // rows past N are zero
+    }
+    __syncthreads();
+    double4_t acc[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) acc[rt] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    if (16 * w < k) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        if (s < KS) {
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt)
+            acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[(16 * rt + li) * kTsmLd + 4 * s + lk], b[s], acc[rt],
+                                                           0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();   // every wave is done reading the X chunk
+    if (16 * w < k && 16 * w + li < k) {
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xs[(16 * rt + lk + 4 * q) * kTsmLd + 16 * w + li] = acc[rt][q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kTsmSE; ++u) {
+      const int e = tid + kBlock * u;
+      if (e < nval) yp[e] = xs[soff[u]] + yv[u];
+    }
+  }
+}
+
 __global__ void set_blocks_kernel(int n, int nh, int k, const double* __restrict__ C0, const double* __restrict__ G,
                                   const double* __restrict__ H, double* __restrict__ T) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -711,9 +802,10 @@ void launch_gemm_f32(bool ta, bool tb, int M, int N, int K, double alpha, const 
 void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, int tb,
                  hipStream_t s) {
   if (k <= 64) {
-    const unsigned blocks = (unsigned)((N + kTsRows - 1) / kTsRows);
-    if (tb) tsmm_kernel<1><<<blocks, kBlock, 0, s>>>(N, k, X, C, Y, accumulate);
-    else tsmm_kernel<0><<<blocks, kBlock, 0, s>>>(N, k, X, C, Y, accumulate);
+    const long long nchunks = (N + kTsmRows - 1) / kTsmRows;
+    const unsigned blocks = (unsigned)((nchunks < 768) ? nchunks : 768);
+    if (tb) tsmm_mfma_kernel<1><<<blocks, kBlock, 0, s>>>(N, k, X, C, Y, accumulate, nchunks);
+    else tsmm_mfma_kernel<0><<<blocks, kBlock, 0, s>>>(N, k, X, C, Y, accumulate, nchunks);
     return;
   }
   launch_gemm(false, tb != 0, (int)N, k, k, 1.0, X, k, C, k, accumulate ? 1.0 : 0.0, Y, k, s);

@@ -443,7 +443,6 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int n, int N
   double beta0;
   double tcur = make_reflector(prow + 1, n - 1, v, beta0, red, parity);
   if (b == 0 && tid == 0) { d[0] = prow[0]; e[0] = beta0; tau[0] = tcur; }
-  if (b == 0) for (int i = 1 + tid; i < n - 1; i += kCoopThreads) T[i + 1] = v[i];
   // p_0 over owned rows r >= 1: p[r-1] = tau0 sum_{c>=1} A[r][c] v[c-1]
   for (int q = wave; q < R; q += kCoopWaves) {
     const int r = q * NW + b;
@@ -460,6 +459,8 @@ __global__ __launch_bounds__(kCoopThreads) void tridiag_coop_kernel(int n, int N
       __hip_atomic_store(&rbuf[c], slab[(size_t)(1 / NW) * n + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   target += NW;
   if (!grid_barrier_fenced(counter, target, err)) return;
+  // reflector 0 goes into row 0 of T only now: every block has read that row before the barrier
+  if (b == 0) for (int i = 1 + tid; i < n - 1; i += kCoopThreads) T[i + 1] = v[i];
   // the cheap barrier only if every working block shares this XCD
   __shared__ int one_xcd;
   if (threadIdx.x == 0) {
