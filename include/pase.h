@@ -102,6 +102,8 @@ typedef struct pase_report {
                                     only, -1 = rejected by a residual, -2 = rejected by the eigenvalue
                                     count, -3 = its Cholesky-QR orthonormalisation broke down */
   int learned_fallbacks;         /* learned form: column switches to the V-cycle, summed over the solve */
+  int lowprec_projection_iters;  /* mixed form: corrections whose projection ran on FP32 vectors with
+                                    split-BF16 Grams (the rest ran in FP64) */
 } pase_report;
 
 typedef struct pase_handle pase_handle;
@@ -158,6 +160,14 @@ pase_status pase_prolong(pase_handle* h, int k, const double* Xc, double* Xf);
 
 /* G = X^T Y for N x k node-major X, Y (G: k x k row-major, device).  N <= N_0. */
 pase_status pase_gram(pase_handle* h, long long N, int k, const double* X, const double* Y, double* G);
+
+/* G = X^T Y (k x k, device, FP64) of FP32 operands X, Y (N x k row-major, device), k <= 64, the
+ * projection Gram of the mixed form's first phase (extension (1) of the method: low-precision
+ * projection, FP64 Rayleigh-Ritz).  Each value is split x = x_hi + x_lo into two BF16 numbers; a
+ * product is x_hi y_hi + x_hi y_lo + x_lo y_hi on BF16 MFMA with FP32 accumulation over blocks of
+ * 256 rows, the block sums added in FP64 in a fixed order.  Error per entry below about
+ * 2^-15 sum_r |x_r y_r|.  Synchronises the handle's stream. */
+pase_status pase_gram_bf16x3(pase_handle* h, long long N, int k, const float* X, const float* Y, double* G);
 
 /* The k smallest eigenpairs of a dense symmetric n x n matrix T (row-major, device):
  * w_host (k, ascending) and V (device, n x k row-major, orthonormal columns).

@@ -28,7 +28,8 @@ class Report(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("n_converged", C.c_int), ("res_host", C.c_void_p),
                 ("res_literal_host", C.c_void_p), ("ritz_history_host", C.c_void_p),
                 ("ritz_history_rows", C.c_int), ("t_solve_ms", C.c_double), ("small_fast_iters", C.c_int),
-                ("small_path_host", C.c_void_p), ("learned_fallbacks", C.c_int)]
+                ("small_path_host", C.c_void_p), ("learned_fallbacks", C.c_int),
+                ("lowprec_projection_iters", C.c_int)]
 
 
 # (name, restype, argtypes) for every entry point of include/pase.h
@@ -49,6 +50,7 @@ SIGNATURES = [
     ("pase_restrict", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     ("pase_prolong", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     ("pase_gram", C.c_int, [C.c_void_p, C.c_longlong, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pase_gram_bf16x3", C.c_int, [C.c_void_p, C.c_longlong, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pase_small_eig", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pase_small_eig_max_n", C.c_int, [C.c_void_p]),
     ("pase_correction", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),

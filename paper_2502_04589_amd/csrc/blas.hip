@@ -323,6 +323,145 @@ __global__ __launch_bounds__(kBlock) void gram_lds_kernel(long long N, int k, co
   }
 }
 
+// ---- split-BF16 Gram of FP32 operands: G_y = X^T Y_y (NY = 1 or 2, k <= 64) on
+// v_mfma_f32_16x16x32_bf16.  Each FP32 value is split as x = x_hi + x_lo with x_hi = bf16(x) and
+// x_lo = bf16(x - x_hi); a product is formed as x_hi y_hi + x_hi y_lo + x_lo y_hi (the dropped
+// x_lo y_lo is below 2^-16 |x y|).  The three MFMAs accumulate in FP32 over a K-block of 256 rows,
+// which is then added to an FP64 accumulator; the per-block partials are reduced in FP64 in a fixed
+// order.  A block walks its rows in 32-row chunks (one MFMA k-step): the chunk of each operand is a
+// contiguous run of 32 k floats, loaded with coalesced accesses and stored split and transposed in
+// LDS ([column][row], so a lane's 8 consecutive rows are one 16-byte read).  Operand layout of the
+// instruction: lane l supplies A[l%16][8(l/16) .. +7] and B[8(l/16) .. +7][l%16]; accumulator
+// register q holds D[4(l/16) + q][l%16].
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+constexpr int kG3Rows = 32;                    // rows per chunk = K of one MFMA
+constexpr int kG3Rs = kG3Rows + 8;             // LDS row stride of a column (bf16 elements)
+constexpr int kG3Flush = 8;                    // chunks per FP32 K-block (256 rows)
+constexpr int kG3SE = kG3Rows * 64 / kBlock;   // staged values per thread per operand
+
+template <int NY>
+__global__ __launch_bounds__(kBlock) void gram_bf16x3_kernel(long long N, int k, const float* __restrict__ X,
+                                                             const float* __restrict__ Y1,
+                                                             const float* __restrict__ Y2,
+                                                             double* __restrict__ partial, int tiles, long long rows) {
+  // [operand (X, Y1, Y2)][hi, lo][column 0..63][row]
+  __shared__ __align__(16) __bf16 st[1 + NY][2][64 * kG3Rs];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= tiles) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int T = (k + 15) >> 4, TT = T * T;
+  for (int e = tid; e < (1 + NY) * 2 * 64 * kG3Rs; e += kBlock) (&st[0][0][0])[e] = (__bf16)0.0f;
+  const long long r0 = (long long)tile * rows;
+  const long long r1 = (r0 + rows < N) ? (r0 + rows) : N;
+  const int ck = kG3Rows * k;
+  int soff[kG3SE];   // LDS slot (column * kG3Rs + row) of each staged value; independent of the chunk
+#pragma unroll
+  for (int u = 0; u < kG3SE; ++u) {
+    const int e = tid + kBlock * u;
+    const int r = e / k;
+    soff[u] = (e < ck) ? (e - r * k) * kG3Rs + r : -1;
+  }
+  float4_t acc1[4], acc2[4];
+  double4_t dacc1[4], dacc2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    acc1[t] = acc2[t] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    dacc1[t] = dacc2[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  }
+  const int li = lane & 15, g = lane >> 4;
+  int nchunk = 0;
+  for (long long rc = r0; rc < r1; rc += kG3Rows) {
+    const long long lim = (r1 - rc) * k;
+    const int nval = (int)((lim < ck) ? lim : ck);
+    float v[1 + NY][kG3SE];
+#pragma unroll
+    for (int u = 0; u < kG3SE; ++u) {   // clamped, unconditional loads: all in flight together
+      const int e = tid + kBlock * u;
+      const long long ec = rc * k + ((e < nval) ? e : nval - 1);
+      v[0][u] = X[ec];
+      v[1][u] = Y1[ec];
+      if (NY == 2) v[2][u] = Y2[ec];
+    }
+    __syncthreads();   // the previous chunk's operands have been read
+#pragma unroll
+    for (int u = 0; u < kG3SE; ++u) {
+      const int e = tid + kBlock * u;
+      if (soff[u] >= 0) {
+#pragma unroll
+        for (int m = 0; m < 1 + NY; ++m) {
+          const float x = (e < nval) ? v[m][u] : 0.0f;   // rows past the block's range are zero
+          const __bf16 hi = (__bf16)x;
+          st[m][0][soff[u]] = hi;
+          st[m][1][soff[u]] = (__bf16)(x - (float)hi);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int tt = wave + 4 * t;
+      if (tt < TT) {
+        const int ti = tt / T, tj = tt - (tt / T) * T;
+        const int ca = (16 * ti + li) * kG3Rs + 8 * g, cb = (16 * tj + li) * kG3Rs + 8 * g;
+        const bf16x8_t ah = *(const bf16x8_t*)&st[0][0][ca], al = *(const bf16x8_t*)&st[0][1][ca];
+        const bf16x8_t bh = *(const bf16x8_t*)&st[1][0][cb], bl = *(const bf16x8_t*)&st[1][1][cb];
+        acc1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc1[t], 0, 0, 0);
+        acc1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc1[t], 0, 0, 0);
+        acc1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc1[t], 0, 0, 0);
+        if (NY == 2) {
+          const bf16x8_t ch = *(const bf16x8_t*)&st[2][0][cb], cl = *(const bf16x8_t*)&st[2][1][cb];
+          acc2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, ch, acc2[t], 0, 0, 0);
+          acc2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, cl, acc2[t], 0, 0, 0);
+          acc2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, ch, acc2[t], 0, 0, 0);
+        }
+      }
+    }
+    if (++nchunk == kG3Flush) {   // end of a K-block: FP32 sums into the FP64 accumulators
+      nchunk = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          dacc1[t][q] += (double)acc1[t][q];
+          dacc2[t][q] += (double)acc2[t][q];
+        }
+        acc1[t] = acc2[t] = (float4_t){0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      dacc1[t][q] += (double)acc1[t][q];
+      dacc2[t][q] += (double)acc2[t][q];
+    }
+#pragma unroll
+  for (int y = 0; y < NY; ++y) {
+    double* p = partial + ((size_t)y * tiles + tile) * k * k;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int tt = wave + 4 * t;
+      if (tt < TT) {
+        const int ti = tt / T, tj = tt - (tt / T) * T;
+        const int j = 16 * tj + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * ti + 4 * g + q;
+          if (i < k && j < k) p[(size_t)i * k + j] = (y == 0) ? dacc1[t][q] : dacc2[t][q];
+        }
+      }
+    }
+  }
+}
+
+__global__ void f2d_kernel(size_t n, const float* __restrict__ a, double* __restrict__ b) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
 // ---- generic tiled FP64 GEMM: C = alpha op(A) op(B) + beta C (row-major)
 constexpr int GT = 64, GK = 16;
 
@@ -764,6 +903,21 @@ void launch_gram2(long long N, int k, const double* X, const double* Y1, const d
   }
   reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial, G1);
   if (Y2) reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial + (size_t)tiles * k * k, G2);
+}
+
+void launch_gram_bf16x3(long long N, int k, const float* X, const float* Y1, const float* Y2, double* partial,
+                        int tiles, double* G1, double* G2, hipStream_t s) {
+  long long rows = (N + tiles - 1) / tiles;
+  rows = ((rows + 3) / 4) * 4;
+  const int blocks = ((tiles + 7) / 8) * 8;
+  if (Y2) gram_bf16x3_kernel<2><<<blocks, kBlock, 0, s>>>(N, k, X, Y1, Y2, partial, tiles, rows);
+  else gram_bf16x3_kernel<1><<<blocks, kBlock, 0, s>>>(N, k, X, Y1, nullptr, partial, tiles, rows);
+  reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial, G1);
+  if (Y2) reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial + (size_t)tiles * k * k, G2);
+}
+
+void launch_f2d(size_t n, const float* a, double* b, hipStream_t s) {
+  f2d_kernel<<<nblk((long long)n), kBlock, 0, s>>>(n, a, b);
 }
 
 void launch_gram(long long N, int k, const double* X, const double* Y, double* partial, int tiles, double* G,

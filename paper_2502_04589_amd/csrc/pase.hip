@@ -91,6 +91,10 @@ struct pase_handle {
   int fallbacks = 0;            // column switches to the V-cycle (this solve)
   int fast_hits = 0;            // corrections solved by the structured path (this solve)
   int last_path = 0;            // 1 accepted, 0 dense only, -1 residual, -2 count, -3 orthonormalisation
+  // mixed form: the projection runs on FP32 vectors with split-BF16 Grams until the residual drops
+  // below 1e-6 or stops halving over two corrections (then FP64 to the end of the solve)
+  bool proj_lp = false;
+  int proj_lp_iters = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 };
@@ -567,9 +571,27 @@ pase_status correction(pase_handle* h, int k) {
   prolong_all(h, k, h->cb, W, 2);
   if (h->fast) launch_copy((size_t)NH * k, h->ca, h->cmw, s);   // P^T M W: W's coarse coordinates
   // (b) projection: A W, M W, a = P^T A W, alpha = W^T A W, beta = W^T M W
-  apply_AM(h, 0, k, W, h->W2, h->W3);
-  restrict_all(h, k, h->W2, h->ca);
-  launch_gram2(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
+  if (h->proj_lp) {
+    // low-precision projection: W in FP32, FP32 stencils, FP32 restriction, split-BF16 Grams with
+    // FP32 K-blocks summed in FP64 (the CG's FP32 vectors are free here)
+    float* W32 = h->R32;
+    float* AW32 = h->Z32;
+    float* MW32 = h->P32;
+    launch_d2f((size_t)N * k, W, W32, s);
+    stencil_op(h, 0, k, EPI_AM, W32, nullptr, AW32, MW32, 1);
+    const float* src = AW32;
+    for (int l = 0; l < h->L; ++l) {
+      launch_restrict(h->dim, h->lev[l].m, h->lev[l + 1].m, k, src, h->vb32[l + 1], 1, s);
+      src = h->vb32[l + 1];
+    }
+    launch_f2d((size_t)NH * k, h->vb32[h->L], h->ca, s);
+    launch_gram_bf16x3(N, k, W32, AW32, MW32, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);
+    ++h->proj_lp_iters;
+  } else {
+    apply_AM(h, 0, k, W, h->W2, h->W3);
+    restrict_all(h, k, h->W2, h->ca);
+    launch_gram2(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
+  }
   launch_symmetrize(k, h->kk1, s);
   launch_symmetrize(k, h->kk2, s);
   if (h->fast) launch_copy((size_t)k * k, h->kk2, h->kkb, s);
@@ -903,6 +925,17 @@ pase_status pase_gram(pase_handle* h, long long N, int k, const double* X, const
   return PASE_OK;
 }
 
+pase_status pase_gram_bf16x3(pase_handle* h, long long N, int k, const float* X, const float* Y, double* G) {
+  pase_status st = check_k(h, k);
+  if (st) return st;
+  if (k > 64) return fail(h, PASE_E_ARG, "the split-BF16 Gram needs k <= 64");
+  if (!X || !Y || !G || N < 1 || N > h->lev[0].N) return fail(h, PASE_E_ARG, "bad Gram arguments");
+  launch_gram_bf16x3(N, k, X, Y, nullptr, h->partial, gram_tiles(N, k), G, nullptr, h->stream);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
 int pase_small_eig_max_n(const pase_handle* h) { return h ? std::min(h->nT, syev_max_n()) : 0; }
 
 pase_status pase_small_eig(pase_handle* h, int n, int k, const double* T, double* w_host, double* V) {
@@ -959,6 +992,9 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   HIPC(hipMemsetAsync(h->info, 0, 16 * sizeof(int), s));
   h->fast_hits = 0;
   h->fallbacks = 0;
+  h->proj_lp = (h->opt.precision == PASE_PREC_MIXED && k <= 64);
+  h->proj_lp_iters = 0;
+  double maxres_prev[2] = {0.0, 0.0};
   if (h->opt.precision == PASE_PREC_LEARNED && !h->net)
     return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
   launch_copy((size_t)N * k, U0, h->U, s);
@@ -1002,6 +1038,15 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     }
     if (nconv == k) { conv = true; break; }
     if (it >= h->opt.max_outer) break;
+    if (h->proj_lp) {
+      double mr = 0.0;
+      for (int j = 0; j < k; ++j) mr = std::max(mr, res[j]);
+      // phase 2 (FP64 projection) once the largest residual is below 1e-6, or when it has not
+      // fallen by 10 % over two corrections (the FP32 projection's accuracy floor)
+      if (mr < 1e-6 || (it >= 2 && mr > 0.9 * maxres_prev[1])) h->proj_lp = false;
+      maxres_prev[1] = maxres_prev[0];
+      maxres_prev[0] = mr;
+    }
     st = correction(h, k);
     if (st) return st;
     if (rep && rep->small_path_host && it < h->opt.max_outer) rep->small_path_host[it] = h->last_path;
@@ -1020,6 +1065,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     rep->t_solve_ms = ms;
     rep->small_fast_iters = h->fast_hits;
     rep->learned_fallbacks = h->fallbacks;
+    rep->lowprec_projection_iters = h->proj_lp_iters;
     if (rep->res_host) std::memcpy(rep->res_host, res.data(), sizeof(double) * k);
     if (rep->res_literal_host) std::memcpy(rep->res_literal_host, lit.data(), sizeof(double) * k);
   }

@@ -88,9 +88,9 @@ class Solver:
             msg = self.lib.pase_last_error(h if h is not None else None)
             raise PaseError(st, msg.decode() if msg else "")
 
-    def _mv(self, t, rows, k, name):
-        if not (isinstance(t, torch.Tensor) and t.device == self.device and t.dtype == torch.float64):
-            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+    def _mv(self, t, rows, k, name, dtype=torch.float64):
+        if not (isinstance(t, torch.Tensor) and t.device == self.device and t.dtype == dtype):
+            raise TypeError(f"{name} must be a {dtype} tensor on {self.device}")
         if t.shape != (rows, k) or not t.is_contiguous():
             raise ValueError(f"{name} must be a contiguous {rows} x {k} tensor")
         return t
@@ -134,6 +134,7 @@ class Solver:
         report = {"outer_iters": rep.outer_iters, "n_converged": rep.n_converged, "res": res,
                   "res_literal": lit, "t_solve_ms": rep.t_solve_ms, "small_fast_iters": rep.small_fast_iters,
                   "small_path": paths[:rep.outer_iters].copy(), "learned_fallbacks": rep.learned_fallbacks,
+                  "lowprec_projection_iters": rep.lowprec_projection_iters,
                   "status": nat.STATUS.get(st, st)}
         if history:
             report["ritz_history"] = hist[:rep.ritz_history_rows].copy()
@@ -184,6 +185,15 @@ class Solver:
         Y = self._mv(Y, N, k, "Y")
         G = self._new(k, k)
         self._check(self.lib.pase_gram(self.h, int(N), k, _ptr(X), _ptr(Y), _ptr(G)), self.h)
+        return G
+
+    def gram_bf16x3(self, X, Y):
+        """X^T Y of float32 N x k blocks (k <= 64) by split-BF16 products, FP64 result."""
+        N, k = X.shape
+        X = self._mv(X, N, k, "X", torch.float32)
+        Y = self._mv(Y, N, k, "Y", torch.float32)
+        G = self._new(k, k)
+        self._check(self.lib.pase_gram_bf16x3(self.h, int(N), k, _ptr(X), _ptr(Y), _ptr(G)), self.h)
         return G
 
     def small_eig(self, T, k):

@@ -89,6 +89,27 @@ def test_gram_mfma(N, k):
     assert np.abs(G - ref).max() <= 1e-13 * np.sqrt(N) * np.abs(X).max() * np.abs(Y).max() + 1e-14
 
 
+@pytest.mark.parametrize("N,k", [(1, 1), (37, 5), (1000, 16), (4099, 17), (20000, 50), (250047, 50), (9001, 64)])
+def test_gram_bf16x3(N, k):
+    """Split-BF16 Gram of FP32 blocks against the exact Gram of the same FP32 values.
+
+    Bound per entry from the arithmetic: each value is split into two BF16 numbers (the split
+    leaves at most 2^-18 |x|), the dropped lo*lo product is at most 2^-18 |xy|, and FP32
+    accumulation over 256-row blocks adds at most 256 * 2^-24 of sum |xy|: 2^-15 sum |x_r y_r|
+    covers all three.  The split must also beat a plain BF16 product (2^-8 relative) by far.
+    """
+    s = Solver(3, [64, 32, 16, 8], nev_max=64)
+    rng = np.random.default_rng(N * 7 + k)
+    X = rng.standard_normal((N, k)).astype(np.float32)
+    Y = (rng.standard_normal((N, k)) + 0.3).astype(np.float32)
+    G = host(s.gram_bf16x3(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()))
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    ref = X64.T @ Y64
+    bound = 2.0 ** -15 * (np.abs(X64).T @ np.abs(Y64))
+    assert np.all(np.abs(G - ref) <= bound), np.max(np.abs(G - ref) / bound)
+    assert np.abs(G - ref).max() <= 2.0 ** -12 * np.abs(ref).max() + 1e-30
+
+
 def test_gram_is_bitwise_deterministic():
     s = Solver(3, [32, 16, 8], nev_max=50)
     rng = np.random.default_rng(1)
@@ -246,6 +267,7 @@ def test_mixed_config1_matches_fp64_oracle():
     np.testing.assert_allclose(lam, q1_laplace_eigs(2, 128, k), rtol=1e-9)
     assert rep["n_converged"] == k and np.all(rep["res"] <= 1e-10)
     assert abs(rep["outer_iters"] - ref.iters) <= 3
+    assert 0 < rep["lowprec_projection_iters"] < rep["outer_iters"]
     Uh = host(U)
     assert np.abs(Uh.T @ (H.M[0] @ Uh) - np.eye(k)).max() < 1e-12
     res = opase.residuals(H.A[0], H.M[0], Uh, lam)[0]
@@ -287,6 +309,8 @@ def test_mixed_config2_closed_form_full_size():
     err = np.abs(lam / q1_laplace_eigs(3, 64, k) - 1)
     assert err.max() < 1e-8, err.max()
     assert rep["n_converged"] == k and np.all(rep["res"] <= 1e-8)
+    # the first phase (FP32 projection, split-BF16 Grams) ran, and the FP64 phase finished the solve
+    assert 0 < rep["lowprec_projection_iters"] < rep["outer_iters"]
     _, MU = s.apply(0, U)
     G = host(U.T.contiguous() @ MU)
     assert np.abs(G - np.eye(k)).max() < 1e-12
