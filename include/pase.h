@@ -86,6 +86,11 @@ typedef struct pase_options {
   double omega;                  /* Jacobi damping (default 2/3) */
   int small_solver;              /* augmented eigenproblem: 0 = structured shift-invert path with dense
                                     fallback (default), 1 = dense eigensolver only */
+  int locking;                   /* 1 (default): soft locking -- the fine solves of a correction run only
+                                    for the pairs whose residual exceeds tol / 10 (a locked pair keeps
+                                    w = u; the Rayleigh-Ritz still spans every pair, and a pair whose
+                                    residual rises again is unlocked); 0: every pair every correction,
+                                    as the algorithm is stated.  Plain FP64 and mixed forms only. */
 } pase_options;
 
 /* Filled by pase_solve.  Array members are optional HOST buffers (NULL = not wanted). */
@@ -104,6 +109,8 @@ typedef struct pase_report {
   int learned_fallbacks;         /* learned form: column switches to the V-cycle, summed over the solve */
   int lowprec_projection_iters;  /* mixed form: corrections whose projection ran on FP32 vectors with
                                     split-BF16 Grams (the rest ran in FP64) */
+  int fine_solve_columns;        /* columns that ran the fine solves, summed over the corrections
+                                    (nev x outer_iters without locking) */
 } pase_report;
 
 typedef struct pase_handle pase_handle;

@@ -21,7 +21,7 @@ class Problem(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("nev_max", C.c_int), ("cg_steps", C.c_int), ("max_outer", C.c_int),
-                ("nu", C.c_int), ("omega", C.c_double), ("small_solver", C.c_int)]
+                ("nu", C.c_int), ("omega", C.c_double), ("small_solver", C.c_int), ("locking", C.c_int)]
 
 
 class Report(C.Structure):
@@ -29,7 +29,7 @@ class Report(C.Structure):
                 ("res_literal_host", C.c_void_p), ("ritz_history_host", C.c_void_p),
                 ("ritz_history_rows", C.c_int), ("t_solve_ms", C.c_double), ("small_fast_iters", C.c_int),
                 ("small_path_host", C.c_void_p), ("learned_fallbacks", C.c_int),
-                ("lowprec_projection_iters", C.c_int)]
+                ("lowprec_projection_iters", C.c_int), ("fine_solve_columns", C.c_int)]
 
 
 # (name, restype, argtypes) for every entry point of include/pase.h

@@ -99,6 +99,23 @@ __global__ void fallback_kernel(int k, double ratio2, const double* rn, const do
 }
 
 // Z[:, j] = (mask[j] == 1) ? A[:, j] : Z[:, j]
+// Column gather / scatter of node-major blocks: C (N x ka) <-> the columns idx[0..ka) of B (N x k).
+__global__ void gather_cols_kernel(long long N, int k, int ka, const int* __restrict__ idx,
+                                   const double* __restrict__ B, double* __restrict__ C) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * ka) return;
+  const long long n = q / ka;
+  C[q] = B[n * k + idx[q - n * ka]];
+}
+
+__global__ void scatter_cols_kernel(long long N, int k, int ka, const int* __restrict__ idx,
+                                    const double* __restrict__ C, double* __restrict__ B) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * ka) return;
+  const long long n = q / ka;
+  B[n * k + idx[q - n * ka]] = C[q];
+}
+
 __global__ void select_cols_kernel(long long N, int k, const int* __restrict__ mask, const double* __restrict__ A,
                                    double* __restrict__ Z) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -834,6 +851,14 @@ void launch_flex_beta(int k, const double* a, const double* b, const double* c, 
 
 void launch_fallback(int k, double ratio, const double* rn, const double* ro, int* mask, hipStream_t s) {
   fallback_kernel<<<1, kBlock, 0, s>>>(k, ratio * ratio, rn, ro, mask);
+}
+
+void launch_gather_cols(long long N, int k, int ka, const int* idx, const double* B, double* C, hipStream_t s) {
+  gather_cols_kernel<<<nblk(N * ka), kBlock, 0, s>>>(N, k, ka, idx, B, C);
+}
+
+void launch_scatter_cols(long long N, int k, int ka, const int* idx, const double* C, double* B, hipStream_t s) {
+  scatter_cols_kernel<<<nblk(N * ka), kBlock, 0, s>>>(N, k, ka, idx, C, B);
 }
 
 void launch_select_cols(long long N, int k, const int* mask, const double* A, double* Z, hipStream_t s) {

@@ -150,6 +150,9 @@ void launch_flex_beta(int k, const double* a, const double* b, const double* c, 
                       hipStream_t s);
 void launch_fallback(int k, double ratio, const double* rn, const double* ro, int* mask, hipStream_t s);
 void launch_select_cols(long long N, int k, const int* mask, const double* A, double* Z, hipStream_t s);
+// C (N x ka) = columns idx[0..ka) of B (N x k), and back
+void launch_gather_cols(long long N, int k, int ka, const int* idx, const double* B, double* C, hipStream_t s);
+void launch_scatter_cols(long long N, int k, int ka, const int* idx, const double* C, double* B, hipStream_t s);
 void launch_fill_int(int n, int v, int* p, hipStream_t s);
 void launch_node_logk(int n, const double* kappa, double* out, hipStream_t s);
 // the network's kernels run on the given stream from now on

@@ -95,6 +95,11 @@ struct pase_handle {
   // below 1e-6 or stops halving over two corrections (then FP64 to the end of the solve)
   bool proj_lp = false;
   int proj_lp_iters = 0;
+  // soft locking: the next correction's fine solves run for the ka columns lock_idx[0..ka)
+  int* lock_idx = nullptr;
+  int ka = 0;
+  std::vector<int> lock_host;
+  int fine_cols = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 };
@@ -131,6 +136,7 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (o->cg_steps < 1 || o->max_outer < 0 || o->nu < 1) return PASE_E_ARG;
   if (!(o->omega > 0.0)) return PASE_E_ARG;
   if (o->small_solver != 0 && o->small_solver != 1) return PASE_E_ARG;
+  if (o->locking != 0 && o->locking != 1) return PASE_E_ARG;
   if (o->precision != PASE_PREC_FP64 && o->precision != PASE_PREC_MIXED && o->precision != PASE_PREC_LEARNED)
     return PASE_E_UNSUPPORTED;
   if (o->precision == PASE_PREC_LEARNED && p->dim != 3) return PASE_E_UNSUPPORTED;   // the network is 3D
@@ -178,6 +184,7 @@ size_t layout(pase_handle* h, void* base) {
     const size_t NHf = (size_t)h->lev[h->L].N;
     h->AinvL32 = b.take<float>(NHf * NHf);
   }
+  h->lock_idx = b.take<int>(K);
   if (h->opt.precision == PASE_PREC_LEARNED) {
     h->logk = b.take<double>((size_t)N0);
     h->rr0 = b.take<double>(K); h->rr1 = b.take<double>(K); h->rzo = b.take<double>(K);
@@ -552,7 +559,18 @@ pase_status correction(pase_handle* h, int k) {
   const long long N = h->lev[0].N;
   const int NH = (int)h->lev[h->L].N;
   // (a) fine solves A w = lam M u from w = u: s CG steps per column
-  if (h->opt.precision == PASE_PREC_MIXED) {
+  const int ka = (h->ka > 0 && h->ka < k) ? h->ka : k;
+  h->fine_cols += ka;
+  if (ka < k) {
+    // soft locking: the active columns of U and R gathered into W2, W3 (leading dimension ka), their
+    // fine solves into R (free until the next residual), then W = U with the active columns replaced
+    launch_gather_cols(N, k, ka, h->lock_idx, h->U, h->W2, s);
+    launch_gather_cols(N, k, ka, h->lock_idx, h->R, h->W3, s);
+    if (h->opt.precision == PASE_PREC_MIXED) pcg_correction_f32(h, ka, h->W2, h->W3, h->R);
+    else pcg(h, ka, h->W2, h->R, h->W3);
+    launch_copy((size_t)N * k, h->U, h->X, s);
+    launch_scatter_cols(N, k, ka, h->lock_idx, h->R, h->X, s);
+  } else if (h->opt.precision == PASE_PREC_MIXED) {
     pcg_correction_f32(h, k, h->U, h->R, h->X);
   } else if (h->opt.precision == PASE_PREC_LEARNED) {
     if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
@@ -674,6 +692,7 @@ void pase_options_default(pase_options* opt) {
   opt->nu = 2;
   opt->omega = 2.0 / 3.0;
   opt->small_solver = 0;
+  opt->locking = 1;
 }
 
 const char* pase_status_string(pase_status s) {
@@ -966,6 +985,7 @@ pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* 
   HIPC(hipMemcpyAsync(h->lam, lambda_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
   launch_copy((size_t)N * k, U, h->U, s);
   eig_residual(h, k, h->U, h->R);
+  h->ka = 0;
   st = correction(h, k);
   if (st) return st;
   launch_copy((size_t)N * k, h->U, U, s);
@@ -994,7 +1014,11 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   h->fallbacks = 0;
   h->proj_lp = (h->opt.precision == PASE_PREC_MIXED && k <= 64);
   h->proj_lp_iters = 0;
-  double maxres_prev[2] = {0.0, 0.0};
+  h->ka = 0;
+  h->fine_cols = 0;
+  const bool locking = h->opt.locking && h->opt.precision != PASE_PREC_LEARNED;
+  double lp_best = 0.0;   // smallest max-residual seen in the first phase
+  int lp_stall = 0;       // corrections since it last decreased
   if (h->opt.precision == PASE_PREC_LEARNED && !h->net)
     return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
   launch_copy((size_t)N * k, U0, h->U, s);
@@ -1038,20 +1062,38 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     }
     if (nconv == k) { conv = true; break; }
     if (it >= h->opt.max_outer) break;
+    if (locking) {
+      // the next correction's fine solves: pairs with res > tol / 10 (ascending column order)
+      h->lock_host.clear();
+      for (int j = 0; j < k; ++j)
+        if (!(res[j] <= 0.1 * tol)) h->lock_host.push_back(j);
+      h->ka = (int)h->lock_host.size();
+      if (h->ka > 0 && h->ka < k)
+        HIPC(hipMemcpyAsync(h->lock_idx, h->lock_host.data(), sizeof(int) * h->ka, hipMemcpyHostToDevice, s));
+    }
     if (h->proj_lp) {
-      double mr = 0.0;
-      for (int j = 0; j < k; ++j) mr = std::max(mr, res[j]);
-      // phase 2 (FP64 projection) once the largest residual is below 1e-6, or when it has not
-      // fallen by 10 % over two corrections (the FP32 projection's accuracy floor)
-      if (mr < 1e-6 || (it >= 2 && mr > 0.9 * maxres_prev[1])) h->proj_lp = false;
-      maxres_prev[1] = maxres_prev[0];
-      maxres_prev[0] = mr;
+      double mr = 0.0, mn = 1e300;
+      for (int j = 0; j < k; ++j) {
+        mr = std::max(mr, res[j]);
+        mn = std::min(mn, res[j]);
+      }
+      // phase 2 (FP64 projection) as soon as some pair nears the low-precision projection's
+      // accuracy floor (residuals of 1e-6 to 5e-6: a pair below 1e-5), or when the largest
+      // residual has not reached a new low for 3 corrections
+      if (it == 0 || mr < lp_best) {
+        lp_best = mr;
+        lp_stall = 0;
+      } else {
+        ++lp_stall;
+      }
+      if (mn < 1e-5 || lp_stall >= 3) h->proj_lp = false;
     }
     st = correction(h, k);
     if (st) return st;
     if (rep && rep->small_path_host && it < h->opt.max_outer) rep->small_path_host[it] = h->last_path;
     ++it;
   }
+  h->ka = 0;   // the standalone correction entry points always run every column
   launch_copy((size_t)N * k, h->U, U, s);
   HIPC(hipEventRecord(h->ev1, s));
   HIPC(hipMemcpyAsync(lambda_host, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
@@ -1066,6 +1108,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     rep->small_fast_iters = h->fast_hits;
     rep->learned_fallbacks = h->fallbacks;
     rep->lowprec_projection_iters = h->proj_lp_iters;
+    rep->fine_solve_columns = h->fine_cols;
     if (rep->res_host) std::memcpy(rep->res_host, res.data(), sizeof(double) * k);
     if (rep->res_literal_host) std::memcpy(rep->res_literal_host, lit.data(), sizeof(double) * k);
   }
@@ -1136,6 +1179,7 @@ pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double*
         // a correction consumes R and overwrites U; run it on copies so repeated calls see the same input
         launch_copy((size_t)N * k, h->U, h->W2, s);
         eig_residual(h, k, h->U, h->R);
+        h->ka = 0;
         correction(h, k);
         launch_copy((size_t)N * k, h->W2, h->U, s);
         break;

@@ -33,10 +33,13 @@ class Solver:
              the last one is the coarse space V_H.
     kappa:   None (kappa = 1) or n^dim element values, x fastest (array or tensor).
     nev_max: largest nev a solve may ask for.
+    locking: True (default): a correction's fine solves skip the pairs whose residual is already
+             below tol / 10 (they keep w = u; the Rayleigh-Ritz still uses every pair); False:
+             every pair every correction, as the algorithm is stated.
     """
 
     def __init__(self, dim, levels, kappa=None, nev_max=16, precision="fp64", cg_steps=2, max_outer=500,
-                 nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0"):
+                 nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0", locking=True):
         self.lib = nat.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
@@ -67,6 +70,7 @@ class Solver:
         opt.nu = int(nu)
         opt.omega = float(omega)
         opt.small_solver = {"auto": 0, "dense": 1}[small_solver]
+        opt.locking = 1 if locking else 0
         self.opt = opt
         nbytes = C.c_size_t(0)
         self._check(self.lib.pase_workspace_bytes(C.byref(prob), C.byref(opt), C.byref(nbytes)), None)
@@ -135,6 +139,7 @@ class Solver:
                   "res_literal": lit, "t_solve_ms": rep.t_solve_ms, "small_fast_iters": rep.small_fast_iters,
                   "small_path": paths[:rep.outer_iters].copy(), "learned_fallbacks": rep.learned_fallbacks,
                   "lowprec_projection_iters": rep.lowprec_projection_iters,
+                  "fine_solve_columns": rep.fine_solve_columns,
                   "status": nat.STATUS.get(st, st)}
         if history:
             report["ritz_history"] = hist[:rep.ritz_history_rows].copy()

@@ -316,6 +316,45 @@ def test_mixed_config2_closed_form_full_size():
     assert np.abs(G - np.eye(k)).max() < 1e-12
 
 
+# ---- soft locking: the fine solves skip pairs already below tol / 10
+
+@pytest.mark.parametrize("dim,levels,kseed,k,prec", [
+    (2, [128, 64, 32, 16], None, 10, "fp64"),
+    (3, [32, 16, 8, 4], None, 20, "fp64"),
+    (3, [16, 8, 4], 5, 8, "mixed"),
+    (3, [32, 16, 8, 4], 7, 13, "mixed"),
+])
+def test_locking_matches_every_column_solves(dim, levels, kseed, k, prec):
+    """Locked and unlocked solves from the same start reach the same eigenpairs (closed form or
+    dense reference to 1e-10); locking performs fewer column solves and every pair still meets tol."""
+    kap = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
+    H = multigrid.Hierarchy(dim, levels, kap)
+    U0 = dev(synth.initial_vectors(H.A[0].shape[0], k, 3))
+    out = {}
+    for lock in (True, False):
+        s = Solver(dim, levels, kap, nev_max=k, precision=prec, locking=lock)
+        lam, U, rep = s.solve(k, 1e-10, U0)
+        assert rep["n_converged"] == k and np.all(rep["res"] <= 1e-10)
+        Uh = host(U)
+        assert np.abs(Uh.T @ (H.M[0] @ Uh) - np.eye(k)).max() < 1e-12
+        res = opase.residuals(H.A[0], H.M[0], Uh, lam)[0]
+        assert np.all(res <= 1e-10 * (1 + 1e-6))
+        out[lock] = (lam, rep)
+    lam_l, rep_l = out[True]
+    lam_u, rep_u = out[False]
+    if kseed is None:
+        ref = q1_laplace_eigs(dim, levels[0], k)
+    elif H.A[0].shape[0] <= 4000:
+        ref = sla.eigh(H.A[0].toarray(), H.M[0].toarray(), subset_by_index=[0, k - 1], eigvals_only=True)
+    else:   # kappa on 31^3 nodes: the unlocked solve (and the oracle residuals above) pin it
+        ref = lam_u
+    np.testing.assert_allclose(lam_l, ref, rtol=1e-10)
+    np.testing.assert_allclose(lam_u, ref, rtol=1e-10)
+    assert rep_u["fine_solve_columns"] == k * rep_u["outer_iters"]
+    assert rep_l["fine_solve_columns"] < k * rep_l["outer_iters"]
+    assert abs(rep_l["outer_iters"] - rep_u["outer_iters"]) <= 3
+
+
 # ---- structured augmented eigenproblem (shift-invert in the eigenbasis of C0) vs the dense solver
 
 @pytest.mark.parametrize("dim,levels,kseed,k,tol", [
