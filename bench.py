@@ -201,7 +201,7 @@ def main():
         for _ in range(args.warmup):
             s.solve(nev, tol, U0, raise_notconv=strict)
         torch.cuda.synchronize()
-        conv, iters, fast, fb, lp = 0, [], [], [], []
+        conv, iters, fast, fb, lp, fc = 0, [], [], [], [], []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             lam, U, rep = s.solve(nev, tol, U0, raise_notconv=strict)
@@ -210,6 +210,7 @@ def main():
             fast.append(rep["small_fast_iters"])
             fb.append(rep["learned_fallbacks"])
             lp.append(rep["lowprec_projection_iters"])
+            fc.append(rep["fine_solve_columns"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         err, per = None, None
@@ -223,7 +224,8 @@ def main():
                         "max_rel_err_vs_closed_form": err, "rel_err_per_eigenvalue": per,
                         "max_res": float(np.max(rep["res"])),
                         "learned_fallbacks": fb[-1] if precision == "learned" else None,
-                        "lowprec_projection_iters": lp[-1] if precision == "mixed" else None}
+                        "lowprec_projection_iters": lp[-1] if precision == "mixed" else None,
+                        "fine_solve_columns": fc[-1]}
 
     s, U0h, plain = run_form("fp64")
     mixed = None if args.no_mixed else run_form("mixed")[2]
@@ -255,7 +257,7 @@ def main():
         "config": {
             "workload": f"{args.workload}: {dim}D Q1 Laplace, {levels[0]}^{dim} mesh "
                         f"({s.N[0]} DOFs), V_H {levels[-1]}^{dim} ({s.N[-1]} DOFs), GMG levels "
-                        f"{'/'.join(map(str, levels))}, nev {nev}, tol {tol:g}, 2 CG steps; value = plain FP64 form",
+                        f"{'/'.join(map(str, levels))}, nev {nev}, tol {tol:g}, 2 CG steps, soft locking of pairs below tol/10; value = plain FP64 form",
             "dofs": s.N[0], "nev": nev, "tol": tol,
         },
         "forms": {
