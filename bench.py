@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned form")
+    ap.add_argument("--no-locking", action="store_true",
+                    help="run the fine solves for every pair every correction (no soft locking)")
     ap.add_argument("--train-steps", type=int, default=200, help="Adam steps of the learned preconditioner")
     ap.add_argument("--harvest-iters", type=int, default=8, help="outer iterations harvested for training")
     args = ap.parse_args()
@@ -189,7 +191,7 @@ def main():
 
     def run_form(precision, net=None):
         t0 = time.perf_counter()
-        s = Solver(dim, levels, kappa, nev_max=nev, precision=precision)
+        s = Solver(dim, levels, kappa, nev_max=nev, precision=precision, locking=not args.no_locking)
         if net is not None:
             s.attach(net)
         torch.cuda.synchronize()
