@@ -90,7 +90,7 @@ typedef struct pase_options {
                                     for the pairs whose residual exceeds tol / 10 (a locked pair keeps
                                     w = u; the Rayleigh-Ritz still spans every pair, and a pair whose
                                     residual rises again is unlocked); 0: every pair every correction,
-                                    as the algorithm is stated.  Plain FP64 and mixed forms only. */
+                                    as the algorithm is stated. */
 } pase_options;
 
 /* Filled by pase_solve.  Array members are optional HOST buffers (NULL = not wanted). */

@@ -468,15 +468,16 @@ void pcg_correction_f32(pase_handle* h, int k, const double* U, const double* R,
 }
 
 // Learned form: z = N(r) for the columns still on the network, z = V(r) for the others.
-// non = number of columns on the network (the host copy of the mask count).
-pase_status learned_precond(pase_handle* h, int k, const double* R, double* Z, int non) {
+// non = number of columns on the network (the host copy of the mask count); scratch (N x k)
+// holds the network's output while some columns are on the V-cycle.
+pase_status learned_precond(pase_handle* h, int k, const double* R, double* Z, int non, double* scratch) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   if (non < k) vcycle(h, 0, k, R, Z);
   if (non == 0) return PASE_OK;
-  const pase_status st = pase_unet_apply(h->net, k, R, h->logk, (non == k) ? Z : h->W2);
+  const pase_status st = pase_unet_apply(h->net, k, R, h->logk, (non == k) ? Z : scratch);
   if (st) return fail(h, st, std::string("network: ") + pase_unet_last_error(h->net));
-  if (non < k) launch_select_cols(N, k, h->netmask, h->W2, Z, s);
+  if (non < k) launch_select_cols(N, k, h->netmask, scratch, Z, s);
   return PASE_OK;
 }
 
@@ -485,14 +486,15 @@ pase_status learned_precond(pase_handle* h, int k, const double* R, double* Z, i
 // column whose residual norm does not fall below half its previous value switches to the
 // V-cycle for the remaining steps; the step is kept and the recurrence restarts (beta = 0), so
 // the remaining steps are V-cycle PCG from that iterate.  Returns the number of switches.
-pase_status learned_pcg(pase_handle* h, int k, const double* X0, double* X, double* R, int* switches) {
+pase_status learned_pcg(pase_handle* h, int k, const double* X0, double* X, double* R, int* switches,
+                        double* scratch) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   *switches = 0;
   launch_fill_int(k, 1, h->netmask, s);
   int non = k;
   std::vector<int> mk(k);
-  pase_status st = learned_precond(h, k, R, h->Z, non);
+  pase_status st = learned_precond(h, k, R, h->Z, non, scratch);
   if (st) return st;
   std::swap(h->Z, h->P);                                      // p_0 = z_0
   coldot(h, N, k, R, h->P, h->rho);
@@ -517,7 +519,7 @@ pase_status learned_pcg(pase_handle* h, int k, const double* X0, double* X, doub
         non = c;
       }
       coldot(h, N, k, R, (j == 0) ? h->P : h->Z, h->rzo);     // r_{j+1}^T z_j (p_0 = z_0)
-      st = learned_precond(h, k, R, h->Z, non);
+      st = learned_precond(h, k, R, h->Z, non, scratch);
       if (st) return st;
       coldot(h, N, k, R, h->Z, h->rho2);                      // r_{j+1}^T z_{j+1}
       launch_flex_beta(k, h->rho2, h->rzo, h->rho, h->netmask, h->beta, s);
@@ -566,8 +568,17 @@ pase_status correction(pase_handle* h, int k) {
     // fine solves into R (free until the next residual), then W = U with the active columns replaced
     launch_gather_cols(N, k, ka, h->lock_idx, h->U, h->W2, s);
     launch_gather_cols(N, k, ka, h->lock_idx, h->R, h->W3, s);
-    if (h->opt.precision == PASE_PREC_MIXED) pcg_correction_f32(h, ka, h->W2, h->W3, h->R);
-    else pcg(h, ka, h->W2, h->R, h->W3);
+    if (h->opt.precision == PASE_PREC_MIXED) {
+      pcg_correction_f32(h, ka, h->W2, h->W3, h->R);
+    } else if (h->opt.precision == PASE_PREC_LEARNED) {
+      if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
+      int sw = 0;
+      const pase_status st = learned_pcg(h, ka, h->W2, h->R, h->W3, &sw, h->X);   // X is free until the copy
+      if (st) return st;
+      h->fallbacks += sw;
+    } else {
+      pcg(h, ka, h->W2, h->R, h->W3);
+    }
     launch_copy((size_t)N * k, h->U, h->X, s);
     launch_scatter_cols(N, k, ka, h->lock_idx, h->R, h->X, s);
   } else if (h->opt.precision == PASE_PREC_MIXED) {
@@ -575,7 +586,7 @@ pase_status correction(pase_handle* h, int k) {
   } else if (h->opt.precision == PASE_PREC_LEARNED) {
     if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
     int sw = 0;
-    const pase_status st = learned_pcg(h, k, h->U, h->X, h->R, &sw);
+    const pase_status st = learned_pcg(h, k, h->U, h->X, h->R, &sw, h->W2);
     if (st) return st;
     h->fallbacks += sw;
   } else {
@@ -902,7 +913,7 @@ pase_status pase_pcg(pase_handle* h, int k, const double* lambda_host, const dou
   if (h->opt.precision == PASE_PREC_LEARNED) {
     if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
     int sw = 0;
-    st = learned_pcg(h, k, U, h->X, h->R, &sw);
+    st = learned_pcg(h, k, U, h->X, h->R, &sw, h->W2);
     if (st) return st;
     h->fallbacks = sw;
   } else {
@@ -1016,7 +1027,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   h->proj_lp_iters = 0;
   h->ka = 0;
   h->fine_cols = 0;
-  const bool locking = h->opt.locking && h->opt.precision != PASE_PREC_LEARNED;
+  const bool locking = h->opt.locking != 0;
   double lp_best = 0.0;   // smallest max-residual seen in the first phase
   int lp_stall = 0;       // corrections since it last decreased
   if (h->opt.precision == PASE_PREC_LEARNED && !h->net)

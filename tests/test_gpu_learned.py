@@ -155,9 +155,9 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def learned_solver(kap, k, weights):
+def learned_solver(kap, k, weights, locking=True):
     from paper_2502_04589_amd import Solver, UNet
-    s = Solver(3, LEVELS, kap, nev_max=k, precision="learned")
+    s = Solver(3, LEVELS, kap, nev_max=k, precision="learned", locking=locking)
     g = UNet(LEVELS[0], batch_max=k)
     g.set_weights(np.asarray(weights, dtype=np.float32))
     s.attach(g)
@@ -229,13 +229,18 @@ def test_learned_solve_with_zero_network_matches_one_step_oracle():
     k = 5
     kap = synth.kappa_field(3, 16, 12)
     H = multigrid.Hierarchy(3, LEVELS, kap)
-    s, g = learned_solver(kap, k, np.zeros(param_count()))
     U0 = synth.initial_vectors(H.A[0].shape[0], k, 4)
-    lam, U, rep = s.solve(k, 1e-9, dev(U0))
     ref = opase.solve(H, k, 1e-9, U0, s=1)
-    np.testing.assert_allclose(lam, ref.lam, rtol=1e-10)
-    assert abs(rep["outer_iters"] - ref.iters) <= 2
-    assert rep["learned_fallbacks"] == k * rep["outer_iters"]
+    # every pair every correction (as the oracle runs it), then with soft locking
+    for locking in (False, True):
+        s, g = learned_solver(kap, k, np.zeros(param_count()), locking)
+        lam, U, rep = s.solve(k, 1e-9, dev(U0))
+        np.testing.assert_allclose(lam, ref.lam, rtol=1e-10)
+        assert abs(rep["outer_iters"] - ref.iters) <= 2
+        # the zero network fails the 0.5 test at every column's first step
+        assert rep["learned_fallbacks"] == rep["fine_solve_columns"]
+        if not locking:
+            assert rep["fine_solve_columns"] == k * rep["outer_iters"]
 
 
 def test_learned_solve_converges_with_a_random_network():
