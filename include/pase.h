@@ -91,6 +91,12 @@ typedef struct pase_options {
                                     w = u; the Rayleigh-Ritz still spans every pair, and a pair whose
                                     residual rises again is unlocked); 0: every pair every correction,
                                     as the algorithm is stated. */
+  int guard;                     /* extra pairs carried in the block (default 0): pase_solve iterates
+                                    nev + guard pairs, stops when the nev smallest meet tol and returns
+                                    those.  The guard columns start from a fixed counter-based
+                                    uniform(-1, 1) sequence.  A block that reaches past a cluster cut
+                                    by nev converges in far fewer corrections.  0 .. 64; the workspace
+                                    holds nev_max + guard columns. */
 } pase_options;
 
 /* Filled by pase_solve.  Array members are optional HOST buffers (NULL = not wanted). */
@@ -135,7 +141,8 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
  * U0: device N_0 x nev start block (any full-rank block; it is M-orthonormalised).
  * lambda_host: nev eigenvalues, ascending.  U: device N_0 x nev, U^T M U = I.
  * U0 and U may be the same buffer.  Stops when every res_i <= tol (see
- * pase_report) or after opt.max_outer corrections (PASE_E_NOTCONV). */
+ * pase_report) or after opt.max_outer corrections (PASE_E_NOTCONV).  With opt.guard > 0 the
+ * iteration carries nev + guard pairs; only the nev smallest decide convergence and are returned. */
 pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, double* lambda_host,
                        double* U, pase_report* rep);
 

@@ -116,6 +116,26 @@ __global__ void scatter_cols_kernel(long long N, int k, int ka, const int* __res
   B[n * k + idx[q - n * ka]] = C[q];
 }
 
+// dst (N x kout) columns 0..nc) = src (N x kin) columns 0..nc); with fill, the columns nc..kout) of
+// dst get a counter-based uniform(-1, 1) value of (node, column): the 64-bit finaliser of
+// SplitMix64 (Steele, Lea and Flood 2014) applied to node * kout + column, top 53 bits.
+__global__ void copy_cols_kernel(long long N, int kin, int kout, int nc, const double* __restrict__ src,
+                                 double* __restrict__ dst, int fill) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * kout) return;
+  const long long n = q / kout;
+  const int j = (int)(q - n * kout);
+  if (j < nc) {
+    dst[q] = src[n * kin + j];
+  } else if (fill) {
+    unsigned long long z = (unsigned long long)q + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    dst[q] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+}
+
 __global__ void select_cols_kernel(long long N, int k, const int* __restrict__ mask, const double* __restrict__ A,
                                    double* __restrict__ Z) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -859,6 +879,11 @@ void launch_gather_cols(long long N, int k, int ka, const int* idx, const double
 
 void launch_scatter_cols(long long N, int k, int ka, const int* idx, const double* C, double* B, hipStream_t s) {
   scatter_cols_kernel<<<nblk(N * ka), kBlock, 0, s>>>(N, k, ka, idx, C, B);
+}
+
+void launch_copy_cols(long long N, int kin, int kout, int nc, const double* src, double* dst, int fill,
+                      hipStream_t s) {
+  copy_cols_kernel<<<nblk(N * kout), kBlock, 0, s>>>(N, kin, kout, nc, src, dst, fill);
 }
 
 void launch_select_cols(long long N, int k, const int* mask, const double* A, double* Z, hipStream_t s) {

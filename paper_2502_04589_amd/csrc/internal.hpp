@@ -153,6 +153,10 @@ void launch_select_cols(long long N, int k, const int* mask, const double* A, do
 // C (N x ka) = columns idx[0..ka) of B (N x k), and back
 void launch_gather_cols(long long N, int k, int ka, const int* idx, const double* B, double* C, hipStream_t s);
 void launch_scatter_cols(long long N, int k, int ka, const int* idx, const double* C, double* B, hipStream_t s);
+// dst (N x kout) columns [0, nc) from src (N x kin); fill: columns [nc, kout) get uniform(-1, 1)
+// values from a counter-based generator (kout = dst's leading dimension)
+void launch_copy_cols(long long N, int kin, int kout, int nc, const double* src, double* dst, int fill,
+                      hipStream_t s);
 void launch_fill_int(int n, int v, int* p, hipStream_t s);
 void launch_node_logk(int n, const double* kappa, double* out, hipStream_t s);
 // the network's kernels run on the given stream from now on

@@ -137,6 +137,7 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (!(o->omega > 0.0)) return PASE_E_ARG;
   if (o->small_solver != 0 && o->small_solver != 1) return PASE_E_ARG;
   if (o->locking != 0 && o->locking != 1) return PASE_E_ARG;
+  if (o->guard < 0 || o->guard > 64 || o->nev_max + o->guard > PASE_MAX_NEV) return PASE_E_ARG;
   if (o->precision != PASE_PREC_FP64 && o->precision != PASE_PREC_MIXED && o->precision != PASE_PREC_LEARNED)
     return PASE_E_UNSUPPORTED;
   if (o->precision == PASE_PREC_LEARNED && p->dim != 3) return PASE_E_UNSUPPORTED;   // the network is 3D
@@ -704,6 +705,7 @@ void pase_options_default(pase_options* opt) {
   opt->omega = 2.0 / 3.0;
   opt->small_solver = 0;
   opt->locking = 1;
+  opt->guard = 0;
 }
 
 const char* pase_status_string(pase_status s) {
@@ -731,7 +733,7 @@ pase_status pase_workspace_bytes(const pase_problem* prob, const pase_options* o
   tmp.dim = prob->dim;
   tmp.L = prob->nlevels - 1;
   tmp.NS = prob->dim == 3 ? 27 : 9;
-  tmp.K = opt->nev_max;
+  tmp.K = opt->nev_max + opt->guard;
   for (int l = 0; l < prob->nlevels; ++l) {
     tmp.lev[l].n = prob->n[l];
     tmp.lev[l].m = prob->n[l] - 1;
@@ -757,7 +759,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   h->dim = prob->dim;
   h->L = prob->nlevels - 1;
   h->NS = prob->dim == 3 ? 27 : 9;
-  h->K = opt->nev_max;
+  h->K = opt->nev_max + opt->guard;
   for (int l = 0; l < prob->nlevels; ++l) {
     h->lev[l].n = prob->n[l];
     h->lev[l].m = prob->n[l] - 1;
@@ -1013,10 +1015,11 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
                        pase_report* rep) {
   pase_status st = check_k(h, nev);
   if (st) return st;
+  if (nev > h->opt.nev_max) return fail(h, PASE_E_ARG, "nev must be in [1, nev_max]");
   if (!h->Tm) return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
   if (!U0 || !lambda_host || !U) return fail(h, PASE_E_ARG, "null argument");
   if (!(tol > 0.0)) return fail(h, PASE_E_ARG, "tol must be positive");
-  const int k = nev;
+  const int k = nev + h->opt.guard;   // block size: the wanted pairs and the guard pairs
   const long long N = h->lev[0].N;
   hipStream_t s = h->stream;
   HIPC(hipEventRecord(h->ev0, s));
@@ -1032,7 +1035,8 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   int lp_stall = 0;       // corrections since it last decreased
   if (h->opt.precision == PASE_PREC_LEARNED && !h->net)
     return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
-  launch_copy((size_t)N * k, U0, h->U, s);
+  if (k > nev) launch_copy_cols(N, nev, k, nev, U0, h->U, 1, s);   // guard columns: fixed uniform(-1, 1)
+  else launch_copy((size_t)N * k, U0, h->U, s);
   // start: two passes of Cholesky-QR in M, Lambda0 = diag(U^T A U)
   for (int pass = 0; pass < 2; ++pass) cholqr_m(h, k, h->U, h->X, 3 + pass);
   apply_AM(h, 0, k, h->U, h->W2, nullptr);
@@ -1061,17 +1065,17 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
       res[j] = rn / (std::fabs(hl[j]) * std::sqrt(hs[k + j]));
       lit[j] = rn / (std::fabs(hl[j]) * std::sqrt(hs[2 * k + j]));
       if (!std::isfinite(res[j]) || !std::isfinite(hl[j])) finite = false;
-      if (res[j] <= tol) ++nconv;
+      if (j < nev && res[j] <= tol) ++nconv;   // only the wanted pairs decide convergence
     }
     if (rep && rep->ritz_history_host && rows <= h->opt.max_outer) {
-      std::memcpy(rep->ritz_history_host + (size_t)rows * k, hl.data(), sizeof(double) * k);
+      std::memcpy(rep->ritz_history_host + (size_t)rows * nev, hl.data(), sizeof(double) * nev);
       ++rows;
     }
     if (!finite) {
       result = fail(h, PASE_E_BREAKDOWN, "non-finite residual or Ritz value");
       break;
     }
-    if (nconv == k) { conv = true; break; }
+    if (nconv == nev) { conv = true; break; }
     if (it >= h->opt.max_outer) break;
     if (locking) {
       // the next correction's fine solves: pairs with res > tol / 10 (ascending column order)
@@ -1105,9 +1109,10 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     ++it;
   }
   h->ka = 0;   // the standalone correction entry points always run every column
-  launch_copy((size_t)N * k, h->U, U, s);
+  if (k > nev) launch_copy_cols(N, k, nev, nev, h->U, U, 0, s);   // the wanted pairs
+  else launch_copy((size_t)N * k, h->U, U, s);
   HIPC(hipEventRecord(h->ev1, s));
-  HIPC(hipMemcpyAsync(lambda_host, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(lambda_host, h->lam, sizeof(double) * nev, hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
   float ms = 0.f;
   HIPC(hipEventElapsedTime(&ms, h->ev0, h->ev1));
@@ -1120,8 +1125,8 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     rep->learned_fallbacks = h->fallbacks;
     rep->lowprec_projection_iters = h->proj_lp_iters;
     rep->fine_solve_columns = h->fine_cols;
-    if (rep->res_host) std::memcpy(rep->res_host, res.data(), sizeof(double) * k);
-    if (rep->res_literal_host) std::memcpy(rep->res_literal_host, lit.data(), sizeof(double) * k);
+    if (rep->res_host) std::memcpy(rep->res_host, res.data(), sizeof(double) * nev);
+    if (rep->res_literal_host) std::memcpy(rep->res_literal_host, lit.data(), sizeof(double) * nev);
   }
   if (result != PASE_OK) return result;
   if (!conv) return fail(h, PASE_E_NOTCONV, "max_outer reached before every pair met tol");
@@ -1132,7 +1137,7 @@ pase_status pase_attach_unet(pase_handle* h, pase_unet* u) {
   if (!h || !u) return fail(h, PASE_E_ARG, "null argument");
   if (h->opt.precision != PASE_PREC_LEARNED) return fail(h, PASE_E_ARG, "the handle is not set up for the learned form");
   if (unet_fine_n(u) != h->lev[0].n) return fail(h, PASE_E_ARG, "the network was created for another fine mesh");
-  if (unet_batch_max(u) < h->K) return fail(h, PASE_E_ARG, "the network's batch_max is below nev_max");
+  if (unet_batch_max(u) < h->K) return fail(h, PASE_E_ARG, "the network's batch_max is below nev_max + guard");
   unet_set_stream(u, h->stream);
   h->net = u;
   return PASE_OK;

@@ -36,10 +36,12 @@ class Solver:
     locking: True (default): a correction's fine solves skip the pairs whose residual is already
              below tol / 10 (they keep w = u; the Rayleigh-Ritz still uses every pair); False:
              every pair every correction, as the algorithm is stated.
+    guard:   extra pairs carried in the block (default 0); solve(nev) iterates nev + guard pairs
+             and returns the nev smallest once they meet tol.
     """
 
     def __init__(self, dim, levels, kappa=None, nev_max=16, precision="fp64", cg_steps=2, max_outer=500,
-                 nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0", locking=True):
+                 nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0", locking=True, guard=0):
         self.lib = nat.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
@@ -71,6 +73,7 @@ class Solver:
         opt.omega = float(omega)
         opt.small_solver = {"auto": 0, "dense": 1}[small_solver]
         opt.locking = 1 if locking else 0
+        opt.guard = int(guard)
         self.opt = opt
         nbytes = C.c_size_t(0)
         self._check(self.lib.pase_workspace_bytes(C.byref(prob), C.byref(opt), C.byref(nbytes)), None)
