@@ -99,6 +99,8 @@ struct pase_handle {
   int* lock_idx = nullptr;
   int ka = 0;
   std::vector<int> lock_host;
+  // structured small solver: residual acceptance relative to max|theta| (set per correction)
+  double small_acc = 1e-11;
   int fine_cols = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
@@ -647,8 +649,8 @@ pase_status correction(pase_handle* h, int k) {
     launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, h->Vtf, h->rqf, s);
     launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
     launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
-    launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, 1e-11 * sc, 1e-9 * sc, h->lam, h->permf,
-                        h->statf, s);
+    launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc, 1e-9 * sc, h->lam,
+                        h->permf, h->statf, s);
     int st[4];
     HIPC(hipMemcpyAsync(st, h->statf, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -999,6 +1001,7 @@ pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* 
   launch_copy((size_t)N * k, U, h->U, s);
   eig_residual(h, k, h->U, h->R);
   h->ka = 0;
+  h->small_acc = 1e-11;
   st = correction(h, k);
   if (st) return st;
   launch_copy((size_t)N * k, h->U, U, s);
@@ -1086,6 +1089,13 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
       if (h->ka > 0 && h->ka < k)
         HIPC(hipMemcpyAsync(h->lock_idx, h->lock_host.data(), sizeof(int) * h->ka, hipMemcpyHostToDevice, s));
     }
+    {
+      // the augmented problem needs no more accuracy than the best outer pair has: accept the
+      // structured solution at residual max(1e-11, 1e-2 min_j res_j) max|theta|
+      double mn = 1e300;
+      for (int j = 0; j < k; ++j) mn = std::min(mn, res[j]);
+      h->small_acc = std::max(1e-11, 1e-2 * mn);
+    }
     if (h->proj_lp) {
       double mr = 0.0, mn = 1e300;
       for (int j = 0; j < k; ++j) {
@@ -1109,6 +1119,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     ++it;
   }
   h->ka = 0;   // the standalone correction entry points always run every column
+  h->small_acc = 1e-11;   // and use the fixed acceptance tolerance
   if (k > nev) launch_copy_cols(N, k, nev, nev, h->U, U, 0, s);   // the wanted pairs
   else launch_copy((size_t)N * k, h->U, U, s);
   HIPC(hipEventRecord(h->ev1, s));
@@ -1196,6 +1207,7 @@ pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double*
         launch_copy((size_t)N * k, h->U, h->W2, s);
         eig_residual(h, k, h->U, h->R);
         h->ka = 0;
+        h->small_acc = 1e-11;
         correction(h, k);
         launch_copy((size_t)N * k, h->W2, h->U, s);
         break;
