@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned form")
     ap.add_argument("--no-locking", action="store_true",
                     help="run the fine solves for every pair every correction (no soft locking)")
-    ap.add_argument("--guard", type=int, default=13,
+    ap.add_argument("--guard", type=int, default=12,
                     help="extra pairs carried in the block beyond nev (0 = the block is exactly nev)")
     ap.add_argument("--train-steps", type=int, default=200, help="Adam steps of the learned preconditioner")
     ap.add_argument("--harvest-iters", type=int, default=8, help="outer iterations harvested for training")

@@ -197,11 +197,12 @@ void launch_small_rqi(int nH, int k, const double* theta, const double* Gt, cons
 // Rayleigh quotients and residual norms of the columns of an orthonormal Vt
 void launch_small_rr(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
                      double* rq, double* res, hipStream_t s);
-// acceptance: residuals <= tol_abs and the inertia count below max(rq) + gap equals k;
-// writes lam ascending, perm, status[0] (1 accepted) and status[1] (the count)
+// acceptance: residuals <= tol_abs (times tolv[r] for the pair at position r of the ascending
+// order when tolv is given) and the inertia count below max(rq) + gap equals k; writes lam
+// ascending, perm, status[0] (1 accepted) and status[1] (the count)
 void launch_small_accept(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* rq,
-                         const double* res, double tol_abs, double gap, double* lam, int* perm, int* status,
-                         hipStream_t s);
+                         const double* res, double tol_abs, const double* tolv, double gap, double* lam, int* perm,
+                         int* status, hipStream_t s);
 // V (n x k row-major) = columns perm of Vt
 void launch_small_emit(int n, int k, const double* Vt, const int* perm, double* V, hipStream_t s);
 void launch_symmetrize(int n, double* A, hipStream_t s);

@@ -99,8 +99,12 @@ struct pase_handle {
   int* lock_idx = nullptr;
   int ka = 0;
   std::vector<int> lock_host;
-  // structured small solver: residual acceptance relative to max|theta| (set per correction)
+  // structured small solver: residual acceptance relative to max|theta|, per position of the
+  // ascending order (host copy set per correction, device copy small_tolv)
   double small_acc = 1e-11;
+  std::vector<double> tolv_host;
+  double* small_tolv = nullptr;
+  bool tolv_on = false;
   int fine_cols = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
@@ -188,6 +192,7 @@ size_t layout(pase_handle* h, void* base) {
     h->AinvL32 = b.take<float>(NHf * NHf);
   }
   h->lock_idx = b.take<int>(K);
+  h->small_tolv = b.take<double>(K);
   if (h->opt.precision == PASE_PREC_LEARNED) {
     h->logk = b.take<double>((size_t)N0);
     h->rr0 = b.take<double>(K); h->rr1 = b.take<double>(K); h->rzo = b.take<double>(K);
@@ -649,8 +654,8 @@ pase_status correction(pase_handle* h, int k) {
     launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, h->Vtf, h->rqf, s);
     launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
     launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
-    launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc, 1e-9 * sc, h->lam,
-                        h->permf, h->statf, s);
+    launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc,
+                        h->tolv_on ? h->small_tolv : nullptr, 1e-9 * sc, h->lam, h->permf, h->statf, s);
     int st[4];
     HIPC(hipMemcpyAsync(st, h->statf, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -1002,6 +1007,7 @@ pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* 
   eig_residual(h, k, h->U, h->R);
   h->ka = 0;
   h->small_acc = 1e-11;
+  h->tolv_on = false;
   st = correction(h, k);
   if (st) return st;
   launch_copy((size_t)N * k, h->U, U, s);
@@ -1090,11 +1096,13 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
         HIPC(hipMemcpyAsync(h->lock_idx, h->lock_host.data(), sizeof(int) * h->ka, hipMemcpyHostToDevice, s));
     }
     {
-      // the augmented problem needs no more accuracy than the best outer pair has: accept the
-      // structured solution at residual max(1e-11, 1e-2 min_j res_j) max|theta|
-      double mn = 1e300;
-      for (int j = 0; j < k; ++j) mn = std::min(mn, res[j]);
-      h->small_acc = std::max(1e-11, 1e-2 * mn);
+      // the augmented problem needs no more accuracy than the outer pairs have: the pair at
+      // position j of the ascending order is accepted at residual max(1e-11, 1e-2 res_j) max|theta|
+      h->tolv_host.resize(k);
+      for (int j = 0; j < k; ++j) h->tolv_host[j] = std::max(1.0, 1e9 * res[j]);   // x 1e-11
+      h->small_acc = 1e-11;
+      h->tolv_on = true;
+      HIPC(hipMemcpyAsync(h->small_tolv, h->tolv_host.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
     }
     if (h->proj_lp) {
       double mr = 0.0, mn = 1e300;
@@ -1120,6 +1128,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   }
   h->ka = 0;   // the standalone correction entry points always run every column
   h->small_acc = 1e-11;   // and use the fixed acceptance tolerance
+  h->tolv_on = false;
   if (k > nev) launch_copy_cols(N, k, nev, nev, h->U, U, 0, s);   // the wanted pairs
   else launch_copy((size_t)N * k, h->U, U, s);
   HIPC(hipEventRecord(h->ev1, s));
@@ -1208,6 +1217,7 @@ pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double*
         eig_residual(h, k, h->U, h->R);
         h->ka = 0;
         h->small_acc = 1e-11;
+        h->tolv_on = false;
         correction(h, k);
         launch_copy((size_t)N * k, h->W2, h->U, s);
         break;

@@ -403,8 +403,9 @@ __global__ __launch_bounds__(kRT) void srr_kernel(int nH, int k, const double* _
 __global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, const double* __restrict__ theta,
                                                     const double* __restrict__ Gt, const double* __restrict__ Hm,
                                                     const double* __restrict__ rq, const double* __restrict__ res,
-                                                    double tol_abs, double gap, double* __restrict__ lam,
-                                                    int* __restrict__ perm, int* __restrict__ status) {
+                                                    double tol_abs, const double* __restrict__ tolv, double gap,
+                                                    double* __restrict__ lam, int* __restrict__ perm,
+                                                    int* __restrict__ status) {
   __shared__ RLds L;
   __shared__ double srt[kSK];
   __shared__ int ok_s, neg_s, cth_s;
@@ -419,12 +420,14 @@ __global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, const doubl
   if (wave == 0) {
     const double v = (lane < k) ? rq[lane] : DBL_MAX;
     const double e = (lane < k) ? res[lane] : 0.0;
-    const bool good = (lane >= k) || (v == v && e == e && fabs(v) < DBL_MAX && e <= tol_abs);
     int rank = 0;
     for (int j = 0; j < k; ++j) {
       const double vj = __shfl(v, j, 64);
       rank += (vj < v || (vj == v && j < lane)) ? 1 : 0;
     }
+    // tolerance of the pair at this position of the ascending order (per position, or one for all)
+    const double tl = (tolv && lane < k) ? tol_abs * tolv[(rank < k) ? rank : k - 1] : tol_abs;
+    const bool good = (lane >= k) || (v == v && e == e && fabs(v) < DBL_MAX && e <= tl);
     if (lane < k) {
       srt[rank] = v;
       perm[rank] = lane;
@@ -514,9 +517,9 @@ void launch_small_rr(int nH, int k, const double* theta, const double* Gt, const
 }
 
 void launch_small_accept(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* rq,
-                         const double* res, double tol_abs, double gap, double* lam, int* perm, int* status,
-                         hipStream_t s) {
-  saccept_kernel<<<1, kRT, 0, s>>>(nH, k, theta, Gt, Hm, rq, res, tol_abs, gap, lam, perm, status);
+                         const double* res, double tol_abs, const double* tolv, double gap, double* lam, int* perm,
+                         int* status, hipStream_t s) {
+  saccept_kernel<<<1, kRT, 0, s>>>(nH, k, theta, Gt, Hm, rq, res, tol_abs, tolv, gap, lam, perm, status);
 }
 
 void launch_small_emit(int n, int k, const double* Vt, const int* perm, double* V, hipStream_t s) {
