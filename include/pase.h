@@ -87,7 +87,8 @@ typedef struct pase_options {
   int small_solver;              /* augmented eigenproblem: 0 = structured shift-invert path with dense
                                     fallback (default), 1 = dense eigensolver only */
   int locking;                   /* 1 (default): soft locking -- the fine solves of a correction run only
-                                    for the pairs whose residual exceeds tol / 10 (a locked pair keeps
+                                    for the pairs whose residual exceeds tol / 10 (guard pairs: 100 tol;
+                                    see guard below) (a locked pair keeps
                                     w = u; the Rayleigh-Ritz still spans every pair, and a pair whose
                                     residual rises again is unlocked); 0: every pair every correction,
                                     as the algorithm is stated. */

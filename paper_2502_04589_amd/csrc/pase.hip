@@ -1087,10 +1087,11 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     if (nconv == nev) { conv = true; break; }
     if (it >= h->opt.max_outer) break;
     if (locking) {
-      // the next correction's fine solves: pairs with res > tol / 10 (ascending column order)
+      // the next correction's fine solves: wanted pairs with res > tol / 10 and guard pairs with
+      // res > 100 tol (they only have to span the space past the wanted ones), ascending order
       h->lock_host.clear();
       for (int j = 0; j < k; ++j)
-        if (!(res[j] <= 0.1 * tol)) h->lock_host.push_back(j);
+        if (!(res[j] <= ((j < nev) ? 0.1 * tol : 100.0 * tol))) h->lock_host.push_back(j);
       h->ka = (int)h->lock_host.size();
       if (h->ka > 0 && h->ka < k)
         HIPC(hipMemcpyAsync(h->lock_idx, h->lock_host.data(), sizeof(int) * h->ka, hipMemcpyHostToDevice, s));
