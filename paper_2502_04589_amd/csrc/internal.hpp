@@ -193,7 +193,7 @@ int small_fast_max_nh();   // N_H limit
 // row-major; first shift its Rayleigh quotient) or, if X0 is null, a fixed pseudo-random vector with
 // first shift sigma[i]; Vt vector-major (N_H + k) x k
 void launch_small_rqi(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* sigma,
-                      const double* X0, double scale, double* Vt, double* rq, hipStream_t s);
+                      const double* X0, double scale, const double* tolv, double* Vt, double* rq, hipStream_t s);
 // Rayleigh quotients and residual norms of the columns of an orthonormal Vt
 void launch_small_rr(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
                      double* rq, double* res, hipStream_t s);

@@ -651,7 +651,8 @@ pase_status correction(pase_handle* h, int k) {
     launch_gemm(true, false, NH, k, NH, 1.0, h->Psi, NH, h->cmw, k, 0.0, h->X0f, k, s);
     launch_gemm(false, false, k, k, k, 1.0, h->kk3, k, h->kkb, k, 0.0, h->X0f + (size_t)NH * k, k, s);
     const double sc = h->small_scale;
-    launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, h->Vtf, h->rqf, s);
+    launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, h->tolv_on ? h->small_tolv : nullptr,
+                     h->Vtf, h->rqf, s);
     launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
     launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
     launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc,

@@ -265,12 +265,14 @@ __device__ double lu_solve_wave(int k, const RLds& L, double b) {
 
 // One workgroup per wanted pair i: shift-invert solves at sigma[i] with one
 // factorisation, then Rayleigh-quotient shifts, until the step residual
-// ||x_old - (rho - mu) y|| / ||y|| is below 1e-13 of the scale or the budget ends.
+// ||x_old - (rho - mu) y|| / ||y|| is below 1e-13 of the scale (with per-pair acceptance
+// factors tolv, 1e-12 tolv[i] of it: a tenth of what the acceptance test asks) or the budget ends.
 // Output: unit vector Vt[i*n .. i*n+n) (n = N_H + k) and its Rayleigh quotient.
 __global__ __launch_bounds__(kRT) void srqi_kernel(int nH, int k, const double* __restrict__ theta,
                                                  const double* __restrict__ Gt, const double* __restrict__ Hm,
                                                  const double* __restrict__ sigma, const double* __restrict__ X0,
-                                                 double scale, double* __restrict__ Vt, double* __restrict__ rq) {
+                                                 double scale, const double* __restrict__ tolv,
+                                                 double* __restrict__ Vt, double* __restrict__ rq) {
   __shared__ RLds L;
   const int i = blockIdx.x;
   const int n = nH + k;
@@ -302,6 +304,7 @@ __global__ __launch_bounds__(kRT) void srqi_kernel(int nH, int k, const double* 
     mu = bsum(part, L.red);
   }
   double rho = mu;
+  const double stop = (tolv ? fmax(1e-13, 1e-12 * tolv[i]) : 1e-13) * scale;
   double dv = (tid < nH) ? 1.0 / (th - mu) : 0.0;
   form_schur_r(nH, k, g, dv, Hm, mu, L);
   lu_factor_r(k, L);
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(kRT) void srqi_kernel(int nH, int k, const double* 
     rr = bsum(rr, L.red);
     ++since;
     if (!(rr == rr) || !(ny == ny)) break;   // NaN: left to the acceptance test
-    if (it >= 1 && sqrt(rr) <= 1e-13 * scale) break;
+    if (it >= 1 && sqrt(rr) <= stop) break;
   }
   __syncthreads();
   for (int r = tid; r < n; r += kRT) Vt[(size_t)i * n + r] = L.xs[r];
@@ -507,8 +510,8 @@ int small_fast_max_k() { return kSK; }
 int small_fast_max_nh() { return kRMaxH; }
 
 void launch_small_rqi(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* sigma,
-                      const double* X0, double scale, double* Vt, double* rq, hipStream_t s) {
-  srqi_kernel<<<k, kRT, 0, s>>>(nH, k, theta, Gt, Hm, sigma, X0, scale, Vt, rq);
+                      const double* X0, double scale, const double* tolv, double* Vt, double* rq, hipStream_t s) {
+  srqi_kernel<<<k, kRT, 0, s>>>(nH, k, theta, Gt, Hm, sigma, X0, scale, tolv, Vt, rq);
 }
 
 void launch_small_rr(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
