@@ -1091,8 +1091,13 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
       // the next correction's fine solves: wanted pairs with res > tol / 10 and guard pairs with
       // res > 100 tol (they only have to span the space past the wanted ones), ascending order
       h->lock_host.clear();
-      for (int j = 0; j < k; ++j)
+      int extra = -1;   // an even count keeps the stencils on their two-column vector loads
+      for (int j = 0; j < k; ++j) {
         if (!(res[j] <= ((j < nev) ? 0.1 * tol : 100.0 * tol))) h->lock_host.push_back(j);
+        else if (extra < 0) extra = j;
+      }
+      if ((h->lock_host.size() & 1) && extra >= 0)
+        h->lock_host.insert(std::lower_bound(h->lock_host.begin(), h->lock_host.end(), extra), extra);
       h->ka = (int)h->lock_host.size();
       if (h->ka > 0 && h->ka < k)
         HIPC(hipMemcpyAsync(h->lock_idx, h->lock_host.data(), sizeof(int) * h->ka, hipMemcpyHostToDevice, s));
