@@ -107,6 +107,11 @@ struct pase_handle {
   bool tolv_on = false;
   int fine_cols = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // pinned host staging of the per-correction transfers (column sums, Ritz values, status words,
+  // locking indices, acceptance factors): truly asynchronous copies, one synchronisation each
+  void* pin = nullptr;
+  double *pin_sums = nullptr, *pin_lam = nullptr, *pin_tolv = nullptr;
+  int *pin_info = nullptr, *pin_st = nullptr, *pin_idx = nullptr;
   std::string err;
 };
 
@@ -657,9 +662,9 @@ pase_status correction(pase_handle* h, int k) {
     launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
     launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc,
                         h->tolv_on ? h->small_tolv : nullptr, 1e-9 * sc, h->lam, h->permf, h->statf, s);
-    int st[4];
-    HIPC(hipMemcpyAsync(st, h->statf, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(h->pin_st, h->statf, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    const int* st = h->pin_st;
     h->last_path = (st[2] != 0) ? -3 : (st[1] == 0 ? -1 : -2);
     if (st[0] == 1 && st[2] == 0) {
       h->last_path = 1;
@@ -786,6 +791,9 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   hipStream_t s = h->stream;
   auto bail = [&](pase_status r) {
     g_last_error = h->err;
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->pin) (void)hipHostFree(h->pin);
     delete h;
     return r;
   };
@@ -874,6 +882,18 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   }
   HIPS(hipEventCreate(&h->ev0));
   HIPS(hipEventCreate(&h->ev1));
+  {
+    const size_t Kp = (size_t)h->K;
+    HIPS(hipHostMalloc(&h->pin, sizeof(double) * 5 * Kp + sizeof(int) * (Kp + 20), hipHostMallocDefault));
+    double* pd = (double*)h->pin;
+    h->pin_sums = pd;
+    h->pin_lam = pd + 3 * Kp;
+    h->pin_tolv = pd + 4 * Kp;
+    int* pi = (int*)(pd + 5 * Kp);
+    h->pin_info = pi;
+    h->pin_st = pi + 16;
+    h->pin_idx = pi + 20;
+  }
 #undef HIPS
   *out = h;
   return PASE_OK;
@@ -883,6 +903,7 @@ pase_status pase_destroy(pase_handle* h) {
   if (!h) return PASE_OK;
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->pin) (void)hipHostFree(h->pin);
   delete h;
   return PASE_OK;
 }
@@ -1061,11 +1082,13 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   while (true) {
     eig_residual(h, k, h->U, h->R);
     HIPC(hipGetLastError());
-    HIPC(hipMemcpyAsync(hs.data(), h->sums, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(hl.data(), h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-    int inf[16];
-    st = read_info(h, inf, 16);
-    if (st) return st;
+    HIPC(hipMemcpyAsync(h->pin_sums, h->sums, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(h->pin_lam, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(h->pin_info, h->info, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    std::memcpy(hs.data(), h->pin_sums, sizeof(double) * 3 * k);
+    std::memcpy(hl.data(), h->pin_lam, sizeof(double) * k);
+    const int* inf = h->pin_info;
     if (inf[1] || inf[2] || inf[3] || inf[4])
       return fail(h, PASE_E_BREAKDOWN, "Cholesky of a Gram matrix or the small eigensolver failed");
     nconv = 0;
@@ -1100,7 +1123,10 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
         h->lock_host.insert(std::lower_bound(h->lock_host.begin(), h->lock_host.end(), extra), extra);
       h->ka = (int)h->lock_host.size();
       if (h->ka > 0 && h->ka < k)
-        HIPC(hipMemcpyAsync(h->lock_idx, h->lock_host.data(), sizeof(int) * h->ka, hipMemcpyHostToDevice, s));
+      {
+        std::memcpy(h->pin_idx, h->lock_host.data(), sizeof(int) * h->ka);
+        HIPC(hipMemcpyAsync(h->lock_idx, h->pin_idx, sizeof(int) * h->ka, hipMemcpyHostToDevice, s));
+      }
     }
     {
       // the augmented problem needs no more accuracy than the outer pairs have: the pair at
@@ -1109,7 +1135,8 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
       for (int j = 0; j < k; ++j) h->tolv_host[j] = std::max(1.0, 1e9 * res[j]);   // x 1e-11
       h->small_acc = 1e-11;
       h->tolv_on = true;
-      HIPC(hipMemcpyAsync(h->small_tolv, h->tolv_host.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+      std::memcpy(h->pin_tolv, h->tolv_host.data(), sizeof(double) * k);
+      HIPC(hipMemcpyAsync(h->small_tolv, h->pin_tolv, sizeof(double) * k, hipMemcpyHostToDevice, s));
     }
     if (h->proj_lp) {
       double mr = 0.0, mn = 1e300;
