@@ -91,6 +91,7 @@ struct pase_handle {
   int fallbacks = 0;            // column switches to the V-cycle (this solve)
   int fast_hits = 0;            // corrections solved by the structured path (this solve)
   int last_path = 0;            // 1 accepted, 0 dense only, -1 residual, -2 count, -3 orthonormalisation
+  bool spec = false;            // a structured solution was enqueued and its status is not read yet
   // mixed form: the projection runs on FP32 vectors with split-BF16 Grams until the residual drops
   // below 1e-6 or stops halving over two corrections (then FP64 to the end of the solve)
   bool proj_lp = false;
@@ -567,9 +568,34 @@ void cholqr_m(pase_handle* h, int k, double*& U, double*& spare, int slot) {
   std::swap(U, spare);
 }
 
-// One correction from (lam, U), U^T M U = I, with R = lam M U - A U already in h->R.
-// Returns new U in h->U (pointer members may be swapped).
-pase_status correction(pase_handle* h, int k) {
+// U = P y_H + W y_W from the small problem's vectors in Vs (y_W = Li^T V_W) and y_H given.
+void prolongation_tail(pase_handle* h, int k, const double* yH) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  const int NH = (int)h->lev[h->L].N;
+  launch_gemm(true, false, k, k, k, 1.0, h->kk3, k, h->Vs + (size_t)NH * k, k, 0.0, h->kk4, k, s);
+  prolong_all(h, k, yH, h->U, 0);
+  launch_tsmm(N, k, h->X, h->kk4, h->U, 1, 0, s);
+}
+
+// Dense path of the small problem, then the prolongation: G = LB^{-1} a Li^T, T = [[C0, G], [G^T, H]].
+pase_status correction_dense_tail(pase_handle* h, int k) {
+  hipStream_t s = h->stream;
+  const int NH = (int)h->lev[h->L].N;
+  const int nT = NH + k;
+  launch_gemm(false, false, NH, k, NH, 1.0, h->LBinv, NH, h->ca, k, 0.0, h->cb, k, s);
+  launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->cc, k, s);
+  launch_set_diag_block(nT, NH, k, h->C0, h->cc, h->kk5, h->Tm, s);
+  launch_syev_lowest(nT, k, h->Tm, h->lam, h->Vs, h->syw, h->info + 2, s);
+  launch_gemm(true, false, NH, k, NH, 1.0, h->LBinv, NH, h->Vs, k, 0.0, h->cb, k, s);   // y_H
+  prolongation_tail(h, k, h->cb);
+  return PASE_OK;
+}
+
+// One correction from (lam, U), U^T M U = I, with R = lam M U - A U already in h->R: everything
+// up to the new U in h->U is enqueued; with the structured small solver the result is speculative
+// (h->spec) until correction_resolve has seen its status.
+pase_status correction_enqueue(pase_handle* h, int k) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   const int NH = (int)h->lev[h->L].N;
@@ -644,11 +670,11 @@ pase_status correction(pase_handle* h, int k) {
   launch_gemm(false, true, k, k, k, 1.0, h->kk4, k, h->kk3, k, 0.0, h->kk5, k, s);
   launch_symmetrize(k, h->kk5, s);
   // (c) small problem
-  const int nT = NH + k;
-  bool solved = false;
   h->last_path = 0;
+  h->spec = false;
   if (h->fast) {
     // structured path in the eigenbasis of C0: Gt = Psi^T a Li^T, shifts = the current Ritz values
+    const int nT = NH + k;
     HIPC(hipMemsetAsync(h->statf, 0, 4 * sizeof(int), s));
     launch_gemm(true, false, NH, k, NH, 1.0, h->Psi, NH, h->ca, k, 0.0, h->cb, k, s);
     launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->Gtl, k, s);
@@ -662,33 +688,43 @@ pase_status correction(pase_handle* h, int k) {
     launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
     launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc,
                         h->tolv_on ? h->small_tolv : nullptr, 1e-9 * sc, h->lam, h->permf, h->statf, s);
-    HIPC(hipMemcpyAsync(h->pin_st, h->statf, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    const int* st = h->pin_st;
-    h->last_path = (st[2] != 0) ? -3 : (st[1] == 0 ? -1 : -2);
-    if (st[0] == 1 && st[2] == 0) {
-      h->last_path = 1;
-      launch_small_emit(nT, k, h->Vtf, h->permf, h->Vs, s);
-      // y_H = L_B^{-T} Phi V_Theta
-      launch_gemm(false, false, NH, k, NH, 1.0, h->Psi, NH, h->Vs, k, 0.0, h->ca, k, s);
-      solved = true;
-      ++h->fast_hits;
-    }
+    // speculative: the prolongation of the structured solution is enqueued before its status is
+    // known (y_H into cc, so that a + its restriction in ca stay for the dense path); the caller
+    // reads statf with its next synchronisation and calls correction_dense_tail on a rejection
+    launch_small_emit(nT, k, h->Vtf, h->permf, h->Vs, s);
+    launch_gemm(false, false, NH, k, NH, 1.0, h->Psi, NH, h->Vs, k, 0.0, h->cc, k, s);   // y_H = L_B^{-T} Phi V
+    prolongation_tail(h, k, h->cc);
+    h->spec = true;
+    return PASE_OK;
   }
-  if (!solved) {
-    // dense path: G = LB^{-1} a Li^T, T = [[C0, G], [G^T, H]]
-    launch_gemm(false, false, NH, k, NH, 1.0, h->LBinv, NH, h->ca, k, 0.0, h->cb, k, s);
-    launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->cc, k, s);
-    launch_set_diag_block(nT, NH, k, h->C0, h->cc, h->kk5, h->Tm, s);
-    launch_syev_lowest(nT, k, h->Tm, h->lam, h->Vs, h->syw, h->info + 2, s);
-    launch_gemm(true, false, NH, k, NH, 1.0, h->LBinv, NH, h->Vs, k, 0.0, h->ca, k, s);
+  return correction_dense_tail(h, k);
+}
+
+// Status of a speculative structured solution (statf copied to pin_st and synchronised by the
+// caller): bookkeeping, and the dense path when it was rejected.
+pase_status correction_resolve(pase_handle* h, int k) {
+  if (!h->spec) return PASE_OK;
+  h->spec = false;
+  const int* st = h->pin_st;
+  if (st[0] == 1 && st[2] == 0) {
+    h->last_path = 1;
+    ++h->fast_hits;
+    return PASE_OK;
   }
-  // coordinates of the W block: y_W = Li^T V_W
-  launch_gemm(true, false, k, k, k, 1.0, h->kk3, k, h->Vs + (size_t)NH * k, k, 0.0, h->kk4, k, s);
-  // prolongation: U = P y_H + W y_W
-  prolong_all(h, k, h->ca, h->U, 0);
-  launch_tsmm(N, k, W, h->kk4, h->U, 1, 0, s);
-  return PASE_OK;
+  h->last_path = (st[2] != 0) ? -3 : (st[1] == 0 ? -1 : -2);
+  return correction_dense_tail(h, k);
+}
+
+// One correction with its small problem resolved before returning (standalone entry points).
+pase_status correction(pase_handle* h, int k) {
+  pase_status st = correction_enqueue(h, k);
+  if (st) return st;
+  if (h->spec) {
+    HIPC(hipMemcpyAsync(h->pin_st, h->statf, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    st = correction_resolve(h, k);
+  }
+  return st;
 }
 
 pase_status read_info(pase_handle* h, int* out, int n) {
@@ -1061,6 +1097,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   h->proj_lp_iters = 0;
   h->ka = 0;
   h->fine_cols = 0;
+  h->spec = false;
   const bool locking = h->opt.locking != 0;
   double lp_best = 0.0;   // smallest max-residual seen in the first phase
   int lp_stall = 0;       // corrections since it last decreased
@@ -1085,7 +1122,17 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     HIPC(hipMemcpyAsync(h->pin_sums, h->sums, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(h->pin_lam, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(h->pin_info, h->info, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
+    if (h->spec) HIPC(hipMemcpyAsync(h->pin_st, h->statf, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    if (h->spec) {
+      // the previous correction's structured solution was used speculatively (one synchronisation
+      // per correction): on a rejection the dense path redoes the prolongation and the residual
+      const bool accepted = h->pin_st[0] == 1 && h->pin_st[2] == 0;
+      st = correction_resolve(h, k);
+      if (st) return st;
+      if (rep && rep->small_path_host && it - 1 < h->opt.max_outer) rep->small_path_host[it - 1] = h->last_path;
+      if (!accepted) continue;
+    }
     std::memcpy(hs.data(), h->pin_sums, sizeof(double) * 3 * k);
     std::memcpy(hl.data(), h->pin_lam, sizeof(double) * k);
     const int* inf = h->pin_info;
@@ -1155,9 +1202,9 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
       }
       if (mn < 1e-5 || lp_stall >= 3) h->proj_lp = false;
     }
-    st = correction(h, k);
+    st = correction_enqueue(h, k);
     if (st) return st;
-    if (rep && rep->small_path_host && it < h->opt.max_outer) rep->small_path_host[it] = h->last_path;
+    if (!h->spec && rep && rep->small_path_host && it < h->opt.max_outer) rep->small_path_host[it] = h->last_path;
     ++it;
   }
   h->ka = 0;   // the standalone correction entry points always run every column
