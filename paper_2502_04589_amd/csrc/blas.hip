@@ -636,77 +636,8 @@ void launch_gemm_small(int ta, int tb, int M, int N, int K, double alpha, const 
   }
 }
 
-// ---- tall-skinny Y = X op(C) (+ Y), X and Y N x k (row-major), C k x k, k <= 64.
-// Lane j of every wave keeps column j of op(C) in registers; a block stages 64
-// consecutive rows of X (one contiguous run) in LDS and each wave produces 16 of
-// the rows, reading X from LDS as a broadcast.
-constexpr int kTsRows = 64;
-
-template <int TB>
-__global__ __launch_bounds__(kBlock) void tsmm_kernel(long long N, int k, const double* __restrict__ X,
-                                                      const double* __restrict__ C, double* __restrict__ Y,
-                                                      int accumulate) {
-  __shared__ double xs[kTsRows * 64];   // row r at xs[64 r], columns k..63 zero
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long long r0 = (long long)blockIdx.x * kTsRows;
-  const int nr = (N - r0 < kTsRows) ? (int)(N - r0) : kTsRows;
-  const double* __restrict__ xp = X + r0 * k;
-  // stage the chunk: slot s = (row s / 64, column s % 64), zero outside (nr, k); the loads are
-  // unconditional from clamped addresses so all of a thread's are in flight together
-  constexpr int SE = kTsRows * 64 / kBlock;
-  double sv[SE];
-#pragma unroll
-  for (int u = 0; u < SE; ++u) {
-    const int sl = tid + kBlock * u;
-    const int r = sl >> 6, c = sl & 63;
-    const int rc = (r < nr) ? r : nr - 1, cc = (c < k) ? c : k - 1;
-    sv[u] = xp[rc * k + cc];
-  }
-#pragma unroll
-  for (int u = 0; u < SE; ++u) {
-    const int sl = tid + kBlock * u;
-    const int r = sl >> 6, c = sl & 63;
-    xs[sl] = (r < nr && c < k) ? sv[u] : 0.0;
-  }
-  // coefficient column of this lane: unconditional loads from clamped addresses (all in flight
-  // together), then zero outside k
-  double creg[64];
-  const int lc = (lane < k) ? lane : k - 1;
-#pragma unroll
-  for (int l = 0; l < 64; ++l) {
-    const int l2 = (l < k) ? l : k - 1;
-    creg[l] = TB ? C[(size_t)lc * k + l2] : C[(size_t)l2 * k + lc];
-  }
-#pragma unroll
-  for (int l = 0; l < 64; ++l) creg[l] = (lane < k && l < k) ? creg[l] : 0.0;
-  __syncthreads();
-  constexpr int RW = kTsRows / 4;   // rows per wave: wave, wave + 4, ...
-#pragma unroll 1
-  for (int half = 0; half < 2; ++half) {
-    double yv[RW / 2];
-#pragma unroll
-    for (int q = 0; q < RW / 2; ++q) {
-      const int rr = wave + 4 * (half * (RW / 2) + q);
-      const int rc = (rr < nr) ? rr : nr - 1;
-      const double y = Y[(r0 + rc) * k + lc];
-      yv[q] = (accumulate && lane < k && rr < nr) ? y : 0.0;
-    }
-#pragma unroll 2
-    for (int q = 0; q < RW / 2; ++q) {
-      const int rr = wave + 4 * (half * (RW / 2) + q);
-      const double* xr = xs + rr * 64;
-      double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-      for (int l = 0; l < 64; l += 2) {
-        a0 = fma(xr[l], creg[l], a0);
-        a1 = fma(xr[l + 1], creg[l + 1], a1);
-      }
-      if (lane < k && rr < nr) Y[(r0 + rr) * k + lane] = yv[q] + (a0 + a1);
-    }
-  }
-}
-
-// ---- the same product on MFMA (v_mfma_f64_16x16x4f64), k <= 64.  A block walks chunks of 64
+// ---- tall-skinny Y = X op(C) (+ Y), X and Y N x k (row-major), C k x k, k <= 64, on MFMA
+// (v_mfma_f64_16x16x4f64).  A block walks chunks of 64
 // consecutive rows; a chunk of X (and of Y) is one contiguous run of 64 k doubles, read and written
 // with coalesced accesses.  Wave w owns output columns 16w .. 16w+15 and keeps that strip of op(C)
 // as B fragments in registers; the X chunk is staged in LDS (row stride kTsmLd) and read as A
