@@ -106,8 +106,8 @@ def main():
     ap.add_argument("--harvest-iters", type=int, default=8, help="outer iterations harvested for training")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design note, not an implementation", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (asked for --gpus {args.gpus}); how it would shard "
+              "over several GPUs is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
