@@ -92,6 +92,7 @@ struct pase_handle {
   int fast_hits = 0;            // corrections solved by the structured path (this solve)
   int last_path = 0;            // 1 accepted, 0 dense only, -1 residual, -2 count, -3 orthonormalisation
   bool spec = false;            // a structured solution was enqueued and its status is not read yet
+  bool try_fast = true;         // attempt the structured path in this correction
   // mixed form: the projection runs on FP32 vectors with split-BF16 Grams until the residual drops
   // below 1e-6 or stops halving over two corrections (then FP64 to the end of the solve)
   bool proj_lp = false;
@@ -672,7 +673,7 @@ pase_status correction_enqueue(pase_handle* h, int k) {
   // (c) small problem
   h->last_path = 0;
   h->spec = false;
-  if (h->fast) {
+  if (h->fast && h->try_fast) {
     // structured path in the eigenbasis of C0: Gt = Psi^T a Li^T, shifts = the current Ritz values
     const int nT = NH + k;
     HIPC(hipMemsetAsync(h->statf, 0, 4 * sizeof(int), s));
@@ -1066,6 +1067,7 @@ pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* 
   h->ka = 0;
   h->small_acc = 1e-11;
   h->tolv_on = false;
+  h->try_fast = true;
   st = correction(h, k);
   if (st) return st;
   launch_copy((size_t)N * k, h->U, U, s);
@@ -1157,6 +1159,13 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     }
     if (nconv == nev) { conv = true; break; }
     if (it >= h->opt.max_outer) break;
+    {
+      // from a start block whose every residual is above 1e-2 (a random one) the Ritz values are
+      // too far off for the structured solver's shifts: the first correction goes dense directly
+      double mn = 1e300;
+      for (int j = 0; j < k; ++j) mn = std::min(mn, res[j]);
+      h->try_fast = !(it == 0 && mn > 1e-2);
+    }
     if (locking) {
       // the next correction's fine solves: wanted pairs with res > tol / 10 and guard pairs with
       // res > 100 tol (they only have to span the space past the wanted ones), ascending order
@@ -1208,6 +1217,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     ++it;
   }
   h->ka = 0;   // the standalone correction entry points always run every column
+  h->try_fast = true;
   h->small_acc = 1e-11;   // and use the fixed acceptance tolerance
   h->tolv_on = false;
   if (k > nev) launch_copy_cols(N, k, nev, nev, h->U, U, 0, s);   // the wanted pairs
@@ -1299,6 +1309,7 @@ pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double*
         h->ka = 0;
         h->small_acc = 1e-11;
         h->tolv_on = false;
+        h->try_fast = true;
         correction(h, k);
         launch_copy((size_t)N * k, h->W2, h->U, s);
         break;
