@@ -134,7 +134,8 @@ pase_status pase_workspace_bytes(const pase_problem* prob, const pase_options* o
 /* Builds the hierarchy (Galerkin coarse stencils, coarse factorisations) inside
  * the caller's device workspace (>= pase_workspace_bytes, 256-byte aligned).
  * prob->kappa is copied; it may be freed after the call.  *out receives a
- * host-side handle released by pase_destroy. */
+ * host-side handle released by pase_destroy (it holds a few KB of pinned host memory for the
+ * per-correction transfers; no device memory is allocated outside the workspace). */
 pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* workspace,
                        size_t workspace_bytes, void* stream, pase_handle** out);
 
