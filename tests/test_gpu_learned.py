@@ -256,6 +256,26 @@ def test_learned_solve_converges_with_a_random_network():
     assert rep["n_converged"] == k
 
 
+def test_learned_solve_with_guard_pairs_and_locking():
+    """The learned form with a block of nev + 3 (soft locking on): the network runs on compact
+    blocks of the unconverged columns, and the nev smallest pairs match the dense reference."""
+    from paper_2502_04589_amd import Solver, UNet
+    k, guard = 5, 3
+    kap = synth.kappa_field(3, 16, 14)
+    H = multigrid.Hierarchy(3, LEVELS, kap)
+    net = ounet.UNet(16)
+    s = Solver(3, LEVELS, kap, nev_max=k, precision="learned", guard=guard)
+    g = UNet(LEVELS[0], batch_max=k + guard)
+    g.set_weights(np.concatenate([w.ravel() for w in net.init(3)]).astype(np.float32))
+    s.attach(g)
+    U0 = synth.initial_vectors(H.A[0].shape[0], k, 6)
+    lam, U, rep = s.solve(k, 1e-9, dev(U0))
+    w = sla.eigh(H.A[0].toarray(), H.M[0].toarray(), subset_by_index=[0, k - 1], eigvals_only=True)
+    np.testing.assert_allclose(lam, w, rtol=1e-9)
+    assert rep["n_converged"] == k and U.shape == (H.A[0].shape[0], k)
+    assert rep["fine_solve_columns"] < (k + guard) * rep["outer_iters"]
+
+
 def test_learned_form_needs_a_network():
     from paper_2502_04589_amd import PaseError, Solver
     s = Solver(3, LEVELS, None, nev_max=2, precision="learned")

@@ -384,6 +384,22 @@ def test_guard_pairs_return_the_same_eigenpairs(dim, levels, kseed, k, guard, pr
     assert rep["outer_iters"] <= rep0["outer_iters"] + 2
 
 
+def test_standalone_correction_after_a_solve_sees_no_solve_state():
+    """A solve leaves per-solve state (active set, acceptance factors, speculation) in the handle;
+    a standalone correction afterwards must give bitwise what it gives on a fresh handle."""
+    levels, k = [32, 16, 8, 4], 12
+    H = multigrid.Hierarchy(3, levels)
+    U = opase.cholqr_m(synth.initial_vectors(H.A[0].shape[0], k, 7), H.M[0])
+    lam = np.einsum("ij,ij->j", U, H.A[0] @ U)
+    fresh = Solver(3, levels, nev_max=k, guard=2)
+    lam_a, U_a = fresh.correction(lam, dev(U))
+    used = Solver(3, levels, nev_max=k, guard=2)
+    used.solve(k, 1e-9, dev(synth.initial_vectors(H.A[0].shape[0], k, 8)))
+    lam_b, U_b = used.correction(lam, dev(U))
+    assert np.array_equal(lam_a, lam_b)
+    assert torch.equal(U_a, U_b)
+
+
 @pytest.mark.slow
 def test_guard_pairs_config2_full_size():
     """64^3, nev 50 with 10 guard pairs: the closed-form eigenvalues to 1e-8 in far fewer corrections
