@@ -657,7 +657,9 @@ pase_status correction_enqueue(pase_handle* h, int k) {
     launch_gram_bf16x3(N, k, W32, AW32, MW32, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);
     ++h->proj_lp_iters;
   } else {
-    apply_AM(h, 0, k, W, h->W2, h->W3);
+    // beta = W_perp^T M W_perp = W_perp^T M W: the complement made P^T M W_perp = 0, so the M W
+    // that the complement formed (W3) serves, and only A W_perp is applied here
+    apply_AM(h, 0, k, W, h->W2, nullptr);
     restrict_all(h, k, h->W2, h->ca);
     launch_gram2(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
   }
