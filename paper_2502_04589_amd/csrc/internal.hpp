@@ -8,7 +8,12 @@
 
 #include "../../include/pase.h"
 
+#include <string>
+
 namespace pase {
+
+// message returned by pase_last_error(NULL) on this thread
+void set_last_error(const std::string& msg);
 
 constexpr int kBlock = 256;          // threads per block of the grid kernels
 constexpr int kMaxStencil = 27;      // 3^dim neighbours
@@ -100,8 +105,6 @@ struct Fine3Args {
 void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s);
 int fine3_spatial_blocks(int m, int nzc);
 int fine3_default_nzc(int m);
-void fine3_set_zrun(int zl);
-void fine3_set_tile(int t);
 int fine3_max_spatial_blocks(int m);
 
 // ---- BLAS-like kernels (blas.hip)

@@ -44,6 +44,8 @@ struct Bump {
 
 }  // namespace
 
+void pase::set_last_error(const std::string& msg) { g_last_error = msg; }
+
 struct pase_handle {
   pase_problem prob{};
   pase_options opt{};
@@ -1070,6 +1072,7 @@ pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* 
   h->small_acc = 1e-11;
   h->tolv_on = false;
   h->try_fast = true;
+  h->proj_lp = false;   // a standalone correction projects in FP64, whatever a solve left behind
   st = correction(h, k);
   if (st) return st;
   launch_copy((size_t)N * k, h->U, U, s);
@@ -1220,6 +1223,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   }
   h->ka = 0;   // the standalone correction entry points always run every column
   h->try_fast = true;
+  h->proj_lp = false;     // project in FP64
   h->small_acc = 1e-11;   // and use the fixed acceptance tolerance
   h->tolv_on = false;
   if (k > nev) launch_copy_cols(N, k, nev, nev, h->U, U, 0, s);   // the wanted pairs
@@ -1286,15 +1290,10 @@ pase_status pase_node_logk(pase_handle* h, double* logk) {
   return PASE_OK;
 }
 
-// Tuning knob: z-run length of the fine-level 3D stencil blocks (0 = default).
-void pase_tune_fine3_zrun(int zl) { fine3_set_zrun(zl); }
-void pase_tune_fine3_tile(int t) { fine3_set_tile(t); }
-
 pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double* ms) {
   pase_status st = check_k(h, k);
   if (st) return st;
-  if (!ms || reps < 1 || which < 0 || which > 5) return fail(h, PASE_E_ARG, "bad timing arguments");
-  if (which == 4 && !h->Tm) return fail(h, PASE_E_UNSUPPORTED, "no dense small-problem workspace");
+  if (!ms || reps < 1 || which < 0 || which > 5 || which == 4) return fail(h, PASE_E_ARG, "bad timing arguments");
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   auto once = [&]() {
@@ -1304,18 +1303,6 @@ pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double*
       case 2: launch_gram(N, k, h->U, h->W2, h->partial, gram_tiles(N, k), h->kk1, s); break;
       case 3: vcycle(h, 0, k, h->R, h->Z); break;
       case 5: launch_axpy2(N, k, h->alpha, h->P, h->Q, h->W2, h->W3, s); break;   // on scratch
-      case 4: {
-        // a correction consumes R and overwrites U; run it on copies so repeated calls see the same input
-        launch_copy((size_t)N * k, h->U, h->W2, s);
-        eig_residual(h, k, h->U, h->R);
-        h->ka = 0;
-        h->small_acc = 1e-11;
-        h->tolv_on = false;
-        h->try_fast = true;
-        correction(h, k);
-        launch_copy((size_t)N * k, h->W2, h->U, s);
-        break;
-      }
     }
   };
   once();   // warm

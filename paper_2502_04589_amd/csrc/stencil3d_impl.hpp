@@ -1,0 +1,500 @@
+// Kernel and launch templates of the fine-level 3D Q1 operator (instantiated for
+// float64 in stencil3d.hip and for float32 in stencil3d_f32.hip).
+//
+// Fine-level 3D Q1 operator over node-major multi-vectors, LDS-staged.
+//
+// A block owns an 8 x 8 tile of nodes in (x, y), a chunk of KC columns and a
+// run of z-planes.  It marches up in z keeping three node planes of the
+// multi-vector (with a one-node halo in x and y) in an LDS ring, so each input
+// value is read from HBM once per block (plus the halo), and every output
+// (node, column) takes its 27 neighbours from LDS.  The A-coefficients of a
+// node come from the kappa of its 8 surrounding cells (two element layers,
+// also staged in LDS):
+//   A[i, i+o] = Kpat(o) * (sum of kappa over the cells shared by nodes i and i+o),
+//   M[i, i+o] = (h/6)^3 prod_a (o_a == 0 ? 4 : 1).
+// Thread (node, column) mapping puts columns fastest, so global loads and
+// stores of a node's KC columns are contiguous.
+#pragma once
+
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace pase {
+
+namespace {
+
+
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  const int per = nblocks >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Sum of kappa over the cells shared by a node and its neighbour at offset o:
+// for each axis with o = -1 only the lower cell, o = +1 only the upper cell,
+// o = 0 both.  kc[cz][cy][cx] are the 8 cells around the node.
+template <int OX, int OY, int OZ>
+__device__ __forceinline__ double shared_kappa(const double (&kc)[2][2][2]) {
+  double s = 0.0;
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx)
+        if ((OX == 0 || cx == (OX > 0)) && (OY == 0 || cy == (OY > 0)) && (OZ == 0 || cz == (OZ > 0)))
+          s += kc[cz][cy][cx];
+  return s;
+}
+
+template <int OX, int OY, int OZ>
+__device__ __forceinline__ double kpat(double k0, double k1, double m0, double m1) {
+  const double kx = (OX == 0) ? k0 : k1, ky = (OY == 0) ? k0 : k1, kz = (OZ == 0) ? k0 : k1;
+  const double mx = (OX == 0) ? m0 : m1, my = (OY == 0) ? m0 : m1, mz = (OZ == 0) ? m0 : m1;
+  return kx * my * mz + mx * ky * mz + mx * my * kz;
+}
+
+// vector of a thread's VW consecutive columns: double2 (16 bytes), float2 (8 bytes, k even)
+// or float4 (16 bytes, k a multiple of 4)
+template <typename T, int W> struct Vec;
+template <> struct Vec<double, 2> { typedef double2 type; };
+template <> struct Vec<float, 2> { typedef float2 type; };
+template <> struct Vec<float, 4> { typedef float4 type; };
+
+template <typename T, int W>
+__device__ __forceinline__ double vget(const typename Vec<T, W>::type& v, int i) {
+  if constexpr (W == 2) return i == 0 ? (double)v.x : (double)v.y;
+  else return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+template <typename T, int W>
+__device__ __forceinline__ void vset(typename Vec<T, W>::type& v, int i, double x) {
+  if constexpr (W == 2) { if (i == 0) v.x = (T)x; else v.y = (T)x; }
+  else { if (i == 0) v.x = (float)x; else if (i == 1) v.y = (float)x; else if (i == 2) v.z = (float)x; else v.w = (float)x; }
+}
+
+constexpr int kSlots = 4;             // LDS ring: planes z-1, z, z+1 and the one being filled
+
+template <typename T, int W, int BX, int BY, int NQ>
+struct Fine3SmemV {
+  typedef typename Vec<T, W>::type V;
+  union {
+    V xs[kSlots][BY + 2][BX + 2][NQ];
+    double red[3][BX * BY * NQ * W];
+  };
+};
+
+// NQ threads per node, each with a VW-column vector: a block covers KC = NQ VW columns of its
+// tile (NQ = 5 when it splits k into whole chunks and 4 does not, e.g. k = 50 with VW = 2)
+template <typename T, int VW, int EPI, bool CONSTK, bool VEC, int BX, int BY, int NQ>
+__global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
+  constexpr int TX = BX, TY = BY;
+  constexpr int kThreadsV = BX * BY * NQ;   // (node, column vector) pairs of a tile
+  typedef typename Vec<T, VW>::type V;
+  constexpr int KC = NQ * VW;                // columns per block
+  __shared__ Fine3SmemV<T, VW, BX, BY, NQ> sm;
+  const int m = a.m, n = m + 1, k = a.k;
+  const int ntx = (m + TX - 1) / TX;
+  const int nty = (m + TY - 1) / TY;
+  const int nch = (k + KC - 1) / KC;
+  const int nzc = a.nzc;
+  const int total = ntx * nty * nzc * nch;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  if (lb >= total) return;
+  // column chunk innermost: the chunks of one tile run together on one XCD and share
+  // its L2 lines (a node's columns are contiguous; a 128-byte line spans two chunks)
+  int q = lb;
+  const int c0 = (q % nch) * KC; q /= nch;
+  const int txi = q % ntx; q /= ntx;
+  const int tyi = q % nty; q /= nty;
+  const int zc = q;
+  const int tx0 = txi * TX, ty0 = tyi * TY;
+  const int zlen = (m + nzc - 1) / nzc;
+  const int z0 = zc * zlen;
+  const int z1 = (z0 + zlen < m) ? z0 + zlen : m;
+  const int tid = threadIdx.x;
+  const int qv = tid % NQ;                   // column vector within the chunk
+  const int node = tid / NQ;
+  const int lx = node % TX, ly = node / TX;
+  const int gx = tx0 + lx, gy = ty0 + ly;
+  const int colv = c0 + qv * VW;             // first column of this thread
+  const bool nodeok = (gx < m) && (gy < m);
+  const T* __restrict__ X = (const T*)a.x;
+
+  // halo plane: (TX+2)(TY+2) nodes x NQ vectors; thread owns entries tid and tid + kThreadsV.
+  // Loads are branch-free: entries outside the domain (or the column range) read a zero
+  // vector, so loaded registers stay in flight until they are stashed.
+  constexpr int HV = (TX + 2) * (TY + 2) * NQ;
+  static_assert(HV <= 2 * kThreadsV, "two halo entries per thread");
+  const V* __restrict__ zerov = (const V*)a.zero;
+  // per-thread halo entry geometry (independent of z)
+  int hoff[2];
+  bool hin[2];
+  int hslot[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * kThreadsV;
+    const int cq = e % NQ;
+    const int hn = e / NQ;
+    const int hx = hn % (TX + 2), hy = hn / (TX + 2);
+    const int x = tx0 + hx - 1, y = ty0 + hy - 1;
+    hin[u] = e < HV && x >= 0 && x < m && y >= 0 && y < m && c0 + cq * VW < k;
+    hoff[u] = (y * m + x) * k + c0 + cq * VW;     // offset within a plane
+    hslot[u] = (e < HV) ? e : -1;
+  }
+  const long long plane = (long long)m * m * k;
+  auto ld1 = [&](int z, int u) -> V {
+    const bool ok = hin[u] && z >= 0 && z < m;
+    if constexpr (VEC) {
+      const V* p = ok ? (const V*)(X + z * plane + hoff[u]) : zerov;
+      return *p;
+    } else {
+      V v;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        const int cq = ((tid + u * kThreadsV) % NQ);
+        const bool oki = ok && (c0 + cq * VW + i < k);
+        const T* p = oki ? X + z * plane + hoff[u] + i : (const T*)zerov;
+        vset<T, VW>(v, i, (double)*p);
+      }
+      return v;
+    }
+  };
+  V* xsflat[kSlots];
+#pragma unroll
+  for (int sl = 0; sl < kSlots; ++sl) xsflat[sl] = &sm.xs[sl][0][0][0];
+  auto st1 = [&](int slot, int u, const V& v) {
+    if (hslot[u] >= 0) xsflat[slot][hslot[u]] = v;
+  };
+  const long long cbase = ((long long)gy * m + gx) * k + colv;
+  constexpr bool kSweep = (EPI == EPI_SWEEP || EPI == EPI_SWEEPDOT);
+  constexpr bool kSums1 = (EPI == EPI_AMDOT || EPI == EPI_SWEEPDOT);   // one column sum
+  const bool bneed = (EPI == EPI_RESID || kSweep) && nodeok && colv < k;
+  auto bload = [&](int z) -> V {
+    const bool ok = bneed && z < z1;
+    const T* B = (const T*)a.b;
+    if constexpr (VEC) {
+      const V* p = ok ? (const V*)(B + z * plane + cbase) : zerov;
+      return *p;
+    } else {
+      V v;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        const bool oki = ok && colv + i < k;
+        const T* p = oki ? B + z * plane + cbase + i : (const T*)zerov;
+        vset<T, VW>(v, i, (double)*p);
+      }
+      return v;
+    }
+  };
+  auto stvec = [&](T* base, long long off, const V& v) {
+    if constexpr (VEC) {
+      *(V*)(base + off) = v;
+    } else {
+#pragma unroll
+      for (int i = 0; i < VW; ++i)
+        if (colv + i < k) base[off + i] = (T)vget<T, VW>(v, i);
+    }
+  };
+  auto kap = [&](int ex, int ey, int ez) -> double {
+    return (ex < n && ey < n && ez >= 0 && ez < n) ? a.kappa[((long long)ez * n + ey) * n + ex] : 0.0;
+  };
+  const double h = a.h;
+  const double k0 = 1.0 / h, k1 = -1.0 / h, m0 = 2.0 * h / 6.0, m1 = h / 6.0;
+  const double mc = h / 6.0, mc3 = mc * mc * mc;
+  const bool needA = (EPI != EPI_AM) || a.out1;
+  const bool needM = (EPI == EPI_EIGRES) || (EPI == EPI_AM && a.out2);
+
+  double kc[2][2][2];
+  // prologue: planes z0-1, z0, z0+1 into slots 0, 1, 2; b(z0) then plane z0+2 in flight
+  {
+    V t0 = ld1(z0 - 1, 0), t1 = ld1(z0 - 1, 1);
+    st1(0, 0, t0); st1(0, 1, t1);
+    t0 = ld1(z0, 0); t1 = ld1(z0, 1);
+    st1(1, 0, t0); st1(1, 1, t1);
+    t0 = ld1(z0 + 1, 0); t1 = ld1(z0 + 1, 1);
+    st1(2, 0, t0); st1(2, 1, t1);
+  }
+  V bA = bload(z0), bB = bA;
+  V pA0 = ld1(z0 + 2, 0), pA1 = ld1(z0 + 2, 1);
+  V pB0 = pA0, pB1 = pA1;
+  if (!CONSTK) {
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) kc[1][cy][cx] = kap(gx + cx, gy + cy, z0);
+  }
+  __syncthreads();
+  double acc0[VW], acc1[VW], acc2[VW];
+#pragma unroll
+  for (int i = 0; i < VW; ++i) acc0[i] = acc1[i] = acc2[i] = 0.0;
+  double lamc[VW];
+#pragma unroll
+  for (int i = 0; i < VW; ++i) lamc[i] = (EPI == EPI_EIGRES && colv + i < k) ? a.lam[colv + i] : 0.0;
+
+  // Output plane z: planes z-1, z, z+1 sit in slots sb, sb+1, sb+2 (mod 4) with sb = (z - z0) & 3;
+  // PS0/PS1 hold plane z+2 (in flight since the previous step) and are stashed into slot sb+3;
+  // PL0/PL1 receive plane z+3; BV is b(z) and BN receives b(z+1).
+#define PASE_STEP(z, PL0, PL1, PS0, PS1, BV, BN)                                                       \
+  {                                                                                                     \
+    const int sb = ((z) - z0) & 3;                                                                      \
+    if (EPI == EPI_RESID || kSweep) BN = bload((z) + 1);                                                \
+    PL0 = ld1((z) + 3, 0);                                                                              \
+    PL1 = ld1((z) + 3, 1);                                                                              \
+    if (!CONSTK) {                                                                                      \
+      _Pragma("unroll") for (int cy = 0; cy < 2; ++cy) _Pragma("unroll") for (int cx = 0; cx < 2; ++cx) { \
+        kc[0][cy][cx] = kc[1][cy][cx];                                                                  \
+        kc[1][cy][cx] = kap(gx + cx, gy + cy, (z) + 1);                                                 \
+      }                                                                                                 \
+    }                                                                                                   \
+    if (nodeok && colv < k) compute_plane((z), sb, BV);                                                 \
+    st1((sb + 3) & 3, 0, PS0);                                                                          \
+    st1((sb + 3) & 3, 1, PS1);                                                                          \
+    __syncthreads();                                                                                    \
+  }
+  // Constant coefficient (residual, sweep and eigen-residual epilogues): reuse along z.  A plane
+  // is read once (9 taps) when it becomes the
+  // newest, and each tap goes into the running sums of the three outputs it touches (its
+  // coefficient depends only on whether the z offset is zero): ra/rm[0] = output z (completed by
+  // plane z+1), [1] = output z+1, [2] = output z+2.  cen[0] is x at output z, cen[1] at z+1.
+  double ra[3][VW], rm[3][VW], cen[2][VW];
+#pragma unroll
+  for (int i = 0; i < VW; ++i) {
+    ra[0][i] = ra[1][i] = ra[2][i] = 0.0;
+    rm[0][i] = rm[1][i] = rm[2][i] = 0.0;
+    cen[0][i] = cen[1][i] = 0.0;
+  }
+  // MODE 0: plane z0-1 (only output z0, offset -1); 1: plane z0 (outputs z0 and z0+1, centre of
+  // z0); 2: plane z+1 in step z (outputs z, z+1, z+2, centre of z+1)
+  auto plane9 = [&](int slot, int mode) {
+#define PASE_TAP9(OX, OY)                                                                            \
+  {                                                                                                  \
+    const V v = sm.xs[slot][ly + 1 + (OY)][lx + 1 + (OX)][qv];                                       \
+    constexpr double sxy = (double)(((OX) == 0 ? 2 : 1) * ((OY) == 0 ? 2 : 1));                      \
+    const double cz = needA ? kpat<OX, OY, 0>(k0, k1, m0, m1) * (2.0 * sxy) : 0.0;                   \
+    const double cn = needA ? kpat<OX, OY, 1>(k0, k1, m0, m1) * sxy : 0.0;                           \
+    constexpr double mxy = (double)(((OX) == 0 ? 4 : 1) * ((OY) == 0 ? 4 : 1));                      \
+    const double mz = mxy * 4.0 * mc3, mn = mxy * mc3;                                               \
+    _Pragma("unroll") for (int i = 0; i < VW; ++i) {                                                 \
+      const double xv = vget<T, VW>(v, i);                                                           \
+      if (mode == 0) {                                                                               \
+        if (needA) ra[0][i] = fma(cn, xv, ra[0][i]);                                                 \
+        if (needM) rm[0][i] = fma(mn, xv, rm[0][i]);                                                 \
+      } else if (mode == 1) {                                                                        \
+        if ((OX) == 0 && (OY) == 0) cen[0][i] = xv;                                                  \
+        if (needA) { ra[0][i] = fma(cz, xv, ra[0][i]); ra[1][i] = fma(cn, xv, ra[1][i]); }           \
+        if (needM) { rm[0][i] = fma(mz, xv, rm[0][i]); rm[1][i] = fma(mn, xv, rm[1][i]); }           \
+      } else {                                                                                       \
+        if ((OX) == 0 && (OY) == 0) cen[1][i] = xv;                                                  \
+        if (needA) {                                                                                 \
+          ra[0][i] = fma(cn, xv, ra[0][i]);                                                          \
+          ra[1][i] = fma(cz, xv, ra[1][i]);                                                          \
+          ra[2][i] = fma(cn, xv, ra[2][i]);                                                          \
+        }                                                                                            \
+        if (needM) {                                                                                 \
+          rm[0][i] = fma(mn, xv, rm[0][i]);                                                          \
+          rm[1][i] = fma(mz, xv, rm[1][i]);                                                          \
+          rm[2][i] = fma(mn, xv, rm[2][i]);                                                          \
+        }                                                                                            \
+      }                                                                                              \
+    }                                                                                                \
+  }
+    PASE_TAP9(-1, -1) PASE_TAP9(0, -1) PASE_TAP9(1, -1)
+    PASE_TAP9(-1, 0)  PASE_TAP9(0, 0)  PASE_TAP9(1, 0)
+    PASE_TAP9(-1, 1)  PASE_TAP9(0, 1)  PASE_TAP9(1, 1)
+#undef PASE_TAP9
+  };
+  auto compute_plane = [&](int z, int sb, const V& bv) {
+    double ax[VW], mx[VW], center[VW];
+#pragma unroll
+    for (int i = 0; i < VW; ++i) ax[i] = mx[i] = center[i] = 0.0;
+    double dcoef = 1.0;
+    if constexpr (CONSTK && EPI != EPI_AM) {
+      plane9((sb + 2) & 3, 2);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        ax[i] = ra[0][i];
+        mx[i] = rm[0][i];
+        center[i] = cen[0][i];
+        ra[0][i] = ra[1][i];
+        ra[1][i] = ra[2][i];
+        ra[2][i] = 0.0;
+        rm[0][i] = rm[1][i];
+        rm[1][i] = rm[2][i];
+        rm[2][i] = 0.0;
+        cen[0][i] = cen[1][i];
+      }
+      dcoef = kpat<0, 0, 0>(k0, k1, m0, m1) * 8.0;
+    } else {
+#define PASE_TAP(OX, OY, OZ)                                                                       \
+  {                                                                                                \
+    const V v = sm.xs[(sb + 1 + (OZ)) & 3][ly + 1 + (OY)][lx + 1 + (OX)][qv];                      \
+    double coef = 0.0, mp = 0.0;                                                                   \
+    if (needA) {                                                                                   \
+      const double s = CONSTK ? (double)(((OX) == 0 ? 2 : 1) * ((OY) == 0 ? 2 : 1) * ((OZ) == 0 ? 2 : 1)) \
+                              : shared_kappa<OX, OY, OZ>(kc);                                      \
+      coef = kpat<OX, OY, OZ>(k0, k1, m0, m1) * s;                                                 \
+      if ((OX) == 0 && (OY) == 0 && (OZ) == 0) dcoef = coef;                                       \
+    }                                                                                              \
+    if (needM) mp = (double)(((OX) == 0 ? 4 : 1) * ((OY) == 0 ? 4 : 1) * ((OZ) == 0 ? 4 : 1)) * mc3; \
+    _Pragma("unroll") for (int i = 0; i < VW; ++i) {                                               \
+      const double xv = vget<T, VW>(v, i);                                                             \
+      if ((OX) == 0 && (OY) == 0 && (OZ) == 0) center[i] = xv;                                     \
+      if (needA) ax[i] = fma(coef, xv, ax[i]);                                                     \
+      if (needM) mx[i] = fma(mp, xv, mx[i]);                                                       \
+    }                                                                                              \
+  }
+    PASE_TAP(-1, -1, -1) PASE_TAP(0, -1, -1) PASE_TAP(1, -1, -1)
+    PASE_TAP(-1, 0, -1)  PASE_TAP(0, 0, -1)  PASE_TAP(1, 0, -1)
+    PASE_TAP(-1, 1, -1)  PASE_TAP(0, 1, -1)  PASE_TAP(1, 1, -1)
+    PASE_TAP(-1, -1, 0)  PASE_TAP(0, -1, 0)  PASE_TAP(1, -1, 0)
+    PASE_TAP(-1, 0, 0)   PASE_TAP(0, 0, 0)   PASE_TAP(1, 0, 0)
+    PASE_TAP(-1, 1, 0)   PASE_TAP(0, 1, 0)   PASE_TAP(1, 1, 0)
+    PASE_TAP(-1, -1, 1)  PASE_TAP(0, -1, 1)  PASE_TAP(1, -1, 1)
+    PASE_TAP(-1, 0, 1)   PASE_TAP(0, 0, 1)   PASE_TAP(1, 0, 1)
+    PASE_TAP(-1, 1, 1)   PASE_TAP(0, 1, 1)   PASE_TAP(1, 1, 1)
+#undef PASE_TAP
+    }
+    const long long off = (long long)z * plane + cbase;
+    V o1, o2;
+    if (EPI == EPI_AM) {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) { vset<T, VW>(o1, i, ax[i]); vset<T, VW>(o2, i, mx[i]); }
+      if (a.out1) stvec((T*)a.out1, off, o1);
+      if (a.out2) stvec((T*)a.out2, off, o2);
+    } else if (EPI == EPI_RESID) {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, vget<T, VW>(bv, i) - ax[i]);
+      stvec((T*)a.out1, off, o1);
+    } else if (EPI == EPI_SWEEP2) {
+      // the staged planes hold b: x1 = c b, A x1 = c (A b), out = x1 + c (b - A x1)
+      const double c = a.omega / dcoef;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, c * center[i] + c * (center[i] - c * ax[i]));
+      stvec((T*)a.out1, off, o1);
+    } else if (kSweep) {
+      const double wd = a.omega / dcoef;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, center[i] + wd * (vget<T, VW>(bv, i) - ax[i]));
+      stvec((T*)a.out1, off, o1);
+      if (EPI == EPI_SWEEPDOT) {
+#pragma unroll
+        for (int i = 0; i < VW; ++i) acc0[i] = fma(vget<T, VW>(bv, i), vget<T, VW>(o1, i), acc0[i]);
+      }
+    } else if (EPI == EPI_AMDOT) {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, ax[i]);
+      stvec((T*)a.out1, off, o1);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) acc0[i] = fma(center[i], vget<T, VW>(o1, i), acc0[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        const double r = lamc[i] * mx[i] - ax[i];
+        vset<T, VW>(o1, i, r);
+        acc0[i] = fma(r, r, acc0[i]);
+        acc1[i] = fma(mx[i], mx[i], acc1[i]);
+        acc2[i] = fma(center[i], mx[i], acc2[i]);
+      }
+      stvec((T*)a.out1, off, o1);
+    }
+  };
+  if (CONSTK && EPI != EPI_AM && nodeok && colv < k) {
+    plane9(0, 0);       // plane z0 - 1
+    plane9(1, 1);       // plane z0
+  }
+  for (int z = z0; z < z1; z += 2) {
+    PASE_STEP(z, pB0, pB1, pA0, pA1, bA, bB)
+    if (z + 1 < z1) PASE_STEP(z + 1, pA0, pA1, pB0, pB1, bB, bA)
+  }
+#undef PASE_STEP
+  if (kSums1) {
+    // one column sum per column: partial[spatial block][column]
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < VW; ++i) sm.red[0][tid * VW + i] = acc0[i];
+    __syncthreads();
+    if (tid < KC && c0 + tid < k) {
+      const int tq = tid / VW, ti = tid % VW;
+      double s0 = 0.0;
+      for (int nd = 0; nd < TX * TY; ++nd) s0 += sm.red[0][(nd * NQ + tq) * VW + ti];
+      const int sbk = (zc * nty + tyi) * ntx + txi;
+      a.partial[(size_t)sbk * k + c0 + tid] = s0;
+    }
+  }
+  if (EPI == EPI_EIGRES) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < VW; ++i) {
+      sm.red[0][tid * VW + i] = acc0[i];
+      sm.red[1][tid * VW + i] = acc1[i];
+      sm.red[2][tid * VW + i] = acc2[i];
+    }
+    __syncthreads();
+    // thread t < KC owns column c0 + t: entries (node, qv = t / VW, i = t % VW)
+    if (tid < KC && c0 + tid < k) {
+      const int tq = tid / VW, ti = tid % VW;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int nd = 0; nd < TX * TY; ++nd) {
+        const int src = (nd * NQ + tq) * VW + ti;
+        s0 += sm.red[0][src];
+        s1 += sm.red[1][src];
+        s2 += sm.red[2][src];
+      }
+      const int sbk = (zc * nty + tyi) * ntx + txi;
+      double* p = a.partial + (size_t)sbk * 3 * k;
+      p[c0 + tid] = s0;
+      p[k + c0 + tid] = s1;
+      p[2 * k + c0 + tid] = s2;
+    }
+  }
+}
+
+template <typename T, int VW, int EPI, bool CONSTK, bool VEC>
+void launchv_tile(const Fine3Args& a, hipStream_t s) {
+  auto go = [&](auto nq) {
+    constexpr int BX = 8, BY = 8, NQ = decltype(nq)::value;
+    constexpr int KC = NQ * VW;
+    const int ntx = (a.m + BX - 1) / BX, nty = (a.m + BY - 1) / BY, nch = (a.k + KC - 1) / KC;
+    const int total = ntx * nty * a.nzc * nch;
+    const int blocks = ((total + 7) / 8) * 8;
+    fine3v_kernel<T, VW, EPI, CONSTK, VEC, BX, BY, NQ><<<blocks, BX * BY * NQ, 0, s>>>(a);
+  };
+  // column chunks of 5 vectors when that wastes fewer padded columns than chunks of 4 (not for
+  // the A+M and eigen-residual epilogues, whose register use makes the larger block slower)
+  const int w4 = ((a.k + 4 * VW - 1) / (4 * VW)) * 4 * VW - a.k;
+  const int w5 = ((a.k + 5 * VW - 1) / (5 * VW)) * 5 * VW - a.k;
+  if constexpr (EPI != EPI_AM && EPI != EPI_EIGRES) {
+    if (w5 < w4) {
+      go(std::integral_constant<int, 5>());
+      return;
+    }
+  }
+  go(std::integral_constant<int, 4>());
+}
+
+template <typename T, int VW, int EPI>
+void launchv_w(const Fine3Args& a, hipStream_t s) {
+  const bool vec = (a.k % VW) == 0;
+  if (a.kappa) {
+    if (vec) launchv_tile<T, VW, EPI, false, true>(a, s);
+    else launchv_tile<T, VW, EPI, false, false>(a, s);
+  } else {
+    if (vec) launchv_tile<T, VW, EPI, true, true>(a, s);
+    else launchv_tile<T, VW, EPI, true, false>(a, s);
+  }
+}
+
+// double: double2 vectors; float: float4 when k is a multiple of 4, else float2
+template <typename T, int EPI>
+void launchv(const Fine3Args& a, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    launchv_w<T, 2, EPI>(a, s);
+  } else {
+    if (a.k % 4 == 0) launchv_w<T, 4, EPI>(a, s);
+    else launchv_w<T, 2, EPI>(a, s);
+  }
+}
+
+}  // namespace
+
+}  // namespace pase
