@@ -185,6 +185,21 @@ pase_status pase_gram(pase_handle* h, long long N, int k, const double* X, const
  * 2^-15 sum_r |x_r y_r|.  Synchronises the handle's stream. */
 pase_status pase_gram_bf16x3(pase_handle* h, long long N, int k, const float* X, const float* Y, double* G);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): G = X^T Y like pase_gram, without a handle or a
+ * workspace.  X, Y: device N x k (row-major, leading dimension k); G: device k x k (row-major);
+ * 1 <= k <= 128.  The per-block partial sums live in a 16 MiB device array of the library (one
+ * copy per GPU, held until the process ends; its address is looked up on the first call on each
+ * device); the call allocates nothing and does not synchronise: the work is enqueued on `stream`
+ * (a hipStream_t as void*, NULL = the null stream).  Calls on one GPU share that array, so calls
+ * that overlap in time on one GPU (different streams, or host threads) race; calls in one stream
+ * are ordered and safe.  Every partial it reads was written by the same call, so nothing has to
+ * be cleared between calls.  For k <= 64 the result is bitwise equal to pase_gram's; for larger k
+ * the partials come from fewer, longer row blocks (equal to rounding).  PASE_E_ARG for null
+ * pointers, N < 1 or k outside [1, 128]; PASE_E_HIP if the launch fails; the message is in
+ * pase_last_error(NULL). */
+pase_status pase_gram_noalloc(long long N, int k, const double* X, const double* Y, double* G, void* stream);
+
 /* The k smallest eigenpairs of a dense symmetric n x n matrix T (row-major, device):
  * w_host (k, ascending) and V (device, n x k row-major, orthonormal columns).
  * n <= pase_small_eig_max_n(h); T is not modified. */

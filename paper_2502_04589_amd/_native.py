@@ -52,6 +52,7 @@ SIGNATURES = [
     ("pase_prolong", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     ("pase_gram", C.c_int, [C.c_void_p, C.c_longlong, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pase_gram_bf16x3", C.c_int, [C.c_void_p, C.c_longlong, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pase_gram_noalloc", C.c_int, [C.c_longlong, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pase_small_eig", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pase_small_eig_max_n", C.c_int, [C.c_void_p]),
     ("pase_correction", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),

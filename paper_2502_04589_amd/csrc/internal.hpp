@@ -189,6 +189,29 @@ void launch_cholinv(int k, double* G, int* info, hipStream_t s);
 // two Cholesky-QR passes over a vector-major n x k block (result back in Vt; Vt2 scratch)
 void launch_vorth2(int n, int k, double* Vt, double* Vt2, double* G, int* info, hipStream_t s);
 
+// Gershgorin bounds and pivmin of the tridiagonal in tri (d, e, tau, scalars) after a reduction
+void launch_tri_finish(int n, double* tri, hipStream_t s);
+// S matrices of the blocked back-transformation from the reflectors stored in the rows of T
+void launch_wy_prep(int n, const double* T, const double* tri, double* Sall, hipStream_t s);
+
+// ---- large dense kernels (dense_large.hip): coarse spaces of thousands of nodes
+// C = alpha op(A) op(B) + beta C (row-major) on FP64 MFMA; the float version stores float and
+// computes in FP64
+void launch_gemm_mfma(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+                      const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s);
+void launch_gemm_mfma_f32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda,
+                          const float* B, int ldb, double beta, float* C, int ldc, hipStream_t s);
+// blocked lower Cholesky in place (*info = 0, or j + 1 for a failed pivot j)
+size_t cholesky_large_scratch_doubles(int n);
+void launch_cholesky_large(int n, double* A, int lda, double* scratch, int* info, hipStream_t s);
+// Li = L^{-1} by block rows (Li must not alias L)
+size_t trinv_large_scratch_doubles(int n);
+void launch_trinv_large(int n, const double* L, int ldl, double* Li, int ldi, double* scratch, hipStream_t s);
+// the k smallest eigenpairs of a dense symmetric n x n matrix, n <= syev_large_max_n() (T overwritten)
+int syev_large_max_n();
+size_t syev_large_work_doubles(int n, int k);
+void launch_syev_large(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s);
+
 // ---- structured augmented eigenproblem (small.hip): Tt = [[diag(theta), Gt], [Gt^T, H]]
 int small_fast_max_k();
 int small_fast_max_nh();   // N_H limit
