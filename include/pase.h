@@ -98,6 +98,14 @@ typedef struct pase_options {
                                     uniform(-1, 1) sequence.  A block that reaches past a cluster cut
                                     by nev converges in far fewer corrections.  0 .. 64; the workspace
                                     holds nev_max + guard columns. */
+  int start;                     /* start block of pase_solve: 0 (default) = U0 as given (U0 = NULL: a
+                                    fixed counter-based uniform(-1, 1) block); 1 = the coarse start of
+                                    Alg. 3 steps 1-2: the nev + guard smallest eigenvectors of the
+                                    coarse pencil (A_H, B_H), interpolated to the fine mesh (U0 is
+                                    ignored and may be NULL; needs small_solver = 0) */
+  double fallback_ratio;         /* learned form: a column switches to the V-cycle when its residual
+                                    norm does not fall below fallback_ratio times its previous value
+                                    (default 0.5) */
 } pase_options;
 
 /* Filled by pase_solve.  Array members are optional HOST buffers (NULL = not wanted). */
@@ -125,7 +133,8 @@ typedef struct pase_unet pase_unet;
 
 /* ---------------------------------------------------------------- core API */
 
-/* Default options: FP64, nev_max 16, s = 2, max_outer 500, nu = 2, omega = 2/3. */
+/* Default options: FP64, nev_max 16, s = 2, max_outer 500, nu = 2, omega = 2/3, soft locking,
+ * no guard pairs, start block U0, fallback ratio 0.5. */
 void pase_options_default(pase_options* opt);
 
 /* Device workspace needed by pase_setup for this problem and options. */
@@ -140,7 +149,8 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
                        size_t workspace_bytes, void* stream, pase_handle** out);
 
 /* Alg. 3 ensure: the nev smallest eigenpairs of (A_h, M).
- * U0: device N_0 x nev start block (any full-rank block; it is M-orthonormalised).
+ * U0: device N_0 x nev start block (any full-rank block; it is M-orthonormalised), or NULL for a
+ * fixed counter-based uniform(-1, 1) block; ignored with opt.start = 1 (coarse eigenvectors).
  * lambda_host: nev eigenvalues, ascending.  U: device N_0 x nev, U^T M U = I.
  * U0 and U may be the same buffer.  Stops when every res_i <= tol (see
  * pase_report) or after opt.max_outer corrections (PASE_E_NOTCONV).  With opt.guard > 0 the

@@ -17,6 +17,9 @@ eigensolver", arXiv 2502.04589) with NumPy/SciPy in float64:
                     composite matrices (eq. Definition_Hh), the augmented
                     eigenproblem (Alg. 3 steps 5-6) and the stopping rule
                     (Sec. 5, opening paragraph).
+* ``reference``  -- the fixed point written out: the k smallest eigenpairs of
+                    the assembled pencil by a library eigensolver (Alg. 3
+                    "Ensure").
 * ``unet``       -- the learned form's preconditioner (a small 3D U-Net with
                     hand-written backward pass), its loss and Adam optimiser,
                     and the flexible PCG with fallback to the V-cycle.  The
@@ -26,4 +29,4 @@ eigensolver", arXiv 2502.04589) with NumPy/SciPy in float64:
 Readings of points the paper leaves open are listed in the docstrings where
 they are taken.
 """
-from . import fem, multigrid, pase, unet  # noqa: F401
+from . import fem, multigrid, pase, reference, unet  # noqa: F401

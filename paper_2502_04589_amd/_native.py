@@ -22,7 +22,7 @@ class Problem(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("nev_max", C.c_int), ("cg_steps", C.c_int), ("max_outer", C.c_int),
                 ("nu", C.c_int), ("omega", C.c_double), ("small_solver", C.c_int), ("locking", C.c_int),
-                ("guard", C.c_int)]
+                ("guard", C.c_int), ("start", C.c_int), ("fallback_ratio", C.c_double)]
 
 
 class Report(C.Structure):

@@ -914,8 +914,16 @@ void launch_gram(long long N, int k, const double* X, const double* Y, double* p
   reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial, G);
 }
 
+// products with a dimension above 1024 (large coarse spaces, and the tall-skinny products with
+// k > 64) run on the MFMA GEMM; the smaller ones keep the latency-oriented kernels
+inline bool gemm_large(int M, int K) { return M > 1024 || K > 1024; }
+
 void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
                  int ldb, double beta, double* C, int ldc, hipStream_t s) {
+  if (gemm_large(M, K)) {
+    launch_gemm_mfma(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    return;
+  }
   if (M <= kSmallM && K <= kSmallK) {
     launch_gemm_small<double>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
     return;
@@ -926,6 +934,10 @@ void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const doub
 
 void launch_gemm_f32(bool ta, bool tb, int M, int N, int K, double alpha, const float* A, int lda, const float* B,
                      int ldb, double beta, float* C, int ldc, hipStream_t s) {
+  if (gemm_large(M, K)) {
+    launch_gemm_mfma_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    return;
+  }
   if (M <= kSmallM && K <= kSmallK) {
     launch_gemm_small<float>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
     return;

@@ -1085,6 +1085,12 @@ void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* w
 
 int syev_max_n() { return kSyevMaxN; }
 
+void launch_tri_finish(int n, double* tri, hipStream_t s) { tri_finish_kernel<<<1, 256, 0, s>>>(n, tri); }
+
+void launch_wy_prep(int n, const double* T, const double* tri, double* Sall, hipStream_t s) {
+  if (n > 2) wy_prep_kernel<<<(n - 2 + kWyB - 1) / kWyB, kBlock, 0, s>>>(n, T, tri, Sall);
+}
+
 void launch_vorth2(int n, int k, double* Vt, double* Vt2, double* G, int* info, hipStream_t s) {
   const unsigned gb = (unsigned)((k * k + kBlock / 64 - 1) / (kBlock / 64));   // vgram: one wave per entry
   const unsigned ab = (unsigned)(((long long)n * k + kBlock - 1) / kBlock);

@@ -233,4 +233,19 @@ void launch_small_accept(int nH, int k, const double* theta, const double* Gt, c
 void launch_small_emit(int n, int k, const double* Vt, const int* perm, double* V, hipStream_t s);
 void launch_symmetrize(int n, double* A, hipStream_t s);
 
+// ---- the same structured solver for large coarse spaces (small_big.hip): N_H <= small_big_max_nh(),
+// k <= small_big_max_k(); rows of Gt stream from L2, each pair keeps two work vectors in `scratch`
+// (small_big_scratch_doubles)
+int small_big_max_k();
+int small_big_max_nh();
+size_t small_big_scratch_doubles(int nH, int k);
+void launch_small_rqi_big(int nH, int k, const double* theta, const double* Gt, const double* Hm,
+                          const double* sigma, const double* X0, double scale, const double* tolv, double* Vt,
+                          double* rq, double* scratch, hipStream_t s);
+void launch_small_rr_big(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
+                         double* rq, double* res, double* scratch, hipStream_t s);
+void launch_small_accept_big(int nH, int k, const double* theta, const double* Gt, const double* Hm,
+                             const double* rq, const double* res, double tol_abs, const double* tolv, double gap,
+                             double* lam, int* perm, int* status, hipStream_t s);
+
 }  // namespace pase

@@ -42,6 +42,17 @@ struct Bump {
   }
 };
 
+// Dense symmetric eigensolver for the k smallest pairs: the one-workgroup / cooperative-LDS
+// solver up to n = 512, the grid solver in global memory above.
+constexpr int kDenseSmallN = 512;
+size_t syev_any_work(int n, int k) {
+  return n <= kDenseSmallN ? syev_work_doubles(n, k) : syev_large_work_doubles(n, k);
+}
+void syev_any(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s) {
+  if (n <= kDenseSmallN) launch_syev_lowest(n, k, T, w, V, work, info, s);
+  else launch_syev_large(n, k, T, w, V, work, info, s);
+}
+
 }  // namespace
 
 void pase::set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -81,6 +92,8 @@ struct pase_handle {
   float* AinvL32 = nullptr;
   // structured augmented eigenproblem: C0 = Phi diag(theta) Phi^T, Psi = L_B^{-T} Phi
   bool fast = false;
+  bool fast_big = false;        // large coarse space or k > 64: the structured kernels of small_big.hip
+  double* sbig = nullptr;       // their per-pair work vectors (2 (N_H + K) x K)
   double *theta = nullptr, *Psi = nullptr, *Gtl = nullptr, *Vtf = nullptr, *Vtf2 = nullptr, *Gf = nullptr;
   double *rqf = nullptr, *resf = nullptr;
   double *cmw = nullptr, *kkb = nullptr, *X0f = nullptr;   // P^T M W, beta, start block
@@ -153,6 +166,8 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (o->small_solver != 0 && o->small_solver != 1) return PASE_E_ARG;
   if (o->locking != 0 && o->locking != 1) return PASE_E_ARG;
   if (o->guard < 0 || o->guard > 64 || o->nev_max + o->guard > PASE_MAX_NEV) return PASE_E_ARG;
+  if (o->start != 0 && o->start != 1) return PASE_E_ARG;
+  if (!(o->fallback_ratio > 0.0)) return PASE_E_ARG;
   if (o->precision != PASE_PREC_FP64 && o->precision != PASE_PREC_MIXED && o->precision != PASE_PREC_LEARNED)
     return PASE_E_UNSUPPORTED;
   if (o->precision == PASE_PREC_LEARNED && p->dim != 3) return PASE_E_UNSUPPORTED;   // the network is 3D
@@ -167,8 +182,12 @@ size_t layout(pase_handle* h, void* base) {
   const size_t K = h->K;
   const size_t NS = h->NS;
   const size_t mv = (size_t)N0 * K;
-  // fine multi-vectors; setup reuses this block as scratch
-  const size_t fine_doubles = std::max<size_t>(10 * mv, 3 * (size_t)N0 * NS + 64);
+  const size_t NHs = (size_t)h->lev[h->L].N;
+  // fine multi-vectors; setup reuses this block as scratch (Galerkin probes, then an N_H x N_H
+  // product and the blocked factorisations of the coarse matrices)
+  const size_t coarse_setup = NHs * NHs + std::max(cholesky_large_scratch_doubles((int)NHs),
+                                                   trinv_large_scratch_doubles((int)NHs)) + 64;
+  const size_t fine_doubles = std::max({10 * mv, 3 * (size_t)N0 * NS + 64, coarse_setup});
   double* fine = b.take<double>(fine_doubles);
   h->setup_scratch = fine;
   double* f = fine;
@@ -215,12 +234,15 @@ size_t layout(pase_handle* h, void* base) {
   h->dtmp = b.take<double>(NH * NH);
   h->nT = (int)(NH + K);
   const size_t nT = (size_t)h->nT;
-  if (h->nT <= syev_max_n() && (int)K <= syev_max_k()) {
-    h->fast = (h->opt.small_solver == 0) && (int)K <= small_fast_max_k() && (int)NH <= small_fast_max_nh();
+  if (h->nT <= syev_large_max_n() && (int)K <= syev_max_k()) {
+    const bool fit_small = (int)K <= small_fast_max_k() && (int)NH <= small_fast_max_nh();
+    const bool fit_big = (int)K <= small_big_max_k() && (int)NH <= small_big_max_nh();
+    h->fast = (h->opt.small_solver == 0) && (fit_small || fit_big);
+    h->fast_big = h->fast && !fit_small;
     h->Tm = b.take<double>(nT * nT);
     h->Vs = b.take<double>(nT * K);
-    size_t sw = syev_work_doubles(h->nT, (int)K);
-    if (h->fast) sw = std::max(sw, syev_work_doubles((int)NH, (int)NH));   // setup: all of C0
+    size_t sw = syev_any_work(h->nT, (int)K);
+    if (h->fast) sw = std::max(sw, syev_any_work((int)NH, (int)NH));   // setup: all of C0
     h->syw = b.take<double>(sw);
   }
   if (h->fast) {
@@ -237,6 +259,7 @@ size_t layout(pase_handle* h, void* base) {
     h->X0f = b.take<double>(nT * K);
     h->permf = b.take<int>(K);
     h->statf = b.take<int>(4);
+    if (h->fast_big) h->sbig = b.take<double>(small_big_scratch_doubles((int)NH, (int)K));
   }
   h->ca = b.take<double>(NH * K);
   h->cb = b.take<double>(NH * K);
@@ -524,7 +547,7 @@ pase_status learned_pcg(pase_handle* h, int k, const double* X0, double* X, doub
     else launch_axpy2(N, k, h->alpha, h->P, h->Q, X, R, s);
     if (non > 0) {
       coldot(h, N, k, R, R, h->rr1);
-      launch_fallback(k, 0.5, h->rr1, h->rr0, h->netmask, s);
+      launch_fallback(k, h->opt.fallback_ratio, h->rr1, h->rr0, h->netmask, s);
     }
     if (j + 1 < h->opt.cg_steps) {
       if (non > 0) {
@@ -589,7 +612,7 @@ pase_status correction_dense_tail(pase_handle* h, int k) {
   launch_gemm(false, false, NH, k, NH, 1.0, h->LBinv, NH, h->ca, k, 0.0, h->cb, k, s);
   launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->cc, k, s);
   launch_set_diag_block(nT, NH, k, h->C0, h->cc, h->kk5, h->Tm, s);
-  launch_syev_lowest(nT, k, h->Tm, h->lam, h->Vs, h->syw, h->info + 2, s);
+  syev_any(nT, k, h->Tm, h->lam, h->Vs, h->syw, h->info + 2, s);
   launch_gemm(true, false, NH, k, NH, 1.0, h->LBinv, NH, h->Vs, k, 0.0, h->cb, k, s);   // y_H
   prolongation_tail(h, k, h->cb);
   return PASE_OK;
@@ -687,12 +710,20 @@ pase_status correction_enqueue(pase_handle* h, int k) {
     launch_gemm(true, false, NH, k, NH, 1.0, h->Psi, NH, h->cmw, k, 0.0, h->X0f, k, s);
     launch_gemm(false, false, k, k, k, 1.0, h->kk3, k, h->kkb, k, 0.0, h->X0f + (size_t)NH * k, k, s);
     const double sc = h->small_scale;
-    launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, h->tolv_on ? h->small_tolv : nullptr,
-                     h->Vtf, h->rqf, s);
-    launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
-    launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
-    launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc,
-                        h->tolv_on ? h->small_tolv : nullptr, 1e-9 * sc, h->lam, h->permf, h->statf, s);
+    const double* tv = h->tolv_on ? h->small_tolv : nullptr;
+    if (h->fast_big) {
+      launch_small_rqi_big(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, tv, h->Vtf, h->rqf, h->sbig, s);
+      launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
+      launch_small_rr_big(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, h->sbig, s);
+      launch_small_accept_big(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc, tv, 1e-9 * sc,
+                              h->lam, h->permf, h->statf, s);
+    } else {
+      launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, tv, h->Vtf, h->rqf, s);
+      launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
+      launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
+      launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc, tv, 1e-9 * sc,
+                          h->lam, h->permf, h->statf, s);
+    }
     // speculative: the prolongation of the structured solution is enqueued before its status is
     // known (y_H into cc, so that a + its restriction in ca stay for the dense path); the caller
     // reads statf with its next synchronisation and calls correction_dense_tail on a rejection
@@ -760,6 +791,8 @@ void pase_options_default(pase_options* opt) {
   opt->small_solver = 0;
   opt->locking = 1;
   opt->guard = 0;
+  opt->start = 0;
+  opt->fallback_ratio = 0.5;
 }
 
 const char* pase_status_string(pase_status s) {
@@ -877,15 +910,27 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   const int NH = (int)cl.N;
   double* AL = h->dtmp;
   launch_stencil_to_dense(h->dim, cl.m, cl.coef, cl.h, 0, AL, s);
-  launch_cholesky(NH, AL, NH, h->info + 8, s);                       // AL <- L_A
-  launch_trinv(NH, AL, NH, h->C0, NH, s);                            // C0 <- L_A^{-1} (temp)
+  // blocked factorisations above one workgroup's size; their scratch follows the N_H x N_H
+  // product area at the start of the setup scratch
+  const bool big_coarse = NH > kDenseSmallN;
+  double* lscr = h->setup_scratch + (size_t)NH * NH;
+  auto cholesky = [&](double* A, int* inf) {
+    if (big_coarse) launch_cholesky_large(NH, A, NH, lscr, inf, s);
+    else launch_cholesky(NH, A, NH, inf, s);
+  };
+  auto trinv = [&](const double* L, double* Li) {
+    if (big_coarse) launch_trinv_large(NH, L, NH, Li, NH, lscr, s);
+    else launch_trinv(NH, L, NH, Li, NH, s);
+  };
+  cholesky(AL, h->info + 8);                                         // AL <- L_A
+  trinv(AL, h->C0);                                                  // C0 <- L_A^{-1} (temp)
   launch_gemm(true, false, NH, NH, NH, 1.0, h->C0, NH, h->C0, NH, 0.0, h->AinvL, NH, s);
   launch_symmetrize(NH, h->AinvL, s);
   if (h->AinvL32) launch_d2f((size_t)NH * NH, h->AinvL, h->AinvL32, s);
   double* BL = h->dtmp;
   launch_stencil_to_dense(h->dim, cl.m, nullptr, cl.h, 1, BL, s);
-  launch_cholesky(NH, BL, NH, h->info + 9, s);                       // BL <- L_B
-  launch_trinv(NH, BL, NH, h->LBinv, NH, s);
+  cholesky(BL, h->info + 9);                                         // BL <- L_B
+  trinv(BL, h->LBinv);
   launch_gemm(true, false, NH, NH, NH, 1.0, h->LBinv, NH, h->LBinv, NH, 0.0, h->BHinv, NH, s);
   launch_symmetrize(NH, h->BHinv, s);
   // C0 = LB^{-1} A_H LB^{-T}
@@ -898,7 +943,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
     // C0 = Phi diag(theta) Phi^T (all N_H pairs, dense solver), Psi = L_B^{-T} Phi
     HIPS(hipMemcpyAsync(h->Tm, h->C0, sizeof(double) * NH * NH, hipMemcpyDeviceToDevice, s));
     double* Phi = h->dtmp;
-    launch_syev_lowest(NH, NH, h->Tm, h->theta, Phi, h->syw, h->info + 10, s);
+    syev_any(NH, NH, h->Tm, h->theta, Phi, h->syw, h->info + 10, s);
     launch_gemm(true, false, NH, NH, NH, 1.0, h->LBinv, NH, Phi, NH, 0.0, h->Psi, NH, s);
   }
   HIPS(hipGetLastError());
@@ -1038,7 +1083,7 @@ pase_status pase_gram_bf16x3(pase_handle* h, long long N, int k, const float* X,
   return PASE_OK;
 }
 
-int pase_small_eig_max_n(const pase_handle* h) { return h ? std::min(h->nT, syev_max_n()) : 0; }
+int pase_small_eig_max_n(const pase_handle* h) { return (h && h->Tm) ? std::min(h->nT, syev_large_max_n()) : 0; }
 
 pase_status pase_small_eig(pase_handle* h, int n, int k, const double* T, double* w_host, double* V) {
   pase_status st = check_k(h, k);
@@ -1047,7 +1092,7 @@ pase_status pase_small_eig(pase_handle* h, int n, int k, const double* T, double
   if (!T || !w_host || !V || n < 2 || n > pase_small_eig_max_n(h) || k > n || k > syev_max_k())
     return fail(h, PASE_E_ARG, "bad small_eig arguments");
   HIPC(hipMemcpyAsync(h->Tm, T, sizeof(double) * n * n, hipMemcpyDeviceToDevice, h->stream));
-  launch_syev_lowest(n, k, h->Tm, h->lam, V, h->syw, h->info + 2, h->stream);
+  syev_any(n, k, h->Tm, h->lam, V, h->syw, h->info + 2, h->stream);
   HIPC(hipGetLastError());
   HIPC(hipMemcpyAsync(w_host, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, h->stream));
   int inf[16];
@@ -1091,7 +1136,9 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   if (st) return st;
   if (nev > h->opt.nev_max) return fail(h, PASE_E_ARG, "nev must be in [1, nev_max]");
   if (!h->Tm) return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
-  if (!U0 || !lambda_host || !U) return fail(h, PASE_E_ARG, "null argument");
+  if (!lambda_host || !U) return fail(h, PASE_E_ARG, "null argument");
+  if (h->opt.start == 1 && !(h->fast && h->Psi))
+    return fail(h, PASE_E_UNSUPPORTED, "the coarse start needs the structured small solver's coarse eigenbasis");
   if (!(tol > 0.0)) return fail(h, PASE_E_ARG, "tol must be positive");
   const int k = nev + h->opt.guard;   // block size: the wanted pairs and the guard pairs
   const long long N = h->lev[0].N;
@@ -1110,8 +1157,19 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   int lp_stall = 0;       // corrections since it last decreased
   if (h->opt.precision == PASE_PREC_LEARNED && !h->net)
     return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
-  if (k > nev) launch_copy_cols(N, nev, k, nev, U0, h->U, 1, s);   // guard columns: fixed uniform(-1, 1)
-  else launch_copy((size_t)N * k, U0, h->U, s);
+  if (h->opt.start == 1) {
+    // Alg. 3 steps 1-2: the k smallest eigenvectors of (A_H, B_H) (the first k columns of
+    // Psi = L_B^{-T} Phi, B_H-orthonormal), interpolated to the fine mesh
+    const int NH = (int)h->lev[h->L].N;
+    launch_copy_cols(NH, NH, k, k, h->Psi, h->cb, 0, s);
+    prolong_all(h, k, h->cb, h->U, 0);
+  } else if (!U0) {
+    launch_copy_cols(N, 0, k, 0, nullptr, h->U, 1, s);              // fixed uniform(-1, 1) block
+  } else if (k > nev) {
+    launch_copy_cols(N, nev, k, nev, U0, h->U, 1, s);               // guard columns: fixed uniform(-1, 1)
+  } else {
+    launch_copy((size_t)N * k, U0, h->U, s);
+  }
   // start: two passes of Cholesky-QR in M, Lambda0 = diag(U^T A U)
   for (int pass = 0; pass < 2; ++pass) cholqr_m(h, k, h->U, h->X, 3 + pass);
   apply_AM(h, 0, k, h->U, h->W2, nullptr);

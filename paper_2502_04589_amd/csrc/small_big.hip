@@ -1,0 +1,486 @@
+// Structured solver of the augmented eigenproblem (Alg. 3 step 5) for large coarse
+// spaces: N_H up to kBigMaxH and k up to kBK pairs.
+//
+// Same method as small.hip: in the M-orthonormal basis [P L_B^{-T} Phi, W_perp L^{-T}]
+// the augmented matrix is Tt = [[Theta, Gt], [Gt^T, H]] (Theta diagonal), and for a
+// shift mu, (Tt - mu I)^{-1} is applied exactly through the k x k Schur complement
+//     S(mu) = H - mu I - Gt^T (Theta - mu I)^{-1} Gt;
+// Sylvester's law of inertia counts the eigenvalues below mu as
+// #{theta_j < mu} + (negative eigenvalues of S(mu)).  Here the rows of Gt (N_H x k, a few
+// MB) no longer fit one thread each: they stream from L2 in 4-row steps into the MFMA
+// operands, S(mu) (k x k) and its in-place LU live in LDS, and the two work vectors of
+// each pair live in a global scratch slice.
+#include <cfloat>
+
+#include "internal.hpp"
+
+namespace pase {
+
+namespace {
+
+constexpr int kBK = 128;           // k <= kBK
+constexpr int kBT = 512;           // threads per workgroup
+constexpr int kBW = kBT / 64;
+constexpr int kBigMaxH = 4096;     // N_H limit
+constexpr int kBMaxFactor = 3;
+constexpr int kBMaxSolve = 6;
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+struct BLds {
+  double S[kBK][kBK + 1];          // S(mu), then its LU factors (unit-lower multipliers below the diagonal)
+  double part[4][kBK];
+  double vh[kBK];                  // a k-vector (x_H, y_H, ...)
+  double vb[kBK];
+  double red[kBW];
+  int ipiv[kBK];
+};
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// fixed-order block sum; every thread gets the result
+__device__ double bsum(double v, double* red) {
+  v = wsum(v);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBW; ++w) s += red[w];
+  return s;
+}
+
+__device__ __forceinline__ double hash_pm1(unsigned a, unsigned b) {
+  unsigned h = a * 0x9E3779B1u ^ (b + 0x632BE5ABu) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  return (double)(h & 0xFFFFFF) / (double)0x800000 - 1.0;
+}
+
+// S = H - mu I - sum_r d_r g_r g_r^T, d_r = 1 / (theta_r - mu), g_r = row r of Gt, on
+// v_mfma_f64_16x16x4f64.  A step covers 4 rows: lane (li, lk) loads Gt[r0 + lk][16 c + li]
+// for the 8 column blocks c, which is both the A operand (times d) of tile row c and the B
+// operand of tile column c.  Wave w accumulates the tiles w, w + 8, ... of the T x T grid.
+__device__ void form_schur_big(int nH, int k, const double* __restrict__ Gt, const double* __restrict__ theta,
+                               const double* __restrict__ Hm, double mu, BLds& L) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int T = (k + 15) >> 4, TT = T * T;
+  double4_t acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  for (int r0 = 0; r0 < nH; r0 += 4) {
+    const int row = r0 + lk;
+    const bool rok = row < nH;
+    const int rc = rok ? row : nH - 1;
+    const double dv = rok ? 1.0 / (theta[rc] - mu) : 0.0;
+    double g[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int col = 16 * c + li;
+      g[c] = (c < T && col < k && rok) ? Gt[(size_t)rc * k + col] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int tt = wave + 8 * t;
+      if (tt < TT) {
+        const int ti = tt / T, tj = tt - (tt / T) * T;
+        double av = 0.0, bv = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          if (c == ti) av = g[c];
+          if (c == tj) bv = g[c];
+        }
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(dv * av, bv, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int tt = wave + 8 * t;
+    if (tt < TT) {
+      const int ti = tt / T, tj = tt - (tt / T) * T;
+      const int c = 16 * tj + li;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ti + lk + 4 * q;
+        if (r < k && c < k) L.S[r][c] = Hm[(size_t)r * k + c] - ((r == c) ? mu : 0.0) - acc[t][q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// In-place LU with partial pivoting of L.S (k x k); rows are exchanged whole, so the
+// multipliers below the diagonal follow their rows (LAPACK getrf order).
+__device__ void lu_big(int k, BLds& L) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tx = tid & 31, ty = tid >> 5;   // 32 columns x 16 rows
+  __shared__ int piv_s;
+  for (int j = 0; j < k; ++j) {
+    if (wave == 0) {
+      // largest |S[r][j]| over r >= j, ties to the lowest row: key = magnitude bits with the
+      // low 7 bits replaced by 127 - r
+      unsigned long long key = 0ull;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = lane + 64 * h;
+        if (r >= j && r < k) {
+          const unsigned long long kk =
+              ((unsigned long long)__double_as_longlong(fabs(L.S[r][j])) & ~127ull) | (unsigned long long)(127 - r);
+          key = (kk > key) ? kk : key;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long k2 = (unsigned long long)__shfl_xor((long long)key, o, 64);
+        key = (k2 > key) ? k2 : key;
+      }
+      if (lane == 0) {
+        const int p = 127 - (int)(key & 127ull);
+        piv_s = (p >= j && p < k) ? p : j;
+        L.ipiv[j] = piv_s;
+      }
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != j) {
+      for (int t = tid; t < k; t += kBT) {
+        const double a = L.S[j][t];
+        L.S[j][t] = L.S[p][t];
+        L.S[p][t] = a;
+      }
+    }
+    __syncthreads();
+    const double rp = 1.0 / L.S[j][j];
+    for (int r = j + 1 + ty; r < k; r += 16) {
+      const double lr = L.S[r][j] * rp;
+      for (int c = j + 1 + tx; c < k; c += 32) L.S[r][c] = fma(-lr, L.S[j][c], L.S[r][c]);
+      if (tx == 0) L.S[r][j] = lr;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double lane_get(double b0, double b1, int j) {
+  const double v0 = __shfl(b0, j & 63, 64), v1 = __shfl(b1, j & 63, 64);
+  return (j < 64) ? v0 : v1;
+}
+
+// Wave 0: solves S y = b with the factors of lu_big; entries r = lane and r = lane + 64 in
+// (b0, b1) on entry, y on exit.
+__device__ void lu_solve_big(int k, const BLds& L, double& b0, double& b1) {
+  const int lane = threadIdx.x & 63;
+  for (int j = 0; j < k; ++j) {
+    const int p = L.ipiv[j];
+    if (p != j) {
+      const double bj = lane_get(b0, b1, j), bp = lane_get(b0, b1, p);
+      if (lane == (j & 63)) { if (j < 64) b0 = bp; else b1 = bp; }
+      if (lane == (p & 63)) { if (p < 64) b0 = bj; else b1 = bj; }
+    }
+  }
+  for (int j = 0; j < k; ++j) {
+    const double zj = lane_get(b0, b1, j);
+    if (lane > j && lane < k) b0 = fma(-L.S[lane][j], zj, b0);
+    if (lane + 64 > j && lane + 64 < k) b1 = fma(-L.S[lane + 64][j], zj, b1);
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    const double yj = lane_get(b0, b1, j) / L.S[j][j];
+    if (lane == (j & 63)) { if (j < 64) b0 = yj; else b1 = yj; }
+    if (lane < j) b0 = fma(-L.S[lane][j], yj, b0);
+    if (lane + 64 < j && lane + 64 < k) b1 = fma(-L.S[lane + 64][j], yj, b1);
+  }
+}
+
+// out[a] = sum_{r < nH} c_r x_r Gt[r][a] (c_r = 1 / (theta_r - mu) when dmu is set, else 1), a < k,
+// into LDS; x is a global vector of the workgroup.
+__device__ void colsum_big(int nH, int k, const double* __restrict__ Gt, const double* __restrict__ theta,
+                           bool dmu, double mu, const double* x, BLds& L, double* out) {
+  const int tid = threadIdx.x;
+  const int a = tid & (kBK - 1), grp = tid >> 7;
+  double s = 0.0;
+  if (a < k) {
+    for (int r = grp; r < nH; r += 4) {
+      const double c = dmu ? 1.0 / (theta[r] - mu) : 1.0;
+      s = fma(c * x[r], Gt[(size_t)r * k + a], s);
+    }
+  }
+  L.part[grp][a] = s;
+  __syncthreads();
+  if (tid < k) out[tid] = (L.part[0][tid] + L.part[1][tid]) + (L.part[2][tid] + L.part[3][tid]);
+  __syncthreads();
+}
+
+// g_r . v for row r of Gt and the LDS k-vector v, by one wave (every lane gets it)
+__device__ __forceinline__ double row_dot(int k, const double* __restrict__ Gt, int r, const double* v) {
+  const int lane = threadIdx.x & 63;
+  const double* __restrict__ g = Gt + (size_t)r * k;
+  double s = (lane < k) ? g[lane] * v[lane] : 0.0;
+  if (lane + 64 < k) s = fma(g[lane + 64], v[lane + 64], s);
+  return wsum(s);
+}
+
+// One workgroup per pair i: shift-invert solves at the start vector's Rayleigh quotient (or
+// sigma[i]), then Rayleigh-quotient shifts, as in the one-workgroup solver; the unit vector goes to
+// Vt[i*n ..] (n = N_H + k) and its Rayleigh quotient to rq[i].  xs: 2 n doubles per pair.
+__global__ __launch_bounds__(kBT) void srqi_big_kernel(int nH, int k, const double* __restrict__ theta,
+                                                     const double* __restrict__ Gt, const double* __restrict__ Hm,
+                                                     const double* __restrict__ sigma,
+                                                     const double* __restrict__ X0, double scale,
+                                                     const double* __restrict__ tolv, double* __restrict__ Vt,
+                                                     double* __restrict__ rq, double* __restrict__ xs) {
+  __shared__ BLds L;
+  const int i = blockIdx.x;
+  const int n = nH + k;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double* x = xs + (size_t)i * 2 * n;
+  double* y = x + n;
+  double nx = 0.0;
+  for (int r = tid; r < n; r += kBT) {
+    const double v = X0 ? X0[(size_t)r * k + i] : hash_pm1((unsigned)i + 1u, (unsigned)r);
+    x[r] = v;
+    nx = fma(v, v, nx);
+  }
+  nx = bsum(nx, L.red);
+  const double inx = 1.0 / sqrt(nx);
+  for (int r = tid; r < n; r += kBT) x[r] *= inx;
+  __syncthreads();
+  double mu = sigma[i];
+  if (X0) {
+    // x^T Tt x = sum_r x_r (theta_r x_r + 2 g_r . x_H) + x_H^T H x_H
+    for (int a = tid; a < k; a += kBT) L.vh[a] = x[nH + a];
+    __syncthreads();
+    double part = 0.0;
+    for (int r = wave; r < nH; r += kBW) {
+      const double gd = row_dot(k, Gt, r, L.vh);
+      if (lane == 0) part = fma(x[r], fma(theta[r], x[r], 2.0 * gd), part);
+    }
+    if (tid < k) {
+      double hx = 0.0;
+      for (int b = 0; b < k; ++b) hx = fma(Hm[(size_t)tid * k + b], L.vh[b], hx);
+      part = fma(L.vh[tid], hx, part);
+    }
+    mu = bsum(part, L.red);
+  }
+  double rho = mu;
+  const double stop = (tolv ? fmax(1e-13, 1e-12 * tolv[i]) : 1e-13) * scale;
+  form_schur_big(nH, k, Gt, theta, Hm, mu, L);
+  lu_big(k, L);
+  int nfac = 1, since = 0;
+  const int hold = X0 ? 3 : 2;
+  for (int it = 0; it < kBMaxSolve; ++it) {
+    if (since >= hold && nfac < kBMaxFactor) {
+      mu = rho;
+      form_schur_big(nH, k, Gt, theta, Hm, mu, L);
+      lu_big(k, L);
+      ++nfac;
+      since = 0;
+    }
+    // rhs = x_H - Gt^T (d o x_Theta), then y_H = S^{-1} rhs
+    colsum_big(nH, k, Gt, theta, true, mu, x, L, L.vb);
+    if (wave == 0) {
+      double b0 = (lane < k) ? x[nH + lane] - L.vb[lane] : 0.0;
+      double b1 = (lane + 64 < k) ? x[nH + lane + 64] - L.vb[lane + 64] : 0.0;
+      lu_solve_big(k, L, b0, b1);
+      if (lane < k) L.vh[lane] = b0;
+      if (lane + 64 < k) L.vh[lane + 64] = b1;
+    }
+    __syncthreads();
+    // y_Theta = d o (x_Theta - Gt y_H), y_H as solved
+    for (int r = wave; r < nH; r += kBW) {
+      const double gd = row_dot(k, Gt, r, L.vh);
+      if (lane == 0) y[r] = (x[r] - gd) / (theta[r] - mu);
+    }
+    for (int a = tid; a < k; a += kBT) y[nH + a] = L.vh[a];
+    __syncthreads();
+    double yy = 0.0, yx = 0.0;
+    for (int r = tid; r < n; r += kBT) {
+      yy = fma(y[r], y[r], yy);
+      yx = fma(y[r], x[r], yx);
+    }
+    yy = bsum(yy, L.red);
+    yx = bsum(yx, L.red);
+    const double ny = sqrt(yy);
+    rho = mu + yx / yy;                       // Tt y = x + mu y
+    const double dm = rho - mu;
+    double rr = 0.0;
+    for (int r = tid; r < n; r += kBT) {
+      const double e = (x[r] - dm * y[r]) / ny;
+      rr = fma(e, e, rr);
+      x[r] = y[r] / ny;
+    }
+    rr = bsum(rr, L.red);
+    __syncthreads();
+    ++since;
+    if (!(rr == rr) || !(ny == ny)) break;
+    if (it >= 1 && sqrt(rr) <= stop) break;
+  }
+  __syncthreads();
+  for (int r = tid; r < n; r += kBT) Vt[(size_t)i * n + r] = x[r];
+  if (tid == 0) rq[i] = rho;
+}
+
+// Rayleigh quotient and residual of column i of an orthonormal Vt with the explicit operator:
+// w = Tt v (into the pair's scratch), rho = v.w, res = ||w - rho v||.
+__global__ __launch_bounds__(kBT) void srr_big_kernel(int nH, int k, const double* __restrict__ theta,
+                                                    const double* __restrict__ Gt, const double* __restrict__ Hm,
+                                                    const double* __restrict__ Vt, double* __restrict__ rq,
+                                                    double* __restrict__ res, double* __restrict__ xs) {
+  __shared__ BLds L;
+  const int i = blockIdx.x;
+  const int n = nH + k;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const double* x = Vt + (size_t)i * n;
+  double* w = xs + (size_t)i * 2 * n;
+  for (int a = tid; a < k; a += kBT) L.vh[a] = x[nH + a];
+  __syncthreads();
+  colsum_big(nH, k, Gt, theta, false, 0.0, x, L, L.vb);       // Gt^T x_Theta
+  if (tid < k) {
+    double s = L.vb[tid];
+    for (int b = 0; b < k; ++b) s = fma(Hm[(size_t)tid * k + b], L.vh[b], s);
+    w[nH + tid] = s;
+  }
+  for (int r = wave; r < nH; r += kBW) {
+    const double gd = row_dot(k, Gt, r, L.vh);
+    if (lane == 0) w[r] = fma(theta[r], x[r], gd);
+  }
+  __syncthreads();
+  double xw = 0.0;
+  for (int r = tid; r < n; r += kBT) xw = fma(x[r], w[r], xw);
+  const double rho = bsum(xw, L.red);
+  double rr = 0.0;
+  for (int r = tid; r < n; r += kBT) {
+    const double e = w[r] - rho * x[r];
+    rr = fma(e, e, rr);
+  }
+  rr = bsum(rr, L.red);
+  if (tid == 0) {
+    rq[i] = rho;
+    res[i] = sqrt(rr);
+  }
+}
+
+// Acceptance (one workgroup): ascending order of the Rayleigh quotients, every residual within
+// its tolerance, and the inertia count below mu* = max rq + gap equal to k (LDL^T of S(mu*)
+// without pivoting; a tiny pivot or element growth makes the count untrusted and rejects).
+// status[0] = 1 on success, status[1] = the count; lam ascending, perm = source column.
+__global__ __launch_bounds__(kBT) void saccept_big_kernel(int nH, int k, const double* __restrict__ theta,
+                                                        const double* __restrict__ Gt,
+                                                        const double* __restrict__ Hm,
+                                                        const double* __restrict__ rq,
+                                                        const double* __restrict__ res, double tol_abs,
+                                                        const double* __restrict__ tolv, double gap,
+                                                        double* __restrict__ lam, int* __restrict__ perm,
+                                                        int* __restrict__ status) {
+  __shared__ BLds L;
+  __shared__ double srt[kBK];
+  __shared__ int ok_s, neg_s, cth_s;
+  __shared__ double amax_s;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) {
+    ok_s = 1;
+    neg_s = 0;
+    cth_s = 0;
+  }
+  __syncthreads();
+  if (tid < k) {
+    const double v = rq[tid], e = res[tid];
+    int rank = 0;
+    for (int j = 0; j < k; ++j) {
+      const double vj = rq[j];
+      rank += (vj < v || (vj == v && j < tid)) ? 1 : 0;
+    }
+    const double tl = tolv ? tol_abs * tolv[(rank < k) ? rank : k - 1] : tol_abs;
+    const bool good = (v == v && e == e && fabs(v) < DBL_MAX && e <= tl);
+    srt[rank] = v;
+    perm[rank] = tid;
+    if (!good) ok_s = 0;
+  }
+  __syncthreads();
+  if (!ok_s) {
+    if (tid == 0) status[0] = 0;
+    return;
+  }
+  const double mus = srt[k - 1] + gap;
+  form_schur_big(nH, k, Gt, theta, Hm, mus, L);
+  if (wave == 0) {
+    double m = 0.0;
+    for (int r = 0; r < k; ++r) {
+      if (lane <= r && lane < k) m = fmax(m, fabs(L.S[r][lane]));
+      if (lane + 64 <= r && lane + 64 < k) m = fmax(m, fabs(L.S[r][lane + 64]));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) amax_s = m;
+  }
+  __syncthreads();
+  const double amax = amax_s;
+  const int tx = tid & 31, ty = tid >> 5;
+  for (int j = 0; j < k; ++j) {
+    const double d = L.S[j][j];
+    if (tid == 0) {
+      if (!(fabs(d) > 1e-12 * amax)) ok_s = 0;
+      if (d < 0.0) ++neg_s;
+    }
+    const double rd = 1.0 / d;
+    for (int r = j + 1 + ty; r < k; r += 16) {
+      const double lr = L.S[r][j] * rd;
+      for (int t = j + 1 + tx; t <= r; t += 32) L.S[r][t] = fma(-lr, L.S[t][j], L.S[r][t]);
+    }
+    __syncthreads();
+  }
+  if (wave == 0) {
+    double m = 0.0;
+    for (int r = 0; r < k; ++r) {
+      if (lane <= r && lane < k) m = fmax(m, fabs(L.S[r][lane]));
+      if (lane + 64 <= r && lane + 64 < k) m = fmax(m, fabs(L.S[r][lane + 64]));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0 && !(m <= 1e6 * amax)) ok_s = 0;
+  }
+  int cth = 0;
+  for (int r = tid; r < nH; r += kBT) cth += (theta[r] < mus) ? 1 : 0;
+  cth = (int)bsum((double)cth, L.red);
+  __syncthreads();
+  if (tid == 0) {
+    const int count = cth + neg_s;
+    status[0] = (ok_s && count == k) ? 1 : 0;
+    status[1] = count;
+  }
+  for (int j = tid; j < k; j += kBT) lam[j] = srt[j];
+}
+
+}  // namespace
+
+int small_big_max_k() { return kBK; }
+int small_big_max_nh() { return kBigMaxH; }
+size_t small_big_scratch_doubles(int nH, int k) { return (size_t)2 * (nH + k) * k; }
+
+void launch_small_rqi_big(int nH, int k, const double* theta, const double* Gt, const double* Hm,
+                          const double* sigma, const double* X0, double scale, const double* tolv, double* Vt,
+                          double* rq, double* scratch, hipStream_t s) {
+  srqi_big_kernel<<<k, kBT, 0, s>>>(nH, k, theta, Gt, Hm, sigma, X0, scale, tolv, Vt, rq, scratch);
+}
+
+void launch_small_rr_big(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
+                         double* rq, double* res, double* scratch, hipStream_t s) {
+  srr_big_kernel<<<k, kBT, 0, s>>>(nH, k, theta, Gt, Hm, Vt, rq, res, scratch);
+}
+
+void launch_small_accept_big(int nH, int k, const double* theta, const double* Gt, const double* Hm,
+                             const double* rq, const double* res, double tol_abs, const double* tolv, double gap,
+                             double* lam, int* perm, int* status, hipStream_t s) {
+  saccept_big_kernel<<<1, kBT, 0, s>>>(nH, k, theta, Gt, Hm, rq, res, tol_abs, tolv, gap, lam, perm, status);
+}
+
+}  // namespace pase

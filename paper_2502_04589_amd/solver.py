@@ -38,10 +38,15 @@ class Solver:
              every pair every correction, as the algorithm is stated.
     guard:   extra pairs carried in the block (default 0); solve(nev) iterates nev + guard pairs
              and returns the nev smallest once they meet tol.
+    start:   "given" (default): solve() starts from its U0 (None: a fixed counter-based
+             uniform(-1, 1) block); "coarse": from the smallest eigenvectors of the coarse pencil,
+             interpolated to the fine mesh (Alg. 3 steps 1-2).
+    fallback_ratio: learned form's switch to the V-cycle (default 0.5).
     """
 
     def __init__(self, dim, levels, kappa=None, nev_max=16, precision="fp64", cg_steps=2, max_outer=500,
-                 nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0", locking=True, guard=0):
+                 nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0", locking=True, guard=0,
+                 start="given", fallback_ratio=0.5):
         self.lib = nat.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
@@ -74,6 +79,8 @@ class Solver:
         opt.small_solver = {"auto": 0, "dense": 1}[small_solver]
         opt.locking = 1 if locking else 0
         opt.guard = int(guard)
+        opt.start = {"given": 0, "coarse": 1}[start]
+        opt.fallback_ratio = float(fallback_ratio)
         self.opt = opt
         nbytes = C.c_size_t(0)
         self._check(self.lib.pase_workspace_bytes(C.byref(prob), C.byref(opt), C.byref(nbytes)), None)
@@ -125,7 +132,8 @@ class Solver:
     def solve(self, nev, tol, U0, history=False, raise_notconv=True):
         """nev smallest eigenpairs.  Returns (lam [np], U [torch N x nev], report dict)."""
         N = self.N[0]
-        U0 = self._mv(U0, N, nev, "U0")
+        if U0 is not None:
+            U0 = self._mv(U0, N, nev, "U0")
         U = self._new(N, nev)
         lam = np.zeros(nev)
         res = np.zeros(nev)

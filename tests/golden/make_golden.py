@@ -1,0 +1,46 @@
+"""Writes the stored expected values under tests/golden/ by calling only ``oracle``.
+
+    python tests/golden/make_golden.py [name ...]
+
+Each entry is the k smallest eigenvalues of the Q1 pencil of -div(kappa grad u) = lambda u
+(Alg. 3 "Ensure"), computed by ``oracle.reference.lowest_eigenpairs`` from the seeded kappa field
+of ``synth.kappa_field``; the file records the recipe beside the values.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle import reference  # noqa: E402
+
+# name: (dim, n, k, kappa seed or None)
+CASES = {
+    # the large coarse space path: 64^3 fine mesh, V_H = 16^3 (N_H = 3375), 120 pairs of a kappa field
+    "kappa3d_64_s21_k120": (3, 64, 120, 21),
+    # the same mesh with kappa = 1 (closed form available too)
+    "kappa3d_32_s5_k40": (3, 32, 40, 5),
+}
+
+
+def write(name):
+    dim, n, k, seed = CASES[name]
+    kappa = None if seed is None else synth.kappa_field(dim, n, seed)
+    t = time.time()
+    w = reference.lowest_eigenpairs(dim, n, k, kappa)
+    path = os.path.join(HERE, name + ".npz")
+    np.savez(path, lam=w, dim=dim, n=n, k=k, kappa_seed=-1 if seed is None else seed,
+             recipe="oracle.reference.lowest_eigenpairs(dim, n, k, synth.kappa_field(dim, n, kappa_seed))")
+    print(f"{name}: {time.time() - t:.1f} s -> {path}", flush=True)
+
+
+if __name__ == "__main__":
+    for name in (sys.argv[1:] or list(CASES)):
+        write(name)
