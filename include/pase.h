@@ -118,9 +118,14 @@ typedef struct pase_report {
   int ritz_history_rows;         /* rows written to ritz_history_host */
   double t_solve_ms;             /* device time of the solve (HIP events on the handle's stream) */
   int small_fast_iters;          /* corrections whose augmented eigenproblem the structured path solved */
-  int* small_path_host;          /* max_outer: per correction, 1 = structured path accepted, 0 = dense
-                                    only, -1 = rejected by a residual, -2 = rejected by the eigenvalue
-                                    count, -3 = its Cholesky-QR orthonormalisation broke down */
+  int* small_path_host;          /* max_outer: per correction, 1 = structured path accepted, 2 = accepted
+                                    with the count certifying the nev wanted pairs only (the guard pairs
+                                    are eigenpairs of the augmented problem, not certified as the next
+                                    ones), 3 = accepted on the retry from the Rayleigh-Ritz start of a
+                                    principal block (after a rejection), 0 = dense only, -1 = rejected
+                                    by a residual, -2 = rejected by the eigenvalue count, -3 = its
+                                    Cholesky-QR orthonormalisation broke down (the last rejection of
+                                    the correction; the dense solver then solved it) */
   int learned_fallbacks;         /* learned form: column switches to the V-cycle, summed over the solve */
   int lowprec_projection_iters;  /* mixed form: corrections whose projection ran on FP32 vectors with
                                     split-BF16 Grams (the rest ran in FP64) */

@@ -360,6 +360,127 @@ __global__ __launch_bounds__(kBlock) void gram_lds_kernel(long long N, int k, co
   }
 }
 
+// ---- symmetric Grams for 64 < k <= 128: G_y = X^T Y_y (NY = 1 or 2) when every G_y is symmetric
+// (the projection's W^T A W and W^T M W, the Cholesky-QR Gram U^T M U).  Only the T(T+1)/2 upper
+// 16 x 16 tiles are multiplied (T = ceil(k / 16)); each writes its entries and their mirror
+// images into the block's partial, so the fixed-order reduction gives the full symmetric matrix.
+// Eight waves share the upper tiles (at most 5 each); the block walks its rows in 32-row chunks
+// staged in LDS exactly like gram_lds_kernel, X read once for both products.
+constexpr int kSymThreads = 512;
+constexpr int kSymTiles = 5;       // ceil(36 / 8)
+
+template <int NY>
+__global__ __launch_bounds__(kSymThreads) void gram_sym_kernel(long long N, int k, const double* __restrict__ X,
+                                                             const double* __restrict__ Y1,
+                                                             const double* __restrict__ Y2,
+                                                             double* __restrict__ partial, int tiles,
+                                                             long long rows) {
+  constexpr int KMAX = 128;
+  constexpr int U = kGramRows * KMAX / kSymThreads;       // staged doubles per thread per matrix
+  extern __shared__ double lds[];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= tiles) return;
+  const int T = (k + 15) >> 4;
+  const int LD = T * 16 + 1;
+  double* xs = lds;
+  double* y1s = xs + kGramRows * LD;
+  double* y2s = y1s + kGramRows * LD;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < (1 + NY) * kGramRows * LD; e += kSymThreads) lds[e] = 0.0;
+  // this wave's upper tiles: q = wave + 8 t enumerates (ti, tj), ti <= tj, row by row
+  int ta[kSymTiles], tb[kSymTiles];
+#pragma unroll
+  for (int t = 0; t < kSymTiles; ++t) {
+    int q = wave + 8 * t, i = 0;
+    while (i < T && q >= T - i) {
+      q -= T - i;
+      ++i;
+    }
+    ta[t] = (i < T) ? i : -1;
+    tb[t] = (i < T) ? i + q : 0;
+  }
+  const long long r0 = (long long)tile * rows;
+  const long long r1 = (r0 + rows < N) ? (r0 + rows) : N;
+  const int ck = kGramRows * k;
+  int soff[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = tid + kSymThreads * u;
+    const int rr = e / k;
+    soff[u] = (e < ck) ? rr * LD + (e - rr * k) : -1;
+  }
+  double rx[U], ry1[U], ry2[U];
+  auto fetch = [&](long long rc) {
+    const long long lim = (r1 - rc) * k;
+    const unsigned nval = (unsigned)((lim < ck) ? lim : ck);
+    const double* __restrict__ px = X + rc * k;
+    const double* __restrict__ py1 = Y1 + rc * k;
+    const double* __restrict__ py2 = (NY == 2) ? Y2 + rc * k : Y1 + rc * k;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned e = (unsigned)(tid + kSymThreads * u);
+      const bool ok = e < nval;
+      rx[u] = ok ? px[e] : 0.0;
+      ry1[u] = ok ? py1[e] : 0.0;
+      if (NY == 2) ry2[u] = ok ? py2[e] : 0.0;
+    }
+  };
+  double4_t acc1[kSymTiles], acc2[kSymTiles];
+#pragma unroll
+  for (int t = 0; t < kSymTiles; ++t) {
+    acc1[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    acc2[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  }
+  const int li = lane & 15, lk = lane >> 4;
+  if (r0 < r1) fetch(r0);
+  __syncthreads();
+  for (long long rc = r0; rc < r1; rc += kGramRows) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (soff[u] >= 0) {
+        xs[soff[u]] = rx[u];
+        y1s[soff[u]] = ry1[u];
+        if (NY == 2) y2s[soff[u]] = ry2[u];
+      }
+    }
+    __syncthreads();
+    if (rc + kGramRows < r1) fetch(rc + kGramRows);
+#pragma unroll 2
+    for (int st = 0; st < kGramRows / 4; ++st) {
+      const int row = (4 * st + lk) * LD;
+#pragma unroll
+      for (int t = 0; t < kSymTiles; ++t) {
+        if (ta[t] >= 0) {
+          const double av = xs[row + ta[t] * 16 + li];
+          acc1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, y1s[row + tb[t] * 16 + li], acc1[t], 0, 0, 0);
+          if (NY == 2)
+            acc2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, y2s[row + tb[t] * 16 + li], acc2[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int y = 0; y < NY; ++y) {
+    double* p = partial + ((size_t)y * tiles + tile) * k * k;
+#pragma unroll
+    for (int t = 0; t < kSymTiles; ++t) {
+      if (ta[t] >= 0) {
+        const int j = tb[t] * 16 + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = ta[t] * 16 + lk + 4 * q;
+          const double v = (y == 0) ? acc1[t][q] : acc2[t][q];
+          if (i < k && j < k) {
+            p[(size_t)i * k + j] = v;
+            if (ta[t] != tb[t]) p[(size_t)j * k + i] = v;
+          }
+        }
+      }
+    }
+  }
+}
+
 // ---- split-BF16 Gram of FP32 operands: G_y = X^T Y_y (NY = 1 or 2, k <= 64) on
 // v_mfma_f32_16x16x32_bf16.  Each FP32 value is split as x = x_hi + x_lo with x_hi = bf16(x) and
 // x_lo = bf16(x - x_hi); a product is formed as x_hi y_hi + x_hi y_lo + x_lo y_hi (the dropped
@@ -636,34 +757,36 @@ void launch_gemm_small(int ta, int tb, int M, int N, int K, double alpha, const 
   }
 }
 
-// ---- tall-skinny Y = X op(C) (+ Y), X and Y N x k (row-major), C k x k, k <= 64, on MFMA
-// (v_mfma_f64_16x16x4f64).  A block walks chunks of 64
-// consecutive rows; a chunk of X (and of Y) is one contiguous run of 64 k doubles, read and written
-// with coalesced accesses.  Wave w owns output columns 16w .. 16w+15 and keeps that strip of op(C)
-// as B fragments in registers; the X chunk is staged in LDS (row stride kTsmLd) and read as A
-// fragments; the 64 x k result goes back through the same LDS array for the contiguous store.
+// ---- tall-skinny Y = X op(C) (+ Y), X and Y N x k (row-major), C k x k, k <= KMAX (64 or 128), on
+// MFMA (v_mfma_f64_16x16x4f64).  A block walks chunks of 64 consecutive rows; a chunk of X (and of
+// Y) is one contiguous run of 64 k doubles, read and written with coalesced accesses.  Wave w
+// (KMAX / 16 waves) owns output columns 16w .. 16w+15 and keeps that strip of op(C) as B fragments
+// in registers; the X chunk is staged in LDS (row stride KMAX + 2) and read as A fragments; the
+// 64 x k result goes back through the same LDS array for the contiguous store.
 // MFMA operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register q
 // holds D[l/16 + 4q][l%16].
 constexpr int kTsmRows = 64;
-constexpr int kTsmLd = 66;   // 16 rows x 4 columns of an A fragment fall in distinct LDS banks
-constexpr int kTsmSE = kTsmRows * 64 / kBlock;   // staged doubles per thread (k <= 64)
 
-template <int TB>
-__global__ __launch_bounds__(kBlock) void tsmm_mfma_kernel(long long N, int k, const double* __restrict__ X,
-                                                           const double* __restrict__ C, double* __restrict__ Y,
-                                                           int accumulate, long long nchunks) {
-  __shared__ double xs[kTsmRows * kTsmLd];
+template <int TB, int KMAX>
+__global__ __launch_bounds__(KMAX * 4) void tsmm_mfma_kernel(long long N, int k, const double* __restrict__ X,
+                                                             const double* __restrict__ C, double* __restrict__ Y,
+                                                             int accumulate, long long nchunks) {
+  constexpr int NT = KMAX * 4;                  // threads: one wave per 16-column strip
+  constexpr int LD = KMAX + 2;                  // 16 rows x 4 columns of an A fragment fall in distinct banks
+  constexpr int SE = kTsmRows * KMAX / NT;      // staged doubles per thread
+  constexpr int KS4 = KMAX / 4;
+  __shared__ double xs[kTsmRows * LD];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const int KS = (k + 3) >> 2;
-  for (int e = tid; e < kTsmRows * kTsmLd; e += kBlock) xs[e] = 0.0;   // columns >= k stay zero
+  for (int e = tid; e < kTsmRows * LD; e += NT) xs[e] = 0.0;   // columns >= k stay zero
   // B fragments of this wave's column strip: b[s] = op(C)[4s + lk][16w + li], zero outside k
-  double b[16];
+  double b[KS4];
   {
     const int j = 16 * w + li, jc = (j < k) ? j : k - 1;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < KS4; ++s) {
       const int kk = 4 * s + lk, kc = (kk < k) ? kk : k - 1;
       const double v = TB ? C[(size_t)jc * k + kc] : C[(size_t)kc * k + jc];
       b[s] = (kk < k && j < k) ? v : 0.0;
@@ -671,30 +794,30 @@ __global__ __launch_bounds__(kBlock) void tsmm_mfma_kernel(long long N, int k, c
   }
   const int ck = kTsmRows * k;
   // LDS slot of each staged element (row e / k, column e % k); independent of the chunk
-  int soff[kTsmSE];
+  int soff[SE];
 #pragma unroll
-  for (int u = 0; u < kTsmSE; ++u) {
-    const int e = tid + kBlock * u;
+  for (int u = 0; u < SE; ++u) {
+    const int e = tid + NT * u;
     const int r = e / k;
-    soff[u] = (e < ck) ? r * kTsmLd + (e - r * k) : -1;
+    soff[u] = (e < ck) ? r * LD + (e - r * k) : -1;
   }
   for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
     const long long lim = (N - c * kTsmRows) * k;
     const int nval = (int)((lim < ck) ? lim : ck);   // valid doubles of this chunk
     const double* __restrict__ xp = X + c * kTsmRows * k;
     double* __restrict__ yp = Y + c * kTsmRows * k;
-    double sv[kTsmSE], yv[kTsmSE];
+    double sv[SE], yv[SE];
 #pragma unroll
-    for (int u = 0; u < kTsmSE; ++u) {
-      const int e = tid + kBlock * u;
+    for (int u = 0; u < SE; ++u) {
+      const int e = tid + NT * u;
       const int ec = (e < nval) ? e : nval - 1;   // clamped, unconditional: all loads in flight together
       sv[u] = xp[ec];
       yv[u] = accumulate ? yp[ec] : 0.0;
     }
     __syncthreads();   // the previous chunk's result has been read out of xs
 #pragma unroll
-    for (int u = 0; u < kTsmSE; ++u) {
-      const int e = tid + kBlock * u;
+    for (int u = 0; u < SE; ++u) {
+      const int e = tid + NT * u;
       if (soff[u] >= 0) xs[soff[u]] = (e < nval) ? sv[u] : 0.0;   // rows past N are zero
     }
     __syncthreads();
@@ -703,12 +826,12 @@ __global__ __launch_bounds__(kBlock) void tsmm_mfma_kernel(long long N, int k, c
     for (int rt = 0; rt < 4; ++rt) acc[rt] = (double4_t){0.0, 0.0, 0.0, 0.0};
     if (16 * w < k) {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
+      for (int s = 0; s < KS4; ++s) {
         if (s < KS) {
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt)
-            acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[(16 * rt + li) * kTsmLd + 4 * s + lk], b[s], acc[rt],
-                                                           0, 0, 0);
+            acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[(16 * rt + li) * LD + 4 * s + lk], b[s], acc[rt], 0, 0,
+                                                           0);
         }
       }
     }
@@ -717,12 +840,12 @@ __global__ __launch_bounds__(kBlock) void tsmm_mfma_kernel(long long N, int k, c
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) xs[(16 * rt + lk + 4 * q) * kTsmLd + 16 * w + li] = acc[rt][q];
+        for (int q = 0; q < 4; ++q) xs[(16 * rt + lk + 4 * q) * LD + 16 * w + li] = acc[rt][q];
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kTsmSE; ++u) {
-      const int e = tid + kBlock * u;
+    for (int u = 0; u < SE; ++u) {
+      const int e = tid + NT * u;
       if (e < nval) yp[e] = xs[soff[u]] + yv[u];
     }
   }
@@ -886,6 +1009,23 @@ void launch_gram2(long long N, int k, const double* X, const double* Y1, const d
   if (Y2) reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial + (size_t)tiles * k * k, G2);
 }
 
+void launch_gram2_sym(long long N, int k, const double* X, const double* Y1, const double* Y2, double* partial,
+                      int tiles, double* G1, double* G2, hipStream_t s) {
+  if (k <= 64) {
+    launch_gram2(N, k, X, Y1, Y2, partial, tiles, G1, G2, s);
+    return;
+  }
+  long long rows = (N + tiles - 1) / tiles;
+  rows = ((rows + 3) / 4) * 4;
+  const int blocks = ((tiles + 7) / 8) * 8;
+  const int T = (k + 15) / 16;
+  const size_t lds = (size_t)(Y2 ? 3 : 2) * kGramRows * (T * 16 + 1) * sizeof(double);
+  if (Y2) gram_sym_kernel<2><<<blocks, kSymThreads, lds, s>>>(N, k, X, Y1, Y2, partial, tiles, rows);
+  else gram_sym_kernel<1><<<blocks, kSymThreads, lds, s>>>(N, k, X, Y1, nullptr, partial, tiles, rows);
+  reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial, G1);
+  if (Y2) reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial + (size_t)tiles * k * k, G2);
+}
+
 void launch_gram_bf16x3(long long N, int k, const float* X, const float* Y1, const float* Y2, double* partial,
                         int tiles, double* G1, double* G2, hipStream_t s) {
   long long rows = (N + tiles - 1) / tiles;
@@ -948,11 +1088,17 @@ void launch_gemm_f32(bool ta, bool tb, int M, int N, int K, double alpha, const 
 
 void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y, int accumulate, int tb,
                  hipStream_t s) {
+  const long long nchunks = (N + kTsmRows - 1) / kTsmRows;
   if (k <= 64) {
-    const long long nchunks = (N + kTsmRows - 1) / kTsmRows;
     const unsigned blocks = (unsigned)((nchunks < 768) ? nchunks : 768);
-    if (tb) tsmm_mfma_kernel<1><<<blocks, kBlock, 0, s>>>(N, k, X, C, Y, accumulate, nchunks);
-    else tsmm_mfma_kernel<0><<<blocks, kBlock, 0, s>>>(N, k, X, C, Y, accumulate, nchunks);
+    if (tb) tsmm_mfma_kernel<1, 64><<<blocks, 256, 0, s>>>(N, k, X, C, Y, accumulate, nchunks);
+    else tsmm_mfma_kernel<0, 64><<<blocks, 256, 0, s>>>(N, k, X, C, Y, accumulate, nchunks);
+    return;
+  }
+  if (k <= 128) {
+    const unsigned blocks = (unsigned)((nchunks < 512) ? nchunks : 512);
+    if (tb) tsmm_mfma_kernel<1, 128><<<blocks, 512, 0, s>>>(N, k, X, C, Y, accumulate, nchunks);
+    else tsmm_mfma_kernel<0, 128><<<blocks, 512, 0, s>>>(N, k, X, C, Y, accumulate, nchunks);
     return;
   }
   launch_gemm(false, tb != 0, (int)N, k, k, 1.0, X, k, C, k, accumulate ? 1.0 : 0.0, Y, k, s);

@@ -24,34 +24,43 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ MFMA GEMM
 // C = alpha op(A) op(B) + beta C (row-major), storage type T (double or float), FP64
-// arithmetic.  A block computes a 64 x 64 tile with four waves (2 x 2 sub-tiles of
-// 16 x 16 each); K advances 16 per LDS stage, the next stage's operands are loaded
-// into registers while the current one is multiplied.  MFMA operand layout: lane l
-// supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register q holds
-// D[l/16 + 4q][l%16].
-constexpr int kGM = 64, kGN = 64, kGK = 16;
+// arithmetic.  A block computes a BM x 64 tile (BM = 64, 32 or 16, the smaller ones for products
+// with few output tiles, such as N_H x N_H times N_H x k) with four waves: 2 x 2 waves of
+// 32 x 32 (BM 64), 2 x 2 waves of 16 x 32 (BM 32) or 1 x 4 waves of 16 x 16 (BM 16), in 16 x 16
+// sub-tiles.  K advances 16 per LDS stage; the next stage's operands are loaded into registers
+// while the current one is multiplied.  MFMA operand layout: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator register q holds D[l/16 + 4q][l%16].
+constexpr int kGN = 64, kGK = 16;
 
-template <typename T>
+template <typename T, int BM>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(int ta, int tb, int M, int N, int K, double alpha,
                                                         const T* __restrict__ A, int lda, const T* __restrict__ B,
                                                         int ldb, double beta, T* __restrict__ C, int ldc) {
-  __shared__ double As[kGK][kGM + 2];
+  constexpr int WC = (BM == 16) ? 4 : 2;         // waves along the columns
+  constexpr int SR = (BM == 64) ? 2 : 1;         // 16-row sub-tiles per wave
+  constexpr int SC = 4 / WC;                     // 16-column sub-tiles per wave
+  constexpr int UA = BM * kGK / 256;             // staged A values per thread
+  __shared__ double As[kGK][BM + 2];
   __shared__ double Bs[kGK][kGN + 2];
-  const int bm = blockIdx.y * kGM, bn = blockIdx.x * kGN;
+  const int bm = blockIdx.y * BM, bn = blockIdx.x * kGN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  double ra[4], rb[4];
+  const int wr = (wave / WC) * 16 * SR, wc = (wave % WC) * 16 * SC;
+  double ra[UA], rb[4];
   // element u of this thread in a stage: (row, kk) of op(A) and (kk, col) of op(B), chosen so
   // that consecutive threads read consecutive addresses
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < UA; ++u) {
       const int e = tid + 256 * u;
       int i, kk;
-      if (ta) { i = e & 63; kk = e >> 6; } else { kk = e & 15; i = e >> 4; }
+      if (ta) { i = e % BM; kk = e / BM; } else { kk = e & 15; i = e >> 4; }
       const int gi = bm + i, gk = k0 + kk;
       ra[u] = (gi < M && gk < K) ? (double)(ta ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
       int j, k2;
       if (tb) { k2 = e & 15; j = e >> 4; } else { j = e & 63; k2 = e >> 6; }
       const int gj = bn + j, gk2 = k0 + k2;
@@ -60,17 +69,21 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int ta, int tb, int M, i
   };
   auto stash = [&]() {
 #pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      const int e = tid + 256 * u;
+      if (ta) As[e / BM][e % BM] = ra[u]; else As[e & 15][e >> 4] = ra[u];
+    }
+#pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = tid + 256 * u;
-      if (ta) As[e >> 6][e & 63] = ra[u]; else As[e & 15][e >> 4] = ra[u];
       if (tb) Bs[e & 15][e >> 4] = rb[u]; else Bs[e >> 6][e & 63] = rb[u];
     }
   };
-  double4_t acc[2][2];
+  double4_t acc[SR][SC];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < SR; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < SC; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
   fetch(0);
   for (int k0 = 0; k0 < K; k0 += kGK) {
     __syncthreads();
@@ -79,22 +92,21 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int ta, int tb, int M, i
     if (k0 + kGK < K) fetch(k0 + kGK);
 #pragma unroll
     for (int s = 0; s < kGK / 4; ++s) {
-      double av[2], bv[2];
+      double av[SR], bv[SC];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = As[4 * s + lk][wr + 16 * t + li];
-        bv[t] = Bs[4 * s + lk][wc + 16 * t + li];
-      }
+      for (int t = 0; t < SR; ++t) av[t] = As[4 * s + lk][wr + 16 * t + li];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int t = 0; t < SC; ++t) bv[t] = Bs[4 * s + lk][wc + 16 * t + li];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      for (int a = 0; a < SR; ++a)
+#pragma unroll
+        for (int b = 0; b < SC; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < SR; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < SC; ++b)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = bm + wr + 16 * a + lk + 4 * q, j = bn + wc + 16 * b + li;
@@ -209,18 +221,30 @@ __device__ __forceinline__ void st_agent(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier across XCDs: release fence and arrival, then a bounded acquire spin (on
-// timeout or when another block has raised *err, the block raises *err and reports false,
-// so every wave of the grid returns).
-__device__ bool grid_sync(unsigned* counter, unsigned target, int* err) {
+// Grid barrier of the NW blocks.  Everything one block writes for another (the products p and
+// the published row) is written and read with agent-scope atomic accesses, which are coherent
+// across the XCDs' L2 caches by themselves; each block's own matrix rows never leave it.  So
+// the barrier needs no cache write-back or invalidation: a block waits until its own stores have
+// completed, then arrives.  Arrival is two-level to spread the atomics: the blocks of group
+// b % 8 count on their group's counter (own cache line), and the last of each group bumps the
+// top counter that everyone polls.  The spin is bounded: on timeout, or when another block has
+// raised *err, the block raises *err and reports false, so every wave of the grid returns.
+// counters: [0] top, [16 g] group g (unsigned, 64-byte apart).
+__device__ bool grid_sync(unsigned* counters, unsigned round, int NW, int* err) {
   __shared__ int ok;
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const int g = blockIdx.x & 7;
+    const unsigned members = (unsigned)((NW - g + 7) / 8);    // blocks b < NW with b % 8 == g
+    const unsigned groups = (unsigned)(NW < 8 ? NW : 8);
+    const unsigned old = __hip_atomic_fetch_add(&counters[16 * (g + 1)], 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == round * members) __hip_atomic_fetch_add(&counters[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = round * groups;
     unsigned spins = 0;
     ok = 1;
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&counters[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kTgMaxSpins || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -228,7 +252,6 @@ __device__ bool grid_sync(unsigned* counter, unsigned target, int* err) {
         break;
       }
     }
-    __threadfence();
   }
   __syncthreads();
   return ok != 0;
@@ -300,7 +323,7 @@ __global__ __launch_bounds__(kTgThreads) void tridiag_grid_kernel(int n, int NW,
   double* d = tri;
   double* e = tri + n;
   double* tau = tri + 2 * n;
-  unsigned target = 0;
+  unsigned round = 0;
   for (int c = tid; c < n; c += kTgThreads) prow[c] = T[c];
   __syncthreads();
   double beta0;
@@ -315,15 +338,26 @@ __global__ __launch_bounds__(kTgThreads) void tridiag_grid_kernel(int n, int NW,
     if (r < 1) continue;
     const double* ar = T + (size_t)r * n;
     double acc = 0.0;
-    for (int c = 1 + lane; c < n; c += 64) acc = fma(ar[c], v[c - 1], acc);
+    for (int c0 = 1 + lane; c0 < n; c0 += 64 * 8) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + 64 * u;
+        a[u] = (c < n) ? ar[c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + 64 * u;
+        if (c < n) acc = fma(a[u], v[c - 1], acc);
+      }
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) st_agent(&pbuf[r - 1], tcur * acc);
     if (r == 1)
       for (int c = lane; c < n; c += 64) st_agent(&rbuf[c], ar[c]);
   }
-  target += NW;
-  if (!grid_sync(counter, target, err)) return;
+  if (!grid_sync(counter, ++round, NW, err)) return;
   // reflector 0 goes into row 0 only now: every block has read that row before the barrier
   if (b == 0)
     for (int i = 1 + tid; i < n - 1; i += kTgThreads) T[i + 1] = v[i];
@@ -373,13 +407,26 @@ __global__ __launch_bounds__(kTgThreads) void tridiag_grid_kernel(int n, int NW,
       const double vr = v[rr], wr = w[rr];
       const bool publish = has_next && r == j + 2;
       double acc = 0.0;
-      for (int c = j + 2 + lane; c < n; c += 64) {
-        const int cc = c - (j + 1);
-        const double a = ar[c] - (vr * w[cc] + wr * v[cc]);
-        ar[c] = a;
-        if (has_next) acc = fma(a, v2[c - (j + 2)], acc);
-        if (publish) st_agent(&rout[c], a);
-        if (!has_next && r == n - 1 && c == n - 1) d[n - 1] = a;
+      // batches of 8 loads per lane in flight (a row streams from the memory-side cache)
+      for (int c0 = j + 2 + lane; c0 < n; c0 += 64 * 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int c = c0 + 64 * u;
+          a[u] = (c < n) ? ar[c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int c = c0 + 64 * u;
+          if (c < n) {
+            const int cc = c - (j + 1);
+            const double val = a[u] - (vr * w[cc] + wr * v[cc]);
+            ar[c] = val;
+            if (has_next) acc = fma(val, v2[c - (j + 2)], acc);
+            if (publish) st_agent(&rout[c], val);
+            if (!has_next && r == n - 1 && c == n - 1) d[n - 1] = val;
+          }
+        }
       }
       if (has_next) {
 #pragma unroll
@@ -392,14 +439,13 @@ __global__ __launch_bounds__(kTgThreads) void tridiag_grid_kernel(int n, int NW,
     v = v2;
     v2 = t1;
     tcur = tnext;
-    target += NW;
-    if (!grid_sync(counter, target, err)) return;
+    if (!grid_sync(counter, ++round, NW, err)) return;
   }
 }
 
 __global__ void tg_reset_kernel(unsigned* counter, int* err) {
-  *counter = 0u;
-  *err = 0;
+  for (int i = threadIdx.x; i < 16 * 9; i += blockDim.x) counter[i] = 0u;
+  if (threadIdx.x == 0) *err = 0;
 }
 
 __global__ void tg_fold_kernel(int* info, const int* err, const int* cinfo) {
@@ -619,12 +665,23 @@ size_t chol_scratch_doubles(int n) { return (size_t)n * kNB + 8; }
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+// The row tile is the largest of 64, 32, 16 that still gives at least 512 blocks (two per CU).
 template <typename T>
 static void gemm_mfma(bool ta, bool tb, int M, int N, int K, double alpha, const T* A, int lda, const T* B, int ldb,
                       double beta, T* C, int ldc, hipStream_t s) {
   if (M <= 0 || N <= 0) return;
-  dim3 grid((N + kGN - 1) / kGN, (M + kGM - 1) / kGM);
-  gemm_mfma_kernel<T><<<grid, 256, 0, s>>>(ta ? 1 : 0, tb ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  const long long cols = (N + kGN - 1) / kGN;
+  const int a = ta ? 1 : 0, b = tb ? 1 : 0;
+  if (cols * ((M + 63) / 64) >= 512) {
+    gemm_mfma_kernel<T, 64><<<dim3((unsigned)cols, (M + 63) / 64), 256, 0, s>>>(a, b, M, N, K, alpha, A, lda, B, ldb,
+                                                                                 beta, C, ldc);
+  } else if (cols * ((M + 31) / 32) >= 512) {
+    gemm_mfma_kernel<T, 32><<<dim3((unsigned)cols, (M + 31) / 32), 256, 0, s>>>(a, b, M, N, K, alpha, A, lda, B, ldb,
+                                                                                 beta, C, ldc);
+  } else {
+    gemm_mfma_kernel<T, 16><<<dim3((unsigned)cols, (M + 15) / 16), 256, 0, s>>>(a, b, M, N, K, alpha, A, lda, B, ldb,
+                                                                                 beta, C, ldc);
+  }
 }
 
 void launch_gemm_mfma(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
@@ -687,7 +744,7 @@ int syev_large_max_n() { return kLargeMaxN; }
 size_t syev_large_work_doubles(int n, int k) {
   const size_t nblk = (size_t)(n + kWyB - 1) / kWyB + 1;
   size_t w = (size_t)3 * n + 8 + (size_t)k + (size_t)2 * n * k + (size_t)2 * k * k + nblk * kWyB * kWyB +
-             (size_t)4 * n + 16;
+             (size_t)4 * n + 80;
   w += chol_scratch_doubles(k) + trinv_large_scratch_doubles(k);
   return w;
 }
@@ -705,15 +762,15 @@ void launch_syev_large(int n, int k, double* T, double* w, double* V, double* wo
   const size_t nblk = (size_t)(n + kWyB - 1) / kWyB + 1;
   double* Sall = G2 + (size_t)k * k;
   double* xchg = Sall + nblk * kWyB * kWyB;            // 4 n
-  unsigned* counter = (unsigned*)(xchg + 4 * (size_t)n);
-  int* err = (int*)(counter + 2);
+  unsigned* counter = (unsigned*)(xchg + 4 * (size_t)n);  // 9 counters, 64 bytes apart
+  int* err = (int*)(counter + 16 * 9);
   int* cinfo = err + 1;                                // Cholesky-QR status (k above one workgroup)
-  double* cscr = xchg + 4 * (size_t)n + 16;
+  double* cscr = xchg + 4 * (size_t)n + 80;
   double* tscr = cscr + chol_scratch_doubles(k);
   set_int_kernel<<<1, 1, 0, s>>>(info, 0);
   set_int_kernel<<<1, 1, 0, s>>>(cinfo, 0);
   set_int_kernel<<<1, 1, 0, s>>>(cinfo + 1, 0);
-  tg_reset_kernel<<<1, 1, 0, s>>>(counter, err);
+  tg_reset_kernel<<<1, 64, 0, s>>>(counter, err);
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);

@@ -130,6 +130,10 @@ void launch_gram2(long long N, int k, const double* X, const double* Y1, const d
                   int tiles, double* G1, double* G2, hipStream_t s);
 void launch_gram(long long N, int k, const double* X, const double* Y, double* partial, int tiles, double* G,
                  hipStream_t s);
+// the same when every product is symmetric (W^T A W, W^T M W, U^T M U): for 64 < k <= 128 only the
+// upper tiles are multiplied and mirrored (for k <= 64 it is launch_gram2)
+void launch_gram2_sym(long long N, int k, const double* X, const double* Y1, const double* Y2, double* partial,
+                      int tiles, double* G1, double* G2, hipStream_t s);
 // C = alpha op(A) op(B) + beta C, row-major, FP64
 void launch_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
                  int ldb, double beta, double* C, int ldc, hipStream_t s);
@@ -224,11 +228,17 @@ void launch_small_rqi(int nH, int k, const double* theta, const double* Gt, cons
 void launch_small_rr(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
                      double* rq, double* res, hipStream_t s);
 // acceptance: residuals <= tol_abs (times tolv[r] for the pair at position r of the ascending
-// order when tolv is given) and the inertia count below max(rq) + gap equals k; writes lam
-// ascending, perm, status[0] (1 accepted) and status[1] (the count)
-void launch_small_accept(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* rq,
-                         const double* res, double tol_abs, const double* tolv, double gap, double* lam, int* perm,
-                         int* status, hipStream_t s);
+// order when tolv is given) and the inertia count below max(rq) + gap equals k (or, failing that,
+// the count below the nev-th value + gap equals nev: the wanted pairs certified, status[0] = 2);
+// writes lam ascending, perm, status[0] (0 rejected) and status[1] (the count)
+void launch_small_accept(int nH, int k, int nev, const double* theta, const double* Gt, const double* Hm,
+                         const double* rq, const double* res, double tol_abs, const double* tolv, double gap,
+                         double* lam, int* perm, int* status, hipStream_t s);
+// principal block of Tt on the first m coarse modes and the k W-directions ((m + k)^2, row-major),
+// and the zero extension of its eigenvectors ((m + k) x k) to start vectors ((nH + k) x k)
+void launch_small_principal(int nH, int m, int k, const double* theta, const double* Gt, const double* Hm,
+                            double* Tr, hipStream_t s);
+void launch_small_expand(int nH, int m, int k, const double* Vr, double* X0, hipStream_t s);
 // V (n x k row-major) = columns perm of Vt
 void launch_small_emit(int n, int k, const double* Vt, const int* perm, double* V, hipStream_t s);
 void launch_symmetrize(int n, double* A, hipStream_t s);
@@ -244,7 +254,7 @@ void launch_small_rqi_big(int nH, int k, const double* theta, const double* Gt, 
                           double* rq, double* scratch, hipStream_t s);
 void launch_small_rr_big(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
                          double* rq, double* res, double* scratch, hipStream_t s);
-void launch_small_accept_big(int nH, int k, const double* theta, const double* Gt, const double* Hm,
+void launch_small_accept_big(int nH, int k, int nev, const double* theta, const double* Gt, const double* Hm,
                              const double* rq, const double* res, double tol_abs, const double* tolv, double gap,
                              double* lam, int* perm, int* status, hipStream_t s);
 

@@ -105,8 +105,12 @@ struct pase_handle {
   int* netmask = nullptr;
   int fallbacks = 0;            // column switches to the V-cycle (this solve)
   int fast_hits = 0;            // corrections solved by the structured path (this solve)
-  int last_path = 0;            // 1 accepted, 0 dense only, -1 residual, -2 count, -3 orthonormalisation
+  int last_path = 0;            // 1 accepted, 2 accepted on the wanted pairs' count, 0 dense only,
+                                // -1 residual, -2 count, -3 orthonormalisation
+  int nev_cur = 0;              // wanted pairs of the running solve (the block minus the guard pairs)
   bool spec = false;            // a structured solution was enqueued and its status is not read yet
+  bool retried = false;         // this correction's structured path already restarted from the reduced
+                                // Rayleigh-Ritz block
   bool try_fast = true;         // attempt the structured path in this correction
   // mixed form: the projection runs on FP32 vectors with split-BF16 Grams until the residual drops
   // below 1e-6 or stops halving over two corrections (then FP64 to the end of the solve)
@@ -588,7 +592,7 @@ void cholqr_m(pase_handle* h, int k, double*& U, double*& spare, int slot) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   apply_AM(h, 0, k, U, nullptr, h->W3);
-  launch_gram(N, k, U, h->W3, h->partial, gram_tiles(N, k), h->kk2, s);
+  launch_gram2_sym(N, k, U, h->W3, nullptr, h->partial, gram_tiles(N, k), h->kk2, nullptr, s);
   launch_cholinv(k, h->kk2, h->info + slot, s);            // kk2 <- L^{-1}
   launch_tsmm(N, k, U, h->kk2, spare, 0, 1, s);
   std::swap(U, spare);
@@ -616,6 +620,52 @@ pase_status correction_dense_tail(pase_handle* h, int k) {
   launch_gemm(true, false, NH, k, NH, 1.0, h->LBinv, NH, h->Vs, k, 0.0, h->cb, k, s);   // y_H
   prolongation_tail(h, k, h->cb);
   return PASE_OK;
+}
+
+// The structured small solver from the start block in X0f (Gt, H = kk5 and Li = kk3 formed),
+// its certification, and the speculative prolongation of its solution: y_H into cc (so that a and
+// its restriction in ca stay for the dense path); the caller reads statf with its next
+// synchronisation (correction_resolve).
+void structured_attempt(pase_handle* h, int k) {
+  hipStream_t s = h->stream;
+  const int NH = (int)h->lev[h->L].N;
+  const int nT = NH + k;
+  const double sc = h->small_scale;
+  const double* tv = h->tolv_on ? h->small_tolv : nullptr;
+  const int nevc = (h->nev_cur >= 1 && h->nev_cur <= k) ? h->nev_cur : k;
+  if (h->fast_big) {
+    launch_small_rqi_big(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, tv, h->Vtf, h->rqf, h->sbig, s);
+    launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
+    launch_small_rr_big(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, h->sbig, s);
+    launch_small_accept_big(NH, k, nevc, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc, tv, 1e-9 * sc,
+                            h->lam, h->permf, h->statf, s);
+  } else {
+    launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, tv, h->Vtf, h->rqf, s);
+    launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
+    launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
+    launch_small_accept(NH, k, nevc, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc, tv, 1e-9 * sc,
+                        h->lam, h->permf, h->statf, s);
+  }
+  launch_small_emit(nT, k, h->Vtf, h->permf, h->Vs, s);
+  launch_gemm(false, false, NH, k, NH, 1.0, h->Psi, NH, h->Vs, k, 0.0, h->cc, k, s);   // y_H = L_B^{-T} Phi V
+  prolongation_tail(h, k, h->cc);
+  h->spec = true;
+}
+
+// Retry of a rejected structured solution from a better start block: the k smallest eigenpairs of
+// the principal block of Tt on its m lowest coarse modes and the k W-directions (a Rayleigh-Ritz
+// approximation of the wanted pairs, Cauchy-interlaced above them), zero-extended to full length.
+void structured_retry(pase_handle* h, int k) {
+  hipStream_t s = h->stream;
+  const int NH = (int)h->lev[h->L].N;
+  const int m = std::max(1, std::min(NH, 384 - k));
+  const int nr = m + k;
+  launch_small_principal(NH, m, k, h->theta, h->Gtl, h->kk5, h->Tm, s);
+  syev_any(nr, k, h->Tm, h->rqf, h->Vs, h->syw, h->info + 6, s);
+  launch_small_expand(NH, m, k, h->Vs, h->X0f, s);
+  launch_fill_int(4, 0, h->statf, s);
+  h->retried = true;
+  structured_attempt(h, k);
 }
 
 // One correction from (lam, U), U^T M U = I, with R = lam M U - A U already in h->R: everything
@@ -686,7 +736,7 @@ pase_status correction_enqueue(pase_handle* h, int k) {
     // that the complement formed (W3) serves, and only A W_perp is applied here
     apply_AM(h, 0, k, W, h->W2, nullptr);
     restrict_all(h, k, h->W2, h->ca);
-    launch_gram2(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
+    launch_gram2_sym(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
   }
   launch_symmetrize(k, h->kk1, s);
   launch_symmetrize(k, h->kk2, s);
@@ -703,34 +753,14 @@ pase_status correction_enqueue(pase_handle* h, int k) {
   if (h->fast && h->try_fast) {
     // structured path in the eigenbasis of C0: Gt = Psi^T a Li^T, shifts = the current Ritz values
     const int nT = NH + k;
-    HIPC(hipMemsetAsync(h->statf, 0, 4 * sizeof(int), s));
+    launch_fill_int(4, 0, h->statf, s);
     launch_gemm(true, false, NH, k, NH, 1.0, h->Psi, NH, h->ca, k, 0.0, h->cb, k, s);
     launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->Gtl, k, s);
     // start block: the coordinates of W in the new basis, [Psi^T P^T M W ; L^T] (L^T = L^{-1} beta)
     launch_gemm(true, false, NH, k, NH, 1.0, h->Psi, NH, h->cmw, k, 0.0, h->X0f, k, s);
     launch_gemm(false, false, k, k, k, 1.0, h->kk3, k, h->kkb, k, 0.0, h->X0f + (size_t)NH * k, k, s);
-    const double sc = h->small_scale;
-    const double* tv = h->tolv_on ? h->small_tolv : nullptr;
-    if (h->fast_big) {
-      launch_small_rqi_big(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, tv, h->Vtf, h->rqf, h->sbig, s);
-      launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
-      launch_small_rr_big(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, h->sbig, s);
-      launch_small_accept_big(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc, tv, 1e-9 * sc,
-                              h->lam, h->permf, h->statf, s);
-    } else {
-      launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, tv, h->Vtf, h->rqf, s);
-      launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
-      launch_small_rr(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, s);
-      launch_small_accept(NH, k, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc, tv, 1e-9 * sc,
-                          h->lam, h->permf, h->statf, s);
-    }
-    // speculative: the prolongation of the structured solution is enqueued before its status is
-    // known (y_H into cc, so that a + its restriction in ca stay for the dense path); the caller
-    // reads statf with its next synchronisation and calls correction_dense_tail on a rejection
-    launch_small_emit(nT, k, h->Vtf, h->permf, h->Vs, s);
-    launch_gemm(false, false, NH, k, NH, 1.0, h->Psi, NH, h->Vs, k, 0.0, h->cc, k, s);   // y_H = L_B^{-T} Phi V
-    prolongation_tail(h, k, h->cc);
-    h->spec = true;
+    h->retried = false;
+    structured_attempt(h, k);
     return PASE_OK;
   }
   return correction_dense_tail(h, k);
@@ -742,12 +772,16 @@ pase_status correction_resolve(pase_handle* h, int k) {
   if (!h->spec) return PASE_OK;
   h->spec = false;
   const int* st = h->pin_st;
-  if (st[0] == 1 && st[2] == 0) {
-    h->last_path = 1;
+  if (st[0] >= 1 && st[2] == 0) {
+    h->last_path = h->retried ? 3 : st[0];
     ++h->fast_hits;
     return PASE_OK;
   }
   h->last_path = (st[2] != 0) ? -3 : (st[1] == 0 ? -1 : -2);
+  if (!h->retried) {
+    structured_retry(h, k);   // speculative again: read with the next synchronisation
+    return PASE_OK;
+  }
   return correction_dense_tail(h, k);
 }
 
@@ -755,10 +789,11 @@ pase_status correction_resolve(pase_handle* h, int k) {
 pase_status correction(pase_handle* h, int k) {
   pase_status st = correction_enqueue(h, k);
   if (st) return st;
-  if (h->spec) {
+  while (h->spec) {
     HIPC(hipMemcpyAsync(h->pin_st, h->statf, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPC(hipStreamSynchronize(h->stream));
     st = correction_resolve(h, k);
+    if (st) return st;
   }
   return st;
 }
@@ -1118,6 +1153,7 @@ pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* 
   h->tolv_on = false;
   h->try_fast = true;
   h->proj_lp = false;   // a standalone correction projects in FP64, whatever a solve left behind
+  h->nev_cur = k;
   st = correction(h, k);
   if (st) return st;
   launch_copy((size_t)N * k, h->U, U, s);
@@ -1141,6 +1177,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     return fail(h, PASE_E_UNSUPPORTED, "the coarse start needs the structured small solver's coarse eigenbasis");
   if (!(tol > 0.0)) return fail(h, PASE_E_ARG, "tol must be positive");
   const int k = nev + h->opt.guard;   // block size: the wanted pairs and the guard pairs
+  h->nev_cur = nev;
   const long long N = h->lev[0].N;
   hipStream_t s = h->stream;
   HIPC(hipEventRecord(h->ev0, s));
@@ -1192,7 +1229,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     if (h->spec) {
       // the previous correction's structured solution was used speculatively (one synchronisation
       // per correction): on a rejection the dense path redoes the prolongation and the residual
-      const bool accepted = h->pin_st[0] == 1 && h->pin_st[2] == 0;
+      const bool accepted = h->pin_st[0] >= 1 && h->pin_st[2] == 0;
       st = correction_resolve(h, k);
       if (st) return st;
       if (rep && rep->small_path_host && it - 1 < h->opt.max_outer) rep->small_path_host[it - 1] = h->last_path;
@@ -1227,7 +1264,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
       // too far off for the structured solver's shifts: the first correction goes dense directly
       double mn = 1e300;
       for (int j = 0; j < k; ++j) mn = std::min(mn, res[j]);
-      h->try_fast = !(it == 0 && mn > 1e-2);
+      h->try_fast = !(it == 0 && mn > 1e-2 && h->opt.start == 0);
     }
     if (locking) {
       // the next correction's fine solves: wanted pairs with res > tol / 10 and guard pairs with

@@ -396,21 +396,11 @@ __global__ __launch_bounds__(kRT) void srr_kernel(int nH, int k, const double* _
   }
 }
 
-// Acceptance of the fast path (one workgroup).  Sorts the Rayleigh quotients,
-// requires every residual <= tol_abs and finite values, then counts the
-// eigenvalues of Tt below mu* = lambda_max + gap by inertia: #{theta_j < mu*}
-// plus the negative pivots of an LDL^T of S(mu*) (no pivoting; a tiny pivot or
-// element growth makes the count untrusted and rejects the block).  On success
-// writes lam (ascending), perm (column of Vt for each output position) and
-// status[0] = 1; otherwise status[0] = 0.  status[1] = the count (0 if not reached).
-__global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, const double* __restrict__ theta,
-                                                    const double* __restrict__ Gt, const double* __restrict__ Hm,
-                                                    const double* __restrict__ rq, const double* __restrict__ res,
-                                                    double tol_abs, const double* __restrict__ tolv, double gap,
-                                                    double* __restrict__ lam, int* __restrict__ perm,
-                                                    int* __restrict__ status) {
-  __shared__ RLds L;
-  __shared__ double srt[kSK];
+// Eigenvalues of Tt below mu by Sylvester's law of inertia: #{theta_j < mu} plus the negative
+// pivots of an LDL^T of S(mu) without pivoting.  *trusted = false when a pivot is tiny or the
+// factor grows (the count is then not certain).  Every thread gets the result.
+__device__ int inertia_r(int nH, int k, const double* g, double th, const double* __restrict__ Hm, double mu,
+                         RLds& L, bool* trusted) {
   __shared__ int ok_s, neg_s, cth_s;
   __shared__ double amax_s;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -419,36 +409,8 @@ __global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, const doubl
     neg_s = 0;
     cth_s = 0;
   }
-  __syncthreads();
-  if (wave == 0) {
-    const double v = (lane < k) ? rq[lane] : DBL_MAX;
-    const double e = (lane < k) ? res[lane] : 0.0;
-    int rank = 0;
-    for (int j = 0; j < k; ++j) {
-      const double vj = __shfl(v, j, 64);
-      rank += (vj < v || (vj == v && j < lane)) ? 1 : 0;
-    }
-    // tolerance of the pair at this position of the ascending order (per position, or one for all)
-    const double tl = (tolv && lane < k) ? tol_abs * tolv[(rank < k) ? rank : k - 1] : tol_abs;
-    const bool good = (lane >= k) || (v == v && e == e && fabs(v) < DBL_MAX && e <= tl);
-    if (lane < k) {
-      srt[rank] = v;
-      perm[rank] = lane;
-    }
-    const unsigned long long bad = __ballot(!good);
-    if (lane == 0 && bad) ok_s = 0;
-  }
-  __syncthreads();
-  if (!ok_s) {
-    if (tid == 0) status[0] = 0;
-    return;
-  }
-  const double mus = srt[k - 1] + gap;
-  double g[kSK];
-  load_row(nH, k, Gt, g);
-  const double th = (tid < nH) ? theta[tid] : 0.0;
-  const double dv = (tid < nH) ? 1.0 / (th - mus) : 0.0;
-  form_schur_r(nH, k, g, dv, Hm, mus, L);
+  const double dv = (tid < nH) ? 1.0 / (th - mu) : 0.0;
+  form_schur_r(nH, k, g, dv, Hm, mu, L);
   if (wave == 0) {
     double m = 0.0;
     for (int r = 0; r < k; ++r)
@@ -459,7 +421,6 @@ __global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, const doubl
   }
   __syncthreads();
   const double amax = amax_s;
-  // LDL^T without pivoting on the lower triangle, counting negative pivots
   const int tx = tid & 15, ty = tid >> 4;
   for (int j = 0; j < k; ++j) {
     const double d = L.S[j][j];
@@ -482,16 +443,105 @@ __global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, const doubl
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
     if (lane == 0 && !(m <= 1e6 * amax)) ok_s = 0;
   }
-  const int cth = (tid < nH && th < mus) ? 1 : 0;
+  const int cth = (tid < nH && th < mu) ? 1 : 0;
   const unsigned long long bl = __ballot(cth != 0);
   if (lane == 0) atomicAdd(&cth_s, __popcll(bl));
   __syncthreads();
+  const int count = cth_s + neg_s;
+  *trusted = ok_s != 0;
+  __syncthreads();
+  return count;
+}
+
+// Acceptance of the fast path (one workgroup).  Sorts the Rayleigh quotients,
+// requires every residual <= tol_abs and finite values, then counts the
+// eigenvalues of Tt below mu* = lambda_max + gap by inertia; the count must be k.
+// When it is not and the block carries guard pairs (nev < k), a count of nev below the
+// nev-th Rayleigh quotient + gap still certifies the wanted pairs as the nev smallest
+// (status[0] = 2: the guard pairs are eigenpairs of Tt, not certified as the next ones).
+// Writes lam (ascending) and perm (column of Vt for each output position);
+// status[0] = 0 rejects; status[1] = the last count (0 if not reached).
+__global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, int nev, const double* __restrict__ theta,
+                                                    const double* __restrict__ Gt, const double* __restrict__ Hm,
+                                                    const double* __restrict__ rq, const double* __restrict__ res,
+                                                    double tol_abs, const double* __restrict__ tolv, double gap,
+                                                    double* __restrict__ lam, int* __restrict__ perm,
+                                                    int* __restrict__ status) {
+  __shared__ RLds L;
+  __shared__ double srt[kSK];
+  __shared__ int ok_s;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) ok_s = 1;
+  __syncthreads();
+  if (wave == 0) {
+    const double v = (lane < k) ? rq[lane] : DBL_MAX;
+    const double e = (lane < k) ? res[lane] : 0.0;
+    int rank = 0;
+    for (int j = 0; j < k; ++j) {
+      const double vj = __shfl(v, j, 64);
+      rank += (vj < v || (vj == v && j < lane)) ? 1 : 0;
+    }
+    // tolerance of the pair at this position of the ascending order (per position, or one for all)
+    const double tl = (tolv && lane < k) ? tol_abs * tolv[(rank < k) ? rank : k - 1] : tol_abs;
+    const bool good = (lane >= k) || (v == v && e == e && fabs(v) < DBL_MAX && e <= tl);
+    if (lane < k) {
+      srt[rank] = v;
+      perm[rank] = lane;
+    }
+    const unsigned long long bad = __ballot(!good);
+    if (lane == 0 && bad) ok_s = 0;
+  }
+  __syncthreads();
+  for (int j = tid; j < k; j += kRT) lam[j] = srt[j];
+  if (!ok_s) {
+    if (tid == 0) {
+      status[0] = 0;
+      status[1] = 0;
+    }
+    return;
+  }
+  double g[kSK];
+  load_row(nH, k, Gt, g);
+  const double th = (tid < nH) ? theta[tid] : 0.0;
+  bool trusted = false;
+  int count = inertia_r(nH, k, g, th, Hm, srt[k - 1] + gap, L, &trusted);
+  int verdict = (trusted && count == k) ? 1 : 0;
+  if (!verdict && nev < k) {
+    count = inertia_r(nH, k, g, th, Hm, srt[nev - 1] + gap, L, &trusted);
+    verdict = (trusted && count == nev) ? 2 : 0;
+  }
   if (tid == 0) {
-    const int count = cth_s + neg_s;
-    status[0] = (ok_s && count == k) ? 1 : 0;
+    status[0] = verdict;
     status[1] = count;
   }
-  for (int j = tid; j < k; j += kRT) lam[j] = srt[j];
+}
+
+// Tr ((m + k) x (m + k)) = the principal block of Tt on its first m coarse modes and the k
+// W-directions: [[diag(theta[0:m]), Gt[0:m, :]], [Gt[0:m, :]^T, H]].
+__global__ void principal_kernel(int m, int k, const double* __restrict__ theta, const double* __restrict__ Gt,
+                                 const double* __restrict__ Hm, double* __restrict__ Tr) {
+  const int n = m + k;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * n) return;
+  const int i = q / n, j = q - (q / n) * n;
+  double v;
+  if (i < m && j < m) v = (i == j) ? theta[i] : 0.0;
+  else if (i < m) v = Gt[(size_t)i * k + (j - m)];
+  else if (j < m) v = Gt[(size_t)j * k + (i - m)];
+  else v = Hm[(size_t)(i - m) * k + (j - m)];
+  Tr[q] = v;
+}
+
+// X0 ((nH + k) x k) from the principal block's eigenvectors Vr ((m + k) x k): coarse rows 0..m-1,
+// zeros for the coarse modes m..nH-1, then the k W-direction rows.
+__global__ void expand_kernel(int nH, int m, int k, const double* __restrict__ Vr, double* __restrict__ X0) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (long long)(nH + k) * k) return;
+  const int r = (int)(q / k), c = (int)(q - (q / k) * k);
+  double v = 0.0;
+  if (r < m) v = Vr[(size_t)r * k + c];
+  else if (r >= nH) v = Vr[(size_t)(r - nH + m) * k + c];
+  X0[q] = v;
 }
 
 // V (n x k row-major) from the orthonormal vector-major Vt, columns in the
@@ -519,10 +569,22 @@ void launch_small_rr(int nH, int k, const double* theta, const double* Gt, const
   srr_kernel<<<k, kRT, 0, s>>>(nH, k, theta, Gt, Hm, Vt, rq, res);
 }
 
-void launch_small_accept(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* rq,
-                         const double* res, double tol_abs, const double* tolv, double gap, double* lam, int* perm,
-                         int* status, hipStream_t s) {
-  saccept_kernel<<<1, kRT, 0, s>>>(nH, k, theta, Gt, Hm, rq, res, tol_abs, tolv, gap, lam, perm, status);
+void launch_small_accept(int nH, int k, int nev, const double* theta, const double* Gt, const double* Hm,
+                         const double* rq, const double* res, double tol_abs, const double* tolv, double gap,
+                         double* lam, int* perm, int* status, hipStream_t s) {
+  saccept_kernel<<<1, kRT, 0, s>>>(nH, k, nev, theta, Gt, Hm, rq, res, tol_abs, tolv, gap, lam, perm, status);
+}
+
+void launch_small_principal(int nH, int m, int k, const double* theta, const double* Gt, const double* Hm,
+                            double* Tr, hipStream_t s) {
+  (void)nH;
+  const int n = m + k;
+  principal_kernel<<<(unsigned)((n * n + kBlock - 1) / kBlock), kBlock, 0, s>>>(m, k, theta, Gt, Hm, Tr);
+}
+
+void launch_small_expand(int nH, int m, int k, const double* Vr, double* X0, hipStream_t s) {
+  const long long tot = (long long)(nH + k) * k;
+  expand_kernel<<<(unsigned)((tot + kBlock - 1) / kBlock), kBlock, 0, s>>>(nH, m, k, Vr, X0);
 }
 
 void launch_small_emit(int n, int k, const double* Vt, const int* perm, double* V, hipStream_t s) {

@@ -369,49 +369,19 @@ __global__ __launch_bounds__(kBT) void srr_big_kernel(int nH, int k, const doubl
   }
 }
 
-// Acceptance (one workgroup): ascending order of the Rayleigh quotients, every residual within
-// its tolerance, and the inertia count below mu* = max rq + gap equal to k (LDL^T of S(mu*)
-// without pivoting; a tiny pivot or element growth makes the count untrusted and rejects).
-// status[0] = 1 on success, status[1] = the count; lam ascending, perm = source column.
-__global__ __launch_bounds__(kBT) void saccept_big_kernel(int nH, int k, const double* __restrict__ theta,
-                                                        const double* __restrict__ Gt,
-                                                        const double* __restrict__ Hm,
-                                                        const double* __restrict__ rq,
-                                                        const double* __restrict__ res, double tol_abs,
-                                                        const double* __restrict__ tolv, double gap,
-                                                        double* __restrict__ lam, int* __restrict__ perm,
-                                                        int* __restrict__ status) {
-  __shared__ BLds L;
-  __shared__ double srt[kBK];
-  __shared__ int ok_s, neg_s, cth_s;
+// Number of eigenvalues of Tt below mu by Sylvester's law of inertia: #{theta_j < mu} plus the
+// negative pivots of an LDL^T of S(mu) without pivoting.  *trusted = false when a pivot is tiny
+// or the factor grows (the count is then not certain).  Every thread gets the result.
+__device__ int inertia_big(int nH, int k, const double* __restrict__ theta, const double* __restrict__ Gt,
+                           const double* __restrict__ Hm, double mu, BLds& L, bool* trusted) {
+  __shared__ int ok_s, neg_s;
   __shared__ double amax_s;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  form_schur_big(nH, k, Gt, theta, Hm, mu, L);
   if (tid == 0) {
     ok_s = 1;
     neg_s = 0;
-    cth_s = 0;
   }
-  __syncthreads();
-  if (tid < k) {
-    const double v = rq[tid], e = res[tid];
-    int rank = 0;
-    for (int j = 0; j < k; ++j) {
-      const double vj = rq[j];
-      rank += (vj < v || (vj == v && j < tid)) ? 1 : 0;
-    }
-    const double tl = tolv ? tol_abs * tolv[(rank < k) ? rank : k - 1] : tol_abs;
-    const bool good = (v == v && e == e && fabs(v) < DBL_MAX && e <= tl);
-    srt[rank] = v;
-    perm[rank] = tid;
-    if (!good) ok_s = 0;
-  }
-  __syncthreads();
-  if (!ok_s) {
-    if (tid == 0) status[0] = 0;
-    return;
-  }
-  const double mus = srt[k - 1] + gap;
-  form_schur_big(nH, k, Gt, theta, Hm, mus, L);
   if (wave == 0) {
     double m = 0.0;
     for (int r = 0; r < k; ++r) {
@@ -449,15 +419,67 @@ __global__ __launch_bounds__(kBT) void saccept_big_kernel(int nH, int k, const d
     if (lane == 0 && !(m <= 1e6 * amax)) ok_s = 0;
   }
   int cth = 0;
-  for (int r = tid; r < nH; r += kBT) cth += (theta[r] < mus) ? 1 : 0;
+  for (int r = tid; r < nH; r += kBT) cth += (theta[r] < mu) ? 1 : 0;
   cth = (int)bsum((double)cth, L.red);
+  const int count = cth + neg_s;
+  *trusted = ok_s != 0;
   __syncthreads();
+  return count;
+}
+
+// Acceptance (one workgroup): ascending order of the Rayleigh quotients, every residual within
+// its tolerance, and the inertia count below mu* = (largest Rayleigh quotient) + gap equal to k.
+// When that count fails and the block carries guard pairs (nev < k), the count below the nev-th
+// Rayleigh quotient + gap equal to nev still certifies the wanted pairs as the nev smallest
+// (status[0] = 2: the guard pairs are then eigenpairs of Tt but not certified as the next ones).
+// status[0] = 0 rejects; status[1] = the last count.  lam ascending, perm = source column.
+__global__ __launch_bounds__(kBT) void saccept_big_kernel(int nH, int k, int nev, const double* __restrict__ theta,
+                                                        const double* __restrict__ Gt,
+                                                        const double* __restrict__ Hm,
+                                                        const double* __restrict__ rq,
+                                                        const double* __restrict__ res, double tol_abs,
+                                                        const double* __restrict__ tolv, double gap,
+                                                        double* __restrict__ lam, int* __restrict__ perm,
+                                                        int* __restrict__ status) {
+  __shared__ BLds L;
+  __shared__ double srt[kBK];
+  __shared__ int ok_s;
+  const int tid = threadIdx.x;
+  if (tid == 0) ok_s = 1;
+  __syncthreads();
+  if (tid < k) {
+    const double v = rq[tid], e = res[tid];
+    int rank = 0;
+    for (int j = 0; j < k; ++j) {
+      const double vj = rq[j];
+      rank += (vj < v || (vj == v && j < tid)) ? 1 : 0;
+    }
+    const double tl = tolv ? tol_abs * tolv[(rank < k) ? rank : k - 1] : tol_abs;
+    const bool good = (v == v && e == e && fabs(v) < DBL_MAX && e <= tl);
+    srt[rank] = v;
+    perm[rank] = tid;
+    if (!good) ok_s = 0;
+  }
+  __syncthreads();
+  for (int j = tid; j < k; j += kBT) lam[j] = srt[j];
+  if (!ok_s) {
+    if (tid == 0) {
+      status[0] = 0;
+      status[1] = 0;
+    }
+    return;
+  }
+  bool trusted = false;
+  int count = inertia_big(nH, k, theta, Gt, Hm, srt[k - 1] + gap, L, &trusted);
+  int verdict = (trusted && count == k) ? 1 : 0;
+  if (!verdict && nev < k) {
+    count = inertia_big(nH, k, theta, Gt, Hm, srt[nev - 1] + gap, L, &trusted);
+    verdict = (trusted && count == nev) ? 2 : 0;
+  }
   if (tid == 0) {
-    const int count = cth + neg_s;
-    status[0] = (ok_s && count == k) ? 1 : 0;
+    status[0] = verdict;
     status[1] = count;
   }
-  for (int j = tid; j < k; j += kBT) lam[j] = srt[j];
 }
 
 }  // namespace
@@ -477,10 +499,10 @@ void launch_small_rr_big(int nH, int k, const double* theta, const double* Gt, c
   srr_big_kernel<<<k, kBT, 0, s>>>(nH, k, theta, Gt, Hm, Vt, rq, res, scratch);
 }
 
-void launch_small_accept_big(int nH, int k, const double* theta, const double* Gt, const double* Hm,
+void launch_small_accept_big(int nH, int k, int nev, const double* theta, const double* Gt, const double* Hm,
                              const double* rq, const double* res, double tol_abs, const double* tolv, double gap,
                              double* lam, int* perm, int* status, hipStream_t s) {
-  saccept_big_kernel<<<1, kBT, 0, s>>>(nH, k, theta, Gt, Hm, rq, res, tol_abs, tolv, gap, lam, perm, status);
+  saccept_big_kernel<<<1, kBT, 0, s>>>(nH, k, nev, theta, Gt, Hm, rq, res, tol_abs, tolv, gap, lam, perm, status);
 }
 
 }  // namespace pase
