@@ -192,7 +192,7 @@ pase_status pase_prolong(pase_handle* h, int k, const double* Xc, double* Xf);
 /* G = X^T Y for N x k node-major X, Y (G: k x k row-major, device).  N <= N_0. */
 pase_status pase_gram(pase_handle* h, long long N, int k, const double* X, const double* Y, double* G);
 
-/* G = X^T Y (k x k, device, FP64) of FP32 operands X, Y (N x k row-major, device), k <= 64, the
+/* G = X^T Y (k x k, device, FP64) of FP32 operands X, Y (N x k row-major, device), k <= 128, the
  * projection Gram of the mixed form's first phase (extension (1) of the method: low-precision
  * projection, FP64 Rayleigh-Ritz).  Each value is split x = x_hi + x_lo into two BF16 numbers; a
  * product is x_hi y_hi + x_hi y_lo + x_lo y_hi on BF16 MFMA with FP32 accumulation over blocks of

@@ -144,13 +144,18 @@ class Result:
 
 
 def solve(hier: Hierarchy, nev, tol, U0=None, s=2, max_outer=500, post_smooth=False,
-          coarse_init=False, callback=None) -> Result:
+          coarse_init=False, callback=None, guard=0) -> Result:
     """Run the augmented subspace method until every pair meets ``tol``.
 
-    ``U0``: N x nev start (seeded, see ``synth``), ignored with coarse_init.
+    ``U0``: N x (nev + guard) start (seeded, see ``synth``), ignored with coarse_init.
     ``max_outer``: number of corrections allowed; the residual test is made
     before each correction and once more at the end.
+    ``guard`` (reading; the algorithms iterate exactly nev vectors): the block
+    carries nev + guard pairs, every step treats them alike, and only the nev
+    smallest decide convergence and are returned.
     """
+    want = nev
+    nev = nev + guard
     A, M, P = hier.A[0], hier.M[0], hier.Pc
     if coarse_init:
         # Alg. 3 steps 1-2: coarse eigenpairs, interpolated
@@ -168,8 +173,8 @@ def solve(hier: Hierarchy, nev, tol, U0=None, s=2, max_outer=500, post_smooth=Fa
     while True:
         res, lit, _, MU = residuals(A, M, U, lam)
         out.res_history.append(res.copy())
-        if np.all(res <= tol) or it >= max_outer:
-            out.converged = bool(np.all(res <= tol))
+        if np.all(res[:want] <= tol) or it >= max_outer:
+            out.converged = bool(np.all(res[:want] <= tol))
             break
         # step 3: fine solves A w = M u lambda, x0 = u
         W = pcg(hier, MU * lam[None, :], U, s)
@@ -187,9 +192,9 @@ def solve(hier: Hierarchy, nev, tol, U0=None, s=2, max_outer=500, post_smooth=Fa
         out.ritz_history.append(lam.copy())
         if callback is not None:
             callback(it, lam, U)
-    out.lam = lam
-    out.U = U
+    out.lam = lam[:want]
+    out.U = U[:, :want]
     out.iters = it
-    out.res = res
-    out.res_literal = lit
+    out.res = res[:want]
+    out.res_literal = lit[:want]
     return out

@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kSymThreads) void gram_sym_kernel(long long N, int 
   }
 }
 
-// ---- split-BF16 Gram of FP32 operands: G_y = X^T Y_y (NY = 1 or 2, k <= 64) on
+// ---- split-BF16 Gram of FP32 operands: G_y = X^T Y_y (NY = 1 or 2, k <= KMAX = 64 or 128) on
 // v_mfma_f32_16x16x32_bf16.  Each FP32 value is split as x = x_hi + x_lo with x_hi = bf16(x) and
 // x_lo = bf16(x - x_hi); a product is formed as x_hi y_hi + x_hi y_lo + x_lo y_hi (the dropped
 // x_lo y_lo is below 2^-16 |x y|).  The three MFMAs accumulate in FP32 over a K-block of 256 rows,
@@ -490,41 +490,46 @@ __global__ __launch_bounds__(kSymThreads) void gram_sym_kernel(long long N, int 
 // contiguous run of 32 k floats, loaded with coalesced accesses and stored split and transposed in
 // LDS ([column][row], so a lane's 8 consecutive rows are one 16-byte read).  Operand layout of the
 // instruction: lane l supplies A[l%16][8(l/16) .. +7] and B[8(l/16) .. +7][l%16]; accumulator
-// register q holds D[4(l/16) + q][l%16].
+// register q holds D[4(l/16) + q][l%16].  KMAX = 64: four waves, four 16 x 16 tiles each; KMAX = 128:
+// eight waves, eight tiles each.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 constexpr int kG3Rows = 32;                    // rows per chunk = K of one MFMA
 constexpr int kG3Rs = kG3Rows + 8;             // LDS row stride of a column (bf16 elements)
 constexpr int kG3Flush = 8;                    // chunks per FP32 K-block (256 rows)
-constexpr int kG3SE = kG3Rows * 64 / kBlock;   // staged values per thread per operand
 
-template <int NY>
-__global__ __launch_bounds__(kBlock) void gram_bf16x3_kernel(long long N, int k, const float* __restrict__ X,
-                                                             const float* __restrict__ Y1,
-                                                             const float* __restrict__ Y2,
-                                                             double* __restrict__ partial, int tiles, long long rows) {
-  // [operand (X, Y1, Y2)][hi, lo][column 0..63][row]
-  __shared__ __align__(16) __bf16 st[1 + NY][2][64 * kG3Rs];
+template <int NY, int KMAX>
+__global__ __launch_bounds__(KMAX * 4) void gram_bf16x3_kernel(long long N, int k, const float* __restrict__ X,
+                                                               const float* __restrict__ Y1,
+                                                               const float* __restrict__ Y2,
+                                                               double* __restrict__ partial, int tiles,
+                                                               long long rows) {
+  constexpr int NT = KMAX * 4;                          // threads
+  constexpr int NW = NT / 64;                           // waves
+  constexpr int TPW = (KMAX / 16) * (KMAX / 16) / NW;   // tiles per wave
+  constexpr int kG3SE = kG3Rows * KMAX / NT;            // staged values per thread per operand
+  // [operand (X, Y1, Y2)][hi, lo][column 0..KMAX-1][row]
+  __shared__ __align__(16) __bf16 st[1 + NY][2][KMAX * kG3Rs];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= tiles) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int T = (k + 15) >> 4, TT = T * T;
-  for (int e = tid; e < (1 + NY) * 2 * 64 * kG3Rs; e += kBlock) (&st[0][0][0])[e] = (__bf16)0.0f;
+  for (int e = tid; e < (1 + NY) * 2 * KMAX * kG3Rs; e += NT) (&st[0][0][0])[e] = (__bf16)0.0f;
   const long long r0 = (long long)tile * rows;
   const long long r1 = (r0 + rows < N) ? (r0 + rows) : N;
   const int ck = kG3Rows * k;
   int soff[kG3SE];   // LDS slot (column * kG3Rs + row) of each staged value; independent of the chunk
 #pragma unroll
   for (int u = 0; u < kG3SE; ++u) {
-    const int e = tid + kBlock * u;
+    const int e = tid + NT * u;
     const int r = e / k;
     soff[u] = (e < ck) ? (e - r * k) * kG3Rs + r : -1;
   }
-  float4_t acc1[4], acc2[4];
-  double4_t dacc1[4], dacc2[4];
+  float4_t acc1[TPW], acc2[TPW];
+  double4_t dacc1[TPW], dacc2[TPW];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < TPW; ++t) {
     acc1[t] = acc2[t] = (float4_t){0.f, 0.f, 0.f, 0.f};
     dacc1[t] = dacc2[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
   }
@@ -536,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void gram_bf16x3_kernel(long long N, int k,
     float v[1 + NY][kG3SE];
 #pragma unroll
     for (int u = 0; u < kG3SE; ++u) {   // clamped, unconditional loads: all in flight together
-      const int e = tid + kBlock * u;
+      const int e = tid + NT * u;
       const long long ec = rc * k + ((e < nval) ? e : nval - 1);
       v[0][u] = X[ec];
       v[1][u] = Y1[ec];
@@ -545,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void gram_bf16x3_kernel(long long N, int k,
     __syncthreads();   // the previous chunk's operands have been read
 #pragma unroll
     for (int u = 0; u < kG3SE; ++u) {
-      const int e = tid + kBlock * u;
+      const int e = tid + NT * u;
       if (soff[u] >= 0) {
 #pragma unroll
         for (int m = 0; m < 1 + NY; ++m) {
@@ -558,8 +563,8 @@ __global__ __launch_bounds__(kBlock) void gram_bf16x3_kernel(long long N, int k,
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int tt = wave + 4 * t;
+    for (int t = 0; t < TPW; ++t) {
+      const int tt = wave + NW * t;
       if (tt < TT) {
         const int ti = tt / T, tj = tt - (tt / T) * T;
         const int ca = (16 * ti + li) * kG3Rs + 8 * g, cb = (16 * tj + li) * kG3Rs + 8 * g;
@@ -579,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void gram_bf16x3_kernel(long long N, int k,
     if (++nchunk == kG3Flush) {   // end of a K-block: FP32 sums into the FP64 accumulators
       nchunk = 0;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TPW; ++t) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           dacc1[t][q] += (double)acc1[t][q];
@@ -590,7 +595,7 @@ __global__ __launch_bounds__(kBlock) void gram_bf16x3_kernel(long long N, int k,
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TPW; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       dacc1[t][q] += (double)acc1[t][q];
@@ -600,8 +605,8 @@ __global__ __launch_bounds__(kBlock) void gram_bf16x3_kernel(long long N, int k,
   for (int y = 0; y < NY; ++y) {
     double* p = partial + ((size_t)y * tiles + tile) * k * k;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int tt = wave + 4 * t;
+    for (int t = 0; t < TPW; ++t) {
+      const int tt = wave + NW * t;
       if (tt < TT) {
         const int ti = tt / T, tj = tt - (tt / T) * T;
         const int j = 16 * tj + li;
@@ -1031,8 +1036,18 @@ void launch_gram_bf16x3(long long N, int k, const float* X, const float* Y1, con
   long long rows = (N + tiles - 1) / tiles;
   rows = ((rows + 3) / 4) * 4;
   const int blocks = ((tiles + 7) / 8) * 8;
-  if (Y2) gram_bf16x3_kernel<2><<<blocks, kBlock, 0, s>>>(N, k, X, Y1, Y2, partial, tiles, rows);
-  else gram_bf16x3_kernel<1><<<blocks, kBlock, 0, s>>>(N, k, X, Y1, nullptr, partial, tiles, rows);
+  if (k <= 64) {
+    if (Y2) gram_bf16x3_kernel<2, 64><<<blocks, 256, 0, s>>>(N, k, X, Y1, Y2, partial, tiles, rows);
+    else gram_bf16x3_kernel<1, 64><<<blocks, 256, 0, s>>>(N, k, X, Y1, nullptr, partial, tiles, rows);
+  } else if (k <= 128) {
+    // one right-hand block per pass (two would not fit the accumulators in registers)
+    gram_bf16x3_kernel<1, 128><<<blocks, 512, 0, s>>>(N, k, X, Y1, nullptr, partial, tiles, rows);
+    if (Y2)
+      gram_bf16x3_kernel<1, 128><<<blocks, 512, 0, s>>>(N, k, X, Y2, nullptr, partial + (size_t)tiles * k * k, tiles,
+                                                        rows);
+  } else {
+    return;   // callers keep k <= 128
+  }
   reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial, G1);
   if (Y2) reduce_partials_kernel<<<k * k, kBlock, 0, s>>>(tiles, k * k, partial + (size_t)tiles * k * k, G2);
 }

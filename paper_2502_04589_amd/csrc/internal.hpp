@@ -147,7 +147,8 @@ void launch_gemm_f32(bool ta, bool tb, int M, int N, int K, double alpha, const 
                      int ldb, double beta, float* C, int ldc, hipStream_t s);
 void launch_d2f(size_t n, const double* a, float* b, hipStream_t s);
 void launch_f2d(size_t n, const float* a, double* b, hipStream_t s);
-// G1 = X^T Y1 (and G2 = X^T Y2) of FP32 operands, split-BF16 products on MFMA, k <= 64
+// G1 = X^T Y1 (and G2 = X^T Y2) of FP32 operands, split-BF16 products on MFMA, k <= 128 (nothing is
+// launched for larger k)
 void launch_gram_bf16x3(long long N, int k, const float* X, const float* Y1, const float* Y2, double* partial,
                         int tiles, double* G1, double* G2, hipStream_t s);
 void launch_add_f2d(size_t n, const double* u, const float* e, double* w, hipStream_t s);

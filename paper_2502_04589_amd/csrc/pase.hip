@@ -1110,7 +1110,7 @@ pase_status pase_gram(pase_handle* h, long long N, int k, const double* X, const
 pase_status pase_gram_bf16x3(pase_handle* h, long long N, int k, const float* X, const float* Y, double* G) {
   pase_status st = check_k(h, k);
   if (st) return st;
-  if (k > 64) return fail(h, PASE_E_ARG, "the split-BF16 Gram needs k <= 64");
+  if (k > 128) return fail(h, PASE_E_ARG, "the split-BF16 Gram needs k <= 128");
   if (!X || !Y || !G || N < 1 || N > h->lev[0].N) return fail(h, PASE_E_ARG, "bad Gram arguments");
   launch_gram_bf16x3(N, k, X, Y, nullptr, h->partial, gram_tiles(N, k), G, nullptr, h->stream);
   HIPC(hipGetLastError());
@@ -1184,7 +1184,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   HIPC(hipMemsetAsync(h->info, 0, 16 * sizeof(int), s));
   h->fast_hits = 0;
   h->fallbacks = 0;
-  h->proj_lp = (h->opt.precision == PASE_PREC_MIXED && k <= 64);
+  h->proj_lp = (h->opt.precision == PASE_PREC_MIXED && k <= 128);   // the split-BF16 Gram's limit
   h->proj_lp_iters = 0;
   h->ka = 0;
   h->fine_cols = 0;

@@ -204,7 +204,7 @@ class Solver:
         return G
 
     def gram_bf16x3(self, X, Y):
-        """X^T Y of float32 N x k blocks (k <= 64) by split-BF16 products, FP64 result."""
+        """X^T Y of float32 N x k blocks (k <= 128) by split-BF16 products, FP64 result."""
         N, k = X.shape
         X = self._mv(X, N, k, "X", torch.float32)
         Y = self._mv(Y, N, k, "Y", torch.float32)

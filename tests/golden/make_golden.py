@@ -25,8 +25,9 @@ from oracle import reference  # noqa: E402
 CASES = {
     # the large coarse space path: 64^3 fine mesh, V_H = 16^3 (N_H = 3375), 120 pairs of a kappa field
     "kappa3d_64_s21_k120": (3, 64, 120, 21),
-    # the same mesh with kappa = 1 (closed form available too)
+    # 32^3 fine mesh with the same 16^3 coarse space: 40 and 120 pairs of a kappa field
     "kappa3d_32_s5_k40": (3, 32, 40, 5),
+    "kappa3d_32_s7_k120": (3, 32, 120, 7),
 }
 
 

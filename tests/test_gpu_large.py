@@ -113,3 +113,22 @@ def test_coarse_3375_nev100_64cubed(precision, nev, rtol):
     _check_pairs(s, lam, U, kap, 3, n, 1e-9)
     print(f"  iters {rep['outer_iters']} structured {rep['small_fast_iters']} t {rep['t_solve_ms']:.0f} ms "
           f"lowprec {rep['lowprec_projection_iters']}", flush=True)
+
+
+@pytest.mark.parametrize("precision, rtol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_coarse_3375_nev100_32cubed(precision, rtol):
+    """32^3 fine mesh, V_H = 16^3 (N_H = 3375), kappa field, nev 100 with 28 guard pairs (block of 128,
+    the structured solver's and the split-BF16 Gram's largest k): every eigenvalue within 1e-10 (plain)
+    or 1e-8 (mixed) of the oracle's lowest eigenpairs of the assembled pencil."""
+    lam_ref, n, seed = golden("kappa3d_32_s7_k120")
+    kap = synth.kappa_field(3, n, seed)
+    nev = 100
+    print(f"32^3 N_H=3375 nev {nev} {precision}", flush=True)
+    s = Solver(3, [n, n // 2], kap, nev_max=nev, precision=precision, guard=28, start="coarse")
+    lam, U, rep = s.solve(nev, 1e-9, None)
+    np.testing.assert_allclose(lam, lam_ref[:nev], rtol=rtol)
+    _check_pairs(s, lam, U, kap, 3, n, 1e-9)
+    if precision == "mixed":
+        assert rep["lowprec_projection_iters"] > 0
+    print(f"  iters {rep['outer_iters']} structured {rep['small_fast_iters']} lowprec "
+          f"{rep['lowprec_projection_iters']}", flush=True)

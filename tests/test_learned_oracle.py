@@ -190,3 +190,85 @@ def test_training_reduces_the_loss():
         L, G = unet.loss_and_grad(net, W, R, C, logk)
         W = opt.step(W, G)
     assert unet.loss_and_grad(net, W, R, C, logk)[0] < 0.6 * L0
+
+
+# ---------------------------------------------------------------- wiring of the forward pass
+def _interp1d(nf, nc):
+    """1D linear interpolation from the nc - 1 interior nodes of a mesh of nc elements to the
+    nf - 1 interior nodes of the mesh of nf = 2 nc elements (written here, not taken from oracle)."""
+    P = np.zeros((nf - 1, nc - 1))
+    for j in range(nc - 1):
+        i = 2 * j + 1                     # fine index of coarse node j
+        P[i, j] = 1.0
+        P[i - 1, j] += 0.5
+        P[i + 1, j] += 0.5
+    return P
+
+
+def _interp3d(nf, nc):
+    p = _interp1d(nf, nc)
+    return np.kron(p, np.kron(p, p))      # x fastest: z (outer) x y x x (inner)
+
+
+def _centre_tap(S):
+    w = np.zeros((27,) + S.shape)
+    w[13] = S                             # offset (0, 0, 0)
+    return w
+
+
+def test_unet_forward_wiring_is_the_explicit_composition():
+    """UNet.forward pinned by weights that make it an explicit linear map: centre-tap convolutions
+    that mix channels by fixed non-negative matrices, on non-negative inputs (so every ReLU passes its
+    input through).  The expected output is the composition written out here with its own trilinear
+    interpolation: down by P^T, up by P, skips concatenated after the up-sampled channels, skips taken
+    from the second convolution of each encoder level.  Distinct coefficients on every path make a
+    swapped concatenation, a skip from the wrong tensor or an up/down mix-up change the result."""
+    n = 8
+    net = unet.UNet(n, channels=(2, 2, 2))
+    m0, m1, m2 = net.m
+    I2 = np.eye(2)
+    S = [np.array([[1.0, 0.0], [0.0, 1.0]]),          # 0: h0 = [r, q]
+         np.array([[2.0, 0.0], [0.0, 1.0]]),          # 1: e0 = [2 r, q]
+         np.array([[1.0, 0.0], [0.0, 0.0]]),          # 2: h1 = [d1_0, 0]
+         np.array([[3.0, 0.0], [0.0, 0.0]]),          # 3: e1 = [3 h1_0, 0]
+         np.array([[1.0, 0.0], [0.0, 0.0]]),          # 4: h2 = [d2_0, 0]
+         np.array([[2.0, 0.0], [0.0, 0.0]]),          # 5: e2 = [2 h2_0, 0]
+         np.array([[1.0, 0.0], [0.0, 0.0], [5.0, 0.0], [0.0, 0.0]]),   # 6: g1_0 = u1_0 + 5 e1_0
+         np.array([[4.0, 0.0], [0.0, 0.0]]),          # 7: f1 = [4 g1_0, 0]
+         np.array([[1.0, 0.0], [0.0, 0.0], [7.0, 0.0], [11.0, 0.0]]),  # 8: g0_0 = u0_0 + 7 e0_0 + 11 e0_1
+         I2 * 0.5,                                     # 9: f0 = g0 / 2
+         np.array([[1.0], [0.0]])]                     # 10: y = f0_0
+    W = [_centre_tap(s) for s in S]
+    rng = np.random.default_rng(5)
+    r = rng.uniform(0.1, 1.0, m0 ** 3)
+    q = rng.uniform(0.1, 1.0, m0 ** 3)
+    x = np.stack([r, q], axis=1)[None]
+    y, _ = net.forward(W, x)
+    P01, P12 = _interp3d(n, n // 2), _interp3d(n // 2, n // 4)
+    e0r, e0q = 2.0 * r, q
+    e1 = 3.0 * (P01.T @ e0r)
+    e2 = 2.0 * (P12.T @ e1)
+    f1 = 4.0 * (P12 @ e2 + 5.0 * e1)
+    g0 = P01 @ f1 + 7.0 * e0r + 11.0 * e0q
+    expect = 0.5 * g0
+    np.testing.assert_allclose(y[0, :, 0], expect, rtol=1e-13)
+
+
+def test_loss_value_is_the_per_column_definition():
+    """loss_and_grad's loss equals the mean over the columns of ||N(r_b) - c_b||^2 / ||c_b||^2 computed
+    column by column with apply (pins the normalisation by ||c||^2, the mean and the output scale)."""
+    n = 8
+    net = unet.UNet(n, channels=(2, 4, 4))
+    W = net.init(3)
+    rng = np.random.default_rng(6)
+    N = net.m[0] ** 3
+    R = rng.standard_normal((N, 3))
+    C = rng.standard_normal((N, 3))
+    logk = rng.standard_normal(N) * 0.3
+    sc = rng.uniform(0.5, 2.0, N)
+    L, _ = unet.loss_and_grad(net, W, R, C, logk, sc)
+    ref = 0.0
+    for b in range(3):
+        z = net.apply(W, R[:, b:b + 1], logk, sc)[:, 0]
+        ref += np.sum((z - C[:, b]) ** 2) / np.sum(C[:, b] ** 2)
+    assert abs(L - ref / 3) <= 1e-13 * ref

@@ -344,3 +344,32 @@ def test_kappa_field_statistics():
     assert abs(c - np.exp(-0.5)) < 0.15
     # seeded: same seed -> same field
     np.testing.assert_array_equal(synth.kappa_field(2, 16, 3), synth.kappa_field(2, 16, 3))
+
+
+def test_guard_pairs_reach_the_same_fixed_point():
+    """Guard pairs change the block, not the answer: the nev wanted pairs still match the closed
+    form (kappa = 1) and a dense generalized eigensolve (kappa field) of the assembled pencil."""
+    H = multigrid.Hierarchy(2, [16, 8, 4])
+    r = pase.solve(H, 4, 1e-11, synth.initial_vectors(15 ** 2, 7, seed=3), guard=3)
+    assert r.converged and r.lam.shape == (4,) and r.U.shape == (15 ** 2, 4)
+    np.testing.assert_allclose(r.lam, q1_laplace_eigs(2, 16, 4), rtol=1e-11)
+    kap = synth.kappa_field(3, 8, seed=4)
+    H = multigrid.Hierarchy(3, [8, 4], kap)
+    r = pase.solve(H, 5, 1e-11, synth.initial_vectors(7 ** 3, 8, seed=2), guard=3)
+    A, M = fem.assemble(3, 8, kap)
+    w = sla.eigh(A.toarray(), M.toarray(), eigvals_only=True)[:5]
+    np.testing.assert_allclose(r.lam, w, rtol=1e-10)
+
+
+def test_post_smoothing_option_reaches_the_dense_eigenpairs():
+    """Alg. 3 step 7 (post-smoothing solve, solve(post_smooth=True)) on an 8 x 8 mesh: the same fixed
+    point as the plain iteration, the k smallest eigenpairs of the dense generalized eigenproblem."""
+    H = multigrid.Hierarchy(2, [8, 4])
+    k = 4
+    r = pase.solve(H, k, 1e-12, synth.initial_vectors(49, k, seed=9), post_smooth=True)
+    assert r.converged
+    A, M = fem.assemble(2, 8)
+    w = sla.eigh(A.toarray(), M.toarray(), eigvals_only=True)[:k]
+    np.testing.assert_allclose(r.lam, w, rtol=1e-11)
+    np.testing.assert_allclose(r.lam, q1_laplace_eigs(2, 8, k), rtol=1e-11)
+    np.testing.assert_allclose(r.U.T @ (M @ r.U), np.eye(k), atol=1e-12)
