@@ -246,8 +246,8 @@ pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double*
  * channels {16, 32, 64} (the only set the kernels are built for); per level two 3x3x3
  * convolutions without bias, each followed by ReLU; full-weighting restriction down,
  * trilinear prolongation up, skip connections by channel concatenation, final 3x3x3
- * convolution to one channel.  Inputs: r / ||r||_2 and the node average of log kappa;
- * N(r) = ||r||_2 net(r / ||r||, log kappa).  BF16 weights and activations on MFMA with
+ * convolution to one channel.  Inputs: r / rho(r), rho(r) = ||r||_2 / sqrt(N_0) (the root mean
+ * square), and the node average of log kappa; N(r) = rho(r) net(r / rho(r), log kappa).  BF16 weights and activations on MFMA with
  * FP32 accumulation; FP32 master weights and Adam moments.
  *
  * Parameters: 11 FP32 tensors W_i[27][Cin][Cout] (offset o = 0..26 enumerates (dx, dy, dz)
@@ -276,7 +276,7 @@ pase_status pase_unet_apply(pase_unet* u, int batch, const double* R, const doub
 pase_status pase_unet_loss_grad(pase_unet* u, int batch, const double* R, const double* C, const double* logk,
                                 double* loss_host, float* G);
 /* Node-wise output scale s (device, N_0 values, caller-owned and kept alive while the network
- * uses it; NULL = 1): from now on N(R) = ||r|| s * net(r / ||r||, log kappa) in apply, loss_grad
+ * uses it; NULL = 1): from now on N(R) = rho(r) s * net(r / rho(r), log kappa) in apply, loss_grad
  * and fit_scale.  The learned form uses s = the inverse diagonal of A (pase_fine_diag_inverse). */
 pase_status pase_unet_set_output_scale(pase_unet* u, const double* scale);
 /* Output scale fit (done once before training): multiplies the weights of the three layers after

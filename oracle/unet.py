@@ -14,13 +14,13 @@ the readings taken here are:
   restriction P^T, up-sampling by trilinear prolongation P (the multigrid
   transfer operators), skip connections by channel concatenation, a final
   3x3x3 convolution to one channel.  Channels 16/32/64 by default.
-* Inputs: the residual scaled to unit 2-norm and the node average of log kappa
-  (mean over the 2^3 elements around a node; zero when kappa = 1).  With no
-  biases the network is positively homogeneous in its first channel only
-  through the scaling, so the output is rescaled by ||r||_2 and, node-wise, by
-  the inverse diagonal of A (D^-1 r is the Jacobi part of V(r) and carries its
-  1/kappa scaling, which the log kappa channel alone learns slowly):
-  N(r) = ||r|| D^-1 net(r / ||r||, log kappa).  The scale is an argument
+* Inputs: the residual divided by its root mean square rho(r) = ||r||_2 / sqrt(N)
+  (per-node values of order one, like the other channel) and the node average of
+  log kappa (mean over the 2^3 elements around a node; zero when kappa = 1).
+  The output is rescaled by rho(r), so N is positively homogeneous in r, and,
+  node-wise, by the inverse diagonal of A (D^-1 r is the Jacobi part of V(r) and
+  carries its 1/kappa scaling, which the log kappa channel alone learns slowly):
+  N(r) = rho(r) D^-1 net(r / rho(r), log kappa).  The scale is an argument
   (None = 1), so the network is also usable without it.
 * Loss: mean over the batch of ||N(r) - c||^2 / ||c||^2 with c = V(r) (one
   V-cycle from zero).
@@ -182,16 +182,16 @@ class UNet:
     # ------------------------------------------------------------ preconditioner use
 
     def inputs(self, R, logk):
-        """(N0, B) residual columns -> network input (B, N0, 2) and the column norms."""
-        nr = np.linalg.norm(R, axis=0)
+        """(N0, B) residual columns -> network input (B, N0, 2) and the columns' root mean squares."""
+        nr = np.linalg.norm(R, axis=0) / np.sqrt(R.shape[0])
         x = np.empty((R.shape[1], R.shape[0], 2))
         x[:, :, 0] = (R / np.where(nr > 0, nr, 1.0)).T
         x[:, :, 1] = logk[None, :]
         return x, nr
 
     def apply(self, W, R, logk, oscale=None):
-        """N(R) column by column: ||r|| s * net(r / ||r||, log kappa); R is (N0, B), s the
-        node-wise output scale (oscale, e.g. the inverse diagonal of A; None = 1)."""
+        """N(R) column by column: rho(r) s * net(r / rho(r), log kappa), rho(r) = ||r|| / sqrt(N0);
+        R is (N0, B), s the node-wise output scale (oscale, e.g. the inverse diagonal of A; None = 1)."""
         x, nr = self.inputs(R, logk)
         y, _ = self.forward(W, x)
         Z = y[:, :, 0].T * nr[None, :]

@@ -77,17 +77,27 @@ __device__ void form_schur_big(int nH, int k, const double* __restrict__ Gt, con
   double4_t acc[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
-  for (int r0 = 0; r0 < nH; r0 += 4) {
+  // the next step's row values are loaded while this step's MFMAs run (two waves per SIMD
+  // leave little else to hide the L2 latency)
+  double gn[8], thn;
+  auto fetch = [&](int r0) {
     const int row = r0 + lk;
-    const bool rok = row < nH;
-    const int rc = rok ? row : nH - 1;
-    const double dv = rok ? 1.0 / (theta[rc] - mu) : 0.0;
-    double g[8];
+    const int rc = (row < nH) ? row : nH - 1;
+    thn = theta[rc];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int col = 16 * c + li;
-      g[c] = (c < T && col < k && rok) ? Gt[(size_t)rc * k + col] : 0.0;
+      gn[c] = (c < T && col < k) ? Gt[(size_t)rc * k + col] : 0.0;
     }
+  };
+  fetch(0);
+  for (int r0 = 0; r0 < nH; r0 += 4) {
+    const bool rok = r0 + lk < nH;
+    const double dv = rok ? 1.0 / (thn - mu) : 0.0;
+    double g[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) g[c] = rok ? gn[c] : 0.0;
+    if (r0 + 4 < nH) fetch(r0 + 4);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int tt = wave + 8 * t;

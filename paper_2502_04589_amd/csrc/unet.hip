@@ -5,7 +5,7 @@
 // followed by ReLU; full-weighting restriction down, trilinear prolongation up
 // (the multigrid transfers), skips by channel concatenation, a final 3x3x3
 // convolution to one channel; inputs r / ||r|| and the node average of
-// log kappa; output scaled by ||r||.
+// log kappa; output scaled by the root mean square of r.
 //
 // Activations are BF16, node-major per batch item ([b][node][channel]).
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 with FP32
@@ -288,28 +288,29 @@ __global__ void up_kernel(int mf, int c, const __bf16* __restrict__ xc, __bf16* 
 }
 
 // ---------------------------------------------------------------- input / output
-// x[b][n][0] = r[n][b] / ||r_b||, x[b][n][1] = logk[n]; nrm[b] = ||r_b|| from the column sums s[b]
+// x[b][n][0] = r[n][b] / rms(r_b), x[b][n][1] = logk[n], rms(r_b) = ||r_b|| / sqrt(N) from the column
+// sums colsq[b] = ||r_b||^2 (a per-node size of order one, like the log kappa channel)
 __global__ void input_kernel(long long N, int k, const double* __restrict__ R, const double* __restrict__ logk,
                              const double* __restrict__ colsq, __bf16* __restrict__ x) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= N * k) return;
   const long long n = q / k;
   const int b = (int)(q % k);
-  const double s = sqrt(colsq[b]);
+  const double s = sqrt(colsq[b] / (double)N);
   const double r = (s > 0.0) ? R[q] / s : 0.0;
   __bf16* xb = x + ((size_t)b * N + n) * 2;
   xb[0] = (__bf16)(float)r;
   xb[1] = (__bf16)(float)(logk ? logk[n] : 0.0);
 }
 
-// Z[n][b] = ||r_b|| s[n] y[b][n] (s = node-wise output scale, NULL = 1)
+// Z[n][b] = rms(r_b) s[n] y[b][n] (s = node-wise output scale, NULL = 1)
 __global__ void output_kernel(long long N, int k, const float* __restrict__ y, const double* __restrict__ colsq,
                               const double* __restrict__ os, double* __restrict__ Z) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= N * k) return;
   const long long n = q / k;
   const int b = (int)(q % k);
-  Z[q] = sqrt(colsq[b]) * (os ? os[n] : 1.0) * (double)y[(size_t)b * N + n];
+  Z[q] = sqrt(colsq[b] / (double)N) * (os ? os[n] : 1.0) * (double)y[(size_t)b * N + n];
 }
 
 }  // namespace
@@ -481,7 +482,7 @@ __global__ void loss_err_kernel(long long N, int k, const float* __restrict__ y,
   if (q >= N * k) return;
   const long long n = q / k;
   const int b = (int)(q % k);
-  err[q] = sqrt(colsq[b]) * (os ? os[n] : 1.0) * (double)y[(size_t)b * N + n] - C[q];
+  err[q] = sqrt(colsq[b] / (double)N) * (os ? os[n] : 1.0) * (double)y[(size_t)b * N + n] - C[q];
 }
 
 // dL/dy[b][n] = 2 err[n][b] / den[b] / B * ||r_b|| s[n]
@@ -492,7 +493,7 @@ __global__ void loss_grad_kernel(long long N, int k, const double* __restrict__ 
   if (q >= N * k) return;
   const long long n = q / k;
   const int b = (int)(q % k);
-  gy[(size_t)b * N + n] = (float)(2.0 * err[q] / den[b] / k * sqrt(colsq[b]) * (os ? os[n] : 1.0));
+  gy[(size_t)b * N + n] = (float)(2.0 * err[q] / den[b] / k * sqrt(colsq[b] / (double)N) * (os ? os[n] : 1.0));
 }
 
 // ---------------------------------------------------------------- elementwise helpers

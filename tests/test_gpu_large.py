@@ -102,12 +102,12 @@ def test_coarse_3375_constant_kappa_closed_form():
 
 @pytest.mark.parametrize("precision, nev, rtol", [("fp64", 100, 1e-10), ("mixed", 100, 1e-8)])
 def test_coarse_3375_nev100_64cubed(precision, nev, rtol):
-    """64^3 fine mesh, V_H = 16^3 (N_H = 3375), kappa field, nev 100 (block of 112): the plain form within
+    """64^3 fine mesh, V_H = 16^3 (N_H = 3375), kappa field, nev 100 (block of 128): the plain form within
     1e-10 and the mixed form within 1e-8 of the oracle's eigenvalues."""
     lam_ref, n, seed = golden("kappa3d_64_s21_k120")
     kap = synth.kappa_field(3, n, seed)
     print(f"64^3 N_H=3375 nev {nev} {precision}", flush=True)
-    s = Solver(3, [n, n // 2, n // 4], kap, nev_max=nev, precision=precision, guard=12, start="coarse")
+    s = Solver(3, [n, n // 2, n // 4], kap, nev_max=nev, precision=precision, guard=28, start="coarse")
     lam, U, rep = s.solve(nev, 1e-9, None)
     np.testing.assert_allclose(lam, lam_ref[:nev], rtol=rtol)
     _check_pairs(s, lam, U, kap, 3, n, 1e-9)
