@@ -234,8 +234,10 @@ pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* 
  *   which = 1: fine-level fused A X, M X
  *   which = 2: Gram W^T (A W) on FP64 MFMA (including its fixed-order reduction)
  *   which = 3: one V-cycle (all levels)
- *   which = 4: one full correction (Alg. 3 steps 3-6)
- *   which = 5: the fused CG update x += alpha p, r -= alpha q (on scratch vectors) */
+ *   which = 5: the fused CG update x += alpha p, r -= alpha q (on scratch vectors)
+ *   which = 6: fine-level A X alone (the projection's SpMM)
+ *   which = 7: fine-level M X alone (the complement's SpMM)
+ * (which = 4 is not used) */
 pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double* ms);
 
 /* ---------------------------------------------------------------- learned preconditioner

@@ -42,6 +42,9 @@ enum Epi : int {
   EPI_SWEEPDOT = 5, // out1 = the sweep of EPI_SWEEP; partials of b.out1 per column (3D LDS-staged only)
   EPI_SWEEP2 = 6,   // out1 = two damped-Jacobi sweeps from x = 0 with x passed as b (constant
                     // coefficient, 3D LDS-staged only): x1 = c b, out = x1 + c (b - A x1), c = omega / a_ii
+  // 3D LDS-staged stencil only, chosen by launch_fine3 for EPI_AM with one output:
+  EPI_A = 7,        // out1 = A x
+  EPI_M = 8,        // out2 = M x (kappa-independent: staged planes are read once)
 };
 
 struct StencilArgs {

@@ -1388,7 +1388,7 @@ pase_status pase_node_logk(pase_handle* h, double* logk) {
 pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double* ms) {
   pase_status st = check_k(h, k);
   if (st) return st;
-  if (!ms || reps < 1 || which < 0 || which > 5 || which == 4) return fail(h, PASE_E_ARG, "bad timing arguments");
+  if (!ms || reps < 1 || which < 0 || which > 7 || which == 4) return fail(h, PASE_E_ARG, "bad timing arguments");
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   auto once = [&]() {
@@ -1398,6 +1398,8 @@ pase_status pase_time_kernel(pase_handle* h, int which, int k, int reps, double*
       case 2: launch_gram(N, k, h->U, h->W2, h->partial, gram_tiles(N, k), h->kk1, s); break;
       case 3: vcycle(h, 0, k, h->R, h->Z); break;
       case 5: launch_axpy2(N, k, h->alpha, h->P, h->Q, h->W2, h->W3, s); break;   // on scratch
+      case 6: apply_AM(h, 0, k, h->U, h->W2, nullptr); break;
+      case 7: apply_AM(h, 0, k, h->U, nullptr, h->W3); break;
     }
   };
   once();   // warm

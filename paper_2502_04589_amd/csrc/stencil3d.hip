@@ -30,13 +30,19 @@ void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s) {
     return;
   }
   switch (epi) {
-    case EPI_AM: launchv<double, EPI_AM>(a, s); break;
+    case EPI_AM:
+      if (a.out1 && a.out2) launchv<double, EPI_AM>(a, s);
+      else if (a.out1) launchv<double, EPI_A>(a, s);
+      else if (a.out2) launchv<double, EPI_M>(a, s);
+      break;
     case EPI_RESID: launchv<double, EPI_RESID>(a, s); break;
     case EPI_SWEEP: launchv<double, EPI_SWEEP>(a, s); break;
     case EPI_EIGRES: launchv<double, EPI_EIGRES>(a, s); break;
     case EPI_AMDOT: launchv<double, EPI_AMDOT>(a, s); break;
     case EPI_SWEEPDOT: launchv<double, EPI_SWEEPDOT>(a, s); break;
     case EPI_SWEEP2: launchv<double, EPI_SWEEP2>(a, s); break;
+    case EPI_A: launchv<double, EPI_A>(a, s); break;
+    case EPI_M: launchv<double, EPI_M>(a, s); break;
   }
 }
 

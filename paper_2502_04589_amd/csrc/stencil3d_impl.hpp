@@ -201,8 +201,9 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   const double h = a.h;
   const double k0 = 1.0 / h, k1 = -1.0 / h, m0 = 2.0 * h / 6.0, m1 = h / 6.0;
   const double mc = h / 6.0, mc3 = mc * mc * mc;
-  const bool needA = (EPI != EPI_AM) || a.out1;
-  const bool needM = (EPI == EPI_EIGRES) || (EPI == EPI_AM && a.out2);
+  // EPI_AM writes both A x and M x; EPI_A and EPI_M one of them
+  constexpr bool needA = (EPI != EPI_M);
+  constexpr bool needM = (EPI == EPI_EIGRES) || (EPI == EPI_AM) || (EPI == EPI_M);
 
   double kc[2][2][2];
   // prologue: planes z0-1, z0, z0+1 into slots 0, 1, 2; b(z0) then plane z0+2 in flight
@@ -359,8 +360,16 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     if (EPI == EPI_AM) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) { vset<T, VW>(o1, i, ax[i]); vset<T, VW>(o2, i, mx[i]); }
-      if (a.out1) stvec((T*)a.out1, off, o1);
-      if (a.out2) stvec((T*)a.out2, off, o2);
+      stvec((T*)a.out1, off, o1);
+      stvec((T*)a.out2, off, o2);
+    } else if (EPI == EPI_A) {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, ax[i]);
+      stvec((T*)a.out1, off, o1);
+    } else if (EPI == EPI_M) {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o2, i, mx[i]);
+      stvec((T*)a.out2, off, o2);
     } else if (EPI == EPI_RESID) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, vget<T, VW>(bv, i) - ax[i]);
@@ -475,7 +484,7 @@ void launchv_tile(const Fine3Args& a, hipStream_t s) {
 template <typename T, int VW, int EPI>
 void launchv_w(const Fine3Args& a, hipStream_t s) {
   const bool vec = (a.k % VW) == 0;
-  if (a.kappa) {
+  if (a.kappa && EPI != EPI_M) {     // M does not depend on kappa: the constant-coefficient path
     if (vec) launchv_tile<T, VW, EPI, false, true>(a, s);
     else launchv_tile<T, VW, EPI, false, false>(a, s);
   } else {

@@ -223,7 +223,7 @@ class Solver:
     def small_eig_max_n(self):
         return int(self.lib.pase_small_eig_max_n(self.h))
 
-    KERNELS = {"sweep": 0, "apply": 1, "gram": 2, "vcycle": 3, "correction": 4, "cg_update": 5}
+    KERNELS = {"sweep": 0, "apply": 1, "gram": 2, "vcycle": 3, "cg_update": 5, "apply_A": 6, "apply_M": 7}
 
     def time_kernel(self, name, k, reps=20):
         """Average device ms per launch of a hot-path kernel (HIP events on the solver's stream)."""
