@@ -202,6 +202,7 @@ def main():
                "outer_iters": rep["outer_iters"], "n_converged": rep["n_converged"], "setup_s": round(setup_s, 3),
                "max_res": float(np.max(rep["res"])), "block": nev + g, "locking": locking, "start": st,
                "fine_solve_columns": rep["fine_solve_columns"],
+               "device_ms_per_phase": {k_: round(v, 2) for k_, v in rep["t_phase_ms"].items()},
                "small_problem": {"structured": int(np.sum(paths >= 1)), "structured_wanted_pairs_only":
                                  int(np.sum(paths == 2)), "structured_after_retry": int(np.sum(paths == 3)),
                                  "dense": int(np.sum(paths <= 0))}}

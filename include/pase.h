@@ -48,6 +48,7 @@ extern "C" {
 #endif
 
 #define PASE_MAX_LEVELS 8
+#define PASE_PHASES 6            /* entries of pase_report.t_phase_ms */
 #define PASE_MAX_NEV 256
 
 typedef enum pase_status {
@@ -131,6 +132,17 @@ typedef struct pase_report {
                                     split-BF16 Grams (the rest ran in FP64) */
   int fine_solve_columns;        /* columns that ran the fine solves, summed over the corrections
                                     (nev x outer_iters without locking) */
+  double t_phase_ms[PASE_PHASES];/* device time per phase (HIP events on the handle's stream; the
+                                    stream's idle gaps while the host reads residuals are left out):
+                                    [0] start block (Alg. 3 steps 1-2: coarse start or the given
+                                    block, Cholesky-QR, Lambda0); [1] eigen-residuals and stop test
+                                    (Alg. 3 step 4); [2] fine solves (step 3: s CG steps per column
+                                    with the V-cycle, the network or the FP32 correction form);
+                                    [3] projection (the complement of W, A W, M W, the coarse
+                                    restriction of A W, the Grams alpha and beta, their Cholesky
+                                    factor and H); [4] the augmented eigenproblem (step 5:
+                                    structured path, retry and dense path); [5] prolongation (step 6:
+                                    u = P y_H + W y_W) */
 } pase_report;
 
 typedef struct pase_handle pase_handle;
@@ -270,6 +282,16 @@ const char* pase_unet_last_error(const pase_unet* u);
 /* W: device FP32 parameter vector (pase_unet_param_count entries); resets the Adam state. */
 pase_status pase_unet_set_weights(pase_unet* u, const float* W);
 pase_status pase_unet_get_weights(const pase_unet* u, float* W);
+/* Checkpoint of the training state; both calls synchronise the network's stream.
+ * pase_unet_save writes the FP32 weights, both Adam moments and the Adam step count, with the
+ * channel widths, to the host file `path` (a 64-byte header -- tag "PASEUNET",
+ * format version 1, the three widths, the parameter count P, the step count -- then 3 P FP32
+ * values, little-endian); pase_unet_load restores them into a network created with the same
+ * widths, so training resumes where it stopped (the next Adam step is step count + 1).  Errors:
+ * PASE_E_ARG for a null argument, a file that cannot be opened, read or written, a foreign or
+ * truncated file, or other widths (the network is then unchanged); PASE_E_HIP for copy failures. */
+pase_status pase_unet_save(pase_unet* u, const char* path);
+pase_status pase_unet_load(pase_unet* u, const char* path);
 /* Z = N(R), column by column. */
 pase_status pase_unet_apply(pase_unet* u, int batch, const double* R, const double* logk, double* Z);
 /* Loss L = mean_b ||N(r_b) - c_b||^2 / ||c_b||^2 (written to *loss_host if non-NULL, which

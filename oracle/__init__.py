@@ -17,6 +17,11 @@ eigensolver", arXiv 2502.04589) with NumPy/SciPy in float64:
                     composite matrices (eq. Definition_Hh), the augmented
                     eigenproblem (Alg. 3 steps 5-6) and the stopping rule
                     (Sec. 5, opening paragraph).
+* ``gcg_aug``    -- PRECOND-A (the block factorisation of eq.
+                    Transformation_0 and the pencil of eq. Eigen_Problem_Hh_2)
+                    and the GCG_AUG eigensolver of the augmented problem
+                    (Sec. 4, Alg. 4 and 5), used by ``pase.solve(small=
+                    "precond_a")`` with V_H on any level of the hierarchy.
 * ``reference``  -- the fixed point written out: the k smallest eigenpairs of
                     the assembled pencil by a library eigensolver (Alg. 3
                     "Ensure").
@@ -29,4 +34,4 @@ eigensolver", arXiv 2502.04589) with NumPy/SciPy in float64:
 Readings of points the paper leaves open are listed in the docstrings where
 they are taken.
 """
-from . import fem, multigrid, pase, reference, unet  # noqa: F401
+from . import fem, gcg_aug, multigrid, pase, reference, unet  # noqa: F401

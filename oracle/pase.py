@@ -34,6 +34,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
+from . import gcg_aug as gcg
 from .multigrid import Hierarchy
 
 
@@ -131,6 +132,33 @@ def small_solve_complement(hier: Hierarchy, W, k):
     return vals, P @ Y[:NH] + Wp @ Y[NH:]
 
 
+def interp_from(hier: Hierarchy, c):
+    """Composite interpolation I_H^h from level c to the fine level (product of P[1] .. P[c])."""
+    Pc = None
+    for l in range(1, c + 1):
+        Pc = hier.P[l] if Pc is None else (Pc @ hier.P[l]).tocsr()
+    return Pc
+
+
+def small_solve_precond_a(hier: Hierarchy, W, k, c, tol, s=2, max_iter=200, stall=4):
+    """Steps 4-6 with V_H = level c and the augmented problem solved by PRECOND-A and GCG_AUG
+    (Sec. 4, Alg. 5 with Alg. 4): the composite blocks of eq. (Definition_Hh) on level c, then
+    ``gcg_aug.solve_augmented`` (the coarse V-cycle below level c preconditions its linear
+    solves), then the prolongation u = I_H^h u_H + u_hat gamma.  Returns (vals, U_new, GcgResult)."""
+    A, M = hier.A[0], hier.M[0]
+    Pc = interp_from(hier, c)
+    AW = A @ W
+    MW = M @ W
+    a = Pc.T @ AW
+    b = Pc.T @ MW
+    alpha = 0.5 * (W.T @ AW + (W.T @ AW).T)
+    beta = 0.5 * (W.T @ MW + (W.T @ MW).T)
+    lam, uH, g, r = gcg.solve_augmented(hier.A[c], hier.M[c], a, alpha, b, beta, k, tol,
+                                        lambda R: hier.vcycle(R, l=c), s=s, max_iter=max_iter,
+                                        stall=stall)
+    return lam, Pc @ uH + W @ g, r
+
+
 class Result:
     def __init__(self):
         self.lam = None
@@ -141,10 +169,12 @@ class Result:
         self.res_literal = None
         self.ritz_history = []
         self.res_history = []
+        self.aug_iters = []          # GCG_AUG iterations per correction (small="precond_a")
 
 
 def solve(hier: Hierarchy, nev, tol, U0=None, s=2, max_outer=500, post_smooth=False,
-          coarse_init=False, callback=None, guard=0) -> Result:
+          coarse_init=False, callback=None, guard=0, small="dense", coarse_level=None,
+          aug_tol=1e-12, aug_s=2) -> Result:
     """Run the augmented subspace method until every pair meets ``tol``.
 
     ``U0``: N x (nev + guard) start (seeded, see ``synth``), ignored with coarse_init.
@@ -153,6 +183,12 @@ def solve(hier: Hierarchy, nev, tol, U0=None, s=2, max_outer=500, post_smooth=Fa
     ``guard`` (reading; the algorithms iterate exactly nev vectors): the block
     carries nev + guard pairs, every step treats them alike, and only the nev
     smallest decide convergence and are returned.
+    ``small``: "dense" solves the augmented problem of step 5 with V_H = the
+    coarsest level by a dense generalized eigensolver; "precond_a" takes
+    V_H = level ``coarse_level`` (default the coarsest) and solves it by
+    PRECOND-A and GCG_AUG (Sec. 4) to the relative residual ``aug_tol`` (a
+    scalar, or a function of the outer residuals giving one value per pair),
+    with ``aug_s`` CG steps in GCG_AUG's linear solves.
     """
     want = nev
     nev = nev + guard
@@ -179,10 +215,16 @@ def solve(hier: Hierarchy, nev, tol, U0=None, s=2, max_outer=500, post_smooth=Fa
         # step 3: fine solves A w = M u lambda, x0 = u
         W = pcg(hier, MU * lam[None, :], U, s)
         # steps 4-6
-        AHh, BHh = composite(hier, W)
-        lam, Y = small_solve(AHh, BHh, nev)
-        NH = AHh.shape[0] - nev
-        U = P @ Y[:NH] + W @ Y[NH:]
+        if small == "precond_a":
+            c = hier.L if coarse_level is None else coarse_level
+            tl = aug_tol(res) if callable(aug_tol) else aug_tol
+            lam, U, gr = small_solve_precond_a(hier, W, nev, c, tl, s=aug_s)
+            out.aug_iters.append(gr.iters)
+        else:
+            AHh, BHh = composite(hier, W)
+            lam, Y = small_solve(AHh, BHh, nev)
+            NH = AHh.shape[0] - nev
+            U = P @ Y[:NH] + W @ Y[NH:]
         if post_smooth:
             # step 7: A u = M u_hat Lambda from u_hat, then a Rayleigh quotient
             U = pcg(hier, (M @ U) * lam[None, :], U, s)

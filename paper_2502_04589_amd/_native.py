@@ -30,7 +30,11 @@ class Report(C.Structure):
                 ("res_literal_host", C.c_void_p), ("ritz_history_host", C.c_void_p),
                 ("ritz_history_rows", C.c_int), ("t_solve_ms", C.c_double), ("small_fast_iters", C.c_int),
                 ("small_path_host", C.c_void_p), ("learned_fallbacks", C.c_int),
-                ("lowprec_projection_iters", C.c_int), ("fine_solve_columns", C.c_int)]
+                ("lowprec_projection_iters", C.c_int), ("fine_solve_columns", C.c_int),
+                ("t_phase_ms", C.c_double * 6)]
+
+# names of pase_report.t_phase_ms's entries, in order
+PHASES = ("start", "residual", "fine_solves", "projection", "small_problem", "prolongation")
 
 
 # (name, restype, argtypes) for every entry point of include/pase.h
@@ -65,6 +69,8 @@ SIGNATURES = [
     ("pase_unet_last_error", C.c_char_p, [C.c_void_p]),
     ("pase_unet_set_weights", C.c_int, [C.c_void_p, C.c_void_p]),
     ("pase_unet_get_weights", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pase_unet_save", C.c_int, [C.c_void_p, C.c_char_p]),
+    ("pase_unet_load", C.c_int, [C.c_void_p, C.c_char_p]),
     ("pase_unet_apply", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pase_unet_loss_grad", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_double), C.c_void_p]),

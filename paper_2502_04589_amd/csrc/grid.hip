@@ -647,6 +647,8 @@ static void stencil_dispatch_epi(const StencilArgs& a, Epi epi, const GridLaunch
     case EPI_EIGRES:
       stencil_kernel<DIM, SRC, EPI_EIGRES, T><<<g.blocks, kBlock, 0, s>>>(a, g.slots, g.nb, g.tiles);
       break;
+    default:   // the fused-dot, two-sweep and single-output epilogues exist on the fine 3D path only
+      break;
   }
 }
 

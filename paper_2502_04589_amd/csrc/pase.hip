@@ -128,6 +128,15 @@ struct pase_handle {
   bool tolv_on = false;
   int fine_cols = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // per-phase device time of a solve: marks (event, phase) enqueued on the stream and resolved after
+  // each synchronisation of the outer loop; a mark of phase -1 opens an interval that is not counted
+  // (the stream idles while the host reads the residuals)
+  static constexpr int kMarks = 24;
+  hipEvent_t evm[kMarks] = {};
+  int mark_phase[kMarks] = {};
+  int nmark = 0;
+  bool timing = false;
+  double t_phase[PASE_PHASES] = {};
   // pinned host staging of the per-correction transfers (column sums, Ritz values, status words,
   // locking indices, acceptance factors): truly asynchronous copies, one synchronisation each
   void* pin = nullptr;
@@ -137,6 +146,33 @@ struct pase_handle {
 };
 
 namespace {
+
+// Phases of the per-phase timers (pase_report.t_phase_ms)
+enum Phase { PH_START = 0, PH_RESIDUAL = 1, PH_FINE = 2, PH_PROJECTION = 3, PH_SMALL = 4, PH_PROLONG = 5 };
+
+// Time from the previous mark on is charged to the previous mark's phase; nothing when not timing.
+// The outer loop settles every completed interval after each synchronisation.
+void settle_marks(pase_handle* h) {
+  for (int i = 0; i + 1 < h->nmark; ++i) {
+    if (h->mark_phase[i] < 0) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->evm[i], h->evm[i + 1]) == hipSuccess) h->t_phase[h->mark_phase[i]] += ms;
+  }
+  if (h->nmark > 1) {
+    std::swap(h->evm[0], h->evm[h->nmark - 1]);
+    h->mark_phase[0] = h->mark_phase[h->nmark - 1];
+    h->nmark = 1;
+  }
+}
+
+void mark(pase_handle* h, int phase) {
+  if (!h->timing) return;
+  if (h->nmark == pase_handle::kMarks) {   // not reached by the outer loop (at most 12 per correction)
+    (void)hipStreamSynchronize(h->stream);
+    settle_marks(h);
+  }
+  if (hipEventRecord(h->evm[h->nmark], h->stream) == hipSuccess) h->mark_phase[h->nmark++] = phase;
+}
 
 pase_status fail(pase_handle* h, pase_status s, const std::string& msg) {
   if (h) h->err = msg;
@@ -613,10 +649,12 @@ pase_status correction_dense_tail(pase_handle* h, int k) {
   hipStream_t s = h->stream;
   const int NH = (int)h->lev[h->L].N;
   const int nT = NH + k;
+  mark(h, PH_SMALL);
   launch_gemm(false, false, NH, k, NH, 1.0, h->LBinv, NH, h->ca, k, 0.0, h->cb, k, s);
   launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->cc, k, s);
   launch_set_diag_block(nT, NH, k, h->C0, h->cc, h->kk5, h->Tm, s);
   syev_any(nT, k, h->Tm, h->lam, h->Vs, h->syw, h->info + 2, s);
+  mark(h, PH_PROLONG);
   launch_gemm(true, false, NH, k, NH, 1.0, h->LBinv, NH, h->Vs, k, 0.0, h->cb, k, s);   // y_H
   prolongation_tail(h, k, h->cb);
   return PASE_OK;
@@ -647,6 +685,7 @@ void structured_attempt(pase_handle* h, int k) {
                         h->lam, h->permf, h->statf, s);
   }
   launch_small_emit(nT, k, h->Vtf, h->permf, h->Vs, s);
+  mark(h, PH_PROLONG);
   launch_gemm(false, false, NH, k, NH, 1.0, h->Psi, NH, h->Vs, k, 0.0, h->cc, k, s);   // y_H = L_B^{-T} Phi V
   prolongation_tail(h, k, h->cc);
   h->spec = true;
@@ -660,6 +699,7 @@ void structured_retry(pase_handle* h, int k) {
   const int NH = (int)h->lev[h->L].N;
   const int m = std::max(1, std::min(NH, 384 - k));
   const int nr = m + k;
+  mark(h, PH_SMALL);
   launch_small_principal(NH, m, k, h->theta, h->Gtl, h->kk5, h->Tm, s);
   syev_any(nr, k, h->Tm, h->rqf, h->Vs, h->syw, h->info + 6, s);
   launch_small_expand(NH, m, k, h->Vs, h->X0f, s);
@@ -676,6 +716,7 @@ pase_status correction_enqueue(pase_handle* h, int k) {
   const long long N = h->lev[0].N;
   const int NH = (int)h->lev[h->L].N;
   // (a) fine solves A w = lam M u from w = u: s CG steps per column
+  mark(h, PH_FINE);
   const int ka = (h->ka > 0 && h->ka < k) ? h->ka : k;
   h->fine_cols += ka;
   if (ka < k) {
@@ -708,6 +749,7 @@ pase_status correction_enqueue(pase_handle* h, int k) {
     pcg(h, k, h->U, h->X, h->R);
   }
   double* W = h->X;
+  mark(h, PH_PROJECTION);
   // complement: W <- W - P B_H^{-1} P^T M W
   apply_AM(h, 0, k, W, nullptr, h->W3);
   restrict_all(h, k, h->W3, h->ca);
@@ -748,11 +790,11 @@ pase_status correction_enqueue(pase_handle* h, int k) {
   launch_gemm(false, true, k, k, k, 1.0, h->kk4, k, h->kk3, k, 0.0, h->kk5, k, s);
   launch_symmetrize(k, h->kk5, s);
   // (c) small problem
+  mark(h, PH_SMALL);
   h->last_path = 0;
   h->spec = false;
   if (h->fast && h->try_fast) {
     // structured path in the eigenbasis of C0: Gt = Psi^T a Li^T, shifts = the current Ritz values
-    const int nT = NH + k;
     launch_fill_int(4, 0, h->statf, s);
     launch_gemm(true, false, NH, k, NH, 1.0, h->Psi, NH, h->ca, k, 0.0, h->cb, k, s);
     launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->Gtl, k, s);
@@ -902,6 +944,8 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
     g_last_error = h->err;
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
+    for (hipEvent_t e : h->evm)
+      if (e) (void)hipEventDestroy(e);
     if (h->pin) (void)hipHostFree(h->pin);
     delete h;
     return r;
@@ -1003,6 +1047,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   }
   HIPS(hipEventCreate(&h->ev0));
   HIPS(hipEventCreate(&h->ev1));
+  for (hipEvent_t& e : h->evm) HIPS(hipEventCreate(&e));
   {
     const size_t Kp = (size_t)h->K;
     HIPS(hipHostMalloc(&h->pin, sizeof(double) * 5 * Kp + sizeof(int) * (Kp + 20), hipHostMallocDefault));
@@ -1024,6 +1069,8 @@ pase_status pase_destroy(pase_handle* h) {
   if (!h) return PASE_OK;
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  for (hipEvent_t e : h->evm)
+    if (e) (void)hipEventDestroy(e);
   if (h->pin) (void)hipHostFree(h->pin);
   delete h;
   return PASE_OK;
@@ -1181,6 +1228,10 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   const long long N = h->lev[0].N;
   hipStream_t s = h->stream;
   HIPC(hipEventRecord(h->ev0, s));
+  h->timing = (rep != nullptr);
+  h->nmark = 0;
+  for (double& t : h->t_phase) t = 0.0;
+  mark(h, PH_START);
   HIPC(hipMemsetAsync(h->info, 0, 16 * sizeof(int), s));
   h->fast_hits = 0;
   h->fallbacks = 0;
@@ -1219,13 +1270,16 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   int rows = 0;
   pase_status result = PASE_OK;
   while (true) {
+    mark(h, PH_RESIDUAL);
     eig_residual(h, k, h->U, h->R);
+    mark(h, -1);
     HIPC(hipGetLastError());
     HIPC(hipMemcpyAsync(h->pin_sums, h->sums, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(h->pin_lam, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(h->pin_info, h->info, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
     if (h->spec) HIPC(hipMemcpyAsync(h->pin_st, h->statf, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    settle_marks(h);
     if (h->spec) {
       // the previous correction's structured solution was used speculatively (one synchronisation
       // per correction): on a rejection the dense path redoes the prolongation and the residual
@@ -1328,7 +1382,10 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   HIPC(hipStreamSynchronize(s));
   float ms = 0.f;
   HIPC(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  settle_marks(h);
+  h->timing = false;
   if (rep) {
+    for (int p = 0; p < PASE_PHASES; ++p) rep->t_phase_ms[p] = h->t_phase[p];
     rep->outer_iters = it;
     rep->n_converged = nconv;
     rep->ritz_history_rows = rows;

@@ -19,6 +19,9 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -956,6 +959,70 @@ pase_status pase_unet_get_weights(const pase_unet* u, float* W) {
   return (hipMemcpyAsync(W, u->W, u->P * sizeof(float), hipMemcpyDeviceToDevice, u->stream) == hipSuccess)
              ? PASE_OK
              : PASE_E_HIP;
+}
+
+// Checkpoint file: a 64-byte header (8-byte tag, format version, the three channel widths, the
+// parameter count, the Adam step count, zero padding), then the FP32 weights, the first and the
+// second Adam moments, P values each, all little-endian.
+namespace {
+constexpr char kCkptTag[8] = {'P', 'A', 'S', 'E', 'U', 'N', 'E', 'T'};
+struct CkptHeader {
+  char tag[8];
+  int32_t version;
+  int32_t ch[3];
+  int64_t P;
+  int64_t t;
+  char pad[24];
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
+}  // namespace
+
+pase_status pase_unet_save(pase_unet* u, const char* path) {
+  if (!u || !path) return PASE_E_ARG;
+  CkptHeader hd{};
+  std::memcpy(hd.tag, kCkptTag, 8);
+  hd.version = 1;
+  for (int i = 0; i < 3; ++i) hd.ch[i] = u->ch[i];
+  hd.P = (int64_t)u->P;
+  hd.t = u->t;
+  std::vector<float> buf(3 * u->P);
+  if (hipStreamSynchronize(u->stream) != hipSuccess ||
+      hipMemcpy(buf.data(), u->W, u->P * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(buf.data() + u->P, u->Mo, u->P * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(buf.data() + 2 * u->P, u->Vo, u->P * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    return ufail(u, PASE_E_HIP, "copy of the training state to the host failed");
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return ufail(u, PASE_E_ARG, "cannot open the checkpoint file for writing");
+  const bool ok = std::fwrite(&hd, sizeof hd, 1, f) == 1 && std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  const bool closed = std::fclose(f) == 0;
+  if (!ok || !closed) return ufail(u, PASE_E_ARG, "writing the checkpoint file failed");
+  return PASE_OK;
+}
+
+pase_status pase_unet_load(pase_unet* u, const char* path) {
+  if (!u || !path) return PASE_E_ARG;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return ufail(u, PASE_E_ARG, "cannot open the checkpoint file");
+  CkptHeader hd{};
+  std::vector<float> buf;
+  bool ok = std::fread(&hd, sizeof hd, 1, f) == 1 && std::memcmp(hd.tag, kCkptTag, 8) == 0 && hd.version == 1;
+  if (ok) ok = hd.ch[0] == u->ch[0] && hd.ch[1] == u->ch[1] && hd.ch[2] == u->ch[2] && hd.P == (int64_t)u->P &&
+               hd.t >= 0 && hd.t < (int64_t)1 << 30;
+  if (ok) {
+    buf.resize(3 * u->P);
+    ok = std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size() && std::fgetc(f) == EOF;
+  }
+  std::fclose(f);
+  if (!ok) return ufail(u, PASE_E_ARG, "not a checkpoint of a network with these channel widths");
+  if (hipMemcpyAsync(u->W, buf.data(), u->P * sizeof(float), hipMemcpyHostToDevice, u->stream) != hipSuccess ||
+      hipMemcpyAsync(u->Mo, buf.data() + u->P, u->P * sizeof(float), hipMemcpyHostToDevice, u->stream) != hipSuccess ||
+      hipMemcpyAsync(u->Vo, buf.data() + 2 * u->P, u->P * sizeof(float), hipMemcpyHostToDevice, u->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(u->stream) != hipSuccess)   // buf is freed on return
+    return ufail(u, PASE_E_HIP, "copy of the training state to the device failed");
+  u->t = (int)hd.t;
+  relayout_all(u);
+  return (hipGetLastError() == hipSuccess) ? PASE_OK : ufail(u, PASE_E_HIP, "kernel launch failed");
 }
 
 pase_status pase_unet_apply(pase_unet* u, int batch, const double* R, const double* logk, double* Z) {

@@ -9,6 +9,7 @@ of pair columns is gathered with torch indexing (data movement only).
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 import torch
@@ -85,6 +86,14 @@ class UNet:
         W = torch.empty(self.num_params, dtype=torch.float32, device=self.device)
         self._check(self.lib.pase_unet_get_weights(self.h, _ptr(W)))
         return W
+
+    def save(self, path):
+        """Write the training state (weights, Adam moments, Adam step count) to the file `path`."""
+        self._check(self.lib.pase_unet_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        """Restore a training state written by save() for a network of the same channel widths."""
+        self._check(self.lib.pase_unet_load(self.h, os.fsencode(path)))
 
     def apply(self, R, logk=None):
         k = R.shape[1]

@@ -151,6 +151,7 @@ class Solver:
                   "small_path": paths[:rep.outer_iters].copy(), "learned_fallbacks": rep.learned_fallbacks,
                   "lowprec_projection_iters": rep.lowprec_projection_iters,
                   "fine_solve_columns": rep.fine_solve_columns,
+                  "t_phase_ms": {name: float(rep.t_phase_ms[i]) for i, name in enumerate(nat.PHASES)},
                   "status": nat.STATUS.get(st, st)}
         if history:
             report["ritz_history"] = hist[:rep.ritz_history_rows].copy()

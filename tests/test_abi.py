@@ -94,3 +94,38 @@ def test_entry_points_reject_null_handle(lib):
     assert lib.pase_apply(None, 0, 1, None, None, None) == 1
     assert lib.pase_solve(None, 1, 1e-8, None, None, None, None) == 1
     assert lib.pase_destroy(None) == 0
+    assert lib.pase_unet_save(None, b"/nonexistent/x") == 1
+    assert lib.pase_unet_load(None, b"/nonexistent/x") == 1
+
+
+def _c_layout(type_name, fields):
+    """sizeof(type) and offsetof(type, f) for each field, from the C compiler on the real header."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    prog = "#include <stdio.h>\n#include <stddef.h>\n#include \"pase.h\"\nint main(void){\n"
+    prog += f'printf("%zu\\n", sizeof({type_name}));\n'
+    for f in fields:
+        prog += f'printf("%zu\\n", offsetof({type_name}, {f}));\n'
+    prog += "return 0;}\n"
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(src, "w").write(prog)
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return [int(v) for v in out]
+
+
+@pytest.mark.parametrize("cls, cname", [(nat.Report, "pase_report"), (nat.Options, "pase_options"),
+                                        (nat.Problem, "pase_problem")])
+def test_ctypes_structs_match_the_header_layout(cls, cname):
+    """The binding's structures have the C layout of include/pase.h (size and every field offset)."""
+    names = [f[0] for f in cls._fields_]
+    got = _c_layout(cname, names)
+    assert got[0] == C.sizeof(cls)
+    for name, off in zip(names, got[1:]):
+        assert getattr(cls, name).offset == off, name

@@ -153,6 +153,40 @@ def test_training_steps_reduce_the_loss():
     assert L1 < 0.85 * L0, (L0, L1)
 
 
+def test_checkpoint_restores_weights_and_adam_state(tmp_path):
+    """pase_unet_save / pase_unet_load: a fresh network loaded from a checkpoint taken after 3 Adam
+    steps holds the same weights bit for bit, and its next Adam step (which needs both moments and
+    the step count) gives the same weights as the original's.  A file of the wrong size or tag is
+    refused and leaves the network unchanged."""
+    from paper_2502_04589_amd import UNet
+    from paper_2502_04589_amd.solver import PaseError
+    net, W, g, R, logk = setup(seed=8, batch=3)
+    H = multigrid.Hierarchy(3, [16, 8, 4])
+    Cm, Rd, lk = dev(H.vcycle(R)), dev(R), dev(logk)
+    for _ in range(3):
+        g.loss_grad(Rd, Cm, lk)
+        g.adam_step(1e-3)
+    path = str(tmp_path / "unet.ckpt")
+    g.save(path)
+    g2 = UNet(16, batch_max=8)
+    g2.set_weights(np.zeros(g2.num_params, dtype=np.float32))
+    g2.load(path)
+    assert torch.equal(g.get_weights(), g2.get_weights())
+    for u in (g, g2):
+        u.loss_grad(Rd, Cm, lk)
+        u.adam_step(1e-3)
+    assert torch.equal(g.get_weights(), g2.get_weights())
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(open(path, "rb").read()[:-4])
+    before = g2.get_weights()
+    with pytest.raises(PaseError):
+        g2.load(str(bad))
+    bad.write_bytes(b"NOTAUNET" + open(path, "rb").read()[8:])
+    with pytest.raises(PaseError):
+        g2.load(str(bad))
+    assert torch.equal(before, g2.get_weights())
+
+
 # ---------------------------------------------------------------- the learned form inside the solver
 LEVELS = [16, 8, 4]
 

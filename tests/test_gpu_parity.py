@@ -416,6 +416,24 @@ def test_guard_pairs_config2_full_size():
     assert np.abs(host(U.T.contiguous() @ MU) - np.eye(k)).max() < 1e-12
 
 
+@pytest.mark.parametrize("small_solver", ["auto", "dense"])
+def test_phase_timers_account_for_the_solve(small_solver):
+    """pase_report.t_phase_ms: every phase of Alg. 3 that the solve runs has positive time, and the
+    phases add up to the solve's device time minus the stream's idle gaps (the host's reads of the
+    residuals): at most t_solve_ms and at least half of it."""
+    levels, k = [32, 16, 8, 4], 12
+    kap = synth.kappa_field(3, 32, 2)
+    s = Solver(3, levels, kap, nev_max=k, guard=4, small_solver=small_solver)
+    lam, U, rep = s.solve(k, 1e-9, dev(synth.initial_vectors(s.N[0], k, 4)))
+    ph = rep["t_phase_ms"]
+    assert list(ph) == ["start", "residual", "fine_solves", "projection", "small_problem", "prolongation"]
+    assert all(v > 0 for v in ph.values()), ph
+    tot = sum(ph.values())
+    assert 0.5 * rep["t_solve_ms"] <= tot <= rep["t_solve_ms"] * 1.001, (tot, rep["t_solve_ms"], ph)
+    print(f"  {small_solver}: t_solve {rep['t_solve_ms']:.1f} ms, phases " +
+          ", ".join(f"{k_} {v:.1f}" for k_, v in ph.items()), flush=True)
+
+
 # ---- structured augmented eigenproblem (shift-invert in the eigenbasis of C0) vs the dense solver
 
 @pytest.mark.parametrize("dim,levels,kseed,k,tol", [
