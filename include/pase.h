@@ -86,7 +86,9 @@ typedef struct pase_options {
   int nu;                        /* damped-Jacobi sweeps before and after the coarse correction (default 2) */
   double omega;                  /* Jacobi damping (default 2/3) */
   int small_solver;              /* augmented eigenproblem: 0 = structured shift-invert path with dense
-                                    fallback (default), 1 = dense eigensolver only */
+                                    fallback (default), 1 = dense eigensolver only, 2 = PRECOND-A and
+                                    GCG_AUG (Sec. 4, Alg. 4 and 5): matrix-free, with V_H on the level
+                                    coarse_level, so N_H is not bounded by a dense eigensolver */
   int locking;                   /* 1 (default): soft locking -- the fine solves of a correction run only
                                     for the pairs whose residual exceeds tol / 10 (guard pairs: 100 tol;
                                     see guard below) (a locked pair keeps
@@ -107,6 +109,12 @@ typedef struct pase_options {
   double fallback_ratio;         /* learned form: a column switches to the V-cycle when its residual
                                     norm does not fall below fallback_ratio times its previous value
                                     (default 0.5) */
+  int coarse_level;              /* the level of the hierarchy that is V_H: 0 (default) = the coarsest;
+                                    1 .. nlevels - 1 selects that level (below the coarsest only with
+                                    small_solver = 2; the V-cycle still runs to the coarsest level,
+                                    whose dense inverse is its bottom solve).  With the coarse start
+                                    (start = 1) the start block comes from the coarsest level's
+                                    eigenvectors. */
 } pase_options;
 
 /* Filled by pase_solve.  Array members are optional HOST buffers (NULL = not wanted). */
@@ -123,8 +131,9 @@ typedef struct pase_report {
                                     with the count certifying the nev wanted pairs only (the guard pairs
                                     are eigenpairs of the augmented problem, not certified as the next
                                     ones), 3 = accepted on the retry from the Rayleigh-Ritz start of a
-                                    principal block (after a rejection), 0 = dense only, -1 = rejected
-                                    by a residual, -2 = rejected by the eigenvalue count, -3 = its
+                                    principal block (after a rejection), 4 = GCG_AUG (small_solver
+                                    2), 0 = dense only, -1 = rejected by a residual, -2 = rejected
+                                    by the eigenvalue count, -3 = its
                                     Cholesky-QR orthonormalisation broke down (the last rejection of
                                     the correction; the dense solver then solved it) */
   int learned_fallbacks;         /* learned form: column switches to the V-cycle, summed over the solve */
@@ -141,8 +150,9 @@ typedef struct pase_report {
                                     [3] projection (the complement of W, A W, M W, the coarse
                                     restriction of A W, the Grams alpha and beta, their Cholesky
                                     factor and H); [4] the augmented eigenproblem (step 5:
-                                    structured path, retry and dense path); [5] prolongation (step 6:
-                                    u = P y_H + W y_W) */
+                                    structured path, retry and dense path, or GCG_AUG); [5]
+                                    prolongation (step 6: u = P y_H + W y_W) */
+  int aug_iters;                 /* small_solver 2: GCG_AUG iterations summed over the corrections */
 } pase_report;
 
 typedef struct pase_handle pase_handle;

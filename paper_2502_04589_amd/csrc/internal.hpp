@@ -182,6 +182,22 @@ void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y
 void launch_set_diag_block(int n, int nh, int k, const double* C0, const double* G, const double* H, double* T,
                            hipStream_t s);
 
+// ---- GCG_AUG (gcg.hip): augmented blocks are (N_H + k) x w row-major
+// C (m x n) = A^T B over N rows, A: N x m (lda), B: N x n (ldb); fixed-order reduction over at most
+// 128 row chunks; partial >= gram_tn_partial_doubles(N, m, n)
+size_t gram_tn_partial_doubles(long long N, int m, int n);
+void launch_gram_tn(long long N, int m, int n, const double* A, int lda, const double* B, int ldb, double* partial,
+                    double* C, hipStream_t s);
+void launch_aug_resid(long long N, int k, const double* AX, const double* BX, const double* lam, double* R,
+                      hipStream_t s);                                            // R = AX - BX diag(lam)
+void launch_gather_scale(long long N, int k, int ka, const int* idx, const double* src, const double* lam,
+                         double* dst, hipStream_t s);                            // dst_j = src_idx[j] lam_idx[j]
+void launch_aug_start(long long NH, int k, const double* ahat, double* X, hipStream_t s);   // [a_hat ; I]
+void launch_assemble_rr(int k, int ny, const double* Gxx, const double* Gxy, const double* Gyy, double* H,
+                        hipStream_t s);
+void launch_ltl(int k, const double* Li, double* C, hipStream_t s);             // C = Li^T Li
+void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s);   // c = a - b (null = 0)
+
 // ---- dense single-workgroup kernels (dense.hip)
 // In-place lower Cholesky of an n x n SPD matrix (row-major); info[0] = 0 ok, j+1 if pivot j failed.
 void launch_cholesky(int n, double* A, int lda, int* info, hipStream_t s);

@@ -127,6 +127,25 @@ struct pase_handle {
   double* small_tolv = nullptr;
   bool tolv_on = false;
   int fine_cols = 0;
+  // PRECOND-A and GCG_AUG (small_solver 2): V_H = level gc (gNH nodes), augmented blocks of
+  // gNH + k rows (the coarse coordinates, then the k fine directions)
+  bool gcg = false;
+  bool psi_only = false;            // the coarse start's eigenbasis without the structured path
+  int gc = 0;
+  long long gNH = 0;
+  double *g_a = nullptr, *g_ahat = nullptr, *g_at = nullptr, *g_bt = nullptr;   // gNH x K
+  double *g_alt = nullptr, *g_bet = nullptr, *g_alinv = nullptr;               // K x K
+  double *gX = nullptr, *gAX = nullptr, *gBX = nullptr, *gXn = nullptr, *gAXn = nullptr, *gBXn = nullptr;
+  double *gP = nullptr, *gBP = nullptr, *gPn = nullptr, *gBPn = nullptr;
+  double *gY = nullptr, *gAY = nullptr, *gBY = nullptr, *gY2 = nullptr;
+  double *gW = nullptr, *gAW = nullptr, *gBW = nullptr;
+  double *gR = nullptr, *gZ = nullptr, *gPp = nullptr, *gQ = nullptr;
+  double *gS = nullptr, *gG = nullptr, *gLi = nullptr, *gH = nullptr, *gC = nullptr, *gCJ = nullptr;
+  double *gGxx = nullptr, *gGxy = nullptr, *gGyy = nullptr, *gw = nullptr, *glam = nullptr, *glamn = nullptr;
+  double *gsyw = nullptr, *gchs = nullptr, *gpart = nullptr, *gnorm = nullptr;
+  int* gidx = nullptr;
+  int aug_iters = 0;                // GCG_AUG iterations of this solve
+  double* pin_gnorm = nullptr;      // pinned: 2 K column norms
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // per-phase device time of a solve: marks (event, phase) enqueued on the stream and resolved after
   // each synchronisation of the outer loop; a mark of phase -1 opens an interval that is not counted
@@ -203,7 +222,10 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (o->nev_max < 1 || o->nev_max > PASE_MAX_NEV) return PASE_E_ARG;
   if (o->cg_steps < 1 || o->max_outer < 0 || o->nu < 1) return PASE_E_ARG;
   if (!(o->omega > 0.0)) return PASE_E_ARG;
-  if (o->small_solver != 0 && o->small_solver != 1) return PASE_E_ARG;
+  if (o->small_solver < 0 || o->small_solver > 2) return PASE_E_ARG;
+  if (o->coarse_level < 0 || o->coarse_level >= p->nlevels) return PASE_E_ARG;
+  if (o->coarse_level != 0 && o->coarse_level != p->nlevels - 1 && o->small_solver != 2)
+    return PASE_E_UNSUPPORTED;   // V_H below the coarsest level: GCG_AUG only
   if (o->locking != 0 && o->locking != 1) return PASE_E_ARG;
   if (o->guard < 0 || o->guard > 64 || o->nev_max + o->guard > PASE_MAX_NEV) return PASE_E_ARG;
   if (o->start != 0 && o->start != 1) return PASE_E_ARG;
@@ -274,7 +296,41 @@ size_t layout(pase_handle* h, void* base) {
   h->dtmp = b.take<double>(NH * NH);
   h->nT = (int)(NH + K);
   const size_t nT = (size_t)h->nT;
-  if (h->nT <= syev_large_max_n() && (int)K <= syev_max_k()) {
+  h->gcg = (h->opt.small_solver == 2);
+  h->gc = (h->opt.coarse_level > 0) ? h->opt.coarse_level : h->L;
+  h->gNH = h->lev[h->gc].N;
+  h->psi_only = h->gcg && h->opt.start == 1 && (int)NH <= syev_large_max_n();
+  if (h->psi_only) {
+    // the coarse start's eigenbasis of the coarsest level (the augmented problems go to GCG_AUG)
+    h->Tm = b.take<double>(NH * NH);
+    h->syw = b.take<double>(syev_any_work((int)NH, (int)NH));
+    h->theta = b.take<double>(NH);
+    h->Psi = b.take<double>(NH * NH);
+  }
+  if (h->gcg) {
+    const size_t gN = (size_t)h->gNH, Na = gN + K, K2 = 2 * K, K3 = 3 * K;
+    h->g_a = b.take<double>(gN * K); h->g_ahat = b.take<double>(gN * K);
+    h->g_at = b.take<double>(gN * K); h->g_bt = b.take<double>(gN * K);
+    h->g_alt = b.take<double>(K * K); h->g_bet = b.take<double>(K * K); h->g_alinv = b.take<double>(K * K);
+    double** nk[] = {&h->gX, &h->gAX, &h->gBX, &h->gXn, &h->gAXn, &h->gBXn, &h->gP, &h->gBP, &h->gPn, &h->gBPn,
+                     &h->gW, &h->gAW, &h->gBW, &h->gR, &h->gZ, &h->gPp, &h->gQ};
+    for (double** q : nk) *q = b.take<double>(Na * K);
+    double** n2k[] = {&h->gY, &h->gAY, &h->gBY, &h->gY2};
+    for (double** q : n2k) *q = b.take<double>(Na * K2);
+    h->gS = b.take<double>(K * K2); h->gG = b.take<double>(K2 * K2); h->gLi = b.take<double>(K2 * K2);
+    h->gH = b.take<double>(K3 * K3); h->gC = b.take<double>(K3 * K); h->gCJ = b.take<double>(K2 * K);
+    h->gGxx = b.take<double>(K * K); h->gGxy = b.take<double>(K * K2); h->gGyy = b.take<double>(K2 * K2);
+    h->gw = b.take<double>(K3); h->glam = b.take<double>(K); h->glamn = b.take<double>(K);
+    // Rayleigh-Ritz sizes run from K to 3K: the largest work of each eigensolver branch
+    h->gsyw = b.take<double>(std::max(syev_any_work((int)std::min<size_t>(K3, kDenseSmallN), (int)K),
+                                      syev_any_work((int)K3, (int)K)));
+    h->gchs = b.take<double>(std::max(cholesky_large_scratch_doubles((int)K2), trinv_large_scratch_doubles((int)K2)));
+    h->gpart = b.take<double>(std::max(gram_tn_partial_doubles((long long)Na, (int)K2, (int)K2),
+                                       gram_tn_partial_doubles((long long)Na, (int)K, (int)K2)));
+    h->gnorm = b.take<double>(2 * K);
+    h->gidx = b.take<int>(K);
+  }
+  if (!h->gcg && h->nT <= syev_large_max_n() && (int)K <= syev_max_k()) {
     const bool fit_small = (int)K <= small_fast_max_k() && (int)NH <= small_fast_max_nh();
     const bool fit_big = (int)K <= small_big_max_k() && (int)NH <= small_big_max_nh();
     h->fast = (h->opt.small_solver == 0) && (fit_small || fit_big);
@@ -708,6 +764,288 @@ void structured_retry(pase_handle* h, int k) {
   structured_attempt(h, k);
 }
 
+// ---------------------------------------------------------------- PRECOND-A and GCG_AUG (Sec. 4)
+// V_H is level gc.  The fine directions W are replaced by their A-orthogonal complement
+// W~ = W - I_H^h a_hat against V_H (a_hat ~ A_H^{-1} I_h^H A W), which is the congruence of eq.
+// (Transformation_0) written on vectors: in the basis [I_H^h, W~] the augmented pencil is
+//   A~ = [[A_H, a~], [a~^T, alpha~]],  B~ = [[B_H, b~], [b~^T, beta~]],
+// a~ = I_h^H A W~ (zero for an exact a_hat, the pencil of eq. Eigen_Problem_Hh_2; here a_hat comes
+// from a few CG steps, and the small a~ that remains is kept so that the pencil stays exactly the
+// augmented problem), alpha~ = W~^T A W~, b~ = I_h^H M W~, beta~ = W~^T M W~.  GCG_AUG (Alg. 4)
+// then works on augmented blocks of gNH + k rows.
+
+constexpr int kAhatSteps = 6;      // CG steps for a_hat (V-cycle from level gc preconditions them)
+constexpr int kGcgMaxIter = 50;    // GCG_AUG iterations per correction at most
+constexpr int kGcgStall = 4;       // ... and at most this many without a new low of the largest residual
+constexpr double kGcgTolFloor = 1e-11;
+
+// composite restriction to level c: xc (N_c x k) = I_h^H xf; and prolongation xf (=, +=, -=) I_H^h xc
+void restrict_to(pase_handle* h, int c, int k, const double* xf, double* xc) {
+  const double* src = xf;
+  for (int l = 0; l < c; ++l) {
+    double* dst = (l + 1 == c) ? xc : h->vr[l + 1];
+    launch_restrict(h->dim, h->lev[l].m, h->lev[l + 1].m, k, src, dst, 0, h->stream);
+    src = dst;
+  }
+}
+
+void prolong_from(pase_handle* h, int c, int k, const double* xc, double* xf, int mode) {
+  const double* src = xc;
+  for (int l = c; l >= 1; --l) {
+    double* dst = (l == 1) ? xf : h->vxa[l - 1];
+    launch_prolong(h->dim, h->lev[l - 1].m, h->lev[l].m, k, src, dst, (l == 1) ? mode : 0, 0, h->stream);
+    src = dst;
+  }
+}
+
+// AY = A~ Y and BY = B~ Y for an augmented block Y of w columns (kb fine directions; either output
+// may be null): the coarse stencils on the first gNH rows, the couplings as tall-skinny products.
+void aug_apply(pase_handle* h, int kb, int w, const double* Y, double* AY, double* BY) {
+  hipStream_t s = h->stream;
+  const long long NH = h->gNH;
+  const int nh = (int)NH;
+  stencil_op(h, h->gc, w, EPI_AM, Y, nullptr, AY, BY);
+  const double* Yg = Y + NH * w;
+  const double* cpl[2] = {h->g_at, h->g_bt};
+  const double* blk[2] = {h->g_alt, h->g_bet};
+  double* out[2] = {AY, BY};
+  for (int o = 0; o < 2; ++o) {
+    if (!out[o]) continue;
+    launch_gemm(false, false, nh, w, kb, 1.0, cpl[o], kb, Yg, w, 1.0, out[o], w, s);       // += c y_g
+    launch_gram_tn(NH, kb, w, cpl[o], kb, Y, w, h->gpart, out[o] + NH * w, s);           // c^T y_H
+    launch_gemm(false, false, kb, w, kb, 1.0, blk[o], kb, Yg, w, 1.0, out[o] + NH * w, w, s);
+  }
+}
+
+// Z = diag(V-cycle on A_H from level gc, alpha~^{-1}) R
+void aug_precond(pase_handle* h, int kb, int w, const double* R, double* Z) {
+  const long long NH = h->gNH;
+  vcycle(h, h->gc, w, R, Z);
+  launch_gemm(false, false, kb, w, kb, 1.0, h->g_alinv, kb, R + NH * w, w, 0.0, Z + NH * w, w, h->stream);
+}
+
+// Step 2 of Alg. 4: s CG steps per column on A~ x = F from X0, preconditioned by aug_precond
+void aug_pcg(pase_handle* h, int kb, int w, const double* F, const double* X0, double* X) {
+  hipStream_t s = h->stream;
+  const long long Na = h->gNH + kb;
+  double *R = h->gR, *Z = h->gZ, *P = h->gPp, *Q = h->gQ;
+  aug_apply(h, kb, w, X0, Q, nullptr);
+  launch_sub(Na * w, F, Q, R, s);
+  aug_precond(h, kb, w, R, Z);
+  coldot(h, Na, w, R, Z, h->rho);
+  std::swap(Z, P);
+  launch_copy((size_t)Na * w, X0, X, s);
+  for (int j = 0; j < h->opt.cg_steps; ++j) {
+    aug_apply(h, kb, w, P, Q, nullptr);
+    coldot(h, Na, w, P, Q, h->pq);
+    launch_pcg_alpha(w, h->rho, h->pq, h->alpha, s);
+    launch_axpy2(Na, w, h->alpha, P, Q, X, R, s);
+    if (j + 1 < h->opt.cg_steps) {
+      aug_precond(h, kb, w, R, Z);
+      coldot(h, Na, w, R, Z, h->rho2);
+      launch_pcg_beta(w, h->rho2, h->rho, h->beta, s);
+      launch_xpby(Na, w, Z, h->beta, P, s);
+      std::swap(h->rho, h->rho2);
+    }
+  }
+}
+
+// a_hat = A_H^{-1} a approximately: kAhatSteps CG steps from zero on level gc (g_a -> g_ahat)
+void ahat_solve(pase_handle* h, int kb) {
+  hipStream_t s = h->stream;
+  const long long NH = h->gNH;
+  const int c = h->gc;
+  double *R = h->gR, *Z = h->gZ, *P = h->gPp, *Q = h->gQ, *X = h->g_ahat;
+  launch_copy((size_t)NH * kb, h->g_a, R, s);
+  launch_sub(NH * kb, nullptr, nullptr, X, s);
+  vcycle(h, c, kb, R, Z);
+  coldot(h, NH, kb, R, Z, h->rho);
+  std::swap(Z, P);
+  for (int j = 0; j < kAhatSteps; ++j) {
+    stencil_op(h, c, kb, EPI_AM, P, nullptr, Q, nullptr);
+    coldot(h, NH, kb, P, Q, h->pq);
+    launch_pcg_alpha(kb, h->rho, h->pq, h->alpha, s);
+    launch_axpy2(NH, kb, h->alpha, P, Q, X, R, s);
+    if (j + 1 < kAhatSteps) {
+      vcycle(h, c, kb, R, Z);
+      coldot(h, NH, kb, R, Z, h->rho2);
+      launch_pcg_beta(kb, h->rho2, h->rho, h->beta, s);
+      launch_xpby(NH, kb, Z, h->beta, P, s);
+      std::swap(h->rho, h->rho2);
+    }
+  }
+}
+
+// Steps 4-5 of Alg. 3 on the GCG_AUG path, from W in h->X: the complement W~ (in place), the
+// couplings and Grams, and alpha~^{-1} for the preconditioner.
+void gcg_projection(pase_handle* h, int k) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  const int c = h->gc;
+  double* W = h->X;
+  apply_AM(h, 0, k, W, h->W2, nullptr);
+  restrict_to(h, c, k, h->W2, h->g_a);                    // a = I_h^H A W
+  ahat_solve(h, k);
+  prolong_from(h, c, k, h->g_ahat, W, 2);                 // W~ = W - I_H^h a_hat
+  apply_AM(h, 0, k, W, h->W2, h->W3);                     // A W~, M W~
+  restrict_to(h, c, k, h->W2, h->g_at);                   // a~
+  restrict_to(h, c, k, h->W3, h->g_bt);                   // b~
+  launch_gram2_sym(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->g_alt, h->g_bet, s);
+  launch_symmetrize(k, h->g_alt, s);
+  launch_symmetrize(k, h->g_bet, s);
+  launch_copy((size_t)k * k, h->g_alt, h->kk2, s);
+  launch_cholinv(k, h->kk2, h->info + 1, s);               // alpha~ = L L^T, kk2 <- L^{-1}
+  launch_ltl(k, h->kk2, h->g_alinv, s);                    // alpha~^{-1} = L^{-T} L^{-1}
+}
+
+// X <- X C, AX <- AX C, BX <- BX C (w x w), through the spare buffers
+void gcg_rotate(pase_handle* h, long long Na, int w, const double* C) {
+  hipStream_t s = h->stream;
+  launch_tsmm(Na, w, h->gX, C, h->gXn, 0, 0, s);
+  launch_tsmm(Na, w, h->gAX, C, h->gAXn, 0, 0, s);
+  launch_tsmm(Na, w, h->gBX, C, h->gBXn, 0, 0, s);
+  std::swap(h->gX, h->gXn);
+  std::swap(h->gAX, h->gAXn);
+  std::swap(h->gBX, h->gBXn);
+}
+
+// GCG_AUG (Alg. 4) for the k smallest pairs of (A~, B~) from the start block [a_hat ; I] (the fine
+// directions themselves); the Ritz values end in glam and the vectors in gX.  One synchronisation
+// per iteration reads the residuals that choose the active pairs.
+pase_status gcg_small(pase_handle* h, int k) {
+  hipStream_t s = h->stream;
+  const long long NH = h->gNH, Na = NH + k;
+  launch_fill_int(5, 0, h->info + 11, s);
+  // step 1: two Cholesky-QR passes in B~, then the Rayleigh-Ritz of the start block
+  launch_aug_start(NH, k, h->g_ahat, h->gX, s);
+  for (int pass = 0; pass < 2; ++pass) {
+    aug_apply(h, k, k, h->gX, nullptr, h->gBX);
+    launch_gram(Na, k, h->gX, h->gBX, h->partial, gram_tiles(Na, k), h->gGxx, s);
+    launch_symmetrize(k, h->gGxx, s);
+    launch_cholinv(k, h->gGxx, h->info + 11, s);
+    launch_tsmm(Na, k, h->gX, h->gGxx, h->gXn, 0, 1, s);
+    std::swap(h->gX, h->gXn);
+  }
+  aug_apply(h, k, k, h->gX, h->gAX, h->gBX);
+  launch_gram(Na, k, h->gX, h->gAX, h->partial, gram_tiles(Na, k), h->gGxx, s);
+  launch_symmetrize(k, h->gGxx, s);
+  syev_any(k, k, h->gGxx, h->glam, h->gC, h->gsyw, h->info + 12, s);
+  gcg_rotate(h, Na, k, h->gC);
+  std::vector<double> tol(k, kGcgTolFloor);
+  if (h->tolv_on)
+    for (int j = 0; j < k && j < (int)h->tolv_host.size(); ++j) tol[j] = kGcgTolFloor * h->tolv_host[j];
+  std::vector<int> act;
+  int kp = 0, kp_prev = 0, it = 0, since = 0;
+  double best = 1e300;
+  bool retried = false;
+  while (true) {
+    launch_aug_resid(Na, k, h->gAX, h->gBX, h->glam, h->gR, s);
+    coldot(h, Na, k, h->gR, h->gR, h->gnorm);
+    coldot(h, Na, k, h->gBX, h->gBX, h->gnorm + k);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(h->pin_gnorm, h->gnorm, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(h->pin_lam, h->glam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(h->pin_info, h->info, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    const int* inf = h->pin_info;
+    if (inf[11] || inf[12]) return fail(h, PASE_E_BREAKDOWN, "GCG_AUG: the start block is not B-orthonormalisable");
+    if (inf[13] || inf[14] || inf[15]) {
+      // the last iteration's orthonormalisation or Rayleigh-Ritz broke down: back to its start
+      // block, and once more without the P block; a second breakdown ends the iteration there
+      std::swap(h->gX, h->gXn);
+      std::swap(h->gAX, h->gAXn);
+      std::swap(h->gBX, h->gBXn);
+      std::swap(h->glam, h->glamn);
+      launch_fill_int(3, 0, h->info + 13, s);
+      if (retried || kp_prev == 0) break;
+      retried = true;
+      kp = 0;
+      continue;
+    }
+    double worst = 0.0;
+    act.clear();
+    for (int j = 0; j < k; ++j) {
+      const double res = std::sqrt(h->pin_gnorm[j]) / (std::fabs(h->pin_lam[j]) * std::sqrt(h->pin_gnorm[k + j]));
+      if (!std::isfinite(res)) return fail(h, PASE_E_BREAKDOWN, "GCG_AUG: non-finite residual");
+      if (res > tol[j]) {
+        act.push_back(j);
+        worst = std::max(worst, res);
+      }
+    }
+    if (!act.empty()) {
+      if (worst < best) {
+        best = worst;
+        since = 0;
+      } else {
+        ++since;
+      }
+    }
+    if (act.empty() || it >= kGcgMaxIter || since >= kGcgStall) break;
+    const int ka = (int)act.size();
+    std::memcpy(h->pin_idx, act.data(), sizeof(int) * ka);
+    HIPC(hipMemcpyAsync(h->gidx, h->pin_idx, sizeof(int) * ka, hipMemcpyHostToDevice, s));
+    // step 2: W = A~^{-1} (B~ X Lambda) approximately, from X, for the active pairs (shift 0)
+    launch_gather_scale(Na, k, ka, h->gidx, h->gBX, h->glam, h->gAW, s);    // F
+    launch_gather_scale(Na, k, ka, h->gidx, h->gX, nullptr, h->gBW, s);     // X0
+    aug_pcg(h, k, ka, h->gAW, h->gBW, h->gW);
+    aug_apply(h, k, ka, h->gW, nullptr, h->gBW);
+    // step 3: Y = [P, W] made B~-orthogonal to X and B~-orthonormal, two passes.  The images of
+    // Y are applied afresh after each change of Y: the remainders of nearly converged pairs are
+    // small, and carrying A~ Y, B~ Y through the scaling of Cholesky-QR would scale their
+    // rounding errors up with them.
+    const int ny = kp + ka;
+    if (kp) launch_copy_cols(Na, kp, ny, kp, h->gP, h->gY, 0, s);
+    launch_copy_cols(Na, ka, ny, ka, h->gW, h->gY + kp, 0, s);
+    if (kp) launch_copy_cols(Na, kp, ny, kp, h->gBP, h->gBY, 0, s);
+    launch_copy_cols(Na, ka, ny, ka, h->gBW, h->gBY + kp, 0, s);
+    launch_fill_int(3, 0, h->info + 13, s);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_gram_tn(Na, k, ny, h->gX, k, h->gBY, ny, h->gpart, h->gS, s);           // S = X^T B~ Y
+      launch_gemm(false, false, (int)Na, ny, k, -1.0, h->gX, k, h->gS, ny, 1.0, h->gY, ny, s);
+      aug_apply(h, k, ny, h->gY, nullptr, h->gBY);
+      launch_gram_tn(Na, ny, ny, h->gY, ny, h->gBY, ny, h->gpart, h->gG, s);         // Y^T B~ Y
+      launch_symmetrize(ny, h->gG, s);
+      launch_cholesky_large(ny, h->gG, ny, h->gchs, h->info + 13 + pass, s);
+      launch_trinv_large(ny, h->gG, ny, h->gLi, ny, h->gchs, s);
+      launch_gemm(false, true, (int)Na, ny, ny, 1.0, h->gY, ny, h->gLi, ny, 0.0, h->gY2, ny, s);
+      std::swap(h->gY, h->gY2);
+      aug_apply(h, k, ny, h->gY, pass == 1 ? h->gAY : nullptr, h->gBY);
+    }
+    // step 4: Rayleigh-Ritz on [X, Y]
+    const int n = k + ny;
+    launch_gram(Na, k, h->gX, h->gAX, h->partial, gram_tiles(Na, k), h->gGxx, s);
+    launch_gram_tn(Na, k, ny, h->gX, k, h->gAY, ny, h->gpart, h->gGxy, s);
+    launch_gram_tn(Na, ny, ny, h->gY, ny, h->gAY, ny, h->gpart, h->gGyy, s);
+    launch_assemble_rr(k, ny, h->gGxx, h->gGxy, h->gGyy, h->gH, s);
+    syev_any(n, k, h->gH, h->glamn, h->gC, h->gsyw, h->info + 15, s);
+    // X_new = X C_X + Y C_Y (and its images), into the spare buffers
+    const double* Cy = h->gC + (size_t)k * k;
+    const double* xs[3] = {h->gX, h->gAX, h->gBX};
+    const double* ys[3] = {h->gY, h->gAY, h->gBY};
+    double* xn[3] = {h->gXn, h->gAXn, h->gBXn};
+    for (int q = 0; q < 3; ++q) {
+      launch_gemm(false, false, (int)Na, k, k, 1.0, xs[q], k, h->gC, k, 0.0, xn[q], k, s);
+      launch_gemm(false, false, (int)Na, k, ny, 1.0, ys[q], ny, Cy, k, 1.0, xn[q], k, s);
+    }
+    // step 6: P = Y C_Y for the active pairs (the part of X_new outside X)
+    launch_gather_cols(ny, k, ka, h->gidx, Cy, h->gCJ, s);
+    double* pn[3] = {h->gPn, nullptr, h->gBPn};   // A~ P is not needed: A~ Y is applied afresh
+    for (int q = 0; q < 3; q += 2)
+      launch_gemm(false, false, (int)Na, ka, ny, 1.0, ys[q], ny, h->gCJ, ka, 0.0, pn[q], ka, s);
+    std::swap(h->gX, h->gXn);
+    std::swap(h->gAX, h->gAXn);
+    std::swap(h->gBX, h->gBXn);
+    std::swap(h->gP, h->gPn);
+    std::swap(h->gBP, h->gBPn);
+    std::swap(h->glam, h->glamn);
+    kp_prev = kp;
+    kp = ka;
+    ++it;
+  }
+  h->aug_iters += it;
+  return PASE_OK;
+}
+
 // One correction from (lam, U), U^T M U = I, with R = lam M U - A U already in h->R: everything
 // up to the new U in h->U is enqueued; with the structured small solver the result is speculative
 // (h->spec) until correction_resolve has seen its status.
@@ -750,6 +1088,20 @@ pase_status correction_enqueue(pase_handle* h, int k) {
   }
   double* W = h->X;
   mark(h, PH_PROJECTION);
+  if (h->gcg) {
+    // PRECOND-A and GCG_AUG (Alg. 5): transform, solve, and u = I_H^h u~_H + W~ gamma~
+    gcg_projection(h, k);
+    mark(h, PH_SMALL);
+    h->spec = false;
+    const pase_status st = gcg_small(h, k);
+    if (st) return st;
+    h->last_path = 4;
+    mark(h, PH_PROLONG);
+    launch_copy((size_t)k, h->glam, h->lam, s);
+    prolong_from(h, h->gc, k, h->gX, h->U, 0);
+    launch_tsmm(N, k, h->X, h->gX + (size_t)h->gNH * k, h->U, 1, 0, s);
+    return PASE_OK;
+  }
   // complement: W <- W - P B_H^{-1} P^T M W
   apply_AM(h, 0, k, W, nullptr, h->W3);
   restrict_all(h, k, h->W3, h->ca);
@@ -870,6 +1222,7 @@ void pase_options_default(pase_options* opt) {
   opt->guard = 0;
   opt->start = 0;
   opt->fallback_ratio = 0.5;
+  opt->coarse_level = 0;
 }
 
 const char* pase_status_string(pase_status s) {
@@ -1018,7 +1371,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   launch_gemm(false, false, NH, NH, NH, 1.0, h->LBinv, NH, AL, NH, 0.0, tmp, NH, s);
   launch_gemm(false, true, NH, NH, NH, 1.0, tmp, NH, h->LBinv, NH, 0.0, h->C0, NH, s);
   launch_symmetrize(NH, h->C0, s);
-  if (h->fast) {
+  if (h->fast || h->psi_only) {
     // C0 = Phi diag(theta) Phi^T (all N_H pairs, dense solver), Psi = L_B^{-T} Phi
     HIPS(hipMemcpyAsync(h->Tm, h->C0, sizeof(double) * NH * NH, hipMemcpyDeviceToDevice, s));
     double* Phi = h->dtmp;
@@ -1033,6 +1386,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
     fail(h, PASE_E_BREAKDOWN, "coarse Cholesky failed");
     return bail(PASE_E_BREAKDOWN);
   }
+  if (h->psi_only && inf[10]) h->psi_only = false;   // no coarse start then
   if (h->fast) {
     if (inf[10]) {
       h->fast = false;   // the dense path stays available
@@ -1050,12 +1404,13 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   for (hipEvent_t& e : h->evm) HIPS(hipEventCreate(&e));
   {
     const size_t Kp = (size_t)h->K;
-    HIPS(hipHostMalloc(&h->pin, sizeof(double) * 5 * Kp + sizeof(int) * (Kp + 20), hipHostMallocDefault));
+    HIPS(hipHostMalloc(&h->pin, sizeof(double) * 7 * Kp + sizeof(int) * (Kp + 20), hipHostMallocDefault));
     double* pd = (double*)h->pin;
     h->pin_sums = pd;
     h->pin_lam = pd + 3 * Kp;
     h->pin_tolv = pd + 4 * Kp;
-    int* pi = (int*)(pd + 5 * Kp);
+    h->pin_gnorm = pd + 5 * Kp;
+    int* pi = (int*)(pd + 7 * Kp);
     h->pin_info = pi;
     h->pin_st = pi + 16;
     h->pin_idx = pi + 20;
@@ -1165,7 +1520,10 @@ pase_status pase_gram_bf16x3(pase_handle* h, long long N, int k, const float* X,
   return PASE_OK;
 }
 
-int pase_small_eig_max_n(const pase_handle* h) { return (h && h->Tm) ? std::min(h->nT, syev_large_max_n()) : 0; }
+int pase_small_eig_max_n(const pase_handle* h) {
+  // a GCG_AUG handle keeps no dense augmented matrix (its Tm, if any, holds the coarse start's C0)
+  return (h && h->Tm && !h->gcg) ? std::min(h->nT, syev_large_max_n()) : 0;
+}
 
 pase_status pase_small_eig(pase_handle* h, int n, int k, const double* T, double* w_host, double* V) {
   pase_status st = check_k(h, k);
@@ -1187,7 +1545,8 @@ pase_status pase_small_eig(pase_handle* h, int n, int k, const double* T, double
 pase_status pase_correction(pase_handle* h, int k, double* lambda_host, double* U) {
   pase_status st = check_k(h, k);
   if (st) return st;
-  if (!h->Tm) return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
+  if (!h->Tm && !h->gcg)
+    return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
   if (!lambda_host || !U) return fail(h, PASE_E_ARG, "null argument");
   const long long N = h->lev[0].N;
   hipStream_t s = h->stream;
@@ -1218,10 +1577,11 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   pase_status st = check_k(h, nev);
   if (st) return st;
   if (nev > h->opt.nev_max) return fail(h, PASE_E_ARG, "nev must be in [1, nev_max]");
-  if (!h->Tm) return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
+  if (!h->Tm && !h->gcg)
+    return fail(h, PASE_E_UNSUPPORTED, "small problem larger than the dense eigensolver supports");
   if (!lambda_host || !U) return fail(h, PASE_E_ARG, "null argument");
-  if (h->opt.start == 1 && !(h->fast && h->Psi))
-    return fail(h, PASE_E_UNSUPPORTED, "the coarse start needs the structured small solver's coarse eigenbasis");
+  if (h->opt.start == 1 && !((h->fast || h->psi_only) && h->Psi))
+    return fail(h, PASE_E_UNSUPPORTED, "the coarse start needs the coarsest level's eigenbasis");
   if (!(tol > 0.0)) return fail(h, PASE_E_ARG, "tol must be positive");
   const int k = nev + h->opt.guard;   // block size: the wanted pairs and the guard pairs
   h->nev_cur = nev;
@@ -1235,7 +1595,8 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   HIPC(hipMemsetAsync(h->info, 0, 16 * sizeof(int), s));
   h->fast_hits = 0;
   h->fallbacks = 0;
-  h->proj_lp = (h->opt.precision == PASE_PREC_MIXED && k <= 128);   // the split-BF16 Gram's limit
+  h->proj_lp = (h->opt.precision == PASE_PREC_MIXED && k <= 128 && !h->gcg);   // the split-BF16 Gram's limit
+  h->aug_iters = 0;
   h->proj_lp_iters = 0;
   h->ka = 0;
   h->fine_cols = 0;
@@ -1394,6 +1755,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     rep->learned_fallbacks = h->fallbacks;
     rep->lowprec_projection_iters = h->proj_lp_iters;
     rep->fine_solve_columns = h->fine_cols;
+    rep->aug_iters = h->aug_iters;
     if (rep->res_host) std::memcpy(rep->res_host, res.data(), sizeof(double) * nev);
     if (rep->res_literal_host) std::memcpy(rep->res_literal_host, lit.data(), sizeof(double) * nev);
   }

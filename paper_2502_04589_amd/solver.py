@@ -30,7 +30,7 @@ class Solver:
 
     dim:     2 or 3.
     levels:  elements per side of each grid, fine first, halving each time;
-             the last one is the coarse space V_H.
+             the last one is the coarse space V_H unless coarse_level says otherwise.
     kappa:   None (kappa = 1) or n^dim element values, x fastest (array or tensor).
     nev_max: largest nev a solve may ask for.
     locking: True (default): a correction's fine solves skip the pairs whose residual is already
@@ -42,11 +42,15 @@ class Solver:
              uniform(-1, 1) block); "coarse": from the smallest eigenvectors of the coarse pencil,
              interpolated to the fine mesh (Alg. 3 steps 1-2).
     fallback_ratio: learned form's switch to the V-cycle (default 0.5).
+    small_solver: the augmented eigenproblem's solver: "auto" (structured shift-invert path with a
+             dense fallback), "dense", or "gcg" (PRECOND-A and GCG_AUG, Sec. 4: matrix-free, so
+             V_H may be a level whose N_H no dense eigensolver reaches).
+    coarse_level: index in levels of V_H (None = the last; levels above the last need "gcg").
     """
 
     def __init__(self, dim, levels, kappa=None, nev_max=16, precision="fp64", cg_steps=2, max_outer=500,
                  nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0", locking=True, guard=0,
-                 start="given", fallback_ratio=0.5):
+                 start="given", fallback_ratio=0.5, coarse_level=None):
         self.lib = nat.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
@@ -76,11 +80,12 @@ class Solver:
         opt.max_outer = int(max_outer)
         opt.nu = int(nu)
         opt.omega = float(omega)
-        opt.small_solver = {"auto": 0, "dense": 1}[small_solver]
+        opt.small_solver = {"auto": 0, "dense": 1, "gcg": 2}[small_solver]
         opt.locking = 1 if locking else 0
         opt.guard = int(guard)
         opt.start = {"given": 0, "coarse": 1}[start]
         opt.fallback_ratio = float(fallback_ratio)
+        opt.coarse_level = 0 if coarse_level is None else int(coarse_level)
         self.opt = opt
         nbytes = C.c_size_t(0)
         self._check(self.lib.pase_workspace_bytes(C.byref(prob), C.byref(opt), C.byref(nbytes)), None)
@@ -152,6 +157,7 @@ class Solver:
                   "lowprec_projection_iters": rep.lowprec_projection_iters,
                   "fine_solve_columns": rep.fine_solve_columns,
                   "t_phase_ms": {name: float(rep.t_phase_ms[i]) for i, name in enumerate(nat.PHASES)},
+                  "aug_iters": rep.aug_iters,
                   "status": nat.STATUS.get(st, st)}
         if history:
             report["ritz_history"] = hist[:rep.ritz_history_rows].copy()
