@@ -128,8 +128,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="kappa3d-128", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp64,mixed,learned",
-                    help="comma list of fp64, mixed, learned, as_stated (fp64 is always run; as_stated = a block "
+    ap.add_argument("--forms", default="fp64,mixed,learned,precond_a",
+                    help="comma list of fp64, mixed, learned, precond_a, as_stated (fp64 is always run; "
+                         "precond_a = V_H one level finer, solved by PRECOND-A and GCG_AUG; as_stated = a block "
                          "of exactly nev, every pair every correction, which needs about 1000 corrections on "
                          "kappa3d-128)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -169,14 +170,15 @@ def main():
             return None
         return torch.from_numpy(synth.initial_vectors(s.N[0], nev, 0)).cuda()
 
-    def run_form(precision, net=None, steps=None, warmup=None, locking=True, g=None, st=None, strict=None):
+    def run_form(precision, net=None, steps=None, warmup=None, locking=True, g=None, st=None, strict=None,
+                 solver_kw=None):
         steps = args.steps if steps is None else steps
         warmup = args.warmup if warmup is None else warmup
         g = guard if g is None else g
         st = start if st is None else st
         t0 = time.perf_counter()
         s = Solver(dim, levels, kappa, nev_max=nev, precision=precision, locking=locking, guard=g, start=st,
-                   max_outer=1000)
+                   max_outer=1000, **(solver_kw or {}))
         if net is not None:
             s.attach(net)
         torch.cuda.synchronize()
@@ -203,13 +205,17 @@ def main():
                "max_res": float(np.max(rep["res"])), "block": nev + g, "locking": locking, "start": st,
                "fine_solve_columns": rep["fine_solve_columns"],
                "device_ms_per_phase": {k_: round(v, 2) for k_, v in rep["t_phase_ms"].items()},
-               "small_problem": {"structured": int(np.sum(paths >= 1)), "structured_wanted_pairs_only":
-                                 int(np.sum(paths == 2)), "structured_after_retry": int(np.sum(paths == 3)),
-                                 "dense": int(np.sum(paths <= 0))}}
+               "small_problem": {"structured": int(np.sum((paths >= 1) & (paths <= 3))),
+                                 "structured_wanted_pairs_only": int(np.sum(paths == 2)),
+                                 "structured_after_retry": int(np.sum(paths == 3)),
+                                 "gcg_aug": int(np.sum(paths == 4)), "dense": int(np.sum(paths <= 0))}}
         if precision == "learned":
             out["learned_fallbacks"] = rep["learned_fallbacks"]
         if precision == "mixed":
             out["lowprec_projection_iters"] = rep["lowprec_projection_iters"]
+        if solver_kw and solver_kw.get("small_solver") == "gcg":
+            out["gcg_aug_iters"] = rep["aug_iters"]
+            out["gcg_aug_restarts"] = rep["aug_restarts"]
         if kseed is None:
             from tests.closed_form import q1_laplace_eigs
             rel = np.abs(lam / q1_laplace_eigs(dim, levels[0], nev) - 1.0)
@@ -289,6 +295,14 @@ def main():
         learned["max_rel_diff_vs_fp64"] = float(np.max(np.abs(lam_l / lam_plain - 1.0)))
         results["learned"] = learned
         del net
+    if "precond_a" in forms and len(levels) >= 3:
+        # Sec. 4: V_H one level finer (the same hierarchy; the V-cycle still ends on the coarsest level),
+        # the augmented problem by PRECOND-A and GCG_AUG
+        c = len(levels) - 2
+        _, lam_g, gcgf = run_form("fp64", solver_kw=dict(small_solver="gcg", coarse_level=c))
+        gcgf["coarse_space"] = f"{levels[c]}^{dim} ({s.N[c]} DOFs)"
+        gcgf["max_rel_diff_vs_fp64"] = float(np.max(np.abs(lam_g / lam_plain - 1.0)))
+        results["precond_a"] = gcgf
     as_stated = None
     if "as_stated" in forms:
         # the algorithm as stated: a block of exactly nev, every pair's fine solves every correction
@@ -349,6 +363,7 @@ def main():
         "ratios": {
             "mixed_over_fp64": results["mixed"]["value"] / plain["value"] if "mixed" in results else None,
             "learned_over_fp64": results["learned"]["value"] / plain["value"] if "learned" in results else None,
+            "precond_a_over_fp64": results["precond_a"]["value"] / plain["value"] if "precond_a" in results else None,
             "tuned_over_as_stated": plain["value"] / as_stated["value"] if as_stated else None,
             "locking_gain": plain["value"] / oracle_cfg["value"] if oracle_cfg else None,
         },
@@ -360,6 +375,9 @@ def main():
                        "output scaled by ||r|| D^-1) with per-column V-cycle fallback; trained on pairs from other "
                        "kappa fields on a 64^3 mesh; training time not in value",
             "as_stated": "block of exactly nev, no locking, same start (the algorithm with no guard pairs)",
+            "precond_a": "V_H one level finer than the workload's (same GMG hierarchy), augmented problem by "
+                         "PRECOND-A and GCG_AUG (Sec. 4, Alg. 4-5), matrix-free; not the workload's V_H, so not "
+                         "value",
             "oracle_config": "same block and start as value, every pair every correction (no locking): the "
                              "configuration the CPU oracle runs",
         },

@@ -115,6 +115,10 @@ typedef struct pase_options {
                                     whose dense inverse is its bottom solve).  With the coarse start
                                     (start = 1) the start block comes from the coarsest level's
                                     eigenvectors. */
+  double aug_rtol;               /* small_solver 2: GCG_AUG stops when every pair's relative residual
+                                    in the augmented problem is at most max(1e-11, aug_rtol times the
+                                    outer residual of the same pair) (default 1e-2; 0: always to
+                                    1e-11, or until the residuals stagnate) */
 } pase_options;
 
 /* Filled by pase_solve.  Array members are optional HOST buffers (NULL = not wanted). */
@@ -153,6 +157,9 @@ typedef struct pase_report {
                                     structured path, retry and dense path, or GCG_AUG); [5]
                                     prolongation (step 6: u = P y_H + W y_W) */
   int aug_iters;                 /* small_solver 2: GCG_AUG iterations summed over the corrections */
+  int aug_restarts;              /* small_solver 2: GCG_AUG iterations whose orthonormalisation or
+                                    Rayleigh-Ritz broke down (each was redone without the P block,
+                                    or ended the augmented solve at the last good iterate) */
 } pase_report;
 
 typedef struct pase_handle pase_handle;

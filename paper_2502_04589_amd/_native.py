@@ -23,7 +23,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("nev_max", C.c_int), ("cg_steps", C.c_int), ("max_outer", C.c_int),
                 ("nu", C.c_int), ("omega", C.c_double), ("small_solver", C.c_int), ("locking", C.c_int),
                 ("guard", C.c_int), ("start", C.c_int), ("fallback_ratio", C.c_double),
-                ("coarse_level", C.c_int)]
+                ("coarse_level", C.c_int), ("aug_rtol", C.c_double)]
 
 
 class Report(C.Structure):
@@ -32,7 +32,8 @@ class Report(C.Structure):
                 ("ritz_history_rows", C.c_int), ("t_solve_ms", C.c_double), ("small_fast_iters", C.c_int),
                 ("small_path_host", C.c_void_p), ("learned_fallbacks", C.c_int),
                 ("lowprec_projection_iters", C.c_int), ("fine_solve_columns", C.c_int),
-                ("t_phase_ms", C.c_double * 6), ("aug_iters", C.c_int)]
+                ("t_phase_ms", C.c_double * 6), ("aug_iters", C.c_int),
+                ("aug_restarts", C.c_int)]
 
 # names of pase_report.t_phase_ms's entries, in order
 PHASES = ("start", "residual", "fine_solves", "projection", "small_problem", "prolongation")

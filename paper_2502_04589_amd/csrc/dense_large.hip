@@ -171,15 +171,30 @@ __global__ __launch_bounds__(1024) void chol_diag_kernel(int b, double* A, int l
   if (tid == 0 && fail) *info = off + fail;
 }
 
-// Li (b x b, ld ldi) = inverse of the lower b x b block L (ld ldl); one thread per column.
-__global__ void trinv_diag_kernel(int b, const double* __restrict__ L, int ldl, double* __restrict__ Li, int ldi) {
+// Li (b x b, ld ldi) = inverse of the lower b x b block L (ld ldl), b <= kNB: L staged in LDS,
+// one thread per column of the inverse (forward substitution in LDS), then written back.
+__global__ __launch_bounds__(kNB) void trinv_diag_kernel(int b, const double* __restrict__ L, int ldl,
+                                                         double* __restrict__ Li, int ldi) {
+  __shared__ double sL[kNB][kNB + 1];
+  __shared__ double sX[kNB][kNB + 1];
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+    const int i = e / b, j = e % b;
+    sL[i][j] = (j <= i) ? L[(size_t)i * ldl + j] : 0.0;
+  }
+  __syncthreads();
   const int c = threadIdx.x;
-  if (c >= b) return;
-  for (int i = 0; i < c; ++i) Li[(size_t)i * ldi + c] = 0.0;
-  for (int i = c; i < b; ++i) {
-    double s = (i == c) ? 1.0 : 0.0;
-    for (int l = c; l < i; ++l) s -= L[(size_t)i * ldl + l] * Li[(size_t)l * ldi + c];
-    Li[(size_t)i * ldi + c] = s / L[(size_t)i * ldl + i];
+  if (c < b) {
+    for (int i = 0; i < c; ++i) sX[i][c] = 0.0;
+    for (int i = c; i < b; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int l = c; l < i; ++l) s = fma(-sL[i][l], sX[l][c], s);
+      sX[i][c] = s / sL[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+    const int i = e / b, j = e % b;
+    Li[(size_t)i * ldi + j] = sX[i][j];
   }
 }
 

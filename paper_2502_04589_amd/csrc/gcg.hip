@@ -130,6 +130,22 @@ __global__ void sub_kernel(long long n, const double* __restrict__ a, const doub
     c[e] = (a ? a[e] : 0.0) - (b ? b[e] : 0.0);
 }
 
+// d[j] = 1 / sqrt(G_jj) (the smallest positive double when G_jj <= 0)
+__global__ void inv_sqrt_diag_kernel(int n, const double* __restrict__ G, double* __restrict__ d) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const double g = G[(size_t)j * n + j];
+    d[j] = 1.0 / sqrt(g > 2.2250738585072014e-308 ? g : 2.2250738585072014e-308);
+  }
+}
+
+// G <- D G D (rows and columns scaled by d); with cols_only, only the columns: M <- M D
+__global__ void scale_sym_kernel(int n, double* __restrict__ G, const double* __restrict__ d, int cols_only) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+    const int i = e / n, j = e % n;
+    G[e] *= cols_only ? d[j] : d[i] * d[j];
+  }
+}
+
 inline unsigned grid_for(long long n) {
   long long b = (n + 255) / 256;
   if (b > 4096) b = 4096;
@@ -175,6 +191,15 @@ void launch_assemble_rr(int k, int ny, const double* Gxx, const double* Gxy, con
                         hipStream_t s) {
   const int n = k + ny;
   assemble_rr_kernel<<<grid_for((long long)n * n), 256, 0, s>>>(k, ny, Gxx, Gxy, Gyy, H);
+}
+
+void launch_unit_diag(int n, double* G, double* d, hipStream_t s) {
+  inv_sqrt_diag_kernel<<<grid_for(n), 256, 0, s>>>(n, G, d);
+  scale_sym_kernel<<<grid_for((long long)n * n), 256, 0, s>>>(n, G, d, 0);
+}
+
+void launch_scale_cols_sq(int n, double* M, const double* d, hipStream_t s) {
+  scale_sym_kernel<<<grid_for((long long)n * n), 256, 0, s>>>(n, M, d, 1);
 }
 
 void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s) {

@@ -197,6 +197,9 @@ void launch_assemble_rr(int k, int ny, const double* Gxx, const double* Gxy, con
                         hipStream_t s);
 void launch_ltl(int k, const double* Li, double* C, hipStream_t s);             // C = Li^T Li
 void launch_sub(long long n, const double* a, const double* b, double* c, hipStream_t s);   // c = a - b (null = 0)
+// n x n G <- D G D with D = diag(G)^{-1/2} (d gets D's diagonal); M <- M D for an n x n M
+void launch_unit_diag(int n, double* G, double* d, hipStream_t s);
+void launch_scale_cols_sq(int n, double* M, const double* d, hipStream_t s);
 
 // ---- dense single-workgroup kernels (dense.hip)
 // In-place lower Cholesky of an n x n SPD matrix (row-major); info[0] = 0 ok, j+1 if pivot j failed.

@@ -124,6 +124,7 @@ struct pase_handle {
   // ascending order (host copy set per correction, device copy small_tolv)
   double small_acc = 1e-11;
   std::vector<double> tolv_host;
+  std::vector<double> outer_res;    // the outer residuals of the pairs before this correction
   double* small_tolv = nullptr;
   bool tolv_on = false;
   int fine_cols = 0;
@@ -145,6 +146,7 @@ struct pase_handle {
   double *gsyw = nullptr, *gchs = nullptr, *gpart = nullptr, *gnorm = nullptr;
   int* gidx = nullptr;
   int aug_iters = 0;                // GCG_AUG iterations of this solve
+  int aug_restarts = 0;             // ... and its iterations redone after a breakdown
   double* pin_gnorm = nullptr;      // pinned: 2 K column norms
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // per-phase device time of a solve: marks (event, phase) enqueued on the stream and resolved after
@@ -224,6 +226,7 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (!(o->omega > 0.0)) return PASE_E_ARG;
   if (o->small_solver < 0 || o->small_solver > 2) return PASE_E_ARG;
   if (o->coarse_level < 0 || o->coarse_level >= p->nlevels) return PASE_E_ARG;
+  if (!(o->aug_rtol >= 0.0)) return PASE_E_ARG;
   if (o->coarse_level != 0 && o->coarse_level != p->nlevels - 1 && o->small_solver != 2)
     return PASE_E_UNSUPPORTED;   // V_H below the coarsest level: GCG_AUG only
   if (o->locking != 0 && o->locking != 1) return PASE_E_ARG;
@@ -932,8 +935,9 @@ pase_status gcg_small(pase_handle* h, int k) {
   syev_any(k, k, h->gGxx, h->glam, h->gC, h->gsyw, h->info + 12, s);
   gcg_rotate(h, Na, k, h->gC);
   std::vector<double> tol(k, kGcgTolFloor);
-  if (h->tolv_on)
-    for (int j = 0; j < k && j < (int)h->tolv_host.size(); ++j) tol[j] = kGcgTolFloor * h->tolv_host[j];
+  if (h->tolv_on && h->opt.aug_rtol > 0.0)
+    for (int j = 0; j < k && j < (int)h->outer_res.size(); ++j)
+      tol[j] = std::max(kGcgTolFloor, h->opt.aug_rtol * h->outer_res[j]);
   std::vector<int> act;
   int kp = 0, kp_prev = 0, it = 0, since = 0;
   double best = 1e300;
@@ -957,6 +961,7 @@ pase_status gcg_small(pase_handle* h, int k) {
       std::swap(h->gBX, h->gBXn);
       std::swap(h->glam, h->glamn);
       launch_fill_int(3, 0, h->info + 13, s);
+      ++h->aug_restarts;
       if (retried || kp_prev == 0) break;
       retried = true;
       kp = 0;
@@ -1005,8 +1010,12 @@ pase_status gcg_small(pase_handle* h, int k) {
       aug_apply(h, k, ny, h->gY, nullptr, h->gBY);
       launch_gram_tn(Na, ny, ny, h->gY, ny, h->gBY, ny, h->gpart, h->gG, s);         // Y^T B~ Y
       launch_symmetrize(ny, h->gG, s);
+      // factor the unit-diagonal D G D (the remainders' norms span many orders, and the
+      // Cholesky's breakdown test is relative to the largest diagonal entry): Li = L^{-1} D
+      launch_unit_diag(ny, h->gG, h->gnorm, s);
       launch_cholesky_large(ny, h->gG, ny, h->gchs, h->info + 13 + pass, s);
       launch_trinv_large(ny, h->gG, ny, h->gLi, ny, h->gchs, s);
+      launch_scale_cols_sq(ny, h->gLi, h->gnorm, s);
       launch_gemm(false, true, (int)Na, ny, ny, 1.0, h->gY, ny, h->gLi, ny, 0.0, h->gY2, ny, s);
       std::swap(h->gY, h->gY2);
       aug_apply(h, k, ny, h->gY, pass == 1 ? h->gAY : nullptr, h->gBY);
@@ -1223,6 +1232,7 @@ void pase_options_default(pase_options* opt) {
   opt->start = 0;
   opt->fallback_ratio = 0.5;
   opt->coarse_level = 0;
+  opt->aug_rtol = 1e-2;
 }
 
 const char* pase_status_string(pase_status s) {
@@ -1597,6 +1607,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   h->fallbacks = 0;
   h->proj_lp = (h->opt.precision == PASE_PREC_MIXED && k <= 128 && !h->gcg);   // the split-BF16 Gram's limit
   h->aug_iters = 0;
+  h->aug_restarts = 0;
   h->proj_lp_iters = 0;
   h->ka = 0;
   h->fine_cols = 0;
@@ -1704,6 +1715,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
       // position j of the ascending order is accepted at residual max(1e-11, 1e-2 res_j) max|theta|
       h->tolv_host.resize(k);
       for (int j = 0; j < k; ++j) h->tolv_host[j] = std::max(1.0, 1e9 * res[j]);   // x 1e-11
+      h->outer_res.assign(res.begin(), res.begin() + k);
       h->small_acc = 1e-11;
       h->tolv_on = true;
       std::memcpy(h->pin_tolv, h->tolv_host.data(), sizeof(double) * k);
@@ -1756,6 +1768,7 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
     rep->lowprec_projection_iters = h->proj_lp_iters;
     rep->fine_solve_columns = h->fine_cols;
     rep->aug_iters = h->aug_iters;
+    rep->aug_restarts = h->aug_restarts;
     if (rep->res_host) std::memcpy(rep->res_host, res.data(), sizeof(double) * nev);
     if (rep->res_literal_host) std::memcpy(rep->res_literal_host, lit.data(), sizeof(double) * nev);
   }

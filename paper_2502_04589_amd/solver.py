@@ -46,11 +46,13 @@ class Solver:
              dense fallback), "dense", or "gcg" (PRECOND-A and GCG_AUG, Sec. 4: matrix-free, so
              V_H may be a level whose N_H no dense eigensolver reaches).
     coarse_level: index in levels of V_H (None = the last; levels above the last need "gcg").
+    aug_rtol: "gcg" only: GCG_AUG's stop, relative to each pair's outer residual (default 1e-2;
+             0: to 1e-11).
     """
 
     def __init__(self, dim, levels, kappa=None, nev_max=16, precision="fp64", cg_steps=2, max_outer=500,
                  nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0", locking=True, guard=0,
-                 start="given", fallback_ratio=0.5, coarse_level=None):
+                 start="given", fallback_ratio=0.5, coarse_level=None, aug_rtol=1e-2):
         self.lib = nat.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
@@ -86,6 +88,7 @@ class Solver:
         opt.start = {"given": 0, "coarse": 1}[start]
         opt.fallback_ratio = float(fallback_ratio)
         opt.coarse_level = 0 if coarse_level is None else int(coarse_level)
+        opt.aug_rtol = float(aug_rtol)
         self.opt = opt
         nbytes = C.c_size_t(0)
         self._check(self.lib.pase_workspace_bytes(C.byref(prob), C.byref(opt), C.byref(nbytes)), None)
@@ -157,7 +160,7 @@ class Solver:
                   "lowprec_projection_iters": rep.lowprec_projection_iters,
                   "fine_solve_columns": rep.fine_solve_columns,
                   "t_phase_ms": {name: float(rep.t_phase_ms[i]) for i, name in enumerate(nat.PHASES)},
-                  "aug_iters": rep.aug_iters,
+                  "aug_iters": rep.aug_iters, "aug_restarts": rep.aug_restarts,
                   "status": nat.STATUS.get(st, st)}
         if history:
             report["ritz_history"] = hist[:rep.ritz_history_rows].copy()
