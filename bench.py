@@ -277,6 +277,40 @@ def main():
                               "train_steps": args.train_steps, "fields": nf, "mesh": f"{tn}^3", "pairs": pairs,
                               "loss_first": losses[0], "loss_last": float(np.mean(losses[-20:]))}
 
+    def one_step_gain(net):
+        """On a held-out block of this workload (2 plain corrections from the solve's start), the median
+        ||r1|| / ||r0|| of one CG step preconditioned by the network and by the V-cycle, and the device
+        time of one application of each to the block."""
+        held = Solver(dim, levels, kappa, nev_max=nev, guard=guard, start=start, max_outer=2)
+        lam, U, _ = held.solve(nev, tol, start_block(held), raise_notconv=False)
+        AU, MU = held.apply(0, U)
+        rhs = MU * torch.from_numpy(lam).cuda()[None, :]
+        R = (rhs - AU).contiguous()
+        r0 = torch.linalg.norm(R, dim=0)
+        ratio = {}
+        for name, prec in (("vcycle", "fp64"), ("network", "learned")):
+            one = Solver(dim, levels, kappa, nev_max=nev, precision=prec, cg_steps=1)
+            if prec == "learned":
+                one.attach(net)
+            W = one.pcg(lam, U)
+            ratio[name] = float(torch.median(torch.linalg.norm(rhs - one.apply(0, W)[0], dim=0) / r0))
+            del one, W
+        lk = held.node_logk()
+        net.apply(R, lk)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            net.apply(R, lk)
+        e1.record()
+        torch.cuda.synchronize()
+        net_ms = e0.elapsed_time(e1) / 3
+        v_ms = held.time_kernel("vcycle", nev, reps=5)
+        del held
+        torch.cuda.empty_cache()
+        return {"residual_ratio_median": ratio, "network_apply_ms": net_ms, "vcycle_ms": v_ms,
+                "block": f"{nev} columns after 2 plain corrections from the solve's start"}
+
     s, lam_plain, plain = run_form("fp64")
     results = {"fp64": plain}
     if "mixed" in forms:
@@ -293,6 +327,7 @@ def main():
         _, lam_l, learned = run_form("learned", net, steps=args.learned_steps, warmup=min(args.warmup, 1))
         learned["training"] = training
         learned["max_rel_diff_vs_fp64"] = float(np.max(np.abs(lam_l / lam_plain - 1.0)))
+        learned["one_step"] = one_step_gain(net)
         results["learned"] = learned
         del net
     if "precond_a" in forms and len(levels) >= 3:
@@ -328,8 +363,10 @@ def main():
         traffic = SPMM_TRAFFIC["bytes"]
     mv = N * k * 8
     rates = {}
-    for name, key, nb in (("spmm_AX_MX", "apply", nbytes), ("cg_update", "cg_update", 6 * mv),
-                          ("vcycle_sweep", "sweep", 3 * mv + (n_elem * 8 if kseed is not None else 0))):
+    kb = n_elem * 8 if kseed is not None else 0
+    for name, key, nb in (("spmm_AX_MX", "apply", nbytes), ("spmm_AX", "apply_A", 2 * mv + kb),
+                          ("spmm_MX", "apply_M", 2 * mv), ("cg_update", "cg_update", 6 * mv),
+                          ("vcycle_sweep", "sweep", 3 * mv + kb)):
         t = ms if key == "apply" else s.time_kernel(key, k, reps=30)
         gbs = nb / (t * 1e-3) / 1e9
         rates[name] = {"us": t * 1e3, "bytes": nb, "GB/s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS}
