@@ -76,6 +76,14 @@ typedef struct pase_problem {
   int nlevels;                   /* 2 .. PASE_MAX_LEVELS */
   int n[PASE_MAX_LEVELS];        /* elements per side; n[l] = 2*n[l+1], n[last] >= 2 */
   const double* kappa;           /* device, n[0]^dim element values (x fastest), or NULL for kappa = 1 */
+  const double* tensor;          /* 3D only, NULL for the kappa problem: the tensor-coefficient workload
+                                    of Sec. 5, eq. (general): -div(T grad u) + phi u = lambda u with T
+                                    symmetric positive definite and constant per element, device
+                                    n[0]^3 x 6 (a11, a12, a13, a22, a23, a33 per element, x fastest);
+                                    kappa must then be NULL.  Read during pase_setup only: the fine
+                                    operator is assembled into a 27-point stencil per node. */
+  const double* reaction;        /* with tensor: device n[0]^3 element values of phi (>= 0), or NULL
+                                    for phi = 0 */
 } pase_problem;
 
 typedef struct pase_options {

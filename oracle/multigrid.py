@@ -56,12 +56,14 @@ class Hierarchy:
     Pc: composite interpolation from the coarsest level to level 0.
     """
 
-    def __init__(self, dim, levels, kappa=None, omega=2.0 / 3.0, nu=2):
+    def __init__(self, dim, levels, kappa=None, omega=2.0 / 3.0, nu=2, operator=None):
+        """``operator``: optional (A0, M0) fine-level pair given in place of the kappa assembly
+        (the tensor-coefficient workload, ``fem.assemble_general``)."""
         self.dim = dim
         self.n = list(levels)
         self.omega = omega
         self.nu = nu
-        A0, M0 = fem.assemble(dim, self.n[0], kappa)
+        A0, M0 = fem.assemble(dim, self.n[0], kappa) if operator is None else operator
         self.A = [A0]
         self.M = [M0]
         self.P = [None]

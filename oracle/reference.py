@@ -22,10 +22,11 @@ import scipy.sparse.linalg as spla
 from . import fem
 
 
-def lowest_eigenpairs(dim: int, n: int, k: int, kappa=None, vectors: bool = False):
+def lowest_eigenpairs(dim: int, n: int, k: int, kappa=None, vectors: bool = False, operator=None):
     """The k smallest eigenvalues (ascending) of the Q1 pencil (A, M) on the n^dim mesh,
-    and with ``vectors`` the M-orthonormal eigenvectors (N x k)."""
-    A, M = fem.assemble(dim, n, kappa)
+    and with ``vectors`` the M-orthonormal eigenvectors (N x k).  ``operator``: an assembled
+    (A, M) pair in place of the kappa assembly (the tensor-coefficient workload)."""
+    A, M = fem.assemble(dim, n, kappa) if operator is None else operator
     w, V = spla.eigsh(A.tocsc(), k=k, M=M.tocsc(), sigma=0.0, which="LM", tol=1e-14)
     order = np.argsort(w)
     w = w[order]

@@ -16,7 +16,8 @@ PREC = {"fp64": 0, "mixed": 1, "learned": 2}
 
 
 class Problem(C.Structure):
-    _fields_ = [("dim", C.c_int), ("nlevels", C.c_int), ("n", C.c_int * MAX_LEVELS), ("kappa", C.c_void_p)]
+    _fields_ = [("dim", C.c_int), ("nlevels", C.c_int), ("n", C.c_int * MAX_LEVELS), ("kappa", C.c_void_p),
+                ("tensor", C.c_void_p), ("reaction", C.c_void_p)]
 
 
 class Options(C.Structure):

@@ -594,6 +594,62 @@ __global__ void extract_galerkin_kernel(int m, const double* __restrict__ Y, dou
   dinv[i] = 1.0 / coef[i * NS + NS / 2];
 }
 
+// 1D Q1 integrals on a cell [0, h] for local vertices i, j in {0, 1}: stiffness, mass, and the
+// derivative-value product int phi_i' phi_j (independent of j)
+__device__ inline double q1_s(int i, int j, double h) { return (i == j ? 1.0 : -1.0) / h; }
+__device__ inline double q1_m(int i, int j, double h) { return (i == j ? 2.0 : 1.0) * h / 6.0; }
+__device__ inline double q1_g(int i) { return i ? 0.5 : -0.5; }
+
+// Element matrix entry between local vertices I and J of a cube cell of side h, for the constant
+// symmetric tensor T (a11, a12, a13, a22, a23, a33) and reaction phi:
+// int grad phi_I . T grad phi_J + phi phi_I phi_J.  Tensor-product factors: the diagonal terms are
+// s m m and its permutations, an off-diagonal pair (a, b) gives T_ab (g_I_a g_J_b + g_I_b g_J_a) m_c.
+__device__ double general_entry(const double* T, double phi, const int* I, const int* J, double h) {
+  double S[3], Mv[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    S[d] = q1_s(I[d], J[d], h);
+    Mv[d] = q1_m(I[d], J[d], h);
+  }
+  double v = phi * Mv[0] * Mv[1] * Mv[2];
+  v += T[0] * S[0] * Mv[1] * Mv[2] + T[3] * Mv[0] * S[1] * Mv[2] + T[5] * Mv[0] * Mv[1] * S[2];
+  v += T[1] * (q1_g(I[0]) * q1_g(J[1]) + q1_g(J[0]) * q1_g(I[1])) * Mv[2];
+  v += T[2] * (q1_g(I[0]) * q1_g(J[2]) + q1_g(J[0]) * q1_g(I[2])) * Mv[1];
+  v += T[4] * (q1_g(I[1]) * q1_g(J[2]) + q1_g(J[1]) * q1_g(I[2])) * Mv[0];
+  return v;
+}
+
+// Fine-level 27-point stencil of A = -div(T grad) + phi (3D, T and phi constant per element), one
+// thread per interior node: coefficient o sums the element entries of the (up to 8) cells that
+// hold both the node and its neighbour o; coefficients to nodes outside the domain are 0.
+__global__ void assemble_general_kernel(int n, const double* __restrict__ tensor, const double* __restrict__ reaction,
+                                        double* __restrict__ coef, double* __restrict__ dinv) {
+  const int m = n - 1;
+  const long long N = (long long)m * m * m;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int x = (int)(i % m), y = (int)((i / m) % m), z = (int)(i / ((long long)m * m));
+  const double h = 1.0 / n;
+  for (int o = 0; o < 27; ++o) {
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+    const bool ok = x + ox >= 0 && x + ox < m && y + oy >= 0 && y + oy < m && z + oz >= 0 && z + oz < m;
+    double v = 0.0;
+    if (ok) {
+      for (int a = 0; a < 8; ++a) {
+        const int I[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
+        const int J[3] = {I[0] + ox, I[1] + oy, I[2] + oz};
+        if (J[0] < 0 || J[0] > 1 || J[1] < 0 || J[1] > 1 || J[2] < 0 || J[2] > 1) continue;
+        // the cell whose corner I is this node (full-grid node coordinate x + 1)
+        const long long e = (long long)(x + 1 - I[0]) + (long long)n * (y + 1 - I[1]) +
+                            (long long)n * n * (z + 1 - I[2]);
+        v += general_entry(tensor + e * 6, reaction ? reaction[e] : 0.0, I, J, h);
+      }
+    }
+    coef[i * 27 + o] = v;
+  }
+  dinv[i] = 1.0 / coef[i * 27 + 13];
+}
+
 template <int DIM>
 __global__ void stencil_to_dense_kernel(int m, const double* __restrict__ coef, double hmass, int use_mass,
                                         double* __restrict__ D) {
@@ -772,6 +828,12 @@ void launch_extract_galerkin(int dim, int m, const double* Y, double* coef, doub
   const long long N = (long long)m * m * (dim == 3 ? m : 1);
   if (dim == 3) extract_galerkin_kernel<3><<<nblk(N), kBlock, 0, s>>>(m, Y, coef, dinv);
   else extract_galerkin_kernel<2><<<nblk(N), kBlock, 0, s>>>(m, Y, coef, dinv);
+}
+
+void launch_assemble_general(int n, const double* tensor, const double* reaction, double* coef, double* dinv,
+                             hipStream_t s) {
+  const long long N = (long long)(n - 1) * (n - 1) * (n - 1);
+  assemble_general_kernel<<<nblk(N), kBlock, 0, s>>>(n, tensor, reaction, coef, dinv);
 }
 
 void launch_stencil_to_dense(int dim, int m, const double* coef, double hmass, int use_mass, double* D,

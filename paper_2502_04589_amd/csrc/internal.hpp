@@ -87,6 +87,10 @@ void launch_color_probe(int dim, int m, double* E, hipStream_t s);              
 void launch_extract_galerkin(int dim, int m, const double* Y, double* coef, double* dinv, hipStream_t s);
 void launch_stencil_to_dense(int dim, int m, const double* coef, double hmass, int use_mass, double* D,
                              hipStream_t s);
+// 3D fine-level 27-point stencil of -div(T grad) + phi from per-element T (upper triangle, 6 values)
+// and phi (may be null), and 1 / diag
+void launch_assemble_general(int n, const double* tensor, const double* reaction, double* coef, double* dinv,
+                             hipStream_t s);
 
 // ---- fine-level 3D LDS-staged stencil (stencil3d.hip)
 struct Fine3Args {

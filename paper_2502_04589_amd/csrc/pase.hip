@@ -70,6 +70,7 @@ struct pase_handle {
   double *vb[PASE_MAX_LEVELS] = {}, *vx[PASE_MAX_LEVELS] = {}, *vxa[PASE_MAX_LEVELS] = {}, *vr[PASE_MAX_LEVELS] = {};
   double* kappa = nullptr;
   bool kappa_is_one = false;    // problem given with kappa = NULL (constant coefficient)
+  bool fine_general = false;    // tensor-coefficient problem: the fine operator is an assembled stencil
   // coarse dense (NH x NH)
   double *AinvL = nullptr, *LBinv = nullptr, *BHinv = nullptr, *C0 = nullptr, *dtmp = nullptr;
   // small problem
@@ -236,6 +237,9 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (o->precision != PASE_PREC_FP64 && o->precision != PASE_PREC_MIXED && o->precision != PASE_PREC_LEARNED)
     return PASE_E_UNSUPPORTED;
   if (o->precision == PASE_PREC_LEARNED && p->dim != 3) return PASE_E_UNSUPPORTED;   // the network is 3D
+  if (p->tensor && (p->dim != 3 || p->kappa)) return PASE_E_ARG;
+  if (!p->tensor && p->reaction) return PASE_E_ARG;
+  if (p->tensor && o->precision == PASE_PREC_LEARNED) return PASE_E_UNSUPPORTED;   // the network reads log kappa
   return PASE_OK;
 }
 
@@ -263,6 +267,7 @@ size_t layout(pase_handle* h, void* base) {
   const long long ne = (long long)h->lev[0].n * h->lev[0].n * (dim == 3 ? h->lev[0].n : 1);
   h->kappa = b.take<double>((size_t)ne);
   h->lev[0].dinv = b.take<double>((size_t)N0);
+  if (h->fine_general) h->lev[0].coef = b.take<double>((size_t)N0 * h->NS);
   for (int l = 1; l <= h->L; ++l) {
     const size_t Nl = (size_t)h->lev[l].N;
     h->lev[l].coef = b.take<double>(Nl * NS);
@@ -392,7 +397,7 @@ StencilArgs stencil_args(pase_handle* h, int l, int k) {
   a.N = lv.N;
   a.k = k;
   a.h = lv.h;
-  a.src = (l == 0) ? ASource::Kappa : ASource::Assembled;
+  a.src = (l == 0 && !h->fine_general) ? ASource::Kappa : ASource::Assembled;
   a.kappa = h->kappa;
   a.coef = lv.coef;
   a.dinv = lv.dinv;
@@ -407,7 +412,7 @@ void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void
   // 3D: the LDS-tiled stencil on the fine level, and on every level when kappa = 1 (nested Q1
   // spaces with exact integration: the Galerkin operator P^T A P equals the Q1 stencil of the
   // coarse mesh, so the constant stencil of width h_l applies it)
-  if (h->dim == 3 && (l == 0 || h->kappa_is_one)) {
+  if (h->dim == 3 && !h->fine_general && (l == 0 || h->kappa_is_one)) {
     Fine3Args f{};
     f.m = h->lev[l].m;
     f.k = k;
@@ -438,7 +443,7 @@ void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void
 }
 
 int eigres_tiles(pase_handle* h, int k) {
-  if (h->dim == 3) return fine3_spatial_blocks(h->lev[0].m, fine3_default_nzc(h->lev[0].m));
+  if (h->dim == 3 && !h->fine_general) return fine3_spatial_blocks(h->lev[0].m, fine3_default_nzc(h->lev[0].m));
   return grid_launch(h->lev[0].N, k).tiles;
 }
 
@@ -503,7 +508,7 @@ void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x
   launch_restrict(h->dim, lv.m, h->lev[l + 1].m, k, B.r[l], B.b[l + 1], B.fp32, s);
   vcycle(h, B, l + 1, k, B.b[l + 1], B.x[l + 1]);
   launch_prolong(h->dim, lv.m, h->lev[l + 1].m, k, B.x[l + 1], cur, 1, B.fp32, s);
-  const bool fuse = dot && l == 0 && h->dim == 3;
+  const bool fuse = dot && l == 0 && h->dim == 3 && !h->fine_general;   // epilogues of the 3D fine kernel
   for (int i = 0; i < h->opt.nu; ++i) {
     const bool last = i + 1 == h->opt.nu;
     stencil_op(h, l, k, (fuse && last) ? EPI_SWEEPDOT : EPI_SWEEP, cur, b, oth, nullptr, B.fp32);
@@ -524,7 +529,7 @@ void vcycle(pase_handle* h, int l, int k, const double* b, double* x, double* do
 // Q = A P and pq[j] = p_j^T A p_j on level 0 (fused into the stencil on the 3D path)
 void apply_dot(pase_handle* h, int k, const void* P, void* Q, double* pq, int fp32) {
   const long long N = h->lev[0].N;
-  if (h->dim == 3) {
+  if (h->dim == 3 && !h->fine_general) {
     stencil_op(h, 0, k, EPI_AMDOT, P, nullptr, Q, nullptr, fp32);
     launch_reduce_partials(eigres_tiles(h, k), k, h->partial, pq, h->stream);
     return;
@@ -1261,6 +1266,7 @@ pase_status pase_workspace_bytes(const pase_problem* prob, const pase_options* o
   tmp.L = prob->nlevels - 1;
   tmp.NS = prob->dim == 3 ? 27 : 9;
   tmp.K = opt->nev_max + opt->guard;
+  tmp.fine_general = (prob->tensor != nullptr);
   for (int l = 0; l < prob->nlevels; ++l) {
     tmp.lev[l].n = prob->n[l];
     tmp.lev[l].m = prob->n[l] - 1;
@@ -1287,6 +1293,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   h->L = prob->nlevels - 1;
   h->NS = prob->dim == 3 ? 27 : 9;
   h->K = opt->nev_max + opt->guard;
+  h->fine_general = (prob->tensor != nullptr);
   for (int l = 0; l < prob->nlevels; ++l) {
     h->lev[l].n = prob->n[l];
     h->lev[l].m = prob->n[l] - 1;
@@ -1301,7 +1308,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   }
   layout(h, workspace);
   h->lev[0].kappa = h->kappa;
-  h->kappa_is_one = (prob->kappa == nullptr);
+  h->kappa_is_one = (prob->kappa == nullptr && !h->fine_general);
   hipStream_t s = h->stream;
   auto bail = [&](pase_status r) {
     g_last_error = h->err;
@@ -1331,7 +1338,8 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
     HIPS(hipStreamSynchronize(s));
   }
   HIPS(hipMemsetAsync(h->zero16, 0, 8 * sizeof(double), s));
-  launch_kappa_dinv(h->dim, f.n, h->kappa, h->lev[0].dinv, s);
+  if (h->fine_general) launch_assemble_general(f.n, prob->tensor, prob->reaction, h->lev[0].coef, h->lev[0].dinv, s);
+  else launch_kappa_dinv(h->dim, f.n, h->kappa, h->lev[0].dinv, s);
   if (h->logk) launch_node_logk(f.n, h->kappa, h->logk, s);
   // Galerkin stencils A_l = P_l^T A_{l-1} P_l from 3^d colour probes
   const int NS = h->NS;
@@ -1811,6 +1819,7 @@ pase_status pase_fine_diag_inverse(pase_handle* h, double* dinv) {
 pase_status pase_node_logk(pase_handle* h, double* logk) {
   if (!h || !logk) return fail(h, PASE_E_ARG, "null argument");
   if (h->dim != 3) return fail(h, PASE_E_UNSUPPORTED, "3D only");
+  if (h->fine_general) return fail(h, PASE_E_UNSUPPORTED, "the tensor-coefficient problem has no log kappa");
   launch_node_logk(h->lev[0].n, h->kappa, logk, h->stream);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(h->stream));

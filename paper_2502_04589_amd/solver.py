@@ -32,6 +32,9 @@ class Solver:
     levels:  elements per side of each grid, fine first, halving each time;
              the last one is the coarse space V_H unless coarse_level says otherwise.
     kappa:   None (kappa = 1) or n^dim element values, x fastest (array or tensor).
+    tensor, reaction: the tensor-coefficient workload (3D, kappa None): n^3 x 6 element values of the
+             symmetric coefficient (a11, a12, a13, a22, a23, a33) and n^3 values of the reaction
+             (None = 0); see synth.general_coefficients.
     nev_max: largest nev a solve may ask for.
     locking: True (default): a correction's fine solves skip the pairs whose residual is already
              below tol / 10 (they keep w = u; the Rayleigh-Ritz still uses every pair); False:
@@ -52,7 +55,7 @@ class Solver:
 
     def __init__(self, dim, levels, kappa=None, nev_max=16, precision="fp64", cg_steps=2, max_outer=500,
                  nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0", locking=True, guard=0,
-                 start="given", fallback_ratio=0.5, coarse_level=None, aug_rtol=1e-2):
+                 start="given", fallback_ratio=0.5, coarse_level=None, aug_rtol=1e-2, tensor=None, reaction=None):
         self.lib = nat.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
@@ -74,6 +77,20 @@ class Solver:
                 raise ValueError(f"kappa must have {ne} entries")
             self._kappa = kt.to(self.device).contiguous()
         prob.kappa = _ptr(self._kappa)
+        self._tensor = self._reaction = None
+        if tensor is not None:
+            ne = self.levels[0] ** self.dim
+            self._tensor = torch.as_tensor(tensor, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
+            if self._tensor.numel() != 6 * ne:
+                raise ValueError(f"tensor must have {6 * ne} entries")
+            if reaction is not None:
+                self._reaction = torch.as_tensor(reaction, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
+                if self._reaction.numel() != ne:
+                    raise ValueError(f"reaction must have {ne} entries")
+        elif reaction is not None:
+            raise ValueError("reaction needs tensor")
+        prob.tensor = _ptr(self._tensor)
+        prob.reaction = _ptr(self._reaction)
         opt = nat.Options()
         self.lib.pase_options_default(C.byref(opt))
         opt.precision = nat.PREC[precision]

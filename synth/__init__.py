@@ -22,12 +22,18 @@ Recipes
   FFT(w)) with L the (clipped, non-negative) DFT of the periodised
   covariance, then the first n cells per axis are kept.  Element (i, j, l)
   is stored at index i + n*j + n*n*l (x fastest).
+* ``general_coefficients(n)``: the coefficients of the second workload of
+  the paper's tests (Sec. 5, eq. general) on the uniform n^3 mesh, one value
+  per element, evaluated at the element centre c: the tensor
+  A(c) = I + (c - 1/2)(c - 1/2)^T, stored as its upper triangle
+  (a11, a12, a13, a22, a23, a33), and the reaction
+  phi(c) = exp((c1 - 1/2)(c2 - 1/2)(c3 - 1/2)).  No randomness.
 """
 from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["initial_vectors", "kappa_field", "interior_count"]
+__all__ = ["initial_vectors", "kappa_field", "interior_count", "general_coefficients"]
 
 
 def interior_count(dim: int, n: int) -> int:
@@ -65,3 +71,16 @@ def kappa_field(dim: int, n: int, seed: int, ell: float = 0.1, var: float = 1.0)
     # axes are (x, y[, z]) in 'ij' order; store x fastest -> transpose to (z, y, x)
     g = np.ascontiguousarray(np.transpose(g))
     return np.exp(g).reshape(-1)
+
+
+def general_coefficients(n: int):
+    """Element-centre tensor (n^3 x 6: a11, a12, a13, a22, a23, a33) and reaction (n^3) of the
+    problem -div(A grad u) + phi u = lambda u with A = I + (x - 1/2)(x - 1/2)^T and
+    phi = exp((x1 - 1/2)(x2 - 1/2)(x3 - 1/2)); element (i, j, l) at index i + n j + n^2 l."""
+    c = (np.arange(n) + 0.5) / n - 0.5
+    d1 = np.tile(c, n * n)
+    d2 = np.tile(np.repeat(c, n), n)
+    d3 = np.repeat(c, n * n)
+    tensor = np.stack([1.0 + d1 * d1, d1 * d2, d1 * d3, 1.0 + d2 * d2, d2 * d3, 1.0 + d3 * d3], axis=1)
+    reaction = np.exp(d1 * d2 * d3)
+    return np.ascontiguousarray(tensor), reaction

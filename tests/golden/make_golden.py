@@ -4,7 +4,9 @@
 
 Each entry is the k smallest eigenvalues of the Q1 pencil of -div(kappa grad u) = lambda u
 (Alg. 3 "Ensure"), computed by ``oracle.reference.lowest_eigenpairs`` from the seeded kappa field
-of ``synth.kappa_field``; the file records the recipe beside the values.
+of ``synth.kappa_field``, or of -div(A grad u) + phi u = lambda u (the tensor-coefficient workload,
+Sec. 5 eq. general) assembled by ``oracle.fem.assemble_general`` from ``synth.general_coefficients``;
+the file records the recipe beside the values.
 """
 from __future__ import annotations
 
@@ -19,7 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
-from oracle import reference  # noqa: E402
+from oracle import fem, reference  # noqa: E402
 
 # name: (dim, n, k, kappa seed or None)
 CASES = {
@@ -28,17 +30,27 @@ CASES = {
     # 32^3 fine mesh with the same 16^3 coarse space: 40 and 120 pairs of a kappa field
     "kappa3d_32_s5_k40": (3, 32, 40, 5),
     "kappa3d_32_s7_k120": (3, 32, 120, 7),
+    # the tensor-coefficient + reaction workload on 32^3 and 64^3 meshes (kappa seed "general")
+    "general3d_32_k40": (3, 32, 40, "general"),
+    "general3d_64_k40": (3, 64, 40, "general"),
 }
 
 
 def write(name):
     dim, n, k, seed = CASES[name]
-    kappa = None if seed is None else synth.kappa_field(dim, n, seed)
     t = time.time()
-    w = reference.lowest_eigenpairs(dim, n, k, kappa)
     path = os.path.join(HERE, name + ".npz")
-    np.savez(path, lam=w, dim=dim, n=n, k=k, kappa_seed=-1 if seed is None else seed,
-             recipe="oracle.reference.lowest_eigenpairs(dim, n, k, synth.kappa_field(dim, n, kappa_seed))")
+    if seed == "general":
+        tensor, reaction = synth.general_coefficients(n)
+        w = reference.lowest_eigenpairs(dim, n, k, operator=fem.assemble_general(n, tensor, reaction))
+        np.savez(path, lam=w, dim=dim, n=n, k=k, kappa_seed=-2,
+                 recipe="oracle.reference.lowest_eigenpairs(dim, n, k, operator=oracle.fem.assemble_general("
+                        "n, *synth.general_coefficients(n)))")
+    else:
+        kappa = None if seed is None else synth.kappa_field(dim, n, seed)
+        w = reference.lowest_eigenpairs(dim, n, k, kappa)
+        np.savez(path, lam=w, dim=dim, n=n, k=k, kappa_seed=-1 if seed is None else seed,
+                 recipe="oracle.reference.lowest_eigenpairs(dim, n, k, synth.kappa_field(dim, n, kappa_seed))")
     print(f"{name}: {time.time() - t:.1f} s -> {path}", flush=True)
 
 
