@@ -50,6 +50,10 @@ WORKLOADS = {
     # config 1: 2D 128^2 Laplace, V_H = 16^2, nev 10, tol 1e-10
     "laplace2d-128": dict(dim=2, levels=[128, 64, 32, 16], nev=10, tol=1e-10, kappa_seed=None, guard=0,
                           start="given", train_n=None),
+    # the paper's second test problem (Sec. 5, eq. general): tensor coefficient + reaction, at the shape of
+    # configs 3 and 5 (128^3, V_H = 16^3, nev 100); the fine operator is an assembled 27-point stencil
+    "general3d-128": dict(dim=3, levels=[128, 64, 32, 16], nev=100, tol=1e-8, kappa_seed=None, guard=28,
+                          start="coarse", train_n=None, general=True),
 }
 
 
@@ -61,9 +65,12 @@ def stencil_hash():
     return h.hexdigest()[:16]
 
 
-def spmm_bytes(N, k, n_elem, variable_kappa):
+def spmm_bytes(N, k, n_elem, variable_kappa, general=False):
     """Algorithmic HBM bytes of one fused A X, M X launch: X read, A X and M X written (N x k doubles
-    each), kappa read once (n^3 doubles) when it varies.  Halo re-reads are not counted."""
+    each), kappa read once (n^3 doubles) when it varies, or the assembled 27 coefficients per node of
+    the tensor-coefficient problem.  Halo re-reads are not counted."""
+    if general:
+        return 3 * N * k * 8 + 27 * N * 8
     return 3 * N * k * 8 + (n_elem * 8 if variable_kappa else 0)
 
 
@@ -86,7 +93,11 @@ def cpu_baseline(w, kappa, gpu_iters, reps=3, k_sample=4):
     dim, levels, nev, guard = w["dim"], w["levels"], w["nev"], w["guard"]
     block = nev + guard
     t0 = time.perf_counter()
-    H = multigrid.Hierarchy(dim, levels, kappa)
+    if w.get("general"):
+        from oracle import fem
+        H = multigrid.Hierarchy(dim, levels, operator=fem.assemble_general(levels[0], *synth.general_coefficients(levels[0])))
+    else:
+        H = multigrid.Hierarchy(dim, levels, kappa)
     t_setup = time.perf_counter() - t0
     N = H.A[0].shape[0]
     U = pase.cholqr_m(synth.initial_vectors(N, k_sample, 0), H.M[0])
@@ -157,6 +168,11 @@ def main():
     dim, levels, nev, tol, kseed = w["dim"], w["levels"], w["nev"], w["tol"], w["kappa_seed"]
     guard, start = w["guard"], w["start"]
     kappa = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
+    # the tensor-coefficient workload: every solver of this run gets the same tensor and reaction
+    gen_kw = {}
+    if w.get("general"):
+        gT, gphi = synth.general_coefficients(levels[0])
+        gen_kw = dict(tensor=gT, reaction=gphi)
 
     # plain copy of a known size (calibrates the FETCH_SIZE / WRITE_SIZE counters of --pmc runs)
     cal_src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -178,7 +194,7 @@ def main():
         st = start if st is None else st
         t0 = time.perf_counter()
         s = Solver(dim, levels, kappa, nev_max=nev, precision=precision, locking=locking, guard=g, start=st,
-                   max_outer=1000, **(solver_kw or {}))
+                   max_outer=1000, **gen_kw, **(solver_kw or {}))
         if net is not None:
             s.attach(net)
         torch.cuda.synchronize()
@@ -315,7 +331,7 @@ def main():
     results = {"fp64": plain}
     if "mixed" in forms:
         results["mixed"] = run_form("mixed")[2]
-    if "learned" in forms and dim == 3 and w["train_n"]:
+    if "learned" in forms and dim == 3 and w["train_n"] and not w.get("general"):
         from paper_2502_04589_amd import UNet
         net_small, weights, training = train_network()
         del net_small
@@ -355,7 +371,7 @@ def main():
     N = s.N[0]
     n_elem = levels[0] ** dim
     ms = s.time_kernel("apply", k, reps=30)
-    nbytes = spmm_bytes(N, k, n_elem, kseed is not None)
+    nbytes = spmm_bytes(N, k, n_elem, kseed is not None, bool(w.get("general")))
     achieved = nbytes / (ms * 1e-3) / 1e9
     traffic = None
     if (SPMM_TRAFFIC["bytes"] is not None and args.workload == "kappa3d-128"
@@ -363,7 +379,7 @@ def main():
         traffic = SPMM_TRAFFIC["bytes"]
     mv = N * k * 8
     rates = {}
-    kb = n_elem * 8 if kseed is not None else 0
+    kb = n_elem * 8 if kseed is not None else (27 * N * 8 if w.get("general") else 0)
     for name, key, nb in (("spmm_AX_MX", "apply", nbytes), ("spmm_AX", "apply_A", 2 * mv + kb),
                           ("spmm_MX", "apply_M", 2 * mv), ("cg_update", "cg_update", 6 * mv),
                           ("vcycle_sweep", "sweep", 3 * mv + kb)):
@@ -376,7 +392,9 @@ def main():
                               "frac_fp64_mfma_peak": tf / FP64_MFMA_PEAK_TFS,
                               "GB/s": 2 * mv / (t * 1e-3) / 1e9,
                               "note": "one general Gram X^T Y (N x k by N x k) incl. its fixed-order reduction"}
-    desc = (f"{args.workload}: {dim}D Q1 {'kappa field (seed %d)' % kseed if kseed is not None else 'Laplace'}, "
+    prob_desc = ("tensor coefficient I + (x-1/2)(x-1/2)^T and reaction exp(prod(x_i-1/2)) (Sec. 5 eq. general)"
+                 if w.get("general") else ('kappa field (seed %d)' % kseed if kseed is not None else 'Laplace'))
+    desc = (f"{args.workload}: {dim}D Q1 {prob_desc}, "
             f"{levels[0]}^{dim} mesh ({N} DOFs), V_H {levels[-1]}^{dim} ({s.N[-1]} DOFs), GMG levels "
             f"{'/'.join(map(str, levels))}, nev {nev}, tol {tol:g}, 2 CG steps, "
             f"{'coarse start (Alg. 3 steps 1-2)' if start == 'coarse' else 'seeded uniform(-1,1) start'}, "
@@ -419,8 +437,10 @@ def main():
                              "configuration the CPU oracle runs",
         },
         "roofline": {
-            "kernel": "fused fine-level A X, M X (fine3v_kernel<double, EPI_AM>, LDS-staged 3D Q1 stencil) "
-                      f"at k = {k}",
+            "kernel": ("fused fine-level A X, M X (fine3v_kernel<double, EPI_AM, ASM>, LDS-staged 3D stencil with an "
+                       "assembled 27-coefficient row per node) " if w.get("general")
+                       else "fused fine-level A X, M X (fine3v_kernel<double, EPI_AM>, LDS-staged 3D Q1 stencil) ")
+                      + f"at k = {k}",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

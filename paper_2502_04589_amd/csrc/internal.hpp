@@ -98,6 +98,7 @@ struct Fine3Args {
   int k;                 // columns
   double h;
   const double* kappa;   // n^3 element coefficients or nullptr (kappa = 1)
+  const double* coef;    // or: an assembled 27-coefficient row of A per node (tensor-coefficient problem)
   const void* x;         // N x k (double or float)
   const void* b;
   const double* lam;

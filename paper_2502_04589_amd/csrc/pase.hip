@@ -412,12 +412,13 @@ void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void
   // 3D: the LDS-tiled stencil on the fine level, and on every level when kappa = 1 (nested Q1
   // spaces with exact integration: the Galerkin operator P^T A P equals the Q1 stencil of the
   // coarse mesh, so the constant stencil of width h_l applies it)
-  if (h->dim == 3 && !h->fine_general && (l == 0 || h->kappa_is_one)) {
+  if (h->dim == 3 && (l == 0 || h->kappa_is_one)) {
     Fine3Args f{};
     f.m = h->lev[l].m;
     f.k = k;
     f.h = h->lev[l].h;
-    f.kappa = h->kappa_is_one ? nullptr : h->kappa;
+    f.kappa = (h->kappa_is_one || h->fine_general) ? nullptr : h->kappa;
+    f.coef = (h->fine_general && l == 0) ? h->lev[0].coef : nullptr;
     f.x = x;
     f.b = b;
     f.lam = h->lam;
@@ -443,7 +444,7 @@ void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void
 }
 
 int eigres_tiles(pase_handle* h, int k) {
-  if (h->dim == 3 && !h->fine_general) return fine3_spatial_blocks(h->lev[0].m, fine3_default_nzc(h->lev[0].m));
+  if (h->dim == 3) return fine3_spatial_blocks(h->lev[0].m, fine3_default_nzc(h->lev[0].m));
   return grid_launch(h->lev[0].N, k).tiles;
 }
 
@@ -508,7 +509,7 @@ void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x
   launch_restrict(h->dim, lv.m, h->lev[l + 1].m, k, B.r[l], B.b[l + 1], B.fp32, s);
   vcycle(h, B, l + 1, k, B.b[l + 1], B.x[l + 1]);
   launch_prolong(h->dim, lv.m, h->lev[l + 1].m, k, B.x[l + 1], cur, 1, B.fp32, s);
-  const bool fuse = dot && l == 0 && h->dim == 3 && !h->fine_general;   // epilogues of the 3D fine kernel
+  const bool fuse = dot && l == 0 && h->dim == 3;
   for (int i = 0; i < h->opt.nu; ++i) {
     const bool last = i + 1 == h->opt.nu;
     stencil_op(h, l, k, (fuse && last) ? EPI_SWEEPDOT : EPI_SWEEP, cur, b, oth, nullptr, B.fp32);
@@ -529,7 +530,7 @@ void vcycle(pase_handle* h, int l, int k, const double* b, double* x, double* do
 // Q = A P and pq[j] = p_j^T A p_j on level 0 (fused into the stencil on the 3D path)
 void apply_dot(pase_handle* h, int k, const void* P, void* Q, double* pq, int fp32) {
   const long long N = h->lev[0].N;
-  if (h->dim == 3 && !h->fine_general) {
+  if (h->dim == 3) {
     stencil_op(h, 0, k, EPI_AMDOT, P, nullptr, Q, nullptr, fp32);
     launch_reduce_partials(eigres_tiles(h, k), k, h->partial, pq, h->stream);
     return;

@@ -9,7 +9,8 @@
 // value is read from HBM once per block (plus the halo), and every output
 // (node, column) takes its 27 neighbours from LDS.  The A-coefficients of a
 // node come from the kappa of its 8 surrounding cells (two element layers,
-// also staged in LDS):
+// held in registers), or (ASM) from an assembled 27-coefficient row per node (the
+// tensor-coefficient problem):
 //   A[i, i+o] = Kpat(o) * (sum of kappa over the cells shared by nodes i and i+o),
 //   M[i, i+o] = (h/6)^3 prod_a (o_a == 0 ? 4 : 1).
 // Thread (node, column) mapping puts columns fastest, so global loads and
@@ -85,7 +86,7 @@ struct Fine3SmemV {
 
 // NQ threads per node, each with a VW-column vector: a block covers KC = NQ VW columns of its
 // tile (NQ = 5 when it splits k into whole chunks and 4 does not, e.g. k = 50 with VW = 2)
-template <typename T, int VW, int EPI, bool CONSTK, bool VEC, int BX, int BY, int NQ>
+template <typename T, int VW, int EPI, bool CONSTK, bool VEC, int BX, int BY, int NQ, bool ASM>
 __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   constexpr int TX = BX, TY = BY;
   constexpr int kThreadsV = BX * BY * NQ;   // (node, column vector) pairs of a tile
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   V bA = bload(z0), bB = bA;
   V pA0 = ld1(z0 + 2, 0), pA1 = ld1(z0 + 2, 1);
   V pB0 = pA0, pB1 = pA1;
-  if (!CONSTK) {
+  if (!CONSTK && !ASM) {
 #pragma unroll
     for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     if (EPI == EPI_RESID || kSweep) BN = bload((z) + 1);                                                \
     PL0 = ld1((z) + 3, 0);                                                                              \
     PL1 = ld1((z) + 3, 1);                                                                              \
-    if (!CONSTK) {                                                                                      \
+    if (!CONSTK && !ASM) {                                                                              \
       _Pragma("unroll") for (int cy = 0; cy < 2; ++cy) _Pragma("unroll") for (int cx = 0; cx < 2; ++cx) { \
         kc[0][cy][cx] = kc[1][cy][cx];                                                                  \
         kc[1][cy][cx] = kap(gx + cx, gy + cy, (z) + 1);                                                 \
@@ -309,6 +310,14 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
 #pragma unroll
     for (int i = 0; i < VW; ++i) ax[i] = mx[i] = center[i] = 0.0;
     double dcoef = 1.0;
+    double cf[ASM ? 27 : 1];
+    if constexpr (ASM) {
+      if (needA) {
+        const double* __restrict__ cp = a.coef + (((long long)z * m + gy) * m + gx) * 27;
+#pragma unroll
+        for (int o = 0; o < 27; ++o) cf[o] = cp[o];
+      }
+    }
     if constexpr (CONSTK && EPI != EPI_AM) {
       plane9((sb + 2) & 3, 2);
 #pragma unroll
@@ -331,9 +340,13 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     const V v = sm.xs[(sb + 1 + (OZ)) & 3][ly + 1 + (OY)][lx + 1 + (OX)][qv];                      \
     double coef = 0.0, mp = 0.0;                                                                   \
     if (needA) {                                                                                   \
-      const double s = CONSTK ? (double)(((OX) == 0 ? 2 : 1) * ((OY) == 0 ? 2 : 1) * ((OZ) == 0 ? 2 : 1)) \
-                              : shared_kappa<OX, OY, OZ>(kc);                                      \
-      coef = kpat<OX, OY, OZ>(k0, k1, m0, m1) * s;                                                 \
+      if constexpr (ASM) {                                                                         \
+        coef = cf[((OX) + 1) + 3 * ((OY) + 1) + 9 * ((OZ) + 1)];                                   \
+      } else {                                                                                     \
+        const double s = CONSTK ? (double)(((OX) == 0 ? 2 : 1) * ((OY) == 0 ? 2 : 1) * ((OZ) == 0 ? 2 : 1)) \
+                                : shared_kappa<OX, OY, OZ>(kc);                                    \
+        coef = kpat<OX, OY, OZ>(k0, k1, m0, m1) * s;                                               \
+      }                                                                                            \
       if ((OX) == 0 && (OY) == 0 && (OZ) == 0) dcoef = coef;                                       \
     }                                                                                              \
     if (needM) mp = (double)(((OX) == 0 ? 4 : 1) * ((OY) == 0 ? 4 : 1) * ((OZ) == 0 ? 4 : 1)) * mc3; \
@@ -458,7 +471,7 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   }
 }
 
-template <typename T, int VW, int EPI, bool CONSTK, bool VEC>
+template <typename T, int VW, int EPI, bool CONSTK, bool VEC, bool ASM>
 void launchv_tile(const Fine3Args& a, hipStream_t s) {
   auto go = [&](auto nq) {
     constexpr int BX = 8, BY = 8, NQ = decltype(nq)::value;
@@ -466,7 +479,7 @@ void launchv_tile(const Fine3Args& a, hipStream_t s) {
     const int ntx = (a.m + BX - 1) / BX, nty = (a.m + BY - 1) / BY, nch = (a.k + KC - 1) / KC;
     const int total = ntx * nty * a.nzc * nch;
     const int blocks = ((total + 7) / 8) * 8;
-    fine3v_kernel<T, VW, EPI, CONSTK, VEC, BX, BY, NQ><<<blocks, BX * BY * NQ, 0, s>>>(a);
+    fine3v_kernel<T, VW, EPI, CONSTK, VEC, BX, BY, NQ, ASM><<<blocks, BX * BY * NQ, 0, s>>>(a);
   };
   // column chunks of 5 vectors when that wastes fewer padded columns than chunks of 4 (not for
   // the A+M and eigen-residual epilogues, whose register use makes the larger block slower)
@@ -484,12 +497,20 @@ void launchv_tile(const Fine3Args& a, hipStream_t s) {
 template <typename T, int VW, int EPI>
 void launchv_w(const Fine3Args& a, hipStream_t s) {
   const bool vec = (a.k % VW) == 0;
-  if (a.kappa && EPI != EPI_M) {     // M does not depend on kappa: the constant-coefficient path
-    if (vec) launchv_tile<T, VW, EPI, false, true>(a, s);
-    else launchv_tile<T, VW, EPI, false, false>(a, s);
+  // M does not depend on the coefficient: the constant-coefficient path
+  if constexpr (EPI != EPI_M && EPI != EPI_SWEEP2) {
+    if (a.coef) {
+      if (vec) launchv_tile<T, VW, EPI, false, true, true>(a, s);
+      else launchv_tile<T, VW, EPI, false, false, true>(a, s);
+      return;
+    }
+  }
+  if (a.kappa && EPI != EPI_M) {
+    if (vec) launchv_tile<T, VW, EPI, false, true, false>(a, s);
+    else launchv_tile<T, VW, EPI, false, false, false>(a, s);
   } else {
-    if (vec) launchv_tile<T, VW, EPI, true, true>(a, s);
-    else launchv_tile<T, VW, EPI, true, false>(a, s);
+    if (vec) launchv_tile<T, VW, EPI, true, true, false>(a, s);
+    else launchv_tile<T, VW, EPI, true, false, false>(a, s);
   }
 }
 
