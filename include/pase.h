@@ -67,6 +67,30 @@ typedef enum pase_precision {
   PASE_PREC_LEARNED = 2    /* learned preconditioner with GMG fallback */
 } pase_precision;
 
+/* A device CSR matrix (0-based int32 indices): rowptr has rows + 1 entries, colind and val
+ * rowptr[rows] each; duplicate entries of a row are summed.  Owned by the caller. */
+typedef struct pase_csr {
+  int rows, cols;
+  const int* rowptr;
+  const int* colind;
+  const double* val;
+} pase_csr;
+
+/* Algebraic input (Alg. 3 "Require" given as matrices, as an AMG hierarchy would give them):
+ * per level l (0 = fine, nlevels - 1 = the coarsest, which is V_H unless coarse_level says
+ * otherwise) the SPD pencil (A_l, M_l), and for l >= 1 the transfers P[l] = I_l^{l-1}
+ * (N_{l-1} x N_l) and R[l] = P[l]^T (N_l x N_{l-1}).  The V-cycle smooths with damped Jacobi on
+ * A_l and solves the coarsest level densely; the coarse operators are taken as given (for the
+ * method they should be the Galerkin products P^T A P, P^T M P).  The caller keeps every array
+ * alive and unchanged while the handle exists. */
+typedef struct pase_hierarchy_csr {
+  int nlevels;                   /* 2 .. PASE_MAX_LEVELS */
+  pase_csr A[PASE_MAX_LEVELS];
+  pase_csr M[PASE_MAX_LEVELS];
+  pase_csr P[PASE_MAX_LEVELS];   /* index 0 unused */
+  pase_csr R[PASE_MAX_LEVELS];   /* index 0 unused */
+} pase_hierarchy_csr;
+
 /* The discrete problem (Alg. 3 "Require"): the fine Q1 pencil (A_h, B_h = M)
  * of the element coefficient kappa and the nested grid hierarchy whose
  * coarsest level is V_H.  I_H^h is trilinear (bilinear) interpolation,
@@ -84,6 +108,9 @@ typedef struct pase_problem {
                                     operator is assembled into a 27-point stencil per node. */
   const double* reaction;        /* with tensor: device n[0]^3 element values of phi (>= 0), or NULL
                                     for phi = 0 */
+  const pase_hierarchy_csr* csr; /* non-NULL: algebraic input; dim, nlevels, n, kappa, tensor and
+                                    reaction are then ignored (must be 0 / NULL for the pointers);
+                                    not for the learned form */
 } pase_problem;
 
 typedef struct pase_options {
@@ -256,6 +283,16 @@ pase_status pase_gram_noalloc(long long N, int k, const double* X, const double*
  * w_host (k, ascending) and V (device, n x k row-major, orthonormal columns).
  * n <= pase_small_eig_max_n(h); T is not modified. */
 pase_status pase_small_eig(pase_handle* h, int n, int k, const double* T, double* w_host, double* V);
+/* A grid handle's hierarchy as device CSR (the input of pase_hierarchy_csr, or for inspection):
+ * which = 0 A_l, 1 M_l (N_l x N_l, 3^dim slots per row), 2 P_l = I_l^{l-1} (N_{l-1} x N_l, 2^dim
+ * slots per row, level >= 1), 3 R_l = P_l^T (N_l x N_{l-1}, 3^dim slots per row, level >= 1).
+ * Every row has exactly `slots` entries (entries outside the matrix's pattern hold 0), so
+ * rowptr[i] = slots * i.  *rows, *cols, *slots are written; rowptr (rows + 1), colind and val
+ * (rows * slots each) are device arrays, or all NULL to query the sizes only.  Synchronises the
+ * handle's stream; uses the fine multi-vector space as scratch (not during a solve).  Errors:
+ * PASE_E_ARG for a bad level / which, PASE_E_UNSUPPORTED for an algebraic handle. */
+pase_status pase_export_csr(pase_handle* h, int level, int which, int* rows, int* cols, int* slots, int* rowptr,
+                            int* colind, double* val);
 int pase_small_eig_max_n(const pase_handle* h);
 
 /* One full correction (Alg. 1 / Alg. 3 steps 3-6) from (lambda, U) with U^T M U = I:

@@ -81,6 +81,30 @@ class Hierarchy:
         AL = self.A[self.L].toarray()
         self.AL_chol = sla.cho_factor(0.5 * (AL + AL.T), lower=True)
 
+    @classmethod
+    def from_matrices(cls, A, M, P, omega=2.0 / 3.0, nu=2):
+        """Algebraic hierarchy (Alg. 3's "Require" given as matrices): level operators A[l], M[l]
+        (sparse, fine first) and interpolations P[l] from level l to l - 1 (P[0] unused), as an AMG
+        setup would give them.  The V-cycle and the composite interpolation are the same as for a
+        grid hierarchy."""
+        self = cls.__new__(cls)
+        self.dim = None
+        self.n = None
+        self.omega = omega
+        self.nu = nu
+        self.A = [sp.csr_matrix(a) for a in A]
+        self.M = [sp.csr_matrix(m) for m in M]
+        self.P = [None] + [sp.csr_matrix(p) for p in P[1:]]
+        self.D = [a.diagonal() for a in self.A]
+        Pc = sp.identity(self.A[0].shape[0], format="csr")
+        for l in range(1, len(self.A)):
+            Pc = (Pc @ self.P[l]).tocsr()
+        self.Pc = Pc
+        self.L = len(self.A) - 1
+        AL = self.A[self.L].toarray()
+        self.AL_chol = sla.cho_factor(0.5 * (AL + AL.T), lower=True)
+        return self
+
     # --- V-cycle -----------------------------------------------------------
     def jacobi(self, l, x, b):
         """One damped-Jacobi sweep x <- x + omega D^{-1} (b - A x) on level l."""

@@ -3,5 +3,5 @@
 Every step of the method runs in the HIP kernels of libpase.so; this module
 only marshals arguments.  PyTorch provides device memory and the stream.
 """
-from .solver import PaseError, Solver  # noqa: F401
+from .solver import CsrMatrix, PaseError, Solver  # noqa: F401
 from .learned import UNet  # noqa: F401

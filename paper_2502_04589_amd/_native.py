@@ -15,9 +15,19 @@ STATUS = {0: "PASE_OK", 1: "PASE_E_ARG", 2: "PASE_E_HIP", 3: "PASE_E_NOMEM", 4: 
 PREC = {"fp64": 0, "mixed": 1, "learned": 2}
 
 
+class Csr(C.Structure):
+    _fields_ = [("rows", C.c_int), ("cols", C.c_int), ("rowptr", C.c_void_p), ("colind", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class HierarchyCsr(C.Structure):
+    _fields_ = [("nlevels", C.c_int), ("A", Csr * MAX_LEVELS), ("M", Csr * MAX_LEVELS), ("P", Csr * MAX_LEVELS),
+                ("R", Csr * MAX_LEVELS)]
+
+
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int), ("nlevels", C.c_int), ("n", C.c_int * MAX_LEVELS), ("kappa", C.c_void_p),
-                ("tensor", C.c_void_p), ("reaction", C.c_void_p)]
+                ("tensor", C.c_void_p), ("reaction", C.c_void_p), ("csr", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -64,6 +74,8 @@ SIGNATURES = [
     ("pase_small_eig_max_n", C.c_int, [C.c_void_p]),
     ("pase_correction", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     ("pase_time_kernel", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]),
+    ("pase_export_csr", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                  C.POINTER(C.c_int), C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pase_unet_param_count", C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
     ("pase_unet_workspace_bytes", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
     ("pase_unet_create", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_void_p, C.c_size_t, C.c_void_p,

@@ -807,6 +807,27 @@ void launch_prolong(int dim, int mf, int mc, int k, const void* xc, void* xf, in
   else launch_prolong_t<double>(dim, mf, mc, k, (const double*)xc, (double*)xf, mode, s);
 }
 
+template <int DIM>
+__global__ void kappa_coefs_kernel(int n, const double* __restrict__ kappa, double* __restrict__ coef) {
+  constexpr int NS = NSt<DIM>::v;
+  const int m = n - 1;
+  long long N = (long long)m * m;
+  if (DIM == 3) N *= m;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int x, y, z;
+  node_xyz<DIM>(i, m, x, y, z);
+  double c[NS];
+  kappa_coefs<DIM>(kappa, m, 1.0 / n, x, y, z, c);
+  for (int o = 0; o < NS; ++o) coef[i * NS + o] = c[o];
+}
+
+void launch_kappa_coefs(int dim, int n, const double* kappa, double* coef, hipStream_t s) {
+  const long long N = (long long)(n - 1) * (n - 1) * (dim == 3 ? (n - 1) : 1);
+  if (dim == 3) kappa_coefs_kernel<3><<<nblk(N), kBlock, 0, s>>>(n, kappa, coef);
+  else kappa_coefs_kernel<2><<<nblk(N), kBlock, 0, s>>>(n, kappa, coef);
+}
+
 void launch_kappa_dinv(int dim, int n, const double* kappa, double* dinv, hipStream_t s) {
   const long long N = (long long)(n - 1) * (n - 1) * (dim == 3 ? (n - 1) : 1);
   if (dim == 3) kappa_dinv_kernel<3><<<nblk(N), kBlock, 0, s>>>(n, kappa, dinv);

@@ -83,6 +83,7 @@ void launch_restrict(int dim, int mf, int mc, int k, const void* xf, void* xc, i
 void launch_prolong(int dim, int mf, int mc, int k, const void* xc, void* xf, int mode, int fp32, hipStream_t s);
 // setup helpers
 void launch_kappa_dinv(int dim, int n, const double* kappa, double* dinv, hipStream_t s);
+void launch_kappa_coefs(int dim, int n, const double* kappa, double* coef, hipStream_t s);   // N x 3^dim
 void launch_color_probe(int dim, int m, double* E, hipStream_t s);                 // N x 3^dim
 void launch_extract_galerkin(int dim, int m, const double* Y, double* coef, double* dinv, hipStream_t s);
 void launch_stencil_to_dense(int dim, int m, const double* coef, double hmass, int use_mass, double* D,
@@ -186,6 +187,41 @@ void launch_tsmm(long long N, int k, const double* X, const double* C, double* Y
 // small helpers
 void launch_set_diag_block(int n, int nh, int k, const double* C0, const double* G, const double* H, double* T,
                            hipStream_t s);
+
+// ---- algebraic input (csr.hip): CSR operators on node-major multi-vectors
+struct CsrMat {
+  const int* rowptr;
+  const int* colind;
+  const double* val;
+};
+struct CsrOpArgs {
+  long long rows;
+  int k;                  // columns (<= 256)
+  CsrMat A, M;
+  const double* dinv;     // SWEEP: 1 / diag(A)
+  double omega;
+  const void* x;          // double, or float when fp32
+  const void* b;          // RESID / SWEEP right-hand side
+  const double* lam;      // EIGRES
+  void* out1;
+  void* out2;
+  double* partial;        // EIGRES: [csr_tiles(rows)][3][k]
+  int fp32;
+};
+int csr_tiles(long long rows);
+// epilogues EPI_AM (either output may be null), EPI_RESID, EPI_SWEEP, EPI_EIGRES
+void launch_csr_op(const CsrOpArgs& a, Epi epi, hipStream_t s);
+// y (=, +=, -=) A x for mode 0, 1, 2
+void launch_csr_apply(const CsrMat& A, long long rows, int k, const void* x, void* y, int mode, int fp32,
+                      hipStream_t s);
+void launch_csr_diag_inv(const CsrMat& A, long long rows, double* dinv, hipStream_t s);
+void launch_csr_to_dense(const CsrMat& A, long long rows, double* D, hipStream_t s);
+// a grid hierarchy as CSR with a fixed number of slots per row (rowptr[i] = slots i, unused slots hold
+// zeros): a level operator from its stencil (coef null: the Q1 mass of width hmass), P, R = P^T
+void launch_export_stencil(int dim, int m, const double* coef, double hmass, int* rowptr, int* colind, double* val,
+                           hipStream_t s);
+void launch_export_prolong(int dim, int mf, int mc, int* rowptr, int* colind, double* val, hipStream_t s);
+void launch_export_restrict(int dim, int mf, int mc, int* rowptr, int* colind, double* val, hipStream_t s);
 
 // ---- GCG_AUG (gcg.hip): augmented blocks are (N_H + k) x w row-major
 // C (m x n) = A^T B over N rows, A: N x m (lda), B: N x n (ldb); fixed-order reduction over at most

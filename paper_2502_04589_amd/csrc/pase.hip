@@ -71,6 +71,8 @@ struct pase_handle {
   double* kappa = nullptr;
   bool kappa_is_one = false;    // problem given with kappa = NULL (constant coefficient)
   bool fine_general = false;    // tensor-coefficient problem: the fine operator is an assembled stencil
+  bool alg = false;             // algebraic input: every level operator and transfer is a CSR matrix
+  pase_hierarchy_csr csr{};
   // coarse dense (NH x NH)
   double *AinvL = nullptr, *LBinv = nullptr, *BHinv = nullptr, *C0 = nullptr, *dtmp = nullptr;
   // small problem
@@ -214,21 +216,73 @@ long long level_nodes(int dim, int n) {
   return dim == 3 ? m * m * m : m * m;
 }
 
+bool csr_ok(const pase_csr& c, int rows, int cols) {
+  return c.rows == rows && c.cols == cols && rows >= 1 && c.rowptr && c.colind && c.val;
+}
+
+// Algebraic input: consistent shapes, every pointer given
+pase_status check_csr(const pase_hierarchy_csr* c) {
+  if (c->nlevels < 2 || c->nlevels > PASE_MAX_LEVELS) return PASE_E_ARG;
+  for (int l = 0; l < c->nlevels; ++l) {
+    const int n = c->A[l].rows;
+    if (!csr_ok(c->A[l], n, n) || !csr_ok(c->M[l], n, n)) return PASE_E_ARG;
+    if (l > 0) {
+      const int nf = c->A[l - 1].rows;
+      if (!csr_ok(c->P[l], nf, n) || !csr_ok(c->R[l], n, nf)) return PASE_E_ARG;
+    }
+  }
+  return PASE_OK;
+}
+
+// level sizes of a problem (grid or algebraic); dim = 0 for algebraic input
+void set_levels(pase_handle* h, const pase_problem* prob) {
+  if (prob->csr) {
+    h->alg = true;
+    h->csr = *prob->csr;
+    h->dim = 0;
+    h->L = prob->csr->nlevels - 1;
+    h->NS = 0;
+    for (int l = 0; l <= h->L; ++l) {
+      h->lev[l].n = h->lev[l].m = 0;
+      h->lev[l].N = prob->csr->A[l].rows;
+      h->lev[l].h = 0.0;
+    }
+    return;
+  }
+  h->dim = prob->dim;
+  h->L = prob->nlevels - 1;
+  h->NS = prob->dim == 3 ? 27 : 9;
+  for (int l = 0; l < prob->nlevels; ++l) {
+    h->lev[l].n = prob->n[l];
+    h->lev[l].m = prob->n[l] - 1;
+    h->lev[l].N = level_nodes(prob->dim, prob->n[l]);
+    h->lev[l].h = 1.0 / prob->n[l];
+  }
+}
+
 pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (!p || !o) return PASE_E_ARG;
-  if (p->dim != 2 && p->dim != 3) return PASE_E_ARG;
-  if (p->nlevels < 2 || p->nlevels > PASE_MAX_LEVELS) return PASE_E_ARG;
-  for (int l = 0; l < p->nlevels; ++l) {
-    if (p->n[l] < 2) return PASE_E_ARG;
-    if (l > 0 && p->n[l - 1] != 2 * p->n[l]) return PASE_E_ARG;
+  const int nlev = p->csr ? p->csr->nlevels : p->nlevels;
+  if (p->csr) {
+    if (p->kappa || p->tensor || p->reaction) return PASE_E_ARG;
+    const pase_status st = check_csr(p->csr);
+    if (st) return st;
+    if (o->precision == PASE_PREC_LEARNED) return PASE_E_UNSUPPORTED;   // the network works on a grid
+  } else {
+    if (p->dim != 2 && p->dim != 3) return PASE_E_ARG;
+    if (p->nlevels < 2 || p->nlevels > PASE_MAX_LEVELS) return PASE_E_ARG;
+    for (int l = 0; l < p->nlevels; ++l) {
+      if (p->n[l] < 2) return PASE_E_ARG;
+      if (l > 0 && p->n[l - 1] != 2 * p->n[l]) return PASE_E_ARG;
+    }
   }
   if (o->nev_max < 1 || o->nev_max > PASE_MAX_NEV) return PASE_E_ARG;
   if (o->cg_steps < 1 || o->max_outer < 0 || o->nu < 1) return PASE_E_ARG;
   if (!(o->omega > 0.0)) return PASE_E_ARG;
   if (o->small_solver < 0 || o->small_solver > 2) return PASE_E_ARG;
-  if (o->coarse_level < 0 || o->coarse_level >= p->nlevels) return PASE_E_ARG;
+  if (o->coarse_level < 0 || o->coarse_level >= nlev) return PASE_E_ARG;
   if (!(o->aug_rtol >= 0.0)) return PASE_E_ARG;
-  if (o->coarse_level != 0 && o->coarse_level != p->nlevels - 1 && o->small_solver != 2)
+  if (o->coarse_level != 0 && o->coarse_level != nlev - 1 && o->small_solver != 2)
     return PASE_E_UNSUPPORTED;   // V_H below the coarsest level: GCG_AUG only
   if (o->locking != 0 && o->locking != 1) return PASE_E_ARG;
   if (o->guard < 0 || o->guard > 64 || o->nev_max + o->guard > PASE_MAX_NEV) return PASE_E_ARG;
@@ -236,8 +290,8 @@ pase_status check_problem(const pase_problem* p, const pase_options* o) {
   if (!(o->fallback_ratio > 0.0)) return PASE_E_ARG;
   if (o->precision != PASE_PREC_FP64 && o->precision != PASE_PREC_MIXED && o->precision != PASE_PREC_LEARNED)
     return PASE_E_UNSUPPORTED;
-  if (o->precision == PASE_PREC_LEARNED && p->dim != 3) return PASE_E_UNSUPPORTED;   // the network is 3D
-  if (p->tensor && (p->dim != 3 || p->kappa)) return PASE_E_ARG;
+  if (o->precision == PASE_PREC_LEARNED && p->dim != 3 && !p->csr) return PASE_E_UNSUPPORTED;   // the network is 3D
+  if (!p->csr && p->tensor && (p->dim != 3 || p->kappa)) return PASE_E_ARG;
   if (!p->tensor && p->reaction) return PASE_E_ARG;
   if (p->tensor && o->precision == PASE_PREC_LEARNED) return PASE_E_UNSUPPORTED;   // the network reads log kappa
   return PASE_OK;
@@ -379,6 +433,7 @@ size_t layout(pase_handle* h, void* base) {
     pd = std::max(pd, (size_t)coldot_tiles(N0, k) * k);
     pd = std::max(pd, (size_t)2 * gram_tiles(N0, k) * k * k);
     pd = std::max(pd, (size_t)grid_launch(N0, k).blocks * 3 * k);
+    if (h->alg) pd = std::max(pd, (size_t)csr_tiles(N0) * 3 * k);
     if (dim == 3) pd = std::max(pd, (size_t)fine3_max_spatial_blocks(h->lev[0].m) * 3 * k);
   }
   h->partial_doubles = pd;
@@ -407,8 +462,28 @@ StencilArgs stencil_args(pase_handle* h, int l, int k) {
 
 // Every stencil application goes through here: the 3D fine level uses the
 // LDS-staged kernel, 2D problems and coarse levels the generic one.
+CsrMat csr_mat(const pase_csr& c);
+
 void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void* b, void* out1, void* out2,
                 int fp32 = 0) {
+  if (h->alg) {
+    CsrOpArgs a{};
+    a.rows = h->lev[l].N;
+    a.k = k;
+    a.A = csr_mat(h->csr.A[l]);
+    a.M = csr_mat(h->csr.M[l]);
+    a.dinv = h->lev[l].dinv;
+    a.omega = h->opt.omega;
+    a.x = x;
+    a.b = b;
+    a.lam = h->lam;
+    a.out1 = out1;
+    a.out2 = out2;
+    a.partial = h->partial;
+    a.fp32 = fp32;
+    launch_csr_op(a, epi, h->stream);
+    return;
+  }
   // 3D: the LDS-tiled stencil on the fine level, and on every level when kappa = 1 (nested Q1
   // spaces with exact integration: the Galerkin operator P^T A P equals the Q1 stencil of the
   // coarse mesh, so the constant stencil of width h_l applies it)
@@ -443,7 +518,27 @@ void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void
   launch_stencil(a, epi, h->stream);
 }
 
+CsrMat csr_mat(const pase_csr& c) { return CsrMat{c.rowptr, c.colind, c.val}; }
+
+// restriction from level l to l + 1 and prolongation from level l to l - 1 ((=, +=, -=) by mode)
+void xfer_restrict(pase_handle* h, int l, int k, const void* xf, void* xc, int fp32) {
+  if (h->alg) {
+    launch_csr_apply(csr_mat(h->csr.R[l + 1]), h->lev[l + 1].N, k, xf, xc, 0, fp32, h->stream);
+    return;
+  }
+  launch_restrict(h->dim, h->lev[l].m, h->lev[l + 1].m, k, xf, xc, fp32, h->stream);
+}
+
+void xfer_prolong(pase_handle* h, int l, int k, const void* xc, void* xf, int mode, int fp32) {
+  if (h->alg) {
+    launch_csr_apply(csr_mat(h->csr.P[l]), h->lev[l - 1].N, k, xc, xf, mode, fp32, h->stream);
+    return;
+  }
+  launch_prolong(h->dim, h->lev[l - 1].m, h->lev[l].m, k, xc, xf, mode, fp32, h->stream);
+}
+
 int eigres_tiles(pase_handle* h, int k) {
+  if (h->alg) return csr_tiles(h->lev[0].N);
   if (h->dim == 3) return fine3_spatial_blocks(h->lev[0].m, fine3_default_nzc(h->lev[0].m));
   return grid_launch(h->lev[0].N, k).tiles;
 }
@@ -506,9 +601,9 @@ void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x
     std::swap(cur, oth);
   }
   stencil_op(h, l, k, EPI_RESID, cur, b, B.r[l], nullptr, B.fp32);
-  launch_restrict(h->dim, lv.m, h->lev[l + 1].m, k, B.r[l], B.b[l + 1], B.fp32, s);
+  xfer_restrict(h, l, k, B.r[l], B.b[l + 1], B.fp32);
   vcycle(h, B, l + 1, k, B.b[l + 1], B.x[l + 1]);
-  launch_prolong(h->dim, lv.m, h->lev[l + 1].m, k, B.x[l + 1], cur, 1, B.fp32, s);
+  xfer_prolong(h, l + 1, k, B.x[l + 1], cur, 1, B.fp32);
   const bool fuse = dot && l == 0 && h->dim == 3;
   for (int i = 0; i < h->opt.nu; ++i) {
     const bool last = i + 1 == h->opt.nu;
@@ -545,7 +640,7 @@ void restrict_all(pase_handle* h, int k, const double* xf, double* xc) {
   const double* src = xf;
   for (int l = 0; l < h->L; ++l) {
     double* dst = (l + 1 == h->L) ? xc : h->vr[l + 1];
-    launch_restrict(h->dim, h->lev[l].m, h->lev[l + 1].m, k, src, dst, 0, h->stream);
+    xfer_restrict(h, l, k, src, dst, 0);
     src = dst;
   }
 }
@@ -555,7 +650,7 @@ void prolong_all(pase_handle* h, int k, const double* xc, double* xf, int mode) 
   const double* src = xc;
   for (int l = h->L; l >= 1; --l) {
     double* dst = (l == 1) ? xf : h->vxa[l - 1];
-    launch_prolong(h->dim, h->lev[l - 1].m, h->lev[l].m, k, src, dst, (l == 1) ? mode : 0, 0, h->stream);
+    xfer_prolong(h, l, k, src, dst, (l == 1) ? mode : 0, 0);
     src = dst;
   }
 }
@@ -793,7 +888,7 @@ void restrict_to(pase_handle* h, int c, int k, const double* xf, double* xc) {
   const double* src = xf;
   for (int l = 0; l < c; ++l) {
     double* dst = (l + 1 == c) ? xc : h->vr[l + 1];
-    launch_restrict(h->dim, h->lev[l].m, h->lev[l + 1].m, k, src, dst, 0, h->stream);
+    xfer_restrict(h, l, k, src, dst, 0);
     src = dst;
   }
 }
@@ -802,7 +897,7 @@ void prolong_from(pase_handle* h, int c, int k, const double* xc, double* xf, in
   const double* src = xc;
   for (int l = c; l >= 1; --l) {
     double* dst = (l == 1) ? xf : h->vxa[l - 1];
-    launch_prolong(h->dim, h->lev[l - 1].m, h->lev[l].m, k, src, dst, (l == 1) ? mode : 0, 0, h->stream);
+    xfer_prolong(h, l, k, src, dst, (l == 1) ? mode : 0, 0);
     src = dst;
   }
 }
@@ -1134,7 +1229,7 @@ pase_status correction_enqueue(pase_handle* h, int k) {
     stencil_op(h, 0, k, EPI_AM, W32, nullptr, AW32, MW32, 1);
     const float* src = AW32;
     for (int l = 0; l < h->L; ++l) {
-      launch_restrict(h->dim, h->lev[l].m, h->lev[l + 1].m, k, src, h->vb32[l + 1], 1, s);
+      xfer_restrict(h, l, k, src, h->vb32[l + 1], 1);
       src = h->vb32[l + 1];
     }
     launch_f2d((size_t)NH * k, h->vb32[h->L], h->ca, s);
@@ -1263,16 +1358,9 @@ pase_status pase_workspace_bytes(const pase_problem* prob, const pase_options* o
   if (st != PASE_OK) return fail(h, st, "invalid or unsupported problem/options");
   pase_handle tmp;
   tmp.opt = *opt;
-  tmp.dim = prob->dim;
-  tmp.L = prob->nlevels - 1;
-  tmp.NS = prob->dim == 3 ? 27 : 9;
+  set_levels(&tmp, prob);
   tmp.K = opt->nev_max + opt->guard;
-  tmp.fine_general = (prob->tensor != nullptr);
-  for (int l = 0; l < prob->nlevels; ++l) {
-    tmp.lev[l].n = prob->n[l];
-    tmp.lev[l].m = prob->n[l] - 1;
-    tmp.lev[l].N = level_nodes(prob->dim, prob->n[l]);
-  }
+  tmp.fine_general = (prob->tensor != nullptr && !prob->csr);
   *bytes = layout(&tmp, nullptr);
   return PASE_OK;
 }
@@ -1290,17 +1378,9 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   h->prob = *prob;
   h->opt = *opt;
   h->stream = (hipStream_t)stream;
-  h->dim = prob->dim;
-  h->L = prob->nlevels - 1;
-  h->NS = prob->dim == 3 ? 27 : 9;
+  set_levels(h, prob);
   h->K = opt->nev_max + opt->guard;
-  h->fine_general = (prob->tensor != nullptr);
-  for (int l = 0; l < prob->nlevels; ++l) {
-    h->lev[l].n = prob->n[l];
-    h->lev[l].m = prob->n[l] - 1;
-    h->lev[l].N = level_nodes(prob->dim, prob->n[l]);
-    h->lev[l].h = 1.0 / prob->n[l];
-  }
+  h->fine_general = (prob->tensor != nullptr && !prob->csr);
   const size_t need = layout(h, nullptr);
   if (workspace_bytes < need) {
     const pase_status r = fail(h, PASE_E_NOMEM, "workspace smaller than pase_workspace_bytes");
@@ -1309,7 +1389,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   }
   layout(h, workspace);
   h->lev[0].kappa = h->kappa;
-  h->kappa_is_one = (prob->kappa == nullptr && !h->fine_general);
+  h->kappa_is_one = (prob->kappa == nullptr && !h->fine_general && !h->alg);
   hipStream_t s = h->stream;
   auto bail = [&](pase_status r) {
     g_last_error = h->err;
@@ -1331,7 +1411,10 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   } while (0)
   const Level& f = h->lev[0];
   const size_t ne = (size_t)f.n * f.n * (h->dim == 3 ? f.n : 1);
-  if (prob->kappa) {
+  if (h->alg) {
+    // algebraic input: Jacobi diagonals of every level from the given A_l
+    for (int l = 0; l <= h->L; ++l) launch_csr_diag_inv(csr_mat(h->csr.A[l]), h->lev[l].N, h->lev[l].dinv, s);
+  } else if (prob->kappa) {
     HIPS(hipMemcpyAsync(h->kappa, prob->kappa, ne * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else {
     std::vector<double> ones(ne, 1.0);
@@ -1339,12 +1422,17 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
     HIPS(hipStreamSynchronize(s));
   }
   HIPS(hipMemsetAsync(h->zero16, 0, 8 * sizeof(double), s));
-  if (h->fine_general) launch_assemble_general(f.n, prob->tensor, prob->reaction, h->lev[0].coef, h->lev[0].dinv, s);
-  else launch_kappa_dinv(h->dim, f.n, h->kappa, h->lev[0].dinv, s);
+  if (h->alg) {
+    // nothing to assemble
+  } else if (h->fine_general) {
+    launch_assemble_general(f.n, prob->tensor, prob->reaction, h->lev[0].coef, h->lev[0].dinv, s);
+  } else {
+    launch_kappa_dinv(h->dim, f.n, h->kappa, h->lev[0].dinv, s);
+  }
   if (h->logk) launch_node_logk(f.n, h->kappa, h->logk, s);
   // Galerkin stencils A_l = P_l^T A_{l-1} P_l from 3^d colour probes
   const int NS = h->NS;
-  for (int l = 1; l <= h->L; ++l) {
+  for (int l = 1; l <= h->L && !h->alg; ++l) {
     const Level& c = h->lev[l];
     const Level& p = h->lev[l - 1];
     double* E = h->setup_scratch;
@@ -1360,7 +1448,11 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   const Level& cl = h->lev[h->L];
   const int NH = (int)cl.N;
   double* AL = h->dtmp;
-  launch_stencil_to_dense(h->dim, cl.m, cl.coef, cl.h, 0, AL, s);
+  auto coarse_dense = [&](int mass, double* D) {   // A_L (mass = 0) or M_L, dense
+    if (h->alg) launch_csr_to_dense(csr_mat(mass ? h->csr.M[h->L] : h->csr.A[h->L]), cl.N, D, s);
+    else launch_stencil_to_dense(h->dim, cl.m, mass ? nullptr : cl.coef, cl.h, mass, D, s);
+  };
+  coarse_dense(0, AL);
   // blocked factorisations above one workgroup's size; their scratch follows the N_H x N_H
   // product area at the start of the setup scratch
   const bool big_coarse = NH > kDenseSmallN;
@@ -1379,13 +1471,13 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   launch_symmetrize(NH, h->AinvL, s);
   if (h->AinvL32) launch_d2f((size_t)NH * NH, h->AinvL, h->AinvL32, s);
   double* BL = h->dtmp;
-  launch_stencil_to_dense(h->dim, cl.m, nullptr, cl.h, 1, BL, s);
+  coarse_dense(1, BL);
   cholesky(BL, h->info + 9);                                         // BL <- L_B
   trinv(BL, h->LBinv);
   launch_gemm(true, false, NH, NH, NH, 1.0, h->LBinv, NH, h->LBinv, NH, 0.0, h->BHinv, NH, s);
   launch_symmetrize(NH, h->BHinv, s);
   // C0 = LB^{-1} A_H LB^{-T}
-  launch_stencil_to_dense(h->dim, cl.m, cl.coef, cl.h, 0, AL, s);
+  coarse_dense(0, AL);
   double* tmp = h->setup_scratch;
   launch_gemm(false, false, NH, NH, NH, 1.0, h->LBinv, NH, AL, NH, 0.0, tmp, NH, s);
   launch_gemm(false, true, NH, NH, NH, 1.0, tmp, NH, h->LBinv, NH, 0.0, h->C0, NH, s);
@@ -1814,6 +1906,55 @@ pase_status pase_fine_diag_inverse(pase_handle* h, double* dinv) {
   if (!h || !dinv) return fail(h, PASE_E_ARG, "null argument");
   HIPC(hipMemcpyAsync(dinv, h->lev[0].dinv, sizeof(double) * h->lev[0].N, hipMemcpyDeviceToDevice, h->stream));
   HIPC(hipStreamSynchronize(h->stream));
+  return PASE_OK;
+}
+
+pase_status pase_export_csr(pase_handle* h, int level, int which, int* rows, int* cols, int* slots, int* rowptr,
+                            int* colind, double* val) {
+  if (!h || !rows || !cols || !slots) return fail(h, PASE_E_ARG, "null argument");
+  if (h->alg) return fail(h, PASE_E_UNSUPPORTED, "the handle's operators are already CSR matrices");
+  if (level < 0 || level > h->L || which < 0 || which > 3 || (which >= 2 && level < 1))
+    return fail(h, PASE_E_ARG, "level or which out of range");
+  const int dim = h->dim;
+  const int ns = dim == 3 ? 27 : 9;
+  const Level& lv = h->lev[level];
+  if (which <= 1) {
+    *rows = *cols = (int)lv.N;
+    *slots = ns;
+  } else if (which == 2) {
+    *rows = (int)h->lev[level - 1].N;
+    *cols = (int)lv.N;
+    *slots = 1 << dim;
+  } else {
+    *rows = (int)lv.N;
+    *cols = (int)h->lev[level - 1].N;
+    *slots = ns;
+  }
+  if (!rowptr && !colind && !val) return PASE_OK;
+  if (!rowptr || !colind || !val) return fail(h, PASE_E_ARG, "rowptr, colind and val go together");
+  if ((long long)*rows * *slots > 0x7fffffffLL) return fail(h, PASE_E_UNSUPPORTED, "more than 2^31 entries");
+  hipStream_t s = h->stream;
+  if (which == 0) {
+    // the level's A stencil; the fine level's comes from kappa (coefficients formed into the
+    // setup scratch) unless it is assembled already
+    const double* coef = lv.coef;
+    if (level == 0 && !h->fine_general) {
+      // the setup scratch (the fine multi-vectors' space, free between solves) holds at least
+      // 3 N_0 3^dim doubles
+      double* tmp = h->setup_scratch;
+      launch_kappa_coefs(dim, lv.n, h->kappa_is_one ? nullptr : h->kappa, tmp, s);
+      coef = tmp;
+    }
+    launch_export_stencil(dim, lv.m, coef, lv.h, rowptr, colind, val, s);
+  } else if (which == 1) {
+    launch_export_stencil(dim, lv.m, nullptr, lv.h, rowptr, colind, val, s);
+  } else if (which == 2) {
+    launch_export_prolong(dim, h->lev[level - 1].m, lv.m, rowptr, colind, val, s);
+  } else {
+    launch_export_restrict(dim, h->lev[level - 1].m, lv.m, rowptr, colind, val, s);
+  }
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(s));
   return PASE_OK;
 }
 

@@ -25,6 +25,31 @@ def _ptr(t):
     return C.c_void_p(0 if t is None else t.data_ptr())
 
 
+class CsrMatrix:
+    """A device CSR matrix for the algebraic input: int32 rowptr / colind and float64 values."""
+
+    def __init__(self, rows, cols, rowptr, colind, val):
+        self.rows, self.cols = int(rows), int(cols)
+        self.rowptr = rowptr.to(torch.int32).contiguous()
+        self.colind = colind.to(torch.int32).contiguous()
+        self.val = val.to(torch.float64).contiguous()
+        if self.rowptr.numel() != self.rows + 1 or self.colind.numel() != self.val.numel():
+            raise ValueError("inconsistent CSR arrays")
+
+    @classmethod
+    def from_scipy(cls, M, device="cuda:0"):
+        M = M.tocsr()
+        dev = torch.device(device)
+        return cls(M.shape[0], M.shape[1], torch.from_numpy(M.indptr.astype(np.int32)).to(dev),
+                   torch.from_numpy(M.indices.astype(np.int32)).to(dev), torch.from_numpy(M.data.astype(np.float64)).to(dev))
+
+    def _struct(self):
+        c = nat.Csr()
+        c.rows, c.cols = self.rows, self.cols
+        c.rowptr, c.colind, c.val = _ptr(self.rowptr), _ptr(self.colind), _ptr(self.val)
+        return c
+
+
 class Solver:
     """Augmented subspace eigensolver for the Q1 pencil of -div(kappa grad u) = lambda u.
 
@@ -49,26 +74,55 @@ class Solver:
              dense fallback), "dense", or "gcg" (PRECOND-A and GCG_AUG, Sec. 4: matrix-free, so
              V_H may be a level whose N_H no dense eigensolver reaches).
     coarse_level: index in levels of V_H (None = the last; levels above the last need "gcg").
+    hierarchy: algebraic input instead of a grid (dim and levels are then ignored): a dict with lists
+             "A", "M" (one CSR matrix per level, fine first) and "P", "R" (index 0 None, P[l] the
+             interpolation from level l to l-1, R[l] = P[l]^T), each a CsrMatrix or a scipy sparse
+             matrix (copied to the device).  The solver keeps them alive.
     aug_rtol: "gcg" only: GCG_AUG's stop, relative to each pair's outer residual (default 1e-2;
              0: to 1e-11).
     """
 
     def __init__(self, dim, levels, kappa=None, nev_max=16, precision="fp64", cg_steps=2, max_outer=500,
                  nu=2, omega=2.0 / 3.0, small_solver="auto", device="cuda:0", locking=True, guard=0,
-                 start="given", fallback_ratio=0.5, coarse_level=None, aug_rtol=1e-2, tensor=None, reaction=None):
+                 start="given", fallback_ratio=0.5, coarse_level=None, aug_rtol=1e-2, tensor=None, reaction=None,
+                 hierarchy=None):
         self.lib = nat.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
-        self.dim = int(dim)
-        self.levels = [int(n) for n in levels]
         prob = nat.Problem()
-        prob.dim = self.dim
-        prob.nlevels = len(self.levels)
-        if not 2 <= prob.nlevels <= nat.MAX_LEVELS:
-            raise ValueError("need 2..8 levels")
-        for i, n in enumerate(self.levels):
-            prob.n[i] = n
+        self._csr_keep = None
+        if hierarchy is not None:
+            if kappa is not None or tensor is not None:
+                raise ValueError("hierarchy excludes kappa and tensor")
+            mats = {}
+            for key in ("A", "M", "P", "R"):
+                mats[key] = [None if m is None else (m if isinstance(m, CsrMatrix) else CsrMatrix.from_scipy(m, device))
+                             for m in hierarchy[key]]
+            nl = len(mats["A"])
+            if not 2 <= nl <= nat.MAX_LEVELS or any(len(mats[key]) != nl for key in mats):
+                raise ValueError("hierarchy: 2..8 levels, the same count for A, M, P, R")
+            hs = nat.HierarchyCsr()
+            hs.nlevels = nl
+            for key in ("A", "M", "P", "R"):
+                arr = getattr(hs, key)
+                for l, m in enumerate(mats[key]):
+                    if m is not None:
+                        arr[l] = m._struct()
+            self._csr_keep = (mats, hs)
+            prob.csr = C.cast(C.pointer(hs), C.c_void_p)
+            self.dim = 0
+            self.levels = [m.rows for m in mats["A"]]
+            dim, levels = 0, []
+        else:
+            self.dim = int(dim)
+            self.levels = [int(n) for n in levels]
+            prob.dim = self.dim
+            prob.nlevels = len(self.levels)
+            if not 2 <= prob.nlevels <= nat.MAX_LEVELS:
+                raise ValueError("need 2..8 levels")
+            for i, n in enumerate(self.levels):
+                prob.n[i] = n
         self._kappa = None
         if kappa is not None:
             ne = self.levels[0] ** self.dim
@@ -136,6 +190,28 @@ class Solver:
 
     def _new(self, rows, k):
         return torch.empty((rows, k), dtype=torch.float64, device=self.device)
+
+    def export_csr(self, level, which):
+        """The grid hierarchy's operator as a CsrMatrix on the device: which = "A", "M" (level l),
+        "P" (interpolation from level l to l - 1) or "R" (P^T)."""
+        w = {"A": 0, "M": 1, "P": 2, "R": 3}[which]
+        rows, cols, slots = C.c_int(0), C.c_int(0), C.c_int(0)
+        self._check(self.lib.pase_export_csr(self.h, int(level), w, C.byref(rows), C.byref(cols), C.byref(slots),
+                                             None, None, None), self.h)
+        r, c, sl = rows.value, cols.value, slots.value
+        rowptr = torch.empty(r + 1, dtype=torch.int32, device=self.device)
+        colind = torch.empty(r * sl, dtype=torch.int32, device=self.device)
+        val = torch.empty(r * sl, dtype=torch.float64, device=self.device)
+        self._check(self.lib.pase_export_csr(self.h, int(level), w, C.byref(rows), C.byref(cols), C.byref(slots),
+                                             _ptr(rowptr), _ptr(colind), _ptr(val)), self.h)
+        return CsrMatrix(r, c, rowptr, colind, val)
+
+    def export_hierarchy(self):
+        """The whole hierarchy, in the form the hierarchy= argument takes."""
+        L = len(self.levels)
+        return {"A": [self.export_csr(l, "A") for l in range(L)], "M": [self.export_csr(l, "M") for l in range(L)],
+                "P": [None] + [self.export_csr(l, "P") for l in range(1, L)],
+                "R": [None] + [self.export_csr(l, "R") for l in range(1, L)]}
 
     def level_size(self, level):
         n = C.c_longlong(0)
