@@ -54,6 +54,10 @@ WORKLOADS = {
     # configs 3 and 5 (128^3, V_H = 16^3, nev 100); the fine operator is an assembled 27-point stencil
     "general3d-128": dict(dim=3, levels=[128, 64, 32, 16], nev=100, tol=1e-8, kappa_seed=None, guard=28,
                           start="coarse", train_n=None, general=True),
+    # configs 3 and 5 given as matrices (the algebraic input): the grid hierarchy exported as CSR, solved
+    # through the CSR kernels
+    "kappa3d-128-csr": dict(dim=3, levels=[128, 64, 32, 16], nev=100, tol=1e-8, kappa_seed=0, guard=28,
+                            start="coarse", train_n=None, csr=True),
 }
 
 
@@ -65,10 +69,13 @@ def stencil_hash():
     return h.hexdigest()[:16]
 
 
-def spmm_bytes(N, k, n_elem, variable_kappa, general=False):
+def spmm_bytes(N, k, n_elem, variable_kappa, general=False, csr_nnz=None):
     """Algorithmic HBM bytes of one fused A X, M X launch: X read, A X and M X written (N x k doubles
     each), kappa read once (n^3 doubles) when it varies, or the assembled 27 coefficients per node of
-    the tensor-coefficient problem.  Halo re-reads are not counted."""
+    the tensor-coefficient problem, or (CSR input) both matrices' row pointers, column indices and
+    values.  Halo / neighbour re-reads are not counted."""
+    if csr_nnz is not None:
+        return 3 * N * k * 8 + 2 * (csr_nnz * 12 + (N + 1) * 4)
     if general:
         return 3 * N * k * 8 + 27 * N * 8
     return 3 * N * k * 8 + (n_elem * 8 if variable_kappa else 0)
@@ -168,11 +175,20 @@ def main():
     dim, levels, nev, tol, kseed = w["dim"], w["levels"], w["nev"], w["tol"], w["kappa_seed"]
     guard, start = w["guard"], w["start"]
     kappa = None if kseed is None else synth.kappa_field(dim, levels[0], kseed)
+    kappa_oracle = kappa          # the coefficient the CPU oracle assembles (also for the CSR input)
     # the tensor-coefficient workload: every solver of this run gets the same tensor and reaction
     gen_kw = {}
+    csr_nnz = None
     if w.get("general"):
         gT, gphi = synth.general_coefficients(levels[0])
         gen_kw = dict(tensor=gT, reaction=gphi)
+    if w.get("csr"):
+        # the grid hierarchy exported as CSR matrices (the library's own export); kappa then lives in them
+        grid = Solver(dim, levels, kappa, nev_max=1)
+        gen_kw = dict(hierarchy=grid.export_hierarchy())
+        csr_nnz = int(gen_kw["hierarchy"]["A"][0].val.numel())
+        del grid
+        kappa = None
 
     # plain copy of a known size (calibrates the FETCH_SIZE / WRITE_SIZE counters of --pmc runs)
     cal_src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -371,7 +387,7 @@ def main():
     N = s.N[0]
     n_elem = levels[0] ** dim
     ms = s.time_kernel("apply", k, reps=30)
-    nbytes = spmm_bytes(N, k, n_elem, kseed is not None, bool(w.get("general")))
+    nbytes = spmm_bytes(N, k, n_elem, kseed is not None, bool(w.get("general")), csr_nnz)
     achieved = nbytes / (ms * 1e-3) / 1e9
     traffic = None
     if (SPMM_TRAFFIC["bytes"] is not None and args.workload == "kappa3d-128"
@@ -380,6 +396,8 @@ def main():
     mv = N * k * 8
     rates = {}
     kb = n_elem * 8 if kseed is not None else (27 * N * 8 if w.get("general") else 0)
+    if csr_nnz is not None:
+        kb = csr_nnz * 12 + (N + 1) * 4
     for name, key, nb in (("spmm_AX_MX", "apply", nbytes), ("spmm_AX", "apply_A", 2 * mv + kb),
                           ("spmm_MX", "apply_M", 2 * mv), ("cg_update", "cg_update", 6 * mv),
                           ("vcycle_sweep", "sweep", 3 * mv + kb)):
@@ -437,7 +455,9 @@ def main():
                              "configuration the CPU oracle runs",
         },
         "roofline": {
-            "kernel": ("fused fine-level A X, M X (fine3v_kernel<double, EPI_AM, ASM>, LDS-staged 3D stencil with an "
+            "kernel": ("fused fine-level A X, M X (csr_op_kernel<double, EPI_AM>, one wavefront per CSR row) "
+                       if csr_nnz is not None else
+                       "fused fine-level A X, M X (fine3v_kernel<double, EPI_AM, ASM>, LDS-staged 3D stencil with an "
                        "assembled 27-coefficient row per node) " if w.get("general")
                        else "fused fine-level A X, M X (fine3v_kernel<double, EPI_AM>, LDS-staged 3D Q1 stencil) ")
                       + f"at k = {k}",
@@ -461,7 +481,7 @@ def main():
     if not args.no_cpu_baseline:
         del s
         torch.cuda.empty_cache()
-        out["cpu_baseline"] = cpu_baseline(w, kappa, oracle_cfg["outer_iters"])
+        out["cpu_baseline"] = cpu_baseline(w, kappa_oracle, oracle_cfg["outer_iters"])
     print(json.dumps(out), flush=True)
 
 

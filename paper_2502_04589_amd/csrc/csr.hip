@@ -17,7 +17,75 @@ namespace {
 constexpr int kCsrWaves = 4;
 constexpr int kCsrQ = 4;             // columns per lane: k <= 256
 
-template <typename T, int EPI>
+// Column of slot q of a lane: lane + 64 q, or with PAIR (k even) the pairs 2 lane + 128 (q / 2)
+// + (q % 2), so that a lane's two adjacent columns are one vector load
+template <bool PAIR>
+__device__ __forceinline__ int col_of(int lane, int q) {
+  return PAIR ? 2 * lane + 128 * (q >> 1) + (q & 1) : lane + 64 * q;
+}
+
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { typedef double2 type; };
+template <> struct Pair2<float> { typedef float2 type; };
+
+// x values of the lane's columns in row c of X
+template <typename T, bool PAIR>
+__device__ __forceinline__ void load_row(const T* __restrict__ X, long long c, int lane, int k, double (&xv)[kCsrQ]) {
+  if constexpr (PAIR) {
+    typedef typename Pair2<T>::type V2;
+#pragma unroll
+    for (int h = 0; h < kCsrQ / 2; ++h) {
+      const int col = 2 * lane + 128 * h;
+      if (col < k) {
+        const V2 v = *(const V2*)(X + c * k + col);
+        xv[2 * h] = (double)v.x;
+        xv[2 * h + 1] = (double)v.y;
+      } else {
+        xv[2 * h] = xv[2 * h + 1] = 0.0;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kCsrQ; ++q) {
+      const int col = lane + 64 * q;
+      xv[q] = (col < k) ? (double)X[c * k + col] : 0.0;
+    }
+  }
+}
+
+// acc[q] += sum over row r of A: val * X[col, col_of(lane, q)]; four nonzeros at a time so that
+// their row loads are in flight together
+template <typename T, bool PAIR>
+__device__ __forceinline__ void csr_row(const CsrMat& A, long long r, int lane, int k, const T* __restrict__ X,
+                                        double (&acc)[kCsrQ]) {
+  const int p0 = A.rowptr[r], p1 = A.rowptr[r + 1];
+  int p = p0;
+  for (; p + 4 <= p1; p += 4) {
+    long long c[4];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c[u] = A.colind[p + u];
+      v[u] = A.val[p + u];
+    }
+    double xv[4][kCsrQ];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load_row<T, PAIR>(X, c[u], lane, k, xv[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < kCsrQ; ++q) acc[q] = fma(v[u], xv[u][q], acc[q]);
+  }
+  for (; p < p1; ++p) {
+    double xv[kCsrQ];
+    load_row<T, PAIR>(X, A.colind[p], lane, k, xv);
+    const double v = A.val[p];
+#pragma unroll
+    for (int q = 0; q < kCsrQ; ++q) acc[q] = fma(v, xv[q], acc[q]);
+  }
+}
+
+template <typename T, int EPI, bool PAIR>
 __global__ __launch_bounds__(64 * kCsrWaves) void csr_op_kernel(CsrOpArgs a, long long rpb) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -37,34 +105,12 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_op_kernel(CsrOpArgs a, lon
     double ax[kCsrQ], mx[kCsrQ], xc[kCsrQ];
 #pragma unroll
     for (int q = 0; q < kCsrQ; ++q) ax[q] = mx[q] = xc[q] = 0.0;
-    if (needA) {
-      const int p0 = a.A.rowptr[r], p1 = a.A.rowptr[r + 1];
-      for (int p = p0; p < p1; ++p) {
-        const long long c = a.A.colind[p];
-        const double v = a.A.val[p];
-#pragma unroll
-        for (int q = 0; q < kCsrQ; ++q) {
-          const int col = lane + 64 * q;
-          if (col < k) ax[q] = fma(v, (double)X[c * k + col], ax[q]);
-        }
-      }
-    }
-    if (needM) {
-      const int p0 = a.M.rowptr[r], p1 = a.M.rowptr[r + 1];
-      for (int p = p0; p < p1; ++p) {
-        const long long c = a.M.colind[p];
-        const double v = a.M.val[p];
-#pragma unroll
-        for (int q = 0; q < kCsrQ; ++q) {
-          const int col = lane + 64 * q;
-          if (col < k) mx[q] = fma(v, (double)X[c * k + col], mx[q]);
-        }
-      }
-    }
+    if (needA) csr_row<T, PAIR>(a.A, r, lane, k, X, ax);
+    if (needM) csr_row<T, PAIR>(a.M, r, lane, k, X, mx);
     const double wd = (EPI == EPI_SWEEP) ? a.omega * a.dinv[r] : 0.0;
 #pragma unroll
     for (int q = 0; q < kCsrQ; ++q) {
-      const int col = lane + 64 * q;
+      const int col = col_of<PAIR>(lane, q);
       if (col >= k) continue;
       const long long e = r * k + col;
       if (EPI == EPI_SWEEP || EPI == EPI_EIGRES) xc[q] = (double)X[e];
@@ -88,9 +134,10 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_op_kernel(CsrOpArgs a, lon
     __shared__ double red[3][kCsrWaves][64 * kCsrQ];
 #pragma unroll
     for (int q = 0; q < kCsrQ; ++q) {
-      red[0][wave][lane + 64 * q] = s0[q];
-      red[1][wave][lane + 64 * q] = s1[q];
-      red[2][wave][lane + 64 * q] = s2[q];
+      const int col = col_of<PAIR>(lane, q);   // a permutation of 0 .. 255
+      red[0][wave][col] = s0[q];
+      red[1][wave][col] = s1[q];
+      red[2][wave][col] = s2[q];
     }
     __syncthreads();
     double* p = a.partial + (size_t)blockIdx.x * 3 * k;
@@ -106,7 +153,7 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_op_kernel(CsrOpArgs a, lon
 }
 
 // y (=, +=, -=) A x (mode 0, 1, 2) for a rows x cols CSR A and multi-vectors of k columns
-template <typename T>
+template <typename T, bool PAIR>
 __global__ __launch_bounds__(64 * kCsrWaves) void csr_apply_kernel(CsrMat A, long long rows, int k, const T* __restrict__ x,
                                                                   T* __restrict__ y, int mode, long long rpb) {
   const int lane = threadIdx.x & 63;
@@ -117,19 +164,10 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_apply_kernel(CsrMat A, lon
     double acc[kCsrQ];
 #pragma unroll
     for (int q = 0; q < kCsrQ; ++q) acc[q] = 0.0;
-    const int p0 = A.rowptr[r], p1 = A.rowptr[r + 1];
-    for (int p = p0; p < p1; ++p) {
-      const long long c = A.colind[p];
-      const double v = A.val[p];
-#pragma unroll
-      for (int q = 0; q < kCsrQ; ++q) {
-        const int col = lane + 64 * q;
-        if (col < k) acc[q] = fma(v, (double)x[c * k + col], acc[q]);
-      }
-    }
+    csr_row<T, PAIR>(A, r, lane, k, x, acc);
 #pragma unroll
     for (int q = 0; q < kCsrQ; ++q) {
-      const int col = lane + 64 * q;
+      const int col = col_of<PAIR>(lane, q);
       if (col >= k) continue;
       const long long e = r * k + col;
       if (mode == 0) y[e] = (T)acc[q];
@@ -268,8 +306,8 @@ __global__ void export_restrict_kernel(int mf, int mc, int* __restrict__ rowptr,
 inline unsigned blocks_of(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 long long csr_rows_per_block(long long rows) {
-  // about 2048 blocks, at least one row per wave
-  long long rpb = (rows + 2047) / 2048;
+  // about 8192 blocks (32 per CU), at least one row per wave
+  long long rpb = (rows + 8191) / 8192;
   if (rpb < kCsrWaves) rpb = kCsrWaves;
   return rpb;
 }
@@ -282,9 +320,15 @@ void launch_csr_op(const CsrOpArgs& a, Epi epi, hipStream_t s) {
   const long long rpb = csr_rows_per_block(a.rows);
   const unsigned nb = (unsigned)((a.rows + rpb - 1) / rpb);
   const dim3 blk(64 * kCsrWaves);
+  const bool pair = (a.k % 2) == 0;
 #define PASE_CSR(E)                                                                                  \
-  if (a.fp32) csr_op_kernel<float, E><<<nb, blk, 0, s>>>(a, rpb);                                   \
-  else csr_op_kernel<double, E><<<nb, blk, 0, s>>>(a, rpb);
+  if (a.fp32) {                                                                                      \
+    if (pair) csr_op_kernel<float, E, true><<<nb, blk, 0, s>>>(a, rpb);                              \
+    else csr_op_kernel<float, E, false><<<nb, blk, 0, s>>>(a, rpb);                                  \
+  } else {                                                                                           \
+    if (pair) csr_op_kernel<double, E, true><<<nb, blk, 0, s>>>(a, rpb);                             \
+    else csr_op_kernel<double, E, false><<<nb, blk, 0, s>>>(a, rpb);                                 \
+  }
   switch (epi) {
     case EPI_AM: PASE_CSR(EPI_AM) break;
     case EPI_RESID: PASE_CSR(EPI_RESID) break;
@@ -299,8 +343,16 @@ void launch_csr_apply(const CsrMat& A, long long rows, int k, const void* x, voi
                       hipStream_t s) {
   const long long rpb = csr_rows_per_block(rows);
   const unsigned nb = (unsigned)((rows + rpb - 1) / rpb);
-  if (fp32) csr_apply_kernel<float><<<nb, 64 * kCsrWaves, 0, s>>>(A, rows, k, (const float*)x, (float*)y, mode, rpb);
-  else csr_apply_kernel<double><<<nb, 64 * kCsrWaves, 0, s>>>(A, rows, k, (const double*)x, (double*)y, mode, rpb);
+  const bool pair = (k % 2) == 0;
+  if (fp32) {
+    if (pair) csr_apply_kernel<float, true><<<nb, 64 * kCsrWaves, 0, s>>>(A, rows, k, (const float*)x, (float*)y, mode, rpb);
+    else csr_apply_kernel<float, false><<<nb, 64 * kCsrWaves, 0, s>>>(A, rows, k, (const float*)x, (float*)y, mode, rpb);
+  } else {
+    if (pair)
+      csr_apply_kernel<double, true><<<nb, 64 * kCsrWaves, 0, s>>>(A, rows, k, (const double*)x, (double*)y, mode, rpb);
+    else
+      csr_apply_kernel<double, false><<<nb, 64 * kCsrWaves, 0, s>>>(A, rows, k, (const double*)x, (double*)y, mode, rpb);
+  }
 }
 
 void launch_csr_diag_inv(const CsrMat& A, long long rows, double* dinv, hipStream_t s) {
