@@ -139,3 +139,20 @@ def test_tensor_problem_argument_checks():
         Solver(3, [8, 4], np.ones(8 ** 3), nev_max=2, tensor=T)
     with pytest.raises(PaseError):
         Solver(3, [8, 4], None, nev_max=2, tensor=T, precision="learned")
+
+
+@pytest.mark.parametrize("small_solver, c", [("auto", None), ("gcg", 1)])
+def test_general_64cubed_matches_golden(small_solver, c):
+    """64^3, the paper's tensor and reaction, nev 40 with 8 guard pairs, coarse start: V_H = 16^3 on the
+    structured path, or V_H = 32^3 (N_H = 29,791) by GCG_AUG; every eigenvalue within 1e-10 of the
+    oracle's lowest eigenpairs of the assembled pencil."""
+    d = np.load(os.path.join(GOLDEN, "general3d_64_k40.npz"))
+    lam_ref, n = d["lam"], int(d["n"])
+    T, phi = synth.general_coefficients(n)
+    kw = dict(small_solver="gcg", coarse_level=c) if small_solver == "gcg" else {}
+    print(f"general 64^3 {small_solver}", flush=True)
+    s = Solver(3, [64, 32, 16], None, nev_max=40, guard=8, start="coarse", tensor=T, reaction=phi, **kw)
+    lam, U, rep = s.solve(40, 1e-10, None)
+    np.testing.assert_allclose(lam, lam_ref, rtol=1e-10)
+    _check_pairs(s, lam, U, 1e-10)
+    print(f"  {rep['outer_iters']} corrections", flush=True)
