@@ -22,6 +22,9 @@ eigensolver", arXiv 2502.04589) with NumPy/SciPy in float64:
                     and the GCG_AUG eigensolver of the augmented problem
                     (Sec. 4, Alg. 4 and 5), used by ``pase.solve(small=
                     "precond_a")`` with V_H on any level of the hierarchy.
+* ``batch``      -- the batch scheme for many eigenpairs (Alg. 7): per batch a
+                    shift, the composite pairs nearest it and the selection of
+                    eq. largest_component, with guard pairs on both sides.
 * ``reference``  -- the fixed point written out: the k smallest eigenpairs of
                     the assembled pencil by a library eigensolver (Alg. 3
                     "Ensure").
@@ -34,4 +37,4 @@ eigensolver", arXiv 2502.04589) with NumPy/SciPy in float64:
 Readings of points the paper leaves open are listed in the docstrings where
 they are taken.
 """
-from . import fem, gcg_aug, multigrid, pase, reference, unet  # noqa: F401
+from . import batch, fem, gcg_aug, multigrid, pase, reference, unet  # noqa: F401
