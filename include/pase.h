@@ -227,6 +227,33 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
 pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, double* lambda_host,
                        double* U, pase_report* rep);
 
+/* Batch scheme (Sec. "Batch scheme for computing plenty of eigenpairs", Alg. 7 step 3): the pairs
+ * first .. first + nb - 1 (0-based, ascending) of (A_h, M) with a working block of nb + 2 guard
+ * pairs at most (opt.guard below the batch, fewer for first < guard, and opt.guard above it).
+ * Start: the block's coarse eigenvectors interpolated and its coarse eigenvalues; shift theta =
+ * the midpoint of the block's first and last coarse eigenvalue.  Per correction: s CG steps, the
+ * composite pencil, its min(2 k, N_H + k) eigenpairs nearest theta (k = the block's width), the k
+ * with the largest component in the span of the fine directions (eq. largest_component),
+ * prolongation; the test on those pairs (res_i <= tol for the batch's own pairs, positions of the
+ * block's ascending order); then s CG steps of post-smoothing from them.
+ * lambda_host: nb eigenvalues, ascending.  U: device, the batch's nb columns with row stride
+ * ldu >= nb (U^T M U = I for them).  rep->res_host (optional): nb residuals.  Needs the dense
+ * small path with the coarsest level's eigenbasis (small_solver 0 with the structured path on,
+ * N_H + nev_max + guard <= 3840, nev_max + guard <= 128) and block width <= nev_max + guard,
+ * first + nb + guard <= N_H;
+ * precision fp64 or mixed.  The pairs found are those that the coarse start resolves: batches
+ * beyond what V_H separates (coarse eigenvalue error above the spectral gaps) may converge to
+ * neighbouring pairs or not at all (PASE_E_NOTCONV after opt.max_outer corrections). */
+pase_status pase_solve_batch(pase_handle* h, int first, int nb, double tol, double* lambda_host, double* U,
+                             int ldu, pase_report* rep);
+
+/* Alg. 7: the m smallest pairs in batches of nb (the last one ragged), solved one after another
+ * by pase_solve_batch into lambda_host (m, ascending per batch) and the columns of U (device
+ * N_0 x m).  rep->res_host (optional) holds m entries; the report sums iterations, times and
+ * phases over the batches.  Stops at the first batch that fails and returns its status. */
+pase_status pase_solve_batches(pase_handle* h, int m, int nb, double tol, double* lambda_host, double* U,
+                               pase_report* rep);
+
 pase_status pase_destroy(pase_handle* h);
 
 const char* pase_status_string(pase_status s);

@@ -58,6 +58,10 @@ SIGNATURES = [
                              C.POINTER(C.c_void_p)]),
     ("pase_solve", C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.POINTER(Report)]),
+    ("pase_solve_batch", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
+                                   C.POINTER(Report)]),
+    ("pase_solve_batches", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
+                                     C.POINTER(Report)]),
     ("pase_destroy", C.c_int, [C.c_void_p]),
     ("pase_status_string", C.c_char_p, [C.c_int]),
     ("pase_last_error", C.c_char_p, [C.c_void_p]),

@@ -482,12 +482,13 @@ __device__ int sturm_count_l(int n, const double* d, const double* e2, double x,
 
 // The (t+1)-th smallest eigenvalue of the tridiagonal, t = blockIdx.x, by 64-point
 // multisection with Sturm counts (d and e^2 in LDS).
+// With off given, the eigenvalue of index *off + blockIdx.x (a window of the spectrum).
 __global__ __launch_bounds__(64) void bisect_large_kernel(int n, const double* __restrict__ tri,
-                                                         double* __restrict__ lam) {
+                                                         double* __restrict__ lam, const int* __restrict__ off) {
   extern __shared__ double dyn[];
   double* d = dyn;
   double* e2 = dyn + n;
-  const int t = blockIdx.x, lane = threadIdx.x;
+  const int t = blockIdx.x + (off ? *off : 0), lane = threadIdx.x;
   for (int i = lane; i < n; i += 64) {
     d[i] = tri[i];
     const double ei = tri[n + i];
@@ -509,7 +510,48 @@ __global__ __launch_bounds__(64) void bisect_large_kernel(int n, const double* _
     lo = nlo;
     hi = nhi;
   }
-  if (lane == 0) lam[t] = 0.5 * (lo + hi);
+  if (lane == 0) lam[blockIdx.x] = 0.5 * (lo + hi);
+}
+
+// Start of the index window of W = min(2 nsel, n) eigenvalues around theta: with c eigenvalues
+// below theta (a Sturm count), the nsel nearest theta form a run of consecutive indices inside
+// [c - nsel, c + nsel); off = that range clamped to [0, n - W].
+__global__ void window_start_kernel(int n, int nsel, double theta, const double* __restrict__ tri, int* off) {
+  if (threadIdx.x != 0) return;
+  const double* d = tri;
+  const double* e = tri + n;
+  const double pivmin = tri[3 * n + 2];
+  int c = 0;
+  double q = d[0] - theta;
+  if (fabs(q) < pivmin) q = -pivmin;
+  c += (q < 0.0);
+  for (int i = 1; i < n; ++i) {
+    q = (d[i] - theta) - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += (q < 0.0);
+  }
+  const int W = (2 * nsel < n) ? 2 * nsel : n;
+  int o = c - nsel;
+  if (o > n - W) o = n - W;
+  if (o < 0) o = 0;
+  *off = o;
+}
+
+// The nsel of the W ascending window values nearest theta (a run): the farther end is dropped
+// until nsel remain, the upper one on a tie.
+__global__ void nearest_run_kernel(int W, int nsel, double theta, const double* __restrict__ lamw,
+                                   double* __restrict__ lam) {
+  __shared__ int first;
+  if (threadIdx.x == 0) {
+    int l = 0, r = W;
+    while (r - l > nsel) {
+      if (fabs(lamw[l] - theta) > fabs(lamw[r - 1] - theta)) ++l;
+      else --r;
+    }
+    first = l;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nsel; i += blockDim.x) lam[i] = lamw[first + i];
 }
 
 __device__ __forceinline__ double hash_unit_l(unsigned a, unsigned b) {
@@ -764,10 +806,14 @@ size_t syev_large_work_doubles(int n, int k) {
   return w;
 }
 
-// The k smallest eigenpairs of the dense symmetric n x n matrix T (overwritten), n <= kLargeMaxN:
-// w (device, ascending), V (device n x k row-major).  *info = 0, or non-zero when the grid
-// barrier timed out or the orthonormalisation broke down.
-void launch_syev_large(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s) {
+size_t syev_window_work_doubles(int n, int nsel) { return syev_large_work_doubles(n, nsel) + 2 * (size_t)nsel + 8; }
+
+namespace {
+
+// k eigenpairs of the dense symmetric n x n matrix T (overwritten): the k smallest, or with
+// window set the k nearest theta.
+void syev_large_impl(int n, int k, bool window, double theta, double* T, double* w, double* V, double* work,
+                     int* info, hipStream_t s) {
   double* tri = work;
   double* lam = tri + 3 * n + 8;
   double* Vt = lam + k;
@@ -803,7 +849,16 @@ void launch_syev_large(int n, int k, double* T, double* w, double* V, double* wo
     }
   }
   launch_tri_finish(n, tri, s);
-  bisect_large_kernel<<<k, 64, 2 * (size_t)n * sizeof(double), s>>>(n, tri, lam);
+  if (window) {
+    double* lamw = work + syev_large_work_doubles(n, k);
+    int* off = (int*)(lamw + 2 * (size_t)k);
+    const int W = (2 * k < n) ? 2 * k : n;
+    window_start_kernel<<<1, 64, 0, s>>>(n, k, theta, tri, off);
+    bisect_large_kernel<<<W, 64, 2 * (size_t)n * sizeof(double), s>>>(n, tri, lamw, off);
+    nearest_run_kernel<<<1, 256, 0, s>>>(W, k, theta, lamw, lam);
+  } else {
+    bisect_large_kernel<<<k, 64, 2 * (size_t)n * sizeof(double), s>>>(n, tri, lam, nullptr);
+  }
   invit_large_kernel<<<k, 64, 5 * (size_t)n * sizeof(double) + (size_t)n, s>>>(n, tri, lam, Vt);
   if (k <= syev_max_k()) {
     launch_vorth2(n, k, Vt, Vt2, G, info, s);
@@ -824,6 +879,22 @@ void launch_syev_large(int n, int k, double* T, double* w, double* V, double* wo
   copy_vals_kernel<<<1, 256, 0, s>>>(k, lam, w);
   tg_fold_kernel<<<1, 1, 0, s>>>(info, err, cinfo);
   tg_fold_kernel<<<1, 1, 0, s>>>(info, err, cinfo + 1);
+}
+
+}  // namespace
+
+// The k smallest eigenpairs of the dense symmetric n x n matrix T (overwritten), n <= kLargeMaxN:
+// w (device, ascending), V (device n x k row-major).  *info = 0, or non-zero when the grid
+// barrier timed out or the orthonormalisation broke down.
+void launch_syev_large(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s) {
+  syev_large_impl(n, k, false, 0.0, T, w, V, work, info, s);
+}
+
+// The nsel eigenpairs of T nearest theta (nsel <= n <= kLargeMaxN), ascending: the window of
+// 2 nsel indices around theta by bisection, its nsel values nearest theta, their vectors.
+void launch_syev_window(int n, int nsel, double theta, double* T, double* w, double* V, double* work, int* info,
+                        hipStream_t s) {
+  syev_large_impl(n, nsel, true, theta, T, w, V, work, info, s);
 }
 
 }  // namespace pase

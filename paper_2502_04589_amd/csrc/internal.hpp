@@ -223,6 +223,11 @@ void launch_export_stencil(int dim, int m, const double* coef, double hmass, int
 void launch_export_prolong(int dim, int mf, int mc, int* rowptr, int* colind, double* val, hipStream_t s);
 void launch_export_restrict(int dim, int mf, int mc, int* rowptr, int* colind, double* val, hipStream_t s);
 
+// ---- batch scheme (batch.hip): the k of nsel <= batch_select_max() composite pairs with the
+// largest component in span(u_hat), from their coordinates Y (k x nsel) in an orthonormal basis of it
+int batch_select_max();
+void launch_batch_select(int k, int nsel, const double* Y, int* sel, int* flag, hipStream_t s);
+
 // ---- GCG_AUG (gcg.hip): augmented blocks are (N_H + k) x w row-major
 // C (m x n) = A^T B over N rows, A: N x m (lda), B: N x n (ldb); fixed-order reduction over at most
 // 128 row chunks; partial >= gram_tn_partial_doubles(N, m, n)
@@ -279,6 +284,10 @@ void launch_trinv_large(int n, const double* L, int ldl, double* Li, int ldi, do
 int syev_large_max_n();
 size_t syev_large_work_doubles(int n, int k);
 void launch_syev_large(int n, int k, double* T, double* w, double* V, double* work, int* info, hipStream_t s);
+// the nsel eigenpairs nearest theta, ascending (T overwritten; work of syev_window_work_doubles)
+size_t syev_window_work_doubles(int n, int nsel);
+void launch_syev_window(int n, int nsel, double theta, double* T, double* w, double* V, double* work, int* info,
+                        hipStream_t s);
 
 // ---- structured augmented eigenproblem (small.hip): Tt = [[diag(theta), Gt], [Gt^T, H]]
 int small_fast_max_k();

@@ -148,6 +148,12 @@ struct pase_handle {
   double *gGxx = nullptr, *gGxy = nullptr, *gGyy = nullptr, *gw = nullptr, *glam = nullptr, *glamn = nullptr;
   double *gsyw = nullptr, *gchs = nullptr, *gpart = nullptr, *gnorm = nullptr;
   int* gidx = nullptr;
+  // batch scheme (Alg. 7): the composite pairs nearest the shift (bnsel at most), their
+  // coordinates along span(u_hat), the selection, and P^T M W before the complement
+  int bnsel = 0;
+  double *bVw = nullptr, *blw = nullptr, *bZ = nullptr, *bS = nullptr, *bY = nullptr, *bGZ = nullptr;
+  double *bmw = nullptr, *bsyw = nullptr;
+  int* bsel = nullptr;
   int aug_iters = 0;                // GCG_AUG iterations of this solve
   int aug_restarts = 0;             // ... and its iterations redone after a breakdown
   double* pin_gnorm = nullptr;      // pinned: 2 K column norms
@@ -402,6 +408,20 @@ size_t layout(pase_handle* h, void* base) {
     size_t sw = syev_any_work(h->nT, (int)K);
     if (h->fast) sw = std::max(sw, syev_any_work((int)NH, (int)NH));   // setup: all of C0
     h->syw = b.take<double>(sw);
+    if (h->fast && 2 * K <= (size_t)batch_select_max()) {
+      // batch scheme: up to 2 K composite pairs nearest the shift
+      h->bnsel = (int)std::min(2 * K, nT);
+      const size_t ns = (size_t)h->bnsel;
+      h->bVw = b.take<double>(nT * ns);
+      h->blw = b.take<double>(ns);
+      h->bZ = b.take<double>(nT * K);
+      h->bS = b.take<double>(K * ns);
+      h->bY = b.take<double>(K * ns);
+      h->bGZ = b.take<double>(K * K);
+      h->bmw = b.take<double>(NH * K);
+      h->bsyw = b.take<double>(syev_window_work_doubles(h->nT, h->bnsel));
+      h->bsel = b.take<int>(K);
+    }
   }
   if (h->fast) {
     h->theta = b.take<double>(NH);
@@ -1302,6 +1322,199 @@ pase_status correction(pase_handle* h, int k) {
   return st;
 }
 
+// ---------------------------------------------------------------- batch scheme (Alg. 7)
+// One correction of a batch block (k columns of U, Lambda in lam, R = M U Lambda - A U) with
+// shift theta: (c) s CG steps, the complement and the projection, (d) the nsel composite pairs
+// nearest theta, (e) the k with the largest component in span(u_hat) (eq. largest_component),
+// prolongated into U with their eigenvalues in lam, ascending.
+//
+// In the basis [P L_B^{-T}, W_perp L^{-T}] of the dense path (B-orthonormal; beta_perp = L L^T)
+// the unmodified directions u_hat = W_perp + P B_H^{-1} P^T M W have the coordinates
+// Z = [L_B^{-1} P^T M W ; L^T], so for an eigenvector v of T the B-norm of its projection onto
+// span(u_hat) is ||L_Z^{-1} Z^T v||^2 with Z^T Z = L_Z L_Z^T.
+void batch_correction(pase_handle* h, int k, double theta) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  const int NH = (int)h->lev[h->L].N;
+  const int nT = NH + k;
+  const int nsel = std::min(2 * k, nT);
+  mark(h, PH_FINE);
+  h->fine_cols += k;
+  if (h->opt.precision == PASE_PREC_MIXED) pcg_correction_f32(h, k, h->U, h->R, h->X);
+  else pcg(h, k, h->U, h->X, h->R);
+  double* W = h->X;
+  mark(h, PH_PROJECTION);
+  apply_AM(h, 0, k, W, nullptr, h->W3);
+  restrict_all(h, k, h->W3, h->bmw);                                   // P^T M W
+  launch_gemm(false, false, NH, k, NH, 1.0, h->BHinv, NH, h->bmw, k, 0.0, h->cb, k, s);
+  prolong_all(h, k, h->cb, W, 2);                                      // W_perp
+  apply_AM(h, 0, k, W, h->W2, nullptr);
+  restrict_all(h, k, h->W2, h->ca);                                    // a = P^T A W_perp
+  launch_gram2_sym(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
+  launch_symmetrize(k, h->kk1, s);
+  launch_symmetrize(k, h->kk2, s);
+  launch_copy((size_t)k * k, h->kk2, h->kk4, s);                       // beta_perp
+  launch_cholinv(k, h->kk2, h->info + 1, s);                           // kk2 <- L^{-1}
+  launch_copy((size_t)k * k, h->kk2, h->kk3, s);                       // Li
+  launch_gemm(false, false, k, k, k, 1.0, h->kk3, k, h->kk4, k, 0.0, h->bZ + (size_t)NH * k, k, s);   // L^T
+  launch_gemm(false, false, NH, k, NH, 1.0, h->LBinv, NH, h->bmw, k, 0.0, h->bZ, k, s);
+  launch_gemm(false, false, k, k, k, 1.0, h->kk3, k, h->kk1, k, 0.0, h->kk4, k, s);
+  launch_gemm(false, true, k, k, k, 1.0, h->kk4, k, h->kk3, k, 0.0, h->kk5, k, s);             // H
+  launch_symmetrize(k, h->kk5, s);
+  // (d) T = [[C0, G], [G^T, H]], G = L_B^{-1} a Li^T; its nsel pairs nearest theta
+  mark(h, PH_SMALL);
+  launch_gemm(false, false, NH, k, NH, 1.0, h->LBinv, NH, h->ca, k, 0.0, h->cb, k, s);
+  launch_gemm(false, true, NH, k, k, 1.0, h->cb, k, h->kk3, k, 0.0, h->cc, k, s);
+  launch_set_diag_block(nT, NH, k, h->C0, h->cc, h->kk5, h->Tm, s);
+  launch_syev_window(nT, nsel, theta, h->Tm, h->blw, h->bVw, h->bsyw, h->info + 2, s);
+  // (e) the selection
+  launch_gemm(true, false, k, k, nT, 1.0, h->bZ, k, h->bZ, k, 0.0, h->bGZ, k, s);
+  launch_symmetrize(k, h->bGZ, s);
+  launch_cholinv(k, h->bGZ, h->info + 5, s);
+  launch_gemm(true, false, k, nsel, nT, 1.0, h->bZ, k, h->bVw, nsel, 0.0, h->bS, nsel, s);
+  launch_gemm(false, false, k, nsel, k, 1.0, h->bGZ, k, h->bS, nsel, 0.0, h->bY, nsel, s);
+  launch_batch_select(k, nsel, h->bY, h->bsel, h->info + 7, s);
+  launch_gather_cols(nT, nsel, k, h->bsel, h->bVw, h->Vs, s);
+  launch_gather_cols(1, nsel, k, h->bsel, h->blw, h->lam, s);
+  mark(h, PH_PROLONG);
+  launch_gemm(true, false, NH, k, NH, 1.0, h->LBinv, NH, h->Vs, k, 0.0, h->cb, k, s);          // y_H
+  prolongation_tail(h, k, h->cb);
+}
+
+struct BatchOut {
+  int iters = 0;
+  int nconv = 0;
+  float ms = 0.f;
+};
+
+// Alg. 7 step 3 for the pairs first .. first + nb - 1 with up to g guard pairs on each side:
+// the block holds the pairs b0 .. b0 + k - 1 (b0 = first - lo, lo = min(g, first), k = lo + nb + g).
+// The batch's pairs (positions lo .. lo + nb - 1 of the block, ascending) go to lam_out and to the
+// nb columns of Uout (row stride ldu); res_out (host, optional) gets their residuals.
+pase_status batch_run(pase_handle* h, int first, int nb, double tol, double* lam_out, double* Uout, int ldu,
+                      double* res_out, BatchOut* bo) {
+  hipStream_t s = h->stream;
+  const long long N = h->lev[0].N;
+  const int NH = (int)h->lev[h->L].N;
+  const int g = h->opt.guard;
+  const int lo = std::min(g, first);
+  const int b0 = first - lo;
+  const int k = lo + nb + g;
+  if (k > h->K) return fail(h, PASE_E_ARG, "the batch and its guard pairs exceed nev_max + guard");
+  if (b0 + k > NH) return fail(h, PASE_E_ARG, "the batch and its guard pairs exceed the coarse space");
+  HIPC(hipEventRecord(h->ev0, s));
+  h->nmark = 0;
+  mark(h, PH_START);
+  launch_fill_int(16, 0, h->info, s);
+  // (a) the coarse eigenvectors b0 .. b0 + k - 1 interpolated, Lambda = their eigenvalues;
+  // (b) theta = the midpoint of the block's first and last coarse eigenvalue
+  launch_copy_cols(NH, NH, k, k, h->Psi + b0, h->cb, 0, s);
+  prolong_all(h, k, h->cb, h->U, 0);
+  launch_copy((size_t)k, h->theta + b0, h->lam, s);
+  double th[2];
+  HIPC(hipMemcpyAsync(&th[0], h->theta + b0, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(&th[1], h->theta + b0 + k - 1, sizeof(double), hipMemcpyDeviceToHost, s));
+  mark(h, PH_RESIDUAL);
+  eig_residual(h, k, h->U, h->R);
+  HIPC(hipStreamSynchronize(s));
+  const double theta = 0.5 * (th[0] + th[1]);
+  std::vector<double> hs(3 * k), hl(k), res(k);
+  int it = 0, nconv = 0;
+  bool conv = false;
+  pase_status result = PASE_OK;
+  while (true) {
+    batch_correction(h, k, theta);
+    ++it;
+    // (g) on the pairs of step (e); their residual also starts the post-smoothing
+    mark(h, PH_RESIDUAL);
+    eig_residual(h, k, h->U, h->R);
+    mark(h, -1);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(h->pin_sums, h->sums, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(h->pin_lam, h->lam, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(h->pin_info, h->info, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    settle_marks(h);
+    std::memcpy(hs.data(), h->pin_sums, sizeof(double) * 3 * k);
+    std::memcpy(hl.data(), h->pin_lam, sizeof(double) * k);
+    const int* inf = h->pin_info;
+    if (inf[1] || inf[2] || inf[5] || inf[7]) {
+      result = fail(h, PASE_E_BREAKDOWN, "Cholesky of a Gram matrix, the windowed eigensolver or the selection failed");
+      break;
+    }
+    nconv = 0;
+    bool finite = true;
+    for (int j = 0; j < k; ++j) {
+      res[j] = std::sqrt(hs[j]) / (std::fabs(hl[j]) * std::sqrt(hs[k + j]));
+      if (!std::isfinite(res[j])) finite = false;
+      if (j >= lo && j < lo + nb && res[j] <= tol) ++nconv;
+    }
+    if (!finite) {
+      result = fail(h, PASE_E_BREAKDOWN, "non-finite residual or Ritz value");
+      break;
+    }
+    if (nconv == nb) { conv = true; break; }
+    if (it >= h->opt.max_outer) break;
+    // (f) post-smoothing from u_hat, then the next (c)'s start residual
+    mark(h, PH_FINE);
+    h->fine_cols += k;
+    if (h->opt.precision == PASE_PREC_MIXED) pcg_correction_f32(h, k, h->U, h->R, h->X);
+    else pcg(h, k, h->U, h->X, h->R);
+    std::swap(h->U, h->X);
+    mark(h, PH_RESIDUAL);
+    eig_residual(h, k, h->U, h->R);
+  }
+  launch_copy_cols(N, k, ldu, nb, h->U + lo, Uout, 0, s);
+  HIPC(hipEventRecord(h->ev1, s));
+  HIPC(hipMemcpyAsync(lam_out, h->lam + lo, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  settle_marks(h);
+  HIPC(hipEventElapsedTime(&bo->ms, h->ev0, h->ev1));
+  bo->iters = it;
+  bo->nconv = nconv;
+  if (res_out) std::memcpy(res_out, res.data() + lo, sizeof(double) * nb);
+  if (result != PASE_OK) return result;
+  if (!conv) return fail(h, PASE_E_NOTCONV, "max_outer reached before every pair of the batch met tol");
+  return PASE_OK;
+}
+
+pase_status batch_check(pase_handle* h, double tol, const double* lam_out, const double* U) {
+  if (!h) return fail(nullptr, PASE_E_ARG, "null handle");
+  if (!h->bsel || !h->Psi || !h->theta)
+    return fail(h, PASE_E_UNSUPPORTED,
+                "the batch scheme needs the dense small path with the coarsest level's eigenbasis "
+                "(small_solver 0, N_H + nev_max + guard <= 3840, nev_max + guard <= 128)");
+  if (h->opt.precision == PASE_PREC_LEARNED) return fail(h, PASE_E_UNSUPPORTED, "the batch scheme runs in fp64 or mixed");
+  if (!lam_out || !U) return fail(h, PASE_E_ARG, "null argument");
+  if (!(tol > 0.0)) return fail(h, PASE_E_ARG, "tol must be positive");
+  return PASE_OK;
+}
+
+void batch_begin(pase_handle* h, pase_report* rep) {
+  h->timing = (rep != nullptr);
+  for (double& t : h->t_phase) t = 0.0;
+  h->fine_cols = 0;
+  h->ka = 0;
+  h->spec = false;
+  h->proj_lp = false;
+}
+
+void batch_report(pase_handle* h, pase_report* rep, int iters, int nconv, double ms) {
+  h->timing = false;
+  if (!rep) return;
+  for (int p = 0; p < PASE_PHASES; ++p) rep->t_phase_ms[p] = h->t_phase[p];
+  rep->outer_iters = iters;
+  rep->n_converged = nconv;
+  rep->ritz_history_rows = 0;
+  rep->t_solve_ms = ms;
+  rep->small_fast_iters = 0;
+  rep->learned_fallbacks = 0;
+  rep->lowprec_projection_iters = 0;
+  rep->fine_solve_columns = h->fine_cols;
+  rep->aug_iters = 0;
+  rep->aug_restarts = 0;
+}
+
 pase_status read_info(pase_handle* h, int* out, int n) {
   HIPC(hipMemcpyAsync(out, h->info, sizeof(int) * n, hipMemcpyDeviceToHost, h->stream));
   HIPC(hipStreamSynchronize(h->stream));
@@ -1876,6 +2089,44 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
   if (result != PASE_OK) return result;
   if (!conv) return fail(h, PASE_E_NOTCONV, "max_outer reached before every pair met tol");
   return PASE_OK;
+}
+
+pase_status pase_solve_batch(pase_handle* h, int first, int nb, double tol, double* lambda_host, double* U, int ldu,
+                             pase_report* rep) {
+  pase_status st = batch_check(h, tol, lambda_host, U);
+  if (st) return st;
+  if (first < 0 || nb < 1 || ldu < nb) return fail(h, PASE_E_ARG, "need first >= 0, nb >= 1 and ldu >= nb");
+  batch_begin(h, rep);
+  BatchOut bo;
+  st = batch_run(h, first, nb, tol, lambda_host, U, ldu, rep ? rep->res_host : nullptr, &bo);
+  batch_report(h, rep, bo.iters, bo.nconv, bo.ms);
+  return st;
+}
+
+pase_status pase_solve_batches(pase_handle* h, int m, int nb, double tol, double* lambda_host, double* U,
+                               pase_report* rep) {
+  pase_status st = batch_check(h, tol, lambda_host, U);
+  if (st) return st;
+  if (m < 1 || nb < 1) return fail(h, PASE_E_ARG, "need m >= 1 and nb >= 1");
+  batch_begin(h, rep);
+  int iters = 0, nconv = 0;
+  double ms = 0.0;
+  double t_phase[PASE_PHASES] = {};
+  // Alg. 7 step 4: the batches one after another, batch i into columns first .. first + k_i - 1
+  for (int first = 0; first < m && st == PASE_OK; first += nb) {
+    const int k = std::min(nb, m - first);
+    BatchOut bo;
+    for (double& t : h->t_phase) t = 0.0;
+    double* ro = (rep && rep->res_host) ? rep->res_host + first : nullptr;
+    st = batch_run(h, first, k, tol, lambda_host + first, U + first, m, ro, &bo);
+    iters += bo.iters;
+    nconv += bo.nconv;
+    ms += bo.ms;
+    for (int p = 0; p < PASE_PHASES; ++p) t_phase[p] += h->t_phase[p];
+  }
+  for (int p = 0; p < PASE_PHASES; ++p) h->t_phase[p] = t_phase[p];
+  batch_report(h, rep, iters, nconv, ms);
+  return st;
 }
 
 pase_status pase_attach_unet(pase_handle* h, pase_unet* u) {

@@ -261,6 +261,38 @@ class Solver:
             self._check(st, self.h)
         return lam, U, report
 
+    def _batch_report(self, rep, st, res):
+        return {"outer_iters": rep.outer_iters, "n_converged": rep.n_converged, "res": res,
+                "t_solve_ms": rep.t_solve_ms, "fine_solve_columns": rep.fine_solve_columns,
+                "t_phase_ms": {name: float(rep.t_phase_ms[i]) for i, name in enumerate(nat.PHASES)},
+                "status": nat.STATUS.get(st, st)}
+
+    def solve_batch(self, first, nb, tol, raise_notconv=True):
+        """Alg. 7 step 3: the pairs first .. first + nb - 1 (guard pairs from the options).
+        Returns (lam [np], U [torch N x nb], report dict)."""
+        U = self._new(self.N[0], nb)
+        lam, res = np.zeros(nb), np.zeros(nb)
+        rep = nat.Report()
+        rep.res_host = res.ctypes.data
+        st = self.lib.pase_solve_batch(self.h, int(first), int(nb), float(tol), lam.ctypes.data, _ptr(U), int(nb),
+                                       C.byref(rep))
+        report = self._batch_report(rep, st, res)
+        if st != 0 and not (st == 4 and not raise_notconv):
+            self._check(st, self.h)
+        return lam, U, report
+
+    def solve_batches(self, m, nb, tol, raise_notconv=True):
+        """Alg. 7: the m smallest pairs in batches of nb.  Returns (lam, U [N x m], report)."""
+        U = self._new(self.N[0], m)
+        lam, res = np.zeros(m), np.zeros(m)
+        rep = nat.Report()
+        rep.res_host = res.ctypes.data
+        st = self.lib.pase_solve_batches(self.h, int(m), int(nb), float(tol), lam.ctypes.data, _ptr(U), C.byref(rep))
+        report = self._batch_report(rep, st, res)
+        if st != 0 and not (st == 4 and not raise_notconv):
+            self._check(st, self.h)
+        return lam, U, report
+
     # ------------------------------------------------------------------ components
     def apply(self, level, X):
         k = X.shape[1]
