@@ -8,6 +8,7 @@
 // partial-pivoting tridiagonal LU for their eigenvectors (re-orthogonalised
 // inside tight clusters, then two passes of Cholesky-QR over the block), and
 // back-transformation by the stored reflectors.
+#include <algorithm>
 #include <cfloat>
 
 #include "internal.hpp"
@@ -1020,8 +1021,11 @@ size_t syev_work_doubles(int n, int k) {
   // tri (3n + 8) + lam (k) + Vt, Vt2 (n k each) + G (k k) + S blocks (+ a second k x k
   // for the triangular inverse when k exceeds the one-block Cholesky-inverse)
   const size_t nblk = (size_t)(n + kWyB - 1) / kWyB + 1;
+  const size_t big = (k > kOrthoMaxK)
+                         ? (size_t)k * k + std::max(cholesky_large_scratch_doubles(k), trinv_large_scratch_doubles(k))
+                         : 0;
   return (size_t)3 * n + 8 + (size_t)k + (size_t)2 * n * k + (size_t)k * k + nblk * kWyB * kWyB +
-         4 * kCoopMaxN + 72 + ((k > kOrthoMaxK) ? (size_t)k * k : 0);
+         4 * kCoopMaxN + 72 + big;
 }
 
 int syev_max_k() { return kOrthoMaxK; }
@@ -1071,8 +1075,9 @@ void launch_syev_lowest(int n, int k, double* T, double* w, double* V, double* w
       launch_cholinv(k, G, info, s);
       vorth_apply_kernel<<<ab, kBlock, 0, s>>>(n, k, G, Vt, Vt2);
     } else {
-      launch_cholesky(k, G, k, info, s);
-      launch_trinv(k, G, k, G2, k, s);
+      // blocked Cholesky and triangular inverse (MFMA panel updates), scratch after G2
+      launch_cholesky_large(k, G, k, G2 + (size_t)k * k, info, s);
+      launch_trinv_large(k, G, k, G2, k, G2 + (size_t)k * k, s);
       vorth_apply_kernel<<<ab, kBlock, 0, s>>>(n, k, G2, Vt, Vt2);
     }
     double* t = Vt; Vt = Vt2; Vt2 = t;

@@ -1668,7 +1668,9 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   coarse_dense(0, AL);
   // blocked factorisations above one workgroup's size; their scratch follows the N_H x N_H
   // product area at the start of the setup scratch
-  const bool big_coarse = NH > kDenseSmallN;
+  // blocked factorisations (MFMA panel updates) above 64: the one-workgroup kernels take milliseconds
+  // already at N_H = 343
+  const bool big_coarse = NH > 64;
   double* lscr = h->setup_scratch + (size_t)NH * NH;
   auto cholesky = [&](double* A, int* inf) {
     if (big_coarse) launch_cholesky_large(NH, A, NH, lscr, inf, s);

@@ -321,7 +321,9 @@ __global__ void output_kernel(long long N, int k, const float* __restrict__ y, c
 namespace {
 
 // ---------------------------------------------------------------- weight gradient
-// Weight gradient, LDS-tiled: dW[o][ci][co] = sum over (b, n) of x[b][n + o][ci] g[b][n][co].
+// Weight gradient, LDS-tiled on FP32 VALU (the layers whose channel counts are not multiples of 16:
+// the first, 2 -> 16, and the last, 16 -> 1; the others use wgrad_mfma_kernel below):
+// dW[o][ci][co] = sum over (b, n) of x[b][n + o][ci] g[b][n][co].
 // grid.x: groups of 256 tasks, a task = (offset o, 8 input channels, 4 output channels) with its
 // 32 sums in registers; grid.y: node chunks, each looping over (batch item, spatial tile) pairs
 // t = blockIdx.y, blockIdx.y + gridDim.y, ...  Per tile the block stages the x halo tile (BF16,
@@ -334,13 +336,13 @@ struct WgCfg<2> { static constexpr int TX = 8, TY = 4, TZ = 4, RS = 8; };
 template <>
 struct WgCfg<16> { static constexpr int TX = 8, TY = 4, TZ = 4, RS = 24; };
 template <>
-struct WgCfg<32> { static constexpr int TX = 8, TY = 4, TZ = 4, RS = 40; };
+struct WgCfg<32> { static constexpr int TX = 8, TY = 4, TZ = 4; };
 template <>
-struct WgCfg<48> { static constexpr int TX = 8, TY = 4, TZ = 4, RS = 48; };
+struct WgCfg<48> { static constexpr int TX = 8, TY = 4, TZ = 4; };
 template <>
-struct WgCfg<64> { static constexpr int TX = 8, TY = 4, TZ = 2, RS = 72; };
+struct WgCfg<64> { static constexpr int TX = 8, TY = 4, TZ = 2; };
 template <>
-struct WgCfg<96> { static constexpr int TX = 8, TY = 4, TZ = 2, RS = 104; };
+struct WgCfg<96> { static constexpr int TX = 8, TY = 4, TZ = 2; };
 
 template <int CIN, int COUT>
 struct WgShape {
@@ -457,6 +459,119 @@ __global__ __launch_bounds__(256) void wgrad_tile_kernel(int m, int batch, const
       const int co = co4 * 4 + j;
       if (co < COUT) dst[(size_t)(o * CIN + ci) * COUT + co] = acc[i][j];
     }
+  }
+}
+
+// Weight gradient on MFMA (layers with CIN and COUT multiples of 16): per offset o,
+// dW[o] (CIN x COUT) = sum over nodes of x(n + o)^T g(n), an A^T B product whose K dimension is the
+// nodes.  Block (mt, node chunk): input channels 16 mt .. 16 mt + 15 against all COUT outputs, every
+// offset; wave w owns the offsets w, w + 4, ... (7 or 6) with COUT / 16 accumulator tiles each.  Per
+// tile of 8 x 4 x 4 nodes the block stages its 16 channels of the x halo in LDS channel-major, once
+// per x-shift d = dx + 1 (xsh[d][c][halo row][lx] = x at halo column lx + d), so that a lane's eight
+// consecutive nodes of one channel at any offset are one aligned 16-byte read, and g transposed to
+// BF16 gt[co][node].  The K loop runs over 32-node chunks (four x-rows of the tile): lane l supplies
+// A[16 mt + l%16][nodes 8(l/16) .. +7] and B[nodes 8(l/16) .. +7][16 t + l%16] (B is read once per
+// chunk and serves all of the wave's offsets).  Accumulator register q holds
+// dW[o][16 mt + 4(l/16) + q][16 t + l%16].
+constexpr int kWmTX = 8, kWmTY = 4, kWmTZ = 4;
+constexpr int kWmRows = (kWmTY + 2) * (kWmTZ + 2);                 // halo rows (y, z) of a tile
+constexpr int kWmTN = kWmTX * kWmTY * kWmTZ;                        // nodes of a tile
+__host__ __device__ inline int wm_tiles(int m) {
+  return ((m + kWmTX - 1) / kWmTX) * ((m + kWmTY - 1) / kWmTY) * ((m + kWmTZ - 1) / kWmTZ);
+}
+
+template <int CINA, int CINB, int COUT, typename TG>
+__global__ __launch_bounds__(256) void wgrad_mfma_kernel(int m, int batch, const __bf16* __restrict__ srcA,
+                                                         const __bf16* __restrict__ srcB, const TG* __restrict__ g,
+                                                         float* __restrict__ partial) {
+  constexpr int CIN = CINA + CINB;
+  constexpr int TX = kWmTX, TY = kWmTY, TZ = kWmTZ, HX = TX + 2, HY = TY + 2, NR = kWmRows, TN = kWmTN;
+  constexpr int NT = COUT / 16, KCH = TN / 32, OPW = 7;
+  constexpr int E = 27 * CIN * COUT;
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0 && CINA % 8 == 0 && TN % 32 == 0, "MFMA weight-gradient shape");
+  __shared__ __align__(16) __bf16 xsh[3 * 16 * NR * 8];
+  __shared__ __align__(16) __bf16 gt[COUT * TN];
+
+  const int N = m * m * m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int mt = blockIdx.x;
+  f32x4 acc[OPW][NT];
+#pragma unroll
+  for (int i = 0; i < OPW; ++i)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[i][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  const int ntx = (m + TX - 1) / TX, nty = (m + TY - 1) / TY;
+  const int nsp = wm_tiles(m);
+  for (int t = blockIdx.y; t < nsp * batch; t += gridDim.y) {
+    const int b = t / nsp, sp = t - (t / nsp) * nsp;
+    const int tx = sp % ntx, ty = (sp / ntx) % nty, tz = sp / (ntx * nty);
+    const int x0 = tx * TX - 1, y0 = ty * TY - 1, z0 = tz * TZ - 1;
+    __syncthreads();
+    // x: item (halo row r, halo column hx, channel half c8) reads 8 channels and writes them to the
+    // shifted copies d with 0 <= hx - d < TX
+    for (int q = threadIdx.x; q < NR * HX * 2; q += 256) {
+      const int c8 = q & 1, h = q >> 1;
+      const int hx = h % HX, r = h / HX;
+      const int hy = r % HY, hz = r / HY;
+      const int X = x0 + hx, Y = y0 + hy, Z = z0 + hz;
+      bf16x8 v;
+      if (X >= 0 && X < m && Y >= 0 && Y < m && Z >= 0 && Z < m) {
+        const size_t nb = (size_t)b * N + (size_t)(Z * m + Y) * m + X;
+        const int c = mt * 16 + c8 * 8;
+        v = (c < CINA) ? *(const bf16x8*)(srcA + nb * CINA + c) : *(const bf16x8*)(srcB + nb * CINB + (c - CINA));
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int lx = hx - d;
+        if (lx < 0 || lx >= TX) continue;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xsh[((d * 16 + c8 * 8 + j) * NR + r) * 8 + lx] = v[j];
+      }
+    }
+    for (int q = threadIdx.x; q < TN * COUT; q += 256) {
+      const int n = q / COUT, c = q - (q / COUT) * COUT;
+      const int X = x0 + 1 + n % TX, Y = y0 + 1 + (n / TX) % TY, Z = z0 + 1 + n / (TX * TY);
+      const bool in = X < m && Y < m && Z < m;
+      const size_t nd = (size_t)b * N + (size_t)(Z * m + Y) * m + X;
+      gt[c * TN + n] = in ? (__bf16)(float)g[nd * COUT + c] : (__bf16)0.0f;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int kc = 0; kc < KCH; ++kc) {
+      const int row = kc * 4 + lg;
+      const int ly = row % TY, lz = row / TY;
+      bf16x8 bv[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) bv[nt] = *(const bf16x8*)(gt + (nt * 16 + li) * TN + kc * 32 + 8 * lg);
+#pragma unroll
+      for (int i = 0; i < OPW; ++i) {
+        const int o = wave + 4 * i;
+        if (o >= 27) continue;
+        const int d = o % 3, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        const int r = (lz + 1 + dz) * HY + (ly + 1 + dy);
+        const bf16x8 av = *(const bf16x8*)(xsh + ((d * 16 + li) * NR + r) * 8);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[i][nt], 0, 0, 0);
+      }
+    }
+  }
+  float* dst = partial + (size_t)blockIdx.y * E;
+#pragma unroll
+  for (int i = 0; i < OPW; ++i) {
+    const int o = wave + 4 * i;
+    if (o >= 27) continue;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ci = mt * 16 + 4 * lg + q, co = nt * 16 + li;
+        dst[(size_t)(o * CIN + ci) * COUT + co] = acc[i][nt][q];
+      }
   }
 }
 
@@ -758,8 +873,15 @@ void wgrad_launch(pase_unet* u, int i, int batch, const __bf16* a, const __bf16*
   const int m = u->m[l.level];
   const int chunks = S::chunks(m, batch);
   const int E = (int)l.E();
-  wgrad_tile_kernel<CINA, CINB, COUT, TG><<<dim3((unsigned)S::TASK_BLOCKS, (unsigned)chunks), 256, 0, u->stream>>>(
-      m, batch, a, b2, g, u->wpart);
+  constexpr int CIN = CINA + CINB;
+  if constexpr (CIN % 16 == 0 && COUT % 16 == 0) {
+    // one block per 16 input channels and node chunk (chunks: as many as the partial buffer holds)
+    wgrad_mfma_kernel<CINA, CINB, COUT, TG><<<dim3((unsigned)(CIN / 16), (unsigned)chunks), 256, 0, u->stream>>>(
+        m, batch, a, b2, g, u->wpart);
+  } else {
+    wgrad_tile_kernel<CINA, CINB, COUT, TG><<<dim3((unsigned)S::TASK_BLOCKS, (unsigned)chunks), 256, 0, u->stream>>>(
+        m, batch, a, b2, g, u->wpart);
+  }
   wgrad_reduce_kernel<<<nb256(E), 256, 0, u->stream>>>(chunks, E, u->wpart, u->G + l.woff);
 }
 
