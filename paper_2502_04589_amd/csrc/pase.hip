@@ -504,16 +504,19 @@ void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void
     launch_csr_op(a, epi, h->stream);
     return;
   }
-  // 3D: the LDS-tiled stencil on the fine level, and on every level when kappa = 1 (nested Q1
-  // spaces with exact integration: the Galerkin operator P^T A P equals the Q1 stencil of the
-  // coarse mesh, so the constant stencil of width h_l applies it)
-  if (h->dim == 3 && (l == 0 || h->kappa_is_one)) {
+  // 3D: the LDS-tiled stencil on every level.  The fine level reads kappa per element (or the
+  // assembled row of the tensor-coefficient problem); kappa = 1 takes the constant stencil on every
+  // level (nested Q1 spaces with exact integration: the Galerkin operator P^T A P equals the Q1
+  // stencil of the coarse mesh); otherwise a coarse level reads its assembled Galerkin row.  M is the
+  // Q1 mass stencil of width h_l on every level, which the Galerkin product of the fine mass equals.
+  if (h->dim == 3) {
+    const bool coarse_rows = (l > 0 && !h->kappa_is_one);
     Fine3Args f{};
     f.m = h->lev[l].m;
     f.k = k;
     f.h = h->lev[l].h;
-    f.kappa = (h->kappa_is_one || h->fine_general) ? nullptr : h->kappa;
-    f.coef = (h->fine_general && l == 0) ? h->lev[0].coef : nullptr;
+    f.kappa = (h->kappa_is_one || h->fine_general || l > 0) ? nullptr : h->kappa;
+    f.coef = coarse_rows ? h->lev[l].coef : ((h->fine_general && l == 0) ? h->lev[0].coef : nullptr);
     f.x = x;
     f.b = b;
     f.lam = h->lam;
