@@ -45,6 +45,10 @@ enum Epi : int {
   // 3D LDS-staged stencil only, chosen by launch_fine3 for EPI_AM with one output:
   EPI_A = 7,        // out1 = A x
   EPI_M = 8,        // out2 = M x (kappa-independent: staged planes are read once)
+  // 3D LDS-staged only, variable coefficient: the first two damped-Jacobi sweeps from x = 0 with x
+  // and b both passed as b: the staged planes hold x1 = omega D^{-1} b (scaled as they are staged),
+  // out = x1 + omega D^{-1} (b - A x1)
+  EPI_SWEEP2V = 9,
 };
 
 struct StencilArgs {
@@ -110,6 +114,7 @@ struct Fine3Args {
   int nzc;               // z-runs per column chunk
   int fp32;              // 1: multi-vectors are float
   const void* zero;      // >= 16 zero bytes (read by out-of-domain halo lanes)
+  const double* dinv;    // EPI_SWEEP2V: 1 / diag(A) per node
 };
 void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s);
 int fine3_spatial_blocks(int m, int nzc);

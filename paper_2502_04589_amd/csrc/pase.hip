@@ -527,6 +527,7 @@ void stencil_op(pase_handle* h, int l, int k, Epi epi, const void* x, const void
     f.nzc = fine3_default_nzc(f.m);
     f.fp32 = fp32;
     f.zero = h->zero16;
+    f.dinv = h->lev[l].dinv;
     launch_fine3(f, epi, h->stream);
     return;
   }
@@ -613,6 +614,13 @@ void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x
   if (h->dim == 3 && h->kappa_is_one && h->opt.nu >= 2) {
     // constant coefficient: the first two sweeps from x = 0 in one pass over b
     stencil_op(h, l, k, EPI_SWEEP2, b, nullptr, t1, nullptr, B.fp32);
+    cur = t1;
+    oth = t0;
+    i0 = 2;
+  } else if (h->dim == 3 && !h->alg && h->opt.nu >= 2) {
+    // variable coefficient: the same pass, the first sweep's x1 = omega D^{-1} b formed as the
+    // planes of b are staged
+    stencil_op(h, l, k, EPI_SWEEP2V, b, b, t1, nullptr, B.fp32);
     cur = t1;
     oth = t0;
     i0 = 2;

@@ -131,6 +131,7 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   int hoff[2];
   bool hin[2];
   int hslot[2];
+  int hnode[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int e = tid + u * kThreadsV;
@@ -141,6 +142,7 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     hin[u] = e < HV && x >= 0 && x < m && y >= 0 && y < m && c0 + cq * VW < k;
     hoff[u] = (y * m + x) * k + c0 + cq * VW;     // offset within a plane
     hslot[u] = (e < HV) ? e : -1;
+    hnode[u] = hin[u] ? y * m + x : 0;            // node within a plane
   }
   const long long plane = (long long)m * m * k;
   auto ld1 = [&](int z, int u) -> V {
@@ -166,8 +168,31 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   auto st1 = [&](int slot, int u, const V& v) {
     if (hslot[u] >= 0) xsflat[slot][hslot[u]] = v;
   };
+  // EPI_SWEEP2V: the staged planes hold x1 = omega D^{-1} b; the diagonal is loaded with the plane
+  // (kept in flight beside it) and applied when the plane is stashed
+  constexpr bool kFirst2 = (EPI == EPI_SWEEP2V);
+  const long long nplane = (long long)m * m;
+  auto ldd = [&](int z, int u) -> double {
+    if constexpr (kFirst2) {
+      const bool ok = hin[u] && z >= 0 && z < m;
+      return ok ? a.dinv[z * nplane + hnode[u]] : 0.0;
+    } else {
+      return 0.0;
+    }
+  };
+  auto st1s = [&](int slot, int u, const V& v, double d) {
+    if constexpr (kFirst2) {
+      const double w = a.omega * d;
+      V r;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(r, i, w * vget<T, VW>(v, i));
+      st1(slot, u, r);
+    } else {
+      st1(slot, u, v);
+    }
+  };
   const long long cbase = ((long long)gy * m + gx) * k + colv;
-  constexpr bool kSweep = (EPI == EPI_SWEEP || EPI == EPI_SWEEPDOT);
+  constexpr bool kSweep = (EPI == EPI_SWEEP || EPI == EPI_SWEEPDOT || EPI == EPI_SWEEP2V);
   constexpr bool kSums1 = (EPI == EPI_AMDOT || EPI == EPI_SWEEPDOT);   // one column sum
   const bool bneed = (EPI == EPI_RESID || kSweep) && nodeok && colv < k;
   auto bload = [&](int z) -> V {
@@ -209,16 +234,19 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   double kc[2][2][2];
   // prologue: planes z0-1, z0, z0+1 into slots 0, 1, 2; b(z0) then plane z0+2 in flight
   {
-    V t0 = ld1(z0 - 1, 0), t1 = ld1(z0 - 1, 1);
-    st1(0, 0, t0); st1(0, 1, t1);
-    t0 = ld1(z0, 0); t1 = ld1(z0, 1);
-    st1(1, 0, t0); st1(1, 1, t1);
-    t0 = ld1(z0 + 1, 0); t1 = ld1(z0 + 1, 1);
-    st1(2, 0, t0); st1(2, 1, t1);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const V t0 = ld1(z0 - 1 + p, 0), t1 = ld1(z0 - 1 + p, 1);
+      const double e0 = ldd(z0 - 1 + p, 0), e1 = ldd(z0 - 1 + p, 1);
+      st1s(p, 0, t0, e0);
+      st1s(p, 1, t1, e1);
+    }
   }
   V bA = bload(z0), bB = bA;
   V pA0 = ld1(z0 + 2, 0), pA1 = ld1(z0 + 2, 1);
   V pB0 = pA0, pB1 = pA1;
+  double dA[2] = {ldd(z0 + 2, 0), ldd(z0 + 2, 1)};
+  double dB[2] = {dA[0], dA[1]};
   if (!CONSTK && !ASM) {
 #pragma unroll
     for (int cy = 0; cy < 2; ++cy)
@@ -236,12 +264,16 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   // Output plane z: planes z-1, z, z+1 sit in slots sb, sb+1, sb+2 (mod 4) with sb = (z - z0) & 3;
   // PS0/PS1 hold plane z+2 (in flight since the previous step) and are stashed into slot sb+3;
   // PL0/PL1 receive plane z+3; BV is b(z) and BN receives b(z+1).
-#define PASE_STEP(z, PL0, PL1, PS0, PS1, BV, BN)                                                       \
+#define PASE_STEP(z, PL0, PL1, PS0, PS1, BV, BN, DL, DS)                                               \
   {                                                                                                     \
     const int sb = ((z) - z0) & 3;                                                                      \
     if (EPI == EPI_RESID || kSweep) BN = bload((z) + 1);                                                \
     PL0 = ld1((z) + 3, 0);                                                                              \
     PL1 = ld1((z) + 3, 1);                                                                              \
+    if (kFirst2) {                                                                                      \
+      DL[0] = ldd((z) + 3, 0);                                                                          \
+      DL[1] = ldd((z) + 3, 1);                                                                          \
+    }                                                                                                   \
     if (!CONSTK && !ASM) {                                                                              \
       _Pragma("unroll") for (int cy = 0; cy < 2; ++cy) _Pragma("unroll") for (int cx = 0; cx < 2; ++cx) { \
         kc[0][cy][cx] = kc[1][cy][cx];                                                                  \
@@ -249,8 +281,8 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
       }                                                                                                 \
     }                                                                                                   \
     if (nodeok && colv < k) compute_plane((z), sb, BV);                                                 \
-    st1((sb + 3) & 3, 0, PS0);                                                                          \
-    st1((sb + 3) & 3, 1, PS1);                                                                          \
+    st1s((sb + 3) & 3, 0, PS0, DS[0]);                                                                  \
+    st1s((sb + 3) & 3, 1, PS1, DS[1]);                                                                  \
     __syncthreads();                                                                                    \
   }
   // Constant coefficient (residual, sweep and eigen-residual epilogues): reuse along z.  A plane
@@ -425,8 +457,8 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     plane9(1, 1);       // plane z0
   }
   for (int z = z0; z < z1; z += 2) {
-    PASE_STEP(z, pB0, pB1, pA0, pA1, bA, bB)
-    if (z + 1 < z1) PASE_STEP(z + 1, pA0, pA1, pB0, pB1, bB, bA)
+    PASE_STEP(z, pB0, pB1, pA0, pA1, bA, bB, dB, dA)
+    if (z + 1 < z1) PASE_STEP(z + 1, pA0, pA1, pB0, pB1, bB, bA, dA, dB)
   }
 #undef PASE_STEP
   if (kSums1) {
@@ -504,6 +536,12 @@ void launchv_w(const Fine3Args& a, hipStream_t s) {
       else launchv_tile<T, VW, EPI, false, false, true>(a, s);
       return;
     }
+  }
+  if constexpr (EPI == EPI_SWEEP2V) {
+    // variable coefficient only (the caller passes coef or kappa)
+    if (vec) launchv_tile<T, VW, EPI, false, true, false>(a, s);
+    else launchv_tile<T, VW, EPI, false, false, false>(a, s);
+    return;
   }
   if (a.kappa && EPI != EPI_M) {
     if (vec) launchv_tile<T, VW, EPI, false, true, false>(a, s);
