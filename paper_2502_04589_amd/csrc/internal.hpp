@@ -334,6 +334,6 @@ void launch_small_rr_big(int nH, int k, const double* theta, const double* Gt, c
                          double* rq, double* res, double* scratch, hipStream_t s);
 void launch_small_accept_big(int nH, int k, int nev, const double* theta, const double* Gt, const double* Hm,
                              const double* rq, const double* res, double tol_abs, const double* tolv, double gap,
-                             double* lam, int* perm, int* status, hipStream_t s);
+                             double* lam, int* perm, int* status, double* scratch, hipStream_t s);
 
 }  // namespace pase

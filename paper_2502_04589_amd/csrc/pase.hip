@@ -867,7 +867,7 @@ void structured_attempt(pase_handle* h, int k) {
     launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);
     launch_small_rr_big(NH, k, h->theta, h->Gtl, h->kk5, h->Vtf, h->rqf, h->resf, h->sbig, s);
     launch_small_accept_big(NH, k, nevc, h->theta, h->Gtl, h->kk5, h->rqf, h->resf, h->small_acc * sc, tv, 1e-9 * sc,
-                            h->lam, h->permf, h->statf, s);
+                            h->lam, h->permf, h->statf, h->sbig, s);
   } else {
     launch_small_rqi(NH, k, h->theta, h->Gtl, h->kk5, h->lam, h->X0f, sc, tv, h->Vtf, h->rqf, s);
     launch_vorth2(nT, k, h->Vtf, h->Vtf2, h->Gf, h->statf + 2, s);

@@ -69,20 +69,19 @@ __device__ __forceinline__ double hash_pm1(unsigned a, unsigned b) {
 // v_mfma_f64_16x16x4f64.  A step covers 4 rows: lane (li, lk) loads Gt[r0 + lk][16 c + li]
 // for the 8 column blocks c, which is both the A operand (times d) of tile row c and the B
 // operand of tile column c.  Wave w accumulates the tiles w, w + 8, ... of the T x T grid.
-__device__ void form_schur_big(int nH, int k, const double* __restrict__ Gt, const double* __restrict__ theta,
-                               const double* __restrict__ Hm, double mu, BLds& L) {
+// acc (this wave's tiles w, w + 8, ... of the T x T grid) += sum over rows rb <= r < re of
+// d_r g_r g_r^T (re > rb)
+__device__ void schur_rows_acc(int rb, int re, int k, const double* __restrict__ Gt,
+                               const double* __restrict__ theta, double mu, double4_t (&acc)[8]) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int T = (k + 15) >> 4, TT = T * T;
-  double4_t acc[8];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
   // the next step's row values are loaded while this step's MFMAs run (two waves per SIMD
   // leave little else to hide the L2 latency)
   double gn[8], thn;
   auto fetch = [&](int r0) {
     const int row = r0 + lk;
-    const int rc = (row < nH) ? row : nH - 1;
+    const int rc = (row < re) ? row : re - 1;
     thn = theta[rc];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -90,14 +89,14 @@ __device__ void form_schur_big(int nH, int k, const double* __restrict__ Gt, con
       gn[c] = (c < T && col < k) ? Gt[(size_t)rc * k + col] : 0.0;
     }
   };
-  fetch(0);
-  for (int r0 = 0; r0 < nH; r0 += 4) {
-    const bool rok = r0 + lk < nH;
+  fetch(rb);
+  for (int r0 = rb; r0 < re; r0 += 4) {
+    const bool rok = r0 + lk < re;
     const double dv = rok ? 1.0 / (thn - mu) : 0.0;
     double g[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) g[c] = rok ? gn[c] : 0.0;
-    if (r0 + 4 < nH) fetch(r0 + 4);
+    if (r0 + 4 < re) fetch(r0 + 4);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int tt = wave + 8 * t;
@@ -113,6 +112,17 @@ __device__ void form_schur_big(int nH, int k, const double* __restrict__ Gt, con
       }
     }
   }
+}
+
+__device__ void form_schur_big(int nH, int k, const double* __restrict__ Gt, const double* __restrict__ theta,
+                               const double* __restrict__ Hm, double mu, BLds& L) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int T = (k + 15) >> 4, TT = T * T;
+  double4_t acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  schur_rows_acc(0, nH, k, Gt, theta, mu, acc);
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
@@ -382,12 +392,11 @@ __global__ __launch_bounds__(kBT) void srr_big_kernel(int nH, int k, const doubl
 // Number of eigenvalues of Tt below mu by Sylvester's law of inertia: #{theta_j < mu} plus the
 // negative pivots of an LDL^T of S(mu) without pivoting.  *trusted = false when a pivot is tiny
 // or the factor grows (the count is then not certain).  Every thread gets the result.
-__device__ int inertia_big(int nH, int k, const double* __restrict__ theta, const double* __restrict__ Gt,
-                           const double* __restrict__ Hm, double mu, BLds& L, bool* trusted) {
+// The count from S(mu) already in L.S (overwritten by its factor).
+__device__ int inertia_count(int nH, int k, const double* __restrict__ theta, double mu, BLds& L, bool* trusted) {
   __shared__ int ok_s, neg_s;
   __shared__ double amax_s;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  form_schur_big(nH, k, Gt, theta, Hm, mu, L);
   if (tid == 0) {
     ok_s = 1;
     neg_s = 0;
@@ -437,21 +446,20 @@ __device__ int inertia_big(int nH, int k, const double* __restrict__ theta, cons
   return count;
 }
 
-// Acceptance (one workgroup): ascending order of the Rayleigh quotients, every residual within
-// its tolerance, and the inertia count below mu* = (largest Rayleigh quotient) + gap equal to k.
-// When that count fails and the block carries guard pairs (nev < k), the count below the nev-th
-// Rayleigh quotient + gap equal to nev still certifies the wanted pairs as the nev smallest
-// (status[0] = 2: the guard pairs are then eigenpairs of Tt but not certified as the next ones).
-// status[0] = 0 rejects; status[1] = the last count.  lam ascending, perm = source column.
-__global__ __launch_bounds__(kBT) void saccept_big_kernel(int nH, int k, int nev, const double* __restrict__ theta,
-                                                        const double* __restrict__ Gt,
-                                                        const double* __restrict__ Hm,
-                                                        const double* __restrict__ rq,
+// Acceptance: ascending order of the Rayleigh quotients, every residual within its tolerance,
+// and the inertia count below mu* = (largest Rayleigh quotient) + gap equal to k.  When that count
+// fails and the block carries guard pairs (nev < k), the count below the nev-th Rayleigh quotient
+// + gap equal to nev still certifies the wanted pairs as the nev smallest (status[0] = 2: the guard
+// pairs are then eigenpairs of Tt but not certified as the next ones).  status[0] = 0 rejects;
+// status[1] = the last count.  lam ascending, perm = source column.
+// Three launches: the order and residual checks with the two shifts (one workgroup), the sums
+// over row chunks of Gt^T D(mu) Gt for both shifts (one workgroup per chunk and shift, partial
+// k x k blocks in part), and the Schur complements with their LDL^T counts (one workgroup).
+__global__ __launch_bounds__(kBT) void saccept_pre_kernel(int k, int nev, const double* __restrict__ rq,
                                                         const double* __restrict__ res, double tol_abs,
                                                         const double* __restrict__ tolv, double gap,
                                                         double* __restrict__ lam, int* __restrict__ perm,
-                                                        int* __restrict__ status) {
-  __shared__ BLds L;
+                                                        double* __restrict__ mus, int* __restrict__ status) {
   __shared__ double srt[kBK];
   __shared__ int ok_s;
   const int tid = threadIdx.x;
@@ -472,19 +480,72 @@ __global__ __launch_bounds__(kBT) void saccept_big_kernel(int nH, int k, int nev
   }
   __syncthreads();
   for (int j = tid; j < k; j += kBT) lam[j] = srt[j];
-  if (!ok_s) {
-    if (tid == 0) {
-      status[0] = 0;
-      status[1] = 0;
-    }
-    return;
+  if (tid == 0) {
+    status[0] = ok_s;           // provisional: 1 = checks passed, the counts decide
+    status[1] = 0;
+    mus[0] = srt[k - 1] + gap;
+    mus[1] = srt[(nev < k ? nev : k) - 1] + gap;
   }
-  bool trusted = false;
-  int count = inertia_big(nH, k, theta, Gt, Hm, srt[k - 1] + gap, L, &trusted);
-  int verdict = (trusted && count == k) ? 1 : 0;
-  if (!verdict && nev < k) {
-    count = inertia_big(nH, k, theta, Gt, Hm, srt[nev - 1] + gap, L, &trusted);
-    verdict = (trusted && count == nev) ? 2 : 0;
+}
+
+__global__ __launch_bounds__(kBT) void saccept_part_kernel(int nH, int k, int nev, int rows,
+                                                         const double* __restrict__ theta,
+                                                         const double* __restrict__ Gt,
+                                                         const double* __restrict__ mus,
+                                                         const int* __restrict__ status, double* __restrict__ part) {
+  const int sh = blockIdx.y;
+  if (status[0] == 0 || (sh == 1 && nev >= k)) return;
+  const int rb = blockIdx.x * rows;
+  const int re = (rb + rows < nH) ? rb + rows : nH;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int T = (k + 15) >> 4, TT = T * T;
+  double4_t acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  if (rb < re) schur_rows_acc(rb, re, k, Gt, theta, mus[sh], acc);
+  double* dst = part + ((size_t)sh * gridDim.x + blockIdx.x) * k * k;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int tt = wave + 8 * t;
+    if (tt < TT) {
+      const int ti = tt / T, tj = tt - (tt / T) * T;
+      const int c = 16 * tj + li;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ti + lk + 4 * q;
+        if (r < k && c < k) dst[(size_t)r * k + c] = acc[t][q];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBT) void saccept_final_kernel(int nH, int k, int nev, int nchunk,
+                                                          const double* __restrict__ theta,
+                                                          const double* __restrict__ Hm,
+                                                          const double* __restrict__ mus,
+                                                          const double* __restrict__ part,
+                                                          int* __restrict__ status) {
+  __shared__ BLds L;
+  if (status[0] == 0) return;
+  const int tid = threadIdx.x;
+  int verdict = 0, count = 0;
+  for (int sh = 0; sh < 2 && verdict == 0; ++sh) {
+    if (sh == 1 && nev >= k) break;
+    const double mu = mus[sh];
+    const double* ps = part + (size_t)sh * nchunk * k * k;
+    for (int e = tid; e < k * k; e += kBT) {
+      const int r = e / k, c = e - (e / k) * k;
+      double a = 0.0;
+      for (int ch = 0; ch < nchunk; ++ch) a += ps[(size_t)ch * k * k + e];
+      L.S[r][c] = Hm[(size_t)r * k + c] - ((r == c) ? mu : 0.0) - a;
+    }
+    __syncthreads();
+    bool trusted = false;
+    count = inertia_count(nH, k, theta, mu, L, &trusted);
+    if (sh == 0) verdict = (trusted && count == k) ? 1 : 0;
+    else verdict = (trusted && count == nev) ? 2 : 0;
+    __syncthreads();
   }
   if (tid == 0) {
     status[0] = verdict;
@@ -492,11 +553,21 @@ __global__ __launch_bounds__(kBT) void saccept_big_kernel(int nH, int k, int nev
   }
 }
 
+// row chunks of the acceptance's Schur sums: at most 32, and at most what the scratch holds
+int accept_chunk_rows(int nH, int k) {
+  int nchunk = (nH + k) / k;
+  if (nchunk > 32) nchunk = 32;
+  if (nchunk < 1) nchunk = 1;
+  int rows = (nH + nchunk - 1) / nchunk;
+  rows = (rows + 3) & ~3;
+  return rows;
+}
+
 }  // namespace
 
 int small_big_max_k() { return kBK; }
 int small_big_max_nh() { return kBigMaxH; }
-size_t small_big_scratch_doubles(int nH, int k) { return (size_t)2 * (nH + k) * k; }
+size_t small_big_scratch_doubles(int nH, int k) { return (size_t)2 * (nH + k) * k + 16; }
 
 void launch_small_rqi_big(int nH, int k, const double* theta, const double* Gt, const double* Hm,
                           const double* sigma, const double* X0, double scale, const double* tolv, double* Vt,
@@ -511,8 +582,15 @@ void launch_small_rr_big(int nH, int k, const double* theta, const double* Gt, c
 
 void launch_small_accept_big(int nH, int k, int nev, const double* theta, const double* Gt, const double* Hm,
                              const double* rq, const double* res, double tol_abs, const double* tolv, double gap,
-                             double* lam, int* perm, int* status, hipStream_t s) {
-  saccept_big_kernel<<<1, kBT, 0, s>>>(nH, k, nev, theta, Gt, Hm, rq, res, tol_abs, tolv, gap, lam, perm, status);
+                             double* lam, int* perm, int* status, double* scratch, hipStream_t s) {
+  // scratch (the solver's per-pair work vectors, free again here): the partial sums, then the shifts
+  const int rows = accept_chunk_rows(nH, k);
+  const int nchunk = (nH + rows - 1) / rows;
+  double* part = scratch;
+  double* mus = scratch + (size_t)2 * nchunk * k * k;
+  saccept_pre_kernel<<<1, kBT, 0, s>>>(k, nev, rq, res, tol_abs, tolv, gap, lam, perm, mus, status);
+  saccept_part_kernel<<<dim3((unsigned)nchunk, 2), kBT, 0, s>>>(nH, k, nev, rows, theta, Gt, mus, status, part);
+  saccept_final_kernel<<<1, kBT, 0, s>>>(nH, k, nev, nchunk, theta, Hm, mus, part, status);
 }
 
 }  // namespace pase
