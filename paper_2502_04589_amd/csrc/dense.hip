@@ -799,15 +799,24 @@ __global__ __launch_bounds__(kDenseThreads) void cholinv_kernel(int k, double* _
   __syncthreads();
   for (int c = tid; c < k; c += kDenseThreads) dinv[c] = 1.0 / L[c][c];
   __syncthreads();
-  // inverse: thread c owns column c of L^{-1}; entry (i, c), i > c, lives at L[c][i]
-  for (int c = tid; c < k; c += kDenseThreads) {
-    const double dc = dinv[c];
-    for (int i = c + 1; i < k; ++i) {
-      double acc = L[i][c] * dc;
-      for (int l = c + 1; l < i; ++l) acc = fma(L[i][l], L[c][l], acc);
-      L[c][i] = -acc * dinv[i];
+  // inverse X = L^{-1}, right-looking: entry (i, c), i > c, lives at L[c][i] (zero on entry) and
+  // accumulates sum_{l < j} L[i][l] X[l][c] until step j = i, when X[i][c] = -acc dinv[i]; at step
+  // j every pair (i > j, c <= j) adds L[i][j] X[j][c], with row j's values formed on the fly (row
+  // j - 1 is scaled in the same step: nothing reads it any more), one barrier per step
+  for (int j = 0; j < k; ++j) {
+    if (j > 0)
+      for (int c = tid; c < j - 1; c += kDenseThreads) L[c][j - 1] = -L[c][j - 1] * dinv[j - 1];
+    const double dj = dinv[j];
+    for (int i = j + 1 + ty; i < k; i += 32) {
+      const double lij = L[i][j];
+      for (int c = tx; c <= j; c += 32) {
+        const double xjc = (c == j) ? dj : -L[c][j] * dj;
+        L[c][i] = fma(lij, xjc, L[c][i]);
+      }
     }
+    __syncthreads();
   }
+  for (int c = tid; c < k - 1; c += kDenseThreads) L[c][k - 1] = -L[c][k - 1] * dinv[k - 1];
   __syncthreads();
   for (int q = tid; q < k * k; q += kDenseThreads) {
     const int i = q / k, c = q % k;
