@@ -151,12 +151,12 @@ __global__ void fill_int_kernel(int n, int v, int* p) {
 template <typename T>
 __global__ void axpy2_kernel(long long N, int k, const double* __restrict__ alpha, const T* __restrict__ P,
                              const T* __restrict__ Q, const T* Xin, T* X, T* __restrict__ R) {
-  // X = Xin + alpha P (Xin may be X), R -= alpha Q
+  // X = Xin + alpha P (Xin may be X), R -= alpha Q (R null: the x update only)
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * k) return;
   const double a = alpha[i % k];
   X[i] = (T)fma(a, (double)P[i], (double)Xin[i]);
-  R[i] = (T)fma(-a, (double)Q[i], (double)R[i]);
+  if (R) R[i] = (T)fma(-a, (double)Q[i], (double)R[i]);
 }
 
 template <typename T>

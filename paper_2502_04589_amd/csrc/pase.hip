@@ -691,7 +691,8 @@ void coldot(pase_handle* h, long long N, int k, const double* x, const double* y
 }
 
 // s PCG steps per column on A x = b from x0 (X0, not modified) into X, with residual
-// R = b - A x0 given.  p_0 = z_0 by exchanging the Z and P buffers, and the first update reads
+// R = b - A x0 given (overwritten; it is left at the residual of step s - 1, the last step
+// updating x only).  p_0 = z_0 by exchanging the Z and P buffers, and the first update reads
 // x0 from X0, so neither start needs a copy.
 void pcg(pase_handle* h, int k, const double* X0, double* X, double* R) {
   hipStream_t s = h->stream;
@@ -701,8 +702,10 @@ void pcg(pase_handle* h, int k, const double* X0, double* X, double* R) {
   for (int j = 0; j < h->opt.cg_steps; ++j) {
     apply_dot(h, k, h->P, h->Q, h->pq, 0);
     launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
-    if (j == 0 && X0 != X) launch_axpy2_from(N, k, h->alpha, h->P, h->Q, X0, X, R, s);
-    else launch_axpy2(N, k, h->alpha, h->P, h->Q, X, R, s);
+    // the last step's residual is not needed (R is scratch to the callers): x update only
+    double* Rj = (j + 1 < h->opt.cg_steps) ? R : nullptr;
+    if (j == 0 && X0 != X) launch_axpy2_from(N, k, h->alpha, h->P, h->Q, X0, X, Rj, s);
+    else launch_axpy2(N, k, h->alpha, h->P, h->Q, X, Rj, s);
     if (j + 1 < h->opt.cg_steps) {
       vcycle(h, 0, k, R, h->Z, h->rho2);
       launch_pcg_beta(k, h->rho2, h->rho, h->beta, s);
@@ -727,7 +730,7 @@ void pcg_correction_f32(pase_handle* h, int k, const double* U, const double* R,
   for (int j = 0; j < h->opt.cg_steps; ++j) {
     apply_dot(h, k, h->P32, h->Q32, h->pq, 1);
     launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
-    launch_axpy2_f32(N, k, h->alpha, h->P32, h->Q32, h->E32, r, s);
+    launch_axpy2_f32(N, k, h->alpha, h->P32, h->Q32, h->E32, (j + 1 < h->opt.cg_steps) ? r : nullptr, s);
     if (j + 1 < h->opt.cg_steps) {
       vcycle(h, B, 0, k, r, h->Z32, h->rho2);
       launch_pcg_beta(k, h->rho2, h->rho, h->beta, s);
