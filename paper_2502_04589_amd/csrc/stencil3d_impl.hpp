@@ -26,6 +26,11 @@ namespace pase {
 namespace {
 
 
+// Write-only target of the stores of lanes that have no output (nodes past the grid, columns past
+// k, the step past the end of an odd z-run): every lane then issues the same memory operations,
+// and no branch around a store leaves the compiler unsure which loads are still in flight.
+__device__ double4 fine3_sink[1];
+
 __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   const int per = nblocks >> 3;
   return (b & 7) * per + (b >> 3);
@@ -162,11 +167,31 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
       return v;
     }
   };
-  V* xsflat[kSlots];
-#pragma unroll
-  for (int sl = 0; sl < kSlots; ++sl) xsflat[sl] = &sm.xs[sl][0][0][0];
+  // the ring is indexed from the shared array itself (not through a table of pointers), so the
+  // stash is an LDS store, not a generic store that would also wait on the global loads in flight
+  constexpr int kPlaneV = (BY + 2) * (BX + 2) * NQ;
   auto st1 = [&](int slot, int u, const V& v) {
-    if (hslot[u] >= 0) xsflat[slot][hslot[u]] = v;
+    if (hslot[u] >= 0) (&sm.xs[0][0][0][0])[slot * kPlaneV + hslot[u]] = v;
+  };
+  // kappa form: the tile's (BX+1) x (BY+1) cells of a layer are staged in an LDS ring beside the
+  // planes (layer L in the slot of plane L), one cell per thread, loaded a step ahead with the
+  // plane, so no step waits on a load that it issued itself
+  constexpr bool kKapL = !CONSTK && !ASM;
+  constexpr int kCells = (BX + 1) * (BY + 1);
+  static_assert(kCells <= kThreadsV, "one cell per thread");
+  __shared__ double ksm[kKapL ? kSlots * kCells : 1];
+  auto kld = [&](int L) -> double {
+    if constexpr (kKapL) {
+      const int ex = tx0 + tid % (BX + 1), ey = ty0 + tid / (BX + 1);
+      const bool ok = tid < kCells && ex < n && ey < n && L >= 0 && L < n;
+      const double* p = ok ? a.kappa + ((long long)L * n + ey) * n + ex : (const double*)a.zero;
+      return *p;
+    } else {
+      return 0.0;
+    }
+  };
+  auto kst = [&](int slot, double v) {
+    if (kKapL && tid < kCells) ksm[slot * kCells + tid] = v;
   };
   // EPI_SWEEP2V: the staged planes hold x1 = omega D^{-1} b; the diagonal is loaded with the plane
   // (kept in flight beside it) and applied when the plane is stashed
@@ -212,17 +237,14 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
       return v;
     }
   };
-  auto stvec = [&](T* base, long long off, const V& v) {
+  auto stvec = [&](T* base, long long off, const V& v, bool ok) {
     if constexpr (VEC) {
-      *(V*)(base + off) = v;
+      *(ok ? (V*)(base + off) : (V*)fine3_sink) = v;
     } else {
 #pragma unroll
       for (int i = 0; i < VW; ++i)
-        if (colv + i < k) base[off + i] = (T)vget<T, VW>(v, i);
+        *((ok && colv + i < k) ? base + off + i : (T*)fine3_sink) = (T)vget<T, VW>(v, i);
     }
-  };
-  auto kap = [&](int ex, int ey, int ez) -> double {
-    return (ex < n && ey < n && ez >= 0 && ez < n) ? a.kappa[((long long)ez * n + ey) * n + ex] : 0.0;
   };
   const double h = a.h;
   const double k0 = 1.0 / h, k1 = -1.0 / h, m0 = 2.0 * h / 6.0, m1 = h / 6.0;
@@ -232,7 +254,8 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   constexpr bool needM = (EPI == EPI_EIGRES) || (EPI == EPI_AM) || (EPI == EPI_M);
 
   double kc[2][2][2];
-  // prologue: planes z0-1, z0, z0+1 into slots 0, 1, 2; b(z0) then plane z0+2 in flight
+  // prologue: planes z0-1, z0, z0+1 into slots 0, 1, 2 (kappa layers z0, z0+1 into slots 1, 2);
+  // b(z0) then plane z0+2 (and kappa layer z0+2) in flight
   {
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -247,13 +270,19 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   V pB0 = pA0, pB1 = pA1;
   double dA[2] = {ldd(z0 + 2, 0), ldd(z0 + 2, 1)};
   double dB[2] = {dA[0], dA[1]};
-  if (!CONSTK && !ASM) {
+  if (kKapL) {
+    const double l0 = kld(z0), l1 = kld(z0 + 1);
+    kst(1, l0);
+    kst(2, l1);
+  }
+  double kA = kld(z0 + 2), kB = kA;
+  __syncthreads();
+  if (kKapL) {
 #pragma unroll
     for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-      for (int cx = 0; cx < 2; ++cx) kc[1][cy][cx] = kap(gx + cx, gy + cy, z0);
+      for (int cx = 0; cx < 2; ++cx) kc[1][cy][cx] = ksm[1 * kCells + (ly + cy) * (BX + 1) + lx + cx];
   }
-  __syncthreads();
   double acc0[VW], acc1[VW], acc2[VW];
 #pragma unroll
   for (int i = 0; i < VW; ++i) acc0[i] = acc1[i] = acc2[i] = 0.0;
@@ -264,7 +293,7 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   // Output plane z: planes z-1, z, z+1 sit in slots sb, sb+1, sb+2 (mod 4) with sb = (z - z0) & 3;
   // PS0/PS1 hold plane z+2 (in flight since the previous step) and are stashed into slot sb+3;
   // PL0/PL1 receive plane z+3; BV is b(z) and BN receives b(z+1).
-#define PASE_STEP(z, PL0, PL1, PS0, PS1, BV, BN, DL, DS)                                               \
+#define PASE_STEP(z, PL0, PL1, PS0, PS1, BV, BN, DL, DS, KL, KS)                                       \
   {                                                                                                     \
     const int sb = ((z) - z0) & 3;                                                                      \
     if (EPI == EPI_RESID || kSweep) BN = bload((z) + 1);                                                \
@@ -274,15 +303,17 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
       DL[0] = ldd((z) + 3, 0);                                                                          \
       DL[1] = ldd((z) + 3, 1);                                                                          \
     }                                                                                                   \
-    if (!CONSTK && !ASM) {                                                                              \
+    if (kKapL) {                                                                                        \
+      KL = kld((z) + 3);                                                                                \
       _Pragma("unroll") for (int cy = 0; cy < 2; ++cy) _Pragma("unroll") for (int cx = 0; cx < 2; ++cx) { \
         kc[0][cy][cx] = kc[1][cy][cx];                                                                  \
-        kc[1][cy][cx] = kap(gx + cx, gy + cy, (z) + 1);                                                 \
+        kc[1][cy][cx] = ksm[((sb + 2) & 3) * kCells + (ly + cy) * (BX + 1) + lx + cx];                  \
       }                                                                                                 \
     }                                                                                                   \
-    if (nodeok && colv < k) compute_plane((z), sb, BV);                                                 \
+    compute_plane((z), sb, BV, nodeok && colv < k && (z) < z1);                                         \
     st1s((sb + 3) & 3, 0, PS0, DS[0]);                                                                  \
     st1s((sb + 3) & 3, 1, PS1, DS[1]);                                                                  \
+    kst((sb + 3) & 3, KS);                                                                              \
     __syncthreads();                                                                                    \
   }
   // Constant coefficient (residual, sweep and eigen-residual epilogues): reuse along z.  A plane
@@ -337,7 +368,9 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     PASE_TAP9(-1, 1)  PASE_TAP9(0, 1)  PASE_TAP9(1, 1)
 #undef PASE_TAP9
   };
-  auto compute_plane = [&](int z, int sb, const V& bv) {
+  // every lane computes (its LDS reads stay inside the tile and its halo); ok says whether the
+  // lane owns an output: the others store to the sink and add nothing to the column sums
+  auto compute_plane = [&](int z, int sb, const V& bv, bool ok) {
     double ax[VW], mx[VW], center[VW];
 #pragma unroll
     for (int i = 0; i < VW; ++i) ax[i] = mx[i] = center[i] = 0.0;
@@ -345,7 +378,8 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     double cf[ASM ? 27 : 1];
     if constexpr (ASM) {
       if (needA) {
-        const double* __restrict__ cp = a.coef + (((long long)z * m + gy) * m + gx) * 27;
+        const long long row = ok ? ((long long)z * m + gy) * m + gx : 0;
+        const double* __restrict__ cp = a.coef + row * 27;
 #pragma unroll
         for (int o = 0; o < 27; ++o) cf[o] = cp[o];
       }
@@ -405,60 +439,67 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     if (EPI == EPI_AM) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) { vset<T, VW>(o1, i, ax[i]); vset<T, VW>(o2, i, mx[i]); }
-      stvec((T*)a.out1, off, o1);
-      stvec((T*)a.out2, off, o2);
+      stvec((T*)a.out1, off, o1, ok);
+      stvec((T*)a.out2, off, o2, ok);
     } else if (EPI == EPI_A) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, ax[i]);
-      stvec((T*)a.out1, off, o1);
+      stvec((T*)a.out1, off, o1, ok);
     } else if (EPI == EPI_M) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o2, i, mx[i]);
-      stvec((T*)a.out2, off, o2);
+      stvec((T*)a.out2, off, o2, ok);
     } else if (EPI == EPI_RESID) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, vget<T, VW>(bv, i) - ax[i]);
-      stvec((T*)a.out1, off, o1);
+      stvec((T*)a.out1, off, o1, ok);
     } else if (EPI == EPI_SWEEP2) {
       // the staged planes hold b: x1 = c b, A x1 = c (A b), out = x1 + c (b - A x1)
       const double c = a.omega / dcoef;
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, c * center[i] + c * (center[i] - c * ax[i]));
-      stvec((T*)a.out1, off, o1);
+      stvec((T*)a.out1, off, o1, ok);
     } else if (kSweep) {
       const double wd = a.omega / dcoef;
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, center[i] + wd * (vget<T, VW>(bv, i) - ax[i]));
-      stvec((T*)a.out1, off, o1);
-      if (EPI == EPI_SWEEPDOT) {
+      stvec((T*)a.out1, off, o1, ok);
+      if (EPI == EPI_SWEEPDOT && ok) {
 #pragma unroll
         for (int i = 0; i < VW; ++i) acc0[i] = fma(vget<T, VW>(bv, i), vget<T, VW>(o1, i), acc0[i]);
       }
     } else if (EPI == EPI_AMDOT) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, ax[i]);
-      stvec((T*)a.out1, off, o1);
+      stvec((T*)a.out1, off, o1, ok);
+      if (ok) {
 #pragma unroll
-      for (int i = 0; i < VW; ++i) acc0[i] = fma(center[i], vget<T, VW>(o1, i), acc0[i]);
+        for (int i = 0; i < VW; ++i) acc0[i] = fma(center[i], vget<T, VW>(o1, i), acc0[i]);
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < VW; ++i) {
         const double r = lamc[i] * mx[i] - ax[i];
         vset<T, VW>(o1, i, r);
-        acc0[i] = fma(r, r, acc0[i]);
-        acc1[i] = fma(mx[i], mx[i], acc1[i]);
-        acc2[i] = fma(center[i], mx[i], acc2[i]);
+        if (ok) {
+          acc0[i] = fma(r, r, acc0[i]);
+          acc1[i] = fma(mx[i], mx[i], acc1[i]);
+          acc2[i] = fma(center[i], mx[i], acc2[i]);
+        }
       }
-      stvec((T*)a.out1, off, o1);
+      stvec((T*)a.out1, off, o1, ok);
     }
   };
   if (CONSTK && EPI != EPI_AM && nodeok && colv < k) {
     plane9(0, 0);       // plane z0 - 1
     plane9(1, 1);       // plane z0
   }
+  // two steps per trip, the in-flight registers alternating; the second step of the last trip of
+  // an odd run lies past z1 and only loads, and stores to the sink, so every trip is the same code
+  // and the waits for the loads in flight stay exact
   for (int z = z0; z < z1; z += 2) {
-    PASE_STEP(z, pB0, pB1, pA0, pA1, bA, bB, dB, dA)
-    if (z + 1 < z1) PASE_STEP(z + 1, pA0, pA1, pB0, pB1, bB, bA, dA, dB)
+    PASE_STEP(z, pB0, pB1, pA0, pA1, bA, bB, dB, dA, kB, kA)
+    PASE_STEP(z + 1, pA0, pA1, pB0, pB1, bB, bA, dA, dB, kA, kB)
   }
 #undef PASE_STEP
   if (kSums1) {
