@@ -117,7 +117,7 @@ struct Fine3Args {
   const double* dinv;    // EPI_SWEEP2V: 1 / diag(A) per node
 };
 void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s);
-int fine3_spatial_blocks(int m, int nzc);
+int fine3_spatial_blocks(int m, int nzc, int k, bool fp32);
 int fine3_default_nzc(int m);
 int fine3_max_spatial_blocks(int m);
 

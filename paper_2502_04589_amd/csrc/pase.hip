@@ -561,9 +561,9 @@ void xfer_prolong(pase_handle* h, int l, int k, const void* xc, void* xf, int mo
   launch_prolong(h->dim, h->lev[l - 1].m, h->lev[l].m, k, xc, xf, mode, fp32, h->stream);
 }
 
-int eigres_tiles(pase_handle* h, int k) {
+int eigres_tiles(pase_handle* h, int k, bool fp32 = false) {
   if (h->alg) return csr_tiles(h->lev[0].N);
-  if (h->dim == 3) return fine3_spatial_blocks(h->lev[0].m, fine3_default_nzc(h->lev[0].m));
+  if (h->dim == 3) return fine3_spatial_blocks(h->lev[0].m, fine3_default_nzc(h->lev[0].m), k, fp32);
   return grid_launch(h->lev[0].N, k).tiles;
 }
 
@@ -642,7 +642,7 @@ void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x
     std::swap(cur, oth);
   }
   if (fuse) {
-    launch_reduce_partials(eigres_tiles(h, k), k, h->partial, dot, s);
+    launch_reduce_partials(eigres_tiles(h, k, B.fp32), k, h->partial, dot, s);
   } else if (dot) {
     if (B.fp32) launch_coldot_f32(lv.N, k, (const float*)b, (const float*)x, h->partial, dot, s);
     else launch_coldot(lv.N, k, (const double*)b, (const double*)x, h->partial, 0, dot, s);
@@ -658,7 +658,7 @@ void apply_dot(pase_handle* h, int k, const void* P, void* Q, double* pq, int fp
   const long long N = h->lev[0].N;
   if (h->dim == 3) {
     stencil_op(h, 0, k, EPI_AMDOT, P, nullptr, Q, nullptr, fp32);
-    launch_reduce_partials(eigres_tiles(h, k), k, h->partial, pq, h->stream);
+    launch_reduce_partials(eigres_tiles(h, k, fp32), k, h->partial, pq, h->stream);
     return;
   }
   stencil_op(h, 0, k, EPI_AM, P, nullptr, Q, nullptr, fp32);

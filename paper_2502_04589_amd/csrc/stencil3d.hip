@@ -6,14 +6,17 @@ namespace pase {
 
 void launch_fine3_f32(const Fine3Args& a, Epi epi, hipStream_t s);
 
-int fine3_spatial_blocks(int m, int nzc) {
-  // the EIGRES partial rows are per (x-tile, y-tile, z-run); column chunks share a row
-  return ((m + 7) / 8) * ((m + 7) / 8) * nzc;
+int fine3_spatial_blocks(int m, int nzc, int k, bool fp32) {
+  // the column-sum partial rows are per (x-tile, y-tile, z-run); column chunks share a row.  Tiles
+  // are 8 x 4 nodes when k is a multiple of 8 vectors (2 doubles, or 4 floats when k % 4 == 0),
+  // else 8 x 8 (the rule of launchv_tile)
+  const int by = (k % (fp32 ? 32 : 16) == 0) ? 4 : 8;
+  return ((m + 7) / 8) * ((m + by - 1) / by) * nzc;
 }
 
 int fine3_max_spatial_blocks(int m) {
-  // bound over every z-run length (8 x 8 tiles, runs of at least 4 planes)
-  return ((m + 7) / 8) * ((m + 7) / 8) * ((m + 3) / 4);
+  // bound over every tile and z-run length (8 x 4 tiles, runs of at least 4 planes)
+  return ((m + 7) / 8) * ((m + 3) / 4) * ((m + 3) / 4);
 }
 
 int fine3_default_nzc(int m) {

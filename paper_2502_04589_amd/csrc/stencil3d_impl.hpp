@@ -36,21 +36,16 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Sum of kappa over the cells shared by a node and its neighbour at offset o:
-// for each axis with o = -1 only the lower cell, o = +1 only the upper cell,
-// o = 0 both.  kc[cz][cy][cx] are the 8 cells around the node.
-template <int OX, int OY, int OZ>
-__device__ __forceinline__ double shared_kappa(const double (&kc)[2][2][2]) {
-  double s = 0.0;
-#pragma unroll
-  for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-      for (int cx = 0; cx < 2; ++cx)
-        if ((OX == 0 || cx == (OX > 0)) && (OY == 0 || cy == (OY > 0)) && (OZ == 0 || cz == (OZ > 0)))
-          s += kc[cz][cy][cx];
-  return s;
+// Sum of kappa over the cells of one layer that a node shares with its neighbour at (ox, oy):
+// along an axis with offset -1 only the lower cell, +1 only the upper cell, 0 both.  c[cy][cx] are
+// the node's 4 cells in that layer.
+template <int OX, int OY>
+__device__ __forceinline__ double cell_sum(const double (&c)[2][2]) {
+  constexpr int x0 = (OX > 0) ? 1 : 0, y0 = (OY > 0) ? 1 : 0;
+  if constexpr (OX != 0 && OY != 0) return c[y0][x0];
+  else if constexpr (OX != 0) return c[0][x0] + c[1][x0];
+  else if constexpr (OY != 0) return c[y0][0] + c[y0][1];
+  else return (c[0][0] + c[0][1]) + (c[1][0] + c[1][1]);
 }
 
 template <int OX, int OY, int OZ>
@@ -253,9 +248,8 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   constexpr bool needA = (EPI != EPI_M);
   constexpr bool needM = (EPI == EPI_EIGRES) || (EPI == EPI_AM) || (EPI == EPI_M);
 
-  double kc[2][2][2];
-  // prologue: planes z0-1, z0, z0+1 into slots 0, 1, 2 (kappa layers z0, z0+1 into slots 1, 2);
-  // b(z0) then plane z0+2 (and kappa layer z0+2) in flight
+  // prologue: planes z0-1, z0, z0+1 into slots 0, 1, 2 (kappa layers z0, z0+1, z0+2 into slots
+  // 1, 2, 3); b(z0), plane z0+2 and kappa layer z0+3 in flight
   {
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -271,18 +265,21 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   double dA[2] = {ldd(z0 + 2, 0), ldd(z0 + 2, 1)};
   double dB[2] = {dA[0], dA[1]};
   if (kKapL) {
-    const double l0 = kld(z0), l1 = kld(z0 + 1);
+    const double l0 = kld(z0), l1 = kld(z0 + 1), l2 = kld(z0 + 2);
     kst(1, l0);
     kst(2, l1);
+    kst(3, l2);
   }
-  double kA = kld(z0 + 2), kB = kA;
+  double kA = kld(z0 + 3), kB = kA;
   __syncthreads();
-  if (kKapL) {
+  // kappa form: the node's cells in layers p (kl) and p+1 (ku) of the plane p being added
+  double kl[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, ku[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  auto kread = [&](int slot, double (&c)[2][2]) {
 #pragma unroll
     for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-      for (int cx = 0; cx < 2; ++cx) kc[1][cy][cx] = ksm[1 * kCells + (ly + cy) * (BX + 1) + lx + cx];
-  }
+      for (int cx = 0; cx < 2; ++cx) c[cy][cx] = ksm[slot * kCells + (ly + cy) * (BX + 1) + lx + cx];
+  };
   double acc0[VW], acc1[VW], acc2[VW];
 #pragma unroll
   for (int i = 0; i < VW; ++i) acc0[i] = acc1[i] = acc2[i] = 0.0;
@@ -292,7 +289,9 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
 
   // Output plane z: planes z-1, z, z+1 sit in slots sb, sb+1, sb+2 (mod 4) with sb = (z - z0) & 3;
   // PS0/PS1 hold plane z+2 (in flight since the previous step) and are stashed into slot sb+3;
-  // PL0/PL1 receive plane z+3; BV is b(z) and BN receives b(z+1).
+  // PL0/PL1 receive plane z+3; BV is b(z) and BN receives b(z+1).  kappa runs a step further
+  // ahead (layer L in the slot of plane L): layer z+2 is read, KS (layer z+3) stashed into slot
+  // sb, KL receives layer z+4.
 #define PASE_STEP(z, PL0, PL1, PS0, PS1, BV, BN, DL, DS, KL, KS)                                       \
   {                                                                                                     \
     const int sb = ((z) - z0) & 3;                                                                      \
@@ -304,16 +303,15 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
       DL[1] = ldd((z) + 3, 1);                                                                          \
     }                                                                                                   \
     if (kKapL) {                                                                                        \
-      KL = kld((z) + 3);                                                                                \
-      _Pragma("unroll") for (int cy = 0; cy < 2; ++cy) _Pragma("unroll") for (int cx = 0; cx < 2; ++cx) { \
-        kc[0][cy][cx] = kc[1][cy][cx];                                                                  \
-        kc[1][cy][cx] = ksm[((sb + 2) & 3) * kCells + (ly + cy) * (BX + 1) + lx + cx];                  \
-      }                                                                                                 \
+      KL = kld((z) + 4);                                                                                \
+      _Pragma("unroll") for (int cy = 0; cy < 2; ++cy) _Pragma("unroll") for (int cx = 0; cx < 2; ++cx) \
+        kl[cy][cx] = ku[cy][cx];                                                                        \
+      kread((sb + 3) & 3, ku);                                                                          \
     }                                                                                                   \
     compute_plane((z), sb, BV, nodeok && colv < k && (z) < z1);                                         \
     st1s((sb + 3) & 3, 0, PS0, DS[0]);                                                                  \
     st1s((sb + 3) & 3, 1, PS1, DS[1]);                                                                  \
-    kst((sb + 3) & 3, KS);                                                                              \
+    kst(sb, KS);                                                                                        \
     __syncthreads();                                                                                    \
   }
   // Constant coefficient (residual, sweep and eigen-residual epilogues): reuse along z.  A plane
@@ -368,6 +366,68 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     PASE_TAP9(-1, 1)  PASE_TAP9(0, 1)  PASE_TAP9(1, 1)
 #undef PASE_TAP9
   };
+  // kappa form, the same running sums.  The Q1 stiffness of a cube of side h couples a node with
+  // itself by h/3, with a neighbour across a face by 0, across an edge or a corner by -h/12 (times
+  // the kappa of the cells they share), so A x = (h/3) K8 x_i - (h/12) sum_j S_ij x_j over the 20
+  // edge and corner neighbours, with K8 the node's 8 cells and S_ij the kappa of the cells shared
+  // with j; ra holds the sums of S_ij x_j, rm the M sums in units of (h/6)^3, dco the K8 of the
+  // outputs z and z+1.  A tap (ox, oy) of plane p meets output p-1 in its upper layer (p, kl),
+  // output p in both, output p+1 in its lower layer (p+1, ku); in plane p only the 4 corner taps
+  // are edge neighbours of output p.  M: the plane's 9 taps weighted (4 or 1 per axis) once, then
+  // 1, 4, 1 for the outputs p-1, p, p+1.
+  double dco[2] = {0.0, 0.0};
+  auto plane9k = [&](int slot, int mode) {
+    double pm[VW];
+#pragma unroll
+    for (int i = 0; i < VW; ++i) pm[i] = 0.0;
+#define PASE_TAPK(OX, OY)                                                                            \
+  {                                                                                                  \
+    const V v = sm.xs[slot][ly + 1 + (OY)][lx + 1 + (OX)][qv];                                       \
+    constexpr bool kCen = (OX) == 0 && (OY) == 0;                                                    \
+    constexpr bool kCorner = (OX) != 0 && (OY) != 0;                                                 \
+    constexpr double mxy = (double)(((OX) == 0 ? 4 : 1) * ((OY) == 0 ? 4 : 1));                      \
+    const double su = cell_sum<OX, OY>(ku);                                                          \
+    const double sl = (mode == 0) ? 0.0 : cell_sum<OX, OY>(kl);                                      \
+    const double slu = sl + su;                                                                      \
+    _Pragma("unroll") for (int i = 0; i < VW; ++i) {                                                 \
+      const double xv = vget<T, VW>(v, i);                                                           \
+      if (needM) pm[i] = fma(mxy, xv, pm[i]);                                                        \
+      if constexpr (kCen) {                                                                          \
+        if (mode == 1) cen[0][i] = xv;                                                               \
+        else if (mode == 2) cen[1][i] = xv;                                                          \
+      } else if (mode == 0) {                                                                        \
+        ra[0][i] = fma(su, xv, ra[0][i]);                                                            \
+      } else if (mode == 1) {                                                                        \
+        if (kCorner) ra[0][i] = fma(slu, xv, ra[0][i]);                                              \
+        ra[1][i] = fma(su, xv, ra[1][i]);                                                            \
+      } else {                                                                                       \
+        ra[0][i] = fma(sl, xv, ra[0][i]);                                                            \
+        if (kCorner) ra[1][i] = fma(slu, xv, ra[1][i]);                                              \
+        ra[2][i] = fma(su, xv, ra[2][i]);                                                            \
+      }                                                                                              \
+    }                                                                                                \
+  }
+    PASE_TAPK(-1, -1) PASE_TAPK(0, -1) PASE_TAPK(1, -1)
+    PASE_TAPK(-1, 0)  PASE_TAPK(0, 0)  PASE_TAPK(1, 0)
+    PASE_TAPK(-1, 1)  PASE_TAPK(0, 1)  PASE_TAPK(1, 1)
+#undef PASE_TAPK
+    if (needM) {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        if (mode == 0) {
+          rm[0][i] += pm[i];
+        } else if (mode == 1) {
+          rm[0][i] = fma(4.0, pm[i], rm[0][i]);
+          rm[1][i] += pm[i];
+        } else {
+          rm[0][i] += pm[i];
+          rm[1][i] = fma(4.0, pm[i], rm[1][i]);
+          rm[2][i] += pm[i];
+        }
+      }
+    }
+    if (mode >= 1) dco[mode - 1] = cell_sum<0, 0>(kl) + cell_sum<0, 0>(ku);
+  };
   // every lane computes (its LDS reads stay inside the tile and its halo); ok says whether the
   // lane owns an output: the others store to the sink and add nothing to the column sums
   auto compute_plane = [&](int z, int sb, const V& bv, bool ok) {
@@ -400,6 +460,24 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
         cen[0][i] = cen[1][i];
       }
       dcoef = kpat<0, 0, 0>(k0, k1, m0, m1) * 8.0;
+    } else if constexpr (kKapL) {
+      plane9k((sb + 2) & 3, 2);
+      const double hd = h / 3.0, ho = -h / 12.0;
+      dcoef = hd * dco[0];
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        ax[i] = fma(dcoef, cen[0][i], ho * ra[0][i]);
+        mx[i] = mc3 * rm[0][i];
+        center[i] = cen[0][i];
+        ra[0][i] = ra[1][i];
+        ra[1][i] = ra[2][i];
+        ra[2][i] = 0.0;
+        rm[0][i] = rm[1][i];
+        rm[1][i] = rm[2][i];
+        rm[2][i] = 0.0;
+        cen[0][i] = cen[1][i];
+      }
+      dco[0] = dco[1];
     } else {
 #define PASE_TAP(OX, OY, OZ)                                                                       \
   {                                                                                                \
@@ -409,8 +487,7 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
       if constexpr (ASM) {                                                                         \
         coef = cf[((OX) + 1) + 3 * ((OY) + 1) + 9 * ((OZ) + 1)];                                   \
       } else {                                                                                     \
-        const double s = CONSTK ? (double)(((OX) == 0 ? 2 : 1) * ((OY) == 0 ? 2 : 1) * ((OZ) == 0 ? 2 : 1)) \
-                                : shared_kappa<OX, OY, OZ>(kc);                                    \
+        const double s = (double)(((OX) == 0 ? 2 : 1) * ((OY) == 0 ? 2 : 1) * ((OZ) == 0 ? 2 : 1)); \
         coef = kpat<OX, OY, OZ>(k0, k1, m0, m1) * s;                                               \
       }                                                                                            \
       if ((OX) == 0 && (OY) == 0 && (OZ) == 0) dcoef = coef;                                       \
@@ -494,6 +571,16 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
     plane9(0, 0);       // plane z0 - 1
     plane9(1, 1);       // plane z0
   }
+  if (kKapL) {
+    kread(1, ku);       // layer z0
+    plane9k(0, 0);      // plane z0 - 1
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) kl[cy][cx] = ku[cy][cx];
+    kread(2, ku);       // layer z0 + 1
+    plane9k(1, 1);      // plane z0
+  }
   // two steps per trip, the in-flight registers alternating; the second step of the last trip of
   // an odd run lies past z1 and only loads, and stores to the sink, so every trip is the same code
   // and the waits for the loads in flight stay exact
@@ -546,16 +633,24 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
 
 template <typename T, int VW, int EPI, bool CONSTK, bool VEC, bool ASM>
 void launchv_tile(const Fine3Args& a, hipStream_t s) {
-  auto go = [&](auto nq) {
-    constexpr int BX = 8, BY = 8, NQ = decltype(nq)::value;
+  auto go = [&](auto bq) {
+    constexpr int BX = 8, NQ = decltype(bq)::value, BY = (NQ == 8) ? 4 : 8;
     constexpr int KC = NQ * VW;
     const int ntx = (a.m + BX - 1) / BX, nty = (a.m + BY - 1) / BY, nch = (a.k + KC - 1) / KC;
     const int total = ntx * nty * a.nzc * nch;
     const int blocks = ((total + 7) / 8) * 8;
     fine3v_kernel<T, VW, EPI, CONSTK, VEC, BX, BY, NQ, ASM><<<blocks, BX * BY * NQ, 0, s>>>(a);
   };
-  // column chunks of 5 vectors when that wastes fewer padded columns than chunks of 4 (not for
-  // the A+M and eigen-residual epilogues, whose register use makes the larger block slower)
+  // 8 x 4 nodes with 8 threads per node when a block's columns are whole 128-byte lines of the
+  // node rows (k a multiple of 8 VW): its halo loads are then full lines, which measured 16 % faster
+  // than 8 x 8 nodes with 4 threads (half lines, the other half read by the next column chunk)
+  if (a.k % (8 * VW) == 0) {
+    go(std::integral_constant<int, 8>());
+    return;
+  }
+  // else 8 x 8 nodes, column chunks of 5 vectors when that wastes fewer padded columns than chunks
+  // of 4 (not for the A+M and eigen-residual epilogues, whose register use makes the larger block
+  // slower)
   const int w4 = ((a.k + 4 * VW - 1) / (4 * VW)) * 4 * VW - a.k;
   const int w5 = ((a.k + 5 * VW - 1) / (5 * VW)) * 5 * VW - a.k;
   if constexpr (EPI != EPI_AM && EPI != EPI_EIGRES) {
