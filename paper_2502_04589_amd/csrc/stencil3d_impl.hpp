@@ -214,7 +214,9 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   const long long cbase = ((long long)gy * m + gx) * k + colv;
   constexpr bool kSweep = (EPI == EPI_SWEEP || EPI == EPI_SWEEPDOT || EPI == EPI_SWEEP2V);
   constexpr bool kSums1 = (EPI == EPI_AMDOT || EPI == EPI_SWEEPDOT);   // one column sum
-  const bool bneed = (EPI == EPI_RESID || kSweep) && nodeok && colv < k;
+  // EPI_SWEEP2V needs no b: its staged x1 = omega D^{-1} b already holds it (see its epilogue)
+  constexpr bool kLoadB = (EPI == EPI_RESID || EPI == EPI_SWEEP || EPI == EPI_SWEEPDOT);
+  const bool bneed = kLoadB && nodeok && colv < k;
   auto bload = [&](int z) -> V {
     const bool ok = bneed && z < z1;
     const T* B = (const T*)a.b;
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
 #define PASE_STEP(z, PL0, PL1, PS0, PS1, BV, BN, DL, DS, KL, KS)                                       \
   {                                                                                                     \
     const int sb = ((z) - z0) & 3;                                                                      \
-    if (EPI == EPI_RESID || kSweep) BN = bload((z) + 1);                                                \
+    if (kLoadB) BN = bload((z) + 1);                                                                    \
     PL0 = ld1((z) + 3, 0);                                                                              \
     PL1 = ld1((z) + 3, 1);                                                                              \
     if (kFirst2) {                                                                                      \
@@ -535,6 +537,12 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
       const double c = a.omega / dcoef;
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, c * center[i] + c * (center[i] - c * ax[i]));
+      stvec((T*)a.out1, off, o1, ok);
+    } else if (EPI == EPI_SWEEP2V) {
+      // second sweep from x1 = omega D^{-1} b: x1 + omega D^{-1} (b - A x1) = 2 x1 - omega D^{-1} A x1
+      const double wd = a.omega / dcoef;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, fma(-wd, ax[i], 2.0 * center[i]));
       stvec((T*)a.out1, off, o1, ok);
     } else if (kSweep) {
       const double wd = a.omega / dcoef;
