@@ -222,17 +222,33 @@ __device__ void lu_solve_big(int k, const BLds& L, double& b0, double& b1) {
 }
 
 // out[a] = sum_{r < nH} c_r x_r Gt[r][a] (c_r = 1 / (theta_r - mu) when dmu is set, else 1), a < k,
-// into LDS; x is a global vector of the workgroup.
+// into LDS; x is a global vector of the workgroup.  With dmu, c_r x_r is formed once per row into
+// cx (nH doubles of the workgroup's global scratch, not x) instead of by every column's thread.
 __device__ void colsum_big(int nH, int k, const double* __restrict__ Gt, const double* __restrict__ theta,
-                           bool dmu, double mu, const double* x, BLds& L, double* out) {
+                           bool dmu, double mu, const double* x, double* cx, BLds& L, double* out) {
   const int tid = threadIdx.x;
   const int a = tid & (kBK - 1), grp = tid >> 7;
+  const double* v = x;
+  if (dmu) {
+    for (int r = tid; r < nH; r += kBT) cx[r] = x[r] / (theta[r] - mu);
+    __syncthreads();
+    v = cx;
+  }
+  // rows r = grp + 4 j; four rows per trip, so four row loads are in flight at once
   double s = 0.0;
   if (a < k) {
-    for (int r = grp; r < nH; r += 4) {
-      const double c = dmu ? 1.0 / (theta[r] - mu) : 1.0;
-      s = fma(c * x[r], Gt[(size_t)r * k + a], s);
+    const double* __restrict__ g = Gt + a;
+    int r = grp;
+    for (; r + 12 < nH; r += 16) {
+      const double g0 = g[(size_t)r * k], g1 = g[(size_t)(r + 4) * k];
+      const double g2 = g[(size_t)(r + 8) * k], g3 = g[(size_t)(r + 12) * k];
+      const double v0 = v[r], v1 = v[r + 4], v2 = v[r + 8], v3 = v[r + 12];
+      s = fma(v0, g0, s);
+      s = fma(v1, g1, s);
+      s = fma(v2, g2, s);
+      s = fma(v3, g3, s);
     }
+    for (; r < nH; r += 4) s = fma(v[r], g[(size_t)r * k], s);
   }
   L.part[grp][a] = s;
   __syncthreads();
@@ -240,13 +256,24 @@ __device__ void colsum_big(int nH, int k, const double* __restrict__ Gt, const d
   __syncthreads();
 }
 
-// g_r . v for row r of Gt and the LDS k-vector v, by one wave (every lane gets it)
-__device__ __forceinline__ double row_dot(int k, const double* __restrict__ Gt, int r, const double* v) {
+// g_r . v for the 4 rows r = r0, r0 + kBW, r0 + 2 kBW, r0 + 3 kBW of Gt and the LDS k-vector v, by
+// one wave (every lane gets them; rows past nH give 0): the 4 rows' loads are issued before the
+// first reduction.
+__device__ __forceinline__ void row_dot4(int nH, int k, const double* __restrict__ Gt, int r0, const double* v,
+                                         double (&d)[4]) {
   const int lane = threadIdx.x & 63;
-  const double* __restrict__ g = Gt + (size_t)r * k;
-  double s = (lane < k) ? g[lane] * v[lane] : 0.0;
-  if (lane + 64 < k) s = fma(g[lane + 64], v[lane + 64], s);
-  return wsum(s);
+  const double v0 = (lane < k) ? v[lane] : 0.0, v1 = (lane + 64 < k) ? v[lane + 64] : 0.0;
+  double s[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = r0 + u * kBW;
+    const int rc = (r < nH) ? r : nH - 1;
+    const double* __restrict__ g = Gt + (size_t)rc * k;
+    const double a0 = (lane < k) ? g[lane] : 0.0, a1 = (lane + 64 < k) ? g[lane + 64] : 0.0;
+    s[u] = (r < nH) ? fma(a1, v1, a0 * v0) : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) d[u] = wsum(s[u]);
 }
 
 // One workgroup per pair i: shift-invert solves at the start vector's Rayleigh quotient (or
@@ -280,9 +307,14 @@ __global__ __launch_bounds__(kBT) void srqi_big_kernel(int nH, int k, const doub
     for (int a = tid; a < k; a += kBT) L.vh[a] = x[nH + a];
     __syncthreads();
     double part = 0.0;
-    for (int r = wave; r < nH; r += kBW) {
-      const double gd = row_dot(k, Gt, r, L.vh);
-      if (lane == 0) part = fma(x[r], fma(theta[r], x[r], 2.0 * gd), part);
+    for (int r0 = wave; r0 < nH; r0 += 4 * kBW) {
+      double gd[4];
+      row_dot4(nH, k, Gt, r0, L.vh, gd);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + u * kBW;
+        if (lane == 0 && r < nH) part = fma(x[r], fma(theta[r], x[r], 2.0 * gd[u]), part);
+      }
     }
     if (tid < k) {
       double hx = 0.0;
@@ -306,7 +338,7 @@ __global__ __launch_bounds__(kBT) void srqi_big_kernel(int nH, int k, const doub
       since = 0;
     }
     // rhs = x_H - Gt^T (d o x_Theta), then y_H = S^{-1} rhs
-    colsum_big(nH, k, Gt, theta, true, mu, x, L, L.vb);
+    colsum_big(nH, k, Gt, theta, true, mu, x, y, L, L.vb);   // y is free until y_Theta below
     if (wave == 0) {
       double b0 = (lane < k) ? x[nH + lane] - L.vb[lane] : 0.0;
       double b1 = (lane + 64 < k) ? x[nH + lane + 64] - L.vb[lane + 64] : 0.0;
@@ -316,9 +348,14 @@ __global__ __launch_bounds__(kBT) void srqi_big_kernel(int nH, int k, const doub
     }
     __syncthreads();
     // y_Theta = d o (x_Theta - Gt y_H), y_H as solved
-    for (int r = wave; r < nH; r += kBW) {
-      const double gd = row_dot(k, Gt, r, L.vh);
-      if (lane == 0) y[r] = (x[r] - gd) / (theta[r] - mu);
+    for (int r0 = wave; r0 < nH; r0 += 4 * kBW) {
+      double gd[4];
+      row_dot4(nH, k, Gt, r0, L.vh, gd);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + u * kBW;
+        if (lane == 0 && r < nH) y[r] = (x[r] - gd[u]) / (theta[r] - mu);
+      }
     }
     for (int a = tid; a < k; a += kBT) y[nH + a] = L.vh[a];
     __syncthreads();
@@ -363,15 +400,20 @@ __global__ __launch_bounds__(kBT) void srr_big_kernel(int nH, int k, const doubl
   double* w = xs + (size_t)i * 2 * n;
   for (int a = tid; a < k; a += kBT) L.vh[a] = x[nH + a];
   __syncthreads();
-  colsum_big(nH, k, Gt, theta, false, 0.0, x, L, L.vb);       // Gt^T x_Theta
+  colsum_big(nH, k, Gt, theta, false, 0.0, x, nullptr, L, L.vb);   // Gt^T x_Theta
   if (tid < k) {
     double s = L.vb[tid];
     for (int b = 0; b < k; ++b) s = fma(Hm[(size_t)tid * k + b], L.vh[b], s);
     w[nH + tid] = s;
   }
-  for (int r = wave; r < nH; r += kBW) {
-    const double gd = row_dot(k, Gt, r, L.vh);
-    if (lane == 0) w[r] = fma(theta[r], x[r], gd);
+  for (int r0 = wave; r0 < nH; r0 += 4 * kBW) {
+    double gd[4];
+    row_dot4(nH, k, Gt, r0, L.vh, gd);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * kBW;
+      if (lane == 0 && r < nH) w[r] = fma(theta[r], x[r], gd[u]);
+    }
   }
   __syncthreads();
   double xw = 0.0;
