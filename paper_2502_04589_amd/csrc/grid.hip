@@ -385,7 +385,8 @@ __global__ __launch_bounds__(kBlock) void restrict_flat_kernel(int mf, int mc, u
 // [0, mc) are the Dirichlet boundary (zero); fine nodes 2g+1 with g = -1 do not exist.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void prolong_cell_kernel(int mf, int mc, unsigned k, const T* __restrict__ xc,
-                                                             T* __restrict__ xf, int mode) {
+                                                             T* __restrict__ xf, int mode, const T* __restrict__ b,
+                                                             const double* __restrict__ dinv, double omega) {
   const unsigned ng = (unsigned)mc + 1;
   unsigned G = ng * ng;
   if (DIM == 3) G *= ng;
@@ -444,7 +445,8 @@ __global__ __launch_bounds__(kBlock) void prolong_cell_kernel(int mf, int mc, un
         T* dst = xf + (size_t)fn * k + col;
         if (mode == 0) *dst = (T)val;
         else if (mode == 1) *dst = (T)((double)*dst + val);
-        else *dst = (T)((double)*dst - val);
+        else if (mode == 2) *dst = (T)((double)*dst - val);
+        else *dst = (T)fma(omega * dinv[fn], (double)b[(size_t)fn * k + col], val);
       }
 }
 
@@ -499,7 +501,7 @@ __device__ __forceinline__ int p1d(int f, int mc, int* I, double* w) {
 
 template <int DIM, typename T>
 __global__ void prolong_kernel(int mf, int mc, int k, const T* __restrict__ xc, T* __restrict__ xf,
-                               int mode) {
+                               int mode, const T* __restrict__ b, const double* __restrict__ dinv, double omega) {
   long long Nf = (long long)mf * mf;
   if (DIM == 3) Nf *= mf;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -522,7 +524,8 @@ __global__ void prolong_kernel(int mf, int mc, int k, const T* __restrict__ xc, 
       }
   if (mode == 0) xf[i] = (T)s;
   else if (mode == 1) xf[i] = (T)((double)xf[i] + s);
-  else xf[i] = (T)((double)xf[i] - s);
+  else if (mode == 2) xf[i] = (T)((double)xf[i] - s);
+  else xf[i] = (T)fma(omega * dinv[node], (double)b[i], s);
 }
 
 // node average of log kappa over the 2^3 elements around each interior node (3D)
@@ -789,22 +792,34 @@ void launch_restrict(int dim, int mf, int mc, int k, const void* xf, void* xc, i
   else launch_restrict_t<double>(dim, mf, mc, k, (const double*)xf, (double*)xc, s);
 }
 
+// mode 0: xf = P xc, 1: xf += P xc, 2: xf -= P xc, 3: xf = omega D^{-1} b + P xc
 template <typename T>
-static void launch_prolong_t(int dim, int mf, int mc, int k, const T* xc, T* xf, int mode, hipStream_t s) {
+static void launch_prolong_t(int dim, int mf, int mc, int k, const T* xc, T* xf, int mode, const T* b,
+                             const double* dinv, double omega, hipStream_t s) {
   long long Nf = (long long)mf * mf * (dim == 3 ? mf : 1);
   const long long G = (long long)(mc + 1) * (mc + 1) * (dim == 3 ? (mc + 1) : 1);
   if (Nf * k <= kFlatMax && G * k <= kFlatMax) {
-    if (dim == 3) prolong_cell_kernel<3, T><<<nblk(G * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode);
-    else prolong_cell_kernel<2, T><<<nblk(G * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode);
+    if (dim == 3)
+      prolong_cell_kernel<3, T><<<nblk(G * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode, b, dinv, omega);
+    else
+      prolong_cell_kernel<2, T><<<nblk(G * k), kBlock, 0, s>>>(mf, mc, (unsigned)k, xc, xf, mode, b, dinv, omega);
     return;
   }
-  if (dim == 3) prolong_kernel<3, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
-  else prolong_kernel<2, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode);
+  if (dim == 3) prolong_kernel<3, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode, b, dinv, omega);
+  else prolong_kernel<2, T><<<nblk(Nf * k), kBlock, 0, s>>>(mf, mc, k, xc, xf, mode, b, dinv, omega);
 }
 
 void launch_prolong(int dim, int mf, int mc, int k, const void* xc, void* xf, int mode, int fp32, hipStream_t s) {
-  if (fp32) launch_prolong_t<float>(dim, mf, mc, k, (const float*)xc, (float*)xf, mode, s);
-  else launch_prolong_t<double>(dim, mf, mc, k, (const double*)xc, (double*)xf, mode, s);
+  if (fp32) launch_prolong_t<float>(dim, mf, mc, k, (const float*)xc, (float*)xf, mode, nullptr, nullptr, 0.0, s);
+  else launch_prolong_t<double>(dim, mf, mc, k, (const double*)xc, (double*)xf, mode, nullptr, nullptr, 0.0, s);
+}
+
+void launch_prolong_first(int dim, int mf, int mc, int k, const void* xc, void* xf, const void* b,
+                          const double* dinv, double omega, int fp32, hipStream_t s) {
+  if (fp32)
+    launch_prolong_t<float>(dim, mf, mc, k, (const float*)xc, (float*)xf, 3, (const float*)b, dinv, omega, s);
+  else
+    launch_prolong_t<double>(dim, mf, mc, k, (const double*)xc, (double*)xf, 3, (const double*)b, dinv, omega, s);
 }
 
 template <int DIM>

@@ -49,6 +49,10 @@ enum Epi : int {
   // and b both passed as b: the staged planes hold x1 = omega D^{-1} b (scaled as they are staged),
   // out = x1 + omega D^{-1} (b - A x1)
   EPI_SWEEP2V = 9,
+  // 3D LDS-staged only, variable coefficient: the residual after one damped-Jacobi sweep from x = 0,
+  // with x passed as b: the staged planes hold x1 = omega D^{-1} b, out = b - A x1 (b recovered from
+  // x1 at the node)
+  EPI_RESID1V = 10,
 };
 
 struct StencilArgs {
@@ -85,6 +89,10 @@ void launch_first_sweep(int dim, long long N, int k, const double* dinv, double 
 // restriction xc = P^T xf (ratio 2), prolongation xf (op)= P xc; mode 0: xf = P xc, 1: xf += P xc, 2: xf -= P xc
 void launch_restrict(int dim, int mf, int mc, int k, const void* xf, void* xc, int fp32, hipStream_t s);
 void launch_prolong(int dim, int mf, int mc, int k, const void* xc, void* xf, int mode, int fp32, hipStream_t s);
+// xf = omega D^{-1} b + P xc (the coarse correction added to one damped-Jacobi sweep from x = 0,
+// formed here instead of being stored by the sweep); dinv per fine node
+void launch_prolong_first(int dim, int mf, int mc, int k, const void* xc, void* xf, const void* b,
+                          const double* dinv, double omega, int fp32, hipStream_t s);
 // setup helpers
 void launch_kappa_dinv(int dim, int n, const double* kappa, double* dinv, hipStream_t s);
 void launch_kappa_coefs(int dim, int n, const double* kappa, double* coef, hipStream_t s);   // N x 3^dim

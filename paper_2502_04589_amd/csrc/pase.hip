@@ -624,17 +624,27 @@ void vcycle(pase_handle* h, const VBufs& B, int l, int k, const void* b, void* x
     cur = t1;
     oth = t0;
     i0 = 2;
+  } else if (h->dim == 3 && !h->alg && !h->kappa_is_one && h->opt.nu == 1) {
+    // variable coefficient, one sweep: x1 = omega D^{-1} b is never stored; the residual pass
+    // forms it as the planes of b are staged, and the prolongation adds it to the correction
+    stencil_op(h, l, k, EPI_RESID1V, b, nullptr, B.r[l], nullptr, B.fp32);
+    xfer_restrict(h, l, k, B.r[l], B.b[l + 1], B.fp32);
+    vcycle(h, B, l + 1, k, B.b[l + 1], B.x[l + 1]);
+    launch_prolong_first(h->dim, lv.m, h->lev[l + 1].m, k, B.x[l + 1], cur, b, lv.dinv, h->opt.omega, B.fp32, s);
+    i0 = -1;   // pre-smoothing, residual and prolongation done
   } else {
     launch_first_sweep(h->dim, lv.N, k, lv.dinv, h->opt.omega, b, t0, B.fp32, s);
   }
-  for (int i = i0; i < h->opt.nu; ++i) {
-    stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr, B.fp32);
-    std::swap(cur, oth);
+  if (i0 >= 0) {
+    for (int i = i0; i < h->opt.nu; ++i) {
+      stencil_op(h, l, k, EPI_SWEEP, cur, b, oth, nullptr, B.fp32);
+      std::swap(cur, oth);
+    }
+    stencil_op(h, l, k, EPI_RESID, cur, b, B.r[l], nullptr, B.fp32);
+    xfer_restrict(h, l, k, B.r[l], B.b[l + 1], B.fp32);
+    vcycle(h, B, l + 1, k, B.b[l + 1], B.x[l + 1]);
+    xfer_prolong(h, l + 1, k, B.x[l + 1], cur, 1, B.fp32);
   }
-  stencil_op(h, l, k, EPI_RESID, cur, b, B.r[l], nullptr, B.fp32);
-  xfer_restrict(h, l, k, B.r[l], B.b[l + 1], B.fp32);
-  vcycle(h, B, l + 1, k, B.b[l + 1], B.x[l + 1]);
-  xfer_prolong(h, l + 1, k, B.x[l + 1], cur, 1, B.fp32);
   const bool fuse = dot && l == 0 && h->dim == 3;
   for (int i = 0; i < h->opt.nu; ++i) {
     const bool last = i + 1 == h->opt.nu;

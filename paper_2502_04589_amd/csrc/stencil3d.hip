@@ -45,6 +45,7 @@ void launch_fine3(const Fine3Args& a, Epi epi, hipStream_t s) {
     case EPI_SWEEPDOT: launchv<double, EPI_SWEEPDOT>(a, s); break;
     case EPI_SWEEP2: launchv<double, EPI_SWEEP2>(a, s); break;
     case EPI_SWEEP2V: launchv<double, EPI_SWEEP2V>(a, s); break;
+    case EPI_RESID1V: launchv<double, EPI_RESID1V>(a, s); break;
     case EPI_A: launchv<double, EPI_A>(a, s); break;
     case EPI_M: launchv<double, EPI_M>(a, s); break;
   }

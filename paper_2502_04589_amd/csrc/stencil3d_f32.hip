@@ -17,6 +17,7 @@ void launch_fine3_f32(const Fine3Args& a, Epi epi, hipStream_t s) {
     case EPI_SWEEPDOT: launchv<float, EPI_SWEEPDOT>(a, s); break;
     case EPI_SWEEP2: launchv<float, EPI_SWEEP2>(a, s); break;
     case EPI_SWEEP2V: launchv<float, EPI_SWEEP2V>(a, s); break;
+    case EPI_RESID1V: launchv<float, EPI_RESID1V>(a, s); break;
     case EPI_A: launchv<float, EPI_A>(a, s); break;
     case EPI_M: launchv<float, EPI_M>(a, s); break;
   }

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
   };
   // EPI_SWEEP2V: the staged planes hold x1 = omega D^{-1} b; the diagonal is loaded with the plane
   // (kept in flight beside it) and applied when the plane is stashed
-  constexpr bool kFirst2 = (EPI == EPI_SWEEP2V);
+  constexpr bool kFirst2 = (EPI == EPI_SWEEP2V || EPI == EPI_RESID1V);
   const long long nplane = (long long)m * m;
   auto ldd = [&](int z, int u) -> double {
     if constexpr (kFirst2) {
@@ -538,6 +538,12 @@ __global__ __launch_bounds__(BX * BY * NQ) void fine3v_kernel(Fine3Args a) {
 #pragma unroll
       for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, c * center[i] + c * (center[i] - c * ax[i]));
       stvec((T*)a.out1, off, o1, ok);
+    } else if (EPI == EPI_RESID1V) {
+      // b - A x1 with b = x1 a_ii / omega at the node (x1 = omega D^{-1} b as staged)
+      const double c = dcoef / a.omega;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) vset<T, VW>(o1, i, fma(c, center[i], -ax[i]));
+      stvec((T*)a.out1, off, o1, ok);
     } else if (EPI == EPI_SWEEP2V) {
       // second sweep from x1 = omega D^{-1} b: x1 + omega D^{-1} (b - A x1) = 2 x1 - omega D^{-1} A x1
       const double wd = a.omega / dcoef;
@@ -681,7 +687,7 @@ void launchv_w(const Fine3Args& a, hipStream_t s) {
       return;
     }
   }
-  if constexpr (EPI == EPI_SWEEP2V) {
+  if constexpr (EPI == EPI_SWEEP2V || EPI == EPI_RESID1V) {
     // variable coefficient only (the caller passes coef or kappa)
     if (vec) launchv_tile<T, VW, EPI, false, true, false>(a, s);
     else launchv_tile<T, VW, EPI, false, false, false>(a, s);

@@ -78,6 +78,26 @@ def test_transfer_and_vcycle(dim, levels, kseed):
         assert relerr(host(s.vcycle(dev(Xf))), H.vcycle(Xf)) < 1e-12
 
 
+@pytest.mark.parametrize("nu", [1, 3])
+def test_vcycle_and_pcg_sweep_counts(nu):
+    """V-cycle and 2-step PCG with nu = 1 (the residual pass that stages x1 = omega D^-1 b itself,
+    and the prolongation that adds x1 to the correction) and nu = 3 against the oracle with the same
+    nu, 3D kappa field; k = 16 takes the 8x4-node tiles, k = 3 the 8x8 tiles with scalar columns."""
+    dim, levels = 3, [32, 16, 8, 4]
+    kap = synth.kappa_field(dim, levels[0], 7)
+    H = multigrid.Hierarchy(dim, levels, kap, nu=nu)
+    s = Solver(dim, levels, kap, nev_max=16, nu=nu, cg_steps=2)
+    rng = np.random.default_rng(nu)
+    for k in (3, 16):
+        Xf = rng.standard_normal((H.A[0].shape[0], k))
+        assert relerr(host(s.vcycle(dev(Xf))), H.vcycle(Xf)) < 1e-12
+    k = 6
+    U = opase.cholqr_m(synth.initial_vectors(H.A[0].shape[0], k, 3), H.M[0])
+    lam = np.einsum("ij,ij->j", U, H.A[0] @ U)
+    W = host(s.pcg(lam, dev(U)))
+    assert relerr(W, opase.pcg(H, (H.M[0] @ U) * lam, U, 2)) < 1e-12
+
+
 @pytest.mark.parametrize("N,k", [(1, 1), (37, 5), (1000, 16), (4099, 17), (20000, 50), (9000, 100)])
 def test_gram_mfma(N, k):
     s = Solver(3, [32, 16, 8], nev_max=max(k, 16))
