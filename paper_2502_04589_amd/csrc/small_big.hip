@@ -66,9 +66,11 @@ __device__ __forceinline__ double hash_pm1(unsigned a, unsigned b) {
 }
 
 // S = H - mu I - sum_r d_r g_r g_r^T, d_r = 1 / (theta_r - mu), g_r = row r of Gt, on
-// v_mfma_f64_16x16x4f64.  A step covers 4 rows: lane (li, lk) loads Gt[r0 + lk][16 c + li]
-// for the 8 column blocks c, which is both the A operand (times d) of tile row c and the B
-// operand of tile column c.  Wave w accumulates the tiles w, w + 8, ... of the T x T grid.
+// v_mfma_f64_16x16x4f64.  A step covers 4 rows, and lane (li, lk) loads Gt[r0 + lk][16 c + li]
+// for the 8 column blocks c.  Wave w accumulates the tiles w, w + 8, ... of the T x T grid.  With
+// T = 8 (k > 112) tile t of wave w is (t, w): its A operand is block t (a compile-time index) and
+// its B operand block w, loaded once more per step; for smaller T the blocks of each tile are
+// picked out of the row by a run-time index.
 // acc (this wave's tiles w, w + 8, ... of the T x T grid) += sum over rows rb <= r < re of
 // d_r g_r g_r^T (re > rb)
 __device__ void schur_rows_acc(int rb, int re, int k, const double* __restrict__ Gt,
@@ -76,9 +78,11 @@ __device__ void schur_rows_acc(int rb, int re, int k, const double* __restrict__
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int T = (k + 15) >> 4, TT = T * T;
+  const bool full = (T == 8);
+  const int colw = 16 * wave + li;     // B-operand column of every tile when T = 8
   // the next step's row values are loaded while this step's MFMAs run (two waves per SIMD
   // leave little else to hide the L2 latency)
-  double gn[8], thn;
+  double gn[8], gwn, thn;
   auto fetch = [&](int r0) {
     const int row = r0 + lk;
     const int rc = (row < re) ? row : re - 1;
@@ -88,6 +92,7 @@ __device__ void schur_rows_acc(int rb, int re, int k, const double* __restrict__
       const int col = 16 * c + li;
       gn[c] = (c < T && col < k) ? Gt[(size_t)rc * k + col] : 0.0;
     }
+    gwn = (full && colw < k) ? Gt[(size_t)rc * k + colw] : 0.0;
   };
   fetch(rb);
   for (int r0 = rb; r0 < re; r0 += 4) {
@@ -96,7 +101,13 @@ __device__ void schur_rows_acc(int rb, int re, int k, const double* __restrict__
     double g[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) g[c] = rok ? gn[c] : 0.0;
+    const double gw = rok ? gwn : 0.0;
     if (r0 + 4 < re) fetch(r0 + 4);
+    if (full) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(dv * g[t], gw, acc[t], 0, 0, 0);
+      continue;
+    }
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int tt = wave + 8 * t;
