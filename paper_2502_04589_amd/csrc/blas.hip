@@ -108,6 +108,17 @@ __global__ void gather_cols_kernel(long long N, int k, int ka, const int* __rest
   C[q] = B[n * k + idx[q - n * ka]];
 }
 
+// B (N x k): column j of U where pos[j] < 0, else column pos[j] of C (N x ka), in one pass (the
+// soft-locked block with the fine solves of its active columns)
+__global__ void merge_cols_kernel(long long N, int k, int ka, const int* __restrict__ pos, const double* __restrict__ C,
+                                  const double* __restrict__ U, double* __restrict__ B) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * k) return;
+  const long long n = q / k;
+  const int p = pos[q - n * k];
+  B[q] = (p >= 0) ? C[n * ka + p] : U[q];
+}
+
 __global__ void scatter_cols_kernel(long long N, int k, int ka, const int* __restrict__ idx,
                                     const double* __restrict__ C, double* __restrict__ B) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,6 +168,31 @@ __global__ void axpy2_kernel(long long N, int k, const double* __restrict__ alph
   const double a = alpha[i % k];
   X[i] = (T)fma(a, (double)P[i], (double)Xin[i]);
   if (R) R[i] = (T)fma(-a, (double)Q[i], (double)R[i]);
+}
+
+// Two CG steps with the first x update folded into the second: R -= alpha Q; Z += beta P;
+// X = X0 + a0 P + a1 Z (per-column scalars)
+__global__ void rsub_kernel(long long N, int k, const double* __restrict__ alpha, const double* __restrict__ Q,
+                            double* __restrict__ R) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  R[i] = fma(-alpha[i % k], Q[i], R[i]);
+}
+
+__global__ void zadd_kernel(long long N, int k, const double* __restrict__ beta, const double* __restrict__ P,
+                            double* __restrict__ Z) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  Z[i] = fma(beta[i % k], P[i], Z[i]);
+}
+
+__global__ void axpy3_kernel(long long N, int k, const double* __restrict__ a0, const double* __restrict__ P,
+                             const double* __restrict__ a1, const double* __restrict__ Z, const double* X0,
+                             double* X) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  const int j = (int)(i % k);
+  X[i] = fma(a1[j], Z[i], fma(a0[j], P[i], X0[i]));
 }
 
 template <typename T>
@@ -936,6 +972,11 @@ void launch_gather_cols(long long N, int k, int ka, const int* idx, const double
   gather_cols_kernel<<<nblk(N * ka), kBlock, 0, s>>>(N, k, ka, idx, B, C);
 }
 
+void launch_merge_cols(long long N, int k, int ka, const int* pos, const double* C, const double* U, double* B,
+                       hipStream_t s) {
+  merge_cols_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, ka, pos, C, U, B);
+}
+
 void launch_scatter_cols(long long N, int k, int ka, const int* idx, const double* C, double* B, hipStream_t s) {
   scatter_cols_kernel<<<nblk(N * ka), kBlock, 0, s>>>(N, k, ka, idx, C, B);
 }
@@ -950,6 +991,19 @@ void launch_select_cols(long long N, int k, const int* mask, const double* A, do
 }
 
 void launch_fill_int(int n, int v, int* p, hipStream_t s) { fill_int_kernel<<<1, kBlock, 0, s>>>(n, v, p); }
+
+void launch_rsub(long long N, int k, const double* alpha, const double* Q, double* R, hipStream_t s) {
+  rsub_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, alpha, Q, R);
+}
+
+void launch_zadd(long long N, int k, const double* beta, const double* P, double* Z, hipStream_t s) {
+  zadd_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, beta, P, Z);
+}
+
+void launch_axpy3(long long N, int k, const double* a0, const double* P, const double* a1, const double* Z,
+                  const double* X0, double* X, hipStream_t s) {
+  axpy3_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, a0, P, a1, Z, X0, X);
+}
 
 void launch_xpby(long long N, int k, const double* Z, const double* beta, double* P, hipStream_t s) {
   xpby_kernel<double><<<nblk(N * k), kBlock, 0, s>>>(N, k, Z, beta, P);

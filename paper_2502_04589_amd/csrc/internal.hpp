@@ -183,6 +183,12 @@ void launch_select_cols(long long N, int k, const int* mask, const double* A, do
 // C (N x ka) = columns idx[0..ka) of B (N x k), and back
 void launch_gather_cols(long long N, int k, int ka, const int* idx, const double* B, double* C, hipStream_t s);
 void launch_scatter_cols(long long N, int k, int ka, const int* idx, const double* C, double* B, hipStream_t s);
+void launch_rsub(long long N, int k, const double* alpha, const double* Q, double* R, hipStream_t s);
+void launch_zadd(long long N, int k, const double* beta, const double* P, double* Z, hipStream_t s);
+void launch_axpy3(long long N, int k, const double* a0, const double* P, const double* a1, const double* Z,
+                  const double* X0, double* X, hipStream_t s);
+void launch_merge_cols(long long N, int k, int ka, const int* pos, const double* C, const double* U, double* B,
+                       hipStream_t s);
 // dst (N x kout) columns [0, nc) from src (N x kin); fill: columns [nc, kout) get uniform(-1, 1)
 // values from a counter-based generator (kout = dst's leading dimension)
 void launch_copy_cols(long long N, int kin, int kout, int nc, const double* src, double* dst, int fill,

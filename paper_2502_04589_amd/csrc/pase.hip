@@ -119,7 +119,8 @@ struct pase_handle {
   // below 1e-6 or stops halving over two corrections (then FP64 to the end of the solve)
   bool proj_lp = false;
   int proj_lp_iters = 0;
-  // soft locking: the next correction's fine solves run for the ka columns lock_idx[0..ka)
+  // soft locking: the next correction's fine solves run for the ka columns lock_idx[0..ka); lock_idx[K + j]
+  // is the position of column j among them (-1: locked)
   int* lock_idx = nullptr;
   int ka = 0;
   std::vector<int> lock_host;
@@ -349,7 +350,7 @@ size_t layout(pase_handle* h, void* base) {
     const size_t NHf = (size_t)h->lev[h->L].N;
     h->AinvL32 = b.take<float>(NHf * NHf);
   }
-  h->lock_idx = b.take<int>(K);
+  h->lock_idx = b.take<int>(2 * K);
   h->small_tolv = b.take<double>(K);
   if (h->opt.precision == PASE_PREC_LEARNED) {
     h->logk = b.take<double>((size_t)N0);
@@ -709,6 +710,20 @@ void pcg(pase_handle* h, int k, const double* X0, double* X, double* R) {
   const long long N = h->lev[0].N;
   vcycle(h, 0, k, R, h->Z, h->rho);
   std::swap(h->Z, h->P);
+  if (h->opt.cg_steps == 2) {
+    // the same two steps with one x update: r1 = r0 - a0 A p0, p1 = z1 + b p0 (formed in Z, so p0
+    // stays in P), x = x0 + a0 p0 + a1 p1; a1 goes to the beta vector once b has been used
+    apply_dot(h, k, h->P, h->Q, h->pq, 0);
+    launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
+    launch_rsub(N, k, h->alpha, h->Q, R, s);
+    vcycle(h, 0, k, R, h->Z, h->rho2);
+    launch_pcg_beta(k, h->rho2, h->rho, h->beta, s);
+    launch_zadd(N, k, h->beta, h->P, h->Z, s);
+    apply_dot(h, k, h->Z, h->Q, h->pq, 0);
+    launch_pcg_alpha(k, h->rho2, h->pq, h->beta, s);
+    launch_axpy3(N, k, h->alpha, h->P, h->beta, h->Z, X0, X, s);
+    return;
+  }
   for (int j = 0; j < h->opt.cg_steps; ++j) {
     apply_dot(h, k, h->P, h->Q, h->pq, 0);
     launch_pcg_alpha(k, h->rho, h->pq, h->alpha, s);
@@ -1227,8 +1242,7 @@ pase_status correction_enqueue(pase_handle* h, int k) {
     } else {
       pcg(h, ka, h->W2, h->R, h->W3);
     }
-    launch_copy((size_t)N * k, h->U, h->X, s);
-    launch_scatter_cols(N, k, ka, h->lock_idx, h->R, h->X, s);
+    launch_merge_cols(N, k, ka, h->lock_idx + h->K, h->R, h->U, h->X, s);
   } else if (h->opt.precision == PASE_PREC_MIXED) {
     pcg_correction_f32(h, k, h->U, h->R, h->X);
   } else if (h->opt.precision == PASE_PREC_LEARNED) {
@@ -1754,7 +1768,7 @@ pase_status pase_setup(const pase_problem* prob, const pase_options* opt, void* 
   for (hipEvent_t& e : h->evm) HIPS(hipEventCreate(&e));
   {
     const size_t Kp = (size_t)h->K;
-    HIPS(hipHostMalloc(&h->pin, sizeof(double) * 7 * Kp + sizeof(int) * (Kp + 20), hipHostMallocDefault));
+    HIPS(hipHostMalloc(&h->pin, sizeof(double) * 7 * Kp + sizeof(int) * (2 * Kp + 20), hipHostMallocDefault));
     double* pd = (double*)h->pin;
     h->pin_sums = pd;
     h->pin_lam = pd + 3 * Kp;
@@ -2047,7 +2061,10 @@ pase_status pase_solve(pase_handle* h, int nev, double tol, const double* U0, do
       if (h->ka > 0 && h->ka < k)
       {
         std::memcpy(h->pin_idx, h->lock_host.data(), sizeof(int) * h->ka);
-        HIPC(hipMemcpyAsync(h->lock_idx, h->pin_idx, sizeof(int) * h->ka, hipMemcpyHostToDevice, s));
+        int* pos = h->pin_idx + h->K;
+        for (int j = 0; j < k; ++j) pos[j] = -1;
+        for (int a = 0; a < h->ka; ++a) pos[h->lock_host[a]] = a;
+        HIPC(hipMemcpyAsync(h->lock_idx, h->pin_idx, sizeof(int) * (h->K + k), hipMemcpyHostToDevice, s));
       }
     }
     {
