@@ -100,6 +100,10 @@ struct pase_handle {
   double *theta = nullptr, *Psi = nullptr, *Gtl = nullptr, *Vtf = nullptr, *Vtf2 = nullptr, *Gf = nullptr;
   double *rqf = nullptr, *resf = nullptr;
   double *cmw = nullptr, *kkb = nullptr, *X0f = nullptr;   // P^T M W, beta, start block
+  // complement coordinates c = B_H^{-1} P^T M W of the last projection, kept for the prolongation when
+  // W_perp = W - P c was not formed on the fine grid (w_perp false)
+  double* cperp = nullptr;
+  bool w_perp = true;
   int *permf = nullptr, *statf = nullptr;
   double small_scale = 1.0;
   // learned form: attached network, node log kappa, flexible-PCG column state
@@ -443,6 +447,7 @@ size_t layout(pase_handle* h, void* base) {
   h->ca = b.take<double>(NH * K);
   h->cb = b.take<double>(NH * K);
   h->cc = b.take<double>(NH * K);
+  h->cperp = b.take<double>(NH * K);
   h->kk1 = b.take<double>(K * K); h->kk2 = b.take<double>(K * K); h->kk3 = b.take<double>(K * K);
   h->kk4 = b.take<double>(K * K); h->kk5 = b.take<double>(K * K);
   h->lam = b.take<double>(K); h->rho = b.take<double>(K); h->rho2 = b.take<double>(K);
@@ -853,12 +858,14 @@ void cholqr_m(pase_handle* h, int k, double*& U, double*& spare, int slot) {
   std::swap(U, spare);
 }
 
-// U = P y_H + W y_W from the small problem's vectors in Vs (y_W = Li^T V_W) and y_H given.
-void prolongation_tail(pase_handle* h, int k, const double* yH) {
+// U = P y_H + W_perp y_W from the small problem's vectors in Vs (y_W = Li^T V_W) and y_H given (y_H is
+// overwritten).  When W_perp = W - P c was not formed, U = P (y_H - c y_W) + W y_W.
+void prolongation_tail(pase_handle* h, int k, double* yH) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   const int NH = (int)h->lev[h->L].N;
   launch_gemm(true, false, k, k, k, 1.0, h->kk3, k, h->Vs + (size_t)NH * k, k, 0.0, h->kk4, k, s);
+  if (!h->w_perp) launch_gemm(false, false, NH, k, k, -1.0, h->cperp, k, h->kk4, k, 1.0, yH, k, s);
   prolong_all(h, k, yH, h->U, 0);
   launch_tsmm(N, k, h->X, h->kk4, h->U, 1, 0, s);
 }
@@ -1270,14 +1277,16 @@ pase_status correction_enqueue(pase_handle* h, int k) {
     launch_tsmm(N, k, h->X, h->gX + (size_t)h->gNH * k, h->U, 1, 0, s);
     return PASE_OK;
   }
-  // complement: W <- W - P B_H^{-1} P^T M W
-  apply_AM(h, 0, k, W, nullptr, h->W3);
-  restrict_all(h, k, h->W3, h->ca);
-  launch_gemm(false, false, NH, k, NH, 1.0, h->BHinv, NH, h->ca, k, 0.0, h->cb, k, s);
-  prolong_all(h, k, h->cb, W, 2);
-  if (h->fast) launch_copy((size_t)NH * k, h->ca, h->cmw, s);   // P^T M W: W's coarse coordinates
-  // (b) projection: A W, M W, a = P^T A W, alpha = W^T A W, beta = W^T M W
+  // (b) complement W_perp = W - P c, c = B_H^{-1} P^T M W, and the projection: a = P^T A W_perp,
+  // alpha = W_perp^T A W_perp, beta = W_perp^T M W_perp
   if (h->proj_lp) {
+    // W_perp formed on the fine grid (the low-precision products below take it)
+    apply_AM(h, 0, k, W, nullptr, h->W3);
+    restrict_all(h, k, h->W3, h->ca);
+    launch_gemm(false, false, NH, k, NH, 1.0, h->BHinv, NH, h->ca, k, 0.0, h->cb, k, s);
+    prolong_all(h, k, h->cb, W, 2);
+    if (h->fast) launch_copy((size_t)NH * k, h->ca, h->cmw, s);   // P^T M W: W's coarse coordinates
+    h->w_perp = true;
     // low-precision projection: W in FP32, FP32 stencils, FP32 restriction, split-BF16 Grams with
     // FP32 K-blocks summed in FP64 (the CG's FP32 vectors are free here)
     float* W32 = h->R32;
@@ -1294,11 +1303,22 @@ pase_status correction_enqueue(pase_handle* h, int k) {
     launch_gram_bf16x3(N, k, W32, AW32, MW32, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);
     ++h->proj_lp_iters;
   } else {
-    // beta = W_perp^T M W_perp = W_perp^T M W: the complement made P^T M W_perp = 0, so the M W
-    // that the complement formed (W3) serves, and only A W_perp is applied here
-    apply_AM(h, 0, k, W, h->W2, nullptr);
-    restrict_all(h, k, h->W2, h->ca);
-    launch_gram2_sym(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
+    // W_perp is not formed: its products follow from W's (one pass of A and M over W, no fine
+    // subtraction and no second stencil pass).  With r = P^T A W, m = P^T M W, c = B_H^{-1} m:
+    //   a = r - A_H c,  alpha = W^T A W - r^T c - c^T a,  beta = W^T M W - c^T m,
+    // and the prolongation takes U = W y_W + P (y_H - c y_W)
+    apply_AM(h, 0, k, W, h->W2, h->W3);
+    restrict_all(h, k, h->W3, h->ca);                                                       // m
+    launch_gemm(false, false, NH, k, NH, 1.0, h->BHinv, NH, h->ca, k, 0.0, h->cb, k, s);   // c
+    if (h->fast) launch_copy((size_t)NH * k, h->ca, h->cmw, s);   // P^T M W: W's coarse coordinates
+    restrict_all(h, k, h->W2, h->cc);                                                       // r
+    launch_gram2_sym(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);
+    launch_gemm(true, false, k, k, NH, -1.0, h->cb, k, h->ca, k, 1.0, h->kk2, k, s);      // beta
+    stencil_op(h, h->L, k, EPI_RESID, h->cb, h->cc, h->ca, nullptr);                       // a = r - A_H c
+    launch_gemm(true, false, k, k, NH, -1.0, h->cc, k, h->cb, k, 1.0, h->kk1, k, s);
+    launch_gemm(true, false, k, k, NH, -1.0, h->cb, k, h->ca, k, 1.0, h->kk1, k, s);      // alpha
+    launch_copy((size_t)NH * k, h->cb, h->cperp, s);
+    h->w_perp = false;
   }
   launch_symmetrize(k, h->kk1, s);
   launch_symmetrize(k, h->kk2, s);
@@ -1386,6 +1406,7 @@ void batch_correction(pase_handle* h, int k, double theta) {
   restrict_all(h, k, h->W3, h->bmw);                                   // P^T M W
   launch_gemm(false, false, NH, k, NH, 1.0, h->BHinv, NH, h->bmw, k, 0.0, h->cb, k, s);
   prolong_all(h, k, h->cb, W, 2);                                      // W_perp
+  h->w_perp = true;
   apply_AM(h, 0, k, W, h->W2, nullptr);
   restrict_all(h, k, h->W2, h->ca);                                    // a = P^T A W_perp
   launch_gram2_sym(N, k, W, h->W2, h->W3, h->partial, gram_tiles(N, k), h->kk1, h->kk2, s);   // alpha, beta
