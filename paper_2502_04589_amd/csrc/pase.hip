@@ -710,7 +710,9 @@ void coldot(pase_handle* h, long long N, int k, const double* x, const double* y
 // R = b - A x0 given (overwritten; it is left at the residual of step s - 1, the last step
 // updating x only).  p_0 = z_0 by exchanging the Z and P buffers, and the first update reads
 // x0 from X0, so neither start needs a copy.
-void pcg(pase_handle* h, int k, const double* X0, double* X, double* R) {
+// With idx (two CG steps only): X0 and X are full blocks of leading dimension ldx and the k columns
+// solved are idx[0..k) of them (R, the residual, is the gathered k-column block).
+void pcg(pase_handle* h, int k, const double* X0, double* X, double* R, const int* idx = nullptr, int ldx = 0) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   vcycle(h, 0, k, R, h->Z, h->rho);
@@ -726,7 +728,8 @@ void pcg(pase_handle* h, int k, const double* X0, double* X, double* R) {
     launch_zadd(N, k, h->beta, h->P, h->Z, s);
     apply_dot(h, k, h->Z, h->Q, h->pq, 0);
     launch_pcg_alpha(k, h->rho2, h->pq, h->beta, s);
-    launch_axpy3(N, k, h->alpha, h->P, h->beta, h->Z, X0, X, s);
+    if (idx) launch_axpy3_gs(N, k, ldx, idx, h->alpha, h->P, h->beta, h->Z, X0, X, s);
+    else launch_axpy3(N, k, h->alpha, h->P, h->beta, h->Z, X0, X, s);
     return;
   }
   for (int j = 0; j < h->opt.cg_steps; ++j) {
@@ -1236,9 +1239,15 @@ pase_status correction_enqueue(pase_handle* h, int k) {
   if (ka < k) {
     // soft locking: the active columns of U and R gathered into W2, W3 (leading dimension ka), their
     // fine solves into R (free until the next residual), then W = U with the active columns replaced
-    launch_gather_cols(N, k, ka, h->lock_idx, h->U, h->W2, s);
+    // plain FP64 with two CG steps: U's active columns are read, and W's written, in place by the
+    // last x update, and the locked columns copied: no gathered U and no merge
+    const bool direct = h->opt.precision == PASE_PREC_FP64 && h->opt.cg_steps == 2;
+    if (!direct) launch_gather_cols(N, k, ka, h->lock_idx, h->U, h->W2, s);
     launch_gather_cols(N, k, ka, h->lock_idx, h->R, h->W3, s);
-    if (h->opt.precision == PASE_PREC_MIXED) {
+    if (direct) {
+      pcg(h, ka, h->U, h->X, h->W3, h->lock_idx, k);
+      launch_copy_locked(N, k, h->lock_idx + h->K, h->U, h->X, s);
+    } else if (h->opt.precision == PASE_PREC_MIXED) {
       pcg_correction_f32(h, ka, h->W2, h->W3, h->R);
     } else if (h->opt.precision == PASE_PREC_LEARNED) {
       if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
@@ -1249,7 +1258,7 @@ pase_status correction_enqueue(pase_handle* h, int k) {
     } else {
       pcg(h, ka, h->W2, h->R, h->W3);
     }
-    launch_merge_cols(N, k, ka, h->lock_idx + h->K, h->R, h->U, h->X, s);
+    if (!direct) launch_merge_cols(N, k, ka, h->lock_idx + h->K, h->R, h->U, h->X, s);
   } else if (h->opt.precision == PASE_PREC_MIXED) {
     pcg_correction_f32(h, k, h->U, h->R, h->X);
   } else if (h->opt.precision == PASE_PREC_LEARNED) {
