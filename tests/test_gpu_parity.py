@@ -78,6 +78,19 @@ def test_transfer_and_vcycle(dim, levels, kseed):
         assert relerr(host(s.vcycle(dev(Xf))), H.vcycle(Xf)) < 1e-12
 
 
+def test_restriction_march_kernels():
+    """The marching restriction (coarse levels of 24 nodes and more per side, one column per thread
+    for odd k and two for even k) against the oracle's P^T at 64^3, where 63 -> 31 takes it."""
+    kap = synth.kappa_field(3, 64, 4)
+    H = multigrid.Hierarchy(3, [64, 32, 16, 8], kap)
+    s = Solver(3, [64, 32, 16, 8], kap, nev_max=16)
+    rng = np.random.default_rng(5)
+    for k in (3, 16):
+        Xf = rng.standard_normal((H.A[0].shape[0], k))
+        assert relerr(host(s.restrict(dev(Xf))), H.Pc.T @ Xf) < 1e-14
+        assert relerr(host(s.vcycle(dev(Xf))), H.vcycle(Xf)) < 1e-12
+
+
 @pytest.mark.parametrize("nu", [1, 3])
 def test_vcycle_and_pcg_sweep_counts(nu):
     """V-cycle and 2-step PCG with nu = 1 (the residual pass that stages x1 = omega D^-1 b itself,
