@@ -118,6 +118,97 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int ta, int tb, int M, i
       }
 }
 
+// Products with few output tiles and a long K (N_H x N_H times N_H x k: 422 tiles of 16 x 64 for
+// N_H = 3375, k = 128) leave the 16-row kernel above with under two waves per SIMD stepping through
+// K in 16-wide stages, each waiting on its loads.  Here a block of 16 waves splits K four ways: the
+// four waves of group g (one 16 x 16 sub-tile each, as above) stage and multiply the K-range
+// [g Kq, (g+1) Kq) through their own LDS buffers, and the four partial tiles are summed in a fixed
+// order at the end (the result does not depend on timing).
+constexpr int kSkGroups = 4;
+
+template <typename T>
+__global__ __launch_bounds__(1024) void gemm_mfma_sk_kernel(int ta, int tb, int M, int N, int K, double alpha,
+                                                             const T* __restrict__ A, int lda, const T* __restrict__ B,
+                                                             int ldb, double beta, T* __restrict__ C, int ldc) {
+  constexpr int BM = 16;
+  // the partial tiles reuse the stage buffers once every group is done with them
+  __shared__ union {
+    struct {
+      double As[kSkGroups][kGK][BM + 2];
+      double Bs[kSkGroups][kGK][kGN + 2];
+    } st;
+    double Red[kSkGroups - 1][BM][kGN];
+  } sm;
+  auto& As = sm.st.As;
+  auto& Bs = sm.st.Bs;
+  auto& Red = sm.Red;
+  const int bm = blockIdx.y * BM, bn = blockIdx.x * kGN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int g = wave >> 2, gt = tid & 255, gw = wave & 3;    // group, thread and wave within it
+  const int li = lane & 15, lk = lane >> 4;
+  const int wc = gw * 16;
+  const int nst = (K + kSkGroups * kGK - 1) / (kSkGroups * kGK);   // stages per group
+  const int kb = g * nst * kGK;                                     // this group's first K
+  double ra, rb[4];
+  auto fetch = [&](int k0) {
+    {
+      int i, kk;
+      if (ta) { i = gt % BM; kk = gt / BM; } else { kk = gt & 15; i = gt >> 4; }
+      const int gi = bm + i, gk = k0 + kk;
+      ra = (gi < M && gk < K) ? (double)(ta ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = gt + 256 * u;
+      int j, k2;
+      if (tb) { k2 = e & 15; j = e >> 4; } else { j = e & 63; k2 = e >> 6; }
+      const int gj = bn + j, gk2 = k0 + k2;
+      rb[u] = (gj < N && gk2 < K) ? (double)(tb ? B[(size_t)gj * ldb + gk2] : B[(size_t)gk2 * ldb + gj]) : 0.0;
+    }
+  };
+  auto stash = [&]() {
+    if (ta) As[g][gt / BM][gt % BM] = ra; else As[g][gt & 15][gt >> 4] = ra;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = gt + 256 * u;
+      if (tb) Bs[g][e & 15][e >> 4] = rb[u]; else Bs[g][e >> 6][e & 63] = rb[u];
+    }
+  };
+  double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+  fetch(kb);
+  for (int st = 0; st < nst; ++st) {
+    __syncthreads();
+    stash();
+    __syncthreads();
+    if (st + 1 < nst) fetch(kb + (st + 1) * kGK);
+#pragma unroll
+    for (int s4 = 0; s4 < kGK / 4; ++s4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[g][4 * s4 + lk][li], Bs[g][4 * s4 + lk][wc + li], acc, 0, 0, 0);
+  }
+  // groups 1..3 hand their partial tiles to group 0, which adds them in group order
+  __syncthreads();
+  if (g > 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Red[g - 1][lk + 4 * q][wc + li] = acc[q];
+  }
+  __syncthreads();
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = lk + 4 * q;
+      double v = acc[q];
+#pragma unroll
+      for (int h = 0; h < kSkGroups - 1; ++h) v += Red[h][r][wc + li];
+      const int i = bm + r, j = bn + wc + li;
+      if (i < M && j < N) {
+        T* c = C + (size_t)i * ldc + j;
+        const double w = alpha * v;
+        *c = (beta == 0.0) ? (T)w : (T)(w + beta * (double)*c);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ blocked Cholesky
 constexpr int kNB = 64;   // panel width
 
@@ -735,6 +826,9 @@ static void gemm_mfma(bool ta, bool tb, int M, int N, int K, double alpha, const
   } else if (cols * ((M + 31) / 32) >= 512) {
     gemm_mfma_kernel<T, 32><<<dim3((unsigned)cols, (M + 31) / 32), 256, 0, s>>>(a, b, M, N, K, alpha, A, lda, B, ldb,
                                                                                  beta, C, ldc);
+  } else if (K >= 1024) {
+    gemm_mfma_sk_kernel<T><<<dim3((unsigned)cols, (M + 15) / 16), 1024, 0, s>>>(a, b, M, N, K, alpha, A, lda, B, ldb,
+                                                                                beta, C, ldc);
   } else {
     gemm_mfma_kernel<T, 16><<<dim3((unsigned)cols, (M + 15) / 16), 256, 0, s>>>(a, b, M, N, K, alpha, A, lda, B, ldb,
                                                                                  beta, C, ldc);
