@@ -195,25 +195,23 @@ __global__ void axpy3_kernel(long long N, int k, const double* __restrict__ a0, 
   X[i] = fma(a1[j], Z[i], fma(a0[j], P[i], X0[i]));
 }
 
-// The same x update for the active columns idx[0..k) of full blocks (leading dimension ldx): U's
-// columns read and X's written in place, with no gathered copy of U and no scatter of the result
-__global__ void axpy3_gs_kernel(long long N, int k, int ldx, const int* __restrict__ idx, const double* __restrict__ a0,
-                                const double* __restrict__ P, const double* __restrict__ a1,
-                                const double* __restrict__ Z, const double* __restrict__ X0, double* __restrict__ X) {
+// The same x update as one pass over full blocks (leading dimension ldx): column j of X is
+// X0 + a0 p + a1 z for the active columns (pos[j] = its position among the k solved ones) and X0 for
+// the locked ones, so whole node rows are read and written
+__global__ void axpy3_merge_kernel(long long N, int k, int ldx, const int* __restrict__ pos,
+                                   const double* __restrict__ a0, const double* __restrict__ P,
+                                   const double* __restrict__ a1, const double* __restrict__ Z,
+                                   const double* __restrict__ X0, double* __restrict__ X) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= N * k) return;
-  const long long n = q / k;
-  const int a = (int)(q - n * k);
-  const long long e = n * ldx + idx[a];
-  X[e] = fma(a1[a], Z[q], fma(a0[a], P[q], X0[e]));
-}
-
-// X = U on the columns j with pos[j] < 0 (the soft-locked ones)
-__global__ void copy_locked_kernel(long long N, int k, const int* __restrict__ pos, const double* __restrict__ U,
-                                   double* __restrict__ X) {
-  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= N * k) return;
-  if (pos[q % k] < 0) X[q] = U[q];
+  if (q >= N * ldx) return;
+  const long long n = q / ldx;
+  const int a = pos[q - n * ldx];
+  double v = X0[q];
+  if (a >= 0) {
+    const long long e = n * k + a;
+    v = fma(a1[a], Z[e], fma(a0[a], P[e], v));
+  }
+  X[q] = v;
 }
 
 template <typename T>
@@ -1026,13 +1024,9 @@ void launch_axpy3(long long N, int k, const double* a0, const double* P, const d
   axpy3_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, a0, P, a1, Z, X0, X);
 }
 
-void launch_axpy3_gs(long long N, int k, int ldx, const int* idx, const double* a0, const double* P, const double* a1,
-                     const double* Z, const double* X0, double* X, hipStream_t s) {
-  axpy3_gs_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, ldx, idx, a0, P, a1, Z, X0, X);
-}
-
-void launch_copy_locked(long long N, int k, const int* pos, const double* U, double* X, hipStream_t s) {
-  copy_locked_kernel<<<nblk(N * k), kBlock, 0, s>>>(N, k, pos, U, X);
+void launch_axpy3_merge(long long N, int k, int ldx, const int* pos, const double* a0, const double* P, const double* a1,
+                        const double* Z, const double* X0, double* X, hipStream_t s) {
+  axpy3_merge_kernel<<<nblk(N * ldx), kBlock, 0, s>>>(N, k, ldx, pos, a0, P, a1, Z, X0, X);
 }
 
 void launch_xpby(long long N, int k, const double* Z, const double* beta, double* P, hipStream_t s) {

@@ -187,9 +187,8 @@ void launch_rsub(long long N, int k, const double* alpha, const double* Q, doubl
 void launch_zadd(long long N, int k, const double* beta, const double* P, double* Z, hipStream_t s);
 void launch_axpy3(long long N, int k, const double* a0, const double* P, const double* a1, const double* Z,
                   const double* X0, double* X, hipStream_t s);
-void launch_axpy3_gs(long long N, int k, int ldx, const int* idx, const double* a0, const double* P, const double* a1,
-                     const double* Z, const double* X0, double* X, hipStream_t s);
-void launch_copy_locked(long long N, int k, const int* pos, const double* U, double* X, hipStream_t s);
+void launch_axpy3_merge(long long N, int k, int ldx, const int* pos, const double* a0, const double* P, const double* a1,
+                        const double* Z, const double* X0, double* X, hipStream_t s);
 void launch_merge_cols(long long N, int k, int ka, const int* pos, const double* C, const double* U, double* B,
                        hipStream_t s);
 // dst (N x kout) columns [0, nc) from src (N x kin); fill: columns [nc, kout) get uniform(-1, 1)

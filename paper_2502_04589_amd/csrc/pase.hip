@@ -710,9 +710,10 @@ void coldot(pase_handle* h, long long N, int k, const double* x, const double* y
 // R = b - A x0 given (overwritten; it is left at the residual of step s - 1, the last step
 // updating x only).  p_0 = z_0 by exchanging the Z and P buffers, and the first update reads
 // x0 from X0, so neither start needs a copy.
-// With idx (two CG steps only): X0 and X are full blocks of leading dimension ldx and the k columns
-// solved are idx[0..k) of them (R, the residual, is the gathered k-column block).
-void pcg(pase_handle* h, int k, const double* X0, double* X, double* R, const int* idx = nullptr, int ldx = 0) {
+// With pos (two CG steps only): X0 and X are full blocks of leading dimension ldx, column j of them
+// solved as column pos[j] of the k-column blocks (R, the residual, is the gathered one) and copied
+// from X0 where pos[j] < 0.
+void pcg(pase_handle* h, int k, const double* X0, double* X, double* R, const int* pos = nullptr, int ldx = 0) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   vcycle(h, 0, k, R, h->Z, h->rho);
@@ -728,7 +729,7 @@ void pcg(pase_handle* h, int k, const double* X0, double* X, double* R, const in
     launch_zadd(N, k, h->beta, h->P, h->Z, s);
     apply_dot(h, k, h->Z, h->Q, h->pq, 0);
     launch_pcg_alpha(k, h->rho2, h->pq, h->beta, s);
-    if (idx) launch_axpy3_gs(N, k, ldx, idx, h->alpha, h->P, h->beta, h->Z, X0, X, s);
+    if (pos) launch_axpy3_merge(N, k, ldx, pos, h->alpha, h->P, h->beta, h->Z, X0, X, s);
     else launch_axpy3(N, k, h->alpha, h->P, h->beta, h->Z, X0, X, s);
     return;
   }
@@ -1239,14 +1240,13 @@ pase_status correction_enqueue(pase_handle* h, int k) {
   if (ka < k) {
     // soft locking: the active columns of U and R gathered into W2, W3 (leading dimension ka), their
     // fine solves into R (free until the next residual), then W = U with the active columns replaced
-    // plain FP64 with two CG steps: U's active columns are read, and W's written, in place by the
-    // last x update, and the locked columns copied: no gathered U and no merge
+    // plain FP64 with two CG steps: the last x update reads U and writes W in one pass over their
+    // full rows (the solved columns updated, the locked ones copied): no gathered U and no merge
     const bool direct = h->opt.precision == PASE_PREC_FP64 && h->opt.cg_steps == 2;
     if (!direct) launch_gather_cols(N, k, ka, h->lock_idx, h->U, h->W2, s);
     launch_gather_cols(N, k, ka, h->lock_idx, h->R, h->W3, s);
     if (direct) {
-      pcg(h, ka, h->U, h->X, h->W3, h->lock_idx, k);
-      launch_copy_locked(N, k, h->lock_idx + h->K, h->U, h->X, s);
+      pcg(h, ka, h->U, h->X, h->W3, h->lock_idx + h->K, k);
     } else if (h->opt.precision == PASE_PREC_MIXED) {
       pcg_correction_f32(h, ka, h->W2, h->W3, h->R);
     } else if (h->opt.precision == PASE_PREC_LEARNED) {
