@@ -248,6 +248,18 @@ __global__ void add_f2d_kernel(size_t n, const double* __restrict__ u, const flo
   if (i < n) w[i] = u[i] + (double)e[i];
 }
 
+// w = u + e over full rows (leading dimension ldw), e taken from column pos[j] of its k-column block
+// where pos[j] >= 0 (the soft-locked columns are u itself)
+__global__ void add_f2d_merge_kernel(long long N, int k, int ldw, const int* __restrict__ pos,
+                                     const double* __restrict__ u, const float* __restrict__ e,
+                                     double* __restrict__ w) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= N * ldw) return;
+  const long long n = q / ldw;
+  const int a = pos[q - n * ldw];
+  w[q] = (a >= 0) ? u[q] + (double)e[n * k + a] : u[q];
+}
+
 __global__ void copy_kernel(size_t n, const double* __restrict__ s, double* __restrict__ d) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = s[i];
@@ -1052,6 +1064,11 @@ void launch_cg_start_f32(size_t n, const double* R, float* r, float* e, hipStrea
 
 void launch_copy_f32(size_t n, const float* src, float* dst, hipStream_t s) {
   copy_f32_kernel<<<nblk((long long)n), kBlock, 0, s>>>(n, src, dst);
+}
+
+void launch_add_f2d_merge(long long N, int k, int ldw, const int* pos, const double* u, const float* e, double* w,
+                          hipStream_t s) {
+  add_f2d_merge_kernel<<<nblk(N * ldw), kBlock, 0, s>>>(N, k, ldw, pos, u, e, w);
 }
 
 void launch_add_f2d(size_t n, const double* u, const float* e, double* w, hipStream_t s) {

@@ -174,6 +174,8 @@ void launch_f2d(size_t n, const float* a, double* b, hipStream_t s);
 void launch_gram_bf16x3(long long N, int k, const float* X, const float* Y1, const float* Y2, double* partial,
                         int tiles, double* G1, double* G2, hipStream_t s);
 void launch_add_f2d(size_t n, const double* u, const float* e, double* w, hipStream_t s);
+void launch_add_f2d_merge(long long N, int k, int ldw, const int* pos, const double* u, const float* e, double* w,
+                          hipStream_t s);
 void launch_cg_start_f32(size_t n, const double* R, float* r, float* e, hipStream_t s);
 // learned form: flexible-PCG beta, per-column fallback to the V-cycle, column selection
 void launch_flex_beta(int k, const double* a, const double* b, const double* c, int* mask, double* beta,

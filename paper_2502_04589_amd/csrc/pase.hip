@@ -752,7 +752,10 @@ void pcg(pase_handle* h, int k, const double* X0, double* X, double* R, const in
 // Mixed precision: s FP32 PCG steps per column on the correction equation A E = R from E = 0
 // (R = lam M U - A U, the FP64 residual), then W = U + E in FP64.  In exact arithmetic W equals
 // the iterate of s PCG steps on A w = lam M u from w = u.
-void pcg_correction_f32(pase_handle* h, int k, const double* U, const double* R, double* W) {
+// With pos: U and W are full blocks of leading dimension ldw, column j of W = U + E[:, pos[j]] (U where
+// pos[j] < 0), and R is the gathered k-column residual.
+void pcg_correction_f32(pase_handle* h, int k, const double* U, const double* R, double* W, const int* pos = nullptr,
+                        int ldw = 0) {
   hipStream_t s = h->stream;
   const long long N = h->lev[0].N;
   const size_t nk = (size_t)N * k;
@@ -772,7 +775,8 @@ void pcg_correction_f32(pase_handle* h, int k, const double* U, const double* R,
       std::swap(h->rho, h->rho2);
     }
   }
-  launch_add_f2d(nk, U, h->E32, W, s);
+  if (pos) launch_add_f2d_merge(N, k, ldw, pos, U, h->E32, W, s);
+  else launch_add_f2d(nk, U, h->E32, W, s);
 }
 
 // Learned form: z = N(r) for the columns still on the network, z = V(r) for the others.
@@ -1240,15 +1244,17 @@ pase_status correction_enqueue(pase_handle* h, int k) {
   if (ka < k) {
     // soft locking: the active columns of U and R gathered into W2, W3 (leading dimension ka), their
     // fine solves into R (free until the next residual), then W = U with the active columns replaced
-    // plain FP64 with two CG steps: the last x update reads U and writes W in one pass over their
-    // full rows (the solved columns updated, the locked ones copied): no gathered U and no merge
-    const bool direct = h->opt.precision == PASE_PREC_FP64 && h->opt.cg_steps == 2;
+    // plain FP64 with two CG steps, and the mixed form: the last update reads U and writes W in one
+    // pass over their full rows (the solved columns updated, the locked ones copied): no gathered U
+    // and no merge
+    const bool direct = (h->opt.precision == PASE_PREC_FP64 && h->opt.cg_steps == 2) ||
+                        h->opt.precision == PASE_PREC_MIXED;
     if (!direct) launch_gather_cols(N, k, ka, h->lock_idx, h->U, h->W2, s);
     launch_gather_cols(N, k, ka, h->lock_idx, h->R, h->W3, s);
-    if (direct) {
+    if (h->opt.precision == PASE_PREC_MIXED) {
+      pcg_correction_f32(h, ka, h->U, h->W3, h->X, h->lock_idx + h->K, k);
+    } else if (direct) {
       pcg(h, ka, h->U, h->X, h->W3, h->lock_idx + h->K, k);
-    } else if (h->opt.precision == PASE_PREC_MIXED) {
-      pcg_correction_f32(h, ka, h->W2, h->W3, h->R);
     } else if (h->opt.precision == PASE_PREC_LEARNED) {
       if (!h->net) return fail(h, PASE_E_ARG, "the learned form needs a network (pase_attach_unet)");
       int sw = 0;
