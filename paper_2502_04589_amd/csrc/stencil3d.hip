@@ -8,9 +8,8 @@ void launch_fine3_f32(const Fine3Args& a, Epi epi, hipStream_t s);
 
 int fine3_spatial_blocks(int m, int nzc, int k, bool fp32) {
   // the column-sum partial rows are per (x-tile, y-tile, z-run); column chunks share a row.  Tiles
-  // are 8 x 4 nodes when k is a multiple of 8 vectors (2 doubles, or 4 floats when k % 4 == 0),
-  // else 8 x 8 (the rule of launchv_tile)
-  const int by = (k % (fp32 ? 32 : 16) == 0) ? 4 : 8;
+  // are 8 x 4 nodes or 8 x 8 by fine3_wide_tile (the rule of launchv_tile)
+  const int by = fine3_wide_tile(k, fp32) ? 4 : 8;
   return ((m + 7) / 8) * ((m + by - 1) / by) * nzc;
 }
 

@@ -31,6 +31,14 @@ namespace {
 // and no branch around a store leaves the compiler unsure which loads are still in flight.
 __device__ double4 fine3_sink[1];
 
+// 8 x 4 tiles with 8 vectors per node when k is a multiple of 8 vectors (whole 128-byte lines of a
+// node row per block) or at least 64 columns in whole vectors (the last column chunk ragged): the
+// rule that the column-sum partial rows follow as well (fine3_spatial_blocks)
+__host__ __device__ inline bool fine3_wide_tile(int k, bool fp32) {
+  const int vw = (fp32 && k % 4 == 0) ? 4 : 2;
+  return k % vw == 0 && (k % (8 * vw) == 0 || k >= 64);
+}
+
 __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   const int per = nblocks >> 3;
   return (b & 7) * per + (b >> 3);
@@ -658,7 +666,7 @@ void launchv_tile(const Fine3Args& a, hipStream_t s) {
   // 8 x 4 nodes with 8 threads per node when a block's columns are whole 128-byte lines of the
   // node rows (k a multiple of 8 VW): its halo loads are then full lines, which measured 16 % faster
   // than 8 x 8 nodes with 4 threads (half lines, the other half read by the next column chunk)
-  if (a.k % (8 * VW) == 0) {
+  if (fine3_wide_tile(a.k, sizeof(T) == 4)) {
     go(std::integral_constant<int, 8>());
     return;
   }
