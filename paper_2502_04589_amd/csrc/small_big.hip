@@ -267,31 +267,33 @@ __device__ void colsum_big(int nH, int k, const double* __restrict__ Gt, const d
   __syncthreads();
 }
 
-// g_r . v for the 4 rows r = r0, r0 + kBW, r0 + 2 kBW, r0 + 3 kBW of Gt and the LDS k-vector v, by
-// one wave (every lane gets them; rows past nH give 0): the 4 rows' loads are issued before the
-// first reduction.
-__device__ __forceinline__ void row_dot4(int nH, int k, const double* __restrict__ Gt, int r0, const double* v,
-                                         double (&d)[4]) {
-  const int lane = threadIdx.x & 63;
-  const double v0 = (lane < k) ? v[lane] : 0.0, v1 = (lane + 64 < k) ? v[lane + 64] : 0.0;
-  double s[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = r0 + u * kBW;
-    const int rc = (r < nH) ? r : nH - 1;
-    const double* __restrict__ g = Gt + (size_t)rc * k;
-    const double a0 = (lane < k) ? g[lane] : 0.0, a1 = (lane + 64 < k) ? g[lane + 64] : 0.0;
-    s[u] = (r < nH) ? fma(a1, v1, a0 * v0) : 0.0;
+// Gt^T is kept column-major as GtT (k x nH, GtT[a nH + r] = Gt[r][a]) for the products Gt v: a thread
+// takes a row r, reads its k entries with loads that are consecutive across the wave, and the LDS
+// vector v by broadcasts; no cross-lane reductions.
+__global__ void gt_transpose_kernel(int nH, int k, const double* __restrict__ Gt, double* __restrict__ GtT) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (long long)nH * k) return;
+  const int r = (int)(q / k), a = (int)(q - (long long)r * k);
+  GtT[(size_t)a * nH + r] = Gt[q];
+}
+
+__device__ __forceinline__ double gt_row_dot(int nH, int k, const double* __restrict__ GtT, int r, const double* v) {
+  double s0 = 0.0, s1 = 0.0;
+  int a = 0;
+  for (; a + 1 < k; a += 2) {
+    s0 = fma(GtT[(size_t)a * nH + r], v[a], s0);
+    s1 = fma(GtT[(size_t)(a + 1) * nH + r], v[a + 1], s1);
   }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) d[u] = wsum(s[u]);
+  if (a < k) s0 = fma(GtT[(size_t)a * nH + r], v[a], s0);
+  return s0 + s1;
 }
 
 // One workgroup per pair i: shift-invert solves at the start vector's Rayleigh quotient (or
 // sigma[i]), then Rayleigh-quotient shifts, as in the one-workgroup solver; the unit vector goes to
 // Vt[i*n ..] (n = N_H + k) and its Rayleigh quotient to rq[i].  xs: 2 n doubles per pair.
 __global__ __launch_bounds__(kBT) void srqi_big_kernel(int nH, int k, const double* __restrict__ theta,
-                                                     const double* __restrict__ Gt, const double* __restrict__ Hm,
+                                                     const double* __restrict__ Gt, const double* __restrict__ GtT,
+                                                     const double* __restrict__ Hm,
                                                      const double* __restrict__ sigma,
                                                      const double* __restrict__ X0, double scale,
                                                      const double* __restrict__ tolv, double* __restrict__ Vt,
@@ -318,15 +320,7 @@ __global__ __launch_bounds__(kBT) void srqi_big_kernel(int nH, int k, const doub
     for (int a = tid; a < k; a += kBT) L.vh[a] = x[nH + a];
     __syncthreads();
     double part = 0.0;
-    for (int r0 = wave; r0 < nH; r0 += 4 * kBW) {
-      double gd[4];
-      row_dot4(nH, k, Gt, r0, L.vh, gd);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = r0 + u * kBW;
-        if (lane == 0 && r < nH) part = fma(x[r], fma(theta[r], x[r], 2.0 * gd[u]), part);
-      }
-    }
+    for (int r = tid; r < nH; r += kBT) part = fma(x[r], fma(theta[r], x[r], 2.0 * gt_row_dot(nH, k, GtT, r, L.vh)), part);
     if (tid < k) {
       double hx = 0.0;
       for (int b = 0; b < k; ++b) hx = fma(Hm[(size_t)tid * k + b], L.vh[b], hx);
@@ -359,15 +353,7 @@ __global__ __launch_bounds__(kBT) void srqi_big_kernel(int nH, int k, const doub
     }
     __syncthreads();
     // y_Theta = d o (x_Theta - Gt y_H), y_H as solved
-    for (int r0 = wave; r0 < nH; r0 += 4 * kBW) {
-      double gd[4];
-      row_dot4(nH, k, Gt, r0, L.vh, gd);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = r0 + u * kBW;
-        if (lane == 0 && r < nH) y[r] = (x[r] - gd[u]) / (theta[r] - mu);
-      }
-    }
+    for (int r = tid; r < nH; r += kBT) y[r] = (x[r] - gt_row_dot(nH, k, GtT, r, L.vh)) / (theta[r] - mu);
     for (int a = tid; a < k; a += kBT) y[nH + a] = L.vh[a];
     __syncthreads();
     double yy = 0.0, yx = 0.0;
@@ -400,13 +386,14 @@ __global__ __launch_bounds__(kBT) void srqi_big_kernel(int nH, int k, const doub
 // Rayleigh quotient and residual of column i of an orthonormal Vt with the explicit operator:
 // w = Tt v (into the pair's scratch), rho = v.w, res = ||w - rho v||.
 __global__ __launch_bounds__(kBT) void srr_big_kernel(int nH, int k, const double* __restrict__ theta,
-                                                    const double* __restrict__ Gt, const double* __restrict__ Hm,
+                                                    const double* __restrict__ Gt, const double* __restrict__ GtT,
+                                                    const double* __restrict__ Hm,
                                                     const double* __restrict__ Vt, double* __restrict__ rq,
                                                     double* __restrict__ res, double* __restrict__ xs) {
   __shared__ BLds L;
   const int i = blockIdx.x;
   const int n = nH + k;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x;
   const double* x = Vt + (size_t)i * n;
   double* w = xs + (size_t)i * 2 * n;
   for (int a = tid; a < k; a += kBT) L.vh[a] = x[nH + a];
@@ -417,15 +404,7 @@ __global__ __launch_bounds__(kBT) void srr_big_kernel(int nH, int k, const doubl
     for (int b = 0; b < k; ++b) s = fma(Hm[(size_t)tid * k + b], L.vh[b], s);
     w[nH + tid] = s;
   }
-  for (int r0 = wave; r0 < nH; r0 += 4 * kBW) {
-    double gd[4];
-    row_dot4(nH, k, Gt, r0, L.vh, gd);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = r0 + u * kBW;
-      if (lane == 0 && r < nH) w[r] = fma(theta[r], x[r], gd[u]);
-    }
-  }
+  for (int r = tid; r < nH; r += kBT) w[r] = fma(theta[r], x[r], gt_row_dot(nH, k, GtT, r, L.vh));
   __syncthreads();
   double xw = 0.0;
   for (int r = tid; r < n; r += kBT) xw = fma(x[r], w[r], xw);
@@ -620,17 +599,22 @@ int accept_chunk_rows(int nH, int k) {
 
 int small_big_max_k() { return kBK; }
 int small_big_max_nh() { return kBigMaxH; }
-size_t small_big_scratch_doubles(int nH, int k) { return (size_t)2 * (nH + k) * k + 16; }
+// the per-pair work vectors (2 (nH + k) k) and 16 more, then G^T column-major (nH k)
+size_t small_big_scratch_doubles(int nH, int k) { return (size_t)2 * (nH + k) * k + 16 + (size_t)nH * k; }
+static double* gtt_slice(int nH, int k, double* scratch) { return scratch + (size_t)2 * (nH + k) * k + 16; }
 
 void launch_small_rqi_big(int nH, int k, const double* theta, const double* Gt, const double* Hm,
                           const double* sigma, const double* X0, double scale, const double* tolv, double* Vt,
                           double* rq, double* scratch, hipStream_t s) {
-  srqi_big_kernel<<<k, kBT, 0, s>>>(nH, k, theta, Gt, Hm, sigma, X0, scale, tolv, Vt, rq, scratch);
+  double* GtT = gtt_slice(nH, k, scratch);
+  gt_transpose_kernel<<<(unsigned)(((long long)nH * k + 255) / 256), 256, 0, s>>>(nH, k, Gt, GtT);
+  srqi_big_kernel<<<k, kBT, 0, s>>>(nH, k, theta, Gt, GtT, Hm, sigma, X0, scale, tolv, Vt, rq, scratch);
 }
 
 void launch_small_rr_big(int nH, int k, const double* theta, const double* Gt, const double* Hm, const double* Vt,
                          double* rq, double* res, double* scratch, hipStream_t s) {
-  srr_big_kernel<<<k, kBT, 0, s>>>(nH, k, theta, Gt, Hm, Vt, rq, res, scratch);
+  // G^T as the RQI launch left it (srr follows it in every sequence)
+  srr_big_kernel<<<k, kBT, 0, s>>>(nH, k, theta, Gt, gtt_slice(nH, k, scratch), Hm, Vt, rq, res, scratch);
 }
 
 void launch_small_accept_big(int nH, int k, int nev, const double* theta, const double* Gt, const double* Hm,
