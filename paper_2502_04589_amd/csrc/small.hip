@@ -455,8 +455,11 @@ __device__ int inertia_r(int nH, int k, const double* g, double th, const double
 
 // Acceptance of the fast path (one workgroup).  Sorts the Rayleigh quotients,
 // requires every residual <= tol_abs and finite values, then counts the
-// eigenvalues of Tt below mu* = lambda_max + gap by inertia; the count must be k.
-// When it is not and the block carries guard pairs (nev < k), a count of nev below the
+// eigenvalues of Tt below mu* = lambda_max + gap by inertia; the count must be k.  A Rayleigh
+// quotient theta_j can lie below its eigenvalue by up to its residual norm r_j, so when that count
+// falls short, a count of k below max_j (theta_j + r_j) + gap (above every eigenvalue the pairs
+// approximate) certifies them too.
+// When both fail and the block carries guard pairs (nev < k), a count of nev below the
 // nev-th Rayleigh quotient + gap still certifies the wanted pairs as the nev smallest
 // (status[0] = 2: the guard pairs are eigenpairs of Tt, not certified as the next ones).
 // Writes lam (ascending) and perm (column of Vt for each output position);
@@ -469,6 +472,7 @@ __global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, int nev, co
                                                     int* __restrict__ status) {
   __shared__ RLds L;
   __shared__ double srt[kSK];
+  __shared__ double up_s;
   __shared__ int ok_s;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (tid == 0) ok_s = 1;
@@ -490,6 +494,10 @@ __global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, int nev, co
     }
     const unsigned long long bad = __ballot(!good);
     if (lane == 0 && bad) ok_s = 0;
+    double up = (lane < k) ? v + e : -DBL_MAX;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) up = fmax(up, __shfl_xor(up, o, 64));
+    if (lane == 0) up_s = up;
   }
   __syncthreads();
   for (int j = tid; j < k; j += kRT) lam[j] = srt[j];
@@ -506,6 +514,10 @@ __global__ __launch_bounds__(kRT) void saccept_kernel(int nH, int k, int nev, co
   bool trusted = false;
   int count = inertia_r(nH, k, g, th, Hm, srt[k - 1] + gap, L, &trusted);
   int verdict = (trusted && count == k) ? 1 : 0;
+  if (!verdict) {
+    count = inertia_r(nH, k, g, th, Hm, fmax(up_s, srt[k - 1]) + gap, L, &trusted);
+    verdict = (trusted && count == k) ? 1 : 0;
+  }
   if (!verdict && nev < k) {
     count = inertia_r(nH, k, g, th, Hm, srt[nev - 1] + gap, L, &trusted);
     verdict = (trusted && count == nev) ? 2 : 0;

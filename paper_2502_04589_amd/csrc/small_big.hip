@@ -479,20 +479,23 @@ __device__ int inertia_count(int nH, int k, const double* __restrict__ theta, do
 }
 
 // Acceptance: ascending order of the Rayleigh quotients, every residual within its tolerance,
-// and the inertia count below mu* = (largest Rayleigh quotient) + gap equal to k.  When that count
-// fails and the block carries guard pairs (nev < k), the count below the nev-th Rayleigh quotient
-// + gap equal to nev still certifies the wanted pairs as the nev smallest (status[0] = 2: the guard
-// pairs are then eigenpairs of Tt but not certified as the next ones).  status[0] = 0 rejects;
-// status[1] = the last count.  lam ascending, perm = source column.
-// Three launches: the order and residual checks with the two shifts (one workgroup), the sums
-// over row chunks of Gt^T D(mu) Gt for both shifts (one workgroup per chunk and shift, partial
+// and the inertia count below mu* = (largest Rayleigh quotient) + gap equal to k.  A Rayleigh
+// quotient theta_j can lie below its eigenvalue by up to its residual norm r_j, so when that count
+// falls short, a count of k below max_j (theta_j + r_j) + gap, a shift above every eigenvalue the
+// pairs approximate, certifies them too.  When both fail and the block carries guard pairs
+// (nev < k), the count below the nev-th Rayleigh quotient + gap equal to nev still certifies the
+// wanted pairs as the nev smallest (status[0] = 2: the guard pairs are then eigenpairs of Tt but not
+// certified as the next ones).  status[0] = 0 rejects; status[1] = the last count.  lam ascending,
+// perm = source column.
+// Three launches: the order and residual checks with the three shifts (one workgroup), the sums
+// over row chunks of Gt^T D(mu) Gt for each shift (one workgroup per chunk and shift, partial
 // k x k blocks in part), and the Schur complements with their LDL^T counts (one workgroup).
 __global__ __launch_bounds__(kBT) void saccept_pre_kernel(int k, int nev, const double* __restrict__ rq,
                                                         const double* __restrict__ res, double tol_abs,
                                                         const double* __restrict__ tolv, double gap,
                                                         double* __restrict__ lam, int* __restrict__ perm,
                                                         double* __restrict__ mus, int* __restrict__ status) {
-  __shared__ double srt[kBK];
+  __shared__ double srt[kBK], sup[kBK];
   __shared__ int ok_s;
   const int tid = threadIdx.x;
   if (tid == 0) ok_s = 1;
@@ -507,6 +510,7 @@ __global__ __launch_bounds__(kBT) void saccept_pre_kernel(int k, int nev, const 
     const double tl = tolv ? tol_abs * tolv[(rank < k) ? rank : k - 1] : tol_abs;
     const bool good = (v == v && e == e && fabs(v) < DBL_MAX && e <= tl);
     srt[rank] = v;
+    sup[rank] = v + e;
     perm[rank] = tid;
     if (!good) ok_s = 0;
   }
@@ -515,8 +519,11 @@ __global__ __launch_bounds__(kBT) void saccept_pre_kernel(int k, int nev, const 
   if (tid == 0) {
     status[0] = ok_s;           // provisional: 1 = checks passed, the counts decide
     status[1] = 0;
+    double up = srt[k - 1];
+    for (int j = 0; j < k; ++j) up = fmax(up, sup[j]);
     mus[0] = srt[k - 1] + gap;
-    mus[1] = srt[(nev < k ? nev : k) - 1] + gap;
+    mus[1] = up + gap;
+    mus[2] = srt[(nev < k ? nev : k) - 1] + gap;
   }
 }
 
@@ -526,7 +533,7 @@ __global__ __launch_bounds__(kBT) void saccept_part_kernel(int nH, int k, int ne
                                                          const double* __restrict__ mus,
                                                          const int* __restrict__ status, double* __restrict__ part) {
   const int sh = blockIdx.y;
-  if (status[0] == 0 || (sh == 1 && nev >= k)) return;
+  if (status[0] == 0 || (sh == 2 && nev >= k)) return;
   const int rb = blockIdx.x * rows;
   const int re = (rb + rows < nH) ? rb + rows : nH;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -562,8 +569,8 @@ __global__ __launch_bounds__(kBT) void saccept_final_kernel(int nH, int k, int n
   if (status[0] == 0) return;
   const int tid = threadIdx.x;
   int verdict = 0, count = 0;
-  for (int sh = 0; sh < 2 && verdict == 0; ++sh) {
-    if (sh == 1 && nev >= k) break;
+  for (int sh = 0; sh < 3 && verdict == 0; ++sh) {
+    if (sh == 2 && nev >= k) break;
     const double mu = mus[sh];
     const double* ps = part + (size_t)sh * nchunk * k * k;
     for (int e = tid; e < k * k; e += kBT) {
@@ -575,7 +582,7 @@ __global__ __launch_bounds__(kBT) void saccept_final_kernel(int nH, int k, int n
     __syncthreads();
     bool trusted = false;
     count = inertia_count(nH, k, theta, mu, L, &trusted);
-    if (sh == 0) verdict = (trusted && count == k) ? 1 : 0;
+    if (sh < 2) verdict = (trusted && count == k) ? 1 : 0;
     else verdict = (trusted && count == nev) ? 2 : 0;
     __syncthreads();
   }
@@ -600,8 +607,8 @@ int accept_chunk_rows(int nH, int k) {
 int small_big_max_k() { return kBK; }
 int small_big_max_nh() { return kBigMaxH; }
 // the per-pair work vectors (2 (nH + k) k) and 16 more, then G^T column-major (nH k)
-size_t small_big_scratch_doubles(int nH, int k) { return (size_t)2 * (nH + k) * k + 16 + (size_t)nH * k; }
-static double* gtt_slice(int nH, int k, double* scratch) { return scratch + (size_t)2 * (nH + k) * k + 16; }
+size_t small_big_scratch_doubles(int nH, int k) { return (size_t)3 * (nH + k) * k + 16 + (size_t)nH * k; }
+static double* gtt_slice(int nH, int k, double* scratch) { return scratch + (size_t)3 * (nH + k) * k + 16; }
 
 void launch_small_rqi_big(int nH, int k, const double* theta, const double* Gt, const double* Hm,
                           const double* sigma, const double* X0, double scale, const double* tolv, double* Vt,
@@ -624,9 +631,9 @@ void launch_small_accept_big(int nH, int k, int nev, const double* theta, const 
   const int rows = accept_chunk_rows(nH, k);
   const int nchunk = (nH + rows - 1) / rows;
   double* part = scratch;
-  double* mus = scratch + (size_t)2 * nchunk * k * k;
+  double* mus = scratch + (size_t)3 * nchunk * k * k;
   saccept_pre_kernel<<<1, kBT, 0, s>>>(k, nev, rq, res, tol_abs, tolv, gap, lam, perm, mus, status);
-  saccept_part_kernel<<<dim3((unsigned)nchunk, 2), kBT, 0, s>>>(nH, k, nev, rows, theta, Gt, mus, status, part);
+  saccept_part_kernel<<<dim3((unsigned)nchunk, 3), kBT, 0, s>>>(nH, k, nev, rows, theta, Gt, mus, status, part);
   saccept_final_kernel<<<1, kBT, 0, s>>>(nH, k, nev, nchunk, theta, Hm, mus, part, status);
 }
 
