@@ -942,6 +942,19 @@ void structured_retry(pase_handle* h, int k) {
   structured_attempt(h, k);
 }
 
+// Retry of a structured solution rejected on residuals alone (its order and count were not
+// reached): that block, emitted in ascending order into Vs, is close to converged, so the
+// Rayleigh-quotient iteration restarts from it, each pair from its own Rayleigh quotient.
+void structured_polish(pase_handle* h, int k) {
+  hipStream_t s = h->stream;
+  const int NH = (int)h->lev[h->L].N;
+  mark(h, PH_SMALL);
+  launch_copy((size_t)(NH + k) * k, h->Vs, h->X0f, s);
+  launch_fill_int(4, 0, h->statf, s);
+  h->retried = true;
+  structured_attempt(h, k);
+}
+
 // ---------------------------------------------------------------- PRECOND-A and GCG_AUG (Sec. 4)
 // V_H is level gc.  The fine directions W are replaced by their A-orthogonal complement
 // W~ = W - I_H^h a_hat against V_H (a_hat ~ A_H^{-1} I_h^H A W), which is the congruence of eq.
@@ -1376,7 +1389,9 @@ pase_status correction_resolve(pase_handle* h, int k) {
   }
   h->last_path = (st[2] != 0) ? -3 : (st[1] == 0 ? -1 : -2);
   if (!h->retried) {
-    structured_retry(h, k);   // speculative again: read with the next synchronisation
+    // speculative again: read with the next synchronisation
+    if (h->last_path == -1) structured_polish(h, k);
+    else structured_retry(h, k);
     return PASE_OK;
   }
   return correction_dense_tail(h, k);
